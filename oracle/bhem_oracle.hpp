@@ -1,0 +1,96 @@
+// BHEM CPU oracle -- TEST INFRASTRUCTURE ONLY.
+//
+// A plain, slow FP64 implementation of what the thin-shell hot path computes,
+// written from "Simulating Parametric Thin Shells by Bicubic Hermite Elements"
+// (Ni et al., arXiv 2312.14839).  Only tests/, the smoke check and the
+// benchmark's CPU-baseline leg may load it.  It shares no code, header, table
+// or constant with the HIP library under paper_2312_14839_amd/.
+//
+// Everything here is templated on the scalar type so that the energy and the
+// gradient can be evaluated with std::complex<double> for complex-step
+// differentiation (tests compare the paper's analytic gradient and Hessian
+// against those exact derivatives).
+#pragma once
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <vector>
+
+namespace orc {
+
+// ---------------------------------------------------------------- shell data
+struct Shell {
+    int32_t n1, n2;          // patches along xi^1 and xi^2
+    int32_t periodic1;       // node column n1 is the same node as column 0
+    double dxi1, dxi2;       // parameter-space cell size
+    double young, poisson, thickness, density;
+    double gravity[3];
+};
+
+// Lame parameters as the paper states them (Sec. 3.3, "Energies"):
+// lambda = Y nu / (1 - nu^2), mu = Y / (2 (1 + nu)).
+inline double lame_lambda(const Shell& s) { return s.young * s.poisson / (1.0 - s.poisson * s.poisson); }
+inline double lame_mu(const Shell& s) { return s.young / (2.0 * (1.0 + s.poisson)); }
+
+// Node numbering of the Cartesian patch grid (Sec. 4.1) with the periodic
+// merge of Sec. 4.2: with periodic1 set only node column 0 is kept.
+inline int num_node_cols(const Shell& s) { return s.periodic1 ? s.n1 : s.n1 + 1; }
+inline int num_nodes(const Shell& s) { return num_node_cols(s) * (s.n2 + 1); }
+inline int node_index(const Shell& s, int i, int j) {
+    int cols = num_node_cols(s);
+    if (s.periodic1) i %= s.n1;
+    return j * cols + i;
+}
+// Corner c = p + 2q of patch (pi, pj) is node (pi + p, pj + q).
+inline void patch_nodes(const Shell& s, int pi, int pj, int nodes[4]) {
+    for (int c = 0; c < 4; ++c) nodes[c] = node_index(s, pi + (c & 1), pj + (c >> 1));
+}
+
+// ------------------------------------------------------------- 3-vectors
+template <class T> struct V3 {
+    T x, y, z;
+};
+template <class T> inline V3<T> operator+(V3<T> a, V3<T> b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <class T> inline V3<T> operator-(V3<T> a, V3<T> b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <class T, class S> inline V3<T> operator*(S s, V3<T> a) { return {T(s) * a.x, T(s) * a.y, T(s) * a.z}; }
+template <class T> inline T dot(V3<T> a, V3<T> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <class T> inline V3<T> cross(V3<T> a, V3<T> b) {
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+template <class T> inline T& comp(V3<T>& a, int i) { return i == 0 ? a.x : (i == 1 ? a.y : a.z); }
+template <class T> inline T compc(const V3<T>& a, int i) { return i == 0 ? a.x : (i == 1 ? a.y : a.z); }
+
+// sqrt that stays analytic for complex-step arguments (no conjugation).
+inline double asqrt(double x) { return std::sqrt(x); }
+inline std::complex<double> asqrt(std::complex<double> x) { return std::sqrt(x); }
+
+// ------------------------------------------------- Appendix A.1: Hermite basis
+// w[p][r], first derivative d1[p][r], second derivative d2[p][r] of the
+// one-dimensional weights at theta in [0,1].  The weights and their first
+// derivatives are those printed in Appendix A.1; the second derivatives are
+// the derivatives of those, which the paper does not print.
+void hermite_1d(double t, double w[2][2], double d1[2][2], double d2[2][2]);
+
+// Shape functions of the 16 local generalized coordinates of one patch and
+// their xi-derivatives at (theta1, theta2).  Row d of out: 0 value, 1 d/dxi1,
+// 2 d/dxi2, 3 d2/dxi1^2, 4 d2/dxi2^2, 5 d2/dxi1dxi2.  Local coordinate
+// I = 4c + k, corner c = p + 2q, kind k = r + 2s (0: x, 1: x_xi1, 2: x_xi2,
+// 3: x_xi1xi2).  Derivative coordinates are xi-derivatives, so the shape
+// function of kind (r,s) carries dxi1^r dxi2^s.
+void shape_functions(double t1, double t2, double dxi1, double dxi2, double out[6][16]);
+
+// ------------------------------------------ Appendix A.2: 4x4 Gauss-Legendre
+// Abscissae on [0,1] in increasing order and their weights on [0,1]
+// (multiply by dxi for a cell of width dxi).
+void gauss4(double theta[4], double weight[4]);
+
+// --------------------------------------------------- per-patch mechanics
+// Local DOF layout of q[48] and qb[48]: 12 c + 3 k + component.
+template <class T> T patch_energy_tensor(const Shell& s, const T* q, const double* qb);
+template <class T> T patch_energy_voigt(const Shell& s, const T* q, const double* qb);
+template <class T> void patch_gradient(const Shell& s, const T* q, const double* qb, T* grad);
+void patch_hessian(const Shell& s, const double* q, const double* qb, int pseudo, double* hess);
+void patch_mass(const Shell& s, const double* qb, double* mass);
+void patch_gravity(const Shell& s, const double* qb, double* f);
+
+}  // namespace orc

@@ -1,0 +1,56 @@
+// BHEM CPU oracle -- TEST INFRASTRUCTURE ONLY (see bhem_oracle.hpp).
+#pragma once
+#include <array>
+#include <vector>
+
+#include "bhem_oracle.hpp"
+
+namespace orc {
+
+// Global symmetric matrix kept as 12x12 blocks per (node, node) pair; the
+// pattern is every pair of nodes that share a patch.
+struct NodeBlocks {
+    struct Entry {
+        int col;
+        std::array<double, 144> v;   // row-major 12x12
+    };
+    Shell shell;
+    int nn;
+    std::vector<std::vector<Entry>> rows;
+    explicit NodeBlocks(const Shell& s);
+    double* find_or_add(int r, int c);
+    double* find(int r, int c);
+    const double* find(int r, int c) const { return const_cast<NodeBlocks*>(this)->find(r, c); }
+    void zero();
+    void add_patch(const int nodes[4], const double* m48, double scale);
+    void matvec(const double* x, double* y) const;
+};
+
+void gather(const Shell& s, int pi, int pj, const double* x, double* loc, int nodes[4]);
+double energy(const Shell& s, const double* q, const double* qb);
+void gradient(const Shell& s, const double* q, const double* qb, double* g);
+void assemble_hessian(const Shell& s, const double* q, const double* qb, int pseudo, NodeBlocks& K, double scale);
+void assemble_mass(const Shell& s, const double* qb, NodeBlocks& M, double scale);
+void gravity_load(const Shell& s, const double* qb, double* f);
+bool banded_ldlt_solve(const NodeBlocks& A, const double* b, double* x);
+int block_jacobi_cg(const NodeBlocks& A, const double* b, double* x, double rtol, int maxit, int* iters);
+
+struct NewtonOpts {
+    int solver;         // 0: banded LDL^T, 1: block-Jacobi CG
+    int pseudo;         // 1: pseudo Hessian
+    int newton_maxit;
+    double newton_rtol;
+    int pcg_maxit;
+    double pcg_rtol;
+};
+struct NewtonStats {
+    int newton_iters, pcg_iters_total, ls_backtracks, pad;
+    double grad_norm0, grad_norm, grad_floor, reg_delta;
+};
+// Converged when ||g_k|| <= max(newton_rtol ||g_0||, 4 eps || P_free |A_{k-1}| |q_k| ||).
+// Returns 0 converged, 1 Newton iteration cap, 2 line search failed,
+// 3 no positive definite system within the regulariser cap.
+int newton_step(const Shell& s, const double* qb, const uint8_t* fixed, double dt, const double* qn, const double* vn,
+                const double* qpresc, const NewtonOpts& o, double* qn1, double* vn1, NewtonStats* st);
+
+}  // namespace orc
