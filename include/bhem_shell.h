@@ -1,0 +1,174 @@
+/*
+ * bhem_shell.h -- C ABI of the MI355X (gfx950) BHEM thin-shell library.
+ *
+ * The library evaluates the Kirchhoff-Love thin-shell model discretised by
+ * bicubic Hermite patches (Ni et al., "Simulating Parametric Thin Shells by
+ * Bicubic Hermite Elements", arXiv 2312.14839) and advances it by one
+ * implicit-Euler step:
+ *   - per-patch 4x4 Gauss quadrature of the StVK membrane + bending energy,
+ *     its gradient and its exact (or pseudo) Hessian (Sec. 3.3, Appendix B);
+ *   - assembly of those Hessians, the consistent mass matrix (Eq. mass) and
+ *     the areal gravity load into a 12x12-block sparse matrix;
+ *   - Newton's method with a line search on the incremental potential of the
+ *     implicit Euler scheme (Sec. 6.1), whose linear systems are solved by a
+ *     block-Jacobi preconditioned conjugate gradient on the GPU.
+ *
+ * Conventions shared by every entry point
+ *   Generalized coordinates.  Each node stores x, dx/dxi1, dx/dxi2 and
+ *   d2x/dxi1dxi2 (Sec. 4.1), i.e. 12 doubles per node, ordered
+ *   [3*kind + component]; arrays of nodal values are [nodes][12] row-major
+ *   float64.  Derivative coordinates are derivatives with respect to xi, not
+ *   to the per-cell parameter theta.
+ *   Grids.  Shell s is an n1 x n2 grid of patches; node (i, j) has index
+ *   j*(n1+1) + i, or j*n1 + (i mod n1) when periodic1 is set (the node column
+ *   at xi1 = n1 dxi1 is the column at 0, Sec. 4.2 "Periodic boundary
+ *   conditions").  With several shells the node arrays are concatenated in
+ *   the order of the descriptors.
+ *   Memory.  Pointers whose name ends in _dev are device pointers valid on the
+ *   context's stream; _host are host pointers.  The caller owns every pointer
+ *   it passes; the library copies what it needs during shell_create and keeps
+ *   no caller pointer.  All device work is ordered on the context's stream.
+ *   Calls that return host values synchronise that stream before returning.
+ *   Errors.  Every call returns a shell_status (0 = success, < 0 = error);
+ *   no exception crosses the ABI.  shell_last_error() describes the last
+ *   error of a context.  SHELL_E_DEVICE means a HIP call failed; destroy the
+ *   context afterwards.  A context is not thread safe: use one per stream.
+ */
+#ifndef BHEM_SHELL_H
+#define BHEM_SHELL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct shell_ctx shell_ctx;
+typedef int32_t shell_status;
+
+enum {
+    SHELL_OK = 0,
+    SHELL_E_INVAL = -1,          /* invalid argument; the context is unchanged */
+    SHELL_E_NOMEM = -2,          /* device allocation failed */
+    SHELL_E_DEVICE = -3,         /* a HIP runtime call failed */
+    SHELL_E_NOT_CONVERGED = -4,  /* Newton or CG iteration cap; outputs hold the last iterate */
+    SHELL_E_INDEFINITE = -5,     /* regulariser reached its cap without a positive definite system */
+    SHELL_E_NONFINITE = -6,      /* non-finite input or result */
+    SHELL_E_LINESEARCH = -7      /* no step along the Newton direction lowered the energy */
+};
+
+enum { SHELL_FP64 = 0, SHELL_MIXED = 1 };             /* Hessian/SpMV precision */
+enum { SHELL_HESS_EXACT = 0, SHELL_HESS_PSEUDO = 1 };  /* Appendix B.2, last paragraph */
+enum { SHELL_WS_NONE = 0, SHELL_WS_MLP = 1 };          /* CG initial guess */
+
+/* One shell (Sec. 4.1-4.2; material of Sec. 3.3; loads of Sec. 4.3). */
+typedef struct {
+    int32_t n1, n2;              /* patches along xi1 and xi2, each >= 1 */
+    int32_t periodic1;           /* 1: node column n1 is node column 0 (needs n1 >= 3) */
+    double dxi1, dxi2;           /* parameter cell size, > 0 */
+    const double *ref_host;      /* [nodes][12] reference (rest) generalized coordinates */
+    const uint8_t *fixed_host;   /* [nodes][12], 1 = prescribed DOF (Sec. 4.2); NULL = none */
+    double young, poisson;       /* Y > 0, 0 <= nu < 0.5; lambda = Y nu/(1 - nu^2), mu = Y/(2(1 + nu)) */
+    double thickness, density;   /* h > 0, rho > 0 */
+    double gravity[3];           /* areal dead load rho h g (Sec. 4.3, "External Forces") */
+} shell_desc;
+
+typedef struct {
+    int32_t precision;           /* SHELL_FP64 or SHELL_MIXED (FP32 Hessian, matrix and inner CG;
+                                    FP64 gradient, residual, refinement and block inverses) */
+    int32_t hessian;             /* SHELL_HESS_EXACT or SHELL_HESS_PSEUDO */
+    int32_t warm_start;          /* SHELL_WS_NONE or SHELL_WS_MLP (needs shell_mlp_set_weights) */
+    int32_t newton_maxit;        /* > 0 */
+    int32_t pcg_maxit;           /* > 0, per linear solve */
+    double newton_rtol;          /* Newton stops at ||g|| <= max(newton_rtol ||g_0||, rounding floor) */
+    double pcg_rtol;             /* CG stops at ||b - A x|| <= pcg_rtol ||b|| (FP64 residual) */
+    int32_t device;              /* HIP device ordinal */
+    void *stream;                /* hipStream_t, NULL = the default stream */
+} shell_opts;
+
+/* Per-shell statistics of one shell_newton_step. */
+typedef struct {
+    int32_t status;              /* shell_status of this shell */
+    int32_t newton_iters;        /* Newton iterations taken */
+    int32_t pcg_iters_total;     /* CG iterations over all Newton iterations */
+    int32_t ls_backtracks;       /* rejected line-search trials */
+    int32_t refine_sweeps;       /* FP64 refinement sweeps (mixed precision) */
+    int32_t warm_start_used;     /* Newton iterations whose CG started from an accepted warm start */
+    double grad_norm0, grad_norm, grad_floor, reg_delta;
+    double t_assemble_ms, t_pcg_ms, t_step_ms;   /* whole-context wall times */
+} shell_step_stats;
+
+/* Default options: FP64, exact Hessian, no warm start, newton_rtol = pcg_rtol
+ * = 1e-10, 50 Newton and 100000 CG iterations, device 0, default stream. */
+void shell_default_opts(shell_opts *o);
+
+/* Create a context for n_shells shells (batching: one context holds all of
+ * them, concatenated).  Copies the descriptors' arrays, builds the patch
+ * colouring and the 12x12-block sparsity pattern (Sec. 4.3, "Properties of
+ * the mass matrix": blocks couple nodes that share a patch) and allocates all
+ * device memory.  On error *out is NULL and shell_last_error(NULL) tells why. */
+shell_status shell_create(const shell_desc *shells, int32_t n_shells, const shell_opts *o, shell_ctx **out);
+
+/* Destroy a context and free its device memory.  NULL is allowed. */
+void shell_destroy(shell_ctx *c);
+
+/* Message of the last error of c (of the last failed create if c is NULL). */
+const char *shell_last_error(const shell_ctx *c);
+
+/* Sizes: total nodes, total patches, and block non-zeros of the matrix. */
+shell_status shell_sizes(const shell_ctx *c, int32_t *total_nodes, int32_t *total_patches, int64_t *nnzb);
+
+/* Elastic energy V_e of every shell at q (Sec. 3.3 energy density integrated
+ * by the 16-point rule of Appendix A.2), its gradient (Appendix B.1,
+ * Eq. matrix) and, if assemble_hessian != 0, its Hessian (Appendix B.2,
+ * exact or pseudo per the options) assembled into the context's matrix.
+ *   q_dev        [total_nodes][12] generalized coordinates
+ *   energy_host  [n_shells] or NULL
+ *   grad_dev     [total_nodes][12] or NULL; no constraint is applied
+ * Returns SHELL_E_NONFINITE if an energy is not finite. */
+shell_status shell_energy_grad_hess(shell_ctx *c, const double *q_dev, double *energy_host, double *grad_dev,
+                                    int32_t assemble_hessian);
+
+/* Assemble K(q) + mass_scale * M into the context's matrix (M of Eq. mass;
+ * K the elastic Hessian; elastic = 0 drops K, giving mass_scale * M). */
+shell_status shell_assemble(shell_ctx *c, const double *q_dev, double mass_scale, int32_t elastic);
+
+/* Copy shell s's part of the context's matrix to the host as BSR with local
+ * node indices: row_ptr[nodes_s + 1], col_idx[nnzb_s], vals[nnzb_s][12][12]
+ * (FP64 even in mixed precision).  Call with NULL arrays to get *nnzb only. */
+shell_status shell_get_bsr(shell_ctx *c, int32_t shell, int32_t *nnzb, int32_t *row_ptr, int32_t *col_idx,
+                           double *vals);
+
+/* y = A x with the context's matrix; rows and columns of prescribed DOFs are
+ * left out when masked != 0 (y is 0 there).  FP64 vectors. */
+shell_status shell_spmv(shell_ctx *c, const double *x_dev, double *y_dev, int32_t masked);
+
+/* Solve A x = b (prescribed DOFs masked out; b must be 0 there) with the
+ * block-Jacobi CG at the options' precision, from x = 0.  iters_host and
+ * relres_host ([n_shells] each, may be NULL) receive per-shell counts and
+ * final ||b - A x|| / ||b|| (FP64).  SHELL_E_INDEFINITE if a diagonal block
+ * or p^T A p is not positive. */
+shell_status shell_pcg_solve(shell_ctx *c, const double *b_dev, double *x_dev, double rtol, int32_t maxit,
+                             int32_t *iters_host, double *relres_host);
+
+/* One implicit-Euler step of every shell (Sec. 6.1): minimise
+ *   E(q) = (1/2 dt^2)(q - qhat)^T M (q - qhat) + V_e(q) - f^T (q - qhat),
+ *   qhat = q_n + dt v_n,
+ * over the free DOFs, prescribed DOFs held at q_presc (or q_n if NULL);
+ * then v_{n+1} = (q_{n+1} - q_n)/dt.  Newton with a backtracking line
+ * search (quadratic, then cubic interpolation); block-Jacobi CG for the
+ * Newton systems; diagonal regulariser A + delta diag(A), delta = 1e-6..1e2,
+ * when a block or p^T A p is not positive (Sec. 6.1, "The Hessian matrix").
+ *   q_n_dev, v_n_dev, q_presc_dev  [total_nodes][12]
+ *   q_np1_dev, v_np1_dev           [total_nodes][12] outputs (may not alias inputs)
+ *   stats_host                     [n_shells] or NULL
+ * Returns the worst shell status. */
+shell_status shell_newton_step(shell_ctx *c, double dt, const double *q_n_dev, const double *v_n_dev,
+                               const double *q_presc_dev, double *q_np1_dev, double *v_np1_dev,
+                               shell_step_stats *stats_host);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BHEM_SHELL_H */

@@ -1,0 +1,81 @@
+// Host-side launchers of the libbhem kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_common.hpp"
+
+namespace bhem {
+
+// ------------------------------------------------------- patch kernels
+void launch_energy_grad(hipStream_t st, int npatch, const int4* patch_nodes, const int* patch_shell,
+                        const ShellParams* shells, const double* phi, const double* q, const double* qbar,
+                        const double* qhat, double mass_scale, int elastic, int loads, double* e_patch,
+                        double* g_patch);
+void launch_gather_grad(hipStream_t st, int nnodes, const int* inc_ptr, const int* inc, const double* g_patch,
+                        const uint16_t* freemask, const int* node_shell, const int* write_shell, double* grad);
+void launch_shell_energy(hipStream_t st, int nshell, const ShellParams* shells, const double* e_patch,
+                         double* e_shell);
+template <class T>
+void launch_hessian(hipStream_t st, const int* patch_list, int nlist, const int4* patch_nodes, const int* patch_shell,
+                    const int* patch_slots, const ShellParams* shells, const double* phi, const double* q,
+                    const double* qbar, double mass_scale, int elastic, int pseudo, T* vals);
+
+// ------------------------------------------------------ solver kernels
+// Row partition of the node rows into blocks that never straddle a shell;
+// used by the CG kernel and by the per-shell reductions.
+struct RowBlocks {
+    int nblk;
+    const int* blk_shell;    // [nblk]
+    const int* blk_row0;     // [nblk]
+    const int* blk_row1;     // [nblk]
+    const int* shell_blk0;   // [nshell]
+    const int* shell_nblk;   // [nshell]
+};
+
+struct CgShellOut {
+    int iters, status;       // status: 0 converged, 1 iteration cap, 2 p^T A p <= 0, 3 barrier timeout
+    double bnorm2, rnorm2;   // ||b||^2 and the final recursive ||r||^2
+};
+
+template <class TM>
+void launch_spmv(hipStream_t st, int nnodes, const int* row_ptr, const int* col_idx, const TM* vals,
+                 const uint16_t* freemask, const double* x, const double* b, double* y, int mode);
+// mode bits: 1 masked (free rows and columns only), 2 abs values (|A| |x|), 4 residual y = b - A x,
+// 8 free rows only (all columns)
+
+template <class TV>
+void launch_bj_factor(hipStream_t st, int nnodes, const int* diag_blk, const void* vals, int vals_fp32,
+                      const uint16_t* freemask, const int* node_shell, TV* dinv, int* fail_shell);
+
+void launch_save_diag(hipStream_t st, int nnodes, const int* diag_blk, const void* vals, int vals_fp32, double* diag);
+void launch_regularize(hipStream_t st, int nnodes, const int* diag_blk, void* vals, int vals_fp32,
+                       const double* diag, const int* node_shell, const double* delta_shell);
+
+template <class TM, class TV>
+hipError_t launch_cg(hipStream_t st, int nblk, const RowBlocks& rb, const int* row_ptr, const int* col_idx,
+                     const TM* vals, const TV* dinv, const uint16_t* freemask, const double* b, TV* x, TV* r, TV* z,
+                     TV* p0, TV* p1, TV* qv, double* partial, unsigned* bar, int* abort_flag, const double* rtol2_shell,
+                     const int* maxit_shell, const int* active_shell, CgShellOut* out);
+int cg_max_blocks(int device, int tm_fp32, int tv_fp32);
+
+// per-shell reductions over node rows (masked = free DOFs only):
+// out[s] = sum x.y over shell s (y = x for norms)
+void launch_shell_dot(hipStream_t st, const RowBlocks& rb, int nshell, const double* x, const double* y,
+                      const uint16_t* freemask, double* partial, double* out);
+
+// elementwise helpers
+void launch_predict(hipStream_t st, int n, const double* qn, const double* vn, const double* qpresc,
+                    const uint16_t* freemask, double dt, double* qhat, double* q);
+void launch_axpy_shell(hipStream_t st, int nnodes, const double* x, const double* d, const double* alpha_shell,
+                       const int* node_shell, double* out);
+void launch_neg_masked(hipStream_t st, int nnodes, const double* g, const uint16_t* freemask,
+                       const int* node_shell, const int* active_shell, double* b);
+void launch_velocity(hipStream_t st, int n, const double* q1, const double* qn, double dt, double* v);
+void launch_copy_shell(hipStream_t st, int nnodes, const double* src, const int* node_shell, const int* flag_shell,
+                       double* dst);
+template <class TV>
+void launch_add_to(hipStream_t st, int n, const TV* dx, double* x);
+void launch_cast_to_float(hipStream_t st, int n, const double* x, float* y);
+
+}  // namespace bhem

@@ -1,0 +1,370 @@
+// Per-patch quadrature kernels of libbhem (gfx950).
+//
+//   k_energy_grad  energy and gradient of every patch (FP64), 16 lanes per
+//                  patch: one lane per Gauss point, then one lane per local
+//                  basis function.
+//   k_hessian      48x48 patch Hessian (FP64 or FP32) scattered into the
+//                  12x12-block matrix, one wavefront per patch:
+//                    1. four lanes per Gauss point build the 15x15 second
+//                       derivative W_g of the energy density (+ the mass term);
+//                    2. per component pair (i, j) the matrix cores contract
+//                       K^{ij} = sum_g Phi_g^T W_g^{ij} Phi_g  (16 x 80(96) x 16);
+//                    3. the 16 node blocks are added into the matrix
+//                       (patches of one colour share no node, so plain
+//                       read-modify-write is race free).
+//
+// Quadrature, basis and model follow the paper (Sec. 3-4, Appendix A-B);
+// the reduced-form derivatives are documented in shell_physics.hpp.
+// Local coordinates: corner c = p + 2q (node (i+p, j+q)), kind k = r + 2s,
+// I = 4c + k; local DOF 12 c + 3 k + component.
+#include "device_common.hpp"
+#include "kernels.hpp"
+#include "shell_physics.hpp"
+
+namespace bhem {
+
+// ---------------------------------------------------------------- K1
+// Energies: e_patch[p][0] elastic, [1] kinetic (mass_scale/2)(x - xhat)^T rho h (x - xhat),
+// [2] load -rho h g.(x - xhat).  Gradient of their sum per patch in g_patch[p][48].
+constexpr int EG_PATCHES = 16;   // patches per 256-thread block
+
+__global__ __launch_bounds__(256) void k_energy_grad(int npatch, const int4* __restrict__ patch_nodes,
+                                                     const int* __restrict__ patch_shell,
+                                                     const ShellParams* __restrict__ shells,
+                                                     const double* __restrict__ phi,
+                                                     const double* __restrict__ q, const double* __restrict__ qbar,
+                                                     const double* __restrict__ qhat, double mass_scale, int elastic,
+                                                     int loads, double* __restrict__ e_patch,
+                                                     double* __restrict__ g_patch) {
+    __shared__ double s_u[EG_PATCHES][48], s_b[EG_PATCHES][48], s_d[EG_PATCHES][48];
+    __shared__ double s_dpsi[EG_PATCHES][16][18];
+    const int lane = threadIdx.x & 15, pl = threadIdx.x >> 4;
+    const int patch = blockIdx.x * EG_PATCHES + pl;
+    const bool active = patch < npatch;
+    ShellParams sp;
+    int4 nd = make_int4(0, 0, 0, 0);
+    if (active) {
+        sp = shells[patch_shell[patch]];
+        nd = patch_nodes[patch];
+    }
+    // phase 0: gather u = q - qbar, qbar and q - qhat, scaled to theta-derivatives
+    if (active) {
+        const int nodes[4] = {nd.x, nd.y, nd.z, nd.w};
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const int d = lane * 3 + t, c = d / 12, w = d % 12;
+            const double ks = kind_scale(w / 3, sp.dxi1, sp.dxi2);
+            const size_t gi = (size_t)nodes[c] * 12 + w;
+            const double qq = q[gi], qb = qbar[gi];
+            s_u[pl][d] = ks * (qq - qb);
+            s_b[pl][d] = ks * qb;
+            s_d[pl][d] = qhat ? ks * (qq - qhat[gi]) : 0.0;
+        }
+    }
+    __syncthreads();
+    // phase 1: lane = Gauss point
+    double e_el = 0.0, e_kin = 0.0, e_ld = 0.0;
+    if (active) {
+        const int g = lane;
+        double kin[30], xd[3] = {0, 0, 0};
+        const double* ph = phi + g * 96;
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            const double sc = slot_scale(a, sp.dxi1, sp.dxi2);
+#pragma unroll
+            for (int comp = 0; comp < 3; ++comp) {
+                double sb = 0.0, su = 0.0;
+                for (int I = 0; I < 16; ++I) {
+                    const double f = ph[a * 16 + I];
+                    sb += f * s_b[pl][3 * I + comp];
+                    su += f * s_u[pl][3 * I + comp];
+                }
+                kin[3 * a + comp] = sc * sb;
+                kin[15 + 3 * a + comp] = sc * su;
+            }
+        }
+#pragma unroll
+        for (int comp = 0; comp < 3; ++comp) {
+            double s = 0.0;
+            for (int I = 0; I < 16; ++I) s += ph[5 * 16 + I] * s_d[pl][3 * I + comp];
+            xd[comp] = s;
+        }
+        GaussPoint<double> G;
+        const double wt = gauss_weight(g & 3) * gauss_weight(g >> 2) * sp.dxi1 * sp.dxi2;
+        gauss_point<double>(kin, wt, sp.lam, sp.mu, sp.h, G);
+        double dp[15];
+        dpsi_dg<double>(G, dp);
+        const double el = elastic ? 1.0 : 0.0;
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            const double sc = G.wq * el * slot_scale(a, sp.dxi1, sp.dxi2);
+#pragma unroll
+            for (int comp = 0; comp < 3; ++comp) s_dpsi[pl][g][3 * a + comp] = sc * dp[3 * a + comp];
+        }
+        const double rh = sp.rho_h * G.wq;
+        const double gx = loads ? sp.grav[0] : 0.0, gy = loads ? sp.grav[1] : 0.0, gz = loads ? sp.grav[2] : 0.0;
+        s_dpsi[pl][g][15] = rh * (mass_scale * xd[0] - gx);
+        s_dpsi[pl][g][16] = rh * (mass_scale * xd[1] - gy);
+        s_dpsi[pl][g][17] = rh * (mass_scale * xd[2] - gz);
+        e_el = el * G.wq * G.psi;
+        e_kin = 0.5 * mass_scale * rh * (xd[0] * xd[0] + xd[1] * xd[1] + xd[2] * xd[2]);
+        e_ld = -rh * (gx * xd[0] + gy * xd[1] + gz * xd[2]);
+    }
+    // patch energies: reduce over the 16 lanes of the patch
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) {
+        e_el += __shfl_xor(e_el, off, 16);
+        e_kin += __shfl_xor(e_kin, off, 16);
+        e_ld += __shfl_xor(e_ld, off, 16);
+    }
+    if (active && lane == 0) {
+        e_patch[3 * (size_t)patch + 0] = e_el;
+        e_patch[3 * (size_t)patch + 1] = e_kin;
+        e_patch[3 * (size_t)patch + 2] = e_ld;
+    }
+    __syncthreads();
+    // phase 2: lane = local basis function I
+    if (active) {
+        const int I = lane;
+        const double ks = kind_scale(I & 3, sp.dxi1, sp.dxi2);
+        double gr[3] = {0, 0, 0};
+        for (int g = 0; g < 16; ++g) {
+            const double* ph = phi + g * 96;
+#pragma unroll
+            for (int a = 0; a < 6; ++a) {
+                const double f = ph[a * 16 + I];
+#pragma unroll
+                for (int comp = 0; comp < 3; ++comp) gr[comp] += f * s_dpsi[pl][g][3 * a + comp];
+            }
+        }
+#pragma unroll
+        for (int comp = 0; comp < 3; ++comp) g_patch[48 * (size_t)patch + 3 * I + comp] = ks * gr[comp];
+    }
+}
+
+// Nodal gradient: sum of the patch contributions of every node.  With
+// mask != 0 prescribed DOFs get 0.  Only nodes of shells with write_shell[s]
+// set are written (NULL = all).
+__global__ void k_gather_grad(int nnodes, const int* __restrict__ inc_ptr, const int* __restrict__ inc,
+                              const double* __restrict__ g_patch, const uint16_t* __restrict__ freemask,
+                              const int* __restrict__ node_shell, const int* __restrict__ write_shell,
+                              double* __restrict__ grad) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int node = t / 12, w = t % 12;
+    if (node >= nnodes) return;
+    if (write_shell && !write_shell[node_shell[node]]) return;
+    double s = 0.0;
+    for (int k = inc_ptr[node]; k < inc_ptr[node + 1]; ++k) {
+        const int pc = inc[k];   // patch * 4 + corner
+        s += g_patch[48 * (size_t)(pc >> 2) + 12 * (pc & 3) + w];
+    }
+    if (freemask && !((freemask[node] >> w) & 1)) s = 0.0;
+    grad[(size_t)node * 12 + w] = s;
+}
+
+// Per-shell sums of the three patch energies, fixed summation order.
+__global__ void k_shell_energy(int nshell, const ShellParams* __restrict__ shells, const double* __restrict__ e_patch,
+                               double* __restrict__ e_shell) {
+    const int s = blockIdx.x;
+    if (s >= nshell) return;
+    __shared__ double red[3][256];
+    double a0 = 0, a1 = 0, a2 = 0;
+    for (int p = shells[s].patch_begin + threadIdx.x; p < shells[s].patch_end; p += blockDim.x) {
+        a0 += e_patch[3 * (size_t)p];
+        a1 += e_patch[3 * (size_t)p + 1];
+        a2 += e_patch[3 * (size_t)p + 2];
+    }
+    red[0][threadIdx.x] = a0;
+    red[1][threadIdx.x] = a1;
+    red[2][threadIdx.x] = a2;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) e_shell[3 * s + k] = red[k][0];
+}
+
+// ---------------------------------------------------------------- K2
+constexpr int HS_WAVES = 4;   // patches (wavefronts) per block
+
+__host__ __device__ constexpr int pair_index(int i, int j) {   // i <= j
+    return i == j ? i : (i == 0 ? (j == 1 ? 3 : 4) : 5);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_hessian(const int* __restrict__ patch_list, int nlist,
+                                                 const int4* __restrict__ patch_nodes,
+                                                 const int* __restrict__ patch_shell,
+                                                 const int* __restrict__ patch_slots,
+                                                 const ShellParams* __restrict__ shells,
+                                                 const double* __restrict__ phi, const double* __restrict__ q,
+                                                 const double* __restrict__ qbar, double mass_scale, int elastic,
+                                                 int pseudo, T* __restrict__ vals) {
+    typedef Mfma<T> MM;
+    constexpr int WSZ = 16 * 121;   // packed W per Gauss point (+ mass term) and pair staging (6*256)
+    static_assert(WSZ >= 6 * 256, "staging must fit");
+    __shared__ T s_u[HS_WAVES][48], s_b[HS_WAVES][48];
+    __shared__ T s_kin[HS_WAVES][16][30];
+    __shared__ T s_w[HS_WAVES][WSZ];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int li = blockIdx.x * HS_WAVES + wv;
+    const bool active = li < nlist;
+    const int patch = active ? patch_list[li] : 0;
+    ShellParams sp = shells[active ? patch_shell[patch] : 0];
+    const int4 nd = patch_nodes[patch];
+    const int nodes[4] = {nd.x, nd.y, nd.z, nd.w};
+    T* W = s_w[wv];
+    // phase 0: displacement and reference coordinates (theta-scaled)
+    if (active && lane < 48) {
+        const int c = lane / 12, w = lane % 12;
+        const double ks = kind_scale(w / 3, sp.dxi1, sp.dxi2);
+        const size_t gi = (size_t)nodes[c] * 12 + w;
+        const double qb = qbar[gi];
+        s_u[wv][lane] = (T)(ks * (q[gi] - qb));
+        s_b[wv][lane] = (T)(ks * qb);
+    }
+    __syncthreads();
+    // phase 1a: kinematics, 30 values per Gauss point split over 4 lanes
+    const int g = lane >> 2, quarter = lane & 3;
+    if (active) {
+        const double* ph = phi + g * 96;
+        for (int vi = quarter; vi < 30; vi += 4) {
+            const int src = vi / 15, a = (vi % 15) / 3, comp = vi % 3;
+            const T* x = src ? s_u[wv] : s_b[wv];
+            T acc = T(0);
+            for (int I = 0; I < 16; ++I) acc += (T)ph[a * 16 + I] * x[3 * I + comp];
+            s_kin[wv][g][vi] = acc * (T)slot_scale(a, sp.dxi1, sp.dxi2);
+        }
+    }
+    __syncthreads();
+    // phase 1b: 15x15 second derivative of the energy density (+ mass term)
+    if (active) {
+        T kin[30];
+#pragma unroll
+        for (int k = 0; k < 30; ++k) kin[k] = s_kin[wv][g][k];
+        GaussPoint<T> G;
+        const T wt = (T)(gauss_weight(g & 3) * gauss_weight(g >> 2) * sp.dxi1 * sp.dxi2);
+        gauss_point<T>(kin, wt, (T)sp.lam, (T)sp.mu, (T)sp.h, G);
+        T* Wg = W + g * 121;
+        if (elastic) {
+            T sc[5];
+#pragma unroll
+            for (int a = 0; a < 5; ++a) sc[a] = (T)slot_scale(a, sp.dxi1, sp.dxi2);
+            hess_blocks<T>(G, quarter, pseudo, sc, Wg);
+        }
+        if (quarter == 3) Wg[120] = G.wq * (T)(sp.rho_h * mass_scale);
+    }
+    __syncthreads();
+    // phase 2: K^{ij} = sum over (slot a, Gauss point g) of Phi^T W^{ij} Phi on the matrix cores.
+    // Lane operand table: ph_l[a][m] = Phi_{g = 4m + lane/16}[a][I = lane%16].
+    T ph_l[6][4];
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) ph_l[a][m] = (T)phi[((4 * m + (lane >> 4)) * 6 + a) * 16 + (lane & 15)];
+    typename MM::acc_t acc[6];
+#pragma unroll
+    for (int pr = 0; pr < 6; ++pr) acc[pr] = typename MM::acc_t{T(0), T(0), T(0), T(0)};
+    const bool has_mass = mass_scale != 0.0;
+    if (active) {
+#pragma unroll
+        for (int pr = 0; pr < 6; ++pr) {
+            const int i = pr < 3 ? pr : (pr == 5 ? 1 : 0);
+            const int j = pr < 3 ? pr : (pr == 3 ? 1 : 2);
+            if (elastic) {
+#pragma unroll
+                for (int a = 0; a < 5; ++a)
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const T* Wg = W + (4 * m + (lane >> 4)) * 121;
+                        const int r = 3 * a + i;
+                        T b = T(0);
+#pragma unroll
+                        for (int bb = 0; bb < 5; ++bb) {
+                            const int c = 3 * bb + j;
+                            const T wv_ = r <= c ? Wg[sym15(r, c)] : Wg[sym15(c, r)];
+                            b += wv_ * ph_l[bb][m];
+                        }
+                        acc[pr] = MM::mma(ph_l[a][m], b, acc[pr]);
+                    }
+            }
+            if (i == j && has_mass) {
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const T* Wg = W + (4 * m + (lane >> 4)) * 121;
+                    acc[pr] = MM::mma(ph_l[5][m], Wg[120] * ph_l[5][m], acc[pr]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // stage the six 16x16 pair blocks: P[pr][I][J]
+    if (active) {
+#pragma unroll
+        for (int pr = 0; pr < 6; ++pr)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) W[pr * 256 + MM::row(lane, v) * 16 + (lane & 15)] = acc[pr][v];
+    }
+    __syncthreads();
+    // phase 3: add the 16 node blocks (column-major 12x12) into the matrix
+    if (active) {
+        const int* slots = patch_slots + 16 * (size_t)patch;
+        for (int e = lane; e < 16 * 144; e += 64) {
+            const int blk = e / 144, w = e % 144;
+            const int c = blk >> 2, d = blk & 3;
+            const int jj = w / 12, ii = w % 12;   // column-major: w = jj*12 + ii
+            const int k = ii / 3, i = ii % 3, l = jj / 3, j = jj % 3;
+            const int I = 4 * c + k, J = 4 * d + l;
+            const T kv = i <= j ? W[pair_index(i, j) * 256 + I * 16 + J] : W[pair_index(j, i) * 256 + J * 16 + I];
+            const T s = (T)(kind_scale(k, sp.dxi1, sp.dxi2) * kind_scale(l, sp.dxi1, sp.dxi2));
+            T* dst = vals + (size_t)slots[blk] * 144 + w;
+            *dst += s * kv;
+        }
+    }
+}
+
+// ------------------------------------------------------------ launchers
+void launch_energy_grad(hipStream_t st, int npatch, const int4* patch_nodes, const int* patch_shell,
+                        const ShellParams* shells, const double* phi, const double* q, const double* qbar,
+                        const double* qhat, double mass_scale, int elastic, int loads, double* e_patch,
+                        double* g_patch) {
+    if (npatch == 0) return;
+    const int nb = (npatch + EG_PATCHES - 1) / EG_PATCHES;
+    hipLaunchKernelGGL(k_energy_grad, dim3(nb), dim3(256), 0, st, npatch, patch_nodes, patch_shell, shells, phi, q,
+                       qbar, qhat, mass_scale, elastic, loads, e_patch, g_patch);
+}
+
+void launch_gather_grad(hipStream_t st, int nnodes, const int* inc_ptr, const int* inc, const double* g_patch,
+                        const uint16_t* freemask, const int* node_shell, const int* write_shell, double* grad) {
+    const int n = nnodes * 12;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_gather_grad, dim3((n + 255) / 256), dim3(256), 0, st, nnodes, inc_ptr, inc, g_patch,
+                       freemask, node_shell, write_shell, grad);
+}
+
+void launch_shell_energy(hipStream_t st, int nshell, const ShellParams* shells, const double* e_patch,
+                         double* e_shell) {
+    hipLaunchKernelGGL(k_shell_energy, dim3(nshell), dim3(256), 0, st, nshell, shells, e_patch, e_shell);
+}
+
+template <class T>
+void launch_hessian(hipStream_t st, const int* patch_list, int nlist, const int4* patch_nodes, const int* patch_shell,
+                    const int* patch_slots, const ShellParams* shells, const double* phi, const double* q,
+                    const double* qbar, double mass_scale, int elastic, int pseudo, T* vals) {
+    if (nlist == 0) return;
+    const int nb = (nlist + HS_WAVES - 1) / HS_WAVES;
+    hipLaunchKernelGGL(k_hessian<T>, dim3(nb), dim3(256), 0, st, patch_list, nlist, patch_nodes, patch_shell,
+                       patch_slots, shells, phi, q, qbar, mass_scale, elastic, pseudo, vals);
+}
+
+template void launch_hessian<double>(hipStream_t, const int*, int, const int4*, const int*, const int*,
+                                     const ShellParams*, const double*, const double*, const double*, double, int,
+                                     int, double*);
+template void launch_hessian<float>(hipStream_t, const int*, int, const int4*, const int*, const int*,
+                                    const ShellParams*, const double*, const double*, const double*, double, int,
+                                    int, float*);
+
+}  // namespace bhem

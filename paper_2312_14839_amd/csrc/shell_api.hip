@@ -1,0 +1,1015 @@
+// Host side of libbhem: context creation (grid layout, colouring, block
+// sparsity pattern, device buffers), the C ABI of include/bhem_shell.h and
+// the implicit-Euler Newton driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/bhem_shell.h"
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+using namespace bhem;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t n = 0;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+template <class T> T* dptr(DevBuf& b) { return static_cast<T*>(b.p); }
+
+struct HostStats {
+    double t_assemble = 0, t_pcg = 0;
+};
+
+}  // namespace
+
+struct shell_ctx {
+    shell_opts opts;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int S = 0, N = 0, P = 0;
+    long long nnzb = 0;
+    bool fp32 = false;
+    std::vector<ShellParams> shells;
+    std::vector<int> h_row_ptr, h_col_idx, h_node_shell;
+    std::vector<uint16_t> h_freemask;
+    std::vector<int> colour_off;   // [ncolour + 1] into the concatenated colour lists
+    int nblk = 0;                  // CG row blocks
+    std::vector<int> h_shell_blk0, h_shell_nblk;
+    // device data
+    DevBuf shells_d, phi, qbar, freemask, node_shell, patch_nodes, patch_shell, patch_slots, colour_list, inc_ptr,
+        inc, row_ptr, col_idx, diag_blk, vals, diag0, dinv;
+    DevBuf blk_shell, blk_row0, blk_row1, shell_blk0, shell_nblk;
+    DevBuf e_patch, g_patch, e_shell, red_part, red_out;
+    // Newton / CG work vectors (FP64 [N*12] unless noted)
+    DevBuf qhat, q, qt, g, gt, dvec, rhs, cg_x, cg_r, cg_z, cg_p0, cg_p1, cg_q, r64, x64;
+    DevBuf cg_partial, cg_bar, cg_abort, cg_rtol2, cg_maxit, cg_active, cg_out, fail_shell, delta_shell, alpha_shell,
+        flag_shell, write_shell;
+    // pinned host mirrors
+    double* h_e_shell = nullptr;   // [S*3]
+    double* h_red = nullptr;       // [S]
+    CgShellOut* h_cg_out = nullptr;
+    int* h_fail = nullptr;
+
+    RowBlocks rb() {
+        return RowBlocks{nblk, dptr<int>(blk_shell), dptr<int>(blk_row0), dptr<int>(blk_row1), dptr<int>(shell_blk0),
+                         dptr<int>(shell_nblk)};
+    }
+    ~shell_ctx() {
+        if (h_e_shell) (void)hipHostFree(h_e_shell);
+        if (h_red) (void)hipHostFree(h_red);
+        if (h_cg_out) (void)hipHostFree(h_cg_out);
+        if (h_fail) (void)hipHostFree(h_fail);
+    }
+};
+
+namespace {
+
+struct HipErr {
+    hipError_t e;
+    const char* what;
+};
+
+#define HIPCHK(call)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess) throw HipErr{e_, #call};                                            \
+    } while (0)
+
+struct InvalErr {
+    std::string msg;
+};
+struct StatusErr {
+    shell_status st;
+    std::string msg;
+};
+
+void alloc(DevBuf& b, size_t bytes) {
+    if (b.p) {
+        (void)hipFree(b.p);
+        b.p = nullptr;
+    }
+    b.n = bytes;
+    if (bytes == 0) return;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) throw StatusErr{SHELL_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+}
+
+template <class T> void upload(DevBuf& b, const std::vector<T>& v, hipStream_t st) {
+    alloc(b, v.size() * sizeof(T));
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+}
+
+void sync(shell_ctx* c) { HIPCHK(hipStreamSynchronize(c->stream)); }
+
+// Small host-to-device copy of control data, complete on return (the host
+// vector may go out of scope right after).
+void h2d(shell_ctx* c, void* dst, const void* src, size_t bytes) {
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+}
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ----------------------------------------------------------- layout
+int node_cols(const shell_desc& d) { return d.periodic1 ? d.n1 : d.n1 + 1; }
+int node_count(const shell_desc& d) { return node_cols(d) * (d.n2 + 1); }
+
+void validate(const shell_desc& d, int s) {
+    auto bad = [&](const std::string& m) { throw InvalErr{"shell " + std::to_string(s) + ": " + m}; };
+    if (d.n1 < 1 || d.n2 < 1) bad("n1 and n2 must be >= 1");
+    if (d.periodic1 && d.n1 < 3) bad("a periodic shell needs n1 >= 3");
+    if (!(d.dxi1 > 0) || !(d.dxi2 > 0)) bad("dxi1 and dxi2 must be > 0");
+    if (!d.ref_host) bad("ref_host is NULL");
+    if (!(d.young > 0) || !(d.poisson >= 0 && d.poisson < 0.5)) bad("need young > 0 and 0 <= poisson < 0.5");
+    if (!(d.thickness > 0) || !(d.density > 0)) bad("thickness and density must be > 0");
+    if ((long long)d.n1 * d.n2 > (1 << 26)) bad("grid too large");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(d.gravity[k])) bad("gravity not finite");
+    const int nn = node_count(d);
+    for (long long i = 0; i < 12LL * nn; ++i)
+        if (!std::isfinite(d.ref_host[i])) bad("reference coordinates not finite");
+}
+
+void build(shell_ctx* c, const shell_desc* ds, int S) {
+    hipStream_t st = c->stream;
+    c->S = S;
+    // node and patch ranges
+    int N = 0, P = 0;
+    c->shells.resize(S);
+    for (int s = 0; s < S; ++s) {
+        const shell_desc& d = ds[s];
+        ShellParams& sp = c->shells[s];
+        sp.dxi1 = d.dxi1;
+        sp.dxi2 = d.dxi2;
+        sp.lam = d.young * d.poisson / (1.0 - d.poisson * d.poisson);
+        sp.mu = d.young / (2.0 * (1.0 + d.poisson));
+        sp.h = d.thickness;
+        sp.rho_h = d.density * d.thickness;
+        for (int k = 0; k < 3; ++k) sp.grav[k] = d.gravity[k];
+        sp.node_begin = N;
+        N += node_count(d);
+        sp.node_end = N;
+        sp.patch_begin = P;
+        P += d.n1 * d.n2;
+        sp.patch_end = P;
+    }
+    c->N = N;
+    c->P = P;
+    // per-node data
+    std::vector<double> qbar((size_t)N * 12);
+    c->h_freemask.assign(N, 0);
+    c->h_node_shell.assign(N, 0);
+    for (int s = 0; s < S; ++s) {
+        const shell_desc& d = ds[s];
+        const int nb = c->shells[s].node_begin, nn = node_count(d);
+        std::memcpy(&qbar[(size_t)nb * 12], d.ref_host, sizeof(double) * 12 * nn);
+        for (int i = 0; i < nn; ++i) {
+            uint16_t m = 0;
+            for (int w = 0; w < 12; ++w)
+                if (!d.fixed_host || !d.fixed_host[12 * i + w]) m |= (uint16_t)(1u << w);
+            c->h_freemask[nb + i] = m;
+            c->h_node_shell[nb + i] = s;
+        }
+    }
+    // patches, colours, pattern
+    std::vector<int4> pnodes(P);
+    std::vector<int> pshell(P);
+    std::vector<std::vector<int>> colour_lists(6);
+    std::vector<std::vector<int>> adj(N);
+    for (int s = 0; s < S; ++s) {
+        const shell_desc& d = ds[s];
+        const int cols = node_cols(d), nb = c->shells[s].node_begin;
+        for (int pj = 0; pj < d.n2; ++pj)
+            for (int pi = 0; pi < d.n1; ++pi) {
+                const int p = c->shells[s].patch_begin + pj * d.n1 + pi;
+                int nd[4];
+                for (int cc = 0; cc < 4; ++cc) {
+                    int i = pi + (cc & 1), j = pj + (cc >> 1);
+                    if (d.periodic1) i %= d.n1;
+                    nd[cc] = nb + j * cols + i;
+                }
+                pnodes[p] = make_int4(nd[0], nd[1], nd[2], nd[3]);
+                pshell[p] = s;
+                // colours: patches of one colour share no node.  Along a
+                // periodic direction with odd n1 the last column gets a third colour.
+                int cx = pi & 1;
+                if (d.periodic1 && (d.n1 & 1) && pi == d.n1 - 1) cx = 2;
+                colour_lists[cx + 3 * (pj & 1)].push_back(p);
+                for (int a = 0; a < 4; ++a)
+                    for (int b = 0; b < 4; ++b) adj[nd[a]].push_back(nd[b]);
+            }
+    }
+    // verify the colouring: no node touched twice within a colour
+    {
+        std::vector<int> seen(N, -1);
+        for (int col = 0; col < 6; ++col)
+            for (int p : colour_lists[col]) {
+                const int nd[4] = {pnodes[p].x, pnodes[p].y, pnodes[p].z, pnodes[p].w};
+                for (int a = 0; a < 4; ++a) {
+                    if (seen[nd[a]] == col) throw InvalErr{"internal: patch colouring conflict"};
+                    seen[nd[a]] = col;
+                }
+            }
+    }
+    c->h_row_ptr.assign(N + 1, 0);
+    c->h_col_idx.clear();
+    std::vector<int> diag(N);
+    for (int n = 0; n < N; ++n) {
+        auto& a = adj[n];
+        std::sort(a.begin(), a.end());
+        a.erase(std::unique(a.begin(), a.end()), a.end());
+        for (size_t k = 0; k < a.size(); ++k)
+            if (a[k] == n) diag[n] = (int)c->h_col_idx.size() + (int)k;
+        c->h_col_idx.insert(c->h_col_idx.end(), a.begin(), a.end());
+        c->h_row_ptr[n + 1] = (int)c->h_col_idx.size();
+    }
+    c->nnzb = (long long)c->h_col_idx.size();
+    std::vector<int> slots((size_t)P * 16);
+    std::vector<std::vector<int>> inc(N);
+    for (int p = 0; p < P; ++p) {
+        const int nd[4] = {pnodes[p].x, pnodes[p].y, pnodes[p].z, pnodes[p].w};
+        for (int a = 0; a < 4; ++a) {
+            inc[nd[a]].push_back(4 * p + a);
+            for (int b = 0; b < 4; ++b) {
+                const int* beg = &c->h_col_idx[c->h_row_ptr[nd[a]]];
+                const int* end = &c->h_col_idx[0] + c->h_row_ptr[nd[a] + 1];
+                slots[(size_t)p * 16 + 4 * a + b] = (int)(std::lower_bound(beg, end, nd[b]) - &c->h_col_idx[0]);
+            }
+        }
+    }
+    std::vector<int> inc_ptr(N + 1, 0), inc_flat;
+    for (int n = 0; n < N; ++n) {
+        inc_flat.insert(inc_flat.end(), inc[n].begin(), inc[n].end());
+        inc_ptr[n + 1] = (int)inc_flat.size();
+    }
+    std::vector<int> clist;
+    c->colour_off.assign(1, 0);
+    for (int col = 0; col < 6; ++col) {
+        clist.insert(clist.end(), colour_lists[col].begin(), colour_lists[col].end());
+        c->colour_off.push_back((int)clist.size());
+    }
+    // CG row blocks: contiguous node rows, never straddling a shell
+    const int cap = cg_max_blocks(c->opts.device, c->fp32, c->fp32);
+    if (cap <= 0) throw StatusErr{SHELL_E_DEVICE, "cannot query CG kernel occupancy"};
+    if (S > cap) throw InvalErr{"too many shells for one context (limit " + std::to_string(cap) + ")"};
+    const int pass = c->fp32 ? 4 * 21 : 4 * 10;   // node rows per block pass of the CG kernel
+    int target = std::max(pass, (N + cap - 1) / cap);
+    target = ((target + pass - 1) / pass) * pass;
+    std::vector<int> bshell, brow0, brow1;
+    c->h_shell_blk0.assign(S, 0);
+    c->h_shell_nblk.assign(S, 0);
+    int used = 0;
+    for (int s = 0; s < S; ++s) {
+        const int r0 = c->shells[s].node_begin, r1 = c->shells[s].node_end;
+        int nb = std::max(1, (r1 - r0 + target - 1) / target);
+        c->h_shell_blk0[s] = used;
+        c->h_shell_nblk[s] = nb;
+        for (int k = 0; k < nb; ++k) {
+            bshell.push_back(s);
+            brow0.push_back(r0 + (int)((long long)(r1 - r0) * k / nb));
+            brow1.push_back(r0 + (int)((long long)(r1 - r0) * (k + 1) / nb));
+        }
+        used += nb;
+    }
+    if (used > cap) {
+        // fall back to fewer blocks per shell
+        throw InvalErr{"grid needs more co-resident CG blocks than the device holds"};
+    }
+    c->nblk = used;
+    // theta-space basis table
+    std::vector<double> phi(16 * 6 * 16);
+    build_theta_basis(phi.data());
+    // uploads
+    upload(c->shells_d, c->shells, st);
+    upload(c->phi, phi, st);
+    upload(c->qbar, qbar, st);
+    upload(c->freemask, c->h_freemask, st);
+    upload(c->node_shell, c->h_node_shell, st);
+    upload(c->patch_nodes, pnodes, st);
+    upload(c->patch_shell, pshell, st);
+    upload(c->patch_slots, slots, st);
+    upload(c->colour_list, clist, st);
+    upload(c->inc_ptr, inc_ptr, st);
+    upload(c->inc, inc_flat, st);
+    upload(c->row_ptr, c->h_row_ptr, st);
+    upload(c->col_idx, c->h_col_idx, st);
+    upload(c->diag_blk, diag, st);
+    upload(c->blk_shell, bshell, st);
+    upload(c->blk_row0, brow0, st);
+    upload(c->blk_row1, brow1, st);
+    upload(c->shell_blk0, c->h_shell_blk0, st);
+    upload(c->shell_nblk, c->h_shell_nblk, st);
+    const size_t vecb = (size_t)N * 12 * sizeof(double);
+    alloc(c->vals, (size_t)c->nnzb * 144 * (c->fp32 ? sizeof(float) : sizeof(double)));
+    alloc(c->diag0, vecb);
+    alloc(c->dinv, (size_t)N * 144 * (c->fp32 ? sizeof(float) : sizeof(double)));
+    alloc(c->e_patch, (size_t)std::max(P, 1) * 3 * sizeof(double));
+    alloc(c->g_patch, (size_t)std::max(P, 1) * 48 * sizeof(double));
+    alloc(c->e_shell, (size_t)S * 3 * sizeof(double));
+    alloc(c->red_part, (size_t)c->nblk * sizeof(double));
+    alloc(c->red_out, (size_t)S * sizeof(double));
+    for (DevBuf* b : {&c->qhat, &c->q, &c->qt, &c->g, &c->gt, &c->dvec, &c->rhs, &c->r64, &c->x64}) alloc(*b, vecb);
+    const size_t tvb = (size_t)N * 12 * (c->fp32 ? sizeof(float) : sizeof(double));
+    for (DevBuf* b : {&c->cg_x, &c->cg_r, &c->cg_z, &c->cg_p0, &c->cg_p1, &c->cg_q}) alloc(*b, tvb);
+    alloc(c->cg_partial, (size_t)c->nblk * 4 * sizeof(double));
+    alloc(c->cg_bar, (size_t)S * sizeof(unsigned));
+    alloc(c->cg_abort, sizeof(int));
+    alloc(c->cg_rtol2, (size_t)S * sizeof(double));
+    alloc(c->cg_maxit, (size_t)S * sizeof(int));
+    alloc(c->cg_active, (size_t)S * sizeof(int));
+    alloc(c->cg_out, (size_t)S * sizeof(CgShellOut));
+    alloc(c->fail_shell, (size_t)S * sizeof(int));
+    alloc(c->delta_shell, (size_t)S * sizeof(double));
+    alloc(c->alpha_shell, (size_t)S * sizeof(double));
+    alloc(c->flag_shell, (size_t)S * sizeof(int));
+    alloc(c->write_shell, (size_t)S * sizeof(int));
+    HIPCHK(hipHostMalloc((void**)&c->h_e_shell, (size_t)S * 3 * sizeof(double), 0));
+    HIPCHK(hipHostMalloc((void**)&c->h_red, (size_t)S * sizeof(double), 0));
+    HIPCHK(hipHostMalloc((void**)&c->h_cg_out, (size_t)S * sizeof(CgShellOut), 0));
+    HIPCHK(hipHostMalloc((void**)&c->h_fail, (size_t)S * sizeof(int), 0));
+    HIPCHK(hipMemsetAsync(c->vals.p, 0, c->vals.n, st));
+    sync(c);
+}
+
+// -------------------------------------------------------- building blocks
+// Energies (three parts per shell, host) and gradient at q_in.
+void eval_energy_grad(shell_ctx* c, const double* q_in, const double* qhat, double mass_scale, int loads,
+                      bool masked, double* grad_out, const int* write_shell_dev) {
+    hipStream_t st = c->stream;
+    launch_energy_grad(st, c->P, dptr<int4>(c->patch_nodes), dptr<int>(c->patch_shell),
+                       dptr<ShellParams>(c->shells_d), dptr<double>(c->phi), q_in, dptr<double>(c->qbar), qhat,
+                       mass_scale, 1, loads, dptr<double>(c->e_patch), dptr<double>(c->g_patch));
+    launch_shell_energy(st, c->S, dptr<ShellParams>(c->shells_d), dptr<double>(c->e_patch), dptr<double>(c->e_shell));
+    if (grad_out)
+        launch_gather_grad(st, c->N, dptr<int>(c->inc_ptr), dptr<int>(c->inc), dptr<double>(c->g_patch),
+                           masked ? dptr<uint16_t>(c->freemask) : nullptr, dptr<int>(c->node_shell), write_shell_dev,
+                           grad_out);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(c->h_e_shell, c->e_shell.p, (size_t)c->S * 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+}
+
+// per-shell x.y over free DOFs (masked) or all DOFs; result in c->h_red after sync
+void shell_dot(shell_ctx* c, const double* x, const double* y, bool masked) {
+    launch_shell_dot(c->stream, c->rb(), c->S, x, y, masked ? dptr<uint16_t>(c->freemask) : nullptr,
+                     dptr<double>(c->red_part), dptr<double>(c->red_out));
+    HIPCHK(hipMemcpyAsync(c->h_red, c->red_out.p, (size_t)c->S * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+}
+
+void assemble(shell_ctx* c, const double* q_in, double mass_scale, int elastic) {
+    hipStream_t st = c->stream;
+    HIPCHK(hipMemsetAsync(c->vals.p, 0, c->vals.n, st));
+    const int pseudo = c->opts.hessian == SHELL_HESS_PSEUDO;
+    for (size_t col = 0; col + 1 < c->colour_off.size(); ++col) {
+        const int off = c->colour_off[col], n = c->colour_off[col + 1] - off;
+        const int* list = dptr<int>(c->colour_list) + off;
+        if (c->fp32)
+            launch_hessian<float>(st, list, n, dptr<int4>(c->patch_nodes), dptr<int>(c->patch_shell),
+                                  dptr<int>(c->patch_slots), dptr<ShellParams>(c->shells_d), dptr<double>(c->phi), q_in,
+                                  dptr<double>(c->qbar), mass_scale, elastic, pseudo, dptr<float>(c->vals));
+        else
+            launch_hessian<double>(st, list, n, dptr<int4>(c->patch_nodes), dptr<int>(c->patch_shell),
+                                   dptr<int>(c->patch_slots), dptr<ShellParams>(c->shells_d), dptr<double>(c->phi),
+                                   q_in, dptr<double>(c->qbar), mass_scale, elastic, pseudo, dptr<double>(c->vals));
+    }
+    HIPCHK(hipGetLastError());
+}
+
+void spmv(shell_ctx* c, const double* x, const double* b, double* y, int mode) {
+    if (c->fp32)
+        launch_spmv<float>(c->stream, c->N, dptr<int>(c->row_ptr), dptr<int>(c->col_idx), dptr<float>(c->vals),
+                           dptr<uint16_t>(c->freemask), x, b, y, mode);
+    else
+        launch_spmv<double>(c->stream, c->N, dptr<int>(c->row_ptr), dptr<int>(c->col_idx), dptr<double>(c->vals),
+                            dptr<uint16_t>(c->freemask), x, b, y, mode);
+    HIPCHK(hipGetLastError());
+}
+
+// Factor the block-Jacobi preconditioner; per-shell failure flags in h_fail.
+void bj_factor(shell_ctx* c) {
+    hipStream_t st = c->stream;
+    HIPCHK(hipMemsetAsync(c->fail_shell.p, 0, c->fail_shell.n, st));
+    if (c->fp32)
+        launch_bj_factor<float>(st, c->N, dptr<int>(c->diag_blk), c->vals.p, 1, dptr<uint16_t>(c->freemask),
+                                dptr<int>(c->node_shell), dptr<float>(c->dinv), dptr<int>(c->fail_shell));
+    else
+        launch_bj_factor<double>(st, c->N, dptr<int>(c->diag_blk), c->vals.p, 0, dptr<uint16_t>(c->freemask),
+                                 dptr<int>(c->node_shell), dptr<double>(c->dinv), dptr<int>(c->fail_shell));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(c->h_fail, c->fail_shell.p, (size_t)c->S * sizeof(int), hipMemcpyDeviceToHost, st));
+    sync(c);
+}
+
+// One CG launch on rhs b for the shells with active[s]; solution in cg_x.
+void cg_launch(shell_ctx* c, const double* b, const std::vector<int>& active, const std::vector<double>& rtol,
+               int maxit) {
+    hipStream_t st = c->stream;
+    std::vector<double> rt2(c->S);
+    std::vector<int> mi(c->S, maxit);
+    for (int s = 0; s < c->S; ++s) rt2[s] = rtol[s] * rtol[s];
+    h2d(c, c->cg_rtol2.p, rt2.data(), c->S * sizeof(double));
+    h2d(c, c->cg_maxit.p, mi.data(), c->S * sizeof(int));
+    h2d(c, c->cg_active.p, active.data(), c->S * sizeof(int));
+    HIPCHK(hipMemsetAsync(c->cg_bar.p, 0, c->cg_bar.n, st));
+    HIPCHK(hipMemsetAsync(c->cg_abort.p, 0, c->cg_abort.n, st));
+    hipError_t e;
+    if (c->fp32)
+        e = launch_cg<float, float>(st, c->nblk, c->rb(), dptr<int>(c->row_ptr), dptr<int>(c->col_idx),
+                                    dptr<float>(c->vals), dptr<float>(c->dinv), dptr<uint16_t>(c->freemask), b,
+                                    dptr<float>(c->cg_x), dptr<float>(c->cg_r), dptr<float>(c->cg_z),
+                                    dptr<float>(c->cg_p0), dptr<float>(c->cg_p1), dptr<float>(c->cg_q),
+                                    dptr<double>(c->cg_partial), dptr<unsigned>(c->cg_bar), dptr<int>(c->cg_abort),
+                                    dptr<double>(c->cg_rtol2), dptr<int>(c->cg_maxit), dptr<int>(c->cg_active),
+                                    dptr<CgShellOut>(c->cg_out));
+    else
+        e = launch_cg<double, double>(st, c->nblk, c->rb(), dptr<int>(c->row_ptr), dptr<int>(c->col_idx),
+                                      dptr<double>(c->vals), dptr<double>(c->dinv), dptr<uint16_t>(c->freemask), b,
+                                      dptr<double>(c->cg_x), dptr<double>(c->cg_r), dptr<double>(c->cg_z),
+                                      dptr<double>(c->cg_p0), dptr<double>(c->cg_p1), dptr<double>(c->cg_q),
+                                      dptr<double>(c->cg_partial), dptr<unsigned>(c->cg_bar), dptr<int>(c->cg_abort),
+                                      dptr<double>(c->cg_rtol2), dptr<int>(c->cg_maxit), dptr<int>(c->cg_active),
+                                      dptr<CgShellOut>(c->cg_out));
+    HIPCHK(e);
+    HIPCHK(hipMemcpyAsync(c->h_cg_out, c->cg_out.p, (size_t)c->S * sizeof(CgShellOut), hipMemcpyDeviceToHost, st));
+    sync(c);
+    for (int s = 0; s < c->S; ++s)
+        if (active[s] && c->h_cg_out[s].status == 3)
+            throw StatusErr{SHELL_E_DEVICE, "CG grid barrier timed out"};
+}
+
+struct SolveResult {
+    std::vector<int> iters, status, sweeps;   // status: 0 ok, 1 cap, 2 indefinite
+    std::vector<double> relres;
+};
+
+// Solve A x = b (masked) for the active shells and write x into x_out for
+// those shells only (other shells' entries of x_out are left as they are).
+// FP64 path: one CG.  Mixed path: FP32 CG sweeps on the FP64 residual,
+// x += dx, r = b - A x in FP64, until ||r|| <= rtol ||b||.
+SolveResult solve(shell_ctx* c, const double* b, double* x_out, const std::vector<int>& active_in, double rtol,
+                  int maxit) {
+    const int S = c->S;
+    hipStream_t st = c->stream;
+    SolveResult R;
+    R.iters.assign(S, 0);
+    R.status.assign(S, 0);
+    R.sweeps.assign(S, 0);
+    R.relres.assign(S, 0.0);
+    double* x64 = dptr<double>(c->x64);
+    if (!c->fp32) {
+        cg_launch(c, b, active_in, std::vector<double>(S, rtol), maxit);
+        for (int s = 0; s < S; ++s) {
+            const CgShellOut& o = c->h_cg_out[s];
+            R.iters[s] = o.iters;
+            R.status[s] = active_in[s] ? o.status : 0;
+            R.relres[s] = o.bnorm2 > 0 ? std::sqrt(o.rnorm2 / o.bnorm2) : 0.0;
+            R.sweeps[s] = 1;
+        }
+        h2d(c, c->flag_shell.p, active_in.data(), S * sizeof(int));
+        HIPCHK(hipMemsetAsync(x64, 0, (size_t)c->N * 12 * sizeof(double), st));
+        launch_add_to<double>(st, c->N * 12, dptr<double>(c->cg_x), x64);
+        launch_copy_shell(st, c->N, x64, dptr<int>(c->node_shell), dptr<int>(c->flag_shell), x_out);
+        HIPCHK(hipGetLastError());
+        return R;
+    }
+    // mixed precision refinement
+    double* r64 = dptr<double>(c->r64);
+    HIPCHK(hipMemsetAsync(x64, 0, (size_t)c->N * 12 * sizeof(double), st));
+    HIPCHK(hipMemcpyAsync(r64, b, (size_t)c->N * 12 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    shell_dot(c, b, b, true);
+    sync(c);
+    std::vector<double> bn2(c->h_red, c->h_red + S);
+    std::vector<int> active = active_in;
+    const double inner = std::max(rtol, 1e-5);
+    std::vector<double> prev(S, 1.0);
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        bool any = false;
+        for (int s = 0; s < S; ++s) {
+            if (active[s] && bn2[s] == 0.0) active[s] = 0;
+            any |= active[s] != 0;
+        }
+        if (!any) break;
+        cg_launch(c, r64, active, std::vector<double>(S, inner), maxit);
+        for (int s = 0; s < S; ++s)
+            if (active[s]) {
+                R.iters[s] += c->h_cg_out[s].iters;
+                R.sweeps[s]++;
+                if (c->h_cg_out[s].status == 2) {
+                    R.status[s] = 2;
+                    active[s] = 0;
+                }
+            }
+        // CG leaves x = 0 for inactive shells, so the update touches active shells only
+        launch_add_to<float>(st, c->N * 12, dptr<float>(c->cg_x), x64);
+        spmv(c, x64, b, r64, 1 | 4);
+        shell_dot(c, r64, r64, true);
+        sync(c);
+        for (int s = 0; s < S; ++s) {
+            if (!active_in[s] || bn2[s] == 0.0) continue;
+            const double rel = std::sqrt(c->h_red[s] / bn2[s]);
+            if (!active[s]) continue;
+            R.relres[s] = rel;
+            if (rel <= rtol) {
+                active[s] = 0;
+            } else if (rel > 0.5 * prev[s] || R.iters[s] >= maxit) {
+                R.status[s] = 1;   // refinement stagnates
+                active[s] = 0;
+            }
+            prev[s] = rel;
+        }
+    }
+    h2d(c, c->flag_shell.p, active_in.data(), S * sizeof(int));
+    launch_copy_shell(st, c->N, x64, dptr<int>(c->node_shell), dptr<int>(c->flag_shell), x_out);
+    HIPCHK(hipGetLastError());
+    return R;
+}
+
+}  // namespace
+
+// ================================================================= C ABI
+extern "C" {
+
+void shell_default_opts(shell_opts* o) {
+    if (!o) return;
+    o->precision = SHELL_FP64;
+    o->hessian = SHELL_HESS_EXACT;
+    o->warm_start = SHELL_WS_NONE;
+    o->newton_maxit = 50;
+    o->pcg_maxit = 100000;
+    o->newton_rtol = 1e-10;
+    o->pcg_rtol = 1e-10;
+    o->device = 0;
+    o->stream = nullptr;
+}
+
+const char* shell_last_error(const shell_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+shell_status shell_create(const shell_desc* shells, int32_t n_shells, const shell_opts* o, shell_ctx** out) {
+    if (out) *out = nullptr;
+    g_create_error.clear();
+    if (!shells || n_shells < 1 || !out) {
+        g_create_error = "shells, n_shells >= 1 and out are required";
+        return SHELL_E_INVAL;
+    }
+    shell_opts opts;
+    shell_default_opts(&opts);
+    if (o) opts = *o;
+    if ((opts.precision != SHELL_FP64 && opts.precision != SHELL_MIXED) ||
+        (opts.hessian != SHELL_HESS_EXACT && opts.hessian != SHELL_HESS_PSEUDO) ||
+        (opts.warm_start != SHELL_WS_NONE && opts.warm_start != SHELL_WS_MLP) || opts.newton_maxit < 1 ||
+        opts.pcg_maxit < 1 || !(opts.newton_rtol >= 0) || !(opts.pcg_rtol > 0)) {
+        g_create_error = "invalid options";
+        return SHELL_E_INVAL;
+    }
+    if (opts.warm_start == SHELL_WS_MLP) {
+        g_create_error = "warm_start = SHELL_WS_MLP is not available in this build";
+        return SHELL_E_INVAL;
+    }
+    shell_ctx* c = nullptr;
+    try {
+        for (int s = 0; s < n_shells; ++s) validate(shells[s], s);
+        int ndev = 0;
+        HIPCHK(hipGetDeviceCount(&ndev));
+        if (opts.device < 0 || opts.device >= ndev) throw InvalErr{"invalid device ordinal"};
+        HIPCHK(hipSetDevice(opts.device));
+        c = new shell_ctx();
+        c->opts = opts;
+        c->stream = (hipStream_t)opts.stream;
+        c->fp32 = opts.precision == SHELL_MIXED;
+        build(c, shells, n_shells);
+    } catch (const InvalErr& e) {
+        g_create_error = e.msg;
+        delete c;
+        return SHELL_E_INVAL;
+    } catch (const StatusErr& e) {
+        g_create_error = e.msg;
+        delete c;
+        return e.st;
+    } catch (const HipErr& e) {
+        g_create_error = std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e);
+        delete c;
+        return SHELL_E_DEVICE;
+    } catch (const std::bad_alloc&) {
+        g_create_error = "host out of memory";
+        delete c;
+        return SHELL_E_NOMEM;
+    }
+    *out = c;
+    return SHELL_OK;
+}
+
+void shell_destroy(shell_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    delete c;
+}
+
+shell_status shell_sizes(const shell_ctx* c, int32_t* total_nodes, int32_t* total_patches, int64_t* nnzb) {
+    if (!c) return SHELL_E_INVAL;
+    if (total_nodes) *total_nodes = c->N;
+    if (total_patches) *total_patches = c->P;
+    if (nnzb) *nnzb = c->nnzb;
+    return SHELL_OK;
+}
+
+#define API_TRY try {
+#define API_CATCH                                                                     \
+    }                                                                                 \
+    catch (const InvalErr& e) {                                                       \
+        c->err = e.msg;                                                               \
+        return SHELL_E_INVAL;                                                         \
+    }                                                                                 \
+    catch (const StatusErr& e) {                                                      \
+        c->err = e.msg;                                                               \
+        return e.st;                                                                  \
+    }                                                                                 \
+    catch (const HipErr& e) {                                                         \
+        c->err = std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e); \
+        return SHELL_E_DEVICE;                                                        \
+    }
+
+shell_status shell_energy_grad_hess(shell_ctx* c, const double* q_dev, double* energy_host, double* grad_dev,
+                                    int32_t assemble_hessian) {
+    if (!c) return SHELL_E_INVAL;
+    if (!q_dev) {
+        c->err = "q_dev is NULL";
+        return SHELL_E_INVAL;
+    }
+    API_TRY
+    HIPCHK(hipSetDevice(c->opts.device));
+    eval_energy_grad(c, q_dev, nullptr, 0.0, 0, false, grad_dev, nullptr);
+    if (assemble_hessian) assemble(c, q_dev, 0.0, 1);
+    sync(c);
+    for (int s = 0; s < c->S; ++s) {
+        const double e = c->h_e_shell[3 * s];
+        if (energy_host) energy_host[s] = e;
+        if (!std::isfinite(e)) {
+            c->err = "non-finite energy in shell " + std::to_string(s);
+            return SHELL_E_NONFINITE;
+        }
+    }
+    return SHELL_OK;
+    API_CATCH
+}
+
+shell_status shell_assemble(shell_ctx* c, const double* q_dev, double mass_scale, int32_t elastic) {
+    if (!c) return SHELL_E_INVAL;
+    if (!q_dev || !std::isfinite(mass_scale)) {
+        c->err = "q_dev is NULL or mass_scale not finite";
+        return SHELL_E_INVAL;
+    }
+    API_TRY
+    HIPCHK(hipSetDevice(c->opts.device));
+    assemble(c, q_dev, mass_scale, elastic ? 1 : 0);
+    sync(c);
+    return SHELL_OK;
+    API_CATCH
+}
+
+shell_status shell_get_bsr(shell_ctx* c, int32_t shell, int32_t* nnzb, int32_t* row_ptr, int32_t* col_idx,
+                           double* vals) {
+    if (!c) return SHELL_E_INVAL;
+    if (shell < 0 || shell >= c->S || !nnzb) {
+        c->err = "invalid shell index or nnzb NULL";
+        return SHELL_E_INVAL;
+    }
+    API_TRY
+    const int n0 = c->shells[shell].node_begin, n1 = c->shells[shell].node_end;
+    const int b0 = c->h_row_ptr[n0], b1 = c->h_row_ptr[n1];
+    *nnzb = b1 - b0;
+    if (row_ptr)
+        for (int n = n0; n <= n1; ++n) row_ptr[n - n0] = c->h_row_ptr[n] - b0;
+    if (col_idx)
+        for (int b = b0; b < b1; ++b) col_idx[b - b0] = c->h_col_idx[b] - n0;
+    if (vals) {
+        const size_t cnt = (size_t)(b1 - b0) * 144;
+        std::vector<double> tmp(cnt);
+        if (c->fp32) {
+            std::vector<float> f(cnt);
+            HIPCHK(hipMemcpyAsync(f.data(), dptr<float>(c->vals) + (size_t)b0 * 144, cnt * sizeof(float),
+                                  hipMemcpyDeviceToHost, c->stream));
+            sync(c);
+            for (size_t i = 0; i < cnt; ++i) tmp[i] = f[i];
+        } else {
+            HIPCHK(hipMemcpyAsync(tmp.data(), dptr<double>(c->vals) + (size_t)b0 * 144, cnt * sizeof(double),
+                                  hipMemcpyDeviceToHost, c->stream));
+            sync(c);
+        }
+        // device blocks are column-major; the ABI returns row-major blocks
+        for (size_t b = 0; b < (size_t)(b1 - b0); ++b)
+            for (int r = 0; r < 12; ++r)
+                for (int cc = 0; cc < 12; ++cc) vals[b * 144 + r * 12 + cc] = tmp[b * 144 + cc * 12 + r];
+    }
+    return SHELL_OK;
+    API_CATCH
+}
+
+shell_status shell_spmv(shell_ctx* c, const double* x_dev, double* y_dev, int32_t masked) {
+    if (!c) return SHELL_E_INVAL;
+    if (!x_dev || !y_dev) {
+        c->err = "x_dev and y_dev are required";
+        return SHELL_E_INVAL;
+    }
+    API_TRY
+    HIPCHK(hipSetDevice(c->opts.device));
+    spmv(c, x_dev, nullptr, y_dev, masked ? 1 : 0);
+    return SHELL_OK;
+    API_CATCH
+}
+
+shell_status shell_pcg_solve(shell_ctx* c, const double* b_dev, double* x_dev, double rtol, int32_t maxit,
+                             int32_t* iters_host, double* relres_host) {
+    if (!c) return SHELL_E_INVAL;
+    if (!b_dev || !x_dev || !(rtol > 0) || maxit < 1) {
+        c->err = "b_dev, x_dev, rtol > 0 and maxit >= 1 are required";
+        return SHELL_E_INVAL;
+    }
+    API_TRY
+    HIPCHK(hipSetDevice(c->opts.device));
+    bj_factor(c);
+    for (int s = 0; s < c->S; ++s)
+        if (c->h_fail[s]) {
+            c->err = "diagonal block not positive definite in shell " + std::to_string(s);
+            return SHELL_E_INDEFINITE;
+        }
+    std::vector<int> active(c->S, 1);
+    SolveResult R = solve(c, b_dev, x_dev, active, rtol, maxit);
+    sync(c);
+    shell_status st = SHELL_OK;
+    for (int s = 0; s < c->S; ++s) {
+        if (iters_host) iters_host[s] = R.iters[s];
+        if (relres_host) relres_host[s] = R.relres[s];
+        if (R.status[s] == 2) st = SHELL_E_INDEFINITE;
+        else if (R.status[s] == 1 && st == SHELL_OK) st = SHELL_E_NOT_CONVERGED;
+    }
+    if (st != SHELL_OK) c->err = "CG did not reach the tolerance";
+    return st;
+    API_CATCH
+}
+
+// ---------------------------------------------------------- Newton step
+shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, const double* v_n_dev,
+                               const double* q_presc_dev, double* q_np1_dev, double* v_np1_dev,
+                               shell_step_stats* stats_host) {
+    if (!c) return SHELL_E_INVAL;
+    if (!(dt > 0) || !std::isfinite(dt) || !q_n_dev || !v_n_dev || !q_np1_dev || !v_np1_dev) {
+        c->err = "dt > 0 and q_n, v_n, q_np1, v_np1 are required";
+        return SHELL_E_INVAL;
+    }
+    if (q_np1_dev == q_n_dev || v_np1_dev == v_n_dev || q_np1_dev == v_n_dev) {
+        c->err = "outputs may not alias inputs";
+        return SHELL_E_INVAL;
+    }
+    API_TRY
+    HIPCHK(hipSetDevice(c->opts.device));
+    const double t_start = now_ms();
+    const int S = c->S, N12 = c->N * 12;
+    hipStream_t st = c->stream;
+    const double ms = 1.0 / (dt * dt);
+    double* q = dptr<double>(c->q);
+    double* qt = dptr<double>(c->qt);
+    double* g = dptr<double>(c->g);
+    double* gt = dptr<double>(c->gt);
+    double* d = dptr<double>(c->dvec);
+    double* rhs = dptr<double>(c->rhs);
+    double* qhat = dptr<double>(c->qhat);
+    std::vector<shell_step_stats> stats(S);
+    std::memset(stats.data(), 0, sizeof(shell_step_stats) * S);
+    launch_predict(st, N12, q_n_dev, v_n_dev, q_presc_dev, dptr<uint16_t>(c->freemask), dt, qhat, q);
+    HIPCHK(hipGetLastError());
+    // E, g at the initial guess
+    eval_energy_grad(c, q, qhat, ms, 1, true, g, nullptr);
+    shell_dot(c, g, g, true);
+    sync(c);
+    std::vector<double> E(S), Escale(S), gn(S), g0(S), floor_(S, 0.0);
+    std::vector<int> active(S, 1), status(S, SHELL_E_NOT_CONVERGED);
+    for (int s = 0; s < S; ++s) {
+        const double* e = c->h_e_shell + 3 * s;
+        E[s] = e[0] + e[1] + e[2];
+        Escale[s] = std::fabs(e[0]) + std::fabs(e[1]) + std::fabs(e[2]);
+        gn[s] = std::sqrt(c->h_red[s]);
+        g0[s] = gn[s];
+        stats[s].grad_norm0 = g0[s];
+        if (!std::isfinite(E[s]) || !std::isfinite(gn[s])) {
+            status[s] = SHELL_E_NONFINITE;
+            active[s] = 0;
+        }
+    }
+    const double eps = 2.220446049250313e-16;
+    bool have_prev = false;
+    double t_asm = 0, t_cg = 0;
+    for (int k = 0;; ++k) {
+        // rounding floor of the gradient from the previous Hessian: 4 eps || P_free |A| |q| ||
+        if (have_prev) {
+            spmv(c, q, nullptr, rhs, 8 | 2);
+            shell_dot(c, rhs, rhs, true);
+            sync(c);
+            for (int s = 0; s < S; ++s) floor_[s] = 4.0 * eps * std::sqrt(c->h_red[s]);
+        }
+        bool any = false;
+        for (int s = 0; s < S; ++s) {
+            if (!active[s]) continue;
+            stats[s].grad_norm = gn[s];
+            stats[s].grad_floor = floor_[s];
+            if (gn[s] == 0.0 || (k > 0 && gn[s] <= std::max(c->opts.newton_rtol * g0[s], floor_[s]))) {
+                status[s] = SHELL_OK;
+                active[s] = 0;
+            } else if (k == c->opts.newton_maxit) {
+                status[s] = SHELL_E_NOT_CONVERGED;
+                active[s] = 0;
+            }
+            any |= active[s] != 0;
+        }
+        if (!any) break;
+        // A = K(q) + M/dt^2, block-Jacobi, regulariser on failure
+        double t0 = now_ms();
+        assemble(c, q, ms, 1);
+        launch_save_diag(st, c->N, dptr<int>(c->diag_blk), c->vals.p, c->fp32, dptr<double>(c->diag0));
+        have_prev = true;
+        std::vector<double> delta(S, 0.0);
+        auto apply_delta = [&]() {
+            h2d(c, c->delta_shell.p, delta.data(), S * sizeof(double));
+            launch_regularize(st, c->N, dptr<int>(c->diag_blk), c->vals.p, c->fp32, dptr<double>(c->diag0),
+                              dptr<int>(c->node_shell), dptr<double>(c->delta_shell));
+        };
+        auto bump = [&](int s) -> bool {   // next regulariser value; false at the cap
+            delta[s] = delta[s] == 0.0 ? 1e-6 : delta[s] * 10.0;
+            return delta[s] <= 1e2 * (1 + 1e-12);
+        };
+        for (;;) {
+            bj_factor(c);
+            bool again = false;
+            for (int s = 0; s < S; ++s)
+                if (active[s] && c->h_fail[s]) {
+                    if (bump(s))
+                        again = true;
+                    else {
+                        status[s] = SHELL_E_INDEFINITE;
+                        active[s] = 0;
+                    }
+                }
+            if (!again) break;
+            apply_delta();
+        }
+        t_asm += now_ms() - t0;
+        t0 = now_ms();
+        // Newton direction: A d = -g
+        std::vector<int> todo = active;
+        for (;;) {
+            h2d(c, c->cg_active.p, todo.data(), S * sizeof(int));
+            launch_neg_masked(st, c->N, g, dptr<uint16_t>(c->freemask), dptr<int>(c->node_shell),
+                              dptr<int>(c->cg_active), rhs);
+            SolveResult R = solve(c, rhs, d, todo, c->opts.pcg_rtol, c->opts.pcg_maxit);
+            bool again = false;
+            for (int s = 0; s < S; ++s) {
+                if (!todo[s]) continue;
+                stats[s].pcg_iters_total += R.iters[s];
+                stats[s].refine_sweeps += R.sweeps[s];
+                if (R.status[s] == 2) {
+                    if (bump(s)) {
+                        again = true;
+                        continue;
+                    }
+                    status[s] = SHELL_E_INDEFINITE;
+                    active[s] = 0;
+                }
+                todo[s] = 0;
+            }
+            if (!again) break;
+            // regularise the failing shells, refactor, solve again for them
+            for (int s = 0; s < S; ++s)
+                if (!active[s]) todo[s] = 0;
+            apply_delta();
+            bj_factor(c);
+        }
+        // (solve() writes d only for the shells it was asked to solve, so a
+        // retry after regularising one shell keeps the others' directions)
+        for (int s = 0; s < S; ++s) stats[s].reg_delta = std::max(stats[s].reg_delta, delta[s]);
+        t_cg += now_ms() - t0;
+        bool any2 = false;
+        for (int s = 0; s < S; ++s) any2 |= active[s] != 0;
+        if (!any2) break;
+        // line search along d, per shell
+        shell_dot(c, g, d, true);
+        sync(c);
+        std::vector<double> slope(c->h_red, c->h_red + S);
+        std::vector<double> alpha(S, 0.0), a_prev(S, 0.0), E_prev(S, 0.0);
+        std::vector<int> searching(S, 0);
+        for (int s = 0; s < S; ++s)
+            if (active[s]) {
+                searching[s] = 1;
+                alpha[s] = 1.0;
+                if (!(slope[s] < 0.0)) {   // not a descent direction: fall back to -g (never expected)
+                    status[s] = SHELL_E_LINESEARCH;
+                    active[s] = 0;
+                    searching[s] = 0;
+                    alpha[s] = 0.0;
+                }
+            }
+        for (int trial = 0; trial < 20; ++trial) {
+            bool anys = false;
+            for (int s = 0; s < S; ++s) anys |= searching[s] != 0;
+            if (!anys) break;
+            std::vector<double> a_dev(S);
+            for (int s = 0; s < S; ++s) a_dev[s] = searching[s] ? alpha[s] : 0.0;
+            h2d(c, c->alpha_shell.p, a_dev.data(), S * sizeof(double));
+            launch_axpy_shell(st, c->N, q, d, dptr<double>(c->alpha_shell), dptr<int>(c->node_shell), qt);
+            eval_energy_grad(c, qt, qhat, ms, 1, true, gt, nullptr);
+            shell_dot(c, gt, gt, true);
+            sync(c);
+            std::vector<int> accept(S, 0);
+            for (int s = 0; s < S; ++s) {
+                if (!searching[s]) continue;
+                const double* e = c->h_e_shell + 3 * s;
+                const double Et = e[0] + e[1] + e[2];
+                const double sc_t = std::fabs(e[0]) + std::fabs(e[1]) + std::fabs(e[2]);
+                const double gtn = std::sqrt(c->h_red[s]);
+                bool ok = false;
+                if (std::isfinite(Et) && std::isfinite(gtn)) {
+                    if (Et <= E[s] + 1e-4 * alpha[s] * slope[s]) ok = true;
+                    const double noise = 1e-12 * std::max(Escale[s], sc_t);
+                    if (-slope[s] <= noise && std::fabs(Et - E[s]) <= noise && gtn < gn[s]) ok = true;
+                }
+                if (ok) {
+                    accept[s] = 1;
+                    searching[s] = 0;
+                    E[s] = Et;
+                    Escale[s] = sc_t;
+                    gn[s] = gtn;
+                    continue;
+                }
+                // next step: quadratic fit first, then cubic; clamped to [0.1, 0.5] alpha
+                double an;
+                const double a = alpha[s];
+                if (!std::isfinite(Et)) {
+                    an = 0.1 * a;
+                } else if (trial == 0) {
+                    an = -slope[s] * a * a / (2.0 * (Et - E[s] - slope[s] * a));
+                } else {
+                    const double ap = a_prev[s];
+                    const double d1 = Et - E[s] - slope[s] * a, d2 = E_prev[s] - E[s] - slope[s] * ap;
+                    const double den = ap * ap * a * a * (a - ap);
+                    const double ca = (ap * ap * d1 - a * a * d2) / den;
+                    const double cb = (-ap * ap * ap * d1 + a * a * a * d2) / den;
+                    if (ca == 0.0)
+                        an = -slope[s] / (2.0 * cb);
+                    else {
+                        const double disc = cb * cb - 3.0 * ca * slope[s];
+                        an = disc >= 0.0 ? (-cb + std::sqrt(disc)) / (3.0 * ca) : 0.5 * a;
+                    }
+                }
+                if (!std::isfinite(an)) an = 0.5 * a;
+                an = std::min(std::max(an, 0.1 * a), 0.5 * a);
+                a_prev[s] = a;
+                E_prev[s] = Et;
+                alpha[s] = an;
+                stats[s].ls_backtracks++;
+            }
+            h2d(c, c->flag_shell.p, accept.data(), S * sizeof(int));
+            launch_copy_shell(st, c->N, qt, dptr<int>(c->node_shell), dptr<int>(c->flag_shell), q);
+            launch_copy_shell(st, c->N, gt, dptr<int>(c->node_shell), dptr<int>(c->flag_shell), g);
+        }
+        for (int s = 0; s < S; ++s) {
+            if (active[s]) stats[s].newton_iters = k + 1;
+            if (searching[s]) {
+                status[s] = SHELL_E_LINESEARCH;
+                active[s] = 0;
+            }
+        }
+    }
+    HIPCHK(hipMemcpyAsync(q_np1_dev, q, (size_t)N12 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    launch_velocity(st, N12, q, q_n_dev, dt, v_np1_dev);
+    HIPCHK(hipGetLastError());
+    sync(c);
+    const double t_step = now_ms() - t_start;
+    shell_status worst = SHELL_OK;
+    for (int s = 0; s < S; ++s) {
+        stats[s].status = status[s];
+        stats[s].t_assemble_ms = t_asm;
+        stats[s].t_pcg_ms = t_cg;
+        stats[s].t_step_ms = t_step;
+        if (status[s] < worst) worst = status[s];
+    }
+    if (stats_host) std::memcpy(stats_host, stats.data(), sizeof(shell_step_stats) * S);
+    if (worst != SHELL_OK) c->err = "Newton step did not converge for every shell (see stats)";
+    return worst;
+    API_CATCH
+}
+
+}  // extern "C"

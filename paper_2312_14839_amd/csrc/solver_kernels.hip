@@ -1,0 +1,644 @@
+// Sparse linear algebra of libbhem (gfx950): 12x12-block matrix products,
+// block-Jacobi factorisation, the persistent block-Jacobi conjugate gradient
+// and per-shell reductions.
+//
+// Matrix storage: block rows per node (row_ptr / col_idx over nodes); each
+// 12x12 block is stored column-major (entry (r, c) at c*12 + r) so that the
+// lanes owning consecutive rows of a block read consecutive memory.  Rows and
+// columns of prescribed DOFs stay in the matrix; the solver masks them
+// (free-DOF bit masks per node), which equals replacing them by identity rows
+// and columns with a zero right-hand side.
+//
+// SpMV lane layout: a node row is handled by L = 12/R lanes, each owning R
+// consecutive rows of the 12 (R = 2 for FP64 blocks, 4 for FP32), so each
+// column of a block is one 16-byte load per lane; the 12 x-values of a
+// column block are exchanged within the lane group by cross-lane reads.
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace bhem {
+
+template <class TM> struct Lay {
+    static constexpr int R = 16 / sizeof(TM);   // rows per lane
+    static constexpr int L = 12 / R;             // lanes per node row
+    static constexpr int G = 64 / L;             // node rows per wavefront
+};
+
+__device__ __forceinline__ bool is_free(const uint16_t* m, int node, int w) { return !m || ((m[node] >> w) & 1); }
+
+template <class TM, int R> struct VecLoad;
+template <> struct VecLoad<double, 2> {
+    static __device__ __forceinline__ void ld(const double* p, double* o) {
+        const double2 v = *reinterpret_cast<const double2*>(p);
+        o[0] = v.x;
+        o[1] = v.y;
+    }
+};
+template <> struct VecLoad<float, 4> {
+    static __device__ __forceinline__ void ld(const float* p, float* o) {
+        const float4 v = *reinterpret_cast<const float4*>(p);
+        o[0] = v.x;
+        o[1] = v.y;
+        o[2] = v.z;
+        o[3] = v.w;
+    }
+};
+
+// acc[0..R) = rows R*t .. R*t+R-1 of (block row `node`) times x_eff, where
+// xe(col, lane-local index) supplies this lane's R values of the column block.
+template <class TM, class TV, class XF>
+__device__ __forceinline__ void row_times(const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
+                                          const TM* __restrict__ vals, int node, int t, int gbase, bool absval,
+                                          XF xe, TV* acc) {
+    constexpr int R = Lay<TM>::R;
+#pragma unroll
+    for (int i = 0; i < R; ++i) acc[i] = TV(0);
+    const int b0 = row_ptr[node], b1 = row_ptr[node + 1];
+    for (int b = b0; b < b1; ++b) {
+        const int col = col_idx[b];
+        TV xv[R];
+        xe(col, xv);
+        if (absval)
+#pragma unroll
+            for (int i = 0; i < R; ++i) xv[i] = fabs(xv[i]);
+        const TM* blk = vals + (size_t)b * 144 + R * t;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            TM a[R];
+            VecLoad<TM, R>::ld(blk + c * 12, a);
+            const TV xc = __shfl(xv[c % R], gbase + c / R);
+#pragma unroll
+            for (int i = 0; i < R; ++i) acc[i] += (absval ? (TV)fabs(a[i]) : (TV)a[i]) * xc;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ SpMV
+template <class TM>
+__global__ __launch_bounds__(256) void k_spmv(int nnodes, const int* __restrict__ row_ptr,
+                                              const int* __restrict__ col_idx, const TM* __restrict__ vals,
+                                              const uint16_t* __restrict__ fm, const double* __restrict__ x,
+                                              const double* __restrict__ b, double* __restrict__ y, int mode) {
+    constexpr int R = Lay<TM>::R, L = Lay<TM>::L, G = Lay<TM>::G;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int grp = lane / L, t = lane % L;
+    const int node = (blockIdx.x * 4 + wv) * G + grp;
+    if (grp >= G || node >= nnodes) return;
+    const bool absval = mode & 2, resid = mode & 4;
+    const uint16_t* m = (mode & 1) ? fm : nullptr;          // free columns only
+    const uint16_t* mr = (mode & (1 | 8)) ? fm : nullptr;   // free rows only
+    double acc[R];
+    row_times<TM, double>(row_ptr, col_idx, vals, node, t, lane - t, absval,
+                          [&](int col, double* xv) {
+#pragma unroll
+                              for (int i = 0; i < R; ++i) {
+                                  const int w = R * t + i;
+                                  xv[i] = is_free(m, col, w) ? x[(size_t)col * 12 + w] : 0.0;
+                              }
+                          },
+                          acc);
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int w = R * t + i;
+        double v = acc[i];
+        if (resid) v = b[(size_t)node * 12 + w] - v;
+        if (!is_free(mr, node, w)) v = 0.0;
+        y[(size_t)node * 12 + w] = v;
+    }
+}
+
+// ---------------------------------------------------- block-Jacobi factor
+// Inverse of each node's 12x12 diagonal block (prescribed rows/columns
+// replaced by identity) by an FP64 Cholesky factorisation; 16 lanes per node.
+template <class TV>
+__global__ __launch_bounds__(256) void k_bj_factor(int nnodes, const int* __restrict__ diag_blk,
+                                                   const void* __restrict__ vals, int vals_fp32,
+                                                   const uint16_t* __restrict__ fm, const int* __restrict__ node_shell,
+                                                   TV* __restrict__ dinv, int* __restrict__ fail_shell) {
+    __shared__ double A[16][12][13];
+    __shared__ int bad[16];
+    const int ln = threadIdx.x & 15, sub = threadIdx.x >> 4;
+    const int node = blockIdx.x * 16 + sub;
+    const bool act = node < nnodes;
+    if (ln == 0) bad[sub] = 0;
+    if (act && ln < 12) {
+        const size_t base = (size_t)diag_blk[node] * 144;
+        for (int c = 0; c < 12; ++c) {
+            double v = vals_fp32 ? (double)((const float*)vals)[base + c * 12 + ln] : ((const double*)vals)[base + c * 12 + ln];
+            const bool fr = is_free(fm, node, ln), fc = is_free(fm, node, c);
+            if (!fr || !fc) v = (ln == c && !fr) ? 1.0 : 0.0;
+            A[sub][ln][c] = v;
+        }
+    }
+    __syncthreads();
+    // right-looking Cholesky: A = L L^T, L stored in the lower triangle
+    for (int j = 0; j < 12; ++j) {
+        if (act && ln == j) {
+            double d = A[sub][j][j];
+            if (!(d > 0.0)) {
+                bad[sub] = 1;
+                d = 1.0;
+            }
+            A[sub][j][j] = sqrt(d);
+        }
+        __syncthreads();
+        if (act && ln > j && ln < 12) A[sub][ln][j] /= A[sub][j][j];
+        __syncthreads();
+        if (act && ln > j && ln < 12)
+            for (int k = j + 1; k <= ln; ++k) A[sub][ln][k] -= A[sub][ln][j] * A[sub][k][j];
+        __syncthreads();
+    }
+    if (act && ln < 12) {
+        // column ln of the inverse: L y = e_ln, L^T x = y
+        double y[12];
+        for (int i = 0; i < 12; ++i) {
+            double v = (i == ln) ? 1.0 : 0.0;
+            for (int k = 0; k < i; ++k) v -= A[sub][i][k] * y[k];
+            y[i] = v / A[sub][i][i];
+        }
+        for (int i = 11; i >= 0; --i) {
+            double v = y[i];
+            for (int k = i + 1; k < 12; ++k) v -= A[sub][k][i] * y[k];
+            y[i] = v / A[sub][i][i];
+        }
+        for (int i = 0; i < 12; ++i) dinv[(size_t)node * 144 + i * 12 + ln] = (TV)y[i];
+        if (ln == 0 && bad[sub]) atomicOr(&fail_shell[node_shell[node]], 1);
+    }
+}
+
+__global__ void k_save_diag(int nnodes, const int* __restrict__ diag_blk, const void* __restrict__ vals, int fp32,
+                            double* __restrict__ diag) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nnodes * 12) return;
+    const int node = t / 12, w = t % 12;
+    const size_t at = (size_t)diag_blk[node] * 144 + w * 12 + w;
+    diag[t] = fp32 ? (double)((const float*)vals)[at] : ((const double*)vals)[at];
+}
+
+// Diagonal regulariser A_ii = (1 + delta) diag_i for shells with delta > 0.
+__global__ void k_regularize(int nnodes, const int* __restrict__ diag_blk, void* __restrict__ vals, int fp32,
+                             const double* __restrict__ diag, const int* __restrict__ node_shell,
+                             const double* __restrict__ delta_shell) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nnodes * 12) return;
+    const int node = t / 12, w = t % 12;
+    const double dl = delta_shell[node_shell[node]];
+    if (dl <= 0.0) return;
+    const size_t at = (size_t)diag_blk[node] * 144 + w * 12 + w;
+    const double v = (1.0 + dl) * diag[t];
+    if (fp32)
+        ((float*)vals)[at] = (float)v;
+    else
+        ((double*)vals)[at] = v;
+}
+
+// ------------------------------------------------------ block reductions
+template <int N> __device__ __forceinline__ void block_sum(double (&v)[N], double* lds /* [4][N] */) {
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < N; ++k) lds[wv * N + k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = lds[k] + lds[N + k] + lds[2 * N + k] + lds[3 * N + k];
+}
+
+// Sum of per-block partials of one shell (partials stored [block][2]),
+// same order in every block.
+template <int N>
+__device__ __forceinline__ void shell_total(const double* __restrict__ part, int blk0, int nblk, double (&v)[N],
+                                            double* lds) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+            v[k] += __hip_atomic_load(&part[2 * (size_t)(blk0 + i) + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    block_sum<N>(v, lds);
+}
+
+// Barrier over the nblk blocks of one shell: a monotone arrival counter
+// (zeroed before the launch); barrier number k completes when it reaches
+// nblk*(k+1).  Every wait is bounded: after 2^22 polls, or when another
+// block has given up, the block sets abort and the kernel ends.
+// (Legitimate waits are one matrix-product phase, far below the bound.)
+__device__ __forceinline__ bool shell_barrier(unsigned* cnt, unsigned nblk, unsigned k, int* abort_flag) {
+    __shared__ int s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned target = nblk * (k + 1);
+        int ok = 1;
+        unsigned spins = 0;
+        while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                ++spins > (1u << 22)) {
+                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __threadfence();
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+// ---------------------------------------------------- persistent CG
+// Block-Jacobi preconditioned CG for every shell at once.  Each shell owns a
+// contiguous set of blocks and node rows; the only synchronisation is the
+// per-shell barrier (two per iteration).  p is double-buffered so that the
+// update p = z + beta p is fused into the matrix product:
+//   phase A: p_new = z + beta p_old (own rows), q = A (z + beta p_old), sum p.q
+//   phase B: x += alpha p, r -= alpha q, z = Dinv r, sums r.z and r.r
+// Partial sums alternate between two buffers so a fast block never
+// overwrites values a slow block of its shell is still reading.
+template <class TM, class TV>
+__global__ __launch_bounds__(256) void k_cg(const int* __restrict__ blk_shell, const int* __restrict__ blk_row0,
+                                            const int* __restrict__ blk_row1, const int* __restrict__ shell_blk0,
+                                            const int* __restrict__ shell_nblk, const int* __restrict__ row_ptr,
+                                            const int* __restrict__ col_idx, const TM* __restrict__ vals,
+                                            const TV* __restrict__ dinv, const uint16_t* __restrict__ fm,
+                                            const double* __restrict__ b, TV* __restrict__ x, TV* __restrict__ r,
+                                            TV* __restrict__ z, TV* __restrict__ p0, TV* __restrict__ p1,
+                                            TV* __restrict__ qv, double* __restrict__ partial,
+                                            unsigned* __restrict__ bar, int* __restrict__ abort_flag,
+                                            const double* __restrict__ rtol2_shell,
+                                            const int* __restrict__ maxit_shell,
+                                            const int* __restrict__ active_shell, CgShellOut* __restrict__ out,
+                                            int nblk_total) {
+    constexpr int R = Lay<TM>::R, L = Lay<TM>::L, G = Lay<TM>::G;
+    __shared__ double lds[16];
+    const int blk = blockIdx.x;
+    const int sh = blk_shell[blk];
+    const int row0 = blk_row0[blk], row1 = blk_row1[blk];
+    const int sb0 = shell_blk0[sh], snb = shell_nblk[sh];
+    unsigned* cnt = bar + sh;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int grp = lane / L, t = lane % L;
+    const bool lane_ok = grp < G;
+    const int rows_per_pass = 4 * G;
+    double* part0 = partial;                              // [nblk_total][2]
+    double* part1 = partial + 2 * (size_t)nblk_total;
+    unsigned nbar = 0;
+    const bool leader = blk == sb0 && threadIdx.x == 0;
+
+    if (!active_shell[sh]) {
+        for (int node = row0 + threadIdx.x / 12; node < row1; node += blockDim.x / 12)
+            if (threadIdx.x < (blockDim.x / 12) * 12) x[(size_t)node * 12 + threadIdx.x % 12] = TV(0);
+        if (leader) out[sh] = CgShellOut{0, 0, 0.0, 0.0};
+        return;
+    }
+
+    // z = Dinv r for this lane's R rows of node (r of the node exchanged in the group)
+    auto precond = [&](int node, const TV* rr, TV* zz) {
+        TV rall[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) rall[c] = __shfl(rr[c % R], lane - t + c / R);
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const TV* drow = dinv + (size_t)node * 144 + (R * t + i) * 12;
+            TV s = TV(0);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) s += drow[c] * rall[c];
+            zz[i] = s;
+        }
+    };
+
+    // ---- init: r = b (masked), x = 0, z = Dinv r; sums r.z and b.b
+    double sums[2] = {0.0, 0.0};
+    for (int base = row0; base < row1; base += rows_per_pass) {
+        const int node = base + wv * G + grp;
+        const bool ok = lane_ok && node < row1;
+        TV rr[R], zz[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int w = R * t + i;
+            rr[i] = ok && is_free(fm, node, w) ? (TV)b[(size_t)node * 12 + w] : TV(0);
+        }
+        precond(ok ? node : row0, rr, zz);
+        if (ok) {
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const int w = R * t + i;
+                const size_t at = (size_t)node * 12 + w;
+                if (!is_free(fm, node, w)) zz[i] = TV(0);
+                r[at] = rr[i];
+                z[at] = zz[i];
+                x[at] = TV(0);
+                p0[at] = TV(0);
+                sums[0] += (double)rr[i] * (double)zz[i];
+                sums[1] += (double)rr[i] * (double)rr[i];
+            }
+        }
+    }
+    block_sum<2>(sums, lds);
+    if (threadIdx.x == 0) {
+        part0[2 * blk] = sums[0];
+        part0[2 * blk + 1] = sums[1];
+    }
+    if (!shell_barrier(cnt, snb, nbar++, abort_flag)) {
+        if (leader) out[sh] = CgShellOut{0, 3, 0.0, 0.0};
+        return;
+    }
+    double tot[2];
+    shell_total<2>(part0, sb0, snb, tot, lds);
+    double rz = tot[0];
+    const double bb = tot[1];
+    const double tol2 = rtol2_shell[sh] * bb;
+    const int maxit = maxit_shell[sh];
+    if (bb == 0.0) {
+        if (leader) out[sh] = CgShellOut{0, 0, 0.0, 0.0};
+        return;
+    }
+    double beta = 0.0;
+    TV* pin = p0;
+    TV* pout = p1;
+    int it = 0, status = 1;
+    double rr2 = bb;
+    for (; it < maxit; ++it) {
+        // ---- phase A
+        double pq = 0.0;
+        for (int base = row0; base < row1; base += rows_per_pass) {
+            const int node = base + wv * G + grp;
+            const bool ok = lane_ok && node < row1;
+            if (!ok) continue;
+            TV acc[R];
+            const TV bt = (TV)beta;
+            row_times<TM, TV>(row_ptr, col_idx, vals, node, t, lane - t, false,
+                              [&](int col, TV* xv) {
+#pragma unroll
+                                  for (int i = 0; i < R; ++i) {
+                                      const size_t at = (size_t)col * 12 + R * t + i;
+                                      xv[i] = z[at] + bt * pin[at];
+                                  }
+                              },
+                              acc);
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const int w = R * t + i;
+                const size_t at = (size_t)node * 12 + w;
+                const TV pn = z[at] + bt * pin[at];
+                const TV qq = is_free(fm, node, w) ? acc[i] : TV(0);
+                pout[at] = pn;
+                qv[at] = qq;
+                pq += (double)pn * (double)qq;
+            }
+        }
+        double s1[1] = {pq};
+        block_sum<1>(s1, lds);
+        if (threadIdx.x == 0) part1[2 * blk] = s1[0];
+        if (!shell_barrier(cnt, snb, nbar++, abort_flag)) {
+            status = 3;
+            break;
+        }
+        double t1[1];
+        shell_total<1>(part1, sb0, snb, t1, lds);
+        const double pqt = t1[0];
+        if (!(pqt > 0.0)) {
+            status = 2;
+            break;
+        }
+        const double alpha = rz / pqt;
+        // ---- phase B
+        double s2[2] = {0.0, 0.0};
+        for (int base = row0; base < row1; base += rows_per_pass) {
+            const int node = base + wv * G + grp;
+            const bool ok = lane_ok && node < row1;
+            TV rr[R], zz[R];
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const size_t at = (size_t)(ok ? node : row0) * 12 + R * t + i;
+                rr[i] = r[at] - (TV)alpha * qv[at];
+            }
+            precond(ok ? node : row0, rr, zz);
+            if (ok) {
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    const int w = R * t + i;
+                    const size_t at = (size_t)node * 12 + w;
+                    if (!is_free(fm, node, w)) zz[i] = TV(0);
+                    x[at] += (TV)alpha * pout[at];
+                    r[at] = rr[i];
+                    z[at] = zz[i];
+                    s2[0] += (double)rr[i] * (double)zz[i];
+                    s2[1] += (double)rr[i] * (double)rr[i];
+                }
+            }
+        }
+        block_sum<2>(s2, lds);
+        if (threadIdx.x == 0) {
+            part0[2 * blk] = s2[0];
+            part0[2 * blk + 1] = s2[1];
+        }
+        if (!shell_barrier(cnt, snb, nbar++, abort_flag)) {
+            status = 3;
+            break;
+        }
+        shell_total<2>(part0, sb0, snb, tot, lds);
+        rr2 = tot[1];
+        if (rr2 <= tol2) {
+            status = 0;
+            ++it;
+            break;
+        }
+        beta = tot[0] / rz;
+        rz = tot[0];
+        TV* tmp = pin;
+        pin = pout;
+        pout = tmp;
+    }
+    if (leader) out[sh] = CgShellOut{it, status, bb, rr2};
+}
+
+// ------------------------------------------------------ per-shell dots
+__global__ __launch_bounds__(256) void k_shell_dot_part(const int* __restrict__ blk_row0,
+                                                        const int* __restrict__ blk_row1, const double* __restrict__ x,
+                                                        const double* __restrict__ y, const uint16_t* __restrict__ fm,
+                                                        double* __restrict__ part) {
+    __shared__ double lds[8];
+    const int blk = blockIdx.x;
+    const int r0 = blk_row0[blk], r1 = blk_row1[blk];
+    double s[1] = {0.0};
+    for (int e = r0 * 12 + threadIdx.x; e < r1 * 12; e += blockDim.x) {
+        const int node = e / 12, w = e % 12;
+        if (is_free(fm, node, w)) s[0] += x[e] * y[e];
+    }
+    block_sum<1>(s, lds);
+    if (threadIdx.x == 0) part[blk] = s[0];
+}
+
+__global__ void k_shell_dot_fin(int nshell, const int* __restrict__ shell_blk0, const int* __restrict__ shell_nblk,
+                                const double* __restrict__ part, double* __restrict__ out) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nshell) return;
+    double v = 0.0;
+    for (int i = 0; i < shell_nblk[s]; ++i) v += part[shell_blk0[s] + i];
+    out[s] = v;
+}
+
+// ------------------------------------------------------------ elementwise
+__global__ void k_predict(int n, const double* __restrict__ qn, const double* __restrict__ vn,
+                          const double* __restrict__ qpresc, const uint16_t* __restrict__ fm, double dt,
+                          double* __restrict__ qhat, double* __restrict__ q) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const double qh = qn[t] + dt * vn[t];
+    qhat[t] = qh;
+    q[t] = is_free(fm, t / 12, t % 12) ? qh : (qpresc ? qpresc[t] : qn[t]);
+}
+
+__global__ void k_axpy_shell(int n, const double* __restrict__ x, const double* __restrict__ d,
+                             const double* __restrict__ alpha_shell, const int* __restrict__ node_shell,
+                             double* __restrict__ out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    out[t] = x[t] + alpha_shell[node_shell[t / 12]] * d[t];
+}
+
+__global__ void k_neg_masked(int n, const double* __restrict__ g, const uint16_t* __restrict__ fm,
+                             const int* __restrict__ node_shell, const int* __restrict__ active_shell,
+                             double* __restrict__ b) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int node = t / 12;
+    b[t] = (is_free(fm, node, t % 12) && active_shell[node_shell[node]]) ? -g[t] : 0.0;
+}
+
+__global__ void k_velocity(int n, const double* __restrict__ q1, const double* __restrict__ qn, double dt,
+                           double* __restrict__ v) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) v[t] = (q1[t] - qn[t]) / dt;
+}
+
+__global__ void k_copy_shell(int n, const double* __restrict__ src, const int* __restrict__ node_shell,
+                             const int* __restrict__ flag_shell, double* __restrict__ dst) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n && flag_shell[node_shell[t / 12]]) dst[t] = src[t];
+}
+
+template <class TV> __global__ void k_add_to(int n, const TV* __restrict__ dx, double* __restrict__ x) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) x[t] += (double)dx[t];
+}
+
+// ------------------------------------------------------------ launchers
+static inline dim3 grid1(int n) { return dim3((n + 255) / 256); }
+
+template <class TM>
+void launch_spmv(hipStream_t st, int nnodes, const int* row_ptr, const int* col_idx, const TM* vals,
+                 const uint16_t* freemask, const double* x, const double* b, double* y, int mode) {
+    if (nnodes == 0) return;
+    const int rows_per_block = 4 * Lay<TM>::G;
+    hipLaunchKernelGGL(k_spmv<TM>, dim3((nnodes + rows_per_block - 1) / rows_per_block), dim3(256), 0, st, nnodes,
+                       row_ptr, col_idx, vals, freemask, x, b, y, mode);
+}
+template void launch_spmv<double>(hipStream_t, int, const int*, const int*, const double*, const uint16_t*,
+                                  const double*, const double*, double*, int);
+template void launch_spmv<float>(hipStream_t, int, const int*, const int*, const float*, const uint16_t*,
+                                 const double*, const double*, double*, int);
+
+template <class TV>
+void launch_bj_factor(hipStream_t st, int nnodes, const int* diag_blk, const void* vals, int vals_fp32,
+                      const uint16_t* freemask, const int* node_shell, TV* dinv, int* fail_shell) {
+    if (nnodes == 0) return;
+    hipLaunchKernelGGL(k_bj_factor<TV>, dim3((nnodes + 15) / 16), dim3(256), 0, st, nnodes, diag_blk, vals, vals_fp32,
+                       freemask, node_shell, dinv, fail_shell);
+}
+template void launch_bj_factor<double>(hipStream_t, int, const int*, const void*, int, const uint16_t*, const int*,
+                                       double*, int*);
+template void launch_bj_factor<float>(hipStream_t, int, const int*, const void*, int, const uint16_t*, const int*,
+                                      float*, int*);
+
+void launch_save_diag(hipStream_t st, int nnodes, const int* diag_blk, const void* vals, int vals_fp32,
+                      double* diag) {
+    hipLaunchKernelGGL(k_save_diag, grid1(nnodes * 12), dim3(256), 0, st, nnodes, diag_blk, vals, vals_fp32, diag);
+}
+
+void launch_regularize(hipStream_t st, int nnodes, const int* diag_blk, void* vals, int vals_fp32,
+                       const double* diag, const int* node_shell, const double* delta_shell) {
+    hipLaunchKernelGGL(k_regularize, grid1(nnodes * 12), dim3(256), 0, st, nnodes, diag_blk, vals, vals_fp32, diag,
+                       node_shell, delta_shell);
+}
+
+template <class TM, class TV>
+hipError_t launch_cg(hipStream_t st, int nblk, const RowBlocks& rb, const int* row_ptr, const int* col_idx,
+                     const TM* vals, const TV* dinv, const uint16_t* freemask, const double* b, TV* x, TV* r, TV* z,
+                     TV* p0, TV* p1, TV* qv, double* partial, unsigned* bar, int* abort_flag, const double* rtol2_shell,
+                     const int* maxit_shell, const int* active_shell, CgShellOut* out) {
+    void* args[] = {(void*)&rb.blk_shell, (void*)&rb.blk_row0, (void*)&rb.blk_row1, (void*)&rb.shell_blk0,
+                    (void*)&rb.shell_nblk, (void*)&row_ptr, (void*)&col_idx, (void*)&vals, (void*)&dinv,
+                    (void*)&freemask, (void*)&b, (void*)&x, (void*)&r, (void*)&z, (void*)&p0, (void*)&p1,
+                    (void*)&qv, (void*)&partial, (void*)&bar, (void*)&abort_flag, (void*)&rtol2_shell,
+                    (void*)&maxit_shell, (void*)&active_shell, (void*)&out, (void*)&nblk};
+    return hipLaunchCooperativeKernel((const void*)k_cg<TM, TV>, dim3(nblk), dim3(256), args, 0, st);
+}
+template hipError_t launch_cg<double, double>(hipStream_t, int, const RowBlocks&, const int*, const int*,
+                                              const double*, const double*, const uint16_t*, const double*, double*,
+                                              double*, double*, double*, double*, double*, double*, unsigned*, int*,
+                                              const double*, const int*, const int*, CgShellOut*);
+template hipError_t launch_cg<float, float>(hipStream_t, int, const RowBlocks&, const int*, const int*, const float*,
+                                            const float*, const uint16_t*, const double*, float*, float*, float*,
+                                            float*, float*, float*, double*, unsigned*, int*, const double*,
+                                            const int*, const int*, CgShellOut*);
+
+int cg_max_blocks(int device, int tm_fp32, int tv_fp32) {
+    int per_cu = 0, cus = 0;
+    hipError_t e;
+    if (tm_fp32)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_cg<float, float>, 256, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_cg<double, double>, 256, 0);
+    (void)tv_fp32;
+    if (e != hipSuccess) return -1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return -1;
+    return per_cu * cus;
+}
+
+void launch_shell_dot(hipStream_t st, const RowBlocks& rb, int nshell, const double* x, const double* y,
+                      const uint16_t* freemask, double* partial, double* out) {
+    hipLaunchKernelGGL(k_shell_dot_part, dim3(rb.nblk), dim3(256), 0, st, rb.blk_row0, rb.blk_row1, x, y, freemask,
+                       partial);
+    hipLaunchKernelGGL(k_shell_dot_fin, grid1(nshell), dim3(256), 0, st, nshell, rb.shell_blk0, rb.shell_nblk,
+                       partial, out);
+}
+
+void launch_predict(hipStream_t st, int n, const double* qn, const double* vn, const double* qpresc,
+                    const uint16_t* freemask, double dt, double* qhat, double* q) {
+    hipLaunchKernelGGL(k_predict, grid1(n), dim3(256), 0, st, n, qn, vn, qpresc, freemask, dt, qhat, q);
+}
+void launch_axpy_shell(hipStream_t st, int nnodes, const double* x, const double* d, const double* alpha_shell,
+                       const int* node_shell, double* out) {
+    const int n = nnodes * 12;
+    hipLaunchKernelGGL(k_axpy_shell, grid1(n), dim3(256), 0, st, n, x, d, alpha_shell, node_shell, out);
+}
+void launch_neg_masked(hipStream_t st, int nnodes, const double* g, const uint16_t* freemask, const int* node_shell,
+                       const int* active_shell, double* b) {
+    const int n = nnodes * 12;
+    hipLaunchKernelGGL(k_neg_masked, grid1(n), dim3(256), 0, st, n, g, freemask, node_shell, active_shell, b);
+}
+void launch_velocity(hipStream_t st, int n, const double* q1, const double* qn, double dt, double* v) {
+    hipLaunchKernelGGL(k_velocity, grid1(n), dim3(256), 0, st, n, q1, qn, dt, v);
+}
+void launch_copy_shell(hipStream_t st, int nnodes, const double* src, const int* node_shell, const int* flag_shell,
+                       double* dst) {
+    const int n = nnodes * 12;
+    hipLaunchKernelGGL(k_copy_shell, grid1(n), dim3(256), 0, st, n, src, node_shell, flag_shell, dst);
+}
+template <class TV> void launch_add_to(hipStream_t st, int n, const TV* dx, double* x) {
+    hipLaunchKernelGGL(k_add_to<TV>, grid1(n), dim3(256), 0, st, n, dx, x);
+}
+template void launch_add_to<double>(hipStream_t, int, const double*, double*);
+template void launch_add_to<float>(hipStream_t, int, const float*, double*);
+
+}  // namespace bhem

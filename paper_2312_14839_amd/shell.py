@@ -1,0 +1,231 @@
+"""ctypes binding of libbhem.so, the C ABI declared in include/bhem_shell.h.
+
+Argument marshalling only: every step of the thin-shell hot path runs in the
+library's HIP kernels.  Device arrays are passed as ``torch`` CUDA(HIP)
+tensors, used for device memory and streams only.  Importing this module
+fails loudly when the built library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbhem.so")
+
+SHELL_OK = 0
+SHELL_E_INVAL = -1
+SHELL_E_NOMEM = -2
+SHELL_E_DEVICE = -3
+SHELL_E_NOT_CONVERGED = -4
+SHELL_E_INDEFINITE = -5
+SHELL_E_NONFINITE = -6
+SHELL_E_LINESEARCH = -7
+SHELL_FP64, SHELL_MIXED = 0, 1
+SHELL_HESS_EXACT, SHELL_HESS_PSEUDO = 0, 1
+SHELL_WS_NONE, SHELL_WS_MLP = 0, 1
+
+STATUS_NAMES = {0: "OK", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_NOT_CONVERGED",
+                -5: "E_INDEFINITE", -6: "E_NONFINITE", -7: "E_LINESEARCH"}
+
+
+class shell_desc(C.Structure):
+    _fields_ = [
+        ("n1", C.c_int32), ("n2", C.c_int32), ("periodic1", C.c_int32),
+        ("dxi1", C.c_double), ("dxi2", C.c_double),
+        ("ref_host", C.POINTER(C.c_double)), ("fixed_host", C.POINTER(C.c_uint8)),
+        ("young", C.c_double), ("poisson", C.c_double),
+        ("thickness", C.c_double), ("density", C.c_double),
+        ("gravity", C.c_double * 3),
+    ]
+
+
+class shell_opts(C.Structure):
+    _fields_ = [
+        ("precision", C.c_int32), ("hessian", C.c_int32), ("warm_start", C.c_int32),
+        ("newton_maxit", C.c_int32), ("pcg_maxit", C.c_int32),
+        ("newton_rtol", C.c_double), ("pcg_rtol", C.c_double),
+        ("device", C.c_int32), ("stream", C.c_void_p),
+    ]
+
+
+class shell_step_stats(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32), ("newton_iters", C.c_int32), ("pcg_iters_total", C.c_int32),
+        ("ls_backtracks", C.c_int32), ("refine_sweeps", C.c_int32), ("warm_start_used", C.c_int32),
+        ("grad_norm0", C.c_double), ("grad_norm", C.c_double), ("grad_floor", C.c_double),
+        ("reg_delta", C.c_double),
+        ("t_assemble_ms", C.c_double), ("t_pcg_ms", C.c_double), ("t_step_ms", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ShellError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(the HIP library is required, there is no fallback)")
+    lib = C.CDLL(LIB_PATH)
+    P, vp = C.POINTER, C.c_void_p
+    lib.shell_default_opts.argtypes = [P(shell_opts)]
+    lib.shell_default_opts.restype = None
+    lib.shell_create.argtypes = [P(shell_desc), C.c_int32, P(shell_opts), P(vp)]
+    lib.shell_create.restype = C.c_int32
+    lib.shell_destroy.argtypes = [vp]
+    lib.shell_destroy.restype = None
+    lib.shell_last_error.argtypes = [vp]
+    lib.shell_last_error.restype = C.c_char_p
+    lib.shell_sizes.argtypes = [vp, P(C.c_int32), P(C.c_int32), P(C.c_int64)]
+    lib.shell_sizes.restype = C.c_int32
+    lib.shell_energy_grad_hess.argtypes = [vp, vp, P(C.c_double), vp, C.c_int32]
+    lib.shell_energy_grad_hess.restype = C.c_int32
+    lib.shell_assemble.argtypes = [vp, vp, C.c_double, C.c_int32]
+    lib.shell_assemble.restype = C.c_int32
+    lib.shell_get_bsr.argtypes = [vp, C.c_int32, P(C.c_int32), P(C.c_int32), P(C.c_int32), P(C.c_double)]
+    lib.shell_get_bsr.restype = C.c_int32
+    lib.shell_spmv.argtypes = [vp, vp, vp, C.c_int32]
+    lib.shell_spmv.restype = C.c_int32
+    lib.shell_pcg_solve.argtypes = [vp, vp, vp, C.c_double, C.c_int32, P(C.c_int32), P(C.c_double)]
+    lib.shell_pcg_solve.restype = C.c_int32
+    lib.shell_newton_step.argtypes = [vp, C.c_double, vp, vp, vp, vp, vp, P(shell_step_stats)]
+    lib.shell_newton_step.restype = C.c_int32
+    return lib
+
+
+lib = _load()
+
+EXPORTED = ["shell_default_opts", "shell_create", "shell_destroy", "shell_last_error", "shell_sizes",
+            "shell_energy_grad_hess", "shell_assemble", "shell_get_bsr", "shell_spmv", "shell_pcg_solve",
+            "shell_newton_step"]
+
+
+def _ptr(t):
+    """Device pointer of a contiguous torch tensor (or None)."""
+    if t is None:
+        return None
+    assert t.is_contiguous(), "device arrays must be contiguous"
+    return C.c_void_p(t.data_ptr())
+
+
+def default_opts() -> shell_opts:
+    o = shell_opts()
+    lib.shell_default_opts(C.byref(o))
+    return o
+
+
+class ShellContext:
+    """One context over one or more shells.  ``cases`` are objects with the
+    fields of paper_2312_14839_amd.workloads.Case (n1, n2, periodic1, dxi1,
+    dxi2, young, poisson, thickness, density, gravity, ref, fixed)."""
+
+    def __init__(self, cases: Sequence, precision=SHELL_FP64, hessian=SHELL_HESS_EXACT,
+                 newton_rtol=1e-10, pcg_rtol=1e-10, newton_maxit=50, pcg_maxit=100000,
+                 device=0, stream=None):
+        self._keep = []
+        descs = (shell_desc * len(cases))()
+        for k, cs in enumerate(cases):
+            ref = np.ascontiguousarray(cs.ref, dtype=np.float64)
+            fixed = np.ascontiguousarray(cs.fixed, dtype=np.uint8) if cs.fixed is not None else None
+            self._keep += [ref, fixed]
+            d = descs[k]
+            d.n1, d.n2, d.periodic1 = int(cs.n1), int(cs.n2), int(cs.periodic1)
+            d.dxi1, d.dxi2 = float(cs.dxi1), float(cs.dxi2)
+            d.ref_host = ref.ctypes.data_as(C.POINTER(C.c_double))
+            d.fixed_host = fixed.ctypes.data_as(C.POINTER(C.c_uint8)) if fixed is not None else None
+            d.young, d.poisson = float(cs.young), float(cs.poisson)
+            d.thickness, d.density = float(cs.thickness), float(cs.density)
+            for i in range(3):
+                d.gravity[i] = float(cs.gravity[i])
+        o = default_opts()
+        o.precision, o.hessian = int(precision), int(hessian)
+        o.newton_rtol, o.pcg_rtol = float(newton_rtol), float(pcg_rtol)
+        o.newton_maxit, o.pcg_maxit = int(newton_maxit), int(pcg_maxit)
+        o.device = int(device)
+        o.stream = C.c_void_p(stream) if stream else None
+        h = C.c_void_p()
+        rc = lib.shell_create(descs, len(cases), C.byref(o), C.byref(h))
+        if rc != SHELL_OK:
+            raise ShellError(rc, lib.shell_last_error(None).decode())
+        self.h = h
+        self.n_shells = len(cases)
+        n, p, nb = C.c_int32(), C.c_int32(), C.c_int64()
+        lib.shell_sizes(h, C.byref(n), C.byref(p), C.byref(nb))
+        self.total_nodes, self.total_patches, self.nnzb = n.value, p.value, nb.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.shell_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, rc, allow=()):
+        if rc != SHELL_OK and rc not in allow:
+            raise ShellError(rc, lib.shell_last_error(self.h).decode())
+        return rc
+
+    def energy_grad_hess(self, q, grad=None, hessian=False):
+        e = (C.c_double * self.n_shells)()
+        self._check(lib.shell_energy_grad_hess(self.h, _ptr(q), e, _ptr(grad), int(hessian)))
+        return np.array(e[:])
+
+    def assemble(self, q, mass_scale=0.0, elastic=True):
+        self._check(lib.shell_assemble(self.h, _ptr(q), float(mass_scale), int(elastic)))
+
+    def get_bsr(self, shell=0):
+        nb = C.c_int32()
+        self._check(lib.shell_get_bsr(self.h, shell, C.byref(nb), None, None, None))
+        # nodes of this shell = len(row_ptr) - 1; query via a second call with arrays
+        nblk = nb.value
+        rows = self._shell_nodes(shell)
+        row_ptr = np.zeros(rows + 1, np.int32)
+        col_idx = np.zeros(nblk, np.int32)
+        vals = np.zeros((nblk, 12, 12))
+        self._check(lib.shell_get_bsr(self.h, shell, C.byref(nb),
+                                      row_ptr.ctypes.data_as(C.POINTER(C.c_int32)),
+                                      col_idx.ctypes.data_as(C.POINTER(C.c_int32)),
+                                      vals.ctypes.data_as(C.POINTER(C.c_double))))
+        return row_ptr, col_idx, vals
+
+    def _shell_nodes(self, shell):
+        return self._node_counts[shell]
+
+    def set_node_counts(self, counts: List[int]):
+        self._node_counts = list(counts)
+
+    def spmv(self, x, y, masked=True):
+        self._check(lib.shell_spmv(self.h, _ptr(x), _ptr(y), int(masked)))
+
+    def pcg_solve(self, b, x, rtol=1e-10, maxit=100000, allow_fail=False):
+        its = (C.c_int32 * self.n_shells)()
+        rel = (C.c_double * self.n_shells)()
+        rc = lib.shell_pcg_solve(self.h, _ptr(b), _ptr(x), float(rtol), int(maxit), its, rel)
+        if not allow_fail:
+            self._check(rc)
+        return rc, np.array(its[:]), np.array(rel[:])
+
+    def newton_step(self, dt, q_n, v_n, q_presc, q_out, v_out, allow_fail=False):
+        st = (shell_step_stats * self.n_shells)()
+        rc = lib.shell_newton_step(self.h, float(dt), _ptr(q_n), _ptr(v_n), _ptr(q_presc), _ptr(q_out),
+                                   _ptr(v_out), st)
+        if not allow_fail:
+            self._check(rc)
+        return rc, [s.as_dict() for s in st]
+
+
+def context_for(cases, **kw) -> ShellContext:
+    """ShellContext that also knows each shell's node count (for get_bsr)."""
+    ctx = ShellContext(cases, **kw)
+    ctx.set_node_counts([c.nodes for c in cases])
+    return ctx

@@ -1,0 +1,227 @@
+"""Parity of the HIP library (through its C ABI) with the CPU oracle.
+
+Element-by-element comparisons on seeded inputs at sizes the oracle handles
+in seconds (several MFMA tiles and CG blocks, ragged row counts, periodic
+seams with an odd patch count, unequal cell sizes), plus the edge cases of
+the method.  Tolerances: FP64 paths 1e-11..1e-12 relative (rounding-order
+differences only); FP32 Hessian/CG paths 1e-5 relative on the Newton
+result (the stated bound for the mixed form) and 2e-5 on the matrix."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2312_14839_amd import workloads as W
+
+from gpu_util import (bsr_from_gpu, newton_residual, oracle_matrix, rect_sheet, rel_disp_error)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def S():
+    from paper_2312_14839_amd import shell
+    return shell
+
+
+CASES = {
+    "sheet1x1": lambda: W.sheet_case(1),
+    "rect3x2": lambda: rect_sheet(3, 2, 0.93, 0.94),
+    "cyl8x5": lambda: W.case_cylinder(8, 5),
+    "cyl7x3_odd": lambda: W.case_cylinder(7, 3),
+    "sheet8x8": lambda: W.case_small_sheet(),
+}
+
+
+def _state(case, seed=11):
+    return W.random_state(case, seed, 1e-3, 1e-2)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_energy_and_gradient(name):
+    case = CASES[name]()
+    q = _state(case)
+    s = O.shell_from_case(case)
+    e_ref = O.energy(s, q, case.ref)
+    g_ref = O.gradient(s, q, case.ref)
+    ctx = S().context_for([case])
+    qd, gd = dev(q), torch.zeros(case.nodes * 12, dtype=torch.float64, device="cuda")
+    e = ctx.energy_grad_hess(qd, gd)
+    assert abs(e[0] - e_ref) <= 1e-12 * abs(e_ref)
+    g = host(gd).reshape(-1, 12)
+    assert np.abs(g - g_ref).max() <= 1e-11 * np.abs(g_ref).max()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("pseudo", [False, True])
+def test_hessian_blocks(name, precision, pseudo):
+    case = CASES[name]()
+    q = _state(case)
+    sh = S()
+    ctx = sh.context_for([case], precision=sh.SHELL_MIXED if precision == "mixed" else sh.SHELL_FP64,
+                         hessian=sh.SHELL_HESS_PSEUDO if pseudo else sh.SHELL_HESS_EXACT)
+    ctx.energy_grad_hess(dev(q), None, hessian=True)
+    K = bsr_from_gpu(*ctx.get_bsr(0)).toarray()
+    K_ref = oracle_matrix(case, q, "hessian", pseudo).toarray()
+    tol = 1e-11 if precision == "fp64" else 2e-5
+    assert np.abs(K - K_ref).max() <= tol * np.abs(K_ref).max()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_mass_blocks_and_pattern(precision):
+    case = W.case_cylinder(7, 3)
+    sh = S()
+    ctx = sh.context_for([case], precision=sh.SHELL_MIXED if precision == "mixed" else sh.SHELL_FP64)
+    ctx.assemble(dev(case.ref), mass_scale=1.0, elastic=False)
+    row_ptr, col_idx, vals = ctx.get_bsr(0)
+    M = bsr_from_gpu(row_ptr, col_idx, vals)
+    M_ref = oracle_matrix(case, case.ref, "mass")
+    assert M.nnz == M_ref.nnz
+    tol = 1e-14 if precision == "fp64" else 1e-6   # FP32: 16-term sums, 16 eps_32 ~ 1e-6
+    assert np.abs((M - M_ref).toarray()).max() <= tol * abs(M_ref).max()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_spmv(precision):
+    case = W.case_twist(9)
+    q = _state(case)
+    sh = S()
+    ctx = sh.context_for([case], precision=sh.SHELL_MIXED if precision == "mixed" else sh.SHELL_FP64)
+    ms = 1.0 / case.dt ** 2
+    ctx.assemble(dev(q), mass_scale=ms)
+    A = bsr_from_gpu(*ctx.get_bsr(0))       # the device matrix itself (FP32 values exactly in mixed mode)
+    x = np.random.default_rng(5).normal(size=case.nodes * 12)
+    free = ~case.fixed.reshape(-1).astype(bool)
+    y = torch.zeros_like(dev(x))
+    ctx.spmv(dev(x), y, masked=True)
+    y_ref = A @ (x * free) * free
+    assert np.abs(host(y) - y_ref).max() <= 1e-13 * np.abs(y_ref).max()
+    ctx.spmv(dev(x), y, masked=False)
+    assert np.abs(host(y) - A @ x).max() <= 1e-13 * np.abs(y_ref).max()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_pcg_solve(precision):
+    case = W.case_small_sheet()
+    q = _state(case)
+    sh = S()
+    ctx = sh.context_for([case], precision=sh.SHELL_MIXED if precision == "mixed" else sh.SHELL_FP64)
+    ms = 1.0 / case.dt ** 2
+    ctx.assemble(dev(q), mass_scale=ms)
+    A = (oracle_matrix(case, q) + ms * oracle_matrix(case, case.ref, "mass")).toarray()
+    free = ~case.fixed.reshape(-1).astype(bool)
+    b = np.random.default_rng(6).normal(size=A.shape[0]) * free
+    x = torch.zeros_like(dev(b))
+    rc, its, rel = ctx.pcg_solve(dev(b), x, rtol=1e-10)
+    xs = host(x)
+    # the refinement solves the system of the stored matrix (FP32 values in
+    # mixed mode) to the FP64 tolerance
+    A_dev = bsr_from_gpu(*ctx.get_bsr(0)).toarray()
+    r = b[free] - A_dev[np.ix_(free, free)] @ xs[free]
+    assert its[0] > 0
+    assert np.linalg.norm(r) <= 2e-10 * np.linalg.norm(b)
+    assert np.all(xs[~free] == 0)
+    if precision == "fp64":
+        r_or = b[free] - A[np.ix_(free, free)] @ xs[free]
+        assert np.linalg.norm(r_or) <= 2e-10 * np.linalg.norm(b)
+
+
+def _newton_gpu(case, precision, qpresc=None, dt=None):
+    sh = S()
+    ctx = sh.context_for([case], precision=sh.SHELL_MIXED if precision == "mixed" else sh.SHELL_FP64)
+    dt = dt or case.dt
+    qn, vn = dev(case.q0), dev(case.v0)
+    qp = dev(qpresc) if qpresc is not None else None
+    q1, v1 = torch.zeros_like(qn), torch.zeros_like(qn)
+    rc, st = ctx.newton_step(dt, qn, vn, qp, q1, v1)
+    return rc, host(q1).reshape(-1, 12), host(v1).reshape(-1, 12), st[0]
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("mixed", 1e-5)])
+def test_newton_step_small_sheet(precision, tol):
+    case = W.case_small_sheet()
+    s = O.shell_from_case(case)
+    rc_o, q_o, v_o, st_o = O.newton_step(s, case.ref, case.fixed, case.dt, case.q0, case.v0)
+    assert rc_o == 0
+    rc, q1, v1, st = _newton_gpu(case, precision)
+    assert rc == 0, st
+    assert st["pcg_iters_total"] > 0 and st["newton_iters"] >= 1
+    assert rel_disp_error(q1, q_o, case.q0) <= tol
+    np.testing.assert_array_equal(q1[case.fixed.astype(bool)], case.q0[case.fixed.astype(bool)])
+    np.testing.assert_allclose(v1, (q1 - case.q0) / case.dt, rtol=0, atol=1e-9)
+    res = newton_residual(case, q1, case.q0, case.v0, case.dt)
+    assert np.linalg.norm(res) <= max(1e-8, tol) * st_o["grad_norm0"] * 10
+
+
+def test_newton_free_fall_exact():
+    case = W.sheet_case(3, edges=(), sigma=0.0)
+    v = np.zeros_like(case.ref)
+    v[:, 0:3] = (0.3, -0.2, 0.5)
+    case.v0 = v
+    case.q0 = case.ref.copy()
+    dt = 1e-2
+    rc, q1, v1, st = _newton_gpu(case, "fp64", dt=dt)
+    assert rc == 0 and st["newton_iters"] == 1
+    exp = case.ref.copy()
+    exp[:, 0:3] += dt * v[:, 0:3] + dt * dt * np.array(case.gravity)
+    np.testing.assert_allclose(q1[:, 0:3], exp[:, 0:3], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(q1[:, 3:], exp[:, 3:], rtol=0, atol=1e-10)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-8), ("mixed", 1e-5)])
+def test_newton_step_twist(precision, tol):
+    case = W.case_twist(30)
+    s = O.shell_from_case(case)
+    qp = case.presc(case.dt)
+    rc_o, q_o, _, _ = O.newton_step(s, case.ref, case.fixed, case.dt, case.q0, case.v0, qp)
+    assert rc_o == 0
+    rc, q1, _, st = _newton_gpu(case, precision, qpresc=qp)
+    assert rc == 0, st
+    assert rel_disp_error(q1, q_o, case.q0) <= tol
+
+
+def test_batched_matches_single_shell_oracle():
+    cases = W.case_batch(count=5, seed=3, nmin=2, nmax=9)
+    sh = S()
+    ctx = sh.context_for(cases)
+    qn = dev(np.concatenate([c.q0 for c in cases]))
+    vn = torch.zeros_like(qn)
+    q1, v1 = torch.zeros_like(qn), torch.zeros_like(qn)
+    rc, stats = ctx.newton_step(cases[0].dt, qn, vn, None, q1, v1)
+    assert rc == 0, stats
+    out = host(q1).reshape(-1, 12)
+    off = 0
+    for c, st in zip(cases, stats):
+        s = O.shell_from_case(c)
+        rc_o, q_o, _, _ = O.newton_step(s, c.ref, c.fixed, c.dt, c.q0, c.v0)
+        assert rc_o == 0
+        assert rel_disp_error(out[off:off + c.nodes], q_o, c.q0) <= 1e-9, c.name
+        off += c.nodes
+
+
+def test_all_dofs_fixed_is_a_no_op():
+    case = W.sheet_case(2, edges=("x0", "x1", "y0", "y1"))
+    case.fixed[:] = 1
+    rc, q1, v1, st = _newton_gpu(case, "fp64")
+    assert rc == 0
+    np.testing.assert_array_equal(q1, case.q0)
+
+
+def test_nonfinite_state_reported():
+    case = W.sheet_case(2)
+    q = case.q0.copy()
+    q[4, 0] = np.nan
+    sh = S()
+    ctx = sh.context_for([case])
+    with pytest.raises(sh.ShellError) as e:
+        ctx.energy_grad_hess(dev(q))
+    assert e.value.status == sh.SHELL_E_NONFINITE
