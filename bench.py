@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Benchmark of the BHEM thin-shell hot path on one MI355X.
+
+A step is one implicit-Euler step (Newton iterations with patch
+energy/gradient/Hessian assembly, block-Jacobi CG and line search) of the
+chosen synthetic workload; inputs stay resident in HBM.  Prints one JSON line.
+
+  value        patch E/grad/Hess evaluations per second of the plain FP64
+               path: patches x Newton iterations (each iteration evaluates
+               every patch's energy, gradient and Hessian) / timed seconds
+  ms_per_step  FP64 implicit-step wall time
+  mixed        the same for the FP32-Hessian/CG + FP64-residual form, with its
+               relative displacement error against the FP64 path
+  roofline     dominant kernel group of the FP64 run, measured with HIP events
+  cpu_baseline the FP64 CPU oracle on a bounded sample of the same workload
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("patch E/grad/Hess evals/s + Newton-step ms at 1e-5 rel err, plain FP64 vs mixed/learned")
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+# matrix-core flops per patch of the Hessian contraction (3 diagonal component
+# pairs with 96-long reductions incl. the mass slot, 3 off-diagonal with 80)
+HESS_MFMA_FLOPS = 2 * 16 * 16 * (3 * 96 + 3 * 80)
+
+
+def make_case(name):
+    from paper_2312_14839_amd import workloads as W
+    if name == "cylinder":
+        return W.case_cylinder(256, 256), "cylinder 256x256 patches (periodic), R=0.2 m, L=1 m, axial compression"
+    if name == "twist":
+        return W.case_twist(30), "sheet 30x30 patches, centre derivatives twisted at 1 rad/s"
+    if name == "sheet":
+        return W.case_small_sheet(), "sheet 8x8 patches, one edge clamped, gravity"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def run_steps(case, precision, steps, warmup, stream):
+    import torch
+    from paper_2312_14839_amd import shell as S
+    ctx = S.context_for([case], precision=precision, stream=stream)
+    q = torch.from_numpy(case.q0.reshape(-1).copy()).cuda()
+    v = torch.from_numpy(case.v0.reshape(-1).copy()).cuda()
+    q1, v1 = torch.empty_like(q), torch.empty_like(q)
+    pres = None
+    t = 0.0
+    stats_all = []
+
+    def one_step():
+        nonlocal q, v, q1, v1, t
+        t += case.dt
+        qp = torch.from_numpy(case.presc(t).reshape(-1).copy()).cuda() if case.presc else None
+        rc, st = ctx.newton_step(case.dt, q, v, qp, q1, v1, allow_fail=True)
+        if rc != S.SHELL_OK:
+            raise RuntimeError(f"newton step failed: {S.STATUS_NAMES.get(rc)} {st[0]}")
+        q, q1 = q1, q
+        v, v1 = v1, v
+        return st[0]
+
+    for _ in range(warmup):
+        one_step()
+    ctx.timing_enable(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        stats_all.append(one_step())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # a second pass over fresh steps with per-kernel event timing (adds syncs)
+    ctx.timing_enable(True)
+    for _ in range(max(1, min(steps, 2))):
+        one_step()
+    timing = ctx.timing_get()
+    ctx.timing_enable(False)
+    q_final = None
+    ctx.close()
+    return wall, stats_all, timing, q
+
+
+def qstate_after(case, precision, nsteps, stream):
+    """State after nsteps steps from q0 (for the FP64-vs-mixed comparison)."""
+    import torch
+    from paper_2312_14839_amd import shell as S
+    ctx = S.context_for([case], precision=precision, stream=stream)
+    q = torch.from_numpy(case.q0.reshape(-1).copy()).cuda()
+    v = torch.from_numpy(case.v0.reshape(-1).copy()).cuda()
+    q1, v1 = torch.empty_like(q), torch.empty_like(q)
+    t = 0.0
+    for _ in range(nsteps):
+        t += case.dt
+        qp = torch.from_numpy(case.presc(t).reshape(-1).copy()).cuda() if case.presc else None
+        rc, st = ctx.newton_step(case.dt, q, v, qp, q1, v1, allow_fail=True)
+        if rc != S.SHELL_OK:
+            raise RuntimeError(f"newton step failed: {S.STATUS_NAMES.get(rc)}")
+        q, q1 = q1, q
+        v, v1 = v1, v
+    torch.cuda.synchronize()
+    out = q.cpu().numpy().reshape(-1, 12)
+    ctx.close()
+    return out
+
+
+def cg_bytes(case, timing, tm_bytes, tv_bytes):
+    """Algorithmic HBM bytes of the CG kernel: per iteration every block
+    non-zero (144 values + a column index), per node row its 12x12 inverse
+    diagonal block and 11 passes over 12-vectors (phase A reads z, p_old and
+    writes p_new, q; phase B reads r, q, p_new, x and writes x, r, z)."""
+    blocks = timing["cg_iter_blocks"]
+    rows = timing["cg_iter_rows"]
+    return blocks * (144 * tm_bytes + 4) + rows * (144 * tv_bytes + 4 + 11 * 12 * tv_bytes)
+
+
+def roofline(case, timing, fp32):
+    ms = timing["ms"]
+    grp = max(ms, key=lambda k: ms[k])
+    n = max(timing["launches"][grp], 1)
+    per_launch_ms = ms[grp] / n
+    if grp == "cg":
+        tb = 4 if fp32 else 8
+        total = cg_bytes(case, timing, tb, tb)
+        ach = total / (ms[grp] * 1e-3) / 1e9
+        return grp, {"kernel": "k_cg (persistent block-Jacobi CG)", "bound": "hbm", "achieved": ach,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_ms": per_launch_ms, "algorithmic_bytes_per_launch": total / n}
+    if grp == "hessian":
+        flops = timing["patch_evals"] * HESS_MFMA_FLOPS
+        ach = flops / (ms[grp] * 1e-3) / 1e12
+        peak = FP32_PEAK_TFLOPS if fp32 else FP64_PEAK_TFLOPS
+        return grp, {"kernel": "k_hessian (patch Hessian + scatter)", "bound": "mfma", "achieved": ach,
+                     "peak": peak, "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
+                     "avg_launch_ms": per_launch_ms, "algorithmic_flops_per_launch": flops / n}
+    return grp, {"kernel": grp, "bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
+                 "traffic": None, "avg_launch_ms": per_launch_ms}
+
+
+def cpu_baseline(budget_s=15.0):
+    """Oracle patch energy + gradient + Hessian evaluations per second on a
+    32x32-patch cylinder section (1024 patches), all host threads."""
+    from oracle import oracle as O
+    from paper_2312_14839_amd import workloads as W
+    c = W.case_cylinder(32, 32)
+    s = O.shell_from_case(c)
+    q = W.random_state(c, 1, 1e-4, 1e-3)
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        O.energy(s, q, c.ref)
+        O.gradient(s, q, c.ref)
+        O.matrix_blocks(s, q, c.ref, "hessian")
+        reps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or reps >= 50:
+            break
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": reps * c.patches / el, "unit": "patch E/grad/Hess evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"E+grad+Hess of the {c.patches} patches of a 32x32-patch cylinder section, {reps} reps, "
+                      f"{el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cylinder", choices=["cylinder", "twist", "sheet"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+              "see DESIGN.md for how the path would shard", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2312_14839_amd import shell as S
+    case, desc = make_case(args.workload)
+    stream = torch.cuda.current_stream().cuda_stream
+    print(f"[bench] workload {case.name}: {case.patches} patches, {12 * case.nodes} DOF", file=sys.stderr, flush=True)
+    wall, st64, tm64, q64 = run_steps(case, S.SHELL_FP64, args.steps, args.warmup, stream)
+    newton64 = sum(s["newton_iters"] for s in st64)
+    value = case.patches * newton64 / wall
+    ms_step = 1e3 * wall / args.steps
+    print(f"[bench] fp64: {ms_step:.2f} ms/step, {newton64} Newton its, "
+          f"{sum(s['pcg_iters_total'] for s in st64)} CG its", file=sys.stderr, flush=True)
+    grp, roof = roofline(case, tm64, False)
+    out = {
+        "metric": METRIC, "value": value, "unit": "patch E/grad/Hess evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc, "patches": case.patches, "dof": 12 * case.nodes, "dt": case.dt,
+                   "precision": "fp64", "newton_rtol": 1e-10, "pcg_rtol": 1e-10},
+        "newton_iters_per_step": newton64 / args.steps,
+        "cg_iters_per_step": sum(s["pcg_iters_total"] for s in st64) / args.steps,
+        "kernel_ms_fp64": {k: v for k, v in tm64["ms"].items()},
+        "kernel_launches_fp64": tm64["launches"],
+        "roofline": roof,
+    }
+    if not args.no_mixed:
+        wallm, stm, tmm, _ = run_steps(case, S.SHELL_MIXED, args.steps, args.warmup, stream)
+        newtonm = sum(s["newton_iters"] for s in stm)
+        nst = args.warmup + args.steps
+        qa = qstate_after(case, S.SHELL_FP64, nst, stream)
+        qb = qstate_after(case, S.SHELL_MIXED, nst, stream)
+        ref = case.q0.reshape(-1, 12)
+        err = np.linalg.norm((qb - qa)[:, 0:3]) / max(np.linalg.norm((qa - ref)[:, 0:3]), 1e-300)
+        _, roofm = roofline(case, tmm, True)
+        out["mixed"] = {"value": case.patches * newtonm / wallm, "ms_per_step": 1e3 * wallm / args.steps,
+                        "dtype": "f32 Hessian/CG + f64 residual", "rel_disp_err_vs_fp64": float(err),
+                        "err_steps": nst, "newton_iters_per_step": newtonm / args.steps,
+                        "cg_iters_per_step": sum(s["pcg_iters_total"] for s in stm) / args.steps,
+                        "kernel_ms": tmm["ms"], "roofline": roofm}
+        print(f"[bench] mixed: {1e3 * wallm / args.steps:.2f} ms/step, err {err:.2e}", file=sys.stderr, flush=True)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

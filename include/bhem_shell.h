@@ -167,6 +167,31 @@ shell_status shell_newton_step(shell_ctx *c, double dt, const double *q_n_dev, c
                                const double *q_presc_dev, double *q_np1_dev, double *v_np1_dev,
                                shell_step_stats *stats_host);
 
+/* Device-time accounting per kernel group, measured with HIP events on the
+ * context's stream (adds a stream synchronisation after each timed launch,
+ * so enable it only to measure). */
+enum {
+    SHELL_T_ENERGY_GRAD = 0,   /* patch energy + gradient kernels (and their reductions) */
+    SHELL_T_HESSIAN = 1,       /* patch Hessian + colour scatter kernels (all colours) */
+    SHELL_T_BJ = 2,            /* block-Jacobi factorisation */
+    SHELL_T_CG = 3,            /* persistent CG kernel */
+    SHELL_T_SPMV = 4,          /* stand-alone SpMV / residual kernels */
+    SHELL_T_NGROUPS = 5
+};
+typedef struct {
+    double ms[SHELL_T_NGROUPS];          /* accumulated device milliseconds */
+    int64_t launches[SHELL_T_NGROUPS];   /* timed launches (a group of colour passes counts once) */
+    int64_t patch_evals;                 /* patches through the Hessian kernel */
+    int64_t cg_iter_rows;                /* sum over CG launches and shells of iterations x node rows */
+    int64_t cg_iter_blocks;              /* same with block non-zeros */
+    int64_t cg_iters_max;                /* sum over CG launches of the largest shell iteration count */
+} shell_timing;
+
+/* Reset the counters and turn event timing on (enable != 0) or off. */
+shell_status shell_timing_enable(shell_ctx *c, int32_t enable);
+/* Copy the counters accumulated since the last shell_timing_enable. */
+shell_status shell_timing_get(const shell_ctx *c, shell_timing *out);
+
 #ifdef __cplusplus
 }
 #endif

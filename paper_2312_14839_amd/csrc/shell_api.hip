@@ -64,12 +64,19 @@ struct shell_ctx {
     double* h_red = nullptr;       // [S]
     CgShellOut* h_cg_out = nullptr;
     int* h_fail = nullptr;
+    // event timing
+    bool timing = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    shell_timing tm;
+    std::vector<long long> rows_s, nnzb_s;   // per-shell node rows and block non-zeros
 
     RowBlocks rb() {
         return RowBlocks{nblk, dptr<int>(blk_shell), dptr<int>(blk_row0), dptr<int>(blk_row1), dptr<int>(shell_blk0),
                          dptr<int>(shell_nblk)};
     }
     ~shell_ctx() {
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
         if (h_e_shell) (void)hipHostFree(h_e_shell);
         if (h_red) (void)hipHostFree(h_red);
         if (h_cg_out) (void)hipHostFree(h_cg_out);
@@ -126,6 +133,24 @@ void h2d(shell_ctx* c, void* dst, const void* src, size_t bytes) {
 double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
+
+// Event timer of one kernel group (no-op unless timing is on).
+struct GroupTimer {
+    shell_ctx* c;
+    int group;
+    GroupTimer(shell_ctx* c_, int g) : c(c_), group(g) {
+        if (c->timing) HIPCHK(hipEventRecord(c->ev0, c->stream));
+    }
+    void stop() {
+        if (!c->timing) return;
+        HIPCHK(hipEventRecord(c->ev1, c->stream));
+        HIPCHK(hipEventSynchronize(c->ev1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        c->tm.ms[group] += ms;
+        c->tm.launches[group] += 1;
+    }
+};
 
 // ----------------------------------------------------------- layout
 int node_cols(const shell_desc& d) { return d.periodic1 ? d.n1 : d.n1 + 1; }
@@ -241,6 +266,12 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
         c->h_row_ptr[n + 1] = (int)c->h_col_idx.size();
     }
     c->nnzb = (long long)c->h_col_idx.size();
+    c->rows_s.assign(S, 0);
+    c->nnzb_s.assign(S, 0);
+    for (int s2 = 0; s2 < S; ++s2) {
+        c->rows_s[s2] = c->shells[s2].node_end - c->shells[s2].node_begin;
+        c->nnzb_s[s2] = c->h_row_ptr[c->shells[s2].node_end] - c->h_row_ptr[c->shells[s2].node_begin];
+    }
     std::vector<int> slots((size_t)P * 16);
     std::vector<std::vector<int>> inc(N);
     for (int p = 0; p < P; ++p) {
@@ -353,6 +384,7 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
 void eval_energy_grad(shell_ctx* c, const double* q_in, const double* qhat, double mass_scale, int loads,
                       bool masked, double* grad_out, const int* write_shell_dev) {
     hipStream_t st = c->stream;
+    GroupTimer tmr(c, SHELL_T_ENERGY_GRAD);
     launch_energy_grad(st, c->P, dptr<int4>(c->patch_nodes), dptr<int>(c->patch_shell),
                        dptr<ShellParams>(c->shells_d), dptr<double>(c->phi), q_in, dptr<double>(c->qbar), qhat,
                        mass_scale, 1, loads, dptr<double>(c->e_patch), dptr<double>(c->g_patch));
@@ -362,6 +394,7 @@ void eval_energy_grad(shell_ctx* c, const double* q_in, const double* qhat, doub
                            masked ? dptr<uint16_t>(c->freemask) : nullptr, dptr<int>(c->node_shell), write_shell_dev,
                            grad_out);
     HIPCHK(hipGetLastError());
+    tmr.stop();
     HIPCHK(hipMemcpyAsync(c->h_e_shell, c->e_shell.p, (size_t)c->S * 3 * sizeof(double), hipMemcpyDeviceToHost, st));
 }
 
@@ -374,6 +407,7 @@ void shell_dot(shell_ctx* c, const double* x, const double* y, bool masked) {
 
 void assemble(shell_ctx* c, const double* q_in, double mass_scale, int elastic) {
     hipStream_t st = c->stream;
+    GroupTimer tmr(c, SHELL_T_HESSIAN);
     HIPCHK(hipMemsetAsync(c->vals.p, 0, c->vals.n, st));
     const int pseudo = c->opts.hessian == SHELL_HESS_PSEUDO;
     for (size_t col = 0; col + 1 < c->colour_off.size(); ++col) {
@@ -389,9 +423,12 @@ void assemble(shell_ctx* c, const double* q_in, double mass_scale, int elastic) 
                                    q_in, dptr<double>(c->qbar), mass_scale, elastic, pseudo, dptr<double>(c->vals));
     }
     HIPCHK(hipGetLastError());
+    tmr.stop();
+    c->tm.patch_evals += c->P;
 }
 
 void spmv(shell_ctx* c, const double* x, const double* b, double* y, int mode) {
+    GroupTimer tmr(c, SHELL_T_SPMV);
     if (c->fp32)
         launch_spmv<float>(c->stream, c->N, dptr<int>(c->row_ptr), dptr<int>(c->col_idx), dptr<float>(c->vals),
                            dptr<uint16_t>(c->freemask), x, b, y, mode);
@@ -399,12 +436,14 @@ void spmv(shell_ctx* c, const double* x, const double* b, double* y, int mode) {
         launch_spmv<double>(c->stream, c->N, dptr<int>(c->row_ptr), dptr<int>(c->col_idx), dptr<double>(c->vals),
                             dptr<uint16_t>(c->freemask), x, b, y, mode);
     HIPCHK(hipGetLastError());
+    tmr.stop();
 }
 
 // Factor the block-Jacobi preconditioner; per-shell failure flags in h_fail.
 void bj_factor(shell_ctx* c) {
     hipStream_t st = c->stream;
     HIPCHK(hipMemsetAsync(c->fail_shell.p, 0, c->fail_shell.n, st));
+    GroupTimer tmr(c, SHELL_T_BJ);
     if (c->fp32)
         launch_bj_factor<float>(st, c->N, dptr<int>(c->diag_blk), c->vals.p, 1, dptr<uint16_t>(c->freemask),
                                 dptr<int>(c->node_shell), dptr<float>(c->dinv), dptr<int>(c->fail_shell));
@@ -412,6 +451,7 @@ void bj_factor(shell_ctx* c) {
         launch_bj_factor<double>(st, c->N, dptr<int>(c->diag_blk), c->vals.p, 0, dptr<uint16_t>(c->freemask),
                                  dptr<int>(c->node_shell), dptr<double>(c->dinv), dptr<int>(c->fail_shell));
     HIPCHK(hipGetLastError());
+    tmr.stop();
     HIPCHK(hipMemcpyAsync(c->h_fail, c->fail_shell.p, (size_t)c->S * sizeof(int), hipMemcpyDeviceToHost, st));
     sync(c);
 }
@@ -428,6 +468,7 @@ void cg_launch(shell_ctx* c, const double* b, const std::vector<int>& active, co
     h2d(c, c->cg_active.p, active.data(), c->S * sizeof(int));
     HIPCHK(hipMemsetAsync(c->cg_bar.p, 0, c->cg_bar.n, st));
     HIPCHK(hipMemsetAsync(c->cg_abort.p, 0, c->cg_abort.n, st));
+    GroupTimer tmr(c, SHELL_T_CG);
     hipError_t e;
     if (c->fp32)
         e = launch_cg<float, float>(st, c->nblk, c->rb(), dptr<int>(c->row_ptr), dptr<int>(c->col_idx),
@@ -446,8 +487,20 @@ void cg_launch(shell_ctx* c, const double* b, const std::vector<int>& active, co
                                       dptr<double>(c->cg_rtol2), dptr<int>(c->cg_maxit), dptr<int>(c->cg_active),
                                       dptr<CgShellOut>(c->cg_out));
     HIPCHK(e);
+    tmr.stop();
     HIPCHK(hipMemcpyAsync(c->h_cg_out, c->cg_out.p, (size_t)c->S * sizeof(CgShellOut), hipMemcpyDeviceToHost, st));
     sync(c);
+    if (c->timing) {
+        long long mx = 0;
+        for (int s = 0; s < c->S; ++s)
+            if (active[s]) {
+                const long long it = c->h_cg_out[s].iters;
+                c->tm.cg_iter_rows += it * c->rows_s[s];
+                c->tm.cg_iter_blocks += it * c->nnzb_s[s];
+                mx = std::max(mx, it);
+            }
+        c->tm.cg_iters_max += mx;
+    }
     for (int s = 0; s < c->S; ++s)
         if (active[s] && c->h_cg_out[s].status == 3)
             throw StatusErr{SHELL_E_DEVICE, "CG grid barrier timed out"};
@@ -1010,6 +1063,26 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
     if (worst != SHELL_OK) c->err = "Newton step did not converge for every shell (see stats)";
     return worst;
     API_CATCH
+}
+
+shell_status shell_timing_enable(shell_ctx* c, int32_t enable) {
+    if (!c) return SHELL_E_INVAL;
+    API_TRY
+    HIPCHK(hipSetDevice(c->opts.device));
+    if (!c->ev0) {
+        HIPCHK(hipEventCreate(&c->ev0));
+        HIPCHK(hipEventCreate(&c->ev1));
+    }
+    std::memset(&c->tm, 0, sizeof(c->tm));
+    c->timing = enable != 0;
+    return SHELL_OK;
+    API_CATCH
+}
+
+shell_status shell_timing_get(const shell_ctx* c, shell_timing* out) {
+    if (!c || !out) return SHELL_E_INVAL;
+    *out = c->tm;
+    return SHELL_OK;
 }
 
 }  // extern "C"

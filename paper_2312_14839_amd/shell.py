@@ -65,6 +65,23 @@ class shell_step_stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+SHELL_T_NGROUPS = 5
+TIMING_GROUPS = ["energy_grad", "hessian", "bj_factor", "cg", "spmv"]
+
+
+class shell_timing(C.Structure):
+    _fields_ = [
+        ("ms", C.c_double * SHELL_T_NGROUPS), ("launches", C.c_int64 * SHELL_T_NGROUPS),
+        ("patch_evals", C.c_int64), ("cg_iter_rows", C.c_int64), ("cg_iter_blocks", C.c_int64),
+        ("cg_iters_max", C.c_int64),
+    ]
+
+    def as_dict(self):
+        return {"ms": dict(zip(TIMING_GROUPS, self.ms[:])), "launches": dict(zip(TIMING_GROUPS, self.launches[:])),
+                "patch_evals": self.patch_evals, "cg_iter_rows": self.cg_iter_rows,
+                "cg_iter_blocks": self.cg_iter_blocks, "cg_iters_max": self.cg_iters_max}
+
+
 class ShellError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -99,6 +116,10 @@ def _load():
     lib.shell_pcg_solve.restype = C.c_int32
     lib.shell_newton_step.argtypes = [vp, C.c_double, vp, vp, vp, vp, vp, P(shell_step_stats)]
     lib.shell_newton_step.restype = C.c_int32
+    lib.shell_timing_enable.argtypes = [vp, C.c_int32]
+    lib.shell_timing_enable.restype = C.c_int32
+    lib.shell_timing_get.argtypes = [vp, P(shell_timing)]
+    lib.shell_timing_get.restype = C.c_int32
     return lib
 
 
@@ -106,7 +127,7 @@ lib = _load()
 
 EXPORTED = ["shell_default_opts", "shell_create", "shell_destroy", "shell_last_error", "shell_sizes",
             "shell_energy_grad_hess", "shell_assemble", "shell_get_bsr", "shell_spmv", "shell_pcg_solve",
-            "shell_newton_step"]
+            "shell_newton_step", "shell_timing_enable", "shell_timing_get"]
 
 
 def _ptr(t):
@@ -222,6 +243,15 @@ class ShellContext:
         if not allow_fail:
             self._check(rc)
         return rc, [s.as_dict() for s in st]
+
+
+    def timing_enable(self, on=True):
+        self._check(lib.shell_timing_enable(self.h, int(on)))
+
+    def timing_get(self):
+        t = shell_timing()
+        self._check(lib.shell_timing_get(self.h, C.byref(t)))
+        return t.as_dict()
 
 
 def context_for(cases, **kw) -> ShellContext:
