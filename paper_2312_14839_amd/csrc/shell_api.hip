@@ -300,7 +300,7 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
     const int cap = cg_max_blocks(c->opts.device, c->fp32, c->fp32);
     if (cap <= 0) throw StatusErr{SHELL_E_DEVICE, "cannot query CG kernel occupancy"};
     if (S > cap) throw InvalErr{"too many shells for one context (limit " + std::to_string(cap) + ")"};
-    const int pass = c->fp32 ? 4 * 21 : 4 * 10;   // node rows per block pass of the CG kernel
+    const int pass = cg_rows_per_pass(c->fp32);   // node rows per block pass of the CG kernel
     int target = std::max(pass, (N + cap - 1) / cap);
     target = ((target + pass - 1) / pass) * pass;
     std::vector<int> bshell, brow0, brow1;
@@ -360,7 +360,7 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
     const size_t tvb = (size_t)N * 12 * (c->fp32 ? sizeof(float) : sizeof(double));
     for (DevBuf* b : {&c->cg_x, &c->cg_r, &c->cg_z, &c->cg_p0, &c->cg_p1, &c->cg_q}) alloc(*b, tvb);
     alloc(c->cg_partial, (size_t)c->nblk * 4 * sizeof(double));
-    alloc(c->cg_bar, (size_t)S * sizeof(unsigned));
+    alloc(c->cg_bar, (size_t)S * cg_sync_bytes());
     alloc(c->cg_abort, sizeof(int));
     alloc(c->cg_rtol2, (size_t)S * sizeof(double));
     alloc(c->cg_maxit, (size_t)S * sizeof(int));
@@ -475,7 +475,7 @@ void cg_launch(shell_ctx* c, const double* b, const std::vector<int>& active, co
                                     dptr<float>(c->vals), dptr<float>(c->dinv), dptr<uint16_t>(c->freemask), b,
                                     dptr<float>(c->cg_x), dptr<float>(c->cg_r), dptr<float>(c->cg_z),
                                     dptr<float>(c->cg_p0), dptr<float>(c->cg_p1), dptr<float>(c->cg_q),
-                                    dptr<double>(c->cg_partial), dptr<unsigned>(c->cg_bar), dptr<int>(c->cg_abort),
+                                    dptr<double>(c->cg_partial), c->cg_bar.p, dptr<int>(c->cg_abort),
                                     dptr<double>(c->cg_rtol2), dptr<int>(c->cg_maxit), dptr<int>(c->cg_active),
                                     dptr<CgShellOut>(c->cg_out));
     else
@@ -483,7 +483,7 @@ void cg_launch(shell_ctx* c, const double* b, const std::vector<int>& active, co
                                       dptr<double>(c->vals), dptr<double>(c->dinv), dptr<uint16_t>(c->freemask), b,
                                       dptr<double>(c->cg_x), dptr<double>(c->cg_r), dptr<double>(c->cg_z),
                                       dptr<double>(c->cg_p0), dptr<double>(c->cg_p1), dptr<double>(c->cg_q),
-                                      dptr<double>(c->cg_partial), dptr<unsigned>(c->cg_bar), dptr<int>(c->cg_abort),
+                                      dptr<double>(c->cg_partial), c->cg_bar.p, dptr<int>(c->cg_abort),
                                       dptr<double>(c->cg_rtol2), dptr<int>(c->cg_maxit), dptr<int>(c->cg_active),
                                       dptr<CgShellOut>(c->cg_out));
     HIPCHK(e);
@@ -549,7 +549,6 @@ SolveResult solve(shell_ctx* c, const double* b, double* x_out, const std::vecto
     sync(c);
     std::vector<double> bn2(c->h_red, c->h_red + S);
     std::vector<int> active = active_in;
-    const double inner = std::max(rtol, 1e-5);
     std::vector<double> prev(S, 1.0);
     for (int sweep = 0; sweep < 30; ++sweep) {
         bool any = false;
@@ -558,7 +557,11 @@ SolveResult solve(shell_ctx* c, const double* b, double* x_out, const std::vecto
             any |= active[s] != 0;
         }
         if (!any) break;
-        cg_launch(c, r64, active, std::vector<double>(S, inner), maxit);
+        // each sweep asks the FP32 CG for the reduction still needed (with a
+        // margin), but not below what FP32 arithmetic resolves
+        std::vector<double> inner(S);
+        for (int s = 0; s < S; ++s) inner[s] = std::max(0.5 * rtol / prev[s], 1e-6);
+        cg_launch(c, r64, active, inner, maxit);
         for (int s = 0; s < S; ++s)
             if (active[s]) {
                 R.iters[s] += c->h_cg_out[s].iters;

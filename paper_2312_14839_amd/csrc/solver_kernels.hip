@@ -195,7 +195,10 @@ __global__ void k_regularize(int nnodes, const int* __restrict__ diag_blk, void*
 }
 
 // ------------------------------------------------------ block reductions
-template <int N> __device__ __forceinline__ void block_sum(double (&v)[N], double* lds /* [4][N] */) {
+constexpr int CG_THREADS = 512;
+constexpr int CG_WAVES = CG_THREADS / 64;
+
+template <int N, int NW> __device__ __forceinline__ void block_sum(double (&v)[N], double* lds /* [NW][N] */) {
 #pragma unroll
     for (int k = 0; k < N; ++k)
 #pragma unroll
@@ -207,95 +210,135 @@ template <int N> __device__ __forceinline__ void block_sum(double (&v)[N], doubl
         for (int k = 0; k < N; ++k) lds[wv * N + k] = v[k];
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < N; ++k) v[k] = lds[k] + lds[N + k] + lds[2 * N + k] + lds[3 * N + k];
+    for (int k = 0; k < N; ++k) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) t += lds[w * N + k];
+        v[k] = t;
+    }
 }
 
-// Sum of per-block partials of one shell (partials stored [block][2]),
-// same order in every block.
+// Synchronisation state of one shell during a CG launch (zeroed before it).
+// Arrivals go through CG_GROUPS group counters on separate 128-byte lines
+// and then one top counter, so no single address takes more than about
+// nblk/CG_GROUPS (or CG_GROUPS) atomic operations per barrier.
+constexpr int CG_GROUPS = 16;
+struct alignas(128) ShellSync {
+    unsigned cnt;        // top-level arrivals (group leaders), monotone
+    unsigned gen;        // barriers released so far
+    unsigned pad0[30];
+    double tot[2][4];    // published totals, by barrier parity
+    double pad1[8];
+    unsigned gcnt[CG_GROUPS][32];   // per-group arrivals, monotone, one line each
+};
+
+// Barrier over the nblk blocks of one shell that also sums one partial
+// vector per block.  The last block to arrive adds the partials of the shell
+// in block order (so every block gets the same, reproducible totals),
+// publishes them and releases the others.  Every wait is bounded: after 2^22
+// polls, or when another block has given up, the block sets abort and the
+// kernel ends (legitimate waits are one matrix-product phase).
 template <int N>
-__device__ __forceinline__ void shell_total(const double* __restrict__ part, int blk0, int nblk, double (&v)[N],
-                                            double* lds) {
-#pragma unroll
-    for (int k = 0; k < N; ++k) v[k] = 0.0;
-    for (int i = threadIdx.x; i < nblk; i += blockDim.x)
-#pragma unroll
-        for (int k = 0; k < N; ++k)
-            v[k] += __hip_atomic_load(&part[2 * (size_t)(blk0 + i) + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    block_sum<N>(v, lds);
-}
-
-// Barrier over the nblk blocks of one shell: a monotone arrival counter
-// (zeroed before the launch); barrier number k completes when it reaches
-// nblk*(k+1).  Every wait is bounded: after 2^22 polls, or when another
-// block has given up, the block sets abort and the kernel ends.
-// (Legitimate waits are one matrix-product phase, far below the bound.)
-__device__ __forceinline__ bool shell_barrier(unsigned* cnt, unsigned nblk, unsigned k, int* abort_flag) {
-    __shared__ int s_ok;
-    __syncthreads();
+__device__ __forceinline__ bool reduce_barrier(ShellSync* ss, double* __restrict__ part, int blk, int sb0, int snb,
+                                               unsigned k, double (&v)[N], int* abort_flag, double* lds) {
+    __shared__ int s_last, s_ok;
+    block_sum<N, CG_WAVES>(v, lds);
     if (threadIdx.x == 0) {
-        __threadfence();
-        __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned target = nblk * (k + 1);
-        int ok = 1;
+#pragma unroll
+        for (int n = 0; n < N; ++n) part[4 * (size_t)blk + n] = v[n];
+        // one release fence publishes this block's vector writes and partial
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const int ng = snb < CG_GROUPS ? snb : CG_GROUPS;
+        const int lb = blk - sb0, g = lb % ng;
+        const unsigned gsize = (unsigned)((snb - g + ng - 1) / ng);
+        int last = 0;
+        const unsigned og = __hip_atomic_fetch_add(&ss->gcnt[g][0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (og == gsize * (k + 1) - 1) {
+            // last of its group: carry the group's arrival to the top counter
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            const unsigned ot = __hip_atomic_fetch_add(&ss->cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            last = ot == (unsigned)ng * (k + 1) - 1;
+        }
+        s_last = last;
+        s_ok = 1;
+    }
+    __syncthreads();
+    if (s_last) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        double t[N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) t[n] = 0.0;
+        for (int i = threadIdx.x; i < snb; i += blockDim.x)
+#pragma unroll
+            for (int n = 0; n < N; ++n)
+                t[n] += __hip_atomic_load(&part[4 * (size_t)(sb0 + i) + n], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        block_sum<N, CG_WAVES>(t, lds);
+#pragma unroll
+        for (int n = 0; n < N; ++n) v[n] = t[n];
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int n = 0; n < N; ++n)
+                __hip_atomic_store(&ss->tot[k & 1][n], t[n], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_store(&ss->gen, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        return true;
+    }
+    if (threadIdx.x == 0) {
+        // poll with plain coherent loads; one acquire fence once released
         unsigned spins = 0;
-        while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(&ss->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < k + 1) {
             if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
                 ++spins > (1u << 22)) {
                 __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = 0;
+                s_ok = 0;
                 break;
             }
-            __builtin_amdgcn_s_sleep(2);
+            __builtin_amdgcn_s_sleep(1);
         }
-        __threadfence();
-        s_ok = ok;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+        v[n] = __hip_atomic_load(&ss->tot[k & 1][n], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return s_ok != 0;
 }
 
 // ---------------------------------------------------- persistent CG
 // Block-Jacobi preconditioned CG for every shell at once.  Each shell owns a
 // contiguous set of blocks and node rows; the only synchronisation is the
-// per-shell barrier (two per iteration).  p is double-buffered so that the
-// update p = z + beta p is fused into the matrix product:
+// per-shell reduce-barrier (two per iteration).  p is double-buffered so that
+// the update p = z + beta p is fused into the matrix product:
 //   phase A: p_new = z + beta p_old (own rows), q = A (z + beta p_old), sum p.q
 //   phase B: x += alpha p, r -= alpha q, z = Dinv r, sums r.z and r.r
-// Partial sums alternate between two buffers so a fast block never
-// overwrites values a slow block of its shell is still reading.
 template <class TM, class TV>
-__global__ __launch_bounds__(256) void k_cg(const int* __restrict__ blk_shell, const int* __restrict__ blk_row0,
-                                            const int* __restrict__ blk_row1, const int* __restrict__ shell_blk0,
-                                            const int* __restrict__ shell_nblk, const int* __restrict__ row_ptr,
-                                            const int* __restrict__ col_idx, const TM* __restrict__ vals,
-                                            const TV* __restrict__ dinv, const uint16_t* __restrict__ fm,
-                                            const double* __restrict__ b, TV* __restrict__ x, TV* __restrict__ r,
-                                            TV* __restrict__ z, TV* __restrict__ p0, TV* __restrict__ p1,
-                                            TV* __restrict__ qv, double* __restrict__ partial,
-                                            unsigned* __restrict__ bar, int* __restrict__ abort_flag,
-                                            const double* __restrict__ rtol2_shell,
-                                            const int* __restrict__ maxit_shell,
-                                            const int* __restrict__ active_shell, CgShellOut* __restrict__ out,
-                                            int nblk_total) {
+__global__ __launch_bounds__(CG_THREADS) void k_cg(
+    const int* __restrict__ blk_shell, const int* __restrict__ blk_row0, const int* __restrict__ blk_row1,
+    const int* __restrict__ shell_blk0, const int* __restrict__ shell_nblk, const int* __restrict__ row_ptr,
+    const int* __restrict__ col_idx, const TM* __restrict__ vals, const TV* __restrict__ dinv,
+    const uint16_t* __restrict__ fm, const double* __restrict__ b, TV* __restrict__ x, TV* __restrict__ r,
+    TV* __restrict__ z, TV* __restrict__ p0, TV* __restrict__ p1, TV* __restrict__ qv, double* __restrict__ partial,
+    ShellSync* __restrict__ sync, int* __restrict__ abort_flag, const double* __restrict__ rtol2_shell,
+    const int* __restrict__ maxit_shell, const int* __restrict__ active_shell, CgShellOut* __restrict__ out) {
     constexpr int R = Lay<TM>::R, L = Lay<TM>::L, G = Lay<TM>::G;
-    __shared__ double lds[16];
+    __shared__ double lds[4 * CG_WAVES];
     const int blk = blockIdx.x;
     const int sh = blk_shell[blk];
     const int row0 = blk_row0[blk], row1 = blk_row1[blk];
     const int sb0 = shell_blk0[sh], snb = shell_nblk[sh];
-    unsigned* cnt = bar + sh;
+    ShellSync* ss = sync + sh;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int grp = lane / L, t = lane % L;
     const bool lane_ok = grp < G;
-    const int rows_per_pass = 4 * G;
-    double* part0 = partial;                              // [nblk_total][2]
-    double* part1 = partial + 2 * (size_t)nblk_total;
+    const int gsrc = lane_ok ? lane - t : 0;   // first lane of this lane's group
+    const int rows_per_pass = CG_WAVES * G;
     unsigned nbar = 0;
     const bool leader = blk == sb0 && threadIdx.x == 0;
 
     if (!active_shell[sh]) {
-        for (int node = row0 + threadIdx.x / 12; node < row1; node += blockDim.x / 12)
-            if (threadIdx.x < (blockDim.x / 12) * 12) x[(size_t)node * 12 + threadIdx.x % 12] = TV(0);
+        for (int e = threadIdx.x; e < (row1 - row0) * 12; e += blockDim.x) x[(size_t)row0 * 12 + e] = TV(0);
         if (leader) out[sh] = CgShellOut{0, 0, 0.0, 0.0};
         return;
     }
@@ -304,7 +347,7 @@ __global__ __launch_bounds__(256) void k_cg(const int* __restrict__ blk_shell, c
     auto precond = [&](int node, const TV* rr, TV* zz) {
         TV rall[12];
 #pragma unroll
-        for (int c = 0; c < 12; ++c) rall[c] = __shfl(rr[c % R], lane - t + c / R);
+        for (int c = 0; c < 12; ++c) rall[c] = __shfl(rr[c % R], gsrc + c / R);
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             const TV* drow = dinv + (size_t)node * 144 + (R * t + i) * 12;
@@ -315,18 +358,19 @@ __global__ __launch_bounds__(256) void k_cg(const int* __restrict__ blk_shell, c
         }
     };
 
-    // ---- init: r = b (masked), x = 0, z = Dinv r; sums r.z and b.b
+    // ---- init: r = b (masked), x = 0, p_old = 0, z = Dinv r; sums r.z and b.b
     double sums[2] = {0.0, 0.0};
     for (int base = row0; base < row1; base += rows_per_pass) {
         const int node = base + wv * G + grp;
         const bool ok = lane_ok && node < row1;
+        const int nd = ok ? node : row0;
         TV rr[R], zz[R];
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             const int w = R * t + i;
             rr[i] = ok && is_free(fm, node, w) ? (TV)b[(size_t)node * 12 + w] : TV(0);
         }
-        precond(ok ? node : row0, rr, zz);
+        precond(nd, rr, zz);
         if (ok) {
 #pragma unroll
             for (int i = 0; i < R; ++i) {
@@ -342,19 +386,12 @@ __global__ __launch_bounds__(256) void k_cg(const int* __restrict__ blk_shell, c
             }
         }
     }
-    block_sum<2>(sums, lds);
-    if (threadIdx.x == 0) {
-        part0[2 * blk] = sums[0];
-        part0[2 * blk + 1] = sums[1];
-    }
-    if (!shell_barrier(cnt, snb, nbar++, abort_flag)) {
+    if (!reduce_barrier<2>(ss, partial, blk, sb0, snb, nbar++, sums, abort_flag, lds)) {
         if (leader) out[sh] = CgShellOut{0, 3, 0.0, 0.0};
         return;
     }
-    double tot[2];
-    shell_total<2>(part0, sb0, snb, tot, lds);
-    double rz = tot[0];
-    const double bb = tot[1];
+    double rz = sums[0];
+    const double bb = sums[1];
     const double tol2 = rtol2_shell[sh] * bb;
     const int maxit = maxit_shell[sh];
     if (bb == 0.0) {
@@ -368,14 +405,13 @@ __global__ __launch_bounds__(256) void k_cg(const int* __restrict__ blk_shell, c
     double rr2 = bb;
     for (; it < maxit; ++it) {
         // ---- phase A
-        double pq = 0.0;
+        double pq[1] = {0.0};
         for (int base = row0; base < row1; base += rows_per_pass) {
             const int node = base + wv * G + grp;
-            const bool ok = lane_ok && node < row1;
-            if (!ok) continue;
+            if (!(lane_ok && node < row1)) continue;
             TV acc[R];
             const TV bt = (TV)beta;
-            row_times<TM, TV>(row_ptr, col_idx, vals, node, t, lane - t, false,
+            row_times<TM, TV>(row_ptr, col_idx, vals, node, t, gsrc, false,
                               [&](int col, TV* xv) {
 #pragma unroll
                                   for (int i = 0; i < R; ++i) {
@@ -392,36 +428,31 @@ __global__ __launch_bounds__(256) void k_cg(const int* __restrict__ blk_shell, c
                 const TV qq = is_free(fm, node, w) ? acc[i] : TV(0);
                 pout[at] = pn;
                 qv[at] = qq;
-                pq += (double)pn * (double)qq;
+                pq[0] += (double)pn * (double)qq;
             }
         }
-        double s1[1] = {pq};
-        block_sum<1>(s1, lds);
-        if (threadIdx.x == 0) part1[2 * blk] = s1[0];
-        if (!shell_barrier(cnt, snb, nbar++, abort_flag)) {
+        if (!reduce_barrier<1>(ss, partial, blk, sb0, snb, nbar++, pq, abort_flag, lds)) {
             status = 3;
             break;
         }
-        double t1[1];
-        shell_total<1>(part1, sb0, snb, t1, lds);
-        const double pqt = t1[0];
-        if (!(pqt > 0.0)) {
+        if (!(pq[0] > 0.0)) {
             status = 2;
             break;
         }
-        const double alpha = rz / pqt;
+        const double alpha = rz / pq[0];
         // ---- phase B
         double s2[2] = {0.0, 0.0};
         for (int base = row0; base < row1; base += rows_per_pass) {
             const int node = base + wv * G + grp;
             const bool ok = lane_ok && node < row1;
+            const int nd = ok ? node : row0;
             TV rr[R], zz[R];
 #pragma unroll
             for (int i = 0; i < R; ++i) {
-                const size_t at = (size_t)(ok ? node : row0) * 12 + R * t + i;
+                const size_t at = (size_t)nd * 12 + R * t + i;
                 rr[i] = r[at] - (TV)alpha * qv[at];
             }
-            precond(ok ? node : row0, rr, zz);
+            precond(nd, rr, zz);
             if (ok) {
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
@@ -436,24 +467,18 @@ __global__ __launch_bounds__(256) void k_cg(const int* __restrict__ blk_shell, c
                 }
             }
         }
-        block_sum<2>(s2, lds);
-        if (threadIdx.x == 0) {
-            part0[2 * blk] = s2[0];
-            part0[2 * blk + 1] = s2[1];
-        }
-        if (!shell_barrier(cnt, snb, nbar++, abort_flag)) {
+        if (!reduce_barrier<2>(ss, partial, blk, sb0, snb, nbar++, s2, abort_flag, lds)) {
             status = 3;
             break;
         }
-        shell_total<2>(part0, sb0, snb, tot, lds);
-        rr2 = tot[1];
+        rr2 = s2[1];
         if (rr2 <= tol2) {
             status = 0;
             ++it;
             break;
         }
-        beta = tot[0] / rz;
-        rz = tot[0];
+        beta = s2[0] / rz;
+        rz = s2[0];
         TV* tmp = pin;
         pin = pout;
         pout = tmp;
@@ -474,7 +499,7 @@ __global__ __launch_bounds__(256) void k_shell_dot_part(const int* __restrict__ 
         const int node = e / 12, w = e % 12;
         if (is_free(fm, node, w)) s[0] += x[e] * y[e];
     }
-    block_sum<1>(s, lds);
+    block_sum<1, 4>(s, lds);
     if (threadIdx.x == 0) part[blk] = s[0];
 }
 
@@ -574,31 +599,35 @@ void launch_regularize(hipStream_t st, int nnodes, const int* diag_blk, void* va
 template <class TM, class TV>
 hipError_t launch_cg(hipStream_t st, int nblk, const RowBlocks& rb, const int* row_ptr, const int* col_idx,
                      const TM* vals, const TV* dinv, const uint16_t* freemask, const double* b, TV* x, TV* r, TV* z,
-                     TV* p0, TV* p1, TV* qv, double* partial, unsigned* bar, int* abort_flag, const double* rtol2_shell,
+                     TV* p0, TV* p1, TV* qv, double* partial, void* sync, int* abort_flag, const double* rtol2_shell,
                      const int* maxit_shell, const int* active_shell, CgShellOut* out) {
+    ShellSync* ss = static_cast<ShellSync*>(sync);
     void* args[] = {(void*)&rb.blk_shell, (void*)&rb.blk_row0, (void*)&rb.blk_row1, (void*)&rb.shell_blk0,
                     (void*)&rb.shell_nblk, (void*)&row_ptr, (void*)&col_idx, (void*)&vals, (void*)&dinv,
                     (void*)&freemask, (void*)&b, (void*)&x, (void*)&r, (void*)&z, (void*)&p0, (void*)&p1,
-                    (void*)&qv, (void*)&partial, (void*)&bar, (void*)&abort_flag, (void*)&rtol2_shell,
-                    (void*)&maxit_shell, (void*)&active_shell, (void*)&out, (void*)&nblk};
-    return hipLaunchCooperativeKernel((const void*)k_cg<TM, TV>, dim3(nblk), dim3(256), args, 0, st);
+                    (void*)&qv, (void*)&partial, (void*)&ss, (void*)&abort_flag, (void*)&rtol2_shell,
+                    (void*)&maxit_shell, (void*)&active_shell, (void*)&out};
+    return hipLaunchCooperativeKernel((const void*)k_cg<TM, TV>, dim3(nblk), dim3(CG_THREADS), args, 0, st);
 }
 template hipError_t launch_cg<double, double>(hipStream_t, int, const RowBlocks&, const int*, const int*,
                                               const double*, const double*, const uint16_t*, const double*, double*,
-                                              double*, double*, double*, double*, double*, double*, unsigned*, int*,
+                                              double*, double*, double*, double*, double*, double*, void*, int*,
                                               const double*, const int*, const int*, CgShellOut*);
 template hipError_t launch_cg<float, float>(hipStream_t, int, const RowBlocks&, const int*, const int*, const float*,
                                             const float*, const uint16_t*, const double*, float*, float*, float*,
-                                            float*, float*, float*, double*, unsigned*, int*, const double*,
+                                            float*, float*, float*, double*, void*, int*, const double*,
                                             const int*, const int*, CgShellOut*);
+
+size_t cg_sync_bytes() { return sizeof(ShellSync); }
+int cg_rows_per_pass(int tm_fp32) { return CG_WAVES * (tm_fp32 ? Lay<float>::G : Lay<double>::G); }
 
 int cg_max_blocks(int device, int tm_fp32, int tv_fp32) {
     int per_cu = 0, cus = 0;
     hipError_t e;
     if (tm_fp32)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_cg<float, float>, 256, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_cg<float, float>, CG_THREADS, 0);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_cg<double, double>, 256, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_cg<double, double>, CG_THREADS, 0);
     (void)tv_fp32;
     if (e != hipSuccess) return -1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return -1;

@@ -225,3 +225,20 @@ def test_nonfinite_state_reported():
     with pytest.raises(sh.ShellError) as e:
         ctx.energy_grad_hess(dev(q))
     assert e.value.status == sh.SHELL_E_NONFINITE
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_full_size_cylinder_newton_residual(precision):
+    """256x256 periodic cylinder in the launch configuration the benchmark
+    times: after one GPU Newton step the oracle's gradient of the incremental
+    potential at the result is at the GPU's convergence level."""
+    case = W.case_cylinder(256, 256)
+    qp = case.presc(case.dt)
+    rc, q1, v1, st = _newton_gpu(case, precision, qpresc=qp)
+    assert rc == 0, st
+    res = newton_residual(case, q1, case.q0, case.v0, case.dt)
+    level = max(1e-10 * st["grad_norm0"], st["grad_floor"])
+    assert np.linalg.norm(res) <= 10 * level, (np.linalg.norm(res), st)
+    # prescribed ring moved, clamped ring unchanged
+    fx = case.fixed.astype(bool)
+    np.testing.assert_array_equal(q1[fx], qp[fx])
