@@ -50,22 +50,32 @@ def make_case(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def presc_on_device(case, nsteps):
+    """Prescribed DOF values of steps 1..nsteps, resident in HBM before timing."""
+    import torch
+    if case.presc is None:
+        return [None] * nsteps
+    return [torch.from_numpy(case.presc((k + 1) * case.dt).reshape(-1).copy()).cuda() for k in range(nsteps)]
+
+
 def run_steps(case, precision, steps, warmup, stream, tol):
+    """Warm up, time `steps` implicit steps, then re-run a few more with the
+    library's per-kernel event timing on.  Returns (wall s, stats, timing)."""
     import torch
     from paper_2312_14839_amd import shell as S
     ctx = S.context_for([case], precision=precision, stream=stream, **tol)
+    n_timing = max(1, min(steps, 2))
+    presc = presc_on_device(case, warmup + steps + n_timing)
     q = torch.from_numpy(case.q0.reshape(-1).copy()).cuda()
     v = torch.from_numpy(case.v0.reshape(-1).copy()).cuda()
     q1, v1 = torch.empty_like(q), torch.empty_like(q)
-    pres = None
-    t = 0.0
+    k = 0
     stats_all = []
 
     def one_step():
-        nonlocal q, v, q1, v1, t
-        t += case.dt
-        qp = torch.from_numpy(case.presc(t).reshape(-1).copy()).cuda() if case.presc else None
-        rc, st = ctx.newton_step(case.dt, q, v, qp, q1, v1, allow_fail=True)
+        nonlocal q, v, q1, v1, k
+        rc, st = ctx.newton_step(case.dt, q, v, presc[k], q1, v1, allow_fail=True)
+        k += 1
         if rc != S.SHELL_OK:
             raise RuntimeError(f"newton step failed: {S.STATUS_NAMES.get(rc)} {st[0]}")
         q, q1 = q1, q
@@ -81,15 +91,14 @@ def run_steps(case, precision, steps, warmup, stream, tol):
         stats_all.append(one_step())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    # a second pass over fresh steps with per-kernel event timing (adds syncs)
+    # further steps with per-kernel event timing on (it adds synchronisations)
     ctx.timing_enable(True)
-    for _ in range(max(1, min(steps, 2))):
+    for _ in range(n_timing):
         one_step()
     timing = ctx.timing_get()
     ctx.timing_enable(False)
-    q_final = None
     ctx.close()
-    return wall, stats_all, timing, q
+    return wall, stats_all, timing
 
 
 def qstate_after(case, precision, nsteps, stream, tol):
@@ -97,14 +106,12 @@ def qstate_after(case, precision, nsteps, stream, tol):
     import torch
     from paper_2312_14839_amd import shell as S
     ctx = S.context_for([case], precision=precision, stream=stream, **tol)
+    presc = presc_on_device(case, nsteps)
     q = torch.from_numpy(case.q0.reshape(-1).copy()).cuda()
     v = torch.from_numpy(case.v0.reshape(-1).copy()).cuda()
     q1, v1 = torch.empty_like(q), torch.empty_like(q)
-    t = 0.0
-    for _ in range(nsteps):
-        t += case.dt
-        qp = torch.from_numpy(case.presc(t).reshape(-1).copy()).cuda() if case.presc else None
-        rc, st = ctx.newton_step(case.dt, q, v, qp, q1, v1, allow_fail=True)
+    for k in range(nsteps):
+        rc, st = ctx.newton_step(case.dt, q, v, presc[k], q1, v1, allow_fail=True)
         if rc != S.SHELL_OK:
             raise RuntimeError(f"newton step failed: {S.STATUS_NAMES.get(rc)}")
         q, q1 = q1, q
@@ -179,6 +186,8 @@ def main():
     ap.add_argument("--workload", default="cylinder", choices=["cylinder", "twist", "sheet"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
+                    help="first run a plain device copy of MB megabytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
@@ -186,10 +195,17 @@ def main():
         sys.exit(2)
     import torch
     from paper_2312_14839_amd import shell as S
+    if args.copy_probe:
+        a = torch.ones(args.copy_probe * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     case, desc, tol = make_case(args.workload)
     stream = torch.cuda.current_stream().cuda_stream
     print(f"[bench] workload {case.name}: {case.patches} patches, {12 * case.nodes} DOF", file=sys.stderr, flush=True)
-    wall, st64, tm64, q64 = run_steps(case, S.SHELL_FP64, args.steps, args.warmup, stream, tol)
+    wall, st64, tm64 = run_steps(case, S.SHELL_FP64, args.steps, args.warmup, stream, tol)
     newton64 = sum(s["newton_iters"] for s in st64)
     value = case.patches * newton64 / wall
     ms_step = 1e3 * wall / args.steps
@@ -209,7 +225,7 @@ def main():
         "roofline": roof,
     }
     if not args.no_mixed:
-        wallm, stm, tmm, _ = run_steps(case, S.SHELL_MIXED, args.steps, args.warmup, stream, tol)
+        wallm, stm, tmm = run_steps(case, S.SHELL_MIXED, args.steps, args.warmup, stream, tol)
         newtonm = sum(s["newton_iters"] for s in stm)
         nst = args.warmup + args.steps
         qa = qstate_after(case, S.SHELL_FP64, nst, stream, tol)

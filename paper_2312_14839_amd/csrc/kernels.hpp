@@ -52,14 +52,15 @@ void launch_save_diag(hipStream_t st, int nnodes, const int* diag_blk, const voi
 void launch_regularize(hipStream_t st, int nnodes, const int* diag_blk, void* vals, int vals_fp32,
                        const double* diag, const int* node_shell, const double* delta_shell);
 
+// Persistent block-Jacobi CG; nthreads is 256 or 1024 per block.
 template <class TM, class TV>
-hipError_t launch_cg(hipStream_t st, int nblk, const RowBlocks& rb, const int* row_ptr, const int* col_idx,
-                     const TM* vals, const TV* dinv, const uint16_t* freemask, const double* b, TV* x, TV* r, TV* z,
-                     TV* p0, TV* p1, TV* qv, double* partial, void* sync, int* abort_flag, const double* rtol2_shell,
-                     const int* maxit_shell, const int* active_shell, CgShellOut* out);
-int cg_max_blocks(int device, int tm_fp32, int tv_fp32);
-size_t cg_sync_bytes();                 // per-shell synchronisation state of the CG kernel
-int cg_rows_per_pass(int tm_fp32);      // node rows one CG block covers per pass
+hipError_t launch_cg(hipStream_t st, int nblk, int nthreads, const RowBlocks& rb, const int* row_ptr,
+                     const int* col_idx, const TM* vals, const TV* dinv, const uint16_t* freemask, const double* b,
+                     TV* x, TV* r, TV* z, TV* p0, TV* p1, TV* qv, double* partial, void* sync, int* abort_flag,
+                     const double* rtol2_shell, const int* maxit_shell, const int* active_shell, CgShellOut* out);
+int cg_max_blocks(int device, int tm_fp32, int nthreads);   // co-resident blocks of the CG kernel
+size_t cg_sync_bytes();                                     // per-shell synchronisation state of the CG kernel
+int cg_rows_per_pass(int tm_fp32, int nthreads);            // node rows one CG block covers per pass
 
 // per-shell reductions over node rows (masked = free DOFs only):
 // out[s] = sum x.y over shell s (y = x for norms)

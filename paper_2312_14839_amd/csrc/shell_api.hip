@@ -49,6 +49,7 @@ struct shell_ctx {
     std::vector<uint16_t> h_freemask;
     std::vector<int> colour_off;   // [ncolour + 1] into the concatenated colour lists
     int nblk = 0;                  // CG row blocks
+    int cg_threads = 256;          // threads per CG block
     std::vector<int> h_shell_blk0, h_shell_nblk;
     // device data
     DevBuf shells_d, phi, qbar, freemask, node_shell, patch_nodes, patch_shell, patch_slots, colour_list, inc_ptr,
@@ -296,17 +297,33 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
         clist.insert(clist.end(), colour_lists[col].begin(), colour_lists[col].end());
         c->colour_off.push_back((int)clist.size());
     }
-    // CG row blocks: contiguous node rows, never straddling a shell
-    const int cap = cg_max_blocks(c->opts.device, c->fp32, c->fp32);
+    // CG row blocks: contiguous node rows, never straddling a shell.  Large
+    // shells use 1024-thread blocks (fewer blocks make the per-iteration
+    // barriers cheaper); small ones 256-thread blocks spread over more CUs.
+    int max_rows = 0;
+    for (int s = 0; s < S; ++s) max_rows = std::max(max_rows, c->shells[s].node_end - c->shells[s].node_begin);
+    c->cg_threads = max_rows >= 16 * cg_rows_per_pass(c->fp32, 1024) ? 1024 : 256;
+    int cap = cg_max_blocks(c->opts.device, c->fp32, c->cg_threads);
     if (cap <= 0) throw StatusErr{SHELL_E_DEVICE, "cannot query CG kernel occupancy"};
+    if (S > cap && c->cg_threads == 1024) {
+        c->cg_threads = 256;
+        cap = cg_max_blocks(c->opts.device, c->fp32, c->cg_threads);
+    }
     if (S > cap) throw InvalErr{"too many shells for one context (limit " + std::to_string(cap) + ")"};
-    const int pass = cg_rows_per_pass(c->fp32);   // node rows per block pass of the CG kernel
+    const int pass = cg_rows_per_pass(c->fp32, c->cg_threads);   // node rows per block pass
     int target = std::max(pass, (N + cap - 1) / cap);
     target = ((target + pass - 1) / pass) * pass;
     std::vector<int> bshell, brow0, brow1;
+    int used = 0;
+    for (;; target += pass) {   // grow the rows per block until every block fits on the device at once
+        used = 0;
+        for (int s = 0; s < S; ++s)
+            used += std::max(1, (c->shells[s].node_end - c->shells[s].node_begin + target - 1) / target);
+        if (used <= cap) break;
+    }
     c->h_shell_blk0.assign(S, 0);
     c->h_shell_nblk.assign(S, 0);
-    int used = 0;
+    used = 0;
     for (int s = 0; s < S; ++s) {
         const int r0 = c->shells[s].node_begin, r1 = c->shells[s].node_end;
         int nb = std::max(1, (r1 - r0 + target - 1) / target);
@@ -318,10 +335,6 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
             brow1.push_back(r0 + (int)((long long)(r1 - r0) * (k + 1) / nb));
         }
         used += nb;
-    }
-    if (used > cap) {
-        // fall back to fewer blocks per shell
-        throw InvalErr{"grid needs more co-resident CG blocks than the device holds"};
     }
     c->nblk = used;
     // theta-space basis table
@@ -471,7 +484,7 @@ void cg_launch(shell_ctx* c, const double* b, const std::vector<int>& active, co
     GroupTimer tmr(c, SHELL_T_CG);
     hipError_t e;
     if (c->fp32)
-        e = launch_cg<float, float>(st, c->nblk, c->rb(), dptr<int>(c->row_ptr), dptr<int>(c->col_idx),
+        e = launch_cg<float, float>(st, c->nblk, c->cg_threads, c->rb(), dptr<int>(c->row_ptr), dptr<int>(c->col_idx),
                                     dptr<float>(c->vals), dptr<float>(c->dinv), dptr<uint16_t>(c->freemask), b,
                                     dptr<float>(c->cg_x), dptr<float>(c->cg_r), dptr<float>(c->cg_z),
                                     dptr<float>(c->cg_p0), dptr<float>(c->cg_p1), dptr<float>(c->cg_q),
@@ -479,7 +492,7 @@ void cg_launch(shell_ctx* c, const double* b, const std::vector<int>& active, co
                                     dptr<double>(c->cg_rtol2), dptr<int>(c->cg_maxit), dptr<int>(c->cg_active),
                                     dptr<CgShellOut>(c->cg_out));
     else
-        e = launch_cg<double, double>(st, c->nblk, c->rb(), dptr<int>(c->row_ptr), dptr<int>(c->col_idx),
+        e = launch_cg<double, double>(st, c->nblk, c->cg_threads, c->rb(), dptr<int>(c->row_ptr), dptr<int>(c->col_idx),
                                       dptr<double>(c->vals), dptr<double>(c->dinv), dptr<uint16_t>(c->freemask), b,
                                       dptr<double>(c->cg_x), dptr<double>(c->cg_r), dptr<double>(c->cg_z),
                                       dptr<double>(c->cg_p0), dptr<double>(c->cg_p1), dptr<double>(c->cg_q),

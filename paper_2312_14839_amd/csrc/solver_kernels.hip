@@ -47,7 +47,10 @@ template <> struct VecLoad<float, 4> {
 };
 
 // acc[0..R) = rows R*t .. R*t+R-1 of (block row `node`) times x_eff, where
-// xe(col, lane-local index) supplies this lane's R values of the column block.
+// xe(col, xv) supplies this lane's R values of column block `col`.  The next
+// block's column index and x-values are fetched while the current block is
+// multiplied, so the dependent index -> vector load chain overlaps the
+// matrix stream.
 template <class TM, class TV, class XF>
 __device__ __forceinline__ void row_times(const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
                                           const TM* __restrict__ vals, int node, int t, int gbase, bool absval,
@@ -56,22 +59,27 @@ __device__ __forceinline__ void row_times(const int* __restrict__ row_ptr, const
 #pragma unroll
     for (int i = 0; i < R; ++i) acc[i] = TV(0);
     const int b0 = row_ptr[node], b1 = row_ptr[node + 1];
+    if (b0 >= b1) return;
+    TV xv[R];
+    xe(col_idx[b0], xv);
     for (int b = b0; b < b1; ++b) {
-        const int col = col_idx[b];
-        TV xv[R];
-        xe(col, xv);
+        TV xn[R];
+        if (b + 1 < b1) xe(col_idx[b + 1], xn);
+        const TM* blk = vals + (size_t)b * 144 + R * t;
+        TM a[12][R];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) VecLoad<TM, R>::ld(blk + c * 12, a[c]);
         if (absval)
 #pragma unroll
             for (int i = 0; i < R; ++i) xv[i] = fabs(xv[i]);
-        const TM* blk = vals + (size_t)b * 144 + R * t;
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-            TM a[R];
-            VecLoad<TM, R>::ld(blk + c * 12, a);
             const TV xc = __shfl(xv[c % R], gbase + c / R);
 #pragma unroll
-            for (int i = 0; i < R; ++i) acc[i] += (absval ? (TV)fabs(a[i]) : (TV)a[i]) * xc;
+            for (int i = 0; i < R; ++i) acc[i] += (absval ? (TV)fabs(a[c][i]) : (TV)a[c][i]) * xc;
         }
+#pragma unroll
+        for (int i = 0; i < R; ++i) xv[i] = xn[i];
     }
 }
 
@@ -195,8 +203,6 @@ __global__ void k_regularize(int nnodes, const int* __restrict__ diag_blk, void*
 }
 
 // ------------------------------------------------------ block reductions
-constexpr int CG_THREADS = 512;
-constexpr int CG_WAVES = CG_THREADS / 64;
 
 template <int N, int NW> __device__ __forceinline__ void block_sum(double (&v)[N], double* lds /* [NW][N] */) {
 #pragma unroll
@@ -238,11 +244,11 @@ struct alignas(128) ShellSync {
 // publishes them and releases the others.  Every wait is bounded: after 2^22
 // polls, or when another block has given up, the block sets abort and the
 // kernel ends (legitimate waits are one matrix-product phase).
-template <int N>
+template <int N, int NW>
 __device__ __forceinline__ bool reduce_barrier(ShellSync* ss, double* __restrict__ part, int blk, int sb0, int snb,
                                                unsigned k, double (&v)[N], int* abort_flag, double* lds) {
     __shared__ int s_last, s_ok;
-    block_sum<N, CG_WAVES>(v, lds);
+    block_sum<N, NW>(v, lds);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int n = 0; n < N; ++n) part[4 * (size_t)blk + n] = v[n];
@@ -272,7 +278,7 @@ __device__ __forceinline__ bool reduce_barrier(ShellSync* ss, double* __restrict
 #pragma unroll
             for (int n = 0; n < N; ++n)
                 t[n] += __hip_atomic_load(&part[4 * (size_t)(sb0 + i) + n], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        block_sum<N, CG_WAVES>(t, lds);
+        block_sum<N, NW>(t, lds);
 #pragma unroll
         for (int n = 0; n < N; ++n) v[n] = t[n];
         if (threadIdx.x == 0) {
@@ -313,8 +319,8 @@ __device__ __forceinline__ bool reduce_barrier(ShellSync* ss, double* __restrict
 // the update p = z + beta p is fused into the matrix product:
 //   phase A: p_new = z + beta p_old (own rows), q = A (z + beta p_old), sum p.q
 //   phase B: x += alpha p, r -= alpha q, z = Dinv r, sums r.z and r.r
-template <class TM, class TV>
-__global__ __launch_bounds__(CG_THREADS) void k_cg(
+template <class TM, class TV, int NT>
+__global__ __launch_bounds__(NT) void k_cg(
     const int* __restrict__ blk_shell, const int* __restrict__ blk_row0, const int* __restrict__ blk_row1,
     const int* __restrict__ shell_blk0, const int* __restrict__ shell_nblk, const int* __restrict__ row_ptr,
     const int* __restrict__ col_idx, const TM* __restrict__ vals, const TV* __restrict__ dinv,
@@ -323,7 +329,8 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg(
     ShellSync* __restrict__ sync, int* __restrict__ abort_flag, const double* __restrict__ rtol2_shell,
     const int* __restrict__ maxit_shell, const int* __restrict__ active_shell, CgShellOut* __restrict__ out) {
     constexpr int R = Lay<TM>::R, L = Lay<TM>::L, G = Lay<TM>::G;
-    __shared__ double lds[4 * CG_WAVES];
+    constexpr int NW = NT / 64;
+    __shared__ double lds[4 * NW];
     const int blk = blockIdx.x;
     const int sh = blk_shell[blk];
     const int row0 = blk_row0[blk], row1 = blk_row1[blk];
@@ -333,7 +340,7 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg(
     const int grp = lane / L, t = lane % L;
     const bool lane_ok = grp < G;
     const int gsrc = lane_ok ? lane - t : 0;   // first lane of this lane's group
-    const int rows_per_pass = CG_WAVES * G;
+    const int rows_per_pass = NW * G;
     unsigned nbar = 0;
     const bool leader = blk == sb0 && threadIdx.x == 0;
 
@@ -386,7 +393,7 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg(
             }
         }
     }
-    if (!reduce_barrier<2>(ss, partial, blk, sb0, snb, nbar++, sums, abort_flag, lds)) {
+    if (!reduce_barrier<2, NW>(ss, partial, blk, sb0, snb, nbar++, sums, abort_flag, lds)) {
         if (leader) out[sh] = CgShellOut{0, 3, 0.0, 0.0};
         return;
     }
@@ -431,7 +438,7 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg(
                 pq[0] += (double)pn * (double)qq;
             }
         }
-        if (!reduce_barrier<1>(ss, partial, blk, sb0, snb, nbar++, pq, abort_flag, lds)) {
+        if (!reduce_barrier<1, NW>(ss, partial, blk, sb0, snb, nbar++, pq, abort_flag, lds)) {
             status = 3;
             break;
         }
@@ -467,7 +474,7 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg(
                 }
             }
         }
-        if (!reduce_barrier<2>(ss, partial, blk, sb0, snb, nbar++, s2, abort_flag, lds)) {
+        if (!reduce_barrier<2, NW>(ss, partial, blk, sb0, snb, nbar++, s2, abort_flag, lds)) {
             status = 3;
             break;
         }
@@ -597,39 +604,39 @@ void launch_regularize(hipStream_t st, int nnodes, const int* diag_blk, void* va
 }
 
 template <class TM, class TV>
-hipError_t launch_cg(hipStream_t st, int nblk, const RowBlocks& rb, const int* row_ptr, const int* col_idx,
-                     const TM* vals, const TV* dinv, const uint16_t* freemask, const double* b, TV* x, TV* r, TV* z,
-                     TV* p0, TV* p1, TV* qv, double* partial, void* sync, int* abort_flag, const double* rtol2_shell,
-                     const int* maxit_shell, const int* active_shell, CgShellOut* out) {
+hipError_t launch_cg(hipStream_t st, int nblk, int nthreads, const RowBlocks& rb, const int* row_ptr,
+                     const int* col_idx, const TM* vals, const TV* dinv, const uint16_t* freemask, const double* b,
+                     TV* x, TV* r, TV* z, TV* p0, TV* p1, TV* qv, double* partial, void* sync, int* abort_flag,
+                     const double* rtol2_shell, const int* maxit_shell, const int* active_shell, CgShellOut* out) {
     ShellSync* ss = static_cast<ShellSync*>(sync);
     void* args[] = {(void*)&rb.blk_shell, (void*)&rb.blk_row0, (void*)&rb.blk_row1, (void*)&rb.shell_blk0,
                     (void*)&rb.shell_nblk, (void*)&row_ptr, (void*)&col_idx, (void*)&vals, (void*)&dinv,
                     (void*)&freemask, (void*)&b, (void*)&x, (void*)&r, (void*)&z, (void*)&p0, (void*)&p1,
                     (void*)&qv, (void*)&partial, (void*)&ss, (void*)&abort_flag, (void*)&rtol2_shell,
                     (void*)&maxit_shell, (void*)&active_shell, (void*)&out};
-    return hipLaunchCooperativeKernel((const void*)k_cg<TM, TV>, dim3(nblk), dim3(CG_THREADS), args, 0, st);
+    const void* fn = nthreads == 1024 ? (const void*)k_cg<TM, TV, 1024> : (const void*)k_cg<TM, TV, 256>;
+    return hipLaunchCooperativeKernel(fn, dim3(nblk), dim3(nthreads), args, 0, st);
 }
-template hipError_t launch_cg<double, double>(hipStream_t, int, const RowBlocks&, const int*, const int*,
+template hipError_t launch_cg<double, double>(hipStream_t, int, int, const RowBlocks&, const int*, const int*,
                                               const double*, const double*, const uint16_t*, const double*, double*,
                                               double*, double*, double*, double*, double*, double*, void*, int*,
                                               const double*, const int*, const int*, CgShellOut*);
-template hipError_t launch_cg<float, float>(hipStream_t, int, const RowBlocks&, const int*, const int*, const float*,
-                                            const float*, const uint16_t*, const double*, float*, float*, float*,
-                                            float*, float*, float*, double*, void*, int*, const double*,
-                                            const int*, const int*, CgShellOut*);
+template hipError_t launch_cg<float, float>(hipStream_t, int, int, const RowBlocks&, const int*, const int*,
+                                            const float*, const float*, const uint16_t*, const double*, float*,
+                                            float*, float*, float*, float*, float*, double*, void*, int*,
+                                            const double*, const int*, const int*, CgShellOut*);
 
 size_t cg_sync_bytes() { return sizeof(ShellSync); }
-int cg_rows_per_pass(int tm_fp32) { return CG_WAVES * (tm_fp32 ? Lay<float>::G : Lay<double>::G); }
+int cg_rows_per_pass(int tm_fp32, int nthreads) { return (nthreads / 64) * (tm_fp32 ? Lay<float>::G : Lay<double>::G); }
 
-int cg_max_blocks(int device, int tm_fp32, int tv_fp32) {
+int cg_max_blocks(int device, int tm_fp32, int nthreads) {
     int per_cu = 0, cus = 0;
-    hipError_t e;
+    const void* fn;
     if (tm_fp32)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_cg<float, float>, CG_THREADS, 0);
+        fn = nthreads == 1024 ? (const void*)k_cg<float, float, 1024> : (const void*)k_cg<float, float, 256>;
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_cg<double, double>, CG_THREADS, 0);
-    (void)tv_fp32;
-    if (e != hipSuccess) return -1;
+        fn = nthreads == 1024 ? (const void*)k_cg<double, double, 1024> : (const void*)k_cg<double, double, 256>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nthreads, 0) != hipSuccess) return -1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return -1;
     return per_cu * cus;
 }
