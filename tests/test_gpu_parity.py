@@ -242,3 +242,32 @@ def test_full_size_cylinder_newton_residual(precision):
     # prescribed ring moved, clamped ring unchanged
     fx = case.fixed.astype(bool)
     np.testing.assert_array_equal(q1[fx], qp[fx])
+
+
+def test_full_size_batch_sampled():
+    """The 256-sheet batch in one context (one persistent CG launch for all
+    sheets): the three smallest sheets match the single-shell oracle Newton
+    step; for three of the largest the oracle gradient at the GPU result is at
+    the GPU's convergence level."""
+    cases = W.case_batch(256)
+    sh = S()
+    ctx = sh.context_for(cases)
+    qn = dev(np.concatenate([c.q0 for c in cases]))
+    vn = torch.zeros_like(qn)
+    q1, v1 = torch.zeros_like(qn), torch.zeros_like(qn)
+    rc, stats = ctx.newton_step(cases[0].dt, qn, vn, None, q1, v1)
+    assert rc == 0, [s for s in stats if s["status"] != 0][:2]
+    out = host(q1).reshape(-1, 12)
+    offs = np.cumsum([0] + [c.nodes for c in cases])
+    order = np.argsort([c.patches for c in cases])
+    for k in list(order[:3]):
+        c = cases[k]
+        s = O.shell_from_case(c)
+        rc_o, q_o, _, _ = O.newton_step(s, c.ref, c.fixed, c.dt, c.q0, c.v0)
+        assert rc_o == 0
+        assert rel_disp_error(out[offs[k]:offs[k + 1]], q_o, c.q0) <= 1e-8, c.name
+    for k in list(order[-3:]):
+        c, st = cases[k], stats[k]
+        res = newton_residual(c, out[offs[k]:offs[k + 1]], c.q0, c.v0, c.dt)
+        level = max(1e-10 * st["grad_norm0"], st["grad_floor"])
+        assert np.linalg.norm(res) <= 10 * level, (c.name, np.linalg.norm(res), st)
