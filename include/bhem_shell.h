@@ -77,7 +77,7 @@ typedef struct {
     int32_t precision;           /* SHELL_FP64 or SHELL_MIXED (FP32 Hessian, matrix and inner CG;
                                     FP64 gradient, residual, refinement and block inverses) */
     int32_t hessian;             /* SHELL_HESS_EXACT or SHELL_HESS_PSEUDO */
-    int32_t warm_start;          /* SHELL_WS_NONE or SHELL_WS_MLP (needs shell_mlp_set_weights) */
+    int32_t warm_start;          /* SHELL_WS_NONE or SHELL_WS_MLP (needs shell_mlp_set_params first) */
     int32_t newton_maxit;        /* > 0 */
     int32_t pcg_maxit;           /* > 0, per linear solve */
     double newton_rtol;          /* Newton stops at ||g|| <= max(newton_rtol ||g_0||, rounding floor) */
@@ -93,7 +93,7 @@ typedef struct {
     int32_t pcg_iters_total;     /* CG iterations over all Newton iterations */
     int32_t ls_backtracks;       /* rejected line-search trials */
     int32_t refine_sweeps;       /* FP64 refinement sweeps (mixed precision) */
-    int32_t warm_start_used;     /* Newton iterations whose CG started from an accepted warm start */
+    int32_t warm_start_used;     /* 1 if the Newton iteration started from the learned guess */
     double grad_norm0, grad_norm, grad_floor, reg_delta;
     double t_assemble_ms, t_pcg_ms, t_step_ms;   /* whole-context wall times */
 } shell_step_stats;
@@ -191,6 +191,85 @@ typedef struct {
 shell_status shell_timing_enable(shell_ctx *c, int32_t enable);
 /* Copy the counters accumulated since the last shell_timing_enable. */
 shell_status shell_timing_get(const shell_ctx *c, shell_timing *out);
+
+/* ------------------------------------------------------------------
+ * Learned warm start of the Newton iteration.  This is an extension: the
+ * paper has no learned component.  Its conclusions note that positions and
+ * their parametric derivatives carry different units (Sec. 8, "Loss
+ * functions"); the features are therefore scaled per DOF kind.
+ *
+ * A per-node network 36 -> 128 -> 128 -> 12 (ReLU, ReLU, linear):
+ *   h1 = relu(x W1 + b1), h2 = relu(h1 W2 + b2), y = h2 W3 + b3,
+ * products in bfloat16 (round to nearest even) with FP32 accumulation,
+ * FP32 master parameters.  Parameter vector (float, row-major, this order):
+ *   W1[36][128], b1[128], W2[128][128], b2[128], W3[128][12], b3[12].
+ * Each step's Newton iteration starts at q_s (qhat = q_n + dt v_n on free
+ * DOFs, prescribed values on the others) and ends at q_{n+1}; its
+ * correction is D = q_{n+1} - q_s on free DOFs.  Features of node n of shell
+ * s at the start of a step, for DOF kind k = w / 3 (x, x_1, x_2, x_12) of
+ * the node's 12 DOFs w = 3k + component:
+ *   x[w]      = (q_s - qbar)[n][w] / s_u[s][k]   (displacement from the reference)
+ *   x[12 + w] = b[n][w] / s_b[s][k]             (b = -grad E(q_s), 0 on prescribed DOFs)
+ *   x[24 + w] = Dprev[n][w] / s_d[s][k]          (the previous step's correction)
+ * with s_*[s][k] the root mean square of that quantity over the free DOFs of
+ * kind k of shell s (1 if it is zero).  The network predicts the change of
+ * the correction, w = s_d y on free DOFs.  The Newton iteration then starts
+ * at q_s + c1 Dprev + c2 w, c the Galerkin solution of the quadratic model
+ * of the incremental potential E in span{Dprev, w} (its Hessian from the
+ * gradient differences grad E(q_s + d) - grad E(q_s), d = Dprev, w), if that
+ * point satisfies the Armijo condition on E and at least halves
+ * ||grad E|| (else the same is tried with Dprev alone).  Otherwise, for
+ * shells whose previous step did not converge
+ * (and at a context's first step), and where the network's output is not
+ * finite, it starts at q_s exactly as without a warm start.
+ * Convergence is still measured against ||grad E(q_s)||.
+ * ------------------------------------------------------------------ */
+#define SHELL_MLP_IN 36
+#define SHELL_MLP_HIDDEN 128
+#define SHELL_MLP_OUT 12
+#define SHELL_MLP_PARAMS 22796
+
+/* Load the network's parameters (theta_host: SHELL_MLP_PARAMS floats, host
+ * memory, copied) and reset the Adam state.  Required before a step with
+ * warm_start = SHELL_WS_MLP.  SHELL_E_NONFINITE for a non-finite value. */
+shell_status shell_mlp_set_params(shell_ctx *c, const float *theta_host);
+
+/* Copy the current parameters to theta_host (SHELL_MLP_PARAMS floats). */
+shell_status shell_mlp_get_params(shell_ctx *c, float *theta_host);
+
+/* Inference: out_dev[n][12] = y(feat_dev[n][36]), device arrays, n >= 0. */
+shell_status shell_mlp_forward(shell_ctx *c, const float *feat_dev, float *out_dev, int64_t n);
+
+/* Loss and gradient of one mini-batch: samples idx_dev[batch] (int64,
+ * device, each in [0, n_samples), checked: SHELL_E_INVAL otherwise) of
+ * feat_dev[n_samples][36] / tgt_dev[n_samples][12]; loss = mean over the
+ * batch of sum_w (y_w - t_w)^2.  batch is a positive multiple of 32.
+ * loss_host (1 double) and grad_host (SHELL_MLP_PARAMS floats) may be NULL.
+ * The parameters are not changed. */
+shell_status shell_mlp_loss_grad(shell_ctx *c, const float *feat_dev, const float *tgt_dev, int64_t n_samples,
+                                 const int64_t *idx_dev, int32_t batch, double *loss_host, float *grad_host);
+
+/* Train on n_samples device samples: steps Adam steps (beta 0.9, 0.999,
+ * eps 1e-8, learning rate lr) on mini-batches of `batch` samples drawn with
+ * replacement by a splitmix64 hash of (seed, step, i).  batch is a positive
+ * multiple of 32.  loss_host ([steps] doubles or NULL) receives each step's
+ * mini-batch loss before its update. */
+shell_status shell_mlp_train(shell_ctx *c, const float *feat_dev, const float *tgt_dev, int64_t n_samples,
+                             int32_t batch, int32_t steps, float lr, uint64_t seed, double *loss_host);
+
+/* Record training samples during shell_newton_step: after each step,
+ * per_shell nodes of every shell that converged and has a previous
+ * correction (picked by a hash of seed, call and sample index) append their
+ * features at the step's start (feat_dev[.][36]) and the target
+ * t = (D - Dprev) / s_d (tgt_dev[.][12]), while capacity samples are not
+ * exceeded.  The buffers are the caller's device memory and must outlive
+ * the recording; feat_dev = NULL stops recording.  The sample count
+ * restarts at 0. */
+shell_status shell_mlp_record(shell_ctx *c, float *feat_dev, float *tgt_dev, int64_t capacity, int32_t per_shell,
+                              uint64_t seed);
+
+/* Samples recorded since the last shell_mlp_record. */
+shell_status shell_mlp_recorded(const shell_ctx *c, int64_t *count);
 
 #ifdef __cplusplus
 }

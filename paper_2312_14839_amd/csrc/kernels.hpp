@@ -80,5 +80,34 @@ void launch_copy_shell(hipStream_t st, int nnodes, const double* src, const int*
 template <class TV>
 void launch_add_to(hipStream_t st, int n, const TV* dx, double* x);
 void launch_cast_to_float(hipStream_t st, int n, const double* x, float* y);
+void launch_add_shell(hipStream_t st, int nnodes, const double* src, const int* node_shell, const int* flag_shell,
+                      double* dst);
+
+// --------------------------------------------------- warm-start network
+constexpr int MLP_IN = 36, MLP_H = 128, MLP_OUT = 12;
+constexpr int MLP_NPARAMS = MLP_IN * MLP_H + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H * MLP_OUT + MLP_OUT;
+int mlp_bf16_elems();
+size_t mlp_train_work_bytes(int batch);
+void launch_mlp_pack(hipStream_t st, const float* theta, void* w_bf16);
+void launch_mlp_forward(hipStream_t st, const float* theta, const void* w, const float* feat, float* out, long long n);
+// loss (atomically added, mean over the batch) and gradient (atomically added) of one mini-batch
+void launch_mlp_grad(hipStream_t st, const float* theta, const void* w, const float* feat, const float* tgt,
+                     const long long* idx, int batch, void* work, float* grad, double* loss);
+void launch_mlp_adam(hipStream_t st, float* theta, const float* g, float* m, float* v, int n, float lr, int step);
+void launch_sample_idx(hipStream_t st, long long n, int batch, unsigned long long seed, long long* idx);
+// per-shell, per-kind RMS scales of u = q - qbar, b, dprev: scale[s*12 + 4*quantity + kind]
+void launch_feat_scale(hipStream_t st, const RowBlocks& rb, int nshell, const double* q, const double* qbar,
+                       const double* b, const double* dprev, const uint16_t* fm, double* part, const int* cnt_kind,
+                       float* scale);
+void launch_mlp_record(hipStream_t st, int nshell, int K, unsigned long long seed, const ShellParams* shells,
+                       const long long* sbase, const double* q, const double* qbar, const double* b,
+                       const double* dprev, const double* d, const float* scale, float* feat_out, float* tgt_out);
+void launch_mlp_guess(hipStream_t st, int nnodes, const float* theta, const void* w, const int* node_shell,
+                      const int* flag, const double* q, const double* qbar, const double* b, const double* dprev,
+                      const uint16_t* fm, const float* scale, double* corr);
+void launch_axpy2_shell(hipStream_t st, int nnodes, const double* x, const double* d1, const double* d2,
+                        const double* coef, const int* node_shell, double* y);
+void launch_masked_diff(hipStream_t st, int nnodes, const double* a, const double* b, const uint16_t* fm,
+                        const int* node_shell, const int* flag, double* out);
 
 }  // namespace bhem

@@ -65,6 +65,21 @@ struct shell_ctx {
     double* h_red = nullptr;       // [S]
     CgShellOut* h_cg_out = nullptr;
     int* h_fail = nullptr;
+    // warm-start network: FP32 master weights, bf16 operand copies, Adam state
+    bool mlp_ready = false;
+    int adam_step = 0;
+    DevBuf mlp_theta, mlp_w, mlp_m, mlp_v, mlp_grad, mlp_loss, mlp_idx, mlp_work, feat_part, feat_scale, cnt_kind,
+        dstep, qstart, b0, guess, rec_base;
+    std::vector<char> h_hist;   // per shell: dstep holds the last step's correction
+    int mlp_work_batch = 0;
+    long long mlp_loss_n = 0;
+    unsigned long long rec_calls = 0;
+    // recording of (features, target) samples during Newton solves
+    float* rec_feat = nullptr;
+    float* rec_tgt = nullptr;
+    long long rec_cap = 0, rec_count = 0;
+    int rec_K = 0;
+    unsigned long long rec_seed = 0;
     // event timing
     bool timing = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -381,9 +396,23 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
     alloc(c->cg_out, (size_t)S * sizeof(CgShellOut));
     alloc(c->fail_shell, (size_t)S * sizeof(int));
     alloc(c->delta_shell, (size_t)S * sizeof(double));
-    alloc(c->alpha_shell, (size_t)S * sizeof(double));
+    alloc(c->alpha_shell, (size_t)2 * S * sizeof(double));
     alloc(c->flag_shell, (size_t)S * sizeof(int));
     alloc(c->write_shell, (size_t)S * sizeof(int));
+    for (DevBuf* b : {&c->dstep, &c->qstart, &c->b0, &c->guess}) alloc(*b, vecb);
+    c->h_hist.assign(S, 0);
+    alloc(c->rec_base, (size_t)S * sizeof(long long));
+    alloc(c->feat_part, (size_t)c->nblk * 12 * sizeof(double));
+    alloc(c->feat_scale, (size_t)S * 12 * sizeof(float));
+    {
+        std::vector<int> cnt((size_t)S * 4, 0);
+        for (int n = 0; n < N; ++n)
+            for (int w = 0; w < 12; ++w)
+                if ((c->h_freemask[n] >> w) & 1) cnt[4 * c->h_node_shell[n] + w / 3]++;
+        upload(c->cnt_kind, cnt, st);
+        sync(c);
+    }
+    HIPCHK(hipMemsetAsync(c->dstep.p, 0, c->dstep.n, st));
     HIPCHK(hipHostMalloc((void**)&c->h_e_shell, (size_t)S * 3 * sizeof(double), 0));
     HIPCHK(hipHostMalloc((void**)&c->h_red, (size_t)S * sizeof(double), 0));
     HIPCHK(hipHostMalloc((void**)&c->h_cg_out, (size_t)S * sizeof(CgShellOut), 0));
@@ -519,6 +548,31 @@ void cg_launch(shell_ctx* c, const double* b, const std::vector<int>& active, co
             throw StatusErr{SHELL_E_DEVICE, "CG grid barrier timed out"};
 }
 
+// ---------------------------------------------------- warm-start network
+void mlp_alloc(shell_ctx* c) {
+    if (c->mlp_theta.p) return;
+    alloc(c->mlp_theta, MLP_NPARAMS * sizeof(float));
+    alloc(c->mlp_w, (size_t)mlp_bf16_elems() * 2);
+    alloc(c->mlp_m, MLP_NPARAMS * sizeof(float));
+    alloc(c->mlp_v, MLP_NPARAMS * sizeof(float));
+    alloc(c->mlp_grad, MLP_NPARAMS * sizeof(float));
+    alloc(c->mlp_loss, sizeof(double));
+}
+
+void mlp_work(shell_ctx* c, int batch) {
+    if (c->mlp_work_batch >= batch) return;
+    alloc(c->mlp_work, mlp_train_work_bytes(batch));
+    alloc(c->mlp_idx, (size_t)batch * sizeof(long long));
+    c->mlp_work_batch = batch;
+}
+
+// Per-shell, per-kind feature scales of (q - qbar, b, dprev).
+void feat_scales(shell_ctx* c, const double* q, const double* b, const double* dprev) {
+    launch_feat_scale(c->stream, c->rb(), c->S, q, dptr<double>(c->qbar), b, dprev, dptr<uint16_t>(c->freemask),
+                      dptr<double>(c->feat_part), dptr<int>(c->cnt_kind), dptr<float>(c->feat_scale));
+    HIPCHK(hipGetLastError());
+}
+
 struct SolveResult {
     std::vector<int> iters, status, sweeps;   // status: 0 ok, 1 cap, 2 indefinite
     std::vector<double> relres;
@@ -528,8 +582,8 @@ struct SolveResult {
 // those shells only (other shells' entries of x_out are left as they are).
 // FP64 path: one CG.  Mixed path: FP32 CG sweeps on the FP64 residual,
 // x += dx, r = b - A x in FP64, until ||r|| <= rtol ||b||.
-SolveResult solve(shell_ctx* c, const double* b, double* x_out, const std::vector<int>& active_in, double rtol,
-                  int maxit) {
+SolveResult solve(shell_ctx* c, const double* b, double* x_out, const std::vector<int>& active_in,
+                  const std::vector<double>& rtol, int maxit) {
     const int S = c->S;
     hipStream_t st = c->stream;
     SolveResult R;
@@ -539,7 +593,7 @@ SolveResult solve(shell_ctx* c, const double* b, double* x_out, const std::vecto
     R.relres.assign(S, 0.0);
     double* x64 = dptr<double>(c->x64);
     if (!c->fp32) {
-        cg_launch(c, b, active_in, std::vector<double>(S, rtol), maxit);
+        cg_launch(c, b, active_in, rtol, maxit);
         for (int s = 0; s < S; ++s) {
             const CgShellOut& o = c->h_cg_out[s];
             R.iters[s] = o.iters;
@@ -573,7 +627,7 @@ SolveResult solve(shell_ctx* c, const double* b, double* x_out, const std::vecto
         // each sweep asks the FP32 CG for the reduction still needed (with a
         // margin), but not below what FP32 arithmetic resolves
         std::vector<double> inner(S);
-        for (int s = 0; s < S; ++s) inner[s] = std::max(0.5 * rtol / prev[s], 1e-6);
+        for (int s = 0; s < S; ++s) inner[s] = std::max(0.5 * rtol[s] / prev[s], 1e-6);
         cg_launch(c, r64, active, inner, maxit);
         for (int s = 0; s < S; ++s)
             if (active[s]) {
@@ -594,7 +648,7 @@ SolveResult solve(shell_ctx* c, const double* b, double* x_out, const std::vecto
             const double rel = std::sqrt(c->h_red[s] / bn2[s]);
             if (!active[s]) continue;
             R.relres[s] = rel;
-            if (rel <= rtol) {
+            if (rel <= rtol[s]) {
                 active[s] = 0;
             } else if (rel > 0.5 * prev[s] || R.iters[s] >= maxit) {
                 R.status[s] = 1;   // refinement stagnates
@@ -607,6 +661,155 @@ SolveResult solve(shell_ctx* c, const double* b, double* x_out, const std::vecto
     launch_copy_shell(st, c->N, x64, dptr<int>(c->node_shell), dptr<int>(c->flag_shell), x_out);
     HIPCHK(hipGetLastError());
     return R;
+}
+
+// Learned warm start of the Newton iteration.  Two directions from the
+// step's start q_s: d1 = the previous step's correction (extrapolation) and
+// d2 = the network's correction s_d y(features).  The start moves to
+// q_s + c1 d1 + c2 d2 with c the Galerkin solution of the quadratic model
+// of E in span{d1, d2}, whose Hessian is taken from gradient differences
+// (H d_j ~ grad E(q_s + d_j) - grad E(q_s), symmetrised); a direction
+// dependent on d1, or with non-positive curvature, is dropped.  The move is
+// taken if E satisfies the Armijo condition and ||grad E|| is at least
+// halved (Newton's convergence measure: a start that lowers E but not the
+// gradient only costs iterations); if the two-direction point fails, the
+// one-direction Galerkin point along d1 is tried.  A shell whose network
+// output is not finite keeps q_s, as does one without a previous
+// correction.  Updates q, g, E, gn of the shells that move.
+void newton_warm_start(shell_ctx* c, double ms, const std::vector<int>& active, std::vector<double>& E,
+                       std::vector<double>& Escale, std::vector<double>& gn, std::vector<shell_step_stats>& stats) {
+    const int S = c->S;
+    hipStream_t st = c->stream;
+    double* q = dptr<double>(c->q);
+    double* qt = dptr<double>(c->qt);
+    double* g = dptr<double>(c->g);
+    double* gt = dptr<double>(c->gt);
+    const double* d1 = dptr<double>(c->dstep);
+    double* d2 = dptr<double>(c->guess);
+    std::vector<int> cand(S, 0);
+    bool any = false;
+    for (int s = 0; s < S; ++s) {
+        cand[s] = active[s] && c->h_hist[s];
+        any |= cand[s] != 0;
+    }
+    if (!any) return;
+    h2d(c, c->flag_shell.p, cand.data(), S * sizeof(int));
+    launch_mlp_guess(st, c->N, dptr<float>(c->mlp_theta), c->mlp_w.p, dptr<int>(c->node_shell),
+                     dptr<int>(c->flag_shell), q, dptr<double>(c->qbar), dptr<double>(c->b0), d1,
+                     dptr<uint16_t>(c->freemask), dptr<float>(c->feat_scale), d2);
+    HIPCHK(hipGetLastError());
+    auto dots = [&](const double* x, const double* y) {
+        shell_dot(c, x, y, true);
+        sync(c);
+        return std::vector<double>(c->h_red, c->h_red + S);
+    };
+    std::vector<double> Et(S), Est(S), gtn(S);
+    // E, ||g|| and g at q + c1 d1 + c2 d2 (coefficients per shell, 0 = unchanged)
+    auto trial = [&](const std::vector<double>& coef) {
+        h2d(c, c->alpha_shell.p, coef.data(), 2 * S * sizeof(double));
+        launch_axpy2_shell(st, c->N, q, d1, d2, dptr<double>(c->alpha_shell), dptr<int>(c->node_shell), qt);
+        eval_energy_grad(c, qt, dptr<double>(c->qhat), ms, 1, true, gt, nullptr);
+        const std::vector<double> n2 = dots(gt, gt);
+        for (int s = 0; s < S; ++s) {
+            const double* e = c->h_e_shell + 3 * s;
+            Et[s] = e[0] + e[1] + e[2];
+            Est[s] = std::fabs(e[0]) + std::fabs(e[1]) + std::fabs(e[2]);
+            gtn[s] = std::sqrt(n2[s]);
+        }
+    };
+    const std::vector<double> a1 = dots(d1, g), a2 = dots(d2, g), n22 = dots(d2, d2);
+    for (int s = 0; s < S; ++s)   // non-finite network output: no warm start for that shell
+        if (cand[s] && !(std::isfinite(a2[s]) && std::isfinite(n22[s]))) cand[s] = 0;
+    // curvature probes along d1 and along d2
+    std::vector<double> coef(2 * S, 0.0);
+    for (int s = 0; s < S; ++s) coef[2 * s] = cand[s] ? 1.0 : 0.0;
+    trial(coef);
+    const std::vector<double> h11 = dots(d1, gt), h21 = dots(d2, gt);
+    for (int s = 0; s < S; ++s) coef[2 * s] = 0.0, coef[2 * s + 1] = (cand[s] && n22[s] > 0.0) ? 1.0 : 0.0;
+    trial(coef);
+    const std::vector<double> h12 = dots(d1, gt), h22 = dots(d2, gt);
+    for (int s = 0; s < S; ++s) {
+        coef[2 * s] = coef[2 * s + 1] = 0.0;
+        if (!cand[s]) continue;
+        const double H11 = h11[s] - a1[s];
+        const double H22 = n22[s] > 0.0 ? h22[s] - a2[s] : 0.0;
+        const double H12 = n22[s] > 0.0 ? 0.5 * ((h12[s] - a1[s]) + (h21[s] - a2[s])) : 0.0;
+        double c1 = 0.0, c2 = 0.0;
+        const double det = H11 * H22 - H12 * H12;
+        if (H11 > 0.0 && H22 > 0.0 && det > 1e-8 * H11 * H22) {
+            c1 = (-a1[s] * H22 + a2[s] * H12) / det;
+            c2 = (-a2[s] * H11 + a1[s] * H12) / det;
+        } else if (H11 > 0.0) {
+            c1 = -a1[s] / H11;
+        } else if (H22 > 0.0) {
+            c2 = -a2[s] / H22;
+        }
+        if (!std::isfinite(c1) || !std::isfinite(c2) || (c1 == 0.0 && c2 == 0.0)) {
+            cand[s] = 0;
+            continue;
+        }
+        coef[2 * s] = c1;
+        coef[2 * s + 1] = c2;
+    }
+    // try the Galerkin point; where it fails and used d2, retry along d1 alone
+    auto accept = [&](const std::vector<double>& cf, const std::vector<int>& which) {
+        std::vector<int> acc(S, 0);
+        for (int s = 0; s < S; ++s) {
+            if (!which[s]) continue;
+            const double slope = cf[2 * s] * a1[s] + cf[2 * s + 1] * a2[s];
+            acc[s] = std::isfinite(Et[s]) && std::isfinite(gtn[s]) && slope < 0.0 &&
+                     Et[s] <= E[s] + 1e-4 * slope && gtn[s] <= 0.5 * gn[s];
+        }
+        h2d(c, c->flag_shell.p, acc.data(), S * sizeof(int));
+        launch_copy_shell(st, c->N, qt, dptr<int>(c->node_shell), dptr<int>(c->flag_shell), q);
+        launch_copy_shell(st, c->N, gt, dptr<int>(c->node_shell), dptr<int>(c->flag_shell), g);
+        HIPCHK(hipGetLastError());
+        for (int s = 0; s < S; ++s)
+            if (acc[s]) {
+                E[s] = Et[s];
+                Escale[s] = Est[s];
+                gn[s] = gtn[s];
+                stats[s].warm_start_used = 1;
+            }
+        return acc;
+    };
+    trial(coef);
+    const std::vector<int> acc = accept(coef, cand);
+    std::vector<int> retry(S, 0);
+    bool anyr = false;
+    for (int s = 0; s < S; ++s) {
+        const double H11 = h11[s] - a1[s];
+        retry[s] = cand[s] && !acc[s] && coef[2 * s + 1] != 0.0 && H11 > 0.0;
+        coef[2 * s] = retry[s] ? -a1[s] / H11 : 0.0;
+        coef[2 * s + 1] = 0.0;
+        anyr |= retry[s] != 0;
+    }
+    if (!anyr) return;
+    trial(coef);
+    accept(coef, retry);
+}
+
+// Append K sampled (features, target) rows per flagged shell to the
+// recording buffers while they have room: features at the start of the
+// step (qstart, b0, dstep), target from the step's correction d.
+void record_samples(shell_ctx* c, const double* d, const std::vector<int>& flag) {
+    if (!c->rec_feat) return;
+    const int S = c->S;
+    std::vector<long long> base(S, -1);
+    bool any = false;
+    for (int s = 0; s < S; ++s)
+        if (flag[s] && c->rec_count + c->rec_K <= c->rec_cap) {
+            base[s] = c->rec_count;
+            c->rec_count += c->rec_K;
+            any = true;
+        }
+    if (!any) return;
+    h2d(c, c->rec_base.p, base.data(), S * sizeof(long long));
+    const unsigned long long seed = c->rec_seed + 0xD1B54A32D192ED03ull * (unsigned long long)(++c->rec_calls);
+    launch_mlp_record(c->stream, S, c->rec_K, seed, dptr<ShellParams>(c->shells_d), dptr<long long>(c->rec_base),
+                      dptr<double>(c->qstart), dptr<double>(c->qbar), dptr<double>(c->b0), dptr<double>(c->dstep), d,
+                      dptr<float>(c->feat_scale), c->rec_feat, c->rec_tgt);
+    HIPCHK(hipGetLastError());
 }
 
 }  // namespace
@@ -644,10 +847,6 @@ shell_status shell_create(const shell_desc* shells, int32_t n_shells, const shel
         (opts.warm_start != SHELL_WS_NONE && opts.warm_start != SHELL_WS_MLP) || opts.newton_maxit < 1 ||
         opts.pcg_maxit < 1 || !(opts.newton_rtol >= 0) || !(opts.pcg_rtol > 0)) {
         g_create_error = "invalid options";
-        return SHELL_E_INVAL;
-    }
-    if (opts.warm_start == SHELL_WS_MLP) {
-        g_create_error = "warm_start = SHELL_WS_MLP is not available in this build";
         return SHELL_E_INVAL;
     }
     shell_ctx* c = nullptr;
@@ -818,7 +1017,7 @@ shell_status shell_pcg_solve(shell_ctx* c, const double* b_dev, double* x_dev, d
             return SHELL_E_INDEFINITE;
         }
     std::vector<int> active(c->S, 1);
-    SolveResult R = solve(c, b_dev, x_dev, active, rtol, maxit);
+    SolveResult R = solve(c, b_dev, x_dev, active, std::vector<double>(c->S, rtol), maxit);
     sync(c);
     shell_status st = SHELL_OK;
     for (int s = 0; s < c->S; ++s) {
@@ -843,6 +1042,10 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
     }
     if (q_np1_dev == q_n_dev || v_np1_dev == v_n_dev || q_np1_dev == v_n_dev) {
         c->err = "outputs may not alias inputs";
+        return SHELL_E_INVAL;
+    }
+    if (c->opts.warm_start == SHELL_WS_MLP && !c->mlp_ready) {
+        c->err = "warm_start = SHELL_WS_MLP needs shell_mlp_set_params first";
         return SHELL_E_INVAL;
     }
     API_TRY
@@ -880,6 +1083,15 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
             active[s] = 0;
         }
     }
+    const bool learned = c->opts.warm_start == SHELL_WS_MLP;
+    if (learned || c->rec_feat) {   // features of the step's start
+        HIPCHK(hipMemcpyAsync(c->qstart.p, q, (size_t)N12 * sizeof(double), hipMemcpyDeviceToDevice, st));
+        h2d(c, c->cg_active.p, active.data(), S * sizeof(int));
+        launch_neg_masked(st, c->N, g, dptr<uint16_t>(c->freemask), dptr<int>(c->node_shell),
+                          dptr<int>(c->cg_active), dptr<double>(c->b0));
+        feat_scales(c, q, dptr<double>(c->b0), dptr<double>(c->dstep));
+    }
+    if (learned) newton_warm_start(c, ms, active, E, Escale, gn, stats);
     const double eps = 2.220446049250313e-16;
     bool have_prev = false;
     double t_asm = 0, t_cg = 0;
@@ -944,7 +1156,7 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
             h2d(c, c->cg_active.p, todo.data(), S * sizeof(int));
             launch_neg_masked(st, c->N, g, dptr<uint16_t>(c->freemask), dptr<int>(c->node_shell),
                               dptr<int>(c->cg_active), rhs);
-            SolveResult R = solve(c, rhs, d, todo, c->opts.pcg_rtol, c->opts.pcg_maxit);
+            SolveResult R = solve(c, rhs, d, todo, std::vector<double>(S, c->opts.pcg_rtol), c->opts.pcg_maxit);
             bool again = false;
             for (int s = 0; s < S; ++s) {
                 if (!todo[s]) continue;
@@ -1062,6 +1274,27 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
             }
         }
     }
+    if (learned || c->rec_feat) {
+        // this step's correction q_{n+1} - q_start of the converged shells:
+        // a training sample (for shells that had a previous correction) and
+        // the next step's previous correction
+        std::vector<int> ok(S), rec(S);
+        for (int s = 0; s < S; ++s) {
+            ok[s] = status[s] == SHELL_OK;
+            rec[s] = ok[s] && c->h_hist[s];
+        }
+        h2d(c, c->flag_shell.p, ok.data(), S * sizeof(int));
+        double* delta = dptr<double>(c->guess);
+        launch_masked_diff(st, c->N, q, dptr<double>(c->qstart), dptr<uint16_t>(c->freemask),
+                           dptr<int>(c->node_shell), dptr<int>(c->flag_shell), delta);
+        HIPCHK(hipGetLastError());
+        record_samples(c, delta, rec);
+        h2d(c, c->flag_shell.p, ok.data(), S * sizeof(int));
+        launch_copy_shell(st, c->N, delta, dptr<int>(c->node_shell), dptr<int>(c->flag_shell),
+                          dptr<double>(c->dstep));
+        HIPCHK(hipGetLastError());
+        for (int s = 0; s < S; ++s) c->h_hist[s] = (char)ok[s];
+    }
     HIPCHK(hipMemcpyAsync(q_np1_dev, q, (size_t)N12 * sizeof(double), hipMemcpyDeviceToDevice, st));
     launch_velocity(st, N12, q, q_n_dev, dt, v_np1_dev);
     HIPCHK(hipGetLastError());
@@ -1098,6 +1331,165 @@ shell_status shell_timing_enable(shell_ctx* c, int32_t enable) {
 shell_status shell_timing_get(const shell_ctx* c, shell_timing* out) {
     if (!c || !out) return SHELL_E_INVAL;
     *out = c->tm;
+    return SHELL_OK;
+}
+
+// ------------------------------------------------------- warm-start network
+static_assert(SHELL_MLP_PARAMS == MLP_NPARAMS && SHELL_MLP_IN == MLP_IN && SHELL_MLP_OUT == MLP_OUT &&
+                  SHELL_MLP_HIDDEN == MLP_H,
+              "network sizes");
+
+shell_status shell_mlp_set_params(shell_ctx* c, const float* theta_host) {
+    if (!c) return SHELL_E_INVAL;
+    if (!theta_host) {
+        c->err = "theta_host is NULL";
+        return SHELL_E_INVAL;
+    }
+    for (int i = 0; i < MLP_NPARAMS; ++i)
+        if (!std::isfinite(theta_host[i])) {
+            c->err = "non-finite network parameter " + std::to_string(i);
+            return SHELL_E_NONFINITE;
+        }
+    API_TRY
+    HIPCHK(hipSetDevice(c->opts.device));
+    mlp_alloc(c);
+    h2d(c, c->mlp_theta.p, theta_host, MLP_NPARAMS * sizeof(float));
+    HIPCHK(hipMemsetAsync(c->mlp_m.p, 0, c->mlp_m.n, c->stream));
+    HIPCHK(hipMemsetAsync(c->mlp_v.p, 0, c->mlp_v.n, c->stream));
+    launch_mlp_pack(c->stream, dptr<float>(c->mlp_theta), c->mlp_w.p);
+    HIPCHK(hipGetLastError());
+    sync(c);
+    c->adam_step = 0;
+    c->mlp_ready = true;
+    return SHELL_OK;
+    API_CATCH
+}
+
+shell_status shell_mlp_get_params(shell_ctx* c, float* theta_host) {
+    if (!c) return SHELL_E_INVAL;
+    if (!theta_host || !c->mlp_ready) {
+        c->err = "theta_host is NULL or no parameters are loaded";
+        return SHELL_E_INVAL;
+    }
+    API_TRY
+    HIPCHK(hipSetDevice(c->opts.device));
+    HIPCHK(hipMemcpyAsync(theta_host, c->mlp_theta.p, MLP_NPARAMS * sizeof(float), hipMemcpyDeviceToHost,
+                          c->stream));
+    sync(c);
+    return SHELL_OK;
+    API_CATCH
+}
+
+shell_status shell_mlp_forward(shell_ctx* c, const float* feat_dev, float* out_dev, int64_t n) {
+    if (!c) return SHELL_E_INVAL;
+    if (!c->mlp_ready || n < 0 || (n > 0 && (!feat_dev || !out_dev))) {
+        c->err = "needs loaded parameters, n >= 0 and device arrays";
+        return SHELL_E_INVAL;
+    }
+    API_TRY
+    HIPCHK(hipSetDevice(c->opts.device));
+    if (n > 0) launch_mlp_forward(c->stream, dptr<float>(c->mlp_theta), c->mlp_w.p, feat_dev, out_dev, n);
+    HIPCHK(hipGetLastError());
+    sync(c);
+    return SHELL_OK;
+    API_CATCH
+}
+
+shell_status shell_mlp_loss_grad(shell_ctx* c, const float* feat_dev, const float* tgt_dev, int64_t n_samples,
+                                 const int64_t* idx_dev, int32_t batch, double* loss_host, float* grad_host) {
+    if (!c) return SHELL_E_INVAL;
+    if (!c->mlp_ready || !feat_dev || !tgt_dev || !idx_dev || n_samples < 1 || batch < 32 || batch % 32) {
+        c->err = "needs loaded parameters, device arrays, n_samples >= 1 and a batch that is a positive multiple "
+                 "of 32";
+        return SHELL_E_INVAL;
+    }
+    API_TRY
+    HIPCHK(hipSetDevice(c->opts.device));
+    hipStream_t st = c->stream;
+    {   // the kernels trust the indices: check them here
+        std::vector<int64_t> h(batch);
+        HIPCHK(hipMemcpyAsync(h.data(), idx_dev, (size_t)batch * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        sync(c);
+        for (int64_t v : h)
+            if (v < 0 || v >= n_samples) throw InvalErr{"sample index out of range"};
+    }
+    mlp_work(c, batch);
+    HIPCHK(hipMemsetAsync(c->mlp_grad.p, 0, c->mlp_grad.n, st));
+    HIPCHK(hipMemsetAsync(c->mlp_loss.p, 0, sizeof(double), st));
+    launch_mlp_grad(st, dptr<float>(c->mlp_theta), c->mlp_w.p, feat_dev, tgt_dev, (const long long*)idx_dev, batch,
+                    c->mlp_work.p, dptr<float>(c->mlp_grad), dptr<double>(c->mlp_loss));
+    HIPCHK(hipGetLastError());
+    if (loss_host) HIPCHK(hipMemcpyAsync(loss_host, c->mlp_loss.p, sizeof(double), hipMemcpyDeviceToHost, st));
+    if (grad_host)
+        HIPCHK(hipMemcpyAsync(grad_host, c->mlp_grad.p, MLP_NPARAMS * sizeof(float), hipMemcpyDeviceToHost, st));
+    sync(c);
+    return SHELL_OK;
+    API_CATCH
+}
+
+shell_status shell_mlp_train(shell_ctx* c, const float* feat_dev, const float* tgt_dev, int64_t n_samples,
+                             int32_t batch, int32_t steps, float lr, uint64_t seed, double* loss_host) {
+    if (!c) return SHELL_E_INVAL;
+    if (!c->mlp_ready || !feat_dev || !tgt_dev || n_samples < 1 || batch < 32 || batch % 32 || steps < 0 ||
+        !(lr > 0.0f) || !std::isfinite(lr)) {
+        c->err = "needs loaded parameters, device arrays, n_samples >= 1, batch a positive multiple of 32, "
+                 "steps >= 0 and lr > 0";
+        return SHELL_E_INVAL;
+    }
+    API_TRY
+    HIPCHK(hipSetDevice(c->opts.device));
+    hipStream_t st = c->stream;
+    mlp_work(c, batch);
+    if (c->mlp_loss_n < std::max(steps, 1)) {
+        alloc(c->mlp_loss, (size_t)std::max(steps, 1) * sizeof(double));
+        c->mlp_loss_n = std::max(steps, 1);
+    }
+    HIPCHK(hipMemsetAsync(c->mlp_loss.p, 0, (size_t)std::max(steps, 1) * sizeof(double), st));
+    double* loss = dptr<double>(c->mlp_loss);
+    for (int i = 0; i < steps; ++i) {
+        launch_sample_idx(st, n_samples, batch, seed + 0x9E3779B97F4A7C15ull * (unsigned long long)(i + 1) * 131ull,
+                          dptr<long long>(c->mlp_idx));
+        HIPCHK(hipMemsetAsync(c->mlp_grad.p, 0, c->mlp_grad.n, st));
+        launch_mlp_grad(st, dptr<float>(c->mlp_theta), c->mlp_w.p, feat_dev, tgt_dev, dptr<long long>(c->mlp_idx),
+                        batch, c->mlp_work.p, dptr<float>(c->mlp_grad), loss + i);
+        launch_mlp_adam(st, dptr<float>(c->mlp_theta), dptr<float>(c->mlp_grad), dptr<float>(c->mlp_m),
+                        dptr<float>(c->mlp_v), MLP_NPARAMS, lr, ++c->adam_step);
+        launch_mlp_pack(st, dptr<float>(c->mlp_theta), c->mlp_w.p);
+        HIPCHK(hipGetLastError());
+    }
+    if (loss_host && steps > 0)
+        HIPCHK(hipMemcpyAsync(loss_host, loss, (size_t)steps * sizeof(double), hipMemcpyDeviceToHost, st));
+    sync(c);
+    return SHELL_OK;
+    API_CATCH
+}
+
+shell_status shell_mlp_record(shell_ctx* c, float* feat_dev, float* tgt_dev, int64_t capacity, int32_t per_shell,
+                              uint64_t seed) {
+    if (!c) return SHELL_E_INVAL;
+    c->rec_count = 0;
+    c->rec_calls = 0;
+    if (!feat_dev) {
+        c->rec_feat = nullptr;
+        c->rec_tgt = nullptr;
+        c->rec_cap = 0;
+        return SHELL_OK;
+    }
+    if (!tgt_dev || capacity < 0 || per_shell < 1) {
+        c->err = "recording needs tgt_dev, capacity >= 0 and per_shell >= 1";
+        return SHELL_E_INVAL;
+    }
+    c->rec_feat = feat_dev;
+    c->rec_tgt = tgt_dev;
+    c->rec_cap = capacity;
+    c->rec_K = per_shell;
+    c->rec_seed = seed;
+    return SHELL_OK;
+}
+
+shell_status shell_mlp_recorded(const shell_ctx* c, int64_t* count) {
+    if (!c || !count) return SHELL_E_INVAL;
+    *count = c->rec_count;
     return SHELL_OK;
 }
 

@@ -559,6 +559,12 @@ __global__ void k_copy_shell(int n, const double* __restrict__ src, const int* _
     if (t < n && flag_shell[node_shell[t / 12]]) dst[t] = src[t];
 }
 
+__global__ void k_add_shell(int n, const double* __restrict__ src, const int* __restrict__ node_shell,
+                            const int* __restrict__ flag_shell, double* __restrict__ dst) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n && flag_shell[node_shell[t / 12]]) dst[t] += src[t];
+}
+
 template <class TV> __global__ void k_add_to(int n, const TV* __restrict__ dx, double* __restrict__ x) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) x[t] += (double)dx[t];
@@ -670,6 +676,11 @@ void launch_copy_shell(hipStream_t st, int nnodes, const double* src, const int*
                        double* dst) {
     const int n = nnodes * 12;
     hipLaunchKernelGGL(k_copy_shell, grid1(n), dim3(256), 0, st, n, src, node_shell, flag_shell, dst);
+}
+void launch_add_shell(hipStream_t st, int nnodes, const double* src, const int* node_shell, const int* flag_shell,
+                      double* dst) {
+    const int n = nnodes * 12;
+    hipLaunchKernelGGL(k_add_shell, grid1(n), dim3(256), 0, st, n, src, node_shell, flag_shell, dst);
 }
 template <class TV> void launch_add_to(hipStream_t st, int n, const TV* dx, double* x) {
     hipLaunchKernelGGL(k_add_to<TV>, grid1(n), dim3(256), 0, st, n, dx, x);

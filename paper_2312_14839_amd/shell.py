@@ -120,6 +120,21 @@ def _load():
     lib.shell_timing_enable.restype = C.c_int32
     lib.shell_timing_get.argtypes = [vp, P(shell_timing)]
     lib.shell_timing_get.restype = C.c_int32
+    lib.shell_mlp_set_params.argtypes = [vp, P(C.c_float)]
+    lib.shell_mlp_set_params.restype = C.c_int32
+    lib.shell_mlp_get_params.argtypes = [vp, P(C.c_float)]
+    lib.shell_mlp_get_params.restype = C.c_int32
+    lib.shell_mlp_forward.argtypes = [vp, vp, vp, C.c_int64]
+    lib.shell_mlp_forward.restype = C.c_int32
+    lib.shell_mlp_loss_grad.argtypes = [vp, vp, vp, C.c_int64, vp, C.c_int32, P(C.c_double), P(C.c_float)]
+    lib.shell_mlp_loss_grad.restype = C.c_int32
+    lib.shell_mlp_train.argtypes = [vp, vp, vp, C.c_int64, C.c_int32, C.c_int32, C.c_float, C.c_uint64,
+                                    P(C.c_double)]
+    lib.shell_mlp_train.restype = C.c_int32
+    lib.shell_mlp_record.argtypes = [vp, vp, vp, C.c_int64, C.c_int32, C.c_uint64]
+    lib.shell_mlp_record.restype = C.c_int32
+    lib.shell_mlp_recorded.argtypes = [vp, P(C.c_int64)]
+    lib.shell_mlp_recorded.restype = C.c_int32
     return lib
 
 
@@ -127,7 +142,12 @@ lib = _load()
 
 EXPORTED = ["shell_default_opts", "shell_create", "shell_destroy", "shell_last_error", "shell_sizes",
             "shell_energy_grad_hess", "shell_assemble", "shell_get_bsr", "shell_spmv", "shell_pcg_solve",
-            "shell_newton_step", "shell_timing_enable", "shell_timing_get"]
+            "shell_newton_step", "shell_timing_enable", "shell_timing_get", "shell_mlp_set_params",
+            "shell_mlp_get_params", "shell_mlp_forward", "shell_mlp_loss_grad", "shell_mlp_train",
+            "shell_mlp_record", "shell_mlp_recorded"]
+
+MLP_IN, MLP_HIDDEN, MLP_OUT = 36, 128, 12
+MLP_PARAMS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_OUT + MLP_OUT
 
 
 def _ptr(t):
@@ -151,7 +171,7 @@ class ShellContext:
 
     def __init__(self, cases: Sequence, precision=SHELL_FP64, hessian=SHELL_HESS_EXACT,
                  newton_rtol=1e-10, pcg_rtol=1e-10, newton_maxit=50, pcg_maxit=100000,
-                 device=0, stream=None):
+                 device=0, stream=None, warm_start=SHELL_WS_NONE):
         self._keep = []
         descs = (shell_desc * len(cases))()
         for k, cs in enumerate(cases):
@@ -168,7 +188,7 @@ class ShellContext:
             for i in range(3):
                 d.gravity[i] = float(cs.gravity[i])
         o = default_opts()
-        o.precision, o.hessian = int(precision), int(hessian)
+        o.precision, o.hessian, o.warm_start = int(precision), int(hessian), int(warm_start)
         o.newton_rtol, o.pcg_rtol = float(newton_rtol), float(pcg_rtol)
         o.newton_maxit, o.pcg_maxit = int(newton_maxit), int(pcg_maxit)
         o.device = int(device)
@@ -244,6 +264,42 @@ class ShellContext:
             self._check(rc)
         return rc, [s.as_dict() for s in st]
 
+
+    # ---- warm-start network
+    def mlp_set_params(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        assert th.size == MLP_PARAMS
+        self._check(lib.shell_mlp_set_params(self.h, th.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def mlp_get_params(self):
+        th = np.zeros(MLP_PARAMS, np.float32)
+        self._check(lib.shell_mlp_get_params(self.h, th.ctypes.data_as(C.POINTER(C.c_float))))
+        return th
+
+    def mlp_forward(self, feat, out):
+        self._check(lib.shell_mlp_forward(self.h, _ptr(feat), _ptr(out), int(feat.shape[0])))
+
+    def mlp_loss_grad(self, feat, tgt, idx):
+        loss = C.c_double()
+        g = np.zeros(MLP_PARAMS, np.float32)
+        self._check(lib.shell_mlp_loss_grad(self.h, _ptr(feat), _ptr(tgt), int(feat.shape[0]), _ptr(idx),
+                                            int(idx.shape[0]), C.byref(loss),
+                                            g.ctypes.data_as(C.POINTER(C.c_float))))
+        return loss.value, g
+
+    def mlp_train(self, feat, tgt, n_samples, batch, steps, lr, seed=0):
+        losses = np.zeros(max(int(steps), 1))
+        self._check(lib.shell_mlp_train(self.h, _ptr(feat), _ptr(tgt), int(n_samples), int(batch), int(steps),
+                                        float(lr), int(seed), losses.ctypes.data_as(C.POINTER(C.c_double))))
+        return losses[:int(steps)]
+
+    def mlp_record(self, feat, tgt, capacity, per_shell, seed=0):
+        self._check(lib.shell_mlp_record(self.h, _ptr(feat), _ptr(tgt), int(capacity), int(per_shell), int(seed)))
+
+    def mlp_recorded(self):
+        n = C.c_int64()
+        self._check(lib.shell_mlp_recorded(self.h, C.byref(n)))
+        return n.value
 
     def timing_enable(self, on=True):
         self._check(lib.shell_timing_enable(self.h, int(on)))

@@ -220,6 +220,46 @@ def case_batch(count: int = 256, seed: int = 3, nmin: int = 8, nmax: int = 64, d
     return out
 
 
+def case_compression(n: int = 64, seed: int = 5, pct_per_100: float = 1.0, dt: float = 2e-3,
+                     sigma: float = 1e-4) -> Case:
+    """n x n sheet with edge xi1 = 0 clamped and edge xi1 = 1 clamped and
+    moved inward along x by pct_per_100 percent of the side every 100 steps;
+    no gravity; N(0, sigma) out-of-plane perturbation of free nodes (the
+    imperfection that lets the sheet buckle)."""
+    rng = np.random.default_rng(seed)
+    ref = flat_sheet_ref(n, n)
+    fixed = clamp_edges(n, n, ("x0", "x1"))
+    q0 = ref.copy()
+    free = ~fixed.any(axis=1)
+    q0[free, 2] += rng.normal(0.0, sigma, size=int(free.sum()))
+    cols = n + 1
+    moving = np.array([j * cols + n for j in range(n + 1)])
+    speed = pct_per_100 / 100.0 / (100.0 * dt)   # m/s for the 1 m side
+
+    def presc(t: float) -> np.ndarray:
+        out = ref.copy()
+        out[moving, 0] -= speed * t
+        return out
+
+    m = _material()
+    return Case(f"compress{n}x{n}", n, n, 0, 1.0 / n, 1.0 / n, m["young"], m["poisson"], m["thickness"],
+                m["density"], (0.0, 0.0, 0.0), ref, fixed, q0, np.zeros_like(q0), dt, presc)
+
+
+def case_random_load(n: int, seed: int, dt: float = 2e-3) -> Case:
+    """The load mix of the learned warm start's evaluation: with probability
+    1/2 a twist at omega ~ U[0.5, 2] rad/s about a random interior node,
+    else a compression at U[0.5, 2] percent per 100 steps."""
+    rng = np.random.default_rng(seed)
+    if rng.random() < 0.5:
+        ci, cj = (int(v) for v in rng.integers(1, n, size=2))
+        c = case_twist(n, seed=seed + 1, omega=float(rng.uniform(0.5, 2.0)), dt=dt, centre=(ci, cj))
+    else:
+        c = case_compression(n, seed=seed + 1, pct_per_100=float(rng.uniform(0.5, 2.0)), dt=dt)
+    c.name = f"{c.name}_s{seed}"
+    return c
+
+
 def random_state(case: Case, seed: int, pos_sigma: float = 1e-3, der_sigma: float = 1e-2) -> np.ndarray:
     """A generic deformed state: reference plus Gaussian noise on every DOF
     (positions pos_sigma, derivative DOFs der_sigma).  For kernel parity."""

@@ -1,0 +1,42 @@
+"""Pins of the CPU oracle of the warm-start MLP: backward pass against central
+finite differences of the FP64 loss, bfloat16 rounding against its
+definition, and a step of Adam against its closed form on a quadratic.
+CPU only."""
+import numpy as np
+
+from oracle import mlp_oracle as M
+
+
+def test_parameter_count():
+    assert M.N_PARAMS == 36 * 128 + 128 + 128 * 128 + 128 + 128 * 12 + 12
+
+
+def test_backward_matches_central_differences():
+    rng = np.random.default_rng(0)
+    theta = M.init_params(1)
+    theta += 0.05 * rng.normal(size=theta.shape)      # non-zero last layer
+    x = rng.normal(size=(7, 36))
+    t = rng.normal(size=(7, 12))
+    loss, g = M.loss_and_grad(theta, x, t)
+    idx = rng.choice(theta.size, 60, replace=False)
+    for i in idx:
+        e = np.zeros_like(theta)
+        e[i] = 1e-6
+        fd = (M.loss_and_grad(theta + e, x, t)[0] - M.loss_and_grad(theta - e, x, t)[0]) / 2e-6
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])), (i, fd, g[i])
+
+
+def test_bf16_rounding():
+    vals = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 2 ** -7, 1.0 + 3 * 2 ** -8, -3.1415926, 1e-3, 65504.0])
+    r = M.bf16_round(vals)
+    # 8 significant bits: 1 + 2^-8 is a tie -> even (1.0); 1 + 3*2^-8 -> 1 + 2^-6
+    assert r[0] == 1.0 and r[1] == 1.0 and r[2] == 1.0 + 2 ** -7 and r[3] == 1.0 + 2 ** -6
+    assert abs(r[4] - vals[4]) <= 2 ** -8 * abs(vals[4])
+    assert np.all(np.abs(r - vals) <= 2 ** -8 * np.abs(vals))
+
+
+def test_adam_first_step_is_lr_sign():
+    theta = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -4.0, 1e-3])
+    th, m, v = M.adam_step(theta, g, np.zeros(3), np.zeros(3), 1, 0.01)
+    np.testing.assert_allclose(th, theta - 0.01 * np.sign(g) * np.abs(g) / (np.abs(g) + 1e-8), rtol=1e-12)
