@@ -84,6 +84,10 @@ typedef struct {
     double pcg_rtol;             /* CG stops at ||b - A x|| <= pcg_rtol ||b|| (FP64 residual) */
     int32_t device;              /* HIP device ordinal */
     void *stream;                /* hipStream_t, NULL = the default stream */
+    int32_t graphs;              /* 1: the fixed launch sequences of a Newton iteration (assembly and
+                                    factorisation, CG, line-search trial, rounding floor) run as HIP
+                                    graphs captured once per context and time-step size; 0: direct
+                                    launches.  Off while event timing is on. */
 } shell_opts;
 
 /* Per-shell statistics of one shell_newton_step. */
@@ -99,7 +103,8 @@ typedef struct {
 } shell_step_stats;
 
 /* Default options: FP64, exact Hessian, no warm start, newton_rtol = pcg_rtol
- * = 1e-10, 50 Newton and 100000 CG iterations, device 0, default stream. */
+ * = 1e-10, 50 Newton and 100000 CG iterations, device 0, default stream,
+ * graphs on. */
 void shell_default_opts(shell_opts *o);
 
 /* Create a context for n_shells shells (batching: one context holds all of
@@ -191,6 +196,23 @@ typedef struct {
 shell_status shell_timing_enable(shell_ctx *c, int32_t enable);
 /* Copy the counters accumulated since the last shell_timing_enable. */
 shell_status shell_timing_get(const shell_ctx *c, shell_timing *out);
+
+/* CG layout autotuner.  The persistent CG kernel covers each shell's node
+ * rows with contiguous row blocks; the tunable layout is the threads per
+ * block (256 or 1024) and the rows per block (1, 2 or 4 times the fewest
+ * that keep every block resident at once).  shell_autotune times cg_iters
+ * CG iterations of every candidate on K(qbar) + M (overwriting the
+ * context's matrix) and keeps the fastest.  Results are cached for the
+ * process by (device, nodes, shells, block non-zeros, precision); a cached
+ * layout is applied without timing the candidates (candidates = 0,
+ * from_cache = 1).  Times are wall-clock microseconds per CG iteration. */
+typedef struct {
+    int32_t threads, rows_per_block, blocks;   /* chosen layout */
+    int32_t default_threads, default_rows_per_block;   /* layout before the call */
+    int32_t candidates, from_cache;
+    double us_per_iter, us_per_iter_default;
+} shell_tune_result;
+shell_status shell_autotune(shell_ctx *c, int32_t cg_iters, shell_tune_result *out);
 
 /* ------------------------------------------------------------------
  * Learned warm start of the Newton iteration.  This is an extension: the

@@ -80,6 +80,8 @@ void launch_copy_shell(hipStream_t st, int nnodes, const double* src, const int*
 template <class TV>
 void launch_add_to(hipStream_t st, int n, const TV* dx, double* x);
 void launch_cast_to_float(hipStream_t st, int n, const double* x, float* y);
+// zero `bytes` (a multiple of 4, 16-byte aligned start) with a kernel
+void launch_zero(hipStream_t st, void* p, size_t bytes);
 void launch_add_shell(hipStream_t st, int nnodes, const double* src, const int* node_shell, const int* flag_shell,
                       double* dst);
 

@@ -5,6 +5,9 @@
 
 #include <algorithm>
 #include <chrono>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -50,6 +53,7 @@ struct shell_ctx {
     std::vector<int> colour_off;   // [ncolour + 1] into the concatenated colour lists
     int nblk = 0;                  // CG row blocks
     int cg_threads = 256;          // threads per CG block
+    int cg_rows_target = 0;        // node rows per CG block (before the even split of a shell)
     std::vector<int> h_shell_blk0, h_shell_nblk;
     // device data
     DevBuf shells_d, phi, qbar, freemask, node_shell, patch_nodes, patch_shell, patch_slots, colour_list, inc_ptr,
@@ -65,6 +69,8 @@ struct shell_ctx {
     double* h_red = nullptr;       // [S]
     CgShellOut* h_cg_out = nullptr;
     int* h_fail = nullptr;
+    char* h_stage = nullptr;       // staging of control uploads
+    size_t stage_cap = 0, stage_off = 0;
     // warm-start network: FP32 master weights, bf16 operand copies, Adam state
     bool mlp_ready = false;
     int adam_step = 0;
@@ -80,6 +86,21 @@ struct shell_ctx {
     long long rec_cap = 0, rec_count = 0;
     int rec_K = 0;
     unsigned long long rec_seed = 0;
+    // HIP graphs of the Newton iteration's fixed launch sequences, captured
+    // on a private stream and replayed on the context's stream
+    struct Seg {
+        hipGraphExec_t exec = nullptr;
+        double key = 0.0;
+    };
+    bool graphs = true;
+    hipStream_t cap_stream = nullptr;
+    Seg g_asm, g_trial, g_floor, g_cg;
+    void graphs_reset() {
+        for (Seg* g : {&g_asm, &g_trial, &g_floor, &g_cg}) {
+            if (g->exec) (void)hipGraphExecDestroy(g->exec);
+            g->exec = nullptr;
+        }
+    }
     // event timing
     bool timing = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -91,12 +112,15 @@ struct shell_ctx {
                          dptr<int>(shell_nblk)};
     }
     ~shell_ctx() {
+        graphs_reset();
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
         if (h_e_shell) (void)hipHostFree(h_e_shell);
         if (h_red) (void)hipHostFree(h_red);
         if (h_cg_out) (void)hipHostFree(h_cg_out);
         if (h_fail) (void)hipHostFree(h_fail);
+        if (h_stage) (void)hipHostFree(h_stage);
     }
 };
 
@@ -137,13 +161,27 @@ template <class T> void upload(DevBuf& b, const std::vector<T>& v, hipStream_t s
     if (!v.empty()) HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
 }
 
-void sync(shell_ctx* c) { HIPCHK(hipStreamSynchronize(c->stream)); }
-
-// Small host-to-device copy of control data, complete on return (the host
-// vector may go out of scope right after).
-void h2d(shell_ctx* c, void* dst, const void* src, size_t bytes) {
-    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+void sync(shell_ctx* c) {
     HIPCHK(hipStreamSynchronize(c->stream));
+    c->stage_off = 0;
+}
+
+// Small host-to-device copy of control data, stream-ordered.  The bytes go
+// through the pinned staging area first (so the caller's host array may go
+// out of scope at once); the area is reused only after the stream has been
+// synchronised, which is forced here when it is full.
+void h2d(shell_ctx* c, void* dst, const void* src, size_t bytes) {
+    const size_t need = (bytes + 15) & ~(size_t)15;
+    if (need > c->stage_cap) {   // larger than the staging area: plain synchronous copy
+        HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+        sync(c);
+        return;
+    }
+    if (c->stage_off + need > c->stage_cap) sync(c);
+    char* h = c->h_stage + c->stage_off;
+    std::memcpy(h, src, bytes);
+    c->stage_off += need;
+    HIPCHK(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, c->stream));
 }
 
 double now_ms() {
@@ -168,6 +206,42 @@ struct GroupTimer {
     }
 };
 
+// Run `body`, which enqueues work on c->stream only (no synchronisation,
+// no memset), directly or as a HIP graph captured once per key and then
+// replayed.  Graphs are off while event timing is on.
+template <class F> void run_graph(shell_ctx* c, shell_ctx::Seg& seg, double key, F&& body) {
+    if (!c->graphs || c->timing) {
+        body();
+        return;
+    }
+    if (!seg.exec || seg.key != key) {
+        if (seg.exec) {
+            (void)hipGraphExecDestroy(seg.exec);
+            seg.exec = nullptr;
+        }
+        if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        hipStream_t user = c->stream;
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        c->stream = c->cap_stream;
+        try {
+            body();
+        } catch (...) {
+            c->stream = user;
+            (void)hipStreamEndCapture(c->cap_stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        c->stream = user;
+        HIPCHK(hipStreamEndCapture(c->cap_stream, &g));
+        const hipError_t e = hipGraphInstantiate(&seg.exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPCHK(e);
+        seg.key = key;
+    }
+    HIPCHK(hipGraphLaunch(seg.exec, c->stream));
+}
+
 // ----------------------------------------------------------- layout
 int node_cols(const shell_desc& d) { return d.periodic1 ? d.n1 : d.n1 + 1; }
 int node_count(const shell_desc& d) { return node_cols(d) * (d.n2 + 1); }
@@ -188,9 +262,64 @@ void validate(const shell_desc& d, int s) {
         if (!std::isfinite(d.ref_host[i])) bad("reference coordinates not finite");
 }
 
+// CG row blocks for `nt` threads per block and at least `spread` x the
+// fewest rows per block that fit all blocks on the device at once; uploads
+// the layout and sizes the per-block buffers.  False if the shells do not
+// fit (more shells than co-resident blocks).
+bool set_row_blocks(shell_ctx* c, int nt, int spread) {
+    const int S = c->S, N = c->N;
+    const int cap = cg_max_blocks(c->opts.device, c->fp32, nt);
+    if (cap <= 0) throw StatusErr{SHELL_E_DEVICE, "cannot query CG kernel occupancy"};
+    if (S > cap) return false;
+    const int pass = cg_rows_per_pass(c->fp32, nt);   // node rows per block pass
+    int target = std::max(pass, (N + cap - 1) / cap);
+    target = ((target + pass - 1) / pass) * pass;
+    int used = 0;
+    for (;; target += pass) {   // grow the rows per block until every block fits on the device at once
+        used = 0;
+        for (int s = 0; s < S; ++s)
+            used += std::max(1, (c->shells[s].node_end - c->shells[s].node_begin + target - 1) / target);
+        if (used <= cap) break;
+    }
+    target *= std::max(1, spread);
+    std::vector<int> bshell, brow0, brow1;
+    c->h_shell_blk0.assign(S, 0);
+    c->h_shell_nblk.assign(S, 0);
+    used = 0;
+    for (int s = 0; s < S; ++s) {
+        const int r0 = c->shells[s].node_begin, r1 = c->shells[s].node_end;
+        int nb = std::max(1, (r1 - r0 + target - 1) / target);
+        c->h_shell_blk0[s] = used;
+        c->h_shell_nblk[s] = nb;
+        for (int k = 0; k < nb; ++k) {
+            bshell.push_back(s);
+            brow0.push_back(r0 + (int)((long long)(r1 - r0) * k / nb));
+            brow1.push_back(r0 + (int)((long long)(r1 - r0) * (k + 1) / nb));
+        }
+        used += nb;
+    }
+    hipStream_t st = c->stream;
+    c->nblk = used;
+    c->cg_threads = nt;
+    c->cg_rows_target = target;
+    upload(c->blk_shell, bshell, st);
+    upload(c->blk_row0, brow0, st);
+    upload(c->blk_row1, brow1, st);
+    upload(c->shell_blk0, c->h_shell_blk0, st);
+    upload(c->shell_nblk, c->h_shell_nblk, st);
+    alloc(c->red_part, (size_t)c->nblk * sizeof(double));
+    alloc(c->cg_partial, (size_t)c->nblk * 4 * sizeof(double));
+    alloc(c->feat_part, (size_t)c->nblk * 12 * sizeof(double));
+    sync(c);
+    c->graphs_reset();
+    return true;
+}
+
 void build(shell_ctx* c, const shell_desc* ds, int S) {
     hipStream_t st = c->stream;
     c->S = S;
+    c->stage_cap = std::max<size_t>(256 * 1024, (size_t)S * 64 * 16);
+    HIPCHK(hipHostMalloc((void**)&c->h_stage, c->stage_cap, 0));
     // node and patch ranges
     int N = 0, P = 0;
     c->shells.resize(S);
@@ -317,41 +446,10 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
     // barriers cheaper); small ones 256-thread blocks spread over more CUs.
     int max_rows = 0;
     for (int s = 0; s < S; ++s) max_rows = std::max(max_rows, c->shells[s].node_end - c->shells[s].node_begin);
-    c->cg_threads = max_rows >= 16 * cg_rows_per_pass(c->fp32, 1024) ? 1024 : 256;
-    int cap = cg_max_blocks(c->opts.device, c->fp32, c->cg_threads);
-    if (cap <= 0) throw StatusErr{SHELL_E_DEVICE, "cannot query CG kernel occupancy"};
-    if (S > cap && c->cg_threads == 1024) {
-        c->cg_threads = 256;
-        cap = cg_max_blocks(c->opts.device, c->fp32, c->cg_threads);
-    }
-    if (S > cap) throw InvalErr{"too many shells for one context (limit " + std::to_string(cap) + ")"};
-    const int pass = cg_rows_per_pass(c->fp32, c->cg_threads);   // node rows per block pass
-    int target = std::max(pass, (N + cap - 1) / cap);
-    target = ((target + pass - 1) / pass) * pass;
-    std::vector<int> bshell, brow0, brow1;
-    int used = 0;
-    for (;; target += pass) {   // grow the rows per block until every block fits on the device at once
-        used = 0;
-        for (int s = 0; s < S; ++s)
-            used += std::max(1, (c->shells[s].node_end - c->shells[s].node_begin + target - 1) / target);
-        if (used <= cap) break;
-    }
-    c->h_shell_blk0.assign(S, 0);
-    c->h_shell_nblk.assign(S, 0);
-    used = 0;
-    for (int s = 0; s < S; ++s) {
-        const int r0 = c->shells[s].node_begin, r1 = c->shells[s].node_end;
-        int nb = std::max(1, (r1 - r0 + target - 1) / target);
-        c->h_shell_blk0[s] = used;
-        c->h_shell_nblk[s] = nb;
-        for (int k = 0; k < nb; ++k) {
-            bshell.push_back(s);
-            brow0.push_back(r0 + (int)((long long)(r1 - r0) * k / nb));
-            brow1.push_back(r0 + (int)((long long)(r1 - r0) * (k + 1) / nb));
-        }
-        used += nb;
-    }
-    c->nblk = used;
+    const int nt0 = max_rows >= 16 * cg_rows_per_pass(c->fp32, 1024) ? 1024 : 256;
+    if (!set_row_blocks(c, nt0, 1) && !set_row_blocks(c, 256, 1))
+        throw InvalErr{"too many shells for one context (limit " +
+                       std::to_string(cg_max_blocks(c->opts.device, c->fp32, 256)) + ")"};
     // theta-space basis table
     std::vector<double> phi(16 * 6 * 16);
     build_theta_basis(phi.data());
@@ -370,11 +468,6 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
     upload(c->row_ptr, c->h_row_ptr, st);
     upload(c->col_idx, c->h_col_idx, st);
     upload(c->diag_blk, diag, st);
-    upload(c->blk_shell, bshell, st);
-    upload(c->blk_row0, brow0, st);
-    upload(c->blk_row1, brow1, st);
-    upload(c->shell_blk0, c->h_shell_blk0, st);
-    upload(c->shell_nblk, c->h_shell_nblk, st);
     const size_t vecb = (size_t)N * 12 * sizeof(double);
     alloc(c->vals, (size_t)c->nnzb * 144 * (c->fp32 ? sizeof(float) : sizeof(double)));
     alloc(c->diag0, vecb);
@@ -382,12 +475,10 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
     alloc(c->e_patch, (size_t)std::max(P, 1) * 3 * sizeof(double));
     alloc(c->g_patch, (size_t)std::max(P, 1) * 48 * sizeof(double));
     alloc(c->e_shell, (size_t)S * 3 * sizeof(double));
-    alloc(c->red_part, (size_t)c->nblk * sizeof(double));
     alloc(c->red_out, (size_t)S * sizeof(double));
     for (DevBuf* b : {&c->qhat, &c->q, &c->qt, &c->g, &c->gt, &c->dvec, &c->rhs, &c->r64, &c->x64}) alloc(*b, vecb);
     const size_t tvb = (size_t)N * 12 * (c->fp32 ? sizeof(float) : sizeof(double));
     for (DevBuf* b : {&c->cg_x, &c->cg_r, &c->cg_z, &c->cg_p0, &c->cg_p1, &c->cg_q}) alloc(*b, tvb);
-    alloc(c->cg_partial, (size_t)c->nblk * 4 * sizeof(double));
     alloc(c->cg_bar, (size_t)S * cg_sync_bytes());
     alloc(c->cg_abort, sizeof(int));
     alloc(c->cg_rtol2, (size_t)S * sizeof(double));
@@ -402,7 +493,6 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
     for (DevBuf* b : {&c->dstep, &c->qstart, &c->b0, &c->guess}) alloc(*b, vecb);
     c->h_hist.assign(S, 0);
     alloc(c->rec_base, (size_t)S * sizeof(long long));
-    alloc(c->feat_part, (size_t)c->nblk * 12 * sizeof(double));
     alloc(c->feat_scale, (size_t)S * 12 * sizeof(float));
     {
         std::vector<int> cnt((size_t)S * 4, 0);
@@ -450,7 +540,7 @@ void shell_dot(shell_ctx* c, const double* x, const double* y, bool masked) {
 void assemble(shell_ctx* c, const double* q_in, double mass_scale, int elastic) {
     hipStream_t st = c->stream;
     GroupTimer tmr(c, SHELL_T_HESSIAN);
-    HIPCHK(hipMemsetAsync(c->vals.p, 0, c->vals.n, st));
+    launch_zero(st, c->vals.p, c->vals.n);
     const int pseudo = c->opts.hessian == SHELL_HESS_PSEUDO;
     for (size_t col = 0; col + 1 < c->colour_off.size(); ++col) {
         const int off = c->colour_off[col], n = c->colour_off[col + 1] - off;
@@ -481,10 +571,11 @@ void spmv(shell_ctx* c, const double* x, const double* b, double* y, int mode) {
     tmr.stop();
 }
 
-// Factor the block-Jacobi preconditioner; per-shell failure flags in h_fail.
-void bj_factor(shell_ctx* c) {
+// Enqueue the block-Jacobi factorisation and the copy of the per-shell
+// failure flags to h_fail (valid after the next synchronisation).
+void bj_factor_enqueue(shell_ctx* c) {
     hipStream_t st = c->stream;
-    HIPCHK(hipMemsetAsync(c->fail_shell.p, 0, c->fail_shell.n, st));
+    launch_zero(st, c->fail_shell.p, c->fail_shell.n);
     GroupTimer tmr(c, SHELL_T_BJ);
     if (c->fp32)
         launch_bj_factor<float>(st, c->N, dptr<int>(c->diag_blk), c->vals.p, 1, dptr<uint16_t>(c->freemask),
@@ -495,21 +586,27 @@ void bj_factor(shell_ctx* c) {
     HIPCHK(hipGetLastError());
     tmr.stop();
     HIPCHK(hipMemcpyAsync(c->h_fail, c->fail_shell.p, (size_t)c->S * sizeof(int), hipMemcpyDeviceToHost, st));
+}
+
+// Factor the block-Jacobi preconditioner; per-shell failure flags in h_fail.
+void bj_factor(shell_ctx* c) {
+    bj_factor_enqueue(c);
     sync(c);
 }
 
 // One CG launch on rhs b for the shells with active[s]; solution in cg_x.
 void cg_launch(shell_ctx* c, const double* b, const std::vector<int>& active, const std::vector<double>& rtol,
                int maxit) {
-    hipStream_t st = c->stream;
     std::vector<double> rt2(c->S);
     std::vector<int> mi(c->S, maxit);
     for (int s = 0; s < c->S; ++s) rt2[s] = rtol[s] * rtol[s];
     h2d(c, c->cg_rtol2.p, rt2.data(), c->S * sizeof(double));
     h2d(c, c->cg_maxit.p, mi.data(), c->S * sizeof(int));
     h2d(c, c->cg_active.p, active.data(), c->S * sizeof(int));
-    HIPCHK(hipMemsetAsync(c->cg_bar.p, 0, c->cg_bar.n, st));
-    HIPCHK(hipMemsetAsync(c->cg_abort.p, 0, c->cg_abort.n, st));
+    run_graph(c, c->g_cg, (double)(uintptr_t)b, [&] {
+    hipStream_t st = c->stream;
+    launch_zero(st, c->cg_bar.p, c->cg_bar.n);
+    launch_zero(st, c->cg_abort.p, c->cg_abort.n);
     GroupTimer tmr(c, SHELL_T_CG);
     hipError_t e;
     if (c->fp32)
@@ -531,6 +628,7 @@ void cg_launch(shell_ctx* c, const double* b, const std::vector<int>& active, co
     HIPCHK(e);
     tmr.stop();
     HIPCHK(hipMemcpyAsync(c->h_cg_out, c->cg_out.p, (size_t)c->S * sizeof(CgShellOut), hipMemcpyDeviceToHost, st));
+    });
     sync(c);
     if (c->timing) {
         long long mx = 0;
@@ -828,6 +926,7 @@ void shell_default_opts(shell_opts* o) {
     o->pcg_rtol = 1e-10;
     o->device = 0;
     o->stream = nullptr;
+    o->graphs = 1;
 }
 
 const char* shell_last_error(const shell_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
@@ -860,6 +959,7 @@ shell_status shell_create(const shell_desc* shells, int32_t n_shells, const shel
         c->opts = opts;
         c->stream = (hipStream_t)opts.stream;
         c->fp32 = opts.precision == SHELL_MIXED;
+        c->graphs = opts.graphs != 0;
         build(c, shells, n_shells);
     } catch (const InvalErr& e) {
         g_create_error = e.msg;
@@ -1098,8 +1198,10 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
     for (int k = 0;; ++k) {
         // rounding floor of the gradient from the previous Hessian: 4 eps || P_free |A| |q| ||
         if (have_prev) {
-            spmv(c, q, nullptr, rhs, 8 | 2);
-            shell_dot(c, rhs, rhs, true);
+            run_graph(c, c->g_floor, 0.0, [&] {
+                spmv(c, q, nullptr, rhs, 8 | 2);
+                shell_dot(c, rhs, rhs, true);
+            });
             sync(c);
             for (int s = 0; s < S; ++s) floor_[s] = 4.0 * eps * std::sqrt(c->h_red[s]);
         }
@@ -1120,8 +1222,12 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
         if (!any) break;
         // A = K(q) + M/dt^2, block-Jacobi, regulariser on failure
         double t0 = now_ms();
-        assemble(c, q, ms, 1);
-        launch_save_diag(st, c->N, dptr<int>(c->diag_blk), c->vals.p, c->fp32, dptr<double>(c->diag0));
+        run_graph(c, c->g_asm, ms, [&] {
+            assemble(c, q, ms, 1);
+            launch_save_diag(c->stream, c->N, dptr<int>(c->diag_blk), c->vals.p, c->fp32, dptr<double>(c->diag0));
+            bj_factor_enqueue(c);
+        });
+        sync(c);
         have_prev = true;
         std::vector<double> delta(S, 0.0);
         auto apply_delta = [&]() {
@@ -1133,8 +1239,8 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
             delta[s] = delta[s] == 0.0 ? 1e-6 : delta[s] * 10.0;
             return delta[s] <= 1e2 * (1 + 1e-12);
         };
-        for (;;) {
-            bj_factor(c);
+        for (bool first = true;; first = false) {
+            if (!first) bj_factor(c);
             bool again = false;
             for (int s = 0; s < S; ++s)
                 if (active[s] && c->h_fail[s]) {
@@ -1210,9 +1316,11 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
             std::vector<double> a_dev(S);
             for (int s = 0; s < S; ++s) a_dev[s] = searching[s] ? alpha[s] : 0.0;
             h2d(c, c->alpha_shell.p, a_dev.data(), S * sizeof(double));
-            launch_axpy_shell(st, c->N, q, d, dptr<double>(c->alpha_shell), dptr<int>(c->node_shell), qt);
-            eval_energy_grad(c, qt, qhat, ms, 1, true, gt, nullptr);
-            shell_dot(c, gt, gt, true);
+            run_graph(c, c->g_trial, ms, [&] {
+                launch_axpy_shell(c->stream, c->N, q, d, dptr<double>(c->alpha_shell), dptr<int>(c->node_shell), qt);
+                eval_energy_grad(c, qt, qhat, ms, 1, true, gt, nullptr);
+                shell_dot(c, gt, gt, true);
+            });
             sync(c);
             std::vector<int> accept(S, 0);
             for (int s = 0; s < S; ++s) {
@@ -1311,6 +1419,98 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
     if (stats_host) std::memcpy(stats_host, stats.data(), sizeof(shell_step_stats) * S);
     if (worst != SHELL_OK) c->err = "Newton step did not converge for every shell (see stats)";
     return worst;
+    API_CATCH
+}
+
+// ------------------------------------------------------------ autotuner
+namespace {
+struct TuneKey {
+    int device, N, S, fp32;
+    long long nnzb;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(device, N, S, fp32, nnzb) < std::tie(o.device, o.N, o.S, o.fp32, o.nnzb);
+    }
+};
+std::mutex g_tune_mutex;
+std::map<TuneKey, std::pair<int, int>> g_tune_cache;   // -> (threads, spread)
+
+// Wall time per CG iteration of the current layout: `iters` iterations of
+// every shell on b (tolerance 0), second of two runs.
+double time_cg(shell_ctx* c, const double* b, int iters) {
+    const std::vector<int> act(c->S, 1);
+    const std::vector<double> rt(c->S, 0.0);
+    double best = 0.0;
+    for (int rep = 0; rep < 2; ++rep) {
+        const double t0 = now_ms();
+        cg_launch(c, b, act, rt, iters);
+        best = now_ms() - t0;
+    }
+    long long mx = 1;
+    for (int s = 0; s < c->S; ++s) mx = std::max<long long>(mx, c->h_cg_out[s].iters);
+    return 1e3 * best / (double)mx;
+}
+}  // namespace
+
+shell_status shell_autotune(shell_ctx* c, int32_t cg_iters, shell_tune_result* out) {
+    if (!c) return SHELL_E_INVAL;
+    if (cg_iters < 1) {
+        c->err = "cg_iters must be >= 1";
+        return SHELL_E_INVAL;
+    }
+    API_TRY
+    HIPCHK(hipSetDevice(c->opts.device));
+    shell_tune_result r;
+    std::memset(&r, 0, sizeof(r));
+    const TuneKey key{c->opts.device, c->N, c->S, (int)c->fp32, c->nnzb};
+    bool cached = false;
+    std::pair<int, int> choice{c->cg_threads, 1};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            choice = it->second;
+            cached = true;
+        }
+    }
+    // operator: K(qbar) + M (symmetric positive definite on the free DOFs)
+    // and a smooth right-hand side; only the time per iteration matters
+    const bool timing = c->timing;
+    c->timing = false;
+    assemble(c, dptr<double>(c->qbar), 1.0, 1);
+    bj_factor(c);
+    std::vector<double> ones((size_t)c->N * 12);
+    for (int n = 0; n < c->N; ++n)
+        for (int w = 0; w < 12; ++w) ones[(size_t)n * 12 + w] = ((c->h_freemask[n] >> w) & 1) ? 1.0 : 0.0;
+    h2d(c, c->rhs.p, ones.data(), ones.size() * sizeof(double));
+    sync(c);
+    const int nt0 = c->cg_threads, target0 = c->cg_rows_target;
+    r.us_per_iter_default = time_cg(c, dptr<double>(c->rhs), cg_iters);
+    if (!cached) {
+        double best = 1e300;
+        for (int nt : {256, 1024})
+            for (int spread : {1, 2, 4}) {
+                if (!set_row_blocks(c, nt, spread)) continue;
+                const double t = time_cg(c, dptr<double>(c->rhs), cg_iters);
+                r.candidates++;
+                if (t < best) {
+                    best = t;
+                    choice = {nt, spread};
+                }
+            }
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        g_tune_cache[key] = choice;
+    }
+    if (!set_row_blocks(c, choice.first, choice.second)) throw StatusErr{SHELL_E_DEVICE, "autotuned layout lost"};
+    r.us_per_iter = time_cg(c, dptr<double>(c->rhs), cg_iters);
+    r.threads = c->cg_threads;
+    r.rows_per_block = c->cg_rows_target;
+    r.blocks = c->nblk;
+    r.from_cache = cached ? 1 : 0;
+    r.default_threads = nt0;
+    r.default_rows_per_block = target0;
+    c->timing = timing;
+    if (out) *out = r;
+    return SHELL_OK;
     API_CATCH
 }
 

@@ -570,8 +570,23 @@ template <class TV> __global__ void k_add_to(int n, const TV* __restrict__ dx, d
     if (t < n) x[t] += (double)dx[t];
 }
 
+// Zero n 16-byte words, then the 4-byte tail (a kernel rather than a
+// memset so that the clearing can sit inside a captured graph).
+__global__ void k_zero(size_t n16, uint4* __restrict__ p, size_t n4_tail, uint32_t* __restrict__ tail) {
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = t; i < n16; i += stride) p[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (t < n4_tail) tail[t] = 0u;
+}
+
 // ------------------------------------------------------------ launchers
 static inline dim3 grid1(int n) { return dim3((n + 255) / 256); }
+
+void launch_zero(hipStream_t st, void* p, size_t bytes) {
+    const size_t n16 = bytes / 16, n4 = (bytes % 16) / 4;
+    const size_t blocks = std::min<size_t>(std::max<size_t>((n16 + 255) / 256, 1), 4096);
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st, n16, (uint4*)p, n4,
+                       (uint32_t*)((char*)p + n16 * 16));
+}
 
 template <class TM>
 void launch_spmv(hipStream_t st, int nnodes, const int* row_ptr, const int* col_idx, const TM* vals,

@@ -48,8 +48,20 @@ class shell_opts(C.Structure):
         ("precision", C.c_int32), ("hessian", C.c_int32), ("warm_start", C.c_int32),
         ("newton_maxit", C.c_int32), ("pcg_maxit", C.c_int32),
         ("newton_rtol", C.c_double), ("pcg_rtol", C.c_double),
-        ("device", C.c_int32), ("stream", C.c_void_p),
+        ("device", C.c_int32), ("stream", C.c_void_p), ("graphs", C.c_int32),
     ]
+
+
+class shell_tune_result(C.Structure):
+    _fields_ = [
+        ("threads", C.c_int32), ("rows_per_block", C.c_int32), ("blocks", C.c_int32),
+        ("default_threads", C.c_int32), ("default_rows_per_block", C.c_int32),
+        ("candidates", C.c_int32), ("from_cache", C.c_int32),
+        ("us_per_iter", C.c_double), ("us_per_iter_default", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class shell_step_stats(C.Structure):
@@ -120,6 +132,8 @@ def _load():
     lib.shell_timing_enable.restype = C.c_int32
     lib.shell_timing_get.argtypes = [vp, P(shell_timing)]
     lib.shell_timing_get.restype = C.c_int32
+    lib.shell_autotune.argtypes = [vp, C.c_int32, P(shell_tune_result)]
+    lib.shell_autotune.restype = C.c_int32
     lib.shell_mlp_set_params.argtypes = [vp, P(C.c_float)]
     lib.shell_mlp_set_params.restype = C.c_int32
     lib.shell_mlp_get_params.argtypes = [vp, P(C.c_float)]
@@ -144,7 +158,7 @@ EXPORTED = ["shell_default_opts", "shell_create", "shell_destroy", "shell_last_e
             "shell_energy_grad_hess", "shell_assemble", "shell_get_bsr", "shell_spmv", "shell_pcg_solve",
             "shell_newton_step", "shell_timing_enable", "shell_timing_get", "shell_mlp_set_params",
             "shell_mlp_get_params", "shell_mlp_forward", "shell_mlp_loss_grad", "shell_mlp_train",
-            "shell_mlp_record", "shell_mlp_recorded"]
+            "shell_mlp_record", "shell_mlp_recorded", "shell_autotune"]
 
 MLP_IN, MLP_HIDDEN, MLP_OUT = 36, 128, 12
 MLP_PARAMS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_OUT + MLP_OUT
@@ -171,7 +185,7 @@ class ShellContext:
 
     def __init__(self, cases: Sequence, precision=SHELL_FP64, hessian=SHELL_HESS_EXACT,
                  newton_rtol=1e-10, pcg_rtol=1e-10, newton_maxit=50, pcg_maxit=100000,
-                 device=0, stream=None, warm_start=SHELL_WS_NONE):
+                 device=0, stream=None, warm_start=SHELL_WS_NONE, graphs=True):
         self._keep = []
         descs = (shell_desc * len(cases))()
         for k, cs in enumerate(cases):
@@ -192,6 +206,7 @@ class ShellContext:
         o.newton_rtol, o.pcg_rtol = float(newton_rtol), float(pcg_rtol)
         o.newton_maxit, o.pcg_maxit = int(newton_maxit), int(pcg_maxit)
         o.device = int(device)
+        o.graphs = int(bool(graphs))
         o.stream = C.c_void_p(stream) if stream else None
         h = C.c_void_p()
         rc = lib.shell_create(descs, len(cases), C.byref(o), C.byref(h))
@@ -264,6 +279,11 @@ class ShellContext:
             self._check(rc)
         return rc, [s.as_dict() for s in st]
 
+
+    def autotune(self, cg_iters=100):
+        r = shell_tune_result()
+        self._check(lib.shell_autotune(self.h, int(cg_iters), C.byref(r)))
+        return r.as_dict()
 
     # ---- warm-start network
     def mlp_set_params(self, theta):
