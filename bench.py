@@ -81,12 +81,14 @@ def presc_on_device(case, nsteps):
     return [torch.from_numpy(case.presc((k + 1) * case.dt).reshape(-1).copy()).cuda() for k in range(nsteps)]
 
 
-def run_steps(case, precision, steps, warmup, stream, tol):
-    """Warm up, time `steps` implicit steps, then re-run a few more with the
-    library's per-kernel event timing on.  Returns (wall s, stats, timing)."""
+def run_steps(case, precision, steps, warmup, stream, tol, autotune=True):
+    """Autotune the CG layout, warm up, time `steps` implicit steps, then
+    re-run a few more with the library's per-kernel event timing on.
+    Returns (wall s, stats, timing, autotune result)."""
     import torch
     from paper_2312_14839_amd import shell as S
     ctx = S.context_for(shells_of(case), precision=precision, stream=stream, **tol)
+    tune = ctx.autotune(100) if autotune else None
     n_timing = max(1, min(steps, 2))
     presc = presc_on_device(case, warmup + steps + n_timing)
     q = torch.from_numpy(case.q0.reshape(-1).copy()).cuda()
@@ -125,7 +127,7 @@ def run_steps(case, precision, steps, warmup, stream, tol):
     timing = ctx.timing_get()
     ctx.timing_enable(False)
     ctx.close()
-    return wall, stats_all, timing
+    return wall, stats_all, timing, tune
 
 
 def qstate_after(case, precision, nsteps, stream, tol):
@@ -182,6 +184,48 @@ def roofline(case, timing, fp32):
                  "traffic": None, "avg_launch_ms": per_launch_ms}
 
 
+def learned_section(stream):
+    """The learned Newton warm start on held-out sheets: samples recorded on
+    12 training sheets (24..48 patches a side, random twist / compression,
+    30 steps), the network trained on the GPU, then 12 steps of two 64x64
+    and one 128x128 unseen sheet, plain solver vs warm start (and the
+    extrapolation-only start, zero network, as the ablation)."""
+    import torch
+    from paper_2312_14839_amd import learned as L, workloads as W
+    t0 = time.perf_counter()
+    rec = L.run(L.training_scene(count=12, seed=100), 30, record=dict(capacity=600000, per_shell=1024, seed=7),
+                stream=stream)
+    t_rec = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    theta, losses = L.train(rec["feat"], rec["tgt"], rec["n_samples"], schedule=((8000, 1e-3), (4000, 3e-4)),
+                            batch=512, seed=1)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del rec
+    scenes = [L.Scene([W.case_random_load(n, seed=sd)]) for n, sd in ((64, 906), (64, 910), (128, 903))]
+    res = {"plain": [0, 0.0], "learned": [0, 0.0], "extrapolation_only": [0, 0.0]}
+    zero = L.init_params(0)
+    steps = 12
+    for sc in scenes:
+        for key, th in (("plain", None), ("learned", theta), ("extrapolation_only", zero)):
+            L.run(sc, 2, theta=th, stream=stream)                      # warm-up (graph capture, caches)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = L.run(sc, steps, theta=th, stream=stream)
+            torch.cuda.synchronize()
+            res[key][0] += int(np.sum(r["pcg_iters"]))
+            res[key][1] += time.perf_counter() - t0
+    nsteps = steps * len(scenes)
+    out = {k: {"cg_iters_per_step": v[0] / nsteps, "ms_per_step": 1e3 * v[1] / nsteps} for k, v in res.items()}
+    out.update({"train_steps": int(losses.size), "train_loss_first": float(np.mean(losses[:20])),
+                "train_loss_last": float(np.mean(losses[-100:])), "record_s": t_rec, "train_s": t_train,
+                "eval": "twist/compression 64x64 (seeds 906, 910) and 128x128 (seed 903), 12 steps each, dt 2e-3"})
+    print(f"[bench] learned: CG its/step plain {out['plain']['cg_iters_per_step']:.1f} learned "
+          f"{out['learned']['cg_iters_per_step']:.1f} extrapolation {out['extrapolation_only']['cg_iters_per_step']:.1f}",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline(budget_s=15.0):
     """Oracle patch energy + gradient + Hessian evaluations per second on a
     32x32-patch cylinder section (1024 patches), all host threads."""
@@ -213,6 +257,8 @@ def main():
     ap.add_argument("--workload", default="cylinder", choices=["cylinder", "twist", "sheet", "batch"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="first run a plain device copy of MB megabytes (counter calibration)")
     args = ap.parse_args()
@@ -234,7 +280,8 @@ def main():
         case = Batch(case)
     stream = torch.cuda.current_stream().cuda_stream
     print(f"[bench] workload {case.name}: {case.patches} patches, {12 * case.nodes} DOF", file=sys.stderr, flush=True)
-    wall, st64, tm64 = run_steps(case, S.SHELL_FP64, args.steps, args.warmup, stream, tol)
+    wall, st64, tm64, tune64 = run_steps(case, S.SHELL_FP64, args.steps, args.warmup, stream, tol,
+                                         not args.no_autotune)
     newton64 = sum(s["newton_iters"] for s in st64)
     # each Newton iteration of a shell evaluates every patch of that shell
     value = sum(s["patch_evals"] for s in st64) / wall
@@ -252,10 +299,12 @@ def main():
         "cg_iters_per_step": sum(s["pcg_iters_total"] for s in st64) / args.steps,
         "kernel_ms_fp64": {k: v for k, v in tm64["ms"].items()},
         "kernel_launches_fp64": tm64["launches"],
+        "cg_layout": tune64,
         "roofline": roof,
     }
     if not args.no_mixed:
-        wallm, stm, tmm = run_steps(case, S.SHELL_MIXED, args.steps, args.warmup, stream, tol)
+        wallm, stm, tmm, _ = run_steps(case, S.SHELL_MIXED, args.steps, args.warmup, stream, tol,
+                                       not args.no_autotune)
         newtonm = sum(s["newton_iters"] for s in stm)
         evalsm = sum(s["patch_evals"] for s in stm)
         nst = args.warmup + args.steps
@@ -270,6 +319,8 @@ def main():
                         "cg_iters_per_step": sum(s["pcg_iters_total"] for s in stm) / args.steps,
                         "kernel_ms": tmm["ms"], "roofline": roofm}
         print(f"[bench] mixed: {1e3 * wallm / args.steps:.2f} ms/step, err {err:.2e}", file=sys.stderr, flush=True)
+    if not args.no_learned:
+        out["learned"] = learned_section(stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -199,8 +199,9 @@ shell_status shell_timing_get(const shell_ctx *c, shell_timing *out);
 
 /* CG layout autotuner.  The persistent CG kernel covers each shell's node
  * rows with contiguous row blocks; the tunable layout is the threads per
- * block (256 or 1024) and the rows per block (1, 2 or 4 times the fewest
- * that keep every block resident at once).  shell_autotune times cg_iters
+ * block (256, 512 or 1024) and the rows per block (the fewest that keep
+ * every block resident at once, or 1, 2 or 4 times that rounded up to the
+ * rows one pass of a block covers).  shell_autotune times cg_iters
  * CG iterations of every candidate on K(qbar) + M (overwriting the
  * context's matrix) and keeps the fastest.  Results are cached for the
  * process by (device, nodes, shells, block non-zeros, precision); a cached

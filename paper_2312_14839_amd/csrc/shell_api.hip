@@ -262,16 +262,19 @@ void validate(const shell_desc& d, int s) {
         if (!std::isfinite(d.ref_host[i])) bad("reference coordinates not finite");
 }
 
-// CG row blocks for `nt` threads per block and at least `spread` x the
-// fewest rows per block that fit all blocks on the device at once; uploads
-// the layout and sizes the per-block buffers.  False if the shells do not
-// fit (more shells than co-resident blocks).
+// CG row blocks for `nt` threads per block.  spread >= 1: rows per block a
+// multiple of the rows one pass of the block covers, at least `spread` x
+// the fewest that fit all blocks on the device at once; spread = 0: the
+// fewest rows per block that fit (every co-resident slot used, the last
+// pass of a block partly idle).  Uploads the layout and sizes the per-block
+// buffers.  False if the shells do not fit (more shells than co-resident
+// blocks).
 bool set_row_blocks(shell_ctx* c, int nt, int spread) {
     const int S = c->S, N = c->N;
     const int cap = cg_max_blocks(c->opts.device, c->fp32, nt);
     if (cap <= 0) throw StatusErr{SHELL_E_DEVICE, "cannot query CG kernel occupancy"};
     if (S > cap) return false;
-    const int pass = cg_rows_per_pass(c->fp32, nt);   // node rows per block pass
+    const int pass = spread >= 1 ? cg_rows_per_pass(c->fp32, nt) : 1;   // granularity of the rows per block
     int target = std::max(pass, (N + cap - 1) / cap);
     target = ((target + pass - 1) / pass) * pass;
     int used = 0;
@@ -1487,8 +1490,8 @@ shell_status shell_autotune(shell_ctx* c, int32_t cg_iters, shell_tune_result* o
     r.us_per_iter_default = time_cg(c, dptr<double>(c->rhs), cg_iters);
     if (!cached) {
         double best = 1e300;
-        for (int nt : {256, 1024})
-            for (int spread : {1, 2, 4}) {
+        for (int nt : {256, 512, 1024})
+            for (int spread : {0, 1, 2, 4}) {
                 if (!set_row_blocks(c, nt, spread)) continue;
                 const double t = time_cg(c, dptr<double>(c->rhs), cg_iters);
                 r.candidates++;

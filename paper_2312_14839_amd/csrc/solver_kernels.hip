@@ -624,6 +624,13 @@ void launch_regularize(hipStream_t st, int nnodes, const int* diag_blk, void* va
                        node_shell, delta_shell);
 }
 
+// the CG kernel instance for a block size of 256, 512 or 1024 threads
+template <class TM, class TV> const void* cg_fn(int nthreads) {
+    return nthreads == 1024 ? (const void*)k_cg<TM, TV, 1024>
+           : nthreads == 512 ? (const void*)k_cg<TM, TV, 512>
+                             : (const void*)k_cg<TM, TV, 256>;
+}
+
 template <class TM, class TV>
 hipError_t launch_cg(hipStream_t st, int nblk, int nthreads, const RowBlocks& rb, const int* row_ptr,
                      const int* col_idx, const TM* vals, const TV* dinv, const uint16_t* freemask, const double* b,
@@ -635,8 +642,7 @@ hipError_t launch_cg(hipStream_t st, int nblk, int nthreads, const RowBlocks& rb
                     (void*)&freemask, (void*)&b, (void*)&x, (void*)&r, (void*)&z, (void*)&p0, (void*)&p1,
                     (void*)&qv, (void*)&partial, (void*)&ss, (void*)&abort_flag, (void*)&rtol2_shell,
                     (void*)&maxit_shell, (void*)&active_shell, (void*)&out};
-    const void* fn = nthreads == 1024 ? (const void*)k_cg<TM, TV, 1024> : (const void*)k_cg<TM, TV, 256>;
-    return hipLaunchCooperativeKernel(fn, dim3(nblk), dim3(nthreads), args, 0, st);
+    return hipLaunchCooperativeKernel(cg_fn<TM, TV>(nthreads), dim3(nblk), dim3(nthreads), args, 0, st);
 }
 template hipError_t launch_cg<double, double>(hipStream_t, int, int, const RowBlocks&, const int*, const int*,
                                               const double*, const double*, const uint16_t*, const double*, double*,
@@ -652,11 +658,7 @@ int cg_rows_per_pass(int tm_fp32, int nthreads) { return (nthreads / 64) * (tm_f
 
 int cg_max_blocks(int device, int tm_fp32, int nthreads) {
     int per_cu = 0, cus = 0;
-    const void* fn;
-    if (tm_fp32)
-        fn = nthreads == 1024 ? (const void*)k_cg<float, float, 1024> : (const void*)k_cg<float, float, 256>;
-    else
-        fn = nthreads == 1024 ? (const void*)k_cg<double, double, 1024> : (const void*)k_cg<double, double, 256>;
+    const void* fn = tm_fp32 ? cg_fn<float, float>(nthreads) : cg_fn<double, double>(nthreads);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nthreads, 0) != hipSuccess) return -1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return -1;
     return per_cu * cus;

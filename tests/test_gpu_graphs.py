@@ -64,7 +64,7 @@ def test_autotune_same_result_and_cache():
     a, _, _ = _run(cases, 2, 0, graphs=True)
     b, _, info = _run(cases, 2, 0, graphs=True, tune=True)
     assert info["candidates"] >= 2 and info["from_cache"] == 0
-    assert info["threads"] in (256, 1024) and info["blocks"] >= len(cases)
+    assert info["threads"] in (256, 512, 1024) and info["blocks"] >= len(cases)
     assert info["us_per_iter"] > 0
     disp = np.abs(a[-1] - np.concatenate([c.q0.reshape(-1) for c in cases])).max()
     assert np.abs(a[-1] - b[-1]).max() <= 1e-8 * disp
