@@ -161,6 +161,27 @@ def cg_bytes(case, timing, tm_bytes, tv_bytes):
     return blocks * (144 * tm_bytes + 4) + rows * (144 * tv_bytes + 4 + 11 * 12 * tv_bytes)
 
 
+def profiled_traffic(case, fp32, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary of this workload, or None when there is
+    none or the kernel source has changed since it was taken."""
+    import hashlib
+    if fp32 or case.name != "cylinder256x256":
+        return None
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "cylinder256_fp64_rocprof.txt")
+    src = os.path.join(here, "paper_2312_14839_amd", "csrc", "solver_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for line in open(path):
+        if line.startswith(f"TRAFFIC {kernel} "):
+            f = dict(kv.split("=") for kv in line.split()[2:])
+            if f.get("solver_kernels_sha256") == digest:
+                return float(f["bytes_per_launch"])
+    return None
+
+
 def roofline(case, timing, fp32):
     ms = timing["ms"]
     grp = max(ms, key=lambda k: ms[k])
@@ -170,8 +191,10 @@ def roofline(case, timing, fp32):
         tb = 4 if fp32 else 8
         total = cg_bytes(case, timing, tb, tb)
         ach = total / (ms[grp] * 1e-3) / 1e9
+        traffic = profiled_traffic(case, fp32, "k_cg")
         return grp, {"kernel": "k_cg (persistent block-Jacobi CG)", "bound": "hbm", "achieved": ach,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
                      "avg_launch_ms": per_launch_ms, "algorithmic_bytes_per_launch": total / n}
     if grp == "hessian":
         flops = timing["patch_evals"] * HESS_MFMA_FLOPS
