@@ -18,8 +18,9 @@ void launch_shell_energy(hipStream_t st, int nshell, const ShellParams* shells, 
                          double* e_shell);
 template <class T>
 void launch_hessian(hipStream_t st, const int* patch_list, int nlist, const int4* patch_nodes, const int* patch_shell,
-                    const int* patch_slots, const ShellParams* shells, const double* phi, const double* q,
-                    const double* qbar, double mass_scale, int elastic, int pseudo, T* vals);
+                    const int* patch_slots, const uint16_t* patch_first, const ShellParams* shells,
+                    const double* phi, const double* q, const double* qbar, double mass_scale, int elastic,
+                    int pseudo, T* vals);
 
 // ------------------------------------------------------ solver kernels
 // Row partition of the node rows into blocks that never straddle a shell;

@@ -56,6 +56,7 @@ struct shell_ctx {
     int cg_rows_target = 0;        // node rows per CG block (before the even split of a shell)
     std::vector<int> h_shell_blk0, h_shell_nblk;
     // device data
+    DevBuf patch_first;   // [P] uint16 first-touch bits of the 16 local blocks
     DevBuf shells_d, phi, qbar, freemask, node_shell, patch_nodes, patch_shell, patch_slots, colour_list, inc_ptr,
         inc, row_ptr, col_idx, diag_blk, vals, diag0, dinv;
     DevBuf blk_shell, blk_row0, blk_row1, shell_blk0, shell_nblk;
@@ -444,6 +445,24 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
         clist.insert(clist.end(), colour_lists[col].begin(), colour_lists[col].end());
         c->colour_off.push_back((int)clist.size());
     }
+    // first touch: bit b of patch p is set when p is the first patch, in
+    // colour-pass order, to add into its local block b (patches of one
+    // colour never share a block), so the assembly stores instead of adding
+    // there and needs no zero fill
+    std::vector<uint16_t> first((size_t)P, 0);
+    {
+        std::vector<char> touched((size_t)c->nnzb, 0);
+        for (int p : clist)
+            for (int b = 0; b < 16; ++b) {
+                const int sl = slots[(size_t)p * 16 + b];
+                if (!touched[sl]) {
+                    touched[sl] = 1;
+                    first[p] |= (uint16_t)(1u << b);
+                }
+            }
+        for (long long k = 0; k < c->nnzb; ++k)
+            if (!touched[k]) throw InvalErr{"internal: matrix block without a patch"};
+    }
     // CG row blocks: contiguous node rows, never straddling a shell.  Large
     // shells use 1024-thread blocks (fewer blocks make the per-iteration
     // barriers cheaper); small ones 256-thread blocks spread over more CUs.
@@ -466,6 +485,7 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
     upload(c->patch_shell, pshell, st);
     upload(c->patch_slots, slots, st);
     upload(c->colour_list, clist, st);
+    upload(c->patch_first, first, st);
     upload(c->inc_ptr, inc_ptr, st);
     upload(c->inc, inc_flat, st);
     upload(c->row_ptr, c->h_row_ptr, st);
@@ -543,18 +563,17 @@ void shell_dot(shell_ctx* c, const double* x, const double* y, bool masked) {
 void assemble(shell_ctx* c, const double* q_in, double mass_scale, int elastic) {
     hipStream_t st = c->stream;
     GroupTimer tmr(c, SHELL_T_HESSIAN);
-    launch_zero(st, c->vals.p, c->vals.n);
     const int pseudo = c->opts.hessian == SHELL_HESS_PSEUDO;
     for (size_t col = 0; col + 1 < c->colour_off.size(); ++col) {
         const int off = c->colour_off[col], n = c->colour_off[col + 1] - off;
         const int* list = dptr<int>(c->colour_list) + off;
         if (c->fp32)
             launch_hessian<float>(st, list, n, dptr<int4>(c->patch_nodes), dptr<int>(c->patch_shell),
-                                  dptr<int>(c->patch_slots), dptr<ShellParams>(c->shells_d), dptr<double>(c->phi), q_in,
+                                  dptr<int>(c->patch_slots), dptr<uint16_t>(c->patch_first), dptr<ShellParams>(c->shells_d), dptr<double>(c->phi), q_in,
                                   dptr<double>(c->qbar), mass_scale, elastic, pseudo, dptr<float>(c->vals));
         else
             launch_hessian<double>(st, list, n, dptr<int4>(c->patch_nodes), dptr<int>(c->patch_shell),
-                                   dptr<int>(c->patch_slots), dptr<ShellParams>(c->shells_d), dptr<double>(c->phi),
+                                   dptr<int>(c->patch_slots), dptr<uint16_t>(c->patch_first), dptr<ShellParams>(c->shells_d), dptr<double>(c->phi),
                                    q_in, dptr<double>(c->qbar), mass_scale, elastic, pseudo, dptr<double>(c->vals));
     }
     HIPCHK(hipGetLastError());
