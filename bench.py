@@ -264,7 +264,7 @@ def cpu_baseline(budget_s=15.0):
         O.matrix_blocks(s, q, c.ref, "hessian")
         reps += 1
         el = time.perf_counter() - t0
-        if el > budget_s or reps >= 50:
+        if el > budget_s or reps >= 400:
             break
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": reps * c.patches / el, "unit": "patch E/grad/Hess evals/s", "cores": cores, "kind": "oracle",
