@@ -3,6 +3,7 @@ finite differences of the FP64 loss, bfloat16 rounding against its
 definition, and a step of Adam against its closed form on a quadratic.
 CPU only."""
 import numpy as np
+import pytest
 
 from oracle import mlp_oracle as M
 
@@ -40,3 +41,36 @@ def test_adam_first_step_is_lr_sign():
     g = np.array([0.3, -4.0, 1e-3])
     th, m, v = M.adam_step(theta, g, np.zeros(3), np.zeros(3), 1, 0.01)
     np.testing.assert_allclose(th, theta - 0.01 * np.sign(g) * np.abs(g) / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+# planted mistakes in the network oracle, caught by the pins above
+_MLP_MUTANTS = [
+    ("ReLU mask dropped in the backward pass", "* (z2 > 0)", ""),
+    ("W2 not transposed in the backward pass", "@ _r(p[\"W2\"], bf16).T)", "@ _r(p[\"W2\"], bf16))"),
+    ("loss gradient without the factor 2", "dy = 2.0 * e / n", "dy = e / n"),
+    ("bias gradient as a mean instead of a sum", "g[\"b3\"] = dy.sum(axis=0)", "g[\"b3\"] = dy.mean(axis=0)"),
+    ("Adam without bias correction of v", "vh = v / (1 - b2 ** step)", "vh = v"),
+    ("bf16 rounding by truncation", "r = ((u + 0x7FFF + lsb) >> 16) << 16", "r = (u >> 16) << 16"),
+]
+
+
+@pytest.mark.parametrize("i", range(len(_MLP_MUTANTS)), ids=[m[0] for m in _MLP_MUTANTS])
+def test_planted_mistake_in_network_oracle_is_caught(i):
+    import types
+    name, old, new = _MLP_MUTANTS[i]
+    src = open(M.__file__).read()
+    assert old in src
+    mod = types.ModuleType("mlp_mutant")
+    exec(compile(src.replace(old, new, 1), "mlp_mutant", "exec"), mod.__dict__)
+    pins = [test_backward_matches_central_differences, test_bf16_rounding, test_adam_first_step_is_lr_sign]
+    original = globals()["M"]
+    failed = 0
+    for pin in pins:
+        globals()["M"] = mod
+        try:
+            pin()
+        except (AssertionError, ValueError, IndexError):
+            failed += 1
+        finally:
+            globals()["M"] = original
+    assert failed, f"no pin caught: {name}"

@@ -1,0 +1,138 @@
+"""Planted mistakes in the CPU oracle are caught by its pins (CPU only).
+
+Each case copies the oracle's C++ sources, changes one expression the way a
+plausible slip would (a dropped factor or term, a wrong sign, a swapped or
+transposed operand, a wrong constant or index), builds the copy into a
+separate library, points the oracle module at it and runs the oracle's pin
+tests of the basis and the mechanics: at least one must fail.  The same
+harness on an unchanged copy must pass every pin, so a failure is the
+mutation's doing.  The original library is restored afterwards."""
+import contextlib
+import os
+import shutil
+import subprocess
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+from oracle import oracle as O
+
+import test_oracle_basis as TB
+import test_oracle_mechanics as TM
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ORACLE = os.path.join(os.path.dirname(HERE), "oracle")
+SOURCES = ["patch.cpp", "global.cpp", "capi.cpp"]
+HEADERS = ["bhem_oracle.hpp", "oracle_global.hpp"]
+
+# (name, file, original text, planted text)
+MUTANTS = [
+    ("bending coefficient h^3/24 -> h^3/12 (Voigt energy)", "patch.cpp",
+     "quad_b * (h * h * h / 24.0)", "quad_b * (h * h * h / 12.0)"),
+    ("Hermite basis: sign of w_11", "patch.cpp", "w[1][1] = -g(1 - t);", "w[1][1] = g(1 - t);"),
+    ("Hermite basis: second derivative of w_01", "patch.cpp",
+     "auto gpp = [](double x) { return 6 * x - 4; };", "auto gpp = [](double x) { return 6 * x - 2; };"),
+    ("Gauss rule: inner and outer weights equal", "patch.cpp",
+     "double win = (18.0 + std::sqrt(30.0)) / 72.0;", "double win = (18.0 - std::sqrt(30.0)) / 72.0;"),
+    ("Lame lambda with 1 + nu^2", "bhem_oracle.hpp",
+     "s.young * s.poisson / (1.0 - s.poisson * s.poisson)", "s.young * s.poisson / (1.0 + s.poisson * s.poisson)"),
+    ("Voigt H: shear entry without the mu term", "patch.cpp",
+     "H[2][2] = (lam + mu) * ai[0][1] * ai[0][1] + mu * ai[0][0] * ai[1][1];",
+     "H[2][2] = (lam + mu) * ai[0][1] * ai[0][1];"),
+    ("gradient: membrane strain factor 1/2 dropped for alpha_1", "patch.cpp",
+     "V3<T> dalpha[3] = {0.5 * da11, 0.5 * da22, 0.5 * (2.0 * da12)};",
+     "V3<T> dalpha[3] = {da11, 0.5 * da22, 0.5 * (2.0 * da12)};"),
+    ("gradient: d b / d q with a transposed cross product", "patch.cpp",
+     "V3<T> t1 = cross(g.a[1], g.a3);   // a_2 x a_3", "V3<T> t1 = cross(g.a3, g.a[1]);   // a_2 x a_3"),
+    ("Hessian: geometric membrane term dropped", "patch.cpp",
+     "for (int i = 0; i < 3; ++i) add_identity(d2al[i] * Ha[i], G1);", ""),
+    ("Hessian: D12 and D21 swapped", "patch.cpp",
+     "p1I * p2J * D[i][2][r][c] + p2I * p1J * D[i][3][r][c]",
+     "p1I * p2J * D[i][3][r][c] + p2I * p1J * D[i][2][r][c]"),
+    ("Hessian: d a3 / d q transposed", "patch.cpp",
+     "d2b[r][c] += pabI * da3[J][r][c] + pabJ * da3[I][c][r];",
+     "d2b[r][c] += pabI * da3[J][c][r] + pabJ * da3[I][r][c];"),
+    ("Hessian: bending factor of the 12-component", "patch.cpp",
+     "const double beta_fac[3] = {1.0, 1.0, 2.0};", "const double beta_fac[3] = {1.0, 1.0, 1.0};"),
+    ("gravity load with the wrong sign", "patch.cpp",
+     "f[3 * I + c] += wq * qp[g].phi[0][I] * s.gravity[c];", "f[3 * I + c] -= wq * qp[g].phi[0][I] * s.gravity[c];"),
+    ("periodic merge: node column n1 not aliased", "bhem_oracle.hpp",
+     "if (s.periodic1) i %= s.n1;", ""),
+]
+
+
+def _pins():
+    """The oracle's own pins of the basis and mechanics (fast ones), each a
+    zero-argument callable."""
+    pins = [TB.test_gauss_points_match_paper_and_legendre, TB.test_hermite_end_values,
+            TB.test_hermite_derivatives_by_differences, TB.test_partition_of_unity,
+            TB.test_bicubic_reproduction, TB.test_c1_continuity_across_shared_edges,
+            TB.test_node_numbering_open_and_periodic,
+            TM.test_tensor_and_voigt_energy_agree, TM.test_zero_energy_and_force_at_rest_and_under_rigid_motion,
+            TM.test_uniform_stretch_matches_plane_stress_stvk, TM.test_cylindrical_bending_converges_to_kirchhoff,
+            lambda: TM.test_gradient_matches_complex_step(0), TM.test_gradient_matches_central_differences,
+            TM.test_net_force_and_torque_vanish, lambda: TM.test_hessian_matches_complex_step_of_gradient(0),
+            TM.test_hessian_matches_central_differences, TM.test_translations_in_hessian_null_space,
+            TM.test_patch_mass_is_kronecker_of_hermite_beam_masses, TM.test_total_mass_and_gravity_load]
+    rows = TB._golden("dof_counts.txt")
+    pins += [lambda r=r: TB.test_printed_dof_and_nonzero_counts(r) for r in rows]
+    return pins
+
+
+def _build(tmp, name, mutation):
+    d = os.path.join(tmp, name)
+    os.makedirs(d)
+    for f in SOURCES + HEADERS:
+        shutil.copy(os.path.join(ORACLE, f), d)
+    if mutation is not None:
+        fname, old, new = mutation
+        path = os.path.join(d, fname)
+        text = open(path).read()
+        assert text.count(old) >= 1, f"mutation site not found: {old!r}"
+        open(path, "w").write(text.replace(old, new, 1))
+    out = os.path.join(d, "liborc.so")
+    subprocess.run(["g++", "-O1", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-w"]
+                   + [os.path.join(d, s) for s in SOURCES] + ["-o", out], check=True)
+    return out
+
+
+@contextlib.contextmanager
+def _using(path):
+    saved = O._lib
+    O._lib = O._load(path)
+    try:
+        yield
+    finally:
+        O._lib = saved
+
+
+def _failures(lib_path):
+    failed = []
+    with _using(lib_path):
+        for i, pin in enumerate(_pins()):
+            try:
+                pin()
+            except AssertionError:
+                failed.append(getattr(pin, "__name__", str(i)))
+    return failed
+
+
+@pytest.fixture(scope="module")
+def built():
+    tmp = tempfile.mkdtemp(prefix="orc_mut_")
+    jobs = [("clean", None)] + [(f"m{i}", (f, o, n)) for i, (_, f, o, n) in enumerate(MUTANTS)]
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        paths = dict(zip([j[0] for j in jobs], ex.map(lambda j: _build(tmp, *j), jobs)))
+    yield paths
+    shutil.rmtree(tmp, ignore_errors=True)
+
+
+def test_unchanged_copy_passes_every_pin(built):
+    assert _failures(built["clean"]) == []
+
+
+@pytest.mark.parametrize("i", range(len(MUTANTS)), ids=[m[0] for m in MUTANTS])
+def test_planted_mistake_is_caught(built, i):
+    failed = _failures(built[f"m{i}"])
+    assert failed, f"no pin caught: {MUTANTS[i][0]}"
