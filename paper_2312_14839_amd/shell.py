@@ -187,6 +187,7 @@ class ShellContext:
                  newton_rtol=1e-10, pcg_rtol=1e-10, newton_maxit=50, pcg_maxit=100000,
                  device=0, stream=None, warm_start=SHELL_WS_NONE, graphs=True):
         self._keep = []
+        self._lib = lib   # kept for close() during interpreter shutdown
         descs = (shell_desc * len(cases))()
         for k, cs in enumerate(cases):
             ref = np.ascontiguousarray(cs.ref, dtype=np.float64)
@@ -219,8 +220,8 @@ class ShellContext:
         self.total_nodes, self.total_patches, self.nnzb = n.value, p.value, nb.value
 
     def close(self):
-        if getattr(self, "h", None):
-            lib.shell_destroy(self.h)
+        if getattr(self, "h", None) and self._lib is not None:
+            self._lib.shell_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -244,6 +244,35 @@ def test_full_size_cylinder_newton_residual(precision):
     np.testing.assert_array_equal(q1[fx], qp[fx])
 
 
+def test_post_buckling_cylinder_step():
+    """The 256x256 cylinder compressed for 300 steps (well past buckling: the
+    radial deviation is centimetres against a 1e-5 m seed), then one more
+    FP64 step: the oracle's gradient of the incremental potential at the GPU
+    result is at the GPU's convergence level (a single-step check; the
+    trajectory itself is rounding-sensitive and not compared)."""
+    sh = S()
+    case = W.case_cylinder(256, 256)
+    ctx = sh.context_for([case], newton_rtol=1e-10, pcg_rtol=1e-8)
+    q = torch.from_numpy(case.q0.reshape(-1).copy()).cuda()
+    v = torch.zeros_like(q)
+    q1, v1 = torch.empty_like(q), torch.empty_like(q)
+    for k in range(300):
+        pr = torch.from_numpy(case.presc((k + 1) * case.dt).reshape(-1).copy()).cuda()
+        rc, st = ctx.newton_step(case.dt, q, v, pr, q1, v1, allow_fail=True)
+        assert rc == 0, (k, st[0])
+        q, q1 = q1, q
+        v, v1 = v1, v
+    qn, vn = host(q).reshape(-1, 12), host(v).reshape(-1, 12)
+    radial = np.hypot(qn[:, 0], qn[:, 1]) - 0.2
+    assert np.abs(radial).max() > 1e-2
+    pr = torch.from_numpy(case.presc(301 * case.dt).reshape(-1).copy()).cuda()
+    rc, st = ctx.newton_step(case.dt, q, v, pr, q1, v1)
+    ctx.close()
+    res = newton_residual(case, host(q1), qn, vn, case.dt)
+    level = max(1e-10 * st[0]["grad_norm0"], st[0]["grad_floor"])
+    assert np.linalg.norm(res) <= 10 * level, (np.linalg.norm(res), st[0])
+
+
 def test_full_size_batch_sampled():
     """The 256-sheet batch in one context (one persistent CG launch for all
     sheets): the three smallest sheets match the single-shell oracle Newton
