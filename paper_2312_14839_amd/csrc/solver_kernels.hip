@@ -461,6 +461,7 @@ __global__ __launch_bounds__(NT) void k_cg(
         for (int base = row0; base < row1; base += rows_per_pass) {
             const int node = base + wv * G + grp;
             if (!(lane_ok && node < row1)) continue;
+            const unsigned fmask = fm[node];   // loaded first: later waits on it drain nothing else
             TV acc[R];
             const TV bt = (TV)beta;
             row_times_grouped<TM, TV>(row_ptr, col_idx, vals, node, t, gsrc, false,
@@ -477,7 +478,7 @@ __global__ __launch_bounds__(NT) void k_cg(
                 const int w = R * t + i;
                 const size_t at = (size_t)node * 12 + w;
                 const TV pn = z[at] + bt * pin[at];
-                const TV qq = is_free(fm, node, w) ? acc[i] : TV(0);
+                const TV qq = ((fmask >> w) & 1u) ? acc[i] : TV(0);
                 pout[at] = pn;
                 qv[at] = qq;
                 pq[0] += (double)pn * (double)qq;
@@ -498,11 +499,15 @@ __global__ __launch_bounds__(NT) void k_cg(
             const int node = base + wv * G + grp;
             const bool ok = lane_ok && node < row1;
             const int nd = ok ? node : row0;
-            TV rr[R], zz[R];
+            // every load of the row is issued before the first use
+            const unsigned fmask = fm[nd];
+            TV rr[R], zz[R], xo[R], pp[R];
 #pragma unroll
             for (int i = 0; i < R; ++i) {
                 const size_t at = (size_t)nd * 12 + R * t + i;
                 rr[i] = r[at] - (TV)alpha * qv[at];
+                xo[i] = x[at];
+                pp[i] = pout[at];
             }
             precond(nd, rr, zz);
             if (ok) {
@@ -510,8 +515,8 @@ __global__ __launch_bounds__(NT) void k_cg(
                 for (int i = 0; i < R; ++i) {
                     const int w = R * t + i;
                     const size_t at = (size_t)node * 12 + w;
-                    if (!is_free(fm, node, w)) zz[i] = TV(0);
-                    x[at] += (TV)alpha * pout[at];
+                    if (!((fmask >> w) & 1u)) zz[i] = TV(0);
+                    x[at] = xo[i] + (TV)alpha * pp[i];
                     r[at] = rr[i];
                     z[at] = zz[i];
                     s2[0] += (double)rr[i] * (double)zz[i];
