@@ -145,10 +145,14 @@ __global__ __launch_bounds__(256) void k_spmv(int nnodes, const int* __restrict_
     double acc[R];
     row_times<TM, double>(row_ptr, col_idx, vals, node, t, lane - t, absval,
                           [&](int col, double* xv) {
+                              // unconditional loads, then a select: no branch, so no
+                              // wait on the mask ahead of the matrix loads
+                              const unsigned fc = m ? (unsigned)m[col] : 0xFFFFu;
 #pragma unroll
                               for (int i = 0; i < R; ++i) {
                                   const int w = R * t + i;
-                                  xv[i] = is_free(m, col, w) ? x[(size_t)col * 12 + w] : 0.0;
+                                  const double xx = x[(size_t)col * 12 + w];
+                                  xv[i] = ((fc >> w) & 1u) ? xx : 0.0;
                               }
                           },
                           acc);

@@ -216,6 +216,25 @@ def test_all_dofs_fixed_is_a_no_op():
     np.testing.assert_array_equal(q1, case.q0)
 
 
+def test_shell_count_limit():
+    """One context holds at most as many shells as CG blocks can be resident
+    at once (each shell needs its own block); beyond that creation fails
+    cleanly with SHELL_E_INVAL, at the limit it works."""
+    sh = S()
+    ok = sh.context_for([W.sheet_case(1)])
+    ok.close()
+    limit = None
+    for n in (4096, 8192, 16384):
+        try:
+            ctx = sh.context_for([W.sheet_case(1)] * n)
+            ctx.close()
+        except sh.ShellError as e:
+            assert e.status == sh.SHELL_E_INVAL and "too many shells" in str(e)
+            limit = n
+            break
+    assert limit is not None, "no shell-count limit reached"
+
+
 def test_nonfinite_state_reported():
     case = W.sheet_case(2)
     q = case.q0.copy()
