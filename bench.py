@@ -207,43 +207,95 @@ def roofline(case, timing, fp32):
                  "traffic": None, "avg_launch_ms": per_launch_ms}
 
 
-def post_buckling_section(stream, steps=3, before=300):
-    """Newton-step time of the 256x256 cylinder after `before` steps of
-    compression (past buckling), FP64, CG layout autotuned; the steps before
-    are not timed."""
+def pseudo_hessian_section(stream, steps=3, warmup=1):
+    """Exact vs pseudo Hessian (the bending geometric term dropped) on the
+    256x256 cylinder, FP64: Newton and CG iterations and time per step."""
     import torch
     from paper_2312_14839_amd import shell as S, workloads as W
     case = W.case_cylinder(256, 256)
-    ctx = S.context_for([case], precision=S.SHELL_FP64, stream=stream, newton_rtol=1e-10, pcg_rtol=1e-8)
-    ctx.autotune(100)
-    q = torch.from_numpy(case.q0.reshape(-1).copy()).cuda()
-    v = torch.zeros_like(q)
-    q1, v1 = torch.empty_like(q), torch.empty_like(q)
+    out = {}
+    for name, hess in (("exact", S.SHELL_HESS_EXACT), ("pseudo", S.SHELL_HESS_PSEUDO)):
+        ctx = S.context_for([case], precision=S.SHELL_FP64, hessian=hess, stream=stream, newton_rtol=1e-10,
+                            pcg_rtol=1e-8)
+        ctx.autotune(100)
+        presc = [torch.from_numpy(case.presc((k + 1) * case.dt).reshape(-1).copy()).cuda()
+                 for k in range(warmup + steps)]
+        q = torch.from_numpy(case.q0.reshape(-1).copy()).cuda()
+        v = torch.zeros_like(q)
+        q1, v1 = torch.empty_like(q), torch.empty_like(q)
+        stats, t0 = [], 0.0
+        for k in range(warmup + steps):
+            if k == warmup:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            rc, st = ctx.newton_step(case.dt, q, v, presc[k], q1, v1, allow_fail=True)
+            if rc != S.SHELL_OK:
+                raise RuntimeError(f"{name} Hessian: step {k + 1} failed: {S.STATUS_NAMES.get(rc)}")
+            if k >= warmup:
+                stats.append(st[0])
+            q, q1 = q1, q
+            v, v1 = v1, v
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[name] = {"ms_per_step": 1e3 * wall / steps,
+                     "newton_iters_per_step": sum(s["newton_iters"] for s in stats) / steps,
+                     "cg_iters_per_step": sum(s["pcg_iters_total"] for s in stats) / steps,
+                     "ls_backtracks_per_step": sum(s["ls_backtracks"] for s in stats) / steps}
+        ctx.close()
+    print(f"[bench] exact vs pseudo Hessian: {out['exact']['ms_per_step']:.2f} vs {out['pseudo']['ms_per_step']:.2f} "
+          f"ms/step", file=sys.stderr, flush=True)
+    return out
+
+
+def post_buckling_section(stream, steps=3, before=300):
+    """Newton-step time of the 256x256 cylinder after `before` steps of
+    compression (past buckling), FP64, CG layout autotuned, with the exact
+    and with the pseudo Hessian from the same state; the steps before are
+    not timed."""
+    import torch
+    from paper_2312_14839_amd import shell as S, workloads as W
+    case = W.case_cylinder(256, 256)
     presc = [torch.from_numpy(case.presc((k + 1) * case.dt).reshape(-1).copy()).cuda()
              for k in range(before + steps)]
-    stats = []
-    t0 = 0.0
-    for k in range(before + steps):
-        if k == before:
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-        rc, st = ctx.newton_step(case.dt, q, v, presc[k], q1, v1, allow_fail=True)
-        if rc != S.SHELL_OK:
-            raise RuntimeError(f"post-buckling run: step {k + 1} failed: {S.STATUS_NAMES.get(rc)}")
-        if k >= before:
+
+    def run(ctx, q, v, k0, k1):
+        q1, v1 = torch.empty_like(q), torch.empty_like(q)
+        stats = []
+        for k in range(k0, k1):
+            rc, st = ctx.newton_step(case.dt, q, v, presc[k], q1, v1, allow_fail=True)
+            if rc != S.SHELL_OK:
+                raise RuntimeError(f"post-buckling run: step {k + 1} failed: {S.STATUS_NAMES.get(rc)}")
             stats.append(st[0])
-        q, q1 = q1, q
-        v, v1 = v1, v
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    qn = q.cpu().numpy().reshape(-1, 12)
-    ctx.close()
-    out = {"steps_before": before, "steps": steps, "ms_per_step": 1e3 * wall / steps,
-           "newton_iters_per_step": sum(s["newton_iters"] for s in stats) / steps,
-           "cg_iters_per_step": sum(s["pcg_iters_total"] for s in stats) / steps,
-           "patch_evals_per_s": case.patches * sum(s["newton_iters"] for s in stats) / wall,
+            q, q1 = q1, q
+            v, v1 = v1, v
+        return q, v, stats
+
+    ctx = S.context_for([case], precision=S.SHELL_FP64, stream=stream, newton_rtol=1e-10, pcg_rtol=1e-8)
+    ctx.autotune(100)
+    q0 = torch.from_numpy(case.q0.reshape(-1).copy()).cuda()
+    qb, vb, _ = run(ctx, q0, torch.zeros_like(q0), 0, before)
+    qn = qb.cpu().numpy().reshape(-1, 12)
+    out = {"steps_before": before, "steps": steps,
            "max_radial_deviation_m": float(np.abs(np.hypot(qn[:, 0], qn[:, 1]) - 0.2).max())}
-    print(f"[bench] post-buckling (after {before} steps): {out['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
+    for name, hess in (("exact", S.SHELL_HESS_EXACT), ("pseudo", S.SHELL_HESS_PSEUDO)):
+        if hess != S.SHELL_HESS_EXACT:
+            ctx.close()
+            ctx = S.context_for([case], precision=S.SHELL_FP64, hessian=hess, stream=stream, newton_rtol=1e-10,
+                                pcg_rtol=1e-8)
+            ctx.autotune(100)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, stats = run(ctx, qb.clone(), vb.clone(), before, before + steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[name] = {"ms_per_step": 1e3 * wall / steps,
+                     "newton_iters_per_step": sum(s["newton_iters"] for s in stats) / steps,
+                     "cg_iters_per_step": sum(s["pcg_iters_total"] for s in stats) / steps,
+                     "ls_backtracks_per_step": sum(s["ls_backtracks"] for s in stats) / steps,
+                     "patch_evals_per_s": case.patches * sum(s["newton_iters"] for s in stats) / wall}
+    ctx.close()
+    print(f"[bench] post-buckling (after {before} steps): exact {out['exact']['ms_per_step']:.2f}, pseudo "
+          f"{out['pseudo']['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
     return out
 
 
@@ -323,6 +375,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-post-buckling", action="store_true")
+    ap.add_argument("--no-pseudo", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="first run a plain device copy of MB megabytes (counter calibration)")
     args = ap.parse_args()
@@ -385,6 +438,8 @@ def main():
         print(f"[bench] mixed: {1e3 * wallm / args.steps:.2f} ms/step, err {err:.2e}", file=sys.stderr, flush=True)
     if args.workload == "cylinder" and not args.no_post_buckling:
         out["post_buckling"] = post_buckling_section(stream)
+    if args.workload == "cylinder" and not args.no_pseudo:
+        out["hessian_variants"] = pseudo_hessian_section(stream)
     if not args.no_learned:
         out["learned"] = learned_section(stream)
     if not args.no_cpu_baseline:
