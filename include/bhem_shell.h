@@ -71,6 +71,9 @@ typedef struct {
     double young, poisson;       /* Y > 0, 0 <= nu < 0.5; lambda = Y nu/(1 - nu^2), mu = Y/(2(1 + nu)) */
     double thickness, density;   /* h > 0, rho > 0 */
     double gravity[3];           /* areal dead load rho h g (Sec. 4.3, "External Forces") */
+    double damping;              /* mass-proportional Rayleigh coefficient alpha >= 0 [1/s]: damping
+                                    force -alpha M qdot in the Newton steps (Table 2 lists a Rayleigh
+                                    coefficient without its form; this is the mass-proportional reading) */
 } shell_desc;
 
 typedef struct {
@@ -171,6 +174,20 @@ shell_status shell_pcg_solve(shell_ctx *c, const double *b_dev, double *x_dev, d
 shell_status shell_newton_step(shell_ctx *c, double dt, const double *q_n_dev, const double *v_n_dev,
                                const double *q_presc_dev, double *q_np1_dev, double *v_np1_dev,
                                shell_step_stats *stats_host);
+
+/* External nodal generalized forces f_dev[total_nodes][12] (device, copied;
+ * NULL clears them), added to the areal gravity load of every later
+ * shell_newton_step: the incremental potential gains -f^T (q - qhat).  On
+ * prescribed DOFs they have no effect.  A point force at a parameter point
+ * is the vector shell_point_load builds (Sec. 4.3, "External Forces"). */
+shell_status shell_set_nodal_forces(shell_ctx *c, const double *f_dev);
+
+/* Consistent nodal load of a point force: adds Phi^I(xi) force into the
+ * host array f_nodal[nodes of this shell][12] for the 16 shape functions of
+ * the patch containing (xi1, xi2) (parameter coordinates in [0, n1 dxi1] x
+ * [0, n2 dxi2]; xi1 taken modulo n1 dxi1 for a periodic shell), so that
+ * f_nodal . q equals force . x(xi) for every state q.  Needs no context. */
+shell_status shell_point_load(const shell_desc *d, double xi1, double xi2, const double *force, double *f_nodal);
 
 /* Device-time accounting per kernel group, measured with HIP events on the
  * context's stream (adds a stream synchronisation after each timed launch,

@@ -25,6 +25,7 @@ struct Shell {
     double dxi1, dxi2;       // parameter-space cell size
     double young, poisson, thickness, density;
     double gravity[3];
+    double damping;          // mass-proportional Rayleigh coefficient alpha [1/s]: force -alpha M qdot
 };
 
 // Lame parameters as the paper states them (Sec. 3.3, "Energies"):

@@ -118,9 +118,9 @@ void orc_matrix_dense(const Shell* s, const double* q, const double* qb, int whi
 }
 
 int orc_newton_step(const Shell* s, const double* qb, const uint8_t* fixed, double dt, const double* qn,
-                    const double* vn, const double* qpresc, const NewtonOpts* o, double* qn1, double* vn1,
-                    NewtonStats* st) {
-    return newton_step(*s, qb, fixed, dt, qn, vn, qpresc, *o, qn1, vn1, st);
+                    const double* vn, const double* qpresc, const double* f_ext, const NewtonOpts* o, double* qn1,
+                    double* vn1, NewtonStats* st) {
+    return newton_step(*s, qb, fixed, dt, qn, vn, qpresc, f_ext, *o, qn1, vn1, st);
 }
 
 // Solve (K + mass_scale M) x = b with fixed DOFs replaced by identity rows

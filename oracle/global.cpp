@@ -297,40 +297,54 @@ int block_jacobi_cg(const NodeBlocks& A, const double* b, double* x, double rtol
 // ----------------------------------------------------------- Newton step
 namespace {
 
+// Incremental potential of one implicit-Euler step with mass-proportional
+// Rayleigh damping (damping force -alpha M qdot, qdot = (q - q_n)/dt):
+//   E(q) = (1/2dt^2)(q - qhat)^T M (q - qhat) + (alpha/2dt)(q - q_n)^T M (q - q_n)
+//          + V(q) - f^T (q - qhat),   f = areal gravity + external nodal forces,
+// whose stationarity is M(q - qhat)/dt^2 + alpha M (q - q_n)/dt + grad V = f.
 struct Problem {
     const Shell& s;
     const double* qb;
     const uint8_t* fixed;
     double dt;
+    const double* qn = nullptr;
     std::vector<double> qhat, f;
     NodeBlocks M;
-    Problem(const Shell& sh, const double* qbar, const uint8_t* fx, double dt_)
+    Problem(const Shell& sh, const double* qbar, const uint8_t* fx, double dt_, const double* f_ext)
         : s(sh), qb(qbar), fixed(fx), dt(dt_), M(sh) {
         assemble_mass(s, qb, M, 1.0);
         f.resize(12 * num_nodes(s));
         gravity_load(s, qb, f.data());
+        if (f_ext)
+            for (size_t i = 0; i < f.size(); ++i) f[i] += f_ext[i];
     }
     int n() const { return 12 * num_nodes(s); }
     bool is_fixed(int i) const { return fixed && fixed[i]; }
     // E(q), grad E(q) (zero on fixed DOFs) and |E| terms for the noise floor.
     double eval(const double* q, double* g, double* scale) {
         const int nd = n();
-        std::vector<double> dq(nd), Mdq(nd);
-        for (int i = 0; i < nd; ++i) dq[i] = q[i] - qhat[i];
+        std::vector<double> dq(nd), Mdq(nd), dn(nd), Mdn(nd);
+        for (int i = 0; i < nd; ++i) {
+            dq[i] = q[i] - qhat[i];
+            dn[i] = q[i] - qn[i];
+        }
         M.matvec(dq.data(), Mdq.data());
-        double ekin = 0, egrav = 0;
+        M.matvec(dn.data(), Mdn.data());
+        const double c_damp = s.damping / dt;
+        double ekin = 0, edamp = 0, egrav = 0;
         for (int i = 0; i < nd; ++i) {
             ekin += 0.5 * dq[i] * Mdq[i] / (dt * dt);
+            edamp += 0.5 * c_damp * dn[i] * Mdn[i];
             egrav -= f[i] * dq[i];
         }
         double eel = energy(s, q, qb);
         gradient(s, q, qb, g);
         for (int i = 0; i < nd; ++i) {
-            g[i] += Mdq[i] / (dt * dt) - f[i];
+            g[i] += Mdq[i] / (dt * dt) + c_damp * Mdn[i] - f[i];
             if (is_fixed(i)) g[i] = 0.0;
         }
-        if (scale) *scale = std::fabs(eel) + std::fabs(ekin) + std::fabs(egrav);
-        return eel + ekin + egrav;
+        if (scale) *scale = std::fabs(eel) + std::fabs(ekin) + std::fabs(edamp) + std::fabs(egrav);
+        return eel + ekin + edamp + egrav;
     }
 };
 
@@ -343,8 +357,10 @@ double norm2(const std::vector<double>& v) {
 }  // namespace
 
 int newton_step(const Shell& s, const double* qb, const uint8_t* fixed, double dt, const double* qn, const double* vn,
-                const double* qpresc, const NewtonOpts& o, double* qn1, double* vn1, NewtonStats* st) {
-    Problem P(s, qb, fixed, dt);
+                const double* qpresc, const double* f_ext, const NewtonOpts& o, double* qn1, double* vn1,
+                NewtonStats* st) {
+    Problem P(s, qb, fixed, dt, f_ext);
+    P.qn = qn;
     const int n = P.n();
     P.qhat.resize(n);
     for (int i = 0; i < n; ++i) P.qhat[i] = qn[i] + dt * vn[i];
@@ -384,13 +400,15 @@ int newton_step(const Shell& s, const double* qb, const uint8_t* fixed, double d
             break;
         }
         if (k == o.newton_maxit) break;
-        // A = M/dt^2 + K(q); the solve sees identity rows and columns on fixed DOFs.
+        // A = (1/dt^2 + alpha/dt) M + K(q); the solve sees identity rows and
+        // columns on fixed DOFs.
         NodeBlocks A(s);
         assemble_hessian(s, q.data(), qb, o.pseudo, A, 1.0);
+        const double mcoef = 1.0 / (dt * dt) + s.damping / dt;
         for (int r = 0; r < A.nn; ++r)
             for (auto& e : A.rows[r]) {
                 const double* m = P.M.find(r, e.col);
-                for (int t = 0; t < 144; ++t) e.v[t] += m[t] / (dt * dt);
+                for (int t = 0; t < 144; ++t) e.v[t] += m[t] * mcoef;
             }
         Aprev = A;
         have_prev = true;

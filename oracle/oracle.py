@@ -26,7 +26,7 @@ class Shell(C.Structure):
         ("dxi1", C.c_double), ("dxi2", C.c_double),
         ("young", C.c_double), ("poisson", C.c_double),
         ("thickness", C.c_double), ("density", C.c_double),
-        ("gravity", C.c_double * 3),
+        ("gravity", C.c_double * 3), ("damping", C.c_double),
     ]
 
 
@@ -75,7 +75,7 @@ def _load(path=_LIB_PATH):
                                       C.POINTER(C.c_int), C.POINTER(C.c_int), d]
     lib.orc_matrix_blocks.restype = C.c_int
     lib.orc_matrix_dense.argtypes = [sp, d, d, C.c_int, C.c_int, d]
-    lib.orc_newton_step.argtypes = [sp, d, C.POINTER(C.c_uint8), C.c_double, d, d, d,
+    lib.orc_newton_step.argtypes = [sp, d, C.POINTER(C.c_uint8), C.c_double, d, d, d, d,
                                     C.POINTER(NewtonOpts), d, d, C.POINTER(NewtonStats)]
     lib.orc_newton_step.restype = C.c_int
     lib.orc_linear_solve.argtypes = [sp, d, d, C.POINTER(C.c_uint8), C.c_double, C.c_int, d, d,
@@ -103,8 +103,9 @@ def _f64(a):
 
 
 def make_shell(n1, n2, dxi1, dxi2, young, poisson, thickness, density,
-               gravity=(0.0, 0.0, 0.0), periodic1=0):
+               gravity=(0.0, 0.0, 0.0), periodic1=0, damping=0.0):
     s = Shell()
+    s.damping = float(damping)
     s.n1, s.n2, s.periodic1 = int(n1), int(n2), int(periodic1)
     s.dxi1, s.dxi2 = float(dxi1), float(dxi2)
     s.young, s.poisson, s.thickness, s.density = float(young), float(poisson), float(thickness), float(density)
@@ -116,7 +117,7 @@ def make_shell(n1, n2, dxi1, dxi2, young, poisson, thickness, density,
 def shell_from_case(case):
     """Oracle shell description from a workload case (see the package's workloads module)."""
     return make_shell(case.n1, case.n2, case.dxi1, case.dxi2, case.young, case.poisson,
-                      case.thickness, case.density, case.gravity, case.periodic1)
+                      case.thickness, case.density, case.gravity, case.periodic1, getattr(case, "damping", 0.0))
 
 
 # ------------------------------------------------------------------ basis
@@ -245,9 +246,12 @@ def matrix_dense(shell, q, qb, which="hessian", pseudo=False):
 
 
 def newton_step(shell, qb, fixed, dt, qn, vn, qpresc=None, solver="ldlt", pseudo=False,
-                newton_rtol=1e-10, newton_maxit=50, pcg_rtol=1e-10, pcg_maxit=100000):
-    """One implicit-Euler step.  Returns (status, q_next, v_next, stats dict)."""
+                newton_rtol=1e-10, newton_maxit=50, pcg_rtol=1e-10, pcg_maxit=100000, f_ext=None):
+    """One implicit-Euler step (mass-proportional damping from shell.damping,
+    optional external nodal forces f_ext [nodes, 12]).  Returns (status,
+    q_next, v_next, stats dict)."""
     qb, qn, vn = _f64(qb), _f64(qn), _f64(vn)
+    fe = _f64(f_ext) if f_ext is not None else None
     fx = np.ascontiguousarray(fixed, dtype=np.uint8) if fixed is not None else None
     qp = _f64(qpresc) if qpresc is not None else None
     o = NewtonOpts(0 if solver == "ldlt" else 1, int(pseudo), int(newton_maxit), float(newton_rtol),
@@ -257,7 +261,7 @@ def newton_step(shell, qb, fixed, dt, qn, vn, qpresc=None, solver="ldlt", pseudo
     rc = lib().orc_newton_step(C.byref(shell), _d(qb),
                                fx.ctypes.data_as(C.POINTER(C.c_uint8)) if fx is not None else None,
                                float(dt), _d(qn), _d(vn), _d(qp) if qp is not None else None,
-                               C.byref(o), _d(q1), _d(v1), C.byref(st))
+                               _d(fe) if fe is not None else None, C.byref(o), _d(q1), _d(v1), C.byref(st))
     stats = {k: getattr(st, k) for k, _ in NewtonStats._fields_ if k != "pad"}
     return rc, q1, v1, stats
 

@@ -50,7 +50,10 @@ struct NewtonStats {
 // Converged when ||g_k|| <= max(newton_rtol ||g_0||, 4 eps || P_free |A_{k-1}| |q_k| ||).
 // Returns 0 converged, 1 Newton iteration cap, 2 line search failed,
 // 3 no positive definite system within the regulariser cap.
+// f_ext (nullable): external nodal generalized forces [nodes][12], added to
+// the areal gravity load.
 int newton_step(const Shell& s, const double* qb, const uint8_t* fixed, double dt, const double* qn, const double* vn,
-                const double* qpresc, const NewtonOpts& o, double* qn1, double* vn1, NewtonStats* st);
+                const double* qpresc, const double* f_ext, const NewtonOpts& o, double* qn1, double* vn1,
+                NewtonStats* st);
 
 }  // namespace orc

@@ -12,6 +12,7 @@ struct ShellParams {
     double lam, mu, h;       // plane-stress lambda = Y nu/(1 - nu^2), mu = Y/(2(1 + nu)), thickness
     double rho_h;            // areal density
     double grav[3];
+    double damp;             // mass-proportional Rayleigh coefficient alpha [1/s]
     int32_t node_begin, node_end;
     int32_t patch_begin, patch_end;
 };

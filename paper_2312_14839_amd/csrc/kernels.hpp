@@ -10,8 +10,8 @@ namespace bhem {
 // ------------------------------------------------------- patch kernels
 void launch_energy_grad(hipStream_t st, int npatch, const int4* patch_nodes, const int* patch_shell,
                         const ShellParams* shells, const double* phi, const double* q, const double* qbar,
-                        const double* qhat, double mass_scale, int elastic, int loads, double* e_patch,
-                        double* g_patch);
+                        const double* qhat, double mass_scale, double dt_damp, int elastic, int loads,
+                        double* e_patch, double* g_patch);
 void launch_gather_grad(hipStream_t st, int nnodes, const int* inc_ptr, const int* inc, const double* g_patch,
                         const uint16_t* freemask, const int* node_shell, const int* write_shell, double* grad);
 void launch_shell_energy(hipStream_t st, int nshell, const ShellParams* shells, const double* e_patch,
@@ -19,8 +19,8 @@ void launch_shell_energy(hipStream_t st, int nshell, const ShellParams* shells, 
 template <class T>
 void launch_hessian(hipStream_t st, const int* patch_list, int nlist, const int4* patch_nodes, const int* patch_shell,
                     const int* patch_slots, const uint16_t* patch_first, const ShellParams* shells,
-                    const double* phi, const double* q, const double* qbar, double mass_scale, int elastic,
-                    int pseudo, T* vals);
+                    const double* phi, const double* q, const double* qbar, double mass_scale, double dt_damp,
+                    int elastic, int pseudo, T* vals);
 
 // ------------------------------------------------------ solver kernels
 // Row partition of the node rows into blocks that never straddle a shell;
@@ -69,8 +69,17 @@ void launch_shell_dot(hipStream_t st, const RowBlocks& rb, int nshell, const dou
                       const uint16_t* freemask, double* partial, double* out);
 
 // elementwise helpers
+// qhat = q_n + dt v_n combined with q_n for mass-proportional damping:
+// (qhat + a q_n)/(1 + a), a = alpha dt of the node's shell; q = qhat on free
+// DOFs, the prescribed value (q_n if NULL) on the others
 void launch_predict(hipStream_t st, int n, const double* qn, const double* vn, const double* qpresc,
-                    const uint16_t* freemask, double dt, double* qhat, double* q);
+                    const uint16_t* freemask, const int* node_shell, const ShellParams* shells, double dt,
+                    double* qhat, double* q);
+// external nodal forces: grad -= f on free DOFs (rows of shells with
+// write_shell set, all if NULL) and e_shell[3s + 2] -= sum f.(q - qhat)
+void launch_nodal_load(hipStream_t st, const RowBlocks& rb, int nshell, const double* f, const double* q,
+                       const double* qhat, const uint16_t* freemask, const int* node_shell, const int* write_shell,
+                       double* grad, double* part, double* e_shell);
 void launch_axpy_shell(hipStream_t st, int nnodes, const double* x, const double* d, const double* alpha_shell,
                        const int* node_shell, double* out);
 void launch_neg_masked(hipStream_t st, int nnodes, const double* g, const uint16_t* freemask,

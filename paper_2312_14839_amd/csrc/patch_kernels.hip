@@ -35,8 +35,9 @@ __global__ __launch_bounds__(256) void k_energy_grad(int npatch, const int4* __r
                                                      const ShellParams* __restrict__ shells,
                                                      const double* __restrict__ phi,
                                                      const double* __restrict__ q, const double* __restrict__ qbar,
-                                                     const double* __restrict__ qhat, double mass_scale, int elastic,
-                                                     int loads, double* __restrict__ e_patch,
+                                                     const double* __restrict__ qhat, double mass_scale,
+                                                     double dt_damp, int elastic, int loads,
+                                                     double* __restrict__ e_patch,
                                                      double* __restrict__ g_patch) {
     __shared__ double s_u[EG_PATCHES][48], s_b[EG_PATCHES][48], s_d[EG_PATCHES][48];
     __shared__ double s_dpsi[EG_PATCHES][16][18];
@@ -64,6 +65,9 @@ __global__ __launch_bounds__(256) void k_energy_grad(int npatch, const int4* __r
         }
     }
     __syncthreads();
+    // inertia coefficient; with damping (Newton steps only) 1/dt^2 + alpha/dt,
+    // the predictor being the matching combination of qhat and q_n
+    const double ms = active ? mass_scale * (1.0 + sp.damp * dt_damp) : 0.0;
     // phase 1: lane = Gauss point
     double e_el = 0.0, e_kin = 0.0, e_ld = 0.0;
     if (active) {
@@ -105,11 +109,11 @@ __global__ __launch_bounds__(256) void k_energy_grad(int npatch, const int4* __r
         }
         const double rh = sp.rho_h * G.wq;
         const double gx = loads ? sp.grav[0] : 0.0, gy = loads ? sp.grav[1] : 0.0, gz = loads ? sp.grav[2] : 0.0;
-        s_dpsi[pl][g][15] = rh * (mass_scale * xd[0] - gx);
-        s_dpsi[pl][g][16] = rh * (mass_scale * xd[1] - gy);
-        s_dpsi[pl][g][17] = rh * (mass_scale * xd[2] - gz);
+        s_dpsi[pl][g][15] = rh * (ms * xd[0] - gx);
+        s_dpsi[pl][g][16] = rh * (ms * xd[1] - gy);
+        s_dpsi[pl][g][17] = rh * (ms * xd[2] - gz);
         e_el = el * G.wq * G.psi;
-        e_kin = 0.5 * mass_scale * rh * (xd[0] * xd[0] + xd[1] * xd[1] + xd[2] * xd[2]);
+        e_kin = 0.5 * ms * rh * (xd[0] * xd[0] + xd[1] * xd[1] + xd[2] * xd[2]);
         e_ld = -rh * (gx * xd[0] + gy * xd[1] + gz * xd[2]);
     }
     // patch energies: reduce over the 16 lanes of the patch
@@ -204,8 +208,8 @@ __global__ __launch_bounds__(256) void k_hessian(const int* __restrict__ patch_l
                                                  const uint16_t* __restrict__ patch_first,
                                                  const ShellParams* __restrict__ shells,
                                                  const double* __restrict__ phi, const double* __restrict__ q,
-                                                 const double* __restrict__ qbar, double mass_scale, int elastic,
-                                                 int pseudo, T* __restrict__ vals) {
+                                                 const double* __restrict__ qbar, double mass_scale,
+                                                 double dt_damp, int elastic, int pseudo, T* __restrict__ vals) {
     typedef Mfma<T> MM;
     constexpr int WSZ = 16 * 121;   // packed W per Gauss point (+ mass term) and pair staging (6*256)
     static_assert(WSZ >= 6 * 256, "staging must fit");
@@ -258,7 +262,7 @@ __global__ __launch_bounds__(256) void k_hessian(const int* __restrict__ patch_l
             for (int a = 0; a < 5; ++a) sc[a] = (T)slot_scale(a, sp.dxi1, sp.dxi2);
             hess_blocks<T>(G, quarter, pseudo, sc, Wg);
         }
-        if (quarter == 3) Wg[120] = G.wq * (T)(sp.rho_h * mass_scale);
+        if (quarter == 3) Wg[120] = G.wq * (T)(sp.rho_h * mass_scale * (1.0 + sp.damp * dt_damp));
     }
     __syncthreads();
     // phase 2: K^{ij} = sum over (slot a, Gauss point g) of Phi^T W^{ij} Phi on the matrix cores.
@@ -346,12 +350,12 @@ __global__ __launch_bounds__(256) void k_hessian(const int* __restrict__ patch_l
 // ------------------------------------------------------------ launchers
 void launch_energy_grad(hipStream_t st, int npatch, const int4* patch_nodes, const int* patch_shell,
                         const ShellParams* shells, const double* phi, const double* q, const double* qbar,
-                        const double* qhat, double mass_scale, int elastic, int loads, double* e_patch,
-                        double* g_patch) {
+                        const double* qhat, double mass_scale, double dt_damp, int elastic, int loads,
+                        double* e_patch, double* g_patch) {
     if (npatch == 0) return;
     const int nb = (npatch + EG_PATCHES - 1) / EG_PATCHES;
     hipLaunchKernelGGL(k_energy_grad, dim3(nb), dim3(256), 0, st, npatch, patch_nodes, patch_shell, shells, phi, q,
-                       qbar, qhat, mass_scale, elastic, loads, e_patch, g_patch);
+                       qbar, qhat, mass_scale, dt_damp, elastic, loads, e_patch, g_patch);
 }
 
 void launch_gather_grad(hipStream_t st, int nnodes, const int* inc_ptr, const int* inc, const double* g_patch,
@@ -370,19 +374,19 @@ void launch_shell_energy(hipStream_t st, int nshell, const ShellParams* shells, 
 template <class T>
 void launch_hessian(hipStream_t st, const int* patch_list, int nlist, const int4* patch_nodes, const int* patch_shell,
                     const int* patch_slots, const uint16_t* patch_first, const ShellParams* shells,
-                    const double* phi, const double* q, const double* qbar, double mass_scale, int elastic,
-                    int pseudo, T* vals) {
+                    const double* phi, const double* q, const double* qbar, double mass_scale, double dt_damp,
+                    int elastic, int pseudo, T* vals) {
     if (nlist == 0) return;
     const int nb = (nlist + HS_WAVES - 1) / HS_WAVES;
     hipLaunchKernelGGL(k_hessian<T>, dim3(nb), dim3(256), 0, st, patch_list, nlist, patch_nodes, patch_shell,
-                       patch_slots, patch_first, shells, phi, q, qbar, mass_scale, elastic, pseudo, vals);
+                       patch_slots, patch_first, shells, phi, q, qbar, mass_scale, dt_damp, elastic, pseudo, vals);
 }
 
 template void launch_hessian<double>(hipStream_t, const int*, int, const int4*, const int*, const int*,
                                      const uint16_t*, const ShellParams*, const double*, const double*,
-                                     const double*, double, int, int, double*);
+                                     const double*, double, double, int, int, double*);
 template void launch_hessian<float>(hipStream_t, const int*, int, const int4*, const int*, const int*,
                                     const uint16_t*, const ShellParams*, const double*, const double*,
-                                    const double*, double, int, int, float*);
+                                    const double*, double, double, int, int, float*);
 
 }  // namespace bhem

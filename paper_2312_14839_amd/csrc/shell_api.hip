@@ -102,6 +102,11 @@ struct shell_ctx {
             g->exec = nullptr;
         }
     }
+    // damping enters the inertia term of Newton steps only: dt there, 0 otherwise
+    double dt_damp = 0.0;
+    // external nodal forces (shell_set_nodal_forces)
+    DevBuf fext;
+    bool has_fext = false;
     // event timing
     bool timing = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -258,6 +263,7 @@ void validate(const shell_desc& d, int s) {
     if ((long long)d.n1 * d.n2 > (1 << 26)) bad("grid too large");
     for (int k = 0; k < 3; ++k)
         if (!std::isfinite(d.gravity[k])) bad("gravity not finite");
+    if (!(d.damping >= 0) || !std::isfinite(d.damping)) bad("damping must be finite and >= 0");
     const int nn = node_count(d);
     for (long long i = 0; i < 12LL * nn; ++i)
         if (!std::isfinite(d.ref_host[i])) bad("reference coordinates not finite");
@@ -337,6 +343,7 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
         sp.h = d.thickness;
         sp.rho_h = d.density * d.thickness;
         for (int k = 0; k < 3; ++k) sp.grav[k] = d.gravity[k];
+        sp.damp = d.damping;
         sp.node_begin = N;
         N += node_count(d);
         sp.node_end = N;
@@ -542,12 +549,16 @@ void eval_energy_grad(shell_ctx* c, const double* q_in, const double* qhat, doub
     GroupTimer tmr(c, SHELL_T_ENERGY_GRAD);
     launch_energy_grad(st, c->P, dptr<int4>(c->patch_nodes), dptr<int>(c->patch_shell),
                        dptr<ShellParams>(c->shells_d), dptr<double>(c->phi), q_in, dptr<double>(c->qbar), qhat,
-                       mass_scale, 1, loads, dptr<double>(c->e_patch), dptr<double>(c->g_patch));
+                       mass_scale, c->dt_damp, 1, loads, dptr<double>(c->e_patch), dptr<double>(c->g_patch));
     launch_shell_energy(st, c->S, dptr<ShellParams>(c->shells_d), dptr<double>(c->e_patch), dptr<double>(c->e_shell));
     if (grad_out)
         launch_gather_grad(st, c->N, dptr<int>(c->inc_ptr), dptr<int>(c->inc), dptr<double>(c->g_patch),
                            masked ? dptr<uint16_t>(c->freemask) : nullptr, dptr<int>(c->node_shell), write_shell_dev,
                            grad_out);
+    if (loads && c->has_fext && qhat)
+        launch_nodal_load(st, c->rb(), c->S, dptr<double>(c->fext), q_in, qhat, dptr<uint16_t>(c->freemask),
+                          dptr<int>(c->node_shell), write_shell_dev, grad_out, dptr<double>(c->red_part),
+                          dptr<double>(c->e_shell));
     HIPCHK(hipGetLastError());
     tmr.stop();
     HIPCHK(hipMemcpyAsync(c->h_e_shell, c->e_shell.p, (size_t)c->S * 3 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -570,11 +581,12 @@ void assemble(shell_ctx* c, const double* q_in, double mass_scale, int elastic) 
         if (c->fp32)
             launch_hessian<float>(st, list, n, dptr<int4>(c->patch_nodes), dptr<int>(c->patch_shell),
                                   dptr<int>(c->patch_slots), dptr<uint16_t>(c->patch_first), dptr<ShellParams>(c->shells_d), dptr<double>(c->phi), q_in,
-                                  dptr<double>(c->qbar), mass_scale, elastic, pseudo, dptr<float>(c->vals));
+                                  dptr<double>(c->qbar), mass_scale, c->dt_damp, elastic, pseudo, dptr<float>(c->vals));
         else
             launch_hessian<double>(st, list, n, dptr<int4>(c->patch_nodes), dptr<int>(c->patch_shell),
                                    dptr<int>(c->patch_slots), dptr<uint16_t>(c->patch_first), dptr<ShellParams>(c->shells_d), dptr<double>(c->phi),
-                                   q_in, dptr<double>(c->qbar), mass_scale, elastic, pseudo, dptr<double>(c->vals));
+                                   q_in, dptr<double>(c->qbar), mass_scale, c->dt_damp, elastic, pseudo,
+                                   dptr<double>(c->vals));
     }
     HIPCHK(hipGetLastError());
     tmr.stop();
@@ -1172,6 +1184,12 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
     }
     API_TRY
     HIPCHK(hipSetDevice(c->opts.device));
+    // damping acts on the inertia term of this step only
+    struct DampScope {
+        shell_ctx* c;
+        ~DampScope() { c->dt_damp = 0.0; }
+    } damp_scope{c};
+    c->dt_damp = dt;
     const double t_start = now_ms();
     const int S = c->S, N12 = c->N * 12;
     hipStream_t st = c->stream;
@@ -1185,7 +1203,8 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
     double* qhat = dptr<double>(c->qhat);
     std::vector<shell_step_stats> stats(S);
     std::memset(stats.data(), 0, sizeof(shell_step_stats) * S);
-    launch_predict(st, N12, q_n_dev, v_n_dev, q_presc_dev, dptr<uint16_t>(c->freemask), dt, qhat, q);
+    launch_predict(st, N12, q_n_dev, v_n_dev, q_presc_dev, dptr<uint16_t>(c->freemask), dptr<int>(c->node_shell),
+                   dptr<ShellParams>(c->shells_d), dt, qhat, q);
     HIPCHK(hipGetLastError());
     // E, g at the initial guess
     eval_energy_grad(c, q, qhat, ms, 1, true, g, nullptr);
@@ -1442,6 +1461,51 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
     if (worst != SHELL_OK) c->err = "Newton step did not converge for every shell (see stats)";
     return worst;
     API_CATCH
+}
+
+// ------------------------------------------------------------ loads
+shell_status shell_set_nodal_forces(shell_ctx* c, const double* f_dev) {
+    if (!c) return SHELL_E_INVAL;
+    API_TRY
+    HIPCHK(hipSetDevice(c->opts.device));
+    if (!f_dev) {
+        c->has_fext = false;
+        return SHELL_OK;
+    }
+    if (!c->fext.p) alloc(c->fext, (size_t)c->N * 12 * sizeof(double));
+    HIPCHK(hipMemcpyAsync(c->fext.p, f_dev, c->fext.n, hipMemcpyDeviceToDevice, c->stream));
+    sync(c);
+    c->has_fext = true;
+    c->graphs_reset();   // the captured evaluations gain the load kernels
+    return SHELL_OK;
+    API_CATCH
+}
+
+shell_status shell_point_load(const shell_desc* d, double xi1, double xi2, const double* force, double* f_nodal) {
+    if (!d || !force || !f_nodal || d->n1 < 1 || d->n2 < 1 || !(d->dxi1 > 0) || !(d->dxi2 > 0) ||
+        (d->periodic1 && d->n1 < 3) || !std::isfinite(xi1) || !std::isfinite(xi2))
+        return SHELL_E_INVAL;
+    const double L1 = d->n1 * d->dxi1, L2 = d->n2 * d->dxi2;
+    if (d->periodic1) xi1 -= L1 * std::floor(xi1 / L1);
+    if (xi1 < 0 || xi1 > L1 || xi2 < 0 || xi2 > L2) return SHELL_E_INVAL;
+    const int i = std::min((int)(xi1 / d->dxi1), d->n1 - 1), j = std::min((int)(xi2 / d->dxi2), d->n2 - 1);
+    const double t1 = xi1 / d->dxi1 - i, t2 = xi2 / d->dxi2 - j;
+    const int cols = d->periodic1 ? d->n1 : d->n1 + 1;
+    for (int c = 0; c < 4; ++c) {
+        const int p = c & 1, q = c >> 1;
+        int ni = i + p;
+        if (d->periodic1) ni %= d->n1;
+        const int node = (j + q) * cols + ni;
+        for (int k = 0; k < 4; ++k) {
+            const int r = k & 1, s = k >> 1;
+            // value of the shape function of corner c, kind k (derivative DOFs
+            // are xi-derivatives, hence the dxi powers)
+            const double phi = hermite(p, r, 0, t1) * hermite(q, s, 0, t2) * (r ? d->dxi1 : 1.0) *
+                               (s ? d->dxi2 : 1.0);
+            for (int comp = 0; comp < 3; ++comp) f_nodal[(size_t)node * 12 + 3 * k + comp] += phi * force[comp];
+        }
+    }
+    return SHELL_OK;
 }
 
 // ------------------------------------------------------------ autotuner

@@ -575,13 +575,46 @@ __global__ void k_shell_dot_fin(int nshell, const int* __restrict__ shell_blk0, 
 
 // ------------------------------------------------------------ elementwise
 __global__ void k_predict(int n, const double* __restrict__ qn, const double* __restrict__ vn,
-                          const double* __restrict__ qpresc, const uint16_t* __restrict__ fm, double dt,
+                          const double* __restrict__ qpresc, const uint16_t* __restrict__ fm,
+                          const int* __restrict__ node_shell, const ShellParams* __restrict__ shells, double dt,
                           double* __restrict__ qhat, double* __restrict__ q) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     const double qh = qn[t] + dt * vn[t];
-    qhat[t] = qh;
+    const double a = shells[node_shell[t / 12]].damp * dt;
+    qhat[t] = a != 0.0 ? (qh + a * qn[t]) / (1.0 + a) : qh;
     q[t] = is_free(fm, t / 12, t % 12) ? qh : (qpresc ? qpresc[t] : qn[t]);
+}
+
+// External nodal forces (see launch_nodal_load).
+__global__ __launch_bounds__(256) void k_nodal_load_part(const int* __restrict__ blk_row0,
+                                                         const int* __restrict__ blk_row1, const double* __restrict__ f,
+                                                         const double* __restrict__ q, const double* __restrict__ qhat,
+                                                         const uint16_t* __restrict__ fm,
+                                                         const int* __restrict__ node_shell,
+                                                         const int* __restrict__ write_shell,
+                                                         double* __restrict__ grad, double* __restrict__ part) {
+    __shared__ double lds[4];
+    double s = 0.0;
+    const int r0 = blk_row0[blockIdx.x], r1 = blk_row1[blockIdx.x];
+    for (int e = r0 * 12 + threadIdx.x; e < r1 * 12; e += blockDim.x) {
+        const int node = e / 12;
+        if (!is_free(fm, node, e % 12)) continue;
+        s += f[e] * (q[e] - qhat[e]);
+        if (grad && (!write_shell || write_shell[node_shell[node]])) grad[e] -= f[e];
+    }
+    double v[1] = {s};
+    block_sum<1, 4>(v, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+__global__ void k_nodal_load_fin(int nshell, const int* __restrict__ shell_blk0, const int* __restrict__ shell_nblk,
+                                 const double* __restrict__ part, double* __restrict__ e_shell) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nshell) return;
+    double v = 0.0;
+    for (int i = 0; i < shell_nblk[s]; ++i) v += part[shell_blk0[s] + i];
+    e_shell[3 * s + 2] -= v;
 }
 
 __global__ void k_axpy_shell(int n, const double* __restrict__ x, const double* __restrict__ d,
@@ -727,8 +760,18 @@ void launch_shell_dot(hipStream_t st, const RowBlocks& rb, int nshell, const dou
 }
 
 void launch_predict(hipStream_t st, int n, const double* qn, const double* vn, const double* qpresc,
-                    const uint16_t* freemask, double dt, double* qhat, double* q) {
-    hipLaunchKernelGGL(k_predict, grid1(n), dim3(256), 0, st, n, qn, vn, qpresc, freemask, dt, qhat, q);
+                    const uint16_t* freemask, const int* node_shell, const ShellParams* shells, double dt,
+                    double* qhat, double* q) {
+    hipLaunchKernelGGL(k_predict, grid1(n), dim3(256), 0, st, n, qn, vn, qpresc, freemask, node_shell, shells, dt,
+                       qhat, q);
+}
+void launch_nodal_load(hipStream_t st, const RowBlocks& rb, int nshell, const double* f, const double* q,
+                       const double* qhat, const uint16_t* freemask, const int* node_shell, const int* write_shell,
+                       double* grad, double* part, double* e_shell) {
+    hipLaunchKernelGGL(k_nodal_load_part, dim3(rb.nblk), dim3(256), 0, st, rb.blk_row0, rb.blk_row1, f, q, qhat,
+                       freemask, node_shell, write_shell, grad, part);
+    hipLaunchKernelGGL(k_nodal_load_fin, grid1(nshell), dim3(256), 0, st, nshell, rb.shell_blk0, rb.shell_nblk,
+                       part, e_shell);
 }
 void launch_axpy_shell(hipStream_t st, int nnodes, const double* x, const double* d, const double* alpha_shell,
                        const int* node_shell, double* out) {

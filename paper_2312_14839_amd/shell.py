@@ -39,7 +39,7 @@ class shell_desc(C.Structure):
         ("ref_host", C.POINTER(C.c_double)), ("fixed_host", C.POINTER(C.c_uint8)),
         ("young", C.c_double), ("poisson", C.c_double),
         ("thickness", C.c_double), ("density", C.c_double),
-        ("gravity", C.c_double * 3),
+        ("gravity", C.c_double * 3), ("damping", C.c_double),
     ]
 
 
@@ -132,6 +132,10 @@ def _load():
     lib.shell_timing_enable.restype = C.c_int32
     lib.shell_timing_get.argtypes = [vp, P(shell_timing)]
     lib.shell_timing_get.restype = C.c_int32
+    lib.shell_set_nodal_forces.argtypes = [vp, vp]
+    lib.shell_set_nodal_forces.restype = C.c_int32
+    lib.shell_point_load.argtypes = [P(shell_desc), C.c_double, C.c_double, P(C.c_double), P(C.c_double)]
+    lib.shell_point_load.restype = C.c_int32
     lib.shell_autotune.argtypes = [vp, C.c_int32, P(shell_tune_result)]
     lib.shell_autotune.restype = C.c_int32
     lib.shell_mlp_set_params.argtypes = [vp, P(C.c_float)]
@@ -158,7 +162,8 @@ EXPORTED = ["shell_default_opts", "shell_create", "shell_destroy", "shell_last_e
             "shell_energy_grad_hess", "shell_assemble", "shell_get_bsr", "shell_spmv", "shell_pcg_solve",
             "shell_newton_step", "shell_timing_enable", "shell_timing_get", "shell_mlp_set_params",
             "shell_mlp_get_params", "shell_mlp_forward", "shell_mlp_loss_grad", "shell_mlp_train",
-            "shell_mlp_record", "shell_mlp_recorded", "shell_autotune"]
+            "shell_mlp_record", "shell_mlp_recorded", "shell_autotune", "shell_set_nodal_forces",
+            "shell_point_load"]
 
 MLP_IN, MLP_HIDDEN, MLP_OUT = 36, 128, 12
 MLP_PARAMS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_OUT + MLP_OUT
@@ -202,6 +207,7 @@ class ShellContext:
             d.thickness, d.density = float(cs.thickness), float(cs.density)
             for i in range(3):
                 d.gravity[i] = float(cs.gravity[i])
+            d.damping = float(getattr(cs, "damping", 0.0))
         o = default_opts()
         o.precision, o.hessian, o.warm_start = int(precision), int(hessian), int(warm_start)
         o.newton_rtol, o.pcg_rtol = float(newton_rtol), float(pcg_rtol)
@@ -281,6 +287,9 @@ class ShellContext:
         return rc, [s.as_dict() for s in st]
 
 
+    def set_nodal_forces(self, f):
+        self._check(lib.shell_set_nodal_forces(self.h, _ptr(f)))
+
     def autotune(self, cg_iters=100):
         r = shell_tune_result()
         self._check(lib.shell_autotune(self.h, int(cg_iters), C.byref(r)))
@@ -329,6 +338,21 @@ class ShellContext:
         t = shell_timing()
         self._check(lib.shell_timing_get(self.h, C.byref(t)))
         return t.as_dict()
+
+
+def point_load(case, xi1, xi2, force, f_nodal=None):
+    """Add the consistent nodal load of a point force at parameter point
+    (xi1, xi2) of `case` into f_nodal [nodes, 12] (new zeros if None)."""
+    d = shell_desc()
+    d.n1, d.n2, d.periodic1 = int(case.n1), int(case.n2), int(case.periodic1)
+    d.dxi1, d.dxi2 = float(case.dxi1), float(case.dxi2)
+    out = np.zeros((case.nodes, 12)) if f_nodal is None else f_nodal
+    assert out.dtype == np.float64 and out.flags["C_CONTIGUOUS"] and out.shape == (case.nodes, 12)
+    fv = (C.c_double * 3)(*[float(v) for v in force])
+    rc = lib.shell_point_load(C.byref(d), float(xi1), float(xi2), fv, out.ctypes.data_as(C.POINTER(C.c_double)))
+    if rc != SHELL_OK:
+        raise ShellError(rc, "point outside the shell's parameter domain or invalid descriptor")
+    return out
 
 
 def context_for(cases, **kw) -> ShellContext:

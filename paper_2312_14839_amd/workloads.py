@@ -52,6 +52,7 @@ class Case:
     dt: float
     # prescribed values of all DOFs at time t (only fixed entries are used)
     presc: Optional[Callable[[float], np.ndarray]] = None
+    damping: float = 0.0       # mass-proportional Rayleigh coefficient [1/s]
 
     @property
     def cols(self) -> int:

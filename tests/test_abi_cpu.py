@@ -75,3 +75,42 @@ def test_null_arguments():
     assert S.lib.shell_create(None, 1, None, C.byref(h)) == S.SHELL_E_INVAL
     S.lib.shell_destroy(None)   # NULL-safe
     assert S.lib.shell_energy_grad_hess(None, None, None, None, 0) == S.SHELL_E_INVAL
+
+
+def S():
+    from paper_2312_14839_amd import shell
+    return shell
+
+
+def test_point_load_is_the_consistent_nodal_load():
+    """shell_point_load (host code of the library, no GPU) against the
+    oracle's shape functions: f_I = Phi^I(xi) f on the 4 corner nodes of the
+    containing patch, and f_nodal . q = f . x(xi) for any state q."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_2312_14839_amd import workloads as W
+    from gpu_util import rect_sheet
+    rng = np.random.default_rng(4)
+    cases = [rect_sheet(5, 4, 0.93, 0.94), W.case_cylinder(7, 3)]
+    for case in cases:
+        s = O.shell_from_case(case)
+        L1, L2 = case.n1 * case.dxi1, case.n2 * case.dxi2
+        for _ in range(5):
+            xi1, xi2 = rng.uniform(0, L1), rng.uniform(0, L2)
+            f = rng.normal(size=3)
+            shift = L1 if case.periodic1 else 0.0          # a periodic shell wraps xi1
+            fn = S().point_load(case, xi1 + shift, xi2, f)
+            i, j = min(int(xi1 / case.dxi1), case.n1 - 1), min(int(xi2 / case.dxi2), case.n2 - 1)
+            t1, t2 = xi1 / case.dxi1 - i, xi2 / case.dxi2 - j
+            phi = O.shape_functions(t1, t2, case.dxi1, case.dxi2)[0]
+            exp = np.zeros_like(fn)
+            for c, node in enumerate(O.patch_nodes(s, i, j)):
+                for k in range(4):
+                    exp[node, 3 * k:3 * k + 3] += phi[4 * c + k] * f
+            np.testing.assert_allclose(fn, exp, rtol=0, atol=1e-13 * np.abs(f).max())   # wrap and formula rounding
+            q = case.ref + rng.normal(scale=1e-2, size=case.ref.shape)
+            x = sum(phi[4 * c + k] * q[node, 3 * k:3 * k + 3]
+                    for c, node in enumerate(O.patch_nodes(s, i, j)) for k in range(4))
+            assert abs(np.sum(fn * q) - f @ x) <= 1e-13 * max(1.0, abs(f @ x))
+    with pytest.raises(S().ShellError):
+        S().point_load(cases[0], -0.1, 0.2, (0, 0, 1))

@@ -177,6 +177,52 @@ def test_newton_free_fall_exact():
     np.testing.assert_allclose(q1[:, 3:], exp[:, 3:], rtol=0, atol=1e-10)
 
 
+def test_damped_free_fall_exact():
+    """Mass-proportional damping: v' = (v + dt g)/(1 + alpha dt) for a free,
+    undeformed sheet in uniform translation."""
+    case = W.sheet_case(3, edges=(), sigma=0.0)
+    case.damping = 7.5
+    v = np.zeros_like(case.ref)
+    v[:, 0:3] = (0.3, -0.2, 0.5)
+    case.v0 = v
+    case.q0 = case.ref.copy()
+    dt = 1e-2
+    rc, q1, v1, st = _newton_gpu(case, "fp64", dt=dt)
+    assert rc == 0 and st["newton_iters"] == 1
+    v_exp = (v[:, 0:3] + dt * np.array(case.gravity)) / (1.0 + case.damping * dt)
+    # CG to 1e-10 relative: positions to ~1e-13 m, velocities to that / dt
+    np.testing.assert_allclose(q1[:, 0:3], case.ref[:, 0:3] + dt * v_exp, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(v1[:, 0:3], v_exp, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(q1[:, 3:], case.ref[:, 3:], rtol=0, atol=1e-9)   # ill-conditioned mass rows
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("mixed", 1e-5)])
+def test_damping_and_point_force_match_oracle(precision, tol):
+    """8x8 sheet with Rayleigh damping and a point force at a parameter point
+    inside a patch (its consistent nodal load), three steps with the same
+    context (graphs replayed), each against the oracle's LDL^T Newton from
+    the GPU's previous state."""
+    sh = S()
+    case = W.case_small_sheet()
+    case.damping = 4.0
+    f = sh.point_load(case, 0.93, 0.41, (0.0, 0.0, 3e-3))
+    s = O.shell_from_case(case)
+    ctx = sh.context_for([case], precision=sh.SHELL_MIXED if precision == "mixed" else sh.SHELL_FP64)
+    ctx.set_nodal_forces(dev(f))
+    q, v = case.q0.copy(), case.v0.copy()
+    for k in range(3):
+        q1d, v1d = torch.zeros(case.nodes * 12, dtype=torch.float64, device="cuda"), \
+            torch.zeros(case.nodes * 12, dtype=torch.float64, device="cuda")
+        rc, st = ctx.newton_step(case.dt, dev(q), dev(v), None, q1d, v1d)
+        assert rc == 0
+        rc_o, q1o, v1o, st_o = O.newton_step(s, case.ref, case.fixed, case.dt, q, v, f_ext=f)
+        assert rc_o == 0
+        q1, v1 = host(q1d).reshape(-1, 12), host(v1d).reshape(-1, 12)
+        assert rel_disp_error(q1, q1o, q) <= tol
+        q, v = q1, v1
+    ctx.close()
+
+
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-8), ("mixed", 1e-5)])
 def test_newton_step_twist(precision, tol):
     case = W.case_twist(30)
