@@ -152,13 +152,18 @@ def qstate_after(case, precision, nsteps, stream, tol):
 
 
 def cg_bytes(case, timing, tm_bytes, tv_bytes):
-    """Algorithmic HBM bytes of the CG kernel: per iteration every block
-    non-zero (144 values + a column index), per node row its 12x12 inverse
-    diagonal block and 11 passes over 12-vectors (phase A reads z, p_old and
-    writes p_new, q; phase B reads r, q, p_new, x and writes x, r, z)."""
+    """Algorithmic HBM bytes of the CG kernel.  Per iteration: every stored
+    block (the diagonal and upper-triangle blocks: 144 values; off the
+    diagonal also a column and a slot index, and the 12-value transposed
+    product written to its slot in phase A and read back in phase B); per
+    node row its 12x12 inverse diagonal block, the row pointer, slot range
+    and free mask (10 bytes) and 11 passes over 12-vectors (phase A reads z,
+    p_old and writes p_new, q; phase B reads r, q, p_new, x and writes x, r,
+    z)."""
     blocks = timing["cg_iter_blocks"]
     rows = timing["cg_iter_rows"]
-    return blocks * (144 * tm_bytes + 4) + rows * (144 * tv_bytes + 4 + 11 * 12 * tv_bytes)
+    return (blocks * 144 * tm_bytes + (blocks - rows) * (8 + 24 * tv_bytes)
+            + rows * (144 * tv_bytes + 10 + 11 * 12 * tv_bytes))
 
 
 def profiled_traffic(case, fp32, kernel):

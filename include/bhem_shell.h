@@ -143,7 +143,11 @@ shell_status shell_assemble(shell_ctx *c, const double *q_dev, double mass_scale
 
 /* Copy shell s's part of the context's matrix to the host as BSR with local
  * node indices: row_ptr[nodes_s + 1], col_idx[nnzb_s], vals[nnzb_s][12][12]
- * (FP64 even in mixed precision).  Call with NULL arrays to get *nnzb only. */
+ * (FP64 even in mixed precision).  Call with NULL arrays to get *nnzb only.
+ * The device keeps the diagonal and upper-triangle blocks only (the Hessian
+ * is symmetric); the full pattern is returned, each block below the
+ * diagonal the transpose of its mirror image: exactly the matrix that
+ * shell_spmv and the CG apply. */
 shell_status shell_get_bsr(shell_ctx *c, int32_t shell, int32_t *nnzb, int32_t *row_ptr, int32_t *col_idx,
                            double *vals);
 

@@ -18,9 +18,9 @@ void launch_shell_energy(hipStream_t st, int nshell, const ShellParams* shells, 
                          double* e_shell);
 template <class T>
 void launch_hessian(hipStream_t st, const int* patch_list, int nlist, const int4* patch_nodes, const int* patch_shell,
-                    const int* patch_slots, const uint16_t* patch_first, const ShellParams* shells,
-                    const double* phi, const double* q, const double* qbar, double mass_scale, double dt_damp,
-                    int elastic, int pseudo, T* vals);
+                    const int* patch_slots, const uint64_t* patch_kid, const uint16_t* patch_first,
+                    const ShellParams* shells, const double* phi, const double* q, const double* qbar,
+                    double mass_scale, double dt_damp, int elastic, int pseudo, T* vals);
 
 // ------------------------------------------------------ solver kernels
 // Row partition of the node rows into blocks that never straddle a shell;
@@ -39,9 +39,22 @@ struct CgShellOut {
     double bnorm2, rnorm2;   // ||b||^2 and the final recursive ||r||^2
 };
 
+// Symmetric block storage: block row i stores its blocks (i, j >= i), the
+// diagonal first; the stored block of pair (i, j) holds A_ji column-major
+// (A_ij row-major).  The product by A_ji = A_ij^T belongs to row j: it is
+// written to slot tslot[b] of the 12-value slot array (-1 for diagonal
+// blocks), and row j's slots are lptr[j] .. lptr[j+1].
+struct SymBsr {
+    const int* row_ptr;   // [nnodes + 1] stored blocks per block row
+    const int* col_idx;   // [stored blocks] column node
+    const int* tslot;     // [stored blocks] slot of the transposed product
+    const int* lptr;      // [nnodes + 1] slots of each row
+};
+
+// y = A x; slot: scratch of 12 doubles per stored off-diagonal block
 template <class TM>
-void launch_spmv(hipStream_t st, int nnodes, const int* row_ptr, const int* col_idx, const TM* vals,
-                 const uint16_t* freemask, const double* x, const double* b, double* y, int mode);
+void launch_spmv(hipStream_t st, int nnodes, const SymBsr& m, const TM* vals, const uint16_t* freemask,
+                 const double* x, const double* b, double* y, double* slot, int mode);
 // mode bits: 1 masked (free rows and columns only), 2 abs values (|A| |x|), 4 residual y = b - A x,
 // 8 free rows only (all columns)
 
@@ -53,12 +66,12 @@ void launch_save_diag(hipStream_t st, int nnodes, const int* diag_blk, const voi
 void launch_regularize(hipStream_t st, int nnodes, const int* diag_blk, void* vals, int vals_fp32,
                        const double* diag, const int* node_shell, const double* delta_shell);
 
-// Persistent block-Jacobi CG; nthreads is 256 or 1024 per block.
+// Persistent block-Jacobi CG; nthreads is 256, 512 or 1024 per block.
 template <class TM, class TV>
-hipError_t launch_cg(hipStream_t st, int nblk, int nthreads, const RowBlocks& rb, const int* row_ptr,
-                     const int* col_idx, const TM* vals, const TV* dinv, const uint16_t* freemask, const double* b,
-                     TV* x, TV* r, TV* z, TV* p0, TV* p1, TV* qv, double* partial, void* sync, int* abort_flag,
-                     const double* rtol2_shell, const int* maxit_shell, const int* active_shell, CgShellOut* out);
+hipError_t launch_cg(hipStream_t st, int nblk, int nthreads, const RowBlocks& rb, const SymBsr& m, const TM* vals,
+                     const TV* dinv, const uint16_t* freemask, const double* b, TV* x, TV* r, TV* z, TV* p0, TV* p1,
+                     TV* qv, TV* slot, double* partial, void* sync, int* abort_flag, const double* rtol2_shell,
+                     const int* maxit_shell, const int* active_shell, CgShellOut* out);
 int cg_max_blocks(int device, int tm_fp32, int nthreads);   // co-resident blocks of the CG kernel
 size_t cg_sync_bytes();                                     // per-shell synchronisation state of the CG kernel
 int cg_rows_per_pass(int tm_fp32, int nthreads);            // node rows one CG block covers per pass

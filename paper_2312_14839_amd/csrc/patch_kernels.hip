@@ -205,6 +205,7 @@ __global__ __launch_bounds__(256) void k_hessian(const int* __restrict__ patch_l
                                                  const int4* __restrict__ patch_nodes,
                                                  const int* __restrict__ patch_shell,
                                                  const int* __restrict__ patch_slots,
+                                                 const uint64_t* __restrict__ patch_kid,
                                                  const uint16_t* __restrict__ patch_first,
                                                  const ShellParams* __restrict__ shells,
                                                  const double* __restrict__ phi, const double* __restrict__ q,
@@ -316,33 +317,41 @@ __global__ __launch_bounds__(256) void k_hessian(const int* __restrict__ patch_l
             for (int v = 0; v < 4; ++v) W[pr * 256 + MM::row(lane, v) * 16 + (lane & 15)] = acc[pr][v];
     }
     __syncthreads();
-    // phase 3: add the 16 node blocks (column-major 12x12) into the matrix;
-    // a block this patch touches first is stored, the others are read,
-    // added to and written back.  Chunks of 12 elements per lane keep 12
-    // reads in flight.
+    // phase 3: add the node blocks the matrix stores (column-major 12x12:
+    // the diagonal blocks and, of each pair (c, d) of distinct nodes, the
+    // one whose row node has the larger index) into the matrix.  Entry m of
+    // the patch's slot list is the m-th stored local block (local index in
+    // nibble m of patch_kid; the list ends at the first -1).  A block this
+    // patch touches first is stored, the others are read, added to and
+    // written back.  Chunks of 12 elements per lane keep 12 reads in flight.
     if (active) {
         const int* slots = patch_slots + 16 * (size_t)patch;
+        const uint64_t kid = patch_kid[patch];
         const unsigned first = patch_first[patch];
         constexpr int CH = 12;
 #pragma unroll 1
         for (int e0 = 0; e0 < 16 * 144; e0 += 64 * CH) {
+            if (slots[e0 / 144] < 0) break;
             T add[CH], old[CH];
             T* dst[CH];
 #pragma unroll
             for (int u = 0; u < CH; ++u) {
                 const int e = e0 + 64 * u + lane;
-                const int blk = e / 144, w = e % 144;
+                const int mm = e / 144, w = e % 144;
+                const int sl = slots[mm];
+                const int blk = (int)((kid >> (4 * mm)) & 15u);
                 const int c = blk >> 2, d = blk & 3;
                 const int jj = w / 12, ii = w % 12;   // column-major: w = jj*12 + ii
                 const int k = ii / 3, i = ii % 3, l = jj / 3, j = jj % 3;
                 const int I = 4 * c + k, J = 4 * d + l;
                 const T kv = i <= j ? W[pair_index(i, j) * 256 + I * 16 + J] : W[pair_index(j, i) * 256 + J * 16 + I];
                 add[u] = (T)(kind_scale(k, sp.dxi1, sp.dxi2) * kind_scale(l, sp.dxi1, sp.dxi2)) * kv;
-                dst[u] = vals + (size_t)slots[blk] * 144 + w;
-                old[u] = ((first >> blk) & 1u) ? T(0) : *dst[u];
+                dst[u] = sl >= 0 ? vals + (size_t)sl * 144 + w : nullptr;
+                old[u] = (!dst[u] || ((first >> mm) & 1u)) ? T(0) : *dst[u];
             }
 #pragma unroll
-            for (int u = 0; u < CH; ++u) *dst[u] = old[u] + add[u];
+            for (int u = 0; u < CH; ++u)
+                if (dst[u]) *dst[u] = old[u] + add[u];
         }
     }
 }
@@ -373,20 +382,20 @@ void launch_shell_energy(hipStream_t st, int nshell, const ShellParams* shells, 
 
 template <class T>
 void launch_hessian(hipStream_t st, const int* patch_list, int nlist, const int4* patch_nodes, const int* patch_shell,
-                    const int* patch_slots, const uint16_t* patch_first, const ShellParams* shells,
-                    const double* phi, const double* q, const double* qbar, double mass_scale, double dt_damp,
-                    int elastic, int pseudo, T* vals) {
+                    const int* patch_slots, const uint64_t* patch_kid, const uint16_t* patch_first,
+                    const ShellParams* shells, const double* phi, const double* q, const double* qbar,
+                    double mass_scale, double dt_damp, int elastic, int pseudo, T* vals) {
     if (nlist == 0) return;
     const int nb = (nlist + HS_WAVES - 1) / HS_WAVES;
     hipLaunchKernelGGL(k_hessian<T>, dim3(nb), dim3(256), 0, st, patch_list, nlist, patch_nodes, patch_shell,
-                       patch_slots, patch_first, shells, phi, q, qbar, mass_scale, dt_damp, elastic, pseudo, vals);
+                       patch_slots, patch_kid, patch_first, shells, phi, q, qbar, mass_scale, dt_damp, elastic, pseudo, vals);
 }
 
 template void launch_hessian<double>(hipStream_t, const int*, int, const int4*, const int*, const int*,
-                                     const uint16_t*, const ShellParams*, const double*, const double*,
+                                     const uint64_t*, const uint16_t*, const ShellParams*, const double*, const double*,
                                      const double*, double, double, int, int, double*);
 template void launch_hessian<float>(hipStream_t, const int*, int, const int4*, const int*, const int*,
-                                    const uint16_t*, const ShellParams*, const double*, const double*,
+                                    const uint64_t*, const uint16_t*, const ShellParams*, const double*, const double*,
                                     const double*, double, double, int, int, float*);
 
 }  // namespace bhem

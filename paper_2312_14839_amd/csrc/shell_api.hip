@@ -45,10 +45,12 @@ struct shell_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     int S = 0, N = 0, P = 0;
-    long long nnzb = 0;
+    long long nnzb = 0;     // block non-zeros of the full matrix
+    long long nnzb_u = 0;   // stored blocks (diagonal and upper triangle)
     bool fp32 = false;
     std::vector<ShellParams> shells;
-    std::vector<int> h_row_ptr, h_col_idx, h_node_shell;
+    std::vector<int> h_row_ptr, h_col_idx, h_node_shell;   // full block pattern
+    std::vector<int> h_urow, h_ucol;                       // stored (upper) pattern
     std::vector<uint16_t> h_freemask;
     std::vector<int> colour_off;   // [ncolour + 1] into the concatenated colour lists
     int nblk = 0;                  // CG row blocks
@@ -56,9 +58,10 @@ struct shell_ctx {
     int cg_rows_target = 0;        // node rows per CG block (before the even split of a shell)
     std::vector<int> h_shell_blk0, h_shell_nblk;
     // device data
-    DevBuf patch_first;   // [P] uint16 first-touch bits of the 16 local blocks
+    DevBuf patch_first;   // [P] uint16 first-touch bits of the stored local blocks
+    DevBuf patch_kid;     // [P] uint64 local block index of each stored local block (4 bits each)
     DevBuf shells_d, phi, qbar, freemask, node_shell, patch_nodes, patch_shell, patch_slots, colour_list, inc_ptr,
-        inc, row_ptr, col_idx, diag_blk, vals, diag0, dinv;
+        inc, row_ptr, col_idx, tslot, lptr, diag_blk, vals, slot, diag0, dinv;
     DevBuf blk_shell, blk_row0, blk_row1, shell_blk0, shell_nblk;
     DevBuf e_patch, g_patch, e_shell, red_part, red_out;
     // Newton / CG work vectors (FP64 [N*12] unless noted)
@@ -111,7 +114,11 @@ struct shell_ctx {
     bool timing = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     shell_timing tm;
-    std::vector<long long> rows_s, nnzb_s;   // per-shell node rows and block non-zeros
+    std::vector<long long> rows_s, nnzb_s;   // per-shell node rows and stored blocks
+
+    SymBsr sym() {
+        return SymBsr{dptr<int>(row_ptr), dptr<int>(col_idx), dptr<int>(tslot), dptr<int>(lptr)};
+    }
 
     RowBlocks rb() {
         return RowBlocks{nblk, dptr<int>(blk_shell), dptr<int>(blk_row0), dptr<int>(blk_row1), dptr<int>(shell_blk0),
@@ -411,33 +418,69 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
     }
     c->h_row_ptr.assign(N + 1, 0);
     c->h_col_idx.clear();
-    std::vector<int> diag(N);
     for (int n = 0; n < N; ++n) {
         auto& a = adj[n];
         std::sort(a.begin(), a.end());
         a.erase(std::unique(a.begin(), a.end()), a.end());
-        for (size_t k = 0; k < a.size(); ++k)
-            if (a[k] == n) diag[n] = (int)c->h_col_idx.size() + (int)k;
         c->h_col_idx.insert(c->h_col_idx.end(), a.begin(), a.end());
         c->h_row_ptr[n + 1] = (int)c->h_col_idx.size();
     }
     c->nnzb = (long long)c->h_col_idx.size();
+    // stored pattern: the columns >= n of block row n (the diagonal first);
+    // the transposed product of stored block (i, j > i) goes to the slots of
+    // row j, ordered by i
+    c->h_urow.assign(N + 1, 0);
+    c->h_ucol.clear();
+    std::vector<int> diag(N), lptr(N + 1, 0);
+    for (int n = 0; n < N; ++n) {
+        for (int k = c->h_row_ptr[n]; k < c->h_row_ptr[n + 1]; ++k) {
+            const int col = c->h_col_idx[k];
+            if (col >= n) c->h_ucol.push_back(col);
+            else lptr[n + 1]++;
+        }
+        c->h_urow[n + 1] = (int)c->h_ucol.size();
+        if (c->h_urow[n + 1] == c->h_urow[n] || c->h_ucol[c->h_urow[n]] != n)
+            throw InvalErr{"internal: block row without its diagonal block"};
+        diag[n] = c->h_urow[n];
+    }
+    for (int n = 0; n < N; ++n) lptr[n + 1] += lptr[n];
+    c->nnzb_u = (long long)c->h_ucol.size();
+    std::vector<int> tslot((size_t)c->nnzb_u, -1);
+    {
+        std::vector<int> fill(lptr.begin(), lptr.end() - 1);
+        for (int n = 0; n < N; ++n)
+            for (int b = c->h_urow[n] + 1; b < c->h_urow[n + 1]; ++b) tslot[b] = fill[c->h_ucol[b]]++;
+        for (int n = 0; n < N; ++n)
+            if (fill[n] != lptr[n + 1]) throw InvalErr{"internal: asymmetric block pattern"};
+    }
     c->rows_s.assign(S, 0);
     c->nnzb_s.assign(S, 0);
     for (int s2 = 0; s2 < S; ++s2) {
         c->rows_s[s2] = c->shells[s2].node_end - c->shells[s2].node_begin;
-        c->nnzb_s[s2] = c->h_row_ptr[c->shells[s2].node_end] - c->h_row_ptr[c->shells[s2].node_begin];
+        c->nnzb_s[s2] = c->h_urow[c->shells[s2].node_end] - c->h_urow[c->shells[s2].node_begin];
     }
-    std::vector<int> slots((size_t)P * 16);
+    // per patch: the stored local blocks (a, b) -- diagonal, or row node
+    // index above the column node's (that block, column-major, is the
+    // stored pair's content) -- with their stored block index
+    std::vector<int> slots((size_t)P * 16, -1);
+    std::vector<uint64_t> kid((size_t)P, 0);
     std::vector<std::vector<int>> inc(N);
     for (int p = 0; p < P; ++p) {
         const int nd[4] = {pnodes[p].x, pnodes[p].y, pnodes[p].z, pnodes[p].w};
+        int mm = 0;
         for (int a = 0; a < 4; ++a) {
             inc[nd[a]].push_back(4 * p + a);
             for (int b = 0; b < 4; ++b) {
-                const int* beg = &c->h_col_idx[c->h_row_ptr[nd[a]]];
-                const int* end = &c->h_col_idx[0] + c->h_row_ptr[nd[a] + 1];
-                slots[(size_t)p * 16 + 4 * a + b] = (int)(std::lower_bound(beg, end, nd[b]) - &c->h_col_idx[0]);
+                if (a != b && nd[a] == nd[b]) throw InvalErr{"internal: patch with a repeated node"};
+                if (!(a == b || nd[a] > nd[b])) continue;
+                const int lo = std::min(nd[a], nd[b]), hi = std::max(nd[a], nd[b]);
+                const int* beg = &c->h_ucol[c->h_urow[lo]];
+                const int* end = &c->h_ucol[0] + c->h_urow[lo + 1];
+                const int* at = std::lower_bound(beg, end, hi);
+                if (at == end || *at != hi) throw InvalErr{"internal: patch block missing from the pattern"};
+                slots[(size_t)p * 16 + mm] = (int)(at - &c->h_ucol[0]);
+                kid[p] |= (uint64_t)(4 * a + b) << (4 * mm);
+                ++mm;
             }
         }
     }
@@ -452,30 +495,33 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
         clist.insert(clist.end(), colour_lists[col].begin(), colour_lists[col].end());
         c->colour_off.push_back((int)clist.size());
     }
-    // first touch: bit b of patch p is set when p is the first patch, in
-    // colour-pass order, to add into its local block b (patches of one
-    // colour never share a block), so the assembly stores instead of adding
-    // there and needs no zero fill
+    // first touch: bit m of patch p is set when p is the first patch, in
+    // colour-pass order, to add into its m-th stored local block (patches of
+    // one colour never share a block), so the assembly stores instead of
+    // adding there and needs no zero fill
     std::vector<uint16_t> first((size_t)P, 0);
     {
-        std::vector<char> touched((size_t)c->nnzb, 0);
+        std::vector<char> touched((size_t)c->nnzb_u, 0);
         for (int p : clist)
-            for (int b = 0; b < 16; ++b) {
-                const int sl = slots[(size_t)p * 16 + b];
+            for (int m = 0; m < 16; ++m) {
+                const int sl = slots[(size_t)p * 16 + m];
+                if (sl < 0) break;
                 if (!touched[sl]) {
                     touched[sl] = 1;
-                    first[p] |= (uint16_t)(1u << b);
+                    first[p] |= (uint16_t)(1u << m);
                 }
             }
-        for (long long k = 0; k < c->nnzb; ++k)
+        for (long long k = 0; k < c->nnzb_u; ++k)
             if (!touched[k]) throw InvalErr{"internal: matrix block without a patch"};
     }
     // CG row blocks: contiguous node rows, never straddling a shell.  Large
-    // shells use 1024-thread blocks (fewer blocks make the per-iteration
-    // barriers cheaper); small ones 256-thread blocks spread over more CUs.
+    // shells use 512-thread blocks (fewer blocks make the per-iteration
+    // barriers cheaper, and one such block per CU leaves each wave the
+    // registers of the symmetric product without spilling); small ones
+    // 256-thread blocks spread over more CUs.
     int max_rows = 0;
     for (int s = 0; s < S; ++s) max_rows = std::max(max_rows, c->shells[s].node_end - c->shells[s].node_begin);
-    const int nt0 = max_rows >= 16 * cg_rows_per_pass(c->fp32, 1024) ? 1024 : 256;
+    const int nt0 = max_rows >= 16 * cg_rows_per_pass(c->fp32, 512) ? 512 : 256;
     if (!set_row_blocks(c, nt0, 1) && !set_row_blocks(c, 256, 1))
         throw InvalErr{"too many shells for one context (limit " +
                        std::to_string(cg_max_blocks(c->opts.device, c->fp32, 256)) + ")"};
@@ -491,15 +537,19 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
     upload(c->patch_nodes, pnodes, st);
     upload(c->patch_shell, pshell, st);
     upload(c->patch_slots, slots, st);
+    upload(c->patch_kid, kid, st);
     upload(c->colour_list, clist, st);
     upload(c->patch_first, first, st);
     upload(c->inc_ptr, inc_ptr, st);
     upload(c->inc, inc_flat, st);
-    upload(c->row_ptr, c->h_row_ptr, st);
-    upload(c->col_idx, c->h_col_idx, st);
+    upload(c->row_ptr, c->h_urow, st);
+    upload(c->col_idx, c->h_ucol, st);
+    upload(c->tslot, tslot, st);
+    upload(c->lptr, lptr, st);
     upload(c->diag_blk, diag, st);
     const size_t vecb = (size_t)N * 12 * sizeof(double);
-    alloc(c->vals, (size_t)c->nnzb * 144 * (c->fp32 ? sizeof(float) : sizeof(double)));
+    alloc(c->vals, (size_t)c->nnzb_u * 144 * (c->fp32 ? sizeof(float) : sizeof(double)));
+    alloc(c->slot, (size_t)std::max(c->nnzb_u - N, 1LL) * 12 * sizeof(double));
     alloc(c->diag0, vecb);
     alloc(c->dinv, (size_t)N * 144 * (c->fp32 ? sizeof(float) : sizeof(double)));
     alloc(c->e_patch, (size_t)std::max(P, 1) * 3 * sizeof(double));
@@ -580,12 +630,13 @@ void assemble(shell_ctx* c, const double* q_in, double mass_scale, int elastic) 
         const int* list = dptr<int>(c->colour_list) + off;
         if (c->fp32)
             launch_hessian<float>(st, list, n, dptr<int4>(c->patch_nodes), dptr<int>(c->patch_shell),
-                                  dptr<int>(c->patch_slots), dptr<uint16_t>(c->patch_first), dptr<ShellParams>(c->shells_d), dptr<double>(c->phi), q_in,
+                                  dptr<int>(c->patch_slots), dptr<uint64_t>(c->patch_kid), dptr<uint16_t>(c->patch_first),
+                                  dptr<ShellParams>(c->shells_d), dptr<double>(c->phi), q_in,
                                   dptr<double>(c->qbar), mass_scale, c->dt_damp, elastic, pseudo, dptr<float>(c->vals));
         else
             launch_hessian<double>(st, list, n, dptr<int4>(c->patch_nodes), dptr<int>(c->patch_shell),
-                                   dptr<int>(c->patch_slots), dptr<uint16_t>(c->patch_first), dptr<ShellParams>(c->shells_d), dptr<double>(c->phi),
-                                   q_in, dptr<double>(c->qbar), mass_scale, c->dt_damp, elastic, pseudo,
+                                   dptr<int>(c->patch_slots), dptr<uint64_t>(c->patch_kid), dptr<uint16_t>(c->patch_first),
+                                   dptr<ShellParams>(c->shells_d), dptr<double>(c->phi), q_in, dptr<double>(c->qbar), mass_scale, c->dt_damp, elastic, pseudo,
                                    dptr<double>(c->vals));
     }
     HIPCHK(hipGetLastError());
@@ -596,11 +647,11 @@ void assemble(shell_ctx* c, const double* q_in, double mass_scale, int elastic) 
 void spmv(shell_ctx* c, const double* x, const double* b, double* y, int mode) {
     GroupTimer tmr(c, SHELL_T_SPMV);
     if (c->fp32)
-        launch_spmv<float>(c->stream, c->N, dptr<int>(c->row_ptr), dptr<int>(c->col_idx), dptr<float>(c->vals),
-                           dptr<uint16_t>(c->freemask), x, b, y, mode);
+        launch_spmv<float>(c->stream, c->N, c->sym(), dptr<float>(c->vals), dptr<uint16_t>(c->freemask), x, b, y,
+                           dptr<double>(c->slot), mode);
     else
-        launch_spmv<double>(c->stream, c->N, dptr<int>(c->row_ptr), dptr<int>(c->col_idx), dptr<double>(c->vals),
-                            dptr<uint16_t>(c->freemask), x, b, y, mode);
+        launch_spmv<double>(c->stream, c->N, c->sym(), dptr<double>(c->vals), dptr<uint16_t>(c->freemask), x, b, y,
+                            dptr<double>(c->slot), mode);
     HIPCHK(hipGetLastError());
     tmr.stop();
 }
@@ -644,19 +695,19 @@ void cg_launch(shell_ctx* c, const double* b, const std::vector<int>& active, co
     GroupTimer tmr(c, SHELL_T_CG);
     hipError_t e;
     if (c->fp32)
-        e = launch_cg<float, float>(st, c->nblk, c->cg_threads, c->rb(), dptr<int>(c->row_ptr), dptr<int>(c->col_idx),
-                                    dptr<float>(c->vals), dptr<float>(c->dinv), dptr<uint16_t>(c->freemask), b,
+        e = launch_cg<float, float>(st, c->nblk, c->cg_threads, c->rb(), c->sym(), dptr<float>(c->vals),
+                                    dptr<float>(c->dinv), dptr<uint16_t>(c->freemask), b,
                                     dptr<float>(c->cg_x), dptr<float>(c->cg_r), dptr<float>(c->cg_z),
                                     dptr<float>(c->cg_p0), dptr<float>(c->cg_p1), dptr<float>(c->cg_q),
-                                    dptr<double>(c->cg_partial), c->cg_bar.p, dptr<int>(c->cg_abort),
+                                    dptr<float>(c->slot), dptr<double>(c->cg_partial), c->cg_bar.p, dptr<int>(c->cg_abort),
                                     dptr<double>(c->cg_rtol2), dptr<int>(c->cg_maxit), dptr<int>(c->cg_active),
                                     dptr<CgShellOut>(c->cg_out));
     else
-        e = launch_cg<double, double>(st, c->nblk, c->cg_threads, c->rb(), dptr<int>(c->row_ptr), dptr<int>(c->col_idx),
-                                      dptr<double>(c->vals), dptr<double>(c->dinv), dptr<uint16_t>(c->freemask), b,
+        e = launch_cg<double, double>(st, c->nblk, c->cg_threads, c->rb(), c->sym(), dptr<double>(c->vals),
+                                      dptr<double>(c->dinv), dptr<uint16_t>(c->freemask), b,
                                       dptr<double>(c->cg_x), dptr<double>(c->cg_r), dptr<double>(c->cg_z),
                                       dptr<double>(c->cg_p0), dptr<double>(c->cg_p1), dptr<double>(c->cg_q),
-                                      dptr<double>(c->cg_partial), c->cg_bar.p, dptr<int>(c->cg_abort),
+                                      dptr<double>(c->slot), dptr<double>(c->cg_partial), c->cg_bar.p, dptr<int>(c->cg_abort),
                                       dptr<double>(c->cg_rtol2), dptr<int>(c->cg_maxit), dptr<int>(c->cg_active),
                                       dptr<CgShellOut>(c->cg_out));
     HIPCHK(e);
@@ -1100,23 +1151,38 @@ shell_status shell_get_bsr(shell_ctx* c, int32_t shell, int32_t* nnzb, int32_t* 
     if (col_idx)
         for (int b = b0; b < b1; ++b) col_idx[b - b0] = c->h_col_idx[b] - n0;
     if (vals) {
-        const size_t cnt = (size_t)(b1 - b0) * 144;
+        // stored blocks of the shell's rows, then the full pattern from them
+        const int u0 = c->h_urow[n0], u1 = c->h_urow[n1];
+        const size_t cnt = (size_t)(u1 - u0) * 144;
         std::vector<double> tmp(cnt);
         if (c->fp32) {
             std::vector<float> f(cnt);
-            HIPCHK(hipMemcpyAsync(f.data(), dptr<float>(c->vals) + (size_t)b0 * 144, cnt * sizeof(float),
+            HIPCHK(hipMemcpyAsync(f.data(), dptr<float>(c->vals) + (size_t)u0 * 144, cnt * sizeof(float),
                                   hipMemcpyDeviceToHost, c->stream));
             sync(c);
             for (size_t i = 0; i < cnt; ++i) tmp[i] = f[i];
         } else {
-            HIPCHK(hipMemcpyAsync(tmp.data(), dptr<double>(c->vals) + (size_t)b0 * 144, cnt * sizeof(double),
+            HIPCHK(hipMemcpyAsync(tmp.data(), dptr<double>(c->vals) + (size_t)u0 * 144, cnt * sizeof(double),
                                   hipMemcpyDeviceToHost, c->stream));
             sync(c);
         }
-        // device blocks are column-major; the ABI returns row-major blocks
-        for (size_t b = 0; b < (size_t)(b1 - b0); ++b)
-            for (int r = 0; r < 12; ++r)
-                for (int cc = 0; cc < 12; ++cc) vals[b * 144 + r * 12 + cc] = tmp[b * 144 + cc * 12 + r];
+        // The products read the stored block of pair (i, j >= i) as A_ij
+        // row-major (for i = j too: the assembled diagonal block, stored
+        // column-major, is symmetric up to rounding, and the matrix returned
+        // here is the one the products apply).  The ABI returns row-major
+        // blocks: block (n, col) is the stored block (n, col) as it is for
+        // col >= n, and the transpose of the stored block (col, n) for col < n.
+        for (int n = n0; n < n1; ++n)
+            for (int b = c->h_row_ptr[n]; b < c->h_row_ptr[n + 1]; ++b) {
+                const int col = c->h_col_idx[b];
+                const int lo = std::min(n, col), hi = std::max(n, col);
+                const int ub = (int)(std::lower_bound(&c->h_ucol[0] + c->h_urow[lo], &c->h_ucol[0] + c->h_urow[lo + 1], hi) -
+                                     &c->h_ucol[0]);
+                const double* src = tmp.data() + (size_t)(ub - u0) * 144;
+                double* dst = vals + (size_t)(b - b0) * 144;
+                for (int r = 0; r < 12; ++r)
+                    for (int cc = 0; cc < 12; ++cc) dst[r * 12 + cc] = col >= n ? src[r * 12 + cc] : src[cc * 12 + r];
+            }
     }
     return SHELL_OK;
     API_CATCH

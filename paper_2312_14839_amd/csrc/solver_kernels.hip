@@ -2,17 +2,26 @@
 // block-Jacobi factorisation, the persistent block-Jacobi conjugate gradient
 // and per-shell reductions.
 //
-// Matrix storage: block rows per node (row_ptr / col_idx over nodes); each
-// 12x12 block is stored column-major (entry (r, c) at c*12 + r) so that the
-// lanes owning consecutive rows of a block read consecutive memory.  Rows and
-// columns of prescribed DOFs stay in the matrix; the solver masks them
-// (free-DOF bit masks per node), which equals replacing them by identity rows
-// and columns with a zero right-hand side.
+// Matrix storage (the Hessian is symmetric): block row i keeps only its
+// blocks (i, j >= i), the diagonal block first.  The stored block of pair
+// (i, j) holds A_ji column-major, which is A_ij row-major (entry (r, c) of
+// A_ij at r*12 + c; the diagonal block A_ii, symmetric, is its own
+// transpose).  Rows and columns of prescribed DOFs stay in the matrix; the
+// solver masks them (free-DOF bit masks per node), which equals replacing
+// them by identity rows and columns with a zero right-hand side.
 //
-// SpMV lane layout: a node row is handled by L = 12/R lanes, each owning R
-// consecutive rows of the 12 (R = 2 for FP64 blocks, 4 for FP32), so each
-// column of a block is one 16-byte load per lane; the 12 x-values of a
-// column block are exchanged within the lane group by cross-lane reads.
+// Product lane layout: a node row is handled by L = 12/R lanes.  Lane t of
+// the group reads the 16 bytes at offset c*12 + R*t of every row c of a
+// stored block (R = 2 for FP64 blocks, 4 for FP32), so each of its 12 loads
+// is one coalesced 16-byte load and the lane owns columns R*t .. R*t+R-1 of
+// A_ij.  Both products a stored block takes part in are then lane-local:
+//   A_ij x_j   partial sums over the lane's columns for all 12 rows, summed
+//              over the group once per block row;
+//   A_ji x_i = A_ij^T x_i   the lane's R entries, which row j needs.
+// The second product goes to a slot of its own (tslot of the block; rows
+// j's slots are the contiguous range lptr[j] .. lptr[j+1], ordered by i), and
+// row j adds its slots after the product phase: every entry is written by
+// one lane and summed in a fixed order, so results are reproducible.
 #include <hip/hip_runtime.h>
 
 #include "device_common.hpp"
@@ -21,7 +30,7 @@
 namespace bhem {
 
 template <class TM> struct Lay {
-    static constexpr int R = 16 / sizeof(TM);   // rows per lane
+    static constexpr int R = 16 / sizeof(TM);   // columns per lane
     static constexpr int L = 12 / R;             // lanes per node row
     static constexpr int G = 64 / L;             // node rows per wavefront
 };
@@ -36,6 +45,15 @@ template <> struct VecLoad<double, 2> {
         o[1] = v.y;
     }
 };
+template <> struct VecLoad<double, 4> {
+    static __device__ __forceinline__ void ld(const double* p, double* o) {
+        const double2 v0 = reinterpret_cast<const double2*>(p)[0], v1 = reinterpret_cast<const double2*>(p)[1];
+        o[0] = v0.x;
+        o[1] = v0.y;
+        o[2] = v1.x;
+        o[3] = v1.y;
+    }
+};
 template <> struct VecLoad<float, 4> {
     static __device__ __forceinline__ void ld(const float* p, float* o) {
         const float4 v = *reinterpret_cast<const float4*>(p);
@@ -45,125 +63,178 @@ template <> struct VecLoad<float, 4> {
         o[3] = v.w;
     }
 };
+template <class TV, int R> struct VecStore;
+template <> struct VecStore<double, 2> {
+    static __device__ __forceinline__ void st(double* p, const double* v) {
+        *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+    }
+};
+template <> struct VecStore<float, 4> {
+    static __device__ __forceinline__ void st(float* p, const float* v) {
+        *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+    }
+};
+template <> struct VecStore<double, 4> {
+    static __device__ __forceinline__ void st(double* p, const double* v) {
+        reinterpret_cast<double2*>(p)[0] = make_double2(v[0], v[1]);
+        reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
+    }
+};
 
-// acc[0..R) = rows R*t .. R*t+R-1 of (block row `node`) times x_eff, where
-// xe(col, xv) supplies this lane's R values of column block `col`.  The next
-// block's column index and x-values are fetched while the current block is
-// multiplied, so the dependent index -> vector load chain overlaps the
-// matrix stream.
-template <class TM, class TV, class XF>
-__device__ __forceinline__ void row_times(const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
-                                          const TM* __restrict__ vals, int node, int t, int gbase, bool absval,
-                                          XF xe, TV* acc) {
+// Orders the wavefront's LDS accesses around a cross-lane exchange (the LDS
+// operations of one wavefront execute in program order; this keeps the
+// compiler from moving them across).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// out[k] = sum over the L lanes of the group of part[R*t + k], through the
+// wave's LDS area red[64][12]: every lane writes its 12 partials and reads
+// its R entries from each lane of its group, in lane order (the same order
+// on every lane, so the result is reproducible).  The partials stay in
+// registers (selecting them by a lane-dependent index would move them to
+// scratch memory).  The LDS operations of one wavefront execute in program
+// order, so the reads see the writes and the next row's writes follow the
+// reads.
+template <class TV, int R, int L>
+__device__ __forceinline__ void group_sum(const TV (&part)[12], int lane, int t, int gbase, TV* __restrict__ red,
+                                          TV (&out)[R]) {
+    constexpr int V = 16 / sizeof(TV);   // values per 16-byte LDS access
+#pragma unroll
+    for (int e = 0; e < 12; e += V) VecStore<TV, V>::st(red + lane * 12 + e, part + e);
+    wave_lds_sync();
+#pragma unroll
+    for (int k = 0; k < R; ++k) out[k] = TV(0);
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+        TV v[R];
+        VecLoad<TV, R>::ld(red + (gbase + j) * 12 + R * t, v);
+#pragma unroll
+        for (int k = 0; k < R; ++k) out[k] += v[k];
+    }
+    wave_lds_sync();
+}
+
+// One stored block in three parts of 4 rows (4 loads of 16 bytes each):
+// part[c] += sum_k A[c][R t + k] xv[k] and tv[k] += sum_c A[c][R t + k] x_i[c],
+// with x_i[c] read from the group's LDS copy xl (re-read per block: kept in
+// registers through the row, the 12 values would cost the registers that
+// let 16 waves share a CU).  FIRST (the diagonal block, xv = this lane's
+// part of x_i): part is set instead, and instead of tv, dl = sum_c x_i[c]
+// part[c], whose sum over the group is x_i^T A_ii x_i (a scalar: a
+// transposed product needed only after the row's other blocks would keep
+// the whole block's registers live through them).  A scheduling barrier
+// after each part keeps one part's loads in flight at a time per wave (more
+// registers per wave measured no faster: the waves of a CU keep enough
+// loads in flight).
+template <class TM, class TV, bool ABS, bool FIRST>
+__device__ __forceinline__ void block_sym(const TM* __restrict__ blk, const TV (&xv)[Lay<TM>::R],
+                                          const TV* __restrict__ xl, TV (&part)[12], TV (&tv)[Lay<TM>::R],
+                                          TV& dl) {
     constexpr int R = Lay<TM>::R;
+    asm volatile("" ::: "memory");   // re-read xl for this block
 #pragma unroll
-    for (int i = 0; i < R; ++i) acc[i] = TV(0);
-    const int b0 = row_ptr[node], b1 = row_ptr[node + 1];
-    if (b0 >= b1) return;
-    TV xv[R];
-    xe(col_idx[b0], xv);
-    for (int b = b0; b < b1; ++b) {
-        TV xn[R];
-        if (b + 1 < b1) xe(col_idx[b + 1], xn);
-        const TM* blk = vals + (size_t)b * 144 + R * t;
-        TM a[12][R];
+    for (int h = 0; h < 3; ++h) {
+        TM a[4][R];
 #pragma unroll
-        for (int c = 0; c < 12; ++c) VecLoad<TM, R>::ld(blk + c * 12, a[c]);
-        if (absval)
+        for (int c = 0; c < 4; ++c) VecLoad<TM, R>::ld(blk + (4 * h + c) * 12, a[c]);
 #pragma unroll
-            for (int i = 0; i < R; ++i) xv[i] = fabs(xv[i]);
+        for (int c = 0; c < 4; ++c) {
+            const int cc = 4 * h + c;
+            const TV xc = xl[cc];
+            TV sacc = FIRST ? TV(0) : part[cc];
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            const TV xc = __shfl(xv[c % R], gbase + c / R);
-#pragma unroll
-            for (int i = 0; i < R; ++i) acc[i] += (absval ? (TV)fabs(a[c][i]) : (TV)a[c][i]) * xc;
+            for (int k = 0; k < R; ++k) {
+                const TV av = ABS ? (TV)fabs(a[c][k]) : (TV)a[c][k];
+                sacc += av * xv[k];
+                if (!FIRST) tv[k] += av * xc;
+            }
+            part[cc] = sacc;
+            if (FIRST) dl += xc * sacc;
         }
-#pragma unroll
-        for (int i = 0; i < R; ++i) xv[i] = xn[i];
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
-// Same product for the CG, whose x-values are formed from two vectors
-// (z + beta p): the column indices and x-values of a group of MB blocks are
-// loaded first, all at once, so the matrix loads of the group do not wait
-// on the dependent index -> vector chain block by block (that chain, with
-// one wait per block, cost ~10% of a CG iteration).  Blocks past the row's
-// end re-read a block of the row with x = 0.
-template <class TM, class TV, class XF>
-__device__ __forceinline__ void row_times_grouped(const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
-                                          const TM* __restrict__ vals, int node, int t, int gbase, bool absval,
-                                          XF xe, TV* acc) {
-    constexpr int R = Lay<TM>::R, MB = 3;
+// The stored blocks of block row `node` against x (see the storage note):
+//   part[c] (c = 0..11): this lane's partial of row c of sum_j A_ij x_j,
+//   returned: this lane's share of x_i^T A_ii x_i (for p^T A p),
+//   slot[tslot[b]] <- A_ij^T x_i for every stored off-diagonal block b.
+// xo: this lane's R entries of x_i (already masked and, with ABS, absolute
+// values), copied for the group to xl[12] in LDS; xe(col, xv) gives this
+// lane's R entries of x for column block col.  ABS multiplies by |A|
+// instead of A.
+template <class TM, class TV, bool ABS, class XF>
+__device__ __forceinline__ TV row_sym(const SymBsr& m, const TM* __restrict__ vals, int node, int t,
+                                      const TV (&xo)[Lay<TM>::R], XF xe, TV* __restrict__ xl, TV* __restrict__ slot,
+                                      TV (&part)[12]) {
+    constexpr int R = Lay<TM>::R;
+    const int b0 = m.row_ptr[node], b1 = m.row_ptr[node + 1];
 #pragma unroll
-    for (int i = 0; i < R; ++i) acc[i] = TV(0);
-    const int b0 = row_ptr[node], b1 = row_ptr[node + 1];
-    for (int bc = b0; bc < b1; bc += MB) {
-        const int nb = min(MB, b1 - bc);
-        int cl[MB];
+    for (int k = 0; k < R; ++k) xl[R * t + k] = xo[k];
+    wave_lds_sync();
+    TV dl = TV(0), tv0[R];
+    block_sym<TM, TV, ABS, true>(vals + (size_t)b0 * 144 + R * t, xo, xl, part, tv0, dl);
+    for (int b = b0 + 1; b < b1; ++b) {
+        TV xv[R], tv[R];
+        xe(m.col_idx[b], xv);
+        const int ts = m.tslot[b];
 #pragma unroll
-        for (int u = 0; u < MB; ++u) cl[u] = col_idx[bc + (u < nb ? u : 0)];
-        TV xv[MB][R];
-#pragma unroll
-        for (int u = 0; u < MB; ++u) {
-            xe(cl[u], xv[u]);
-#pragma unroll
-            for (int i = 0; i < R; ++i) {
-                if (u >= nb) xv[u][i] = TV(0);
-                if (absval) xv[u][i] = fabs(xv[u][i]);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < MB; ++u) {
-            const TM* blk = vals + (size_t)(bc + (u < nb ? u : 0)) * 144 + R * t;
-            TM a[12][R];
-#pragma unroll
-            for (int c = 0; c < 12; ++c) VecLoad<TM, R>::ld(blk + c * 12, a[c]);
-#pragma unroll
-            for (int c = 0; c < 12; ++c) {
-                const TV xc = __shfl(xv[u][c % R], gbase + c / R);
-#pragma unroll
-                for (int i = 0; i < R; ++i) acc[i] += (absval ? (TV)fabs(a[c][i]) : (TV)a[c][i]) * xc;
-            }
-        }
+        for (int k = 0; k < R; ++k) tv[k] = TV(0);
+        block_sym<TM, TV, ABS, false>(vals + (size_t)b * 144 + R * t, xv, xl, part, tv, dl);
+        VecStore<TV, R>::st(slot + (size_t)ts * 12 + R * t, tv);
     }
+    wave_lds_sync();
+    return dl;
 }
 
 // ------------------------------------------------------------------ SpMV
-template <class TM>
-__global__ __launch_bounds__(256) void k_spmv(int nnodes, const int* __restrict__ row_ptr,
-                                              const int* __restrict__ col_idx, const TM* __restrict__ vals,
-                                              const uint16_t* __restrict__ fm, const double* __restrict__ x,
-                                              const double* __restrict__ b, double* __restrict__ y, int mode) {
+// y = A x in two launches: k_spmv_rows writes the stored-block part of every
+// row and the transposed products to the slots; k_spmv_fin adds each row's
+// slots and applies the residual form and the row mask.
+//   fc: column mask (x restricted to free DOFs) or NULL
+template <class TM, bool ABS>
+__global__ __launch_bounds__(256) void k_spmv_rows(int nnodes, SymBsr m, const TM* __restrict__ vals,
+                                                   const uint16_t* __restrict__ fc, const double* __restrict__ x,
+                                                   double* __restrict__ y, double* __restrict__ slot) {
     constexpr int R = Lay<TM>::R, L = Lay<TM>::L, G = Lay<TM>::G;
+    __shared__ double red[4][64 * 12];
+    __shared__ double xls[4][G * 12];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int grp = lane / L, t = lane % L;
+    const int grp = lane / L, t = lane % L, gbase = lane - t;
     const int node = (blockIdx.x * 4 + wv) * G + grp;
     if (grp >= G || node >= nnodes) return;
-    const bool absval = mode & 2, resid = mode & 4;
-    const uint16_t* m = (mode & 1) ? fm : nullptr;          // free columns only
-    const uint16_t* mr = (mode & (1 | 8)) ? fm : nullptr;   // free rows only
-    double acc[R];
-    row_times<TM, double>(row_ptr, col_idx, vals, node, t, lane - t, absval,
-                          [&](int col, double* xv) {
-                              // unconditional loads, then a select: no branch, so no
-                              // wait on the mask ahead of the matrix loads
-                              const unsigned fc = m ? (unsigned)m[col] : 0xFFFFu;
+    auto xe = [&](int col, double* xv) {
+        // unconditional loads, then a select: no branch, so no wait on the
+        // mask ahead of the matrix loads
+        const unsigned f = fc ? (unsigned)fc[col] : 0xFFFFu;
 #pragma unroll
-                              for (int i = 0; i < R; ++i) {
-                                  const int w = R * t + i;
-                                  const double xx = x[(size_t)col * 12 + w];
-                                  xv[i] = ((fc >> w) & 1u) ? xx : 0.0;
-                              }
-                          },
-                          acc);
+        for (int i = 0; i < R; ++i) {
+            const int w = R * t + i;
+            const double xx = x[(size_t)col * 12 + w];
+            xv[i] = ((f >> w) & 1u) ? (ABS ? fabs(xx) : xx) : 0.0;
+        }
+    };
+    double xo[R], part[12], yo[R];
+    xe(node, xo);
+    (void)row_sym<TM, double, ABS>(m, vals, node, t, xo, xe, xls[wv] + grp * 12, slot, part);
+    group_sum<double, R, L>(part, lane, t, gbase, red[wv], yo);
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-        const int w = R * t + i;
-        double v = acc[i];
-        if (resid) v = b[(size_t)node * 12 + w] - v;
-        if (!is_free(mr, node, w)) v = 0.0;
-        y[(size_t)node * 12 + w] = v;
-    }
+    for (int i = 0; i < R; ++i) y[(size_t)node * 12 + R * t + i] = yo[i];
+}
+
+__global__ void k_spmv_fin(int nnodes, const int* __restrict__ lptr, const double* __restrict__ slot,
+                           const uint16_t* __restrict__ fr, const double* __restrict__ b, double* __restrict__ y) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= nnodes * 12) return;
+    const int node = e / 12, w = e % 12;
+    double v = y[e];
+    for (int k = lptr[node]; k < lptr[node + 1]; ++k) v += slot[(size_t)k * 12 + w];
+    if (b) v = b[e] - v;
+    if (!is_free(fr, node, w)) v = 0.0;
+    y[e] = v;
 }
 
 // ---------------------------------------------------- block-Jacobi factor
@@ -366,20 +437,25 @@ __device__ __forceinline__ bool reduce_barrier(ShellSync* ss, double* __restrict
 // contiguous set of blocks and node rows; the only synchronisation is the
 // per-shell reduce-barrier (two per iteration).  p is double-buffered so that
 // the update p = z + beta p is fused into the matrix product:
-//   phase A: p_new = z + beta p_old (own rows), q = A (z + beta p_old), sum p.q
-//   phase B: x += alpha p, r -= alpha q, z = Dinv r, sums r.z and r.r
+//   phase A: p_new = z + beta p_old (own rows); the stored blocks give
+//            u = (A_ii p_i + sum_{j>i} A_ij p_j) into qv and A_ji p_i into
+//            the slots; p^T A p = sum_i (2 p_i.u_i - p_i^T A_ii p_i)
+//   phase B: q = u + own slots (masked), x += alpha p, r -= alpha q,
+//            z = Dinv r, sums r.z and r.r
 template <class TM, class TV, int NT>
 __global__ __launch_bounds__(NT) void k_cg(
     const int* __restrict__ blk_shell, const int* __restrict__ blk_row0, const int* __restrict__ blk_row1,
-    const int* __restrict__ shell_blk0, const int* __restrict__ shell_nblk, const int* __restrict__ row_ptr,
-    const int* __restrict__ col_idx, const TM* __restrict__ vals, const TV* __restrict__ dinv,
-    const uint16_t* __restrict__ fm, const double* __restrict__ b, TV* __restrict__ x, TV* __restrict__ r,
-    TV* __restrict__ z, TV* __restrict__ p0, TV* __restrict__ p1, TV* __restrict__ qv, double* __restrict__ partial,
+    const int* __restrict__ shell_blk0, const int* __restrict__ shell_nblk, SymBsr m,
+    const TM* __restrict__ vals, const TV* __restrict__ dinv, const uint16_t* __restrict__ fm,
+    const double* __restrict__ b, TV* __restrict__ x, TV* __restrict__ r, TV* __restrict__ z, TV* __restrict__ p0,
+    TV* __restrict__ p1, TV* __restrict__ qv, TV* __restrict__ slot, double* __restrict__ partial,
     ShellSync* __restrict__ sync, int* __restrict__ abort_flag, const double* __restrict__ rtol2_shell,
     const int* __restrict__ maxit_shell, const int* __restrict__ active_shell, CgShellOut* __restrict__ out) {
     constexpr int R = Lay<TM>::R, L = Lay<TM>::L, G = Lay<TM>::G;
     constexpr int NW = NT / 64;
     __shared__ double lds[4 * NW];
+    __shared__ TV red[NW][64 * 12];
+    __shared__ TV xls[NW][G * 12];
     const int blk = blockIdx.x;
     const int sh = blk_shell[blk];
     const int row0 = blk_row0[blk], row1 = blk_row1[blk];
@@ -465,27 +541,25 @@ __global__ __launch_bounds__(NT) void k_cg(
         for (int base = row0; base < row1; base += rows_per_pass) {
             const int node = base + wv * G + grp;
             if (!(lane_ok && node < row1)) continue;
-            const unsigned fmask = fm[node];   // loaded first: later waits on it drain nothing else
-            TV acc[R];
             const TV bt = (TV)beta;
-            row_times_grouped<TM, TV>(row_ptr, col_idx, vals, node, t, gsrc, false,
-                              [&](int col, TV* xv) {
+            auto xe = [&](int col, TV* xv) {
 #pragma unroll
-                                  for (int i = 0; i < R; ++i) {
-                                      const size_t at = (size_t)col * 12 + R * t + i;
-                                      xv[i] = z[at] + bt * pin[at];
-                                  }
-                              },
-                              acc);
+                for (int i = 0; i < R; ++i) {
+                    const size_t at = (size_t)col * 12 + R * t + i;
+                    xv[i] = z[at] + bt * pin[at];
+                }
+            };
+            TV pn[R], part[12], u[R];
+            xe(node, pn);
+            const TV dl = row_sym<TM, TV, false>(m, vals, node, t, pn, xe, xls[wv] + grp * 12, slot, part);
+            group_sum<TV, R, L>(part, lane, t, gsrc, red[wv], u);
+            pq[0] -= (double)dl;
 #pragma unroll
             for (int i = 0; i < R; ++i) {
-                const int w = R * t + i;
-                const size_t at = (size_t)node * 12 + w;
-                const TV pn = z[at] + bt * pin[at];
-                const TV qq = ((fmask >> w) & 1u) ? acc[i] : TV(0);
-                pout[at] = pn;
-                qv[at] = qq;
-                pq[0] += (double)pn * (double)qq;
+                const size_t at = (size_t)node * 12 + R * t + i;
+                pout[at] = pn[i];
+                qv[at] = u[i];
+                pq[0] += 2.0 * (double)pn[i] * (double)u[i];
             }
         }
         if (!reduce_barrier<1, NW>(ss, partial, blk, sb0, snb, nbar++, pq, abort_flag, lds)) {
@@ -505,14 +579,33 @@ __global__ __launch_bounds__(NT) void k_cg(
             const int nd = ok ? node : row0;
             // every load of the row is issued before the first use
             const unsigned fmask = fm[nd];
-            TV rr[R], zz[R], xo[R], pp[R];
+            const int k0 = m.lptr[nd], k1 = m.lptr[nd + 1];
+            TV rr[R], zz[R], xo[R], pp[R], qq[R];
 #pragma unroll
             for (int i = 0; i < R; ++i) {
                 const size_t at = (size_t)nd * 12 + R * t + i;
-                rr[i] = r[at] - (TV)alpha * qv[at];
+                rr[i] = r[at];
+                qq[i] = qv[at];
                 xo[i] = x[at];
                 pp[i] = pout[at];
             }
+            // the transposed products of the rows above (4 per interior node)
+            for (int k = k0; k < k1; k += 4) {
+                TV sv[4][R];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int kk = k + u < k1 ? k + u : k0;
+                    VecLoad<TV, R>::ld(slot + (size_t)kk * 12 + R * t, sv[u]);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int i = 0; i < R; ++i)
+                        if (k + u < k1) qq[i] += sv[u][i];
+            }
+#pragma unroll
+            for (int i = 0; i < R; ++i)
+                if ((fmask >> (R * t + i)) & 1u) rr[i] -= (TV)alpha * qq[i];
             precond(nd, rr, zz);
             if (ok) {
 #pragma unroll
@@ -676,17 +769,24 @@ void launch_zero(hipStream_t st, void* p, size_t bytes) {
 }
 
 template <class TM>
-void launch_spmv(hipStream_t st, int nnodes, const int* row_ptr, const int* col_idx, const TM* vals,
-                 const uint16_t* freemask, const double* x, const double* b, double* y, int mode) {
+void launch_spmv(hipStream_t st, int nnodes, const SymBsr& m, const TM* vals, const uint16_t* freemask,
+                 const double* x, const double* b, double* y, double* slot, int mode) {
     if (nnodes == 0) return;
     const int rows_per_block = 4 * Lay<TM>::G;
-    hipLaunchKernelGGL(k_spmv<TM>, dim3((nnodes + rows_per_block - 1) / rows_per_block), dim3(256), 0, st, nnodes,
-                       row_ptr, col_idx, vals, freemask, x, b, y, mode);
+    const dim3 grid((nnodes + rows_per_block - 1) / rows_per_block);
+    const uint16_t* fc = (mode & 1) ? freemask : nullptr;         // free columns only
+    const uint16_t* fr = (mode & (1 | 8)) ? freemask : nullptr;   // free rows only
+    if (mode & 2)
+        hipLaunchKernelGGL((k_spmv_rows<TM, true>), grid, dim3(256), 0, st, nnodes, m, vals, fc, x, y, slot);
+    else
+        hipLaunchKernelGGL((k_spmv_rows<TM, false>), grid, dim3(256), 0, st, nnodes, m, vals, fc, x, y, slot);
+    hipLaunchKernelGGL(k_spmv_fin, grid1(nnodes * 12), dim3(256), 0, st, nnodes, m.lptr, slot, fr,
+                       (mode & 4) ? b : nullptr, y);
 }
-template void launch_spmv<double>(hipStream_t, int, const int*, const int*, const double*, const uint16_t*,
-                                  const double*, const double*, double*, int);
-template void launch_spmv<float>(hipStream_t, int, const int*, const int*, const float*, const uint16_t*,
-                                 const double*, const double*, double*, int);
+template void launch_spmv<double>(hipStream_t, int, const SymBsr&, const double*, const uint16_t*, const double*,
+                                  const double*, double*, double*, int);
+template void launch_spmv<float>(hipStream_t, int, const SymBsr&, const float*, const uint16_t*, const double*,
+                                 const double*, double*, double*, int);
 
 template <class TV>
 void launch_bj_factor(hipStream_t st, int nnodes, const int* diag_blk, const void* vals, int vals_fp32,
@@ -719,26 +819,27 @@ template <class TM, class TV> const void* cg_fn(int nthreads) {
 }
 
 template <class TM, class TV>
-hipError_t launch_cg(hipStream_t st, int nblk, int nthreads, const RowBlocks& rb, const int* row_ptr,
-                     const int* col_idx, const TM* vals, const TV* dinv, const uint16_t* freemask, const double* b,
-                     TV* x, TV* r, TV* z, TV* p0, TV* p1, TV* qv, double* partial, void* sync, int* abort_flag,
-                     const double* rtol2_shell, const int* maxit_shell, const int* active_shell, CgShellOut* out) {
+hipError_t launch_cg(hipStream_t st, int nblk, int nthreads, const RowBlocks& rb, const SymBsr& m, const TM* vals,
+                     const TV* dinv, const uint16_t* freemask, const double* b, TV* x, TV* r, TV* z, TV* p0, TV* p1,
+                     TV* qv, TV* slot, double* partial, void* sync, int* abort_flag, const double* rtol2_shell,
+                     const int* maxit_shell, const int* active_shell, CgShellOut* out) {
     ShellSync* ss = static_cast<ShellSync*>(sync);
+    SymBsr mm = m;
     void* args[] = {(void*)&rb.blk_shell, (void*)&rb.blk_row0, (void*)&rb.blk_row1, (void*)&rb.shell_blk0,
-                    (void*)&rb.shell_nblk, (void*)&row_ptr, (void*)&col_idx, (void*)&vals, (void*)&dinv,
-                    (void*)&freemask, (void*)&b, (void*)&x, (void*)&r, (void*)&z, (void*)&p0, (void*)&p1,
-                    (void*)&qv, (void*)&partial, (void*)&ss, (void*)&abort_flag, (void*)&rtol2_shell,
-                    (void*)&maxit_shell, (void*)&active_shell, (void*)&out};
+                    (void*)&rb.shell_nblk, (void*)&mm, (void*)&vals, (void*)&dinv, (void*)&freemask, (void*)&b,
+                    (void*)&x, (void*)&r, (void*)&z, (void*)&p0, (void*)&p1, (void*)&qv, (void*)&slot,
+                    (void*)&partial, (void*)&ss, (void*)&abort_flag, (void*)&rtol2_shell, (void*)&maxit_shell,
+                    (void*)&active_shell, (void*)&out};
     return hipLaunchCooperativeKernel(cg_fn<TM, TV>(nthreads), dim3(nblk), dim3(nthreads), args, 0, st);
 }
-template hipError_t launch_cg<double, double>(hipStream_t, int, int, const RowBlocks&, const int*, const int*,
-                                              const double*, const double*, const uint16_t*, const double*, double*,
+template hipError_t launch_cg<double, double>(hipStream_t, int, int, const RowBlocks&, const SymBsr&, const double*,
+                                              const double*, const uint16_t*, const double*, double*, double*,
                                               double*, double*, double*, double*, double*, double*, void*, int*,
                                               const double*, const int*, const int*, CgShellOut*);
-template hipError_t launch_cg<float, float>(hipStream_t, int, int, const RowBlocks&, const int*, const int*,
-                                            const float*, const float*, const uint16_t*, const double*, float*,
-                                            float*, float*, float*, float*, float*, double*, void*, int*,
-                                            const double*, const int*, const int*, CgShellOut*);
+template hipError_t launch_cg<float, float>(hipStream_t, int, int, const RowBlocks&, const SymBsr&, const float*,
+                                            const float*, const uint16_t*, const double*, float*, float*, float*,
+                                            float*, float*, float*, float*, double*, void*, int*, const double*,
+                                            const int*, const int*, CgShellOut*);
 
 size_t cg_sync_bytes() { return sizeof(ShellSync); }
 int cg_rows_per_pass(int tm_fp32, int nthreads) { return (nthreads / 64) * (tm_fp32 ? Lay<float>::G : Lay<double>::G); }
