@@ -212,6 +212,75 @@ def roofline(case, timing, fp32):
                  "traffic": None, "avg_launch_ms": per_launch_ms}
 
 
+def spmv_bytes(stored, rows, s):
+    """Algorithmic HBM bytes of one stand-alone SpMV (two launches) with the
+    symmetric storage: every stored block (144 values of s bytes; off the
+    diagonal a column and a slot index, and the 12 FP64 values of its
+    transposed product written and read back); per row the row pointer,
+    slot range and free mask (10 bytes), x read once, y written, then read
+    and written again by the slot-summing launch (4 passes of 12 FP64)."""
+    off = stored - rows
+    return stored * 144 * s + off * (8 + 2 * 96) + rows * (10 + 4 * 96)
+
+
+def assembly_bytes(patches, stored, rows, s):
+    """Algorithmic HBM bytes of one Hessian assembly: each patch adds its 10
+    stored node blocks (4 diagonal, 6 of the upper triangle) into the matrix,
+    a read and a write of 144 values each, except the first touch of every
+    stored block (a write only); the state q and reference q-bar read once
+    per node."""
+    return (2 * 10 * patches - stored) * 144 * s + rows * 2 * 96
+
+
+def kernels_section(case, stream, reps=20):
+    """Stand-alone rooflines on the workload's matrix at its initial state
+    (K(q0) + M/dt^2): the SpMV (masked, both launches) against 8 TB/s, the
+    Hessian assembly against the MFMA peak of its precision and (as the
+    spec figure) assembly + SpMV bytes against 8 TB/s."""
+    import torch
+    from paper_2312_14839_amd import shell as S
+    out = {}
+    for name, prec, s, peak in (("fp64", S.SHELL_FP64, 8, FP64_PEAK_TFLOPS), ("fp32", S.SHELL_MIXED, 4, FP32_PEAK_TFLOPS)):
+        ctx = S.context_for(shells_of(case), precision=prec, stream=stream)
+        rows = ctx.total_nodes
+        stored = (ctx.nnzb + rows) // 2
+        q = torch.from_numpy(case.q0.reshape(-1).copy()).cuda()
+        ms = 1.0 / case.dt ** 2
+        ctx.assemble(q, mass_scale=ms)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(5)
+        x = torch.randn(q.shape, dtype=q.dtype, device="cuda", generator=g)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            ctx.spmv(x, y, masked=True)
+            ctx.assemble(q, mass_scale=ms)
+        ctx.timing_enable(True)
+        for _ in range(reps):
+            ctx.spmv(x, y, masked=True)
+        for _ in range(reps // 4):
+            ctx.assemble(q, mass_scale=ms)
+        t = ctx.timing_get()
+        ctx.timing_enable(False)
+        ctx.close()
+        t_spmv = t["ms"]["spmv"] / reps * 1e-3
+        t_asm = t["ms"]["hessian"] / (reps // 4) * 1e-3
+        b_spmv = spmv_bytes(stored, rows, s)
+        b_asm = assembly_bytes(case.patches, stored, rows, s)
+        fl_asm = case.patches * HESS_MFMA_FLOPS
+        out[name] = {
+            "spmv": {"us": t_spmv * 1e6, "bytes": b_spmv, "GB_s": b_spmv / t_spmv / 1e9,
+                     "frac_hbm": b_spmv / t_spmv / 1e9 / HBM_PEAK_GBS},
+            "assembly": {"ms": t_asm * 1e3, "mfma_TFLOP_s": fl_asm / t_asm / 1e12,
+                         "frac_mfma": fl_asm / t_asm / 1e12 / peak, "bytes": b_asm,
+                         "GB_s": b_asm / t_asm / 1e9},
+            "assembly_plus_spmv_frac_hbm": (b_spmv + b_asm) / (t_spmv + t_asm) / 1e9 / HBM_PEAK_GBS,
+        }
+        print(f"[bench] {name}: SpMV {t_spmv * 1e6:.1f} us ({b_spmv / t_spmv / 1e9:.0f} GB/s), assembly "
+              f"{t_asm * 1e3:.3f} ms ({fl_asm / t_asm / 1e12:.1f} TFLOP/s MFMA, {b_asm / t_asm / 1e9:.0f} GB/s)",
+              file=sys.stderr, flush=True)
+    return out
+
+
 def pseudo_hessian_section(stream, steps=3, warmup=1):
     """Exact vs pseudo Hessian (the bending geometric term dropped) on the
     256x256 cylinder, FP64: Newton and CG iterations and time per step."""
@@ -381,6 +450,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-post-buckling", action="store_true")
     ap.add_argument("--no-pseudo", action="store_true")
+    ap.add_argument("--no-kernels", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="first run a plain device copy of MB megabytes (counter calibration)")
     args = ap.parse_args()
@@ -441,6 +511,8 @@ def main():
                         "cg_iters_per_step": sum(s["pcg_iters_total"] for s in stm) / args.steps,
                         "kernel_ms": tmm["ms"], "roofline": roofm}
         print(f"[bench] mixed: {1e3 * wallm / args.steps:.2f} ms/step, err {err:.2e}", file=sys.stderr, flush=True)
+    if not args.no_kernels:
+        out["kernels"] = kernels_section(case, stream)
     if args.workload == "cylinder" and not args.no_post_buckling:
         out["post_buckling"] = post_buckling_section(stream)
     if args.workload == "cylinder" and not args.no_pseudo:

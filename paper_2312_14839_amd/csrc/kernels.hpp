@@ -70,7 +70,7 @@ void launch_regularize(hipStream_t st, int nnodes, const int* diag_blk, void* va
 template <class TM, class TV>
 hipError_t launch_cg(hipStream_t st, int nblk, int nthreads, const RowBlocks& rb, const SymBsr& m, const TM* vals,
                      const TV* dinv, const uint16_t* freemask, const double* b, TV* x, TV* r, TV* z, TV* p0, TV* p1,
-                     TV* qv, TV* slot, double* partial, void* sync, int* abort_flag, const double* rtol2_shell,
+                     TV* qv, TV* slot, double* partial /* [2][nblk][4] */, void* sync, int* abort_flag, const double* rtol2_shell,
                      const int* maxit_shell, const int* active_shell, CgShellOut* out);
 int cg_max_blocks(int device, int tm_fp32, int nthreads);   // co-resident blocks of the CG kernel
 size_t cg_sync_bytes();                                     // per-shell synchronisation state of the CG kernel

@@ -325,7 +325,7 @@ bool set_row_blocks(shell_ctx* c, int nt, int spread) {
     upload(c->shell_blk0, c->h_shell_blk0, st);
     upload(c->shell_nblk, c->h_shell_nblk, st);
     alloc(c->red_part, (size_t)c->nblk * sizeof(double));
-    alloc(c->cg_partial, (size_t)c->nblk * 4 * sizeof(double));
+    alloc(c->cg_partial, (size_t)c->nblk * 8 * sizeof(double));   // [2][nblk][4]: by barrier parity
     alloc(c->feat_part, (size_t)c->nblk * 12 * sizeof(double));
     sync(c);
     c->graphs_reset();

@@ -128,11 +128,14 @@ __device__ __forceinline__ void group_sum(const TV (&part)[12], int lane, int t,
 // the whole block's registers live through them).  A scheduling barrier
 // after each part keeps one part's loads in flight at a time per wave (more
 // registers per wave measured no faster: the waves of a CU keep enough
-// loads in flight).
+// loads in flight).  pst/pv: the previous block's transposed product, stored
+// after this block's first loads are issued (loads and stores share one
+// in-order completion counter, so a store issued first would delay the
+// wait for the loads behind it).
 template <class TM, class TV, bool ABS, bool FIRST>
 __device__ __forceinline__ void block_sym(const TM* __restrict__ blk, const TV (&xv)[Lay<TM>::R],
                                           const TV* __restrict__ xl, TV (&part)[12], TV (&tv)[Lay<TM>::R],
-                                          TV& dl) {
+                                          TV& dl, TV* pst = nullptr, const TV* pv = nullptr) {
     constexpr int R = Lay<TM>::R;
     asm volatile("" ::: "memory");   // re-read xl for this block
 #pragma unroll
@@ -140,6 +143,7 @@ __device__ __forceinline__ void block_sym(const TM* __restrict__ blk, const TV (
         TM a[4][R];
 #pragma unroll
         for (int c = 0; c < 4; ++c) VecLoad<TM, R>::ld(blk + (4 * h + c) * 12, a[c]);
+        if (h == 0 && pst) VecStore<TV, R>::st(pst, pv);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const int cc = 4 * h + c;
@@ -177,15 +181,20 @@ __device__ __forceinline__ TV row_sym(const SymBsr& m, const TM* __restrict__ va
     wave_lds_sync();
     TV dl = TV(0), tv0[R];
     block_sym<TM, TV, ABS, true>(vals + (size_t)b0 * 144 + R * t, xo, xl, part, tv0, dl);
+    TV pv[R];
+    TV* pst = nullptr;
     for (int b = b0 + 1; b < b1; ++b) {
         TV xv[R], tv[R];
         xe(m.col_idx[b], xv);
         const int ts = m.tslot[b];
 #pragma unroll
         for (int k = 0; k < R; ++k) tv[k] = TV(0);
-        block_sym<TM, TV, ABS, false>(vals + (size_t)b * 144 + R * t, xv, xl, part, tv, dl);
-        VecStore<TV, R>::st(slot + (size_t)ts * 12 + R * t, tv);
+        block_sym<TM, TV, ABS, false>(vals + (size_t)b * 144 + R * t, xv, xl, part, tv, dl, pst, pv);
+        pst = slot + (size_t)ts * 12 + R * t;
+#pragma unroll
+        for (int k = 0; k < R; ++k) pv[k] = tv[k];
     }
+    if (pst) VecStore<TV, R>::st(pst, pv);
     wave_lds_sync();
     return dl;
 }
@@ -351,85 +360,82 @@ template <int N, int NW> __device__ __forceinline__ void block_sum(double (&v)[N
 constexpr int CG_GROUPS = 16;
 struct alignas(128) ShellSync {
     unsigned cnt;        // top-level arrivals (group leaders), monotone
-    unsigned gen;        // barriers released so far
-    unsigned pad0[30];
-    double tot[2][4];    // published totals, by barrier parity
-    double pad1[8];
+    unsigned pad0[31];
     unsigned gcnt[CG_GROUPS][32];   // per-group arrivals, monotone, one line each
 };
 
-// Barrier over the nblk blocks of one shell that also sums one partial
-// vector per block.  The last block to arrive adds the partials of the shell
-// in block order (so every block gets the same, reproducible totals),
-// publishes them and releases the others.  Every wait is bounded: after 2^22
-// polls, or when another block has given up, the block sets abort and the
-// kernel ends (legitimate waits are one matrix-product phase).
+// Barrier over the snb blocks of one shell that also sums one partial
+// vector per block.  Each block writes its partials, publishes them (and the
+// phase's vector writes) with one release fence and arrives; once the top
+// counter shows every group complete, each block's first wavefront sums the
+// shell's partials in block order -- the same operations in every block, so
+// all blocks get the same, reproducible totals, and no block has to publish
+// them for the others.  Partials are double-buffered by barrier parity
+// (part[2][nblk][4]): a block overwrites its record of barrier k only at
+// barrier k + 2, after every block has passed barrier k + 1 and so finished
+// reading it.  Every wait is bounded: after 2^22 polls, or when another
+// block has given up, the block sets abort and the kernel ends (legitimate
+// waits are one matrix-product phase).
 template <int N, int NW>
 __device__ __forceinline__ bool reduce_barrier(ShellSync* ss, double* __restrict__ part, int blk, int sb0, int snb,
                                                unsigned k, double (&v)[N], int* abort_flag, double* lds) {
-    __shared__ int s_last, s_ok;
+    __shared__ int s_ok;
+    __shared__ double s_tot[N];
     block_sum<N, NW>(v, lds);
+    double* buf = part + (size_t)(k & 1) * 4 * gridDim.x;
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int n = 0; n < N; ++n) part[4 * (size_t)blk + n] = v[n];
-        // one release fence publishes this block's vector writes and partial
+        for (int n = 0; n < N; ++n) buf[4 * (size_t)blk + n] = v[n];
+        // one release fence publishes this block's vector writes and partials
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         const int ng = snb < CG_GROUPS ? snb : CG_GROUPS;
         const int lb = blk - sb0, g = lb % ng;
         const unsigned gsize = (unsigned)((snb - g + ng - 1) / ng);
-        int last = 0;
         const unsigned og = __hip_atomic_fetch_add(&ss->gcnt[g][0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (og == gsize * (k + 1) - 1) {
             // last of its group: carry the group's arrival to the top counter
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-            const unsigned ot = __hip_atomic_fetch_add(&ss->cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            last = ot == (unsigned)ng * (k + 1) - 1;
+            __hip_atomic_fetch_add(&ss->cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        s_last = last;
-        s_ok = 1;
-    }
-    __syncthreads();
-    if (s_last) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        double t[N];
-#pragma unroll
-        for (int n = 0; n < N; ++n) t[n] = 0.0;
-        for (int i = threadIdx.x; i < snb; i += blockDim.x)
-#pragma unroll
-            for (int n = 0; n < N; ++n)
-                t[n] += __hip_atomic_load(&part[4 * (size_t)(sb0 + i) + n], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        block_sum<N, NW>(t, lds);
-#pragma unroll
-        for (int n = 0; n < N; ++n) v[n] = t[n];
-        if (threadIdx.x == 0) {
-#pragma unroll
-            for (int n = 0; n < N; ++n)
-                __hip_atomic_store(&ss->tot[k & 1][n], t[n], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __hip_atomic_store(&ss->gen, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __syncthreads();
-        return true;
-    }
-    if (threadIdx.x == 0) {
-        // poll with plain coherent loads; one acquire fence once released
+        // poll with plain coherent loads
+        int ok = 1;
         unsigned spins = 0;
-        while (__hip_atomic_load(&ss->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < k + 1) {
-            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
-                ++spins > (1u << 22)) {
+        while (__hip_atomic_load(&ss->cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)ng * (k + 1)) {
+            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || ++spins > (1u << 22)) {
                 __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                s_ok = 0;
+                ok = 0;
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
         }
+        s_ok = ok;
+    }
+    __syncthreads();
+    if (!s_ok) return false;
+    if (threadIdx.x < 64) {
+        // the wavefront of the polling thread: one acquire fence, then the
+        // partials in block order (lane i: blocks i, i + 64, ...) and a
+        // fixed butterfly over the lanes
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        double t[N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) t[n] = 0.0;
+        for (int i = threadIdx.x; i < snb; i += 64)
+#pragma unroll
+            for (int n = 0; n < N; ++n)
+                t[n] += __hip_atomic_load(&buf[4 * (size_t)(sb0 + i) + n], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+        for (int n = 0; n < N; ++n)
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) t[n] += __shfl_xor(t[n], off);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int n = 0; n < N; ++n) s_tot[n] = t[n];
     }
     __syncthreads();
 #pragma unroll
-    for (int n = 0; n < N; ++n)
-        v[n] = __hip_atomic_load(&ss->tot[k & 1][n], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return s_ok != 0;
+    for (int n = 0; n < N; ++n) v[n] = s_tot[n];
+    return true;
 }
 
 // ---------------------------------------------------- persistent CG

@@ -77,6 +77,42 @@ def test_hessian_blocks(name, precision, pseudo):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_stored_triangle_expands_to_the_full_symmetric_matrix(precision):
+    """The device stores the diagonal and upper-triangle blocks once; the
+    returned matrix has the full pattern (the oracle's non-zero blocks, the
+    block count shell_sizes reports), its blocks below the diagonal are the
+    exact transposes of their mirror images, its diagonal blocks are
+    symmetric to rounding, and the SpMV applies exactly this matrix (sheet
+    and a periodic cylinder whose seam puts blocks of both triangles in one
+    patch)."""
+    sh = S()
+    for case in (W.case_twist(9), W.case_cylinder(7, 3)):
+        q = _state(case)
+        ctx = sh.context_for([case], precision=sh.SHELL_MIXED if precision == "mixed" else sh.SHELL_FP64)
+        ctx.assemble(dev(q), mass_scale=1.0 / case.dt ** 2)
+        row_ptr, col_idx, vals = ctx.get_bsr(0)
+        assert len(col_idx) == ctx.nnzb
+        A = bsr_from_gpu(row_ptr, col_idx, vals)
+        K_ref = oracle_matrix(case, q, "hessian")
+        assert A.nnz == K_ref.nnz
+        blocks = {}
+        for r in range(case.nodes):
+            for k in range(row_ptr[r], row_ptr[r + 1]):
+                blocks[(r, col_idx[k])] = vals[k]
+        for (r, c), blk in blocks.items():
+            if r != c:
+                assert np.array_equal(blk, blocks[(c, r)].T), (r, c)
+            else:
+                tol = 1e-14 if precision == "fp64" else 1e-6
+                assert np.abs(blk - blk.T).max() <= tol * np.abs(blk).max()
+        x = np.random.default_rng(3).normal(size=case.nodes * 12)
+        y = torch.zeros_like(dev(x))
+        ctx.spmv(dev(x), y, masked=False)
+        assert np.abs(host(y) - A @ x).max() <= 1e-13 * np.abs(A @ x).max()
+        ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_mass_blocks_and_pattern(precision):
     case = W.case_cylinder(7, 3)
     sh = S()
