@@ -515,13 +515,15 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
             if (!touched[k]) throw InvalErr{"internal: matrix block without a patch"};
     }
     // CG row blocks: contiguous node rows, never straddling a shell.  Large
-    // shells use 512-thread blocks (fewer blocks make the per-iteration
-    // barriers cheaper, and one such block per CU leaves each wave the
-    // registers of the symmetric product without spilling); small ones
-    // 256-thread blocks spread over more CUs.
+    // shells use big blocks (fewer blocks make the per-iteration barriers
+    // cheaper): 1024 threads with FP32 matrices, 512 with FP64 ones (one
+    // such block per CU leaves each wave the registers of the symmetric
+    // product without spilling); small shells 256-thread blocks spread over
+    // more CUs.
     int max_rows = 0;
     for (int s = 0; s < S; ++s) max_rows = std::max(max_rows, c->shells[s].node_end - c->shells[s].node_begin);
-    const int nt0 = max_rows >= 16 * cg_rows_per_pass(c->fp32, 512) ? 512 : 256;
+    const int big = c->fp32 ? 1024 : 512;
+    const int nt0 = max_rows >= 16 * cg_rows_per_pass(c->fp32, big) ? big : 256;
     if (!set_row_blocks(c, nt0, 1) && !set_row_blocks(c, 256, 1))
         throw InvalErr{"too many shells for one context (limit " +
                        std::to_string(cg_max_blocks(c->opts.device, c->fp32, 256)) + ")"};

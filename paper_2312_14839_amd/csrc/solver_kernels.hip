@@ -10,11 +10,13 @@
 // solver masks them (free-DOF bit masks per node), which equals replacing
 // them by identity rows and columns with a zero right-hand side.
 //
-// Product lane layout: a node row is handled by L = 12/R lanes.  Lane t of
-// the group reads the 16 bytes at offset c*12 + R*t of every row c of a
-// stored block (R = 2 for FP64 blocks, 4 for FP32), so each of its 12 loads
-// is one coalesced 16-byte load and the lane owns columns R*t .. R*t+R-1 of
-// A_ij.  Both products a stored block takes part in are then lane-local:
+// Product lane layout: a node row is handled by L = 6 lanes.  Lane t of the
+// group reads the R = 2 values at offset c*12 + 2t of every row c of a
+// stored block (16 bytes for FP64 blocks, 8 for FP32; the six lanes of a
+// group read one row's 12 values together, coalesced), and owns columns
+// 2t, 2t+1 of A_ij.  (Four FP32 columns per lane, 16-byte loads, were
+// measured slower: 21 rows per wavefront leave more blocks on a partial
+// last pass and need more registers.)  Both products a stored block takes part in are then lane-local:
 //   A_ij x_j   partial sums over the lane's columns for all 12 rows, summed
 //              over the group once per block row;
 //   A_ji x_i = A_ij^T x_i   the lane's R entries, which row j needs.
@@ -30,9 +32,9 @@
 namespace bhem {
 
 template <class TM> struct Lay {
-    static constexpr int R = 16 / sizeof(TM);   // columns per lane
-    static constexpr int L = 12 / R;             // lanes per node row
-    static constexpr int G = 64 / L;             // node rows per wavefront
+    static constexpr int R = 2;        // columns per lane
+    static constexpr int L = 12 / R;   // lanes per node row
+    static constexpr int G = 64 / L;   // node rows per wavefront
 };
 
 __device__ __forceinline__ bool is_free(const uint16_t* m, int node, int w) { return !m || ((m[node] >> w) & 1); }
@@ -54,6 +56,13 @@ template <> struct VecLoad<double, 4> {
         o[3] = v1.y;
     }
 };
+template <> struct VecLoad<float, 2> {
+    static __device__ __forceinline__ void ld(const float* p, float* o) {
+        const float2 v = *reinterpret_cast<const float2*>(p);
+        o[0] = v.x;
+        o[1] = v.y;
+    }
+};
 template <> struct VecLoad<float, 4> {
     static __device__ __forceinline__ void ld(const float* p, float* o) {
         const float4 v = *reinterpret_cast<const float4*>(p);
@@ -67,6 +76,11 @@ template <class TV, int R> struct VecStore;
 template <> struct VecStore<double, 2> {
     static __device__ __forceinline__ void st(double* p, const double* v) {
         *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+    }
+};
+template <> struct VecStore<float, 2> {
+    static __device__ __forceinline__ void st(float* p, const float* v) {
+        *reinterpret_cast<float2*>(p) = make_float2(v[0], v[1]);
     }
 };
 template <> struct VecStore<float, 4> {
@@ -117,7 +131,7 @@ __device__ __forceinline__ void group_sum(const TV (&part)[12], int lane, int t,
     wave_lds_sync();
 }
 
-// One stored block in three parts of 4 rows (4 loads of 16 bytes each):
+// One stored block in three parts of 4 rows (4 loads of R values each):
 // part[c] += sum_k A[c][R t + k] xv[k] and tv[k] += sum_c A[c][R t + k] x_i[c],
 // with x_i[c] read from the group's LDS copy xl (re-read per block: kept in
 // registers through the row, the 12 values would cost the registers that
