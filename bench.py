@@ -415,27 +415,54 @@ def learned_section(stream):
     return out
 
 
-def cpu_baseline(budget_s=15.0):
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(budget_s=12.0, budget_1t=8.0):
     """Oracle patch energy + gradient + Hessian evaluations per second on a
-    32x32-patch cylinder section (1024 patches), all host threads."""
+    32x32-patch cylinder section (1024 patches): all host threads (the
+    reported value), then one thread (OpenMP thread count set through the
+    runtime the oracle library links)."""
+    import ctypes
     from oracle import oracle as O
     from paper_2312_14839_amd import workloads as W
     c = W.case_cylinder(32, 32)
     s = O.shell_from_case(c)
     q = W.random_state(c, 1, 1e-4, 1e-3)
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        O.energy(s, q, c.ref)
-        O.gradient(s, q, c.ref)
-        O.matrix_blocks(s, q, c.ref, "hessian")
-        reps += 1
-        el = time.perf_counter() - t0
-        if el > budget_s or reps >= 400:
-            break
+
+    def rate(budget, max_reps):
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            O.energy(s, q, c.ref)
+            O.gradient(s, q, c.ref)
+            O.matrix_blocks(s, q, c.ref, "hessian")
+            reps += 1
+            el = time.perf_counter() - t0
+            if el > budget or reps >= max_reps:
+                return reps, el
+
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": reps * c.patches / el, "unit": "patch E/grad/Hess evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"E+grad+Hess of the {c.patches} patches of a 32x32-patch cylinder section, {reps} reps, "
-                      f"{el:.1f} s"}
+    reps, el = rate(budget_s, 400)
+    out = {"value": reps * c.patches / el, "unit": "patch E/grad/Hess evals/s", "cores": cores, "kind": "oracle",
+           "sample": f"E+grad+Hess of the {c.patches} patches of a 32x32-patch cylinder section, {reps} reps, "
+                     f"{el:.1f} s", "cpu_model": _cpu_model()}
+    try:
+        omp = ctypes.CDLL("libgomp.so.1")
+        omp.omp_set_num_threads(1)
+        r1, e1 = rate(budget_1t, 100)
+        omp.omp_set_num_threads(cores)
+        out["value_1thread"] = r1 * c.patches / e1
+        out["sample_1thread"] = f"{r1} reps, {e1:.1f} s on one thread"
+    except OSError:
+        out["value_1thread"] = None
+    return out
 
 
 def main():

@@ -47,29 +47,11 @@ template <> struct VecLoad<double, 2> {
         o[1] = v.y;
     }
 };
-template <> struct VecLoad<double, 4> {
-    static __device__ __forceinline__ void ld(const double* p, double* o) {
-        const double2 v0 = reinterpret_cast<const double2*>(p)[0], v1 = reinterpret_cast<const double2*>(p)[1];
-        o[0] = v0.x;
-        o[1] = v0.y;
-        o[2] = v1.x;
-        o[3] = v1.y;
-    }
-};
 template <> struct VecLoad<float, 2> {
     static __device__ __forceinline__ void ld(const float* p, float* o) {
         const float2 v = *reinterpret_cast<const float2*>(p);
         o[0] = v.x;
         o[1] = v.y;
-    }
-};
-template <> struct VecLoad<float, 4> {
-    static __device__ __forceinline__ void ld(const float* p, float* o) {
-        const float4 v = *reinterpret_cast<const float4*>(p);
-        o[0] = v.x;
-        o[1] = v.y;
-        o[2] = v.z;
-        o[3] = v.w;
     }
 };
 template <class TV, int R> struct VecStore;
@@ -86,12 +68,6 @@ template <> struct VecStore<float, 2> {
 template <> struct VecStore<float, 4> {
     static __device__ __forceinline__ void st(float* p, const float* v) {
         *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
-    }
-};
-template <> struct VecStore<double, 4> {
-    static __device__ __forceinline__ void st(double* p, const double* v) {
-        reinterpret_cast<double2*>(p)[0] = make_double2(v[0], v[1]);
-        reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
     }
 };
 
