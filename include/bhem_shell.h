@@ -123,7 +123,9 @@ void shell_destroy(shell_ctx *c);
 /* Message of the last error of c (of the last failed create if c is NULL). */
 const char *shell_last_error(const shell_ctx *c);
 
-/* Sizes: total nodes, total patches, and block non-zeros of the matrix. */
+/* Sizes: total nodes, total patches, and block non-zeros of the full matrix
+ * (both triangles; the device stores the diagonal and upper-triangle blocks,
+ * (nnzb + total_nodes) / 2 of them). */
 shell_status shell_sizes(const shell_ctx *c, int32_t *total_nodes, int32_t *total_patches, int64_t *nnzb);
 
 /* Elastic energy V_e of every shell at q (Sec. 3.3 energy density integrated

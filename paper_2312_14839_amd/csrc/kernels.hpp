@@ -16,6 +16,9 @@ void launch_gather_grad(hipStream_t st, int nnodes, const int* inc_ptr, const in
                         const uint16_t* freemask, const int* node_shell, const int* write_shell, double* grad);
 void launch_shell_energy(hipStream_t st, int nshell, const ShellParams* shells, const double* e_patch,
                          double* e_shell);
+// patch_slots[16 * p + m]: stored block of the patch's m-th stored local block
+// (-1 past the last), patch_kid[p]: its local block index in bits 4m..4m+3,
+// patch_first[p]: bit m set where patch p is the first to reach that block
 template <class T>
 void launch_hessian(hipStream_t st, const int* patch_list, int nlist, const int4* patch_nodes, const int* patch_shell,
                     const int* patch_slots, const uint64_t* patch_kid, const uint16_t* patch_first,

@@ -9,8 +9,9 @@
 //                       derivative W_g of the energy density (+ the mass term);
 //                    2. per component pair (i, j) the matrix cores contract
 //                       K^{ij} = sum_g Phi_g^T W_g^{ij} Phi_g  (16 x 80(96) x 16);
-//                    3. the 16 node blocks are added into the matrix
-//                       (patches of one colour share no node, so plain
+//                    3. the 10 node blocks the matrix stores (diagonal
+//                       and upper triangle) are added into it (patches of
+//                       one colour share no node, so plain
 //                       read-modify-write is race free; the first patch,
 //                       in colour order, to reach a block stores it, so
 //                       the matrix needs no zero fill).
