@@ -59,7 +59,7 @@ enum {
 
 enum { SHELL_FP64 = 0, SHELL_MIXED = 1 };             /* Hessian/SpMV precision */
 enum { SHELL_HESS_EXACT = 0, SHELL_HESS_PSEUDO = 1 };  /* Appendix B.2, last paragraph */
-enum { SHELL_WS_NONE = 0, SHELL_WS_MLP = 1 };          /* CG initial guess */
+enum { SHELL_WS_NONE = 0, SHELL_WS_MLP = 1 };          /* initial Newton iterate of each step */
 
 /* One shell (Sec. 4.1-4.2; material of Sec. 3.3; loads of Sec. 4.3). */
 typedef struct {
