@@ -54,6 +54,7 @@ struct shell_ctx {
     std::vector<uint16_t> h_freemask;
     std::vector<int> colour_off;   // [ncolour + 1] into the concatenated colour lists
     int nblk = 0;                  // CG row blocks
+    int cg_max_rows = 0;           // node rows of the largest CG block
     int cg_threads = 256;          // threads per CG block
     int cg_rows_target = 0;        // node rows per CG block (before the even split of a shell)
     std::vector<int> h_shell_blk0, h_shell_nblk;
@@ -121,8 +122,8 @@ struct shell_ctx {
     }
 
     RowBlocks rb() {
-        return RowBlocks{nblk, dptr<int>(blk_shell), dptr<int>(blk_row0), dptr<int>(blk_row1), dptr<int>(shell_blk0),
-                         dptr<int>(shell_nblk)};
+        return RowBlocks{nblk, cg_max_rows, dptr<int>(blk_shell), dptr<int>(blk_row0), dptr<int>(blk_row1),
+                         dptr<int>(shell_blk0), dptr<int>(shell_nblk)};
     }
     ~shell_ctx() {
         graphs_reset();
@@ -317,6 +318,8 @@ bool set_row_blocks(shell_ctx* c, int nt, int spread) {
     }
     hipStream_t st = c->stream;
     c->nblk = used;
+    c->cg_max_rows = 0;
+    for (int k = 0; k < used; ++k) c->cg_max_rows = std::max(c->cg_max_rows, brow1[k] - brow0[k]);
     c->cg_threads = nt;
     c->cg_rows_target = target;
     upload(c->blk_shell, bshell, st);

@@ -434,11 +434,20 @@ __device__ __forceinline__ bool reduce_barrier(ShellSync* ss, double* __restrict
 // per-shell reduce-barrier (two per iteration).  p is double-buffered so that
 // the update p = z + beta p is fused into the matrix product:
 //   phase A: p_new = z + beta p_old (own rows); the stored blocks give
-//            u = (A_ii p_i + sum_{j>i} A_ij p_j) into qv and A_ji p_i into
-//            the slots; p^T A p = sum_i (2 p_i.u_i - p_i^T A_ii p_i)
+//            u = (A_ii p_i + sum_{j>i} A_ij p_j) and A_ji p_i into the
+//            slots; p^T A p = sum_i (2 p_i.u_i - p_i^T A_ii p_i)
 //   phase B: q = u + own slots (masked), x += alpha p, r -= alpha q,
 //            z = Dinv r, sums r.z and r.r
-template <class TM, class TV, int NT>
+// A lane handles the same node rows (one per pass over the block's rows) in
+// every phase.  With MAXP > 0 the block has at most MAXP passes and u, r and
+// x of the lane's rows stay in registers for the whole solve (x is written
+// once at the end): only p, z and the slots, which other rows read, go
+// through memory.  Writes mixed into an HBM-bound read stream cost several
+// times their share of the bytes (measured: 25 MB of slot stores added to a
+// 379 MB block stream cost as much as 100 MB more of reads), so keeping
+// these three vectors resident saves more than their bytes.  MAXP = 0: any
+// number of passes, u, r and x in memory.
+template <class TM, class TV, int NT, int MAXP>
 __global__ __launch_bounds__(NT) void k_cg(
     const int* __restrict__ blk_shell, const int* __restrict__ blk_row0, const int* __restrict__ blk_row1,
     const int* __restrict__ shell_blk0, const int* __restrict__ shell_nblk, SymBsr m,
@@ -449,6 +458,7 @@ __global__ __launch_bounds__(NT) void k_cg(
     const int* __restrict__ maxit_shell, const int* __restrict__ active_shell, CgShellOut* __restrict__ out) {
     constexpr int R = Lay<TM>::R, L = Lay<TM>::L, G = Lay<TM>::G;
     constexpr int NW = NT / 64;
+    constexpr int NP = MAXP > 0 ? MAXP : 1;   // register-resident passes
     __shared__ double lds[4 * NW];
     __shared__ TV red[NW][64 * 12];
     __shared__ TV xls[NW][G * 12];
@@ -471,6 +481,39 @@ __global__ __launch_bounds__(NT) void k_cg(
         return;
     }
 
+    // Resident r, x, u of the lane's rows (MAXP > 0): entry 0 belongs to the
+    // current pass; after every pass (taken or not) the arrays rotate by one,
+    // so the loop body is emitted once and indexes its registers statically.
+    TV rk[NP][R], xk[NP][R], uk[NP][R];
+    auto rotate = [&]() {
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const TV r0 = rk[0][i], x0 = xk[0][i], u0 = uk[0][i];
+#pragma unroll
+            for (int q = 0; q + 1 < NP; ++q) {
+                rk[q][i] = rk[q + 1][i];
+                xk[q][i] = xk[q + 1][i];
+                uk[q][i] = uk[q + 1][i];
+            }
+            rk[NP - 1][i] = r0;
+            xk[NP - 1][i] = x0;
+            uk[NP - 1][i] = u0;
+        }
+    };
+    // runs f(base) over the block's passes
+    auto passes = [&](auto&& f) {
+        if constexpr (MAXP > 0) {
+#pragma unroll 1
+            for (int ps = 0; ps < MAXP; ++ps) {
+                const int base = row0 + ps * rows_per_pass;
+                if (base < row1) f(base);
+                rotate();
+            }
+        } else {
+            for (int base = row0; base < row1; base += rows_per_pass) f(base);
+        }
+    };
+
     // z = Dinv r for this lane's R rows of node (r of the node exchanged in the group)
     auto precond = [&](int node, const TV* rr, TV* zz) {
         TV rall[12];
@@ -488,7 +531,7 @@ __global__ __launch_bounds__(NT) void k_cg(
 
     // ---- init: r = b (masked), x = 0, p_old = 0, z = Dinv r; sums r.z and b.b
     double sums[2] = {0.0, 0.0};
-    for (int base = row0; base < row1; base += rows_per_pass) {
+    passes([&](int base) {
         const int node = base + wv * G + grp;
         const bool ok = lane_ok && node < row1;
         const int nd = ok ? node : row0;
@@ -505,7 +548,12 @@ __global__ __launch_bounds__(NT) void k_cg(
                 const int w = R * t + i;
                 const size_t at = (size_t)node * 12 + w;
                 if (!is_free(fm, node, w)) zz[i] = TV(0);
-                r[at] = rr[i];
+                if constexpr (MAXP > 0) {
+                    rk[0][i] = rr[i];
+                    xk[0][i] = TV(0);
+                } else {
+                    r[at] = rr[i];
+                }
                 z[at] = zz[i];
                 x[at] = TV(0);
                 p0[at] = TV(0);
@@ -513,7 +561,7 @@ __global__ __launch_bounds__(NT) void k_cg(
                 sums[1] += (double)rr[i] * (double)rr[i];
             }
         }
-    }
+    });
     if (!reduce_barrier<2, NW>(ss, partial, blk, sb0, snb, nbar++, sums, abort_flag, lds)) {
         if (leader) out[sh] = CgShellOut{0, 3, 0.0, 0.0};
         return;
@@ -534,9 +582,9 @@ __global__ __launch_bounds__(NT) void k_cg(
     for (; it < maxit; ++it) {
         // ---- phase A
         double pq[1] = {0.0};
-        for (int base = row0; base < row1; base += rows_per_pass) {
+        passes([&](int base) {
             const int node = base + wv * G + grp;
-            if (!(lane_ok && node < row1)) continue;
+            if (!(lane_ok && node < row1)) return;
             const TV bt = (TV)beta;
             auto xe = [&](int col, TV* xv) {
 #pragma unroll
@@ -554,10 +602,11 @@ __global__ __launch_bounds__(NT) void k_cg(
             for (int i = 0; i < R; ++i) {
                 const size_t at = (size_t)node * 12 + R * t + i;
                 pout[at] = pn[i];
-                qv[at] = u[i];
+                if constexpr (MAXP > 0) uk[0][i] = u[i];
+                else qv[at] = u[i];
                 pq[0] += 2.0 * (double)pn[i] * (double)u[i];
             }
-        }
+        });
         if (!reduce_barrier<1, NW>(ss, partial, blk, sb0, snb, nbar++, pq, abort_flag, lds)) {
             status = 3;
             break;
@@ -569,7 +618,7 @@ __global__ __launch_bounds__(NT) void k_cg(
         const double alpha = rz / pq[0];
         // ---- phase B
         double s2[2] = {0.0, 0.0};
-        for (int base = row0; base < row1; base += rows_per_pass) {
+        passes([&](int base) {
             const int node = base + wv * G + grp;
             const bool ok = lane_ok && node < row1;
             const int nd = ok ? node : row0;
@@ -580,9 +629,15 @@ __global__ __launch_bounds__(NT) void k_cg(
 #pragma unroll
             for (int i = 0; i < R; ++i) {
                 const size_t at = (size_t)nd * 12 + R * t + i;
-                rr[i] = r[at];
-                qq[i] = qv[at];
-                xo[i] = x[at];
+                if constexpr (MAXP > 0) {
+                    rr[i] = rk[0][i];
+                    qq[i] = uk[0][i];
+                    xo[i] = xk[0][i];
+                } else {
+                    rr[i] = r[at];
+                    qq[i] = qv[at];
+                    xo[i] = x[at];
+                }
                 pp[i] = pout[at];
             }
             // the transposed products of the rows above (4 per interior node)
@@ -609,14 +664,19 @@ __global__ __launch_bounds__(NT) void k_cg(
                     const int w = R * t + i;
                     const size_t at = (size_t)node * 12 + w;
                     if (!((fmask >> w) & 1u)) zz[i] = TV(0);
-                    x[at] = xo[i] + (TV)alpha * pp[i];
-                    r[at] = rr[i];
+                    if constexpr (MAXP > 0) {
+                        xk[0][i] = xo[i] + (TV)alpha * pp[i];
+                        rk[0][i] = rr[i];
+                    } else {
+                        x[at] = xo[i] + (TV)alpha * pp[i];
+                        r[at] = rr[i];
+                    }
                     z[at] = zz[i];
                     s2[0] += (double)rr[i] * (double)zz[i];
                     s2[1] += (double)rr[i] * (double)rr[i];
                 }
             }
-        }
+        });
         if (!reduce_barrier<2, NW>(ss, partial, blk, sb0, snb, nbar++, s2, abort_flag, lds)) {
             status = 3;
             break;
@@ -632,6 +692,15 @@ __global__ __launch_bounds__(NT) void k_cg(
         TV* tmp = pin;
         pin = pout;
         pout = tmp;
+    }
+    if constexpr (MAXP > 0) {
+        // the solution of the lane's rows, once
+        passes([&](int base) {
+            const int node = base + wv * G + grp;
+            if (!(lane_ok && node < row1)) return;
+#pragma unroll
+            for (int i = 0; i < R; ++i) x[(size_t)node * 12 + R * t + i] = xk[0][i];
+        });
     }
     if (leader) out[sh] = CgShellOut{it, status, bb, rr2};
 }
@@ -807,11 +876,23 @@ void launch_regularize(hipStream_t st, int nnodes, const int* diag_blk, void* va
                        node_shell, delta_shell);
 }
 
-// the CG kernel instance for a block size of 256, 512 or 1024 threads
-template <class TM, class TV> const void* cg_fn(int nthreads) {
-    return nthreads == 1024 ? (const void*)k_cg<TM, TV, 1024>
-           : nthreads == 512 ? (const void*)k_cg<TM, TV, 512>
-                             : (const void*)k_cg<TM, TV, 256>;
+// Passes over a block's rows up to which the CG keeps u, r and x in
+// registers (beyond it the memory instance runs): 4 for FP64 matrices at
+// most 512 threads per block, 2 otherwise, within the register budget.
+template <class TM> constexpr int cg_maxp(int nthreads) {
+    return sizeof(TM) == 8 && nthreads <= 512 ? 4 : 2;
+}
+
+// the CG kernel instance for a block size of 256, 512 or 1024 threads,
+// register-resident vectors or not
+template <class TM, class TV> const void* cg_fn(int nthreads, bool resident) {
+    if (resident)
+        return nthreads == 1024 ? (const void*)k_cg<TM, TV, 1024, cg_maxp<TM>(1024)>
+               : nthreads == 512 ? (const void*)k_cg<TM, TV, 512, cg_maxp<TM>(512)>
+                                 : (const void*)k_cg<TM, TV, 256, cg_maxp<TM>(256)>;
+    return nthreads == 1024 ? (const void*)k_cg<TM, TV, 1024, 0>
+           : nthreads == 512 ? (const void*)k_cg<TM, TV, 512, 0>
+                             : (const void*)k_cg<TM, TV, 256, 0>;
 }
 
 template <class TM, class TV>
@@ -826,7 +907,9 @@ hipError_t launch_cg(hipStream_t st, int nblk, int nthreads, const RowBlocks& rb
                     (void*)&x, (void*)&r, (void*)&z, (void*)&p0, (void*)&p1, (void*)&qv, (void*)&slot,
                     (void*)&partial, (void*)&ss, (void*)&abort_flag, (void*)&rtol2_shell, (void*)&maxit_shell,
                     (void*)&active_shell, (void*)&out};
-    return hipLaunchCooperativeKernel(cg_fn<TM, TV>(nthreads), dim3(nblk), dim3(nthreads), args, 0, st);
+    const int pass = (nthreads / 64) * Lay<TM>::G;
+    const bool resident = rb.max_rows <= cg_maxp<TM>(nthreads) * pass;
+    return hipLaunchCooperativeKernel(cg_fn<TM, TV>(nthreads, resident), dim3(nblk), dim3(nthreads), args, 0, st);
 }
 template hipError_t launch_cg<double, double>(hipStream_t, int, int, const RowBlocks&, const SymBsr&, const double*,
                                               const double*, const uint16_t*, const double*, double*, double*,
@@ -842,8 +925,13 @@ int cg_rows_per_pass(int tm_fp32, int nthreads) { return (nthreads / 64) * (tm_f
 
 int cg_max_blocks(int device, int tm_fp32, int nthreads) {
     int per_cu = 0, cus = 0;
-    const void* fn = tm_fp32 ? cg_fn<float, float>(nthreads) : cg_fn<double, double>(nthreads);
+    // the register-resident instance: it needs at least the registers of the other
+    int per_cu2 = 0;
+    const void* fn = tm_fp32 ? cg_fn<float, float>(nthreads, true) : cg_fn<double, double>(nthreads, true);
+    const void* fn2 = tm_fp32 ? cg_fn<float, float>(nthreads, false) : cg_fn<double, double>(nthreads, false);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nthreads, 0) != hipSuccess) return -1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, fn2, nthreads, 0) != hipSuccess) return -1;
+    per_cu = per_cu < per_cu2 ? per_cu : per_cu2;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return -1;
     return per_cu * cus;
 }
