@@ -91,6 +91,10 @@ typedef struct {
                                     factorisation, CG, line-search trial, rounding floor) run as HIP
                                     graphs captured once per context and time-step size; 0: direct
                                     launches.  Off while event timing is on. */
+    int32_t cg_resident;         /* 1: where a CG block has few enough row passes, the solver keeps
+                                    its own rows' residual, solution and product in registers
+                                    instead of device memory; 0: always in device memory (same
+                                    arithmetic, for comparison) */
 } shell_opts;
 
 /* Per-shell statistics of one shell_newton_step. */
@@ -107,7 +111,7 @@ typedef struct {
 
 /* Default options: FP64, exact Hessian, no warm start, newton_rtol = pcg_rtol
  * = 1e-10, 50 Newton and 100000 CG iterations, device 0, default stream,
- * graphs on. */
+ * graphs on, register-resident CG vectors on. */
 void shell_default_opts(shell_opts *o);
 
 /* Create a context for n_shells shells (batching: one context holds all of

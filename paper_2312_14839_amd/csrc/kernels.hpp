@@ -30,7 +30,7 @@ void launch_hessian(hipStream_t st, const int* patch_list, int nlist, const int4
 // used by the CG kernel and by the per-shell reductions.
 struct RowBlocks {
     int nblk;
-    int max_rows;            // node rows of the largest block
+    int max_rows;            // node rows of the largest block (INT32_MAX: never register-resident)
     const int* blk_shell;    // [nblk]
     const int* blk_row0;     // [nblk]
     const int* blk_row1;     // [nblk]

@@ -98,6 +98,7 @@ struct shell_ctx {
         double key = 0.0;
     };
     bool graphs = true;
+    bool cg_resident = true;   // register-resident CG vectors where the layout allows
     hipStream_t cap_stream = nullptr;
     Seg g_asm, g_trial, g_floor, g_cg;
     void graphs_reset() {
@@ -122,8 +123,8 @@ struct shell_ctx {
     }
 
     RowBlocks rb() {
-        return RowBlocks{nblk, cg_max_rows, dptr<int>(blk_shell), dptr<int>(blk_row0), dptr<int>(blk_row1),
-                         dptr<int>(shell_blk0), dptr<int>(shell_nblk)};
+        return RowBlocks{nblk, cg_resident ? cg_max_rows : INT32_MAX, dptr<int>(blk_shell), dptr<int>(blk_row0),
+                         dptr<int>(blk_row1), dptr<int>(shell_blk0), dptr<int>(shell_nblk)};
     }
     ~shell_ctx() {
         graphs_reset();
@@ -1017,6 +1018,7 @@ void shell_default_opts(shell_opts* o) {
     o->device = 0;
     o->stream = nullptr;
     o->graphs = 1;
+    o->cg_resident = 1;
 }
 
 const char* shell_last_error(const shell_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
@@ -1050,6 +1052,7 @@ shell_status shell_create(const shell_desc* shells, int32_t n_shells, const shel
         c->stream = (hipStream_t)opts.stream;
         c->fp32 = opts.precision == SHELL_MIXED;
         c->graphs = opts.graphs != 0;
+        c->cg_resident = opts.cg_resident != 0;
         build(c, shells, n_shells);
     } catch (const InvalErr& e) {
         g_create_error = e.msg;

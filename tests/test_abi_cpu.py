@@ -32,6 +32,7 @@ def test_default_opts():
     from paper_2312_14839_amd import shell as S
     o = S.default_opts()
     assert o.precision == S.SHELL_FP64 and o.hessian == S.SHELL_HESS_EXACT
+    assert o.graphs == 1 and o.cg_resident == 1
     assert o.newton_rtol == 1e-10 and o.pcg_rtol == 1e-10 and o.newton_maxit == 50
 
 
