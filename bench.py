@@ -151,19 +151,30 @@ def qstate_after(case, precision, nsteps, stream, tol):
     return out
 
 
-def cg_bytes(case, timing, tm_bytes, tv_bytes):
+def cg_resident(layout, fp32):
+    """Whether the CG ran its register-resident instance: blocks of at most
+    4 (FP64 matrix, <= 512 threads) or 2 row passes of threads/64 x 10 rows."""
+    if not layout:
+        return False
+    maxp = 4 if (not fp32 and layout["threads"] <= 512) else 2
+    return layout["rows_per_block"] <= maxp * (layout["threads"] // 64) * 10
+
+
+def cg_bytes(case, timing, tm_bytes, tv_bytes, resident):
     """Algorithmic HBM bytes of the CG kernel.  Per iteration: every stored
     block (the diagonal and upper-triangle blocks: 144 values; off the
     diagonal also a column and a slot index, and the 12-value transposed
     product written to its slot in phase A and read back in phase B); per
     node row its 12x12 inverse diagonal block, the row pointer, slot range
-    and free mask (10 bytes) and 11 passes over 12-vectors (phase A reads z,
-    p_old and writes p_new, q; phase B reads r, q, p_new, x and writes x, r,
-    z)."""
+    and free mask (10 bytes) and the passes over 12-vectors: with the
+    register-resident instance 5 (phase A reads z, p_old and writes p_new;
+    phase B reads p_new and writes z), else 11 (also u written and read, r
+    and x read and written)."""
     blocks = timing["cg_iter_blocks"]
     rows = timing["cg_iter_rows"]
+    vec = 5 if resident else 11
     return (blocks * 144 * tm_bytes + (blocks - rows) * (8 + 24 * tv_bytes)
-            + rows * (144 * tv_bytes + 10 + 11 * 12 * tv_bytes))
+            + rows * (144 * tv_bytes + 10 + vec * 12 * tv_bytes))
 
 
 def profiled_traffic(case, fp32, kernel):
@@ -187,17 +198,18 @@ def profiled_traffic(case, fp32, kernel):
     return None
 
 
-def roofline(case, timing, fp32):
+def roofline(case, timing, fp32, layout=None):
     ms = timing["ms"]
     grp = max(ms, key=lambda k: ms[k])
     n = max(timing["launches"][grp], 1)
     per_launch_ms = ms[grp] / n
     if grp == "cg":
         tb = 4 if fp32 else 8
-        total = cg_bytes(case, timing, tb, tb)
+        total = cg_bytes(case, timing, tb, tb, cg_resident(layout, fp32))
         ach = total / (ms[grp] * 1e-3) / 1e9
         traffic = profiled_traffic(case, fp32, "k_cg")
-        return grp, {"kernel": "k_cg (persistent block-Jacobi CG)", "bound": "hbm", "achieved": ach,
+        inst = "register-resident u, r, x" if cg_resident(layout, fp32) else "vectors in memory"
+        return grp, {"kernel": f"k_cg (persistent block-Jacobi CG, {inst})", "bound": "hbm", "achieved": ach,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
                      "avg_launch_ms": per_launch_ms, "algorithmic_bytes_per_launch": total / n}
@@ -507,7 +519,7 @@ def main():
     ms_step = 1e3 * wall / args.steps
     print(f"[bench] fp64: {ms_step:.2f} ms/step, {newton64} Newton its, "
           f"{sum(s['pcg_iters_total'] for s in st64)} CG its", file=sys.stderr, flush=True)
-    grp, roof = roofline(case, tm64, False)
+    grp, roof = roofline(case, tm64, False, tune64)
     out = {
         "metric": METRIC, "value": value, "unit": "patch E/grad/Hess evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
@@ -522,8 +534,8 @@ def main():
         "roofline": roof,
     }
     if not args.no_mixed:
-        wallm, stm, tmm, _ = run_steps(case, S.SHELL_MIXED, args.steps, args.warmup, stream, tol,
-                                       not args.no_autotune)
+        wallm, stm, tmm, tunem = run_steps(case, S.SHELL_MIXED, args.steps, args.warmup, stream, tol,
+                                           not args.no_autotune)
         newtonm = sum(s["newton_iters"] for s in stm)
         evalsm = sum(s["patch_evals"] for s in stm)
         nst = args.warmup + args.steps
@@ -531,7 +543,7 @@ def main():
         qb = qstate_after(case, S.SHELL_MIXED, nst, stream, tol)
         ref = case.q0.reshape(-1, 12)
         err = np.linalg.norm((qb - qa)[:, 0:3]) / max(np.linalg.norm((qa - ref)[:, 0:3]), 1e-300)
-        _, roofm = roofline(case, tmm, True)
+        _, roofm = roofline(case, tmm, True, tunem)
         out["mixed"] = {"value": evalsm / wallm, "ms_per_step": 1e3 * wallm / args.steps,
                         "dtype": "f32 Hessian/CG + f64 residual", "rel_disp_err_vs_fp64": float(err),
                         "err_steps": nst, "newton_iters_per_step": newtonm / args.steps,
