@@ -218,7 +218,9 @@ __global__ __launch_bounds__(256) void k_hessian(const int* __restrict__ patch_l
     __shared__ T s_u[HS_WAVES][48], s_b[HS_WAVES][48];
     __shared__ T s_kin[HS_WAVES][16][30];
     __shared__ T s_w[HS_WAVES][WSZ];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // the wavefront's patch and everything derived from it are wave-uniform
+    // (scalar registers and loads)
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = blockIdx.x * HS_WAVES + wv;
     const bool active = li < nlist;
     const int patch = active ? patch_list[li] : 0;
@@ -324,35 +326,58 @@ __global__ __launch_bounds__(256) void k_hessian(const int* __restrict__ patch_l
     // the patch's slot list is the m-th stored local block (local index in
     // nibble m of patch_kid; the list ends at the first -1).  A block this
     // patch touches first is stored, the others are read, added to and
-    // written back.  Chunks of 12 elements per lane keep 12 reads in flight.
+    // written back.  Lane l takes elements w = l + 64 u (u = 0, 1, and 2 for
+    // l < 16) of every block, so its index arithmetic is done once; the
+    // block's nodes and slot are the same for the whole wavefront.  Four
+    // blocks per round keep 12 reads per lane in flight.
     if (active) {
         const int* slots = patch_slots + 16 * (size_t)patch;
         const uint64_t kid = patch_kid[patch];
         const unsigned first = patch_first[patch];
-        constexpr int CH = 12;
-#pragma unroll 1
-        for (int e0 = 0; e0 < 16 * 144; e0 += 64 * CH) {
-            if (slots[e0 / 144] < 0) break;
-            T add[CH], old[CH];
-            T* dst[CH];
+        int lo[3];
+        bool sw[3];
+        T ks[3];
 #pragma unroll
-            for (int u = 0; u < CH; ++u) {
-                const int e = e0 + 64 * u + lane;
-                const int mm = e / 144, w = e % 144;
-                const int sl = slots[mm];
-                const int blk = (int)((kid >> (4 * mm)) & 15u);
+        for (int u = 0; u < 3; ++u) {
+            const int w = u < 2 ? lane + 64 * u : (lane & 15) + 128;
+            const int jj = w / 12, ii = w % 12;   // column-major: w = jj*12 + ii
+            const int k = ii / 3, i = ii % 3, l = jj / 3, j = jj % 3;
+            // K block (I, J) = (4c + k, 4d + l) of component pair (i, j): the
+            // staged pair blocks hold i <= j, so i > j reads the transpose
+            sw[u] = i > j;
+            lo[u] = sw[u] ? pair_index(j, i) * 256 + 16 * l + k : pair_index(i, j) * 256 + 16 * k + l;
+            ks[u] = (T)(kind_scale(k, sp.dxi1, sp.dxi2) * kind_scale(l, sp.dxi1, sp.dxi2));
+        }
+        constexpr int MB = 4;
+#pragma unroll 1
+        for (int m0 = 0; m0 < 16; m0 += MB) {
+            if (slots[m0] < 0) break;
+            T add[MB][3], old[MB][3];
+            int sl[MB];
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                const int m = m0 + mb;
+                sl[mb] = m < 16 ? slots[m] : -1;
+                if (sl[mb] < 0) continue;
+                const int blk = (int)((kid >> (4 * m)) & 15u);
                 const int c = blk >> 2, d = blk & 3;
-                const int jj = w / 12, ii = w % 12;   // column-major: w = jj*12 + ii
-                const int k = ii / 3, i = ii % 3, l = jj / 3, j = jj % 3;
-                const int I = 4 * c + k, J = 4 * d + l;
-                const T kv = i <= j ? W[pair_index(i, j) * 256 + I * 16 + J] : W[pair_index(j, i) * 256 + J * 16 + I];
-                add[u] = (T)(kind_scale(k, sp.dxi1, sp.dxi2) * kind_scale(l, sp.dxi1, sp.dxi2)) * kv;
-                dst[u] = sl >= 0 ? vals + (size_t)sl * 144 + w : nullptr;
-                old[u] = (!dst[u] || ((first >> mm) & 1u)) ? T(0) : *dst[u];
+                const int cd = 64 * c + 4 * d, dc = 64 * d + 4 * c;
+                const T* src = vals + (size_t)sl[mb] * 144;
+                const bool fresh = (first >> m) & 1u;
+#pragma unroll
+                for (int u = 0; u < 3; ++u) {
+                    add[mb][u] = ks[u] * W[lo[u] + (sw[u] ? dc : cd)];
+                    old[mb][u] = (fresh || (u == 2 && lane >= 16)) ? T(0) : src[lane + 64 * u];
+                }
             }
 #pragma unroll
-            for (int u = 0; u < CH; ++u)
-                if (dst[u]) *dst[u] = old[u] + add[u];
+            for (int mb = 0; mb < MB; ++mb) {
+                if (sl[mb] < 0) continue;
+                T* dst = vals + (size_t)sl[mb] * 144;
+#pragma unroll
+                for (int u = 0; u < 3; ++u)
+                    if (u < 2 || lane < 16) dst[lane + 64 * u] = old[mb][u] + add[mb][u];
+            }
         }
     }
 }
