@@ -165,16 +165,16 @@ def cg_bytes(case, timing, tm_bytes, tv_bytes, resident):
     block (the diagonal and upper-triangle blocks: 144 values; off the
     diagonal also a column and a slot index, and the 12-value transposed
     product written to its slot in phase A and read back in phase B); per
-    node row its 12x12 inverse diagonal block, the row pointer, slot range
-    and free mask (10 bytes) and the passes over 12-vectors: with the
-    register-resident instance 5 (phase A reads z, p_old and writes p_new;
-    phase B reads p_new and writes z), else 11 (also u written and read, r
-    and x read and written)."""
+    node row its inverse diagonal block (symmetric, 84 stored values), the
+    row pointer, slot range and free mask (10 bytes) and the passes over
+    12-vectors: with the register-resident instance 5 (phase A reads z,
+    p_old and writes p_new; phase B reads p_new and writes z), else 11 (also
+    u written and read, r and x read and written)."""
     blocks = timing["cg_iter_blocks"]
     rows = timing["cg_iter_rows"]
     vec = 5 if resident else 11
     return (blocks * 144 * tm_bytes + (blocks - rows) * (8 + 24 * tv_bytes)
-            + rows * (144 * tv_bytes + 10 + vec * 12 * tv_bytes))
+            + rows * (84 * tv_bytes + 10 + vec * 12 * tv_bytes))
 
 
 def profiled_traffic(case, fp32, kernel):

@@ -62,6 +62,14 @@ void launch_spmv(hipStream_t st, int nnodes, const SymBsr& m, const TM* vals, co
 // mode bits: 1 masked (free rows and columns only), 2 abs values (|A| |x|), 4 residual y = b - A x,
 // 8 free rows only (all columns)
 
+// Block-Jacobi inverse of a node, symmetric: its 21 distinct 2x2 blocks
+// (row pair a, column pair b), each row-major (4 values), 84 values:
+//   at 12 a + 4 k (a = 0..5, k = 0..2): block (a, (a + k) mod 6);
+//   at 72 + 4 a   (a = 0..2):           block (a, a + 3).
+// Row pair t then finds blocks (t, t), (t, t+1), (t, t+2) side by side and
+// the other three as transposes (or, for t < 3, block (t, t+3) itself).
+constexpr int DINV_VALS = 84;
+
 template <class TV>
 void launch_bj_factor(hipStream_t st, int nnodes, const int* diag_blk, const void* vals, int vals_fp32,
                       const uint16_t* freemask, const int* node_shell, TV* dinv, int* fail_shell);

@@ -557,7 +557,7 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
     alloc(c->vals, (size_t)c->nnzb_u * 144 * (c->fp32 ? sizeof(float) : sizeof(double)));
     alloc(c->slot, (size_t)std::max(c->nnzb_u - N, 1LL) * 12 * sizeof(double));
     alloc(c->diag0, vecb);
-    alloc(c->dinv, (size_t)N * 144 * (c->fp32 ? sizeof(float) : sizeof(double)));
+    alloc(c->dinv, (size_t)N * DINV_VALS * (c->fp32 ? sizeof(float) : sizeof(double)));
     alloc(c->e_patch, (size_t)std::max(P, 1) * 3 * sizeof(double));
     alloc(c->g_patch, (size_t)std::max(P, 1) * 48 * sizeof(double));
     alloc(c->e_shell, (size_t)S * 3 * sizeof(double));

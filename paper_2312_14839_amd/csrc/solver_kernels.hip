@@ -54,6 +54,25 @@ template <> struct VecLoad<float, 2> {
         o[1] = v.y;
     }
 };
+template <class T> struct Vec4;
+template <> struct Vec4<double> {
+    static __device__ __forceinline__ void ld(const double* p, double* o) {
+        const double2 a = reinterpret_cast<const double2*>(p)[0], b = reinterpret_cast<const double2*>(p)[1];
+        o[0] = a.x;
+        o[1] = a.y;
+        o[2] = b.x;
+        o[3] = b.y;
+    }
+};
+template <> struct Vec4<float> {
+    static __device__ __forceinline__ void ld(const float* p, float* o) {
+        const float4 a = *reinterpret_cast<const float4*>(p);
+        o[0] = a.x;
+        o[1] = a.y;
+        o[2] = a.z;
+        o[3] = a.w;
+    }
+};
 template <class TV, int R> struct VecStore;
 template <> struct VecStore<double, 2> {
     static __device__ __forceinline__ void st(double* p, const double* v) {
@@ -239,6 +258,10 @@ __global__ void k_spmv_fin(int nnodes, const int* __restrict__ lptr, const doubl
 // ---------------------------------------------------- block-Jacobi factor
 // Inverse of each node's 12x12 diagonal block (prescribed rows/columns
 // replaced by identity) by an FP64 Cholesky factorisation; 16 lanes per node.
+// The inverse is symmetric, so a node keeps its 21 distinct 2x2 blocks
+// (84 values instead of 144, layout at DINV_VALS).  A 2x2 diagonal block
+// takes both off-diagonal entries from column 2a + 1, so the stored matrix
+// is exactly symmetric.
 template <class TV>
 __global__ __launch_bounds__(256) void k_bj_factor(int nnodes, const int* __restrict__ diag_blk,
                                                    const void* __restrict__ vals, int vals_fp32,
@@ -290,7 +313,26 @@ __global__ __launch_bounds__(256) void k_bj_factor(int nnodes, const int* __rest
             for (int k = i + 1; k < 12; ++k) v -= A[sub][k][i] * y[k];
             y[i] = v / A[sub][i][i];
         }
-        for (int i = 0; i < 12; ++i) dinv[(size_t)node * 144 + i * 12 + ln] = (TV)y[i];
+        // column ln = 2b + j goes into the stored blocks (a, b) of column
+        // pair b: a = b - k (mod 6) at 12 a + 4 k, and a = b - 3 at 72 + 4 a
+        const int bc = ln >> 1, j = ln & 1;
+        TV* dn = dinv + (size_t)node * DINV_VALS;
+        for (int k = 1; k < 3; ++k) {
+            const int a = (bc + 6 - k) % 6;
+            dn[12 * a + 4 * k + j] = (TV)y[2 * a];
+            dn[12 * a + 4 * k + 2 + j] = (TV)y[2 * a + 1];
+        }
+        if (bc >= 3) {
+            const int a = bc - 3;
+            dn[72 + 4 * a + j] = (TV)y[2 * a];
+            dn[72 + 4 * a + 2 + j] = (TV)y[2 * a + 1];
+        }
+        if (j == 0) {
+            dn[12 * bc] = (TV)y[2 * bc];
+        } else {
+            dn[12 * bc + 1] = dn[12 * bc + 2] = (TV)y[2 * bc];
+            dn[12 * bc + 3] = (TV)y[2 * bc + 1];
+        }
         if (ln == 0 && bad[sub]) atomicOr(&fail_shell[node_shell[node]], 1);
     }
 }
@@ -347,7 +389,7 @@ template <int N, int NW> __device__ __forceinline__ void block_sum(double (&v)[N
 // Arrivals go through CG_GROUPS group counters on separate 128-byte lines
 // and then one top counter, so no single address takes more than about
 // nblk/CG_GROUPS (or CG_GROUPS) atomic operations per barrier.
-constexpr int CG_GROUPS = 16;
+constexpr int CG_GROUPS = 4;
 struct alignas(128) ShellSync {
     unsigned cnt;        // top-level arrivals (group leaders), monotone
     unsigned pad0[31];
@@ -391,7 +433,9 @@ __device__ __forceinline__ bool reduce_barrier(ShellSync* ss, double* __restrict
         int ok = 1;
         unsigned spins = 0;
         while (__hip_atomic_load(&ss->cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)ng * (k + 1)) {
-            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || ++spins > (1u << 22)) {
+            // the abort flag is looked at every 32nd poll, so a poll is one round trip
+            if ((++spins & 31u) == 0 &&
+                (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || spins > (1u << 22))) {
                 __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 ok = 0;
                 break;
@@ -410,10 +454,24 @@ __device__ __forceinline__ bool reduce_barrier(ShellSync* ss, double* __restrict
         double t[N];
 #pragma unroll
         for (int n = 0; n < N; ++n) t[n] = 0.0;
-        for (int i = threadIdx.x; i < snb; i += 64)
+        // up to 8 loads per lane in flight before the first add (these
+        // partials come from other XCDs' L2s: one round trip each)
+        constexpr int CH = 8;
+        for (int i0 = threadIdx.x; i0 < snb; i0 += 64 * CH) {
+            double pv[CH][N];
 #pragma unroll
-            for (int n = 0; n < N; ++n)
-                t[n] += __hip_atomic_load(&buf[4 * (size_t)(sb0 + i) + n], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int c = 0; c < CH; ++c)
+#pragma unroll
+                for (int n = 0; n < N; ++n)
+                    pv[c][n] = i0 + 64 * c < snb ? __hip_atomic_load(&buf[4 * (size_t)(sb0 + i0 + 64 * c) + n],
+                                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                                 : 0.0;
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+#pragma unroll
+                for (int n = 0; n < N; ++n)
+                    if (i0 + 64 * c < snb) t[n] += pv[c][n];
+        }
 #pragma unroll
         for (int n = 0; n < N; ++n)
 #pragma unroll
@@ -514,19 +572,45 @@ __global__ __launch_bounds__(NT) void k_cg(
         }
     };
 
-    // z = Dinv r for this lane's R rows of node (r of the node exchanged in the group)
+    // z = Dinv r for this lane's rows 2t, 2t+1 of node: the six 2x2 blocks
+    // (t, b), b = t + k (mod 6), of the packed inverse times r of column
+    // pair b, which lane b of the group holds
+    static_assert(R == 2, "the packed inverse is read by row pairs");
     auto precond = [&](int node, const TV* rr, TV* zz) {
-        TV rall[12];
+        // the lane-dependent offsets below are recomputed per call (an
+        // opaque copy of t): hoisted out of the iteration loop they would
+        // hold 9 registers through it
+        int t = Lay<TM>::L;
+        t = lane % t;
+        asm volatile("" : "+v"(t));
+        const TV* dn = dinv + (size_t)node * DINV_VALS;
+        TV m[6][4];
+        TV s0 = TV(0), s1 = TV(0);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) rall[c] = __shfl(rr[c % R], gsrc + c / R);
+        for (int k = 0; k < 6; ++k) {
+            if (k == 0 || k == 3) {
+                // three blocks at a time
+                __builtin_amdgcn_sched_barrier(0);
+                if (k == 0) {
 #pragma unroll
-        for (int i = 0; i < R; ++i) {
-            const TV* drow = dinv + (size_t)node * 144 + (R * t + i) * 12;
-            TV s = TV(0);
-#pragma unroll
-            for (int c = 0; c < 12; ++c) s += drow[c] * rall[c];
-            zz[i] = s;
+                    for (int h = 0; h < 3; ++h) Vec4<TV>::ld(dn + 12 * t + 4 * h, m[h]);   // (t, t+h)
+                } else {
+                    Vec4<TV>::ld(dn + 72 + 4 * (t % 3), m[3]);         // (t, t+3), transposed for t >= 3
+                    Vec4<TV>::ld(dn + 12 * ((t + 4) % 6) + 8, m[4]);   // (t-2, t), transposed
+                    Vec4<TV>::ld(dn + 12 * ((t + 5) % 6) + 4, m[5]);   // (t-1, t), transposed
+                }
+            }
+            const int src = gsrc + (t + k) % 6;
+            const TV r0 = __shfl(rr[0], src), r1 = __shfl(rr[1], src);
+            const bool tr = k >= 4 || (k == 3 && t >= 3);
+            const TV m01 = tr ? m[k][2] : m[k][1], m10 = tr ? m[k][1] : m[k][2];
+            s0 += m[k][0] * r0;
+            s0 += m01 * r1;
+            s1 += m10 * r0;
+            s1 += m[k][3] * r1;
         }
+        zz[0] = s0;
+        zz[1] = s1;
     };
 
     // ---- init: r = b (masked), x = 0, p_old = 0, z = Dinv r; sums r.z and b.b
