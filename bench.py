@@ -162,9 +162,9 @@ def cg_resident(layout, fp32):
 
 def cg_bytes(case, timing, tm_bytes, tv_bytes, resident):
     """Algorithmic HBM bytes of the CG kernel.  Per iteration: every stored
-    block (the diagonal and upper-triangle blocks: 144 values; off the
-    diagonal also a column and a slot index, and the 12-value transposed
-    product written to its slot in phase A and read back in phase B); per
+    block (the upper-triangle blocks: 144 values, a column and a slot index,
+    and the 12-value transposed product written to its slot in phase A and
+    read back in phase B; the diagonal blocks, symmetric: 84 values); per
     node row its inverse diagonal block (symmetric, 84 stored values), the
     row pointer, slot range and free mask (10 bytes) and the passes over
     12-vectors: with the register-resident instance 5 (phase A reads z,
@@ -173,8 +173,8 @@ def cg_bytes(case, timing, tm_bytes, tv_bytes, resident):
     blocks = timing["cg_iter_blocks"]
     rows = timing["cg_iter_rows"]
     vec = 5 if resident else 11
-    return (blocks * 144 * tm_bytes + (blocks - rows) * (8 + 24 * tv_bytes)
-            + rows * (84 * tv_bytes + 10 + vec * 12 * tv_bytes))
+    return ((blocks - rows) * (144 * tm_bytes + 8 + 24 * tv_bytes)
+            + rows * (84 * tm_bytes + 84 * tv_bytes + 10 + vec * 12 * tv_bytes))
 
 
 def profiled_traffic(case, fp32, kernel):
@@ -226,22 +226,24 @@ def roofline(case, timing, fp32, layout=None):
 
 def spmv_bytes(stored, rows, s):
     """Algorithmic HBM bytes of one stand-alone SpMV (two launches) with the
-    symmetric storage: every stored block (144 values of s bytes; off the
-    diagonal a column and a slot index, and the 12 FP64 values of its
-    transposed product written and read back); per row the row pointer,
-    slot range and free mask (10 bytes), x read once, y written, then read
-    and written again by the slot-summing launch (4 passes of 12 FP64)."""
+    symmetric storage: every stored upper-triangle block (144 values of s
+    bytes, a column and a slot index, and the 12 FP64 values of its
+    transposed product written and read back) and diagonal block (84
+    values); per row the row pointer, slot range and free mask (10 bytes),
+    x read once, y written, then read and written again by the slot-summing
+    launch (4 passes of 12 FP64)."""
     off = stored - rows
-    return stored * 144 * s + off * (8 + 2 * 96) + rows * (10 + 4 * 96)
+    return off * (144 * s + 8 + 2 * 96) + rows * (84 * s + 10 + 4 * 96)
 
 
 def assembly_bytes(patches, stored, rows, s):
     """Algorithmic HBM bytes of one Hessian assembly: each patch adds its 10
-    stored node blocks (4 diagonal, 6 of the upper triangle) into the matrix,
-    a read and a write of 144 values each, except the first touch of every
-    stored block (a write only); the state q and reference q-bar read once
-    per node."""
-    return (2 * 10 * patches - stored) * 144 * s + rows * 2 * 96
+    stored node blocks into the matrix, a read and a write of 84 values for
+    each of the 4 diagonal blocks (packed symmetric) and of 144 for each of
+    the 6 of the upper triangle, except the first touch of every stored block
+    (a write only); the state q and reference q-bar read once per node."""
+    off = stored - rows
+    return ((2 * 4 * patches - rows) * 84 + (2 * 6 * patches - off) * 144) * s + rows * 2 * 96
 
 
 def kernels_section(case, stream, reps=20):

@@ -62,13 +62,39 @@ void launch_spmv(hipStream_t st, int nnodes, const SymBsr& m, const TM* vals, co
 // mode bits: 1 masked (free rows and columns only), 2 abs values (|A| |x|), 4 residual y = b - A x,
 // 8 free rows only (all columns)
 
-// Block-Jacobi inverse of a node, symmetric: its 21 distinct 2x2 blocks
-// (row pair a, column pair b), each row-major (4 values), 84 values:
+// Symmetric 12x12 blocks (the matrix's diagonal node blocks and their
+// block-Jacobi inverses) keep their 21 distinct 2x2 blocks (row pair a,
+// column pair b), each row-major (4 values), 84 values:
 //   at 12 a + 4 k (a = 0..5, k = 0..2): block (a, (a + k) mod 6);
 //   at 72 + 4 a   (a = 0..2):           block (a, a + 3).
 // Row pair t then finds blocks (t, t), (t, t+1), (t, t+2) side by side and
 // the other three as transposes (or, for t < 3, block (t, t+3) itself).
-constexpr int DINV_VALS = 84;
+// Entry (2a, 2a+1) of a 2x2 diagonal block is also stored as (2a+1, 2a),
+// with the same value.  A diagonal node block keeps this layout in the
+// first 84 values of its 144-value place in the matrix.
+constexpr int SYM12_VALS = 84;
+
+// position of entry (r, c), either triangle
+__host__ __device__ constexpr int sym12_pos(int r, int c) {
+    const int a = r >> 1, i = r & 1, b = c >> 1, j = c & 1;
+    const int d = (b - a + 6) % 6;
+    return d <= 2 ? 12 * a + 4 * d + 2 * i + j
+           : d >= 4 ? 12 * b + 4 * (6 - d) + 2 * j + i
+                    : (a < 3 ? 72 + 4 * a + 2 * i + j : 72 + 4 * b + 2 * j + i);
+}
+
+// the entry (r, c) that position p holds, in the orientation the layout
+// lists its 2x2 block (for p = 12a + 2 the upper one, (2a, 2a+1))
+__host__ __device__ constexpr int sym12_row(int p) {
+    return p < 72 ? ((p % 12) == 2 ? 2 * (p / 12) : 2 * (p / 12) + ((p >> 1) & 1)) : 2 * ((p - 72) >> 2) + ((p >> 1) & 1);
+}
+__host__ __device__ constexpr int sym12_col(int p) {
+    return p < 72 ? ((p % 12) == 2 ? 2 * (p / 12) + 1 : 2 * ((p / 12 + (p % 12) / 4) % 6) + (p & 1))
+                  : 2 * (((p - 72) >> 2) + 3) + (p & 1);
+}
+static_assert(sym12_pos(sym12_row(2), sym12_col(2)) == 1 && sym12_pos(11, 0) == 12 * 5 + 4 + 2 &&
+                  sym12_pos(0, 11) == 12 * 5 + 4 + 2 && sym12_pos(7, 1) == 72 + 3,
+              "packed symmetric layout");
 
 template <class TV>
 void launch_bj_factor(hipStream_t st, int nnodes, const int* diag_blk, const void* vals, int vals_fp32,

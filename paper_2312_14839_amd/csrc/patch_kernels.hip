@@ -20,6 +20,8 @@
 // the reduced-form derivatives are documented in shell_physics.hpp.
 // Local coordinates: corner c = p + 2q (node (i+p, j+q)), kind k = r + 2s,
 // I = 4c + k; local DOF 12 c + 3 k + component.
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "kernels.hpp"
 #include "shell_physics.hpp"
@@ -320,27 +322,38 @@ __global__ __launch_bounds__(256) void k_hessian(const int* __restrict__ patch_l
             for (int v = 0; v < 4; ++v) W[pr * 256 + MM::row(lane, v) * 16 + (lane & 15)] = acc[pr][v];
     }
     __syncthreads();
-    // phase 3: add the node blocks the matrix stores (column-major 12x12:
-    // the diagonal blocks and, of each pair (c, d) of distinct nodes, the
-    // one whose row node has the larger index) into the matrix.  Entry m of
-    // the patch's slot list is the m-th stored local block (local index in
-    // nibble m of patch_kid; the list ends at the first -1).  A block this
-    // patch touches first is stored, the others are read, added to and
-    // written back.  Lane l takes elements w = l + 64 u (u = 0, 1, and 2 for
-    // l < 16) of every block, so its index arithmetic is done once; the
-    // block's nodes and slot are the same for the whole wavefront.  Four
-    // blocks per round keep 12 reads per lane in flight.
+    // phase 3: add the node blocks the matrix stores (the diagonal blocks
+    // and, of each pair (c, d) of distinct nodes, the one whose row node has
+    // the larger index; column-major 12x12, a diagonal block in the packed
+    // symmetric layout at SYM12_VALS) into the matrix.  Entry m of the
+    // patch's slot list is the m-th stored local block (local index in
+    // nibble m of patch_kid; the 4 diagonal blocks first, the list ends at
+    // the first -1).  A block this patch touches first is stored, the others
+    // are read, added to and written back.  Lane l takes elements
+    // w = l + 64 u of every block (u = 0, 1, and 2 for l < 16; of a diagonal
+    // block's 84 values l and, for l < 20, l + 64), so its index arithmetic
+    // is done once; the block's nodes and slot are the same for the whole
+    // wavefront.  Four blocks per round keep 12 reads per lane in flight.
     if (active) {
         const int* slots = patch_slots + 16 * (size_t)patch;
         const uint64_t kid = patch_kid[patch];
         const unsigned first = patch_first[patch];
-        int lo[3];
-        bool sw[3];
-        T ks[3];
+        // u = 0..2: off-diagonal blocks; u = 3, 4: diagonal blocks
+        int lo[5];
+        bool sw[5];
+        T ks[5];
 #pragma unroll
-        for (int u = 0; u < 3; ++u) {
-            const int w = u < 2 ? lane + 64 * u : (lane & 15) + 128;
-            const int jj = w / 12, ii = w % 12;   // column-major: w = jj*12 + ii
+        for (int u = 0; u < 5; ++u) {
+            int ii, jj;
+            if (u < 3) {
+                const int w = u < 2 ? lane + 64 * u : (lane & 15) + 128;
+                jj = w / 12;   // column-major: w = jj*12 + ii
+                ii = w % 12;
+            } else {
+                const int p = u == 3 ? lane : (lane < 20 ? lane : lane & 15) + 64;
+                ii = sym12_row(p);
+                jj = sym12_col(p);
+            }
             const int k = ii / 3, i = ii % 3, l = jj / 3, j = jj % 3;
             // K block (I, J) = (4c + k, 4d + l) of component pair (i, j): the
             // staged pair blocks hold i <= j, so i > j reads the transpose
@@ -349,10 +362,13 @@ __global__ __launch_bounds__(256) void k_hessian(const int* __restrict__ patch_l
             ks[u] = (T)(kind_scale(k, sp.dxi1, sp.dxi2) * kind_scale(l, sp.dxi1, sp.dxi2));
         }
         constexpr int MB = 4;
-#pragma unroll 1
-        for (int m0 = 0; m0 < 16; m0 += MB) {
-            if (slots[m0] < 0) break;
-            T add[MB][3], old[MB][3];
+        // one round: blocks m0 .. m0 + MB - 1 of the list, all diagonal (DG)
+        // or all off the diagonal
+        auto round = [&](int m0, auto dg_tag) {
+            constexpr bool DG = decltype(dg_tag)::value;
+            constexpr int NU = DG ? 2 : 3;
+            const bool last_ok = DG ? lane < 20 : lane < 16;   // u = NU - 1
+            T add[MB][NU], old[MB][NU];
             int sl[MB];
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) {
@@ -365,9 +381,10 @@ __global__ __launch_bounds__(256) void k_hessian(const int* __restrict__ patch_l
                 const T* src = vals + (size_t)sl[mb] * 144;
                 const bool fresh = (first >> m) & 1u;
 #pragma unroll
-                for (int u = 0; u < 3; ++u) {
-                    add[mb][u] = ks[u] * W[lo[u] + (sw[u] ? dc : cd)];
-                    old[mb][u] = (fresh || (u == 2 && lane >= 16)) ? T(0) : src[lane + 64 * u];
+                for (int u = 0; u < NU; ++u) {
+                    const int v = DG ? u + 3 : u;
+                    add[mb][u] = ks[v] * W[lo[v] + (sw[v] ? dc : cd)];
+                    old[mb][u] = (fresh || (u == NU - 1 && !last_ok)) ? T(0) : src[lane + 64 * u];
                 }
             }
 #pragma unroll
@@ -375,9 +392,15 @@ __global__ __launch_bounds__(256) void k_hessian(const int* __restrict__ patch_l
                 if (sl[mb] < 0) continue;
                 T* dst = vals + (size_t)sl[mb] * 144;
 #pragma unroll
-                for (int u = 0; u < 3; ++u)
-                    if (u < 2 || lane < 16) dst[lane + 64 * u] = old[mb][u] + add[mb][u];
+                for (int u = 0; u < NU; ++u)
+                    if (u < NU - 1 || last_ok) dst[lane + 64 * u] = old[mb][u] + add[mb][u];
             }
+        };
+        round(0, std::true_type{});
+#pragma unroll 1
+        for (int m0 = 4; m0 < 16; m0 += MB) {
+            if (slots[m0] < 0) break;
+            round(m0, std::false_type{});
         }
     }
 }

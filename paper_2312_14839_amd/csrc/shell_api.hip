@@ -463,30 +463,31 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
         c->rows_s[s2] = c->shells[s2].node_end - c->shells[s2].node_begin;
         c->nnzb_s[s2] = c->h_urow[c->shells[s2].node_end] - c->h_urow[c->shells[s2].node_begin];
     }
-    // per patch: the stored local blocks (a, b) -- diagonal, or row node
-    // index above the column node's (that block, column-major, is the
-    // stored pair's content) -- with their stored block index
+    // per patch: the stored local blocks (a, b) -- the 4 diagonal ones
+    // first, then those whose row node index is above the column node's
+    // (that block, column-major, is the stored pair's content) -- with their
+    // stored block index
     std::vector<int> slots((size_t)P * 16, -1);
     std::vector<uint64_t> kid((size_t)P, 0);
     std::vector<std::vector<int>> inc(N);
     for (int p = 0; p < P; ++p) {
         const int nd[4] = {pnodes[p].x, pnodes[p].y, pnodes[p].z, pnodes[p].w};
+        for (int a = 0; a < 4; ++a) inc[nd[a]].push_back(4 * p + a);
         int mm = 0;
-        for (int a = 0; a < 4; ++a) {
-            inc[nd[a]].push_back(4 * p + a);
-            for (int b = 0; b < 4; ++b) {
-                if (a != b && nd[a] == nd[b]) throw InvalErr{"internal: patch with a repeated node"};
-                if (!(a == b || nd[a] > nd[b])) continue;
-                const int lo = std::min(nd[a], nd[b]), hi = std::max(nd[a], nd[b]);
-                const int* beg = &c->h_ucol[c->h_urow[lo]];
-                const int* end = &c->h_ucol[0] + c->h_urow[lo + 1];
-                const int* at = std::lower_bound(beg, end, hi);
-                if (at == end || *at != hi) throw InvalErr{"internal: patch block missing from the pattern"};
-                slots[(size_t)p * 16 + mm] = (int)(at - &c->h_ucol[0]);
-                kid[p] |= (uint64_t)(4 * a + b) << (4 * mm);
-                ++mm;
-            }
-        }
+        for (int pass = 0; pass < 2; ++pass)   // diagonal blocks, then the others
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b) {
+                    if (a != b && nd[a] == nd[b]) throw InvalErr{"internal: patch with a repeated node"};
+                    if (pass == 0 ? a != b : !(nd[a] > nd[b])) continue;
+                    const int lo = std::min(nd[a], nd[b]), hi = std::max(nd[a], nd[b]);
+                    const int* beg = &c->h_ucol[c->h_urow[lo]];
+                    const int* end = &c->h_ucol[0] + c->h_urow[lo + 1];
+                    const int* at = std::lower_bound(beg, end, hi);
+                    if (at == end || *at != hi) throw InvalErr{"internal: patch block missing from the pattern"};
+                    slots[(size_t)p * 16 + mm] = (int)(at - &c->h_ucol[0]);
+                    kid[p] |= (uint64_t)(4 * a + b) << (4 * mm);
+                    ++mm;
+                }
     }
     std::vector<int> inc_ptr(N + 1, 0), inc_flat;
     for (int n = 0; n < N; ++n) {
@@ -557,7 +558,7 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
     alloc(c->vals, (size_t)c->nnzb_u * 144 * (c->fp32 ? sizeof(float) : sizeof(double)));
     alloc(c->slot, (size_t)std::max(c->nnzb_u - N, 1LL) * 12 * sizeof(double));
     alloc(c->diag0, vecb);
-    alloc(c->dinv, (size_t)N * DINV_VALS * (c->fp32 ? sizeof(float) : sizeof(double)));
+    alloc(c->dinv, (size_t)N * SYM12_VALS * (c->fp32 ? sizeof(float) : sizeof(double)));
     alloc(c->e_patch, (size_t)std::max(P, 1) * 3 * sizeof(double));
     alloc(c->g_patch, (size_t)std::max(P, 1) * 48 * sizeof(double));
     alloc(c->e_shell, (size_t)S * 3 * sizeof(double));
@@ -1174,12 +1175,12 @@ shell_status shell_get_bsr(shell_ctx* c, int32_t shell, int32_t* nnzb, int32_t* 
                                   hipMemcpyDeviceToHost, c->stream));
             sync(c);
         }
-        // The products read the stored block of pair (i, j >= i) as A_ij
-        // row-major (for i = j too: the assembled diagonal block, stored
-        // column-major, is symmetric up to rounding, and the matrix returned
-        // here is the one the products apply).  The ABI returns row-major
-        // blocks: block (n, col) is the stored block (n, col) as it is for
-        // col >= n, and the transpose of the stored block (col, n) for col < n.
+        // The products read the stored block of pair (i, j > i) as A_ij
+        // row-major and a diagonal block from its packed symmetric layout
+        // (the matrix returned here is the one the products apply).  The ABI
+        // returns row-major blocks: block (n, col) is the stored block
+        // (n, col) as it is for col > n, the transpose of the stored block
+        // (col, n) for col < n, and the expanded packed block for col = n.
         for (int n = n0; n < n1; ++n)
             for (int b = c->h_row_ptr[n]; b < c->h_row_ptr[n + 1]; ++b) {
                 const int col = c->h_col_idx[b];
@@ -1189,7 +1190,10 @@ shell_status shell_get_bsr(shell_ctx* c, int32_t shell, int32_t* nnzb, int32_t* 
                 const double* src = tmp.data() + (size_t)(ub - u0) * 144;
                 double* dst = vals + (size_t)(b - b0) * 144;
                 for (int r = 0; r < 12; ++r)
-                    for (int cc = 0; cc < 12; ++cc) dst[r * 12 + cc] = col >= n ? src[r * 12 + cc] : src[cc * 12 + r];
+                    for (int cc = 0; cc < 12; ++cc)
+                        dst[r * 12 + cc] = col == n  ? src[sym12_pos(r, cc)]
+                                           : col > n ? src[r * 12 + cc]
+                                                     : src[cc * 12 + r];
             }
     }
     return SHELL_OK;

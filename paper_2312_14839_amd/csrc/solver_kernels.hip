@@ -4,9 +4,10 @@
 //
 // Matrix storage (the Hessian is symmetric): block row i keeps only its
 // blocks (i, j >= i), the diagonal block first.  The stored block of pair
-// (i, j) holds A_ji column-major, which is A_ij row-major (entry (r, c) of
-// A_ij at r*12 + c; the diagonal block A_ii, symmetric, is its own
-// transpose).  Rows and columns of prescribed DOFs stay in the matrix; the
+// (i, j > i) holds A_ji column-major, which is A_ij row-major (entry (r, c)
+// of A_ij at r*12 + c); the diagonal block A_ii, symmetric, keeps its 84
+// distinct values in the packed layout at SYM12_VALS (the first 84 of its
+// 144 places).  Rows and columns of prescribed DOFs stay in the matrix; the
 // solver masks them (free-DOF bit masks per node), which equals replacing
 // them by identity rows and columns with a zero right-hand side.
 //
@@ -126,25 +127,21 @@ __device__ __forceinline__ void group_sum(const TV (&part)[12], int lane, int t,
     wave_lds_sync();
 }
 
-// One stored block in three parts of 4 rows (4 loads of R values each):
-// part[c] += sum_k A[c][R t + k] xv[k] and tv[k] += sum_c A[c][R t + k] x_i[c],
-// with x_i[c] read from the group's LDS copy xl (re-read per block: kept in
-// registers through the row, the 12 values would cost the registers that
-// let 16 waves share a CU).  FIRST (the diagonal block, xv = this lane's
-// part of x_i): part is set instead, and instead of tv, dl = sum_c x_i[c]
-// part[c], whose sum over the group is x_i^T A_ii x_i (a scalar: a
-// transposed product needed only after the row's other blocks would keep
-// the whole block's registers live through them).  A scheduling barrier
+// One stored off-diagonal block in three parts of 4 rows (4 loads of R
+// values each): part[c] += sum_k A[c][R t + k] xv[k] and tv[k] += sum_c
+// A[c][R t + k] x_i[c], with x_i[c] read from the group's LDS copy xl
+// (re-read per block: kept in registers through the row, the 12 values would
+// cost the registers that let 16 waves share a CU).  A scheduling barrier
 // after each part keeps one part's loads in flight at a time per wave (more
 // registers per wave measured no faster: the waves of a CU keep enough
 // loads in flight).  pst/pv: the previous block's transposed product, stored
 // after this block's first loads are issued (loads and stores share one
 // in-order completion counter, so a store issued first would delay the
 // wait for the loads behind it).
-template <class TM, class TV, bool ABS, bool FIRST>
+template <class TM, class TV, bool ABS>
 __device__ __forceinline__ void block_sym(const TM* __restrict__ blk, const TV (&xv)[Lay<TM>::R],
                                           const TV* __restrict__ xl, TV (&part)[12], TV (&tv)[Lay<TM>::R],
-                                          TV& dl, TV* pst = nullptr, const TV* pv = nullptr) {
+                                          TV* pst = nullptr, const TV* pv = nullptr) {
     constexpr int R = Lay<TM>::R;
     asm volatile("" ::: "memory");   // re-read xl for this block
 #pragma unroll
@@ -157,16 +154,62 @@ __device__ __forceinline__ void block_sym(const TM* __restrict__ blk, const TV (
         for (int c = 0; c < 4; ++c) {
             const int cc = 4 * h + c;
             const TV xc = xl[cc];
-            TV sacc = FIRST ? TV(0) : part[cc];
+            TV sacc = part[cc];
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 const TV av = ABS ? (TV)fabs(a[c][k]) : (TV)a[c][k];
                 sacc += av * xv[k];
-                if (!FIRST) tv[k] += av * xc;
+                tv[k] += av * xc;
             }
             part[cc] = sacc;
-            if (FIRST) dl += xc * sacc;
         }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// The diagonal block of a row, kept as its 84 distinct values (packed
+// layout at SYM12_VALS), against x_i: part[c] = sum_k A[c][R t + k] xv[k]
+// for the 12 rows c (set, not added) and dl = sum_c x_i[c] part[c], whose
+// sum over the group is x_i^T A_ii x_i (a scalar: a transposed product,
+// needed only after the row's other blocks, would keep the block's registers
+// live through them).
+// Row pair b needs the 2x2 block (b, t): stored as such at 12 b + 4 d
+// (d = t - b mod 6 <= 2) or 72 + 4 b (d = 3, b < 3), else as the transpose
+// of block (t, b) at 12 t + 4 (6 - d) or 72 + 4 t.  Three parts of two row
+// pairs, as block_sym.
+template <class TM, class TV, bool ABS>
+__device__ __forceinline__ void block_diag_sym(const TM* __restrict__ dblk, int t, const TV (&xv)[2],
+                                               const TV* __restrict__ xl, TV (&part)[12], TV& dl) {
+    asm volatile("" ::: "memory");   // re-read xl for this block
+    // the lane-dependent positions are recomputed per row from an opaque
+    // copy of t (hoisted out of the caller's loops they would hold registers)
+    asm volatile("" : "+v"(t));
+#pragma unroll
+    for (int h = 0; h < 3; ++h) {
+        TM a[2][4];
+        bool tr[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int b = 2 * h + e;
+            const int d = (t - b + 6) % 6;
+            tr[e] = d >= 4 || (d == 3 && b >= 3);
+            const int pos = d <= 2 ? 12 * b + 4 * d : d >= 4 ? 12 * t + 4 * (6 - d) : 72 + 4 * (b < 3 ? b : t);
+            Vec4<TM>::ld(dblk + pos, a[e]);
+        }
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int cc = 2 * (2 * h + e) + i;
+                // A[cc][R t + k], k = 0, 1: entry (i, k) of block (b, t)
+                const TM m0 = i == 0 ? a[e][0] : (tr[e] ? a[e][1] : a[e][2]);
+                const TM m1 = i == 0 ? (tr[e] ? a[e][2] : a[e][1]) : a[e][3];
+                const TV v0 = ABS ? (TV)fabs(m0) : (TV)m0, v1 = ABS ? (TV)fabs(m1) : (TV)m1;
+                TV sacc = v0 * xv[0];
+                sacc += v1 * xv[1];
+                part[cc] = sacc;
+                dl += xl[cc] * sacc;
+            }
         __builtin_amdgcn_sched_barrier(0);
     }
 }
@@ -188,8 +231,9 @@ __device__ __forceinline__ TV row_sym(const SymBsr& m, const TM* __restrict__ va
 #pragma unroll
     for (int k = 0; k < R; ++k) xl[R * t + k] = xo[k];
     wave_lds_sync();
-    TV dl = TV(0), tv0[R];
-    block_sym<TM, TV, ABS, true>(vals + (size_t)b0 * 144 + R * t, xo, xl, part, tv0, dl);
+    static_assert(R == 2, "the packed diagonal block is read by column pairs");
+    TV dl = TV(0);
+    block_diag_sym<TM, TV, ABS>(vals + (size_t)b0 * 144, t, xo, xl, part, dl);
     TV pv[R];
     TV* pst = nullptr;
     for (int b = b0 + 1; b < b1; ++b) {
@@ -198,7 +242,7 @@ __device__ __forceinline__ TV row_sym(const SymBsr& m, const TM* __restrict__ va
         const int ts = m.tslot[b];
 #pragma unroll
         for (int k = 0; k < R; ++k) tv[k] = TV(0);
-        block_sym<TM, TV, ABS, false>(vals + (size_t)b * 144 + R * t, xv, xl, part, tv, dl, pst, pv);
+        block_sym<TM, TV, ABS>(vals + (size_t)b * 144 + R * t, xv, xl, part, tv, pst, pv);
         pst = slot + (size_t)ts * 12 + R * t;
 #pragma unroll
         for (int k = 0; k < R; ++k) pv[k] = tv[k];
@@ -259,7 +303,7 @@ __global__ void k_spmv_fin(int nnodes, const int* __restrict__ lptr, const doubl
 // Inverse of each node's 12x12 diagonal block (prescribed rows/columns
 // replaced by identity) by an FP64 Cholesky factorisation; 16 lanes per node.
 // The inverse is symmetric, so a node keeps its 21 distinct 2x2 blocks
-// (84 values instead of 144, layout at DINV_VALS).  A 2x2 diagonal block
+// (84 values instead of 144, layout at SYM12_VALS).  A 2x2 diagonal block
 // takes both off-diagonal entries from column 2a + 1, so the stored matrix
 // is exactly symmetric.
 template <class TV>
@@ -276,7 +320,8 @@ __global__ __launch_bounds__(256) void k_bj_factor(int nnodes, const int* __rest
     if (act && ln < 12) {
         const size_t base = (size_t)diag_blk[node] * 144;
         for (int c = 0; c < 12; ++c) {
-            double v = vals_fp32 ? (double)((const float*)vals)[base + c * 12 + ln] : ((const double*)vals)[base + c * 12 + ln];
+            const size_t at = base + sym12_pos(ln, c);
+            double v = vals_fp32 ? (double)((const float*)vals)[at] : ((const double*)vals)[at];
             const bool fr = is_free(fm, node, ln), fc = is_free(fm, node, c);
             if (!fr || !fc) v = (ln == c && !fr) ? 1.0 : 0.0;
             A[sub][ln][c] = v;
@@ -316,7 +361,7 @@ __global__ __launch_bounds__(256) void k_bj_factor(int nnodes, const int* __rest
         // column ln = 2b + j goes into the stored blocks (a, b) of column
         // pair b: a = b - k (mod 6) at 12 a + 4 k, and a = b - 3 at 72 + 4 a
         const int bc = ln >> 1, j = ln & 1;
-        TV* dn = dinv + (size_t)node * DINV_VALS;
+        TV* dn = dinv + (size_t)node * SYM12_VALS;
         for (int k = 1; k < 3; ++k) {
             const int a = (bc + 6 - k) % 6;
             dn[12 * a + 4 * k + j] = (TV)y[2 * a];
@@ -342,7 +387,7 @@ __global__ void k_save_diag(int nnodes, const int* __restrict__ diag_blk, const 
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nnodes * 12) return;
     const int node = t / 12, w = t % 12;
-    const size_t at = (size_t)diag_blk[node] * 144 + w * 12 + w;
+    const size_t at = (size_t)diag_blk[node] * 144 + sym12_pos(w, w);
     diag[t] = fp32 ? (double)((const float*)vals)[at] : ((const double*)vals)[at];
 }
 
@@ -355,7 +400,7 @@ __global__ void k_regularize(int nnodes, const int* __restrict__ diag_blk, void*
     const int node = t / 12, w = t % 12;
     const double dl = delta_shell[node_shell[node]];
     if (dl <= 0.0) return;
-    const size_t at = (size_t)diag_blk[node] * 144 + w * 12 + w;
+    const size_t at = (size_t)diag_blk[node] * 144 + sym12_pos(w, w);
     const double v = (1.0 + dl) * diag[t];
     if (fp32)
         ((float*)vals)[at] = (float)v;
@@ -604,7 +649,7 @@ __global__ __launch_bounds__(NT) void k_cg(
         int t = Lay<TM>::L;
         t = lane % t;
         asm volatile("" : "+v"(t));
-        const TV* dn = dinv + (size_t)node * DINV_VALS;
+        const TV* dn = dinv + (size_t)node * SYM12_VALS;
         TV m[6][4];
         TV s0 = TV(0), s1 = TV(0);
 #pragma unroll
