@@ -335,6 +335,68 @@ def pseudo_hessian_section(stream, steps=3, warmup=1):
     return out
 
 
+def twist_section(stream, steps=200):
+    """The 30x30-patch twisting sheet (11,532 DOF), `steps` implicit steps of
+    2 ms from rest, plain FP64 and mixed: wall time per step, per-step
+    assembly (Hessian + block-Jacobi factorisation) and PCG kernel time from
+    a second, event-timed run, and the relative displacement error of the
+    mixed trajectory against the FP64 one (position DOFs, against the FP64
+    displacement from the reference) after every step, reported not gated."""
+    import torch
+    from paper_2312_14839_amd import shell as S, workloads as W
+    case = W.case_twist(30)
+    presc = presc_on_device(case, steps)
+    out = {}
+    traj = {}
+    for name, prec in (("fp64", S.SHELL_FP64), ("mixed", S.SHELL_MIXED)):
+        ctx = S.context_for([case], precision=prec, stream=stream, newton_rtol=1e-10, pcg_rtol=1e-10)
+        ctx.autotune(100)
+        res = {}
+        for timed in (False, True):
+            q = torch.from_numpy(case.q0.reshape(-1).copy()).cuda()
+            v = torch.from_numpy(case.v0.reshape(-1).copy()).cuda()
+            q1, v1 = torch.empty_like(q), torch.empty_like(q)
+            qs, stats = [], []
+            ctx.timing_enable(timed)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(steps):
+                rc, st = ctx.newton_step(case.dt, q, v, presc[k], q1, v1, allow_fail=True)
+                if rc != S.SHELL_OK:
+                    raise RuntimeError(f"twist {name}: step {k + 1} failed: {S.STATUS_NAMES.get(rc)}")
+                stats.append(st[0])
+                q, q1 = q1, q
+                v, v1 = v1, v
+                if not timed:
+                    qs.append(q.clone())
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            if timed:
+                tm = ctx.timing_get()["ms"]
+                res["assembly_ms_per_step"] = (tm["hessian"] + tm["bj_factor"]) / steps
+                res["pcg_ms_per_step"] = tm["cg"] / steps
+            else:
+                res["ms_per_step"] = 1e3 * wall / steps
+                res["newton_iters_per_step"] = sum(s["newton_iters"] for s in stats) / steps
+                res["cg_iters_per_step"] = sum(s["pcg_iters_total"] for s in stats) / steps
+                traj[name] = torch.stack(qs).cpu().numpy().reshape(steps, -1, 12)
+        ctx.timing_enable(False)
+        ctx.close()
+        out[name] = res
+    ref_pos = case.ref[:, 0:3]
+    num = np.linalg.norm((traj["mixed"] - traj["fp64"])[:, :, 0:3], axis=(1, 2))
+    den = np.linalg.norm(traj["fp64"][:, :, 0:3] - ref_pos[None], axis=(1, 2))
+    err = num / np.maximum(den, 1e-300)
+    out["mixed"]["rel_disp_err_vs_fp64_max"] = float(err.max())
+    out["mixed"]["rel_disp_err_vs_fp64_last"] = float(err[-1])
+    out["steps"] = steps
+    out["workload"] = "sheet 30x30 patches, centre derivatives twisted at 1 rad/s, dt 2 ms, from rest"
+    print(f"[bench] twist 30x30, {steps} steps: fp64 {out['fp64']['ms_per_step']:.2f} ms/step "
+          f"(assembly {out['fp64']['assembly_ms_per_step']:.3f}, PCG {out['fp64']['pcg_ms_per_step']:.3f}), "
+          f"mixed {out['mixed']['ms_per_step']:.2f} ms/step, max err {err.max():.2e}", file=sys.stderr, flush=True)
+    return out
+
+
 def post_buckling_section(stream, steps=3, before=300):
     """Newton-step time of the 256x256 cylinder after `before` steps of
     compression (past buckling), FP64, CG layout autotuned, with the exact
@@ -492,6 +554,7 @@ def main():
     ap.add_argument("--no-post-buckling", action="store_true")
     ap.add_argument("--no-pseudo", action="store_true")
     ap.add_argument("--no-kernels", action="store_true")
+    ap.add_argument("--no-twist", action="store_true", help="skip the 200-step 30x30 twist section")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="first run a plain device copy of MB megabytes (counter calibration)")
     args = ap.parse_args()
@@ -558,6 +621,8 @@ def main():
         out["post_buckling"] = post_buckling_section(stream)
     if args.workload == "cylinder" and not args.no_pseudo:
         out["hessian_variants"] = pseudo_hessian_section(stream)
+    if args.workload == "cylinder" and not args.no_twist:
+        out["twist"] = twist_section(stream)
     if not args.no_learned:
         out["learned"] = learned_section(stream)
     if not args.no_cpu_baseline:
