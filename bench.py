@@ -178,20 +178,22 @@ def cg_bytes(case, timing, tm_bytes, tv_bytes, resident):
 
 
 def profiled_traffic(case, fp32, kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary of this workload, or None when there is
-    none or the kernel source has changed since it was taken."""
+    """HBM bytes per launch of `kernel` (its FP64 or FP32 instance) from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of this workload, or
+    None when there is none or the kernel source has changed since it was
+    taken."""
     import hashlib
-    if fp32 or case.name != "cylinder256x256":
+    if case.name != "cylinder256x256":
         return None
+    tag = f"{kernel}_fp32" if fp32 else kernel
     here = os.path.dirname(os.path.abspath(__file__))
-    path = os.path.join(here, "profiles", "cylinder256_fp64_rocprof.txt")
+    path = os.path.join(here, "profiles", "cylinder256_rocprof.txt")
     src = os.path.join(here, "paper_2312_14839_amd", "csrc", "solver_kernels.hip")
     if not os.path.exists(path):
         return None
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     for line in open(path):
-        if line.startswith(f"TRAFFIC {kernel} "):
+        if line.startswith(f"TRAFFIC {tag} "):
             f = dict(kv.split("=") for kv in line.split()[2:])
             if f.get("solver_kernels_sha256") == digest:
                 return float(f["bytes_per_launch"])
@@ -613,7 +615,7 @@ def main():
                         "dtype": "f32 Hessian/CG + f64 residual", "rel_disp_err_vs_fp64": float(err),
                         "err_steps": nst, "newton_iters_per_step": newtonm / args.steps,
                         "cg_iters_per_step": sum(s["pcg_iters_total"] for s in stm) / args.steps,
-                        "kernel_ms": tmm["ms"], "roofline": roofm}
+                        "kernel_ms": tmm["ms"], "kernel_launches": tmm["launches"], "roofline": roofm}
         print(f"[bench] mixed: {1e3 * wallm / args.steps:.2f} ms/step, err {err:.2e}", file=sys.stderr, flush=True)
     if not args.no_kernels:
         out["kernels"] = kernels_section(case, stream)
