@@ -334,6 +334,38 @@ def test_newton_step_twist(precision, tol):
     assert rel_disp_error(q1, q_o, case.q0) <= tol
 
 
+def test_twist_trajectory_mixed_tracks_fp64():
+    """The 30x30 twisting sheet stepped 200 times from rest (2 ms steps),
+    plain FP64 and mixed precision from the same start: after every step the
+    mixed state is within 1e-5 relative displacement of the FP64 state
+    (position DOFs, against the FP64 displacement from the reference), and
+    every step converges.  The trajectory is compared path to path; the
+    oracle's bar is per-step parity, tested on the first step."""
+    case = W.case_twist(30)
+    sh = S()
+    steps = 200
+    presc = [dev(case.presc((k + 1) * case.dt)) for k in range(steps)]
+    traj = {}
+    for precision in ("fp64", "mixed"):
+        ctx = sh.context_for([case], precision=sh.SHELL_MIXED if precision == "mixed" else sh.SHELL_FP64)
+        q, v = dev(case.q0), dev(case.v0)
+        q1, v1 = torch.empty_like(q), torch.empty_like(q)
+        out = []
+        for k in range(steps):
+            rc, st = ctx.newton_step(case.dt, q, v, presc[k], q1, v1)
+            assert rc == 0, (precision, k, st)
+            q, q1 = q1, q
+            v, v1 = v1, v
+            out.append(q.clone())
+        traj[precision] = torch.stack(out).cpu().numpy().reshape(steps, -1, 12)
+        ctx.close()
+    a, b = traj["fp64"][:, :, 0:3], traj["mixed"][:, :, 0:3]
+    den = np.linalg.norm(a - case.ref[None, :, 0:3], axis=(1, 2))
+    err = np.linalg.norm(b - a, axis=(1, 2)) / den
+    assert den.min() > 0
+    assert err.max() <= 1e-5, err.max()
+
+
 def test_batched_matches_single_shell_oracle():
     cases = W.case_batch(count=5, seed=3, nmin=2, nmax=9)
     sh = S()
