@@ -127,32 +127,34 @@ __device__ __forceinline__ void group_sum(const TV (&part)[12], int lane, int t,
     wave_lds_sync();
 }
 
-// One stored off-diagonal block in three parts of 4 rows (4 loads of R
-// values each): part[c] += sum_k A[c][R t + k] xv[k] and tv[k] += sum_c
+// One stored off-diagonal block in parts of NR rows (NR loads of R values
+// each): part[c] += sum_k A[c][R t + k] xv[k] and tv[k] += sum_c
 // A[c][R t + k] x_i[c], with x_i[c] read from the group's LDS copy xl
 // (re-read per block: kept in registers through the row, the 12 values would
 // cost the registers that let 16 waves share a CU).  A scheduling barrier
-// after each part keeps one part's loads in flight at a time per wave (more
-// registers per wave measured no faster: the waves of a CU keep enough
-// loads in flight).  pst/pv: the previous block's transposed product, stored
-// after this block's first loads are issued (loads and stores share one
-// in-order completion counter, so a store issued first would delay the
-// wait for the loads behind it).
-template <class TM, class TV, bool ABS>
+// after each part keeps one part's loads in flight at a time per wave.
+// NR = 12 (the whole block in flight) where the registers allow it: FP64
+// CG at 2 waves per SIMD 115 -> 114 us per iteration, the SpMV 93 -> 90 us;
+// the FP32 CG at 1024 threads would spill and keeps NR = 4.  pst/pv: the
+// previous block's transposed product, stored after this block's first
+// loads are issued (loads and stores share one in-order completion counter,
+// so a store issued first would delay the wait for the loads behind it).
+template <class TM, class TV, bool ABS, int NR>
 __device__ __forceinline__ void block_sym(const TM* __restrict__ blk, const TV (&xv)[Lay<TM>::R],
                                           const TV* __restrict__ xl, TV (&part)[12], TV (&tv)[Lay<TM>::R],
                                           TV* pst = nullptr, const TV* pv = nullptr) {
     constexpr int R = Lay<TM>::R;
+    static_assert(12 % NR == 0, "parts of equal size");
     asm volatile("" ::: "memory");   // re-read xl for this block
 #pragma unroll
-    for (int h = 0; h < 3; ++h) {
-        TM a[4][R];
+    for (int h = 0; h < 12 / NR; ++h) {
+        TM a[NR][R];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) VecLoad<TM, R>::ld(blk + (4 * h + c) * 12, a[c]);
+        for (int c = 0; c < NR; ++c) VecLoad<TM, R>::ld(blk + (NR * h + c) * 12, a[c]);
         if (h == 0 && pst) VecStore<TV, R>::st(pst, pv);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int cc = 4 * h + c;
+        for (int c = 0; c < NR; ++c) {
+            const int cc = NR * h + c;
             const TV xc = xl[cc];
             TV sacc = part[cc];
 #pragma unroll
@@ -222,7 +224,7 @@ __device__ __forceinline__ void block_diag_sym(const TM* __restrict__ dblk, int 
 // values), copied for the group to xl[12] in LDS; xe(col, xv) gives this
 // lane's R entries of x for column block col.  ABS multiplies by |A|
 // instead of A.
-template <class TM, class TV, bool ABS, class XF>
+template <class TM, class TV, bool ABS, int NR, class XF>
 __device__ __forceinline__ TV row_sym(const SymBsr& m, const TM* __restrict__ vals, int node, int t,
                                       const TV (&xo)[Lay<TM>::R], XF xe, TV* __restrict__ xl, TV* __restrict__ slot,
                                       TV (&part)[12]) {
@@ -242,7 +244,7 @@ __device__ __forceinline__ TV row_sym(const SymBsr& m, const TM* __restrict__ va
         const int ts = m.tslot[b];
 #pragma unroll
         for (int k = 0; k < R; ++k) tv[k] = TV(0);
-        block_sym<TM, TV, ABS>(vals + (size_t)b * 144 + R * t, xv, xl, part, tv, pst, pv);
+        block_sym<TM, TV, ABS, NR>(vals + (size_t)b * 144 + R * t, xv, xl, part, tv, pst, pv);
         pst = slot + (size_t)ts * 12 + R * t;
 #pragma unroll
         for (int k = 0; k < R; ++k) pv[k] = tv[k];
@@ -281,7 +283,7 @@ __global__ __launch_bounds__(256) void k_spmv_rows(int nnodes, SymBsr m, const T
     };
     double xo[R], part[12], yo[R];
     xe(node, xo);
-    (void)row_sym<TM, double, ABS>(m, vals, node, t, xo, xe, xls[wv] + grp * 12, slot, part);
+    (void)row_sym<TM, double, ABS, 12>(m, vals, node, t, xo, xe, xls[wv] + grp * 12, slot, part);
     group_sum<double, R, L>(part, lane, t, gbase, red[wv], yo);
 #pragma unroll
     for (int i = 0; i < R; ++i) y[(size_t)node * 12 + R * t + i] = yo[i];
@@ -745,7 +747,8 @@ __global__ __launch_bounds__(NT) void k_cg(
             };
             TV pn[R], part[12], u[R];
             xe(node, pn);
-            const TV dl = row_sym<TM, TV, false>(m, vals, node, t, pn, xe, xls[wv] + grp * 12, slot, part);
+            const TV dl = row_sym<TM, TV, false, sizeof(TM) == 8 ? 12 : 4>(m, vals, node, t, pn, xe,
+                                                                          xls[wv] + grp * 12, slot, part);
             group_sum<TV, R, L>(part, lane, t, gsrc, red[wv], u);
             pq[0] -= (double)dl;
 #pragma unroll
