@@ -134,7 +134,7 @@ __device__ __forceinline__ void group_sum(const TV (&part)[12], int lane, int t,
 // cost the registers that let 16 waves share a CU).  A scheduling barrier
 // after each part keeps one part's loads in flight at a time per wave.
 // NR = 12 (the whole block in flight) where the registers allow it: FP64
-// CG at 2 waves per SIMD 115 -> 114 us per iteration, the SpMV 93 -> 90 us;
+// CG at 2 waves per SIMD 115 -> 113 us per iteration, the SpMV 93 -> 90 us;
 // the FP32 CG at 1024 threads would spill and keeps NR = 4.  pst/pv: the
 // previous block's transposed product, stored after this block's first
 // loads are issued (loads and stores share one in-order completion counter,
