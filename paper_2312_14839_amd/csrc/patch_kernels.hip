@@ -188,7 +188,7 @@ __global__ void k_shell_energy(int nshell, const ShellParams* __restrict__ shell
     red[2][threadIdx.x] = a2;
     __syncthreads();
     for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
+        if ((int)threadIdx.x < w)
             for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
         __syncthreads();
     }
