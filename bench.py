@@ -251,8 +251,8 @@ def assembly_bytes(patches, stored, rows, s):
 def kernels_section(case, stream, reps=20):
     """Stand-alone rooflines on the workload's matrix at its initial state
     (K(q0) + M/dt^2): the SpMV (masked, both launches) against 8 TB/s, the
-    Hessian assembly against the MFMA peak of its precision and (as the
-    spec figure) assembly + SpMV bytes against 8 TB/s."""
+    Hessian assembly against the MFMA peak of its precision and the
+    combined assembly + SpMV bytes against 8 TB/s."""
     import torch
     from paper_2312_14839_amd import shell as S
     out = {}
@@ -561,8 +561,8 @@ def main():
                     help="first run a plain device copy of MB megabytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
-              "see DESIGN.md for how the path would shard", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU (asked for {args.gpus}); "
+              "sharding across GPUs is designed but not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2312_14839_amd import shell as S
