@@ -289,8 +289,10 @@ __global__ __launch_bounds__(256) void k_spmv_rows(int nnodes, SymBsr m, const T
     for (int i = 0; i < R; ++i) y[(size_t)node * 12 + R * t + i] = yo[i];
 }
 
-__global__ void k_spmv_fin(int nnodes, const int* __restrict__ lptr, const double* __restrict__ slot,
-                           const uint16_t* __restrict__ fr, const double* __restrict__ b, double* __restrict__ y) {
+// Two entries (16 bytes) of one row per thread; the row's slots in order.
+// y and b 16-byte aligned (k_spmv_fin1 otherwise: one entry per thread).
+__global__ void k_spmv_fin1(int nnodes, const int* __restrict__ lptr, const double* __restrict__ slot,
+                            const uint16_t* __restrict__ fr, const double* __restrict__ b, double* __restrict__ y) {
     const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= nnodes * 12) return;
     const int node = e / 12, w = e % 12;
@@ -299,6 +301,31 @@ __global__ void k_spmv_fin(int nnodes, const int* __restrict__ lptr, const doubl
     if (b) v = b[e] - v;
     if (!is_free(fr, node, w)) v = 0.0;
     y[e] = v;
+}
+__global__ void k_spmv_fin(int nnodes, const int* __restrict__ lptr, const double* __restrict__ slot,
+                           const uint16_t* __restrict__ fr, const double* __restrict__ b, double* __restrict__ y) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= nnodes * 6) return;
+    const int node = e / 6, w = 2 * (e % 6);
+    const size_t at = (size_t)node * 12 + w;
+    double v[2];
+    VecLoad<double, 2>::ld(y + at, v);
+    const int k0 = lptr[node], k1 = lptr[node + 1];
+    for (int k = k0; k < k1; ++k) {
+        double sv[2];
+        VecLoad<double, 2>::ld(slot + (size_t)k * 12 + w, sv);
+        v[0] += sv[0];
+        v[1] += sv[1];
+    }
+    if (b) {
+        double bv[2];
+        VecLoad<double, 2>::ld(b + at, bv);
+        v[0] = bv[0] - v[0];
+        v[1] = bv[1] - v[1];
+    }
+    if (!is_free(fr, node, w)) v[0] = 0.0;
+    if (!is_free(fr, node, w + 1)) v[1] = 0.0;
+    VecStore<double, 2>::st(y + at, v);
 }
 
 // ---------------------------------------------------- block-Jacobi factor
@@ -998,8 +1025,11 @@ void launch_spmv(hipStream_t st, int nnodes, const SymBsr& m, const TM* vals, co
         hipLaunchKernelGGL((k_spmv_rows<TM, true>), grid, dim3(256), 0, st, nnodes, m, vals, fc, x, y, slot);
     else
         hipLaunchKernelGGL((k_spmv_rows<TM, false>), grid, dim3(256), 0, st, nnodes, m, vals, fc, x, y, slot);
-    hipLaunchKernelGGL(k_spmv_fin, grid1(nnodes * 12), dim3(256), 0, st, nnodes, m.lptr, slot, fr,
-                       (mode & 4) ? b : nullptr, y);
+    const double* bb = (mode & 4) ? b : nullptr;
+    if ((((uintptr_t)y | (uintptr_t)bb) & 15u) == 0)
+        hipLaunchKernelGGL(k_spmv_fin, grid1(nnodes * 6), dim3(256), 0, st, nnodes, m.lptr, slot, fr, bb, y);
+    else
+        hipLaunchKernelGGL(k_spmv_fin1, grid1(nnodes * 12), dim3(256), 0, st, nnodes, m.lptr, slot, fr, bb, y);
 }
 template void launch_spmv<double>(hipStream_t, int, const SymBsr&, const double*, const uint16_t*, const double*,
                                   const double*, double*, double*, int);

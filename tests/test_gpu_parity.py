@@ -143,6 +143,15 @@ def test_spmv(precision):
     assert np.abs(host(y) - y_ref).max() <= 1e-13 * np.abs(y_ref).max()
     ctx.spmv(dev(x), y, masked=False)
     assert np.abs(host(y) - A @ x).max() <= 1e-13 * np.abs(y_ref).max()
+    # vectors only 8-byte aligned (views one double into a buffer): the same
+    # bits as from aligned ones
+    xb = torch.zeros(x.size + 1, dtype=torch.float64, device="cuda")
+    yb = torch.zeros_like(xb)
+    xb[1:] = dev(x)
+    for masked in (True, False):
+        ctx.spmv(dev(x), y, masked=masked)
+        ctx.spmv(xb[1:], yb[1:], masked=masked)
+        assert torch.equal(yb[1:], y)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
