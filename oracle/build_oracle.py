@@ -4,7 +4,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["patch.cpp", "global.cpp", "capi.cpp"]
+SOURCES = ["patch.cpp", "global.cpp", "capi.cpp", "ray.cpp"]
 LIB = os.path.join(HERE, "liborc.so")
 
 

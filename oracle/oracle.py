@@ -81,6 +81,13 @@ def _load(path=_LIB_PATH):
     lib.orc_linear_solve.argtypes = [sp, d, d, C.POINTER(C.c_uint8), C.c_double, C.c_int, d, d,
                                      C.c_double, C.c_int, C.POINTER(C.c_int)]
     lib.orc_linear_solve.restype = C.c_int
+    i64 = C.POINTER(C.c_int64)
+    lib.orc_bh_to_bezier.argtypes = [d, C.c_double, C.c_double, d]
+    lib.orc_bezier_eval.argtypes = [d, C.c_double, C.c_double, d, d, d]
+    lib.orc_ray_cast.argtypes = [d, C.c_int, d, C.c_double, C.c_int, C.c_double, C.c_double, C.c_int, d, i64]
+    lib.orc_ray_cast.restype = C.c_int
+    lib.orc_ray_cast_many.argtypes = [d, C.c_int, d, C.c_int64, C.c_double, C.c_int, C.c_double, C.c_double,
+                                      C.c_int, d, C.POINTER(C.c_int), i64]
     return lib
 
 

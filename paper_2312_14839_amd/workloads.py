@@ -269,3 +269,95 @@ def random_state(case: Case, seed: int, pos_sigma: float = 1e-3, der_sigma: floa
     q[:, 0:3] += rng.normal(0.0, pos_sigma, size=(case.nodes, 3))
     q[:, 3:12] += rng.normal(0.0, der_sigma, size=(case.nodes, 9))
     return q
+
+
+# ------------------------------------------------------- ray casting scenes
+def height_field_ref(n1: int, n2: int, f, lx: float = 1.0, ly: float = 1.0, x0: float = 0.0,
+                     y0: float = 0.0) -> np.ndarray:
+    """Open n1 x n2 grid over [x0, x0+lx] x [y0, y0+ly] with xi = (x, y) and
+    z = f(x, y); ``f`` returns (z, z_x, z_y, z_xy) so the nodal DOFs are the
+    surface's own position and derivatives."""
+    cols = n1 + 1
+    ref = np.zeros(((n2 + 1) * cols, 12))
+    for j in range(n2 + 1):
+        for i in range(cols):
+            x, y = x0 + lx * i / n1, y0 + ly * j / n2
+            z, zx, zy, zxy = f(x, y)
+            n = j * cols + i
+            ref[n, 0:3] = (x, y, z)
+            ref[n, 3:6] = (1.0, 0.0, zx)
+            ref[n, 6:9] = (0.0, 1.0, zy)
+            ref[n, 9:12] = (0.0, 0.0, zxy)
+    return ref
+
+
+def _saddle(x, y):
+    # a bicubic Hermite patch reproduces this polynomial exactly
+    return (0.25 * x * y - 0.15 * x * x + 0.1 * y * y, 0.25 * y - 0.3 * x, 0.25 * x + 0.2 * y, 0.25)
+
+
+def _drape(x, y):
+    # a bump with folds: A g(x) g(y) + B sin(k x) y^2, g(t) = exp(-t^2 / s)
+    A, s, B, k = 0.35, 0.08, 0.04, 8.0 * math.pi
+    gx, gy = math.exp(-x * x / s), math.exp(-y * y / s)
+    dgx, dgy = -2.0 * x / s * gx, -2.0 * y / s * gy
+    sk, ck = math.sin(k * x), math.cos(k * x)
+    return (A * gx * gy + B * sk * y * y, A * dgx * gy + B * k * ck * y * y, A * gx * dgy + 2.0 * B * sk * y,
+            A * dgx * dgy + 2.0 * B * k * ck * y)
+
+
+def _scene_case(name, n1, n2, periodic1, dxi1, dxi2, ref) -> Case:
+    m = _material()
+    z = np.zeros_like(ref)
+    return Case(name, n1, n2, periodic1, dxi1, dxi2, m["young"], m["poisson"], m["thickness"], m["density"],
+                GRAVITY, ref, np.zeros_like(ref, dtype=np.uint8), ref.copy(), z, 1e-3)
+
+
+RENDER_SCENES = ("plane", "cylinder", "drape")
+
+
+def render_scene(name: str) -> Case:
+    """The three scenes of the paper's rendering comparison (Sec. 5.1,
+    Table 1): one warped patch ("plane"), a 10x10-patch open cylinder and a
+    10x10-patch draped sheet."""
+    if name == "plane":
+        return _scene_case("plane", 1, 1, 0, 1.0, 1.0, height_field_ref(1, 1, _saddle))
+    if name == "cylinder":
+        return _scene_case("cylinder", 10, 10, 1, 2.0 * math.pi * 0.3 / 10, 0.1, cylinder_ref(10, 10, 0.3, 1.0))
+    if name == "drape":
+        return _scene_case("drape", 10, 10, 0, 0.1, 0.1, height_field_ref(10, 10, _drape, x0=-0.5, y0=-0.5))
+    raise ValueError(f"unknown scene {name!r}")
+
+
+# camera (eye, target) per scene: every scene fills most of the frame
+_CAMERAS = {
+    "plane": ((0.5, -0.35, 0.95), (0.5, 0.5, 0.0)),
+    "cylinder": ((1.2, -1.4, 1.0), (0.0, 0.0, 0.5)),
+    "drape": ((0.0, -1.05, 1.05), (0.0, 0.02, 0.02)),
+}
+
+
+def camera_rays(scene: str, width: int, height: int, spp: int = 1, seed: int = 8, fov_deg: float = 35.0,
+                eye=None, target=None) -> np.ndarray:
+    """Pinhole camera rays [height*width*spp, 6] (origin, unit direction),
+    pixel-major, ``spp`` samples per pixel jittered uniformly inside the
+    pixel with a seeded generator (up = +z)."""
+    e, t = _CAMERAS.get(scene, ((0.0, -2.0, 1.0), (0.0, 0.0, 0.0)))
+    e = np.asarray(eye if eye is not None else e, dtype=np.float64)
+    t = np.asarray(target if target is not None else t, dtype=np.float64)
+    fwd = t - e
+    fwd /= np.linalg.norm(fwd)
+    right = np.cross(fwd, (0.0, 0.0, 1.0))
+    right /= np.linalg.norm(right)
+    up = np.cross(right, fwd)
+    th = math.tan(math.radians(fov_deg) / 2.0)
+    rng = np.random.default_rng(seed)
+    jit = rng.random((height, width, spp, 2))
+    px = (np.arange(width)[None, :, None] + jit[..., 0]) / width * 2.0 - 1.0
+    py = 1.0 - (np.arange(height)[:, None, None] + jit[..., 1]) / height * 2.0
+    d = fwd + (px * th * width / height)[..., None] * right + (py * th)[..., None] * up
+    d /= np.linalg.norm(d, axis=-1, keepdims=True)
+    rays = np.empty((height * width * spp, 6))
+    rays[:, 0:3] = e
+    rays[:, 3:6] = d.reshape(-1, 3)
+    return rays

@@ -1,0 +1,176 @@
+"""Pins of the oracle's ray--patch intersection (Sec. 5), CPU only.
+
+The Bezier form is pinned to the Hermite patch (the oracle's Hermite shape
+functions, themselves pinned in test_oracle_basis) and to the end
+properties every cubic Bezier curve has.  Ray casting is pinned to closed
+forms: a bicubic Hermite patch built from the nodal data of a polynomial of
+degree <= 3 per variable *is* that polynomial surface, so the hit of a ray
+with the saddle z = 0.25xy - 0.15x^2 + 0.1y^2 is a root of a quadratic in
+tau.  Then: the closest of several surfaces wins whatever the patch order,
+misses are misses, the midpoint and the Newton forms agree, every hit lies
+on its ray, and the candidate heap of the test scenes stays within the
+device kernel's capacity."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle import ray_oracle as R
+from paper_2312_14839_amd import workloads as W
+
+EPS = 1e-10
+HEAP_MAX = 64      # candidates one ray may hold in the device kernel
+
+
+def _scene(name):
+    c = W.render_scene(name)
+    sh = O.make_shell(c.n1, c.n2, c.dxi1, c.dxi2, c.young, c.poisson, c.thickness, c.density,
+                      periodic1=c.periodic1)
+    return R.bezier_grid(sh, c.ref)
+
+
+def _saddle_ctrl():
+    return _scene("plane")
+
+
+def _saddle_tau(o, d):
+    """Smallest tau > 0 with o + tau d on z = 0.25xy - 0.15x^2 + 0.1y^2 over
+    [0, 1]^2 (closed form), or inf."""
+    ox, oy, oz = o
+    dx, dy, dz = d
+    a = 0.25 * dx * dy - 0.15 * dx * dx + 0.1 * dy * dy
+    b = 0.25 * (ox * dy + oy * dx) - 0.3 * ox * dx + 0.2 * oy * dy - dz
+    c = 0.25 * ox * oy - 0.15 * ox * ox + 0.1 * oy * oy - oz
+    if abs(a) < 1e-14:
+        roots = [-c / b]
+    else:
+        disc = b * b - 4 * a * c
+        if disc < 0:
+            return math.inf
+        sq = math.sqrt(disc)
+        q = -0.5 * (b + math.copysign(sq, b))
+        roots = [q / a, c / q]
+    best = math.inf
+    for t in roots:
+        x, y = ox + t * dx, oy + t * dy
+        if t > 0 and 0 <= x <= 1 and 0 <= y <= 1:
+            best = min(best, t)
+    return best
+
+
+def _random_rays(rng, n, lo=0.05, hi=0.95, above=1.0):
+    x, y = rng.uniform(lo, hi, n), rng.uniform(lo, hi, n)
+    tgt = np.column_stack([x, y, 0.25 * x * y - 0.15 * x * x + 0.1 * y * y])   # on the saddle
+    org = tgt + np.column_stack([rng.normal(0, 0.4, n), rng.normal(0, 0.4, n), np.full(n, above)])
+    d = tgt - org
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    return np.hstack([org, d])
+
+
+def _sin_incidence(ctrl, patch, u, v, d):
+    _, xu, xv = R.bezier_eval(ctrl[patch], u, v)
+    n = np.cross(xu, xv)
+    return abs(n @ d) / (np.linalg.norm(n) * np.linalg.norm(d))
+
+
+def test_bezier_form_reproduces_the_hermite_patch():
+    rng = np.random.default_rng(11)
+    for _ in range(5):
+        corner = rng.normal(size=(4, 12))
+        dxi1, dxi2 = rng.uniform(0.05, 2.0, 2)
+        ctrl = R.bezier_patch(corner, dxi1, dxi2)
+        q = corner.reshape(16, 3)          # shape function I = 4c + k
+        for u, v in rng.random((8, 2)):
+            phi = O.shape_functions(u, v, dxi1, dxi2)
+            x, xu, xv = R.bezier_eval(ctrl, u, v)
+            np.testing.assert_allclose(x, phi[0] @ q, rtol=1e-13, atol=1e-13)
+            np.testing.assert_allclose(xu, dxi1 * (phi[1] @ q), rtol=1e-12, atol=1e-12)
+            np.testing.assert_allclose(xv, dxi2 * (phi[2] @ q), rtol=1e-12, atol=1e-12)
+
+
+def test_bezier_corners_and_end_tangents():
+    """A Bezier patch interpolates its corner control points; its edge
+    tangents there are 3 (p_10 - p_00) and 3 (p_01 - p_00); its twist is
+    9 (p_11 - p_10 - p_01 + p_00)."""
+    rng = np.random.default_rng(12)
+    corner = rng.normal(size=(4, 12))
+    h1, h2 = 0.3, 0.7
+    p = R.bezier_patch(corner, h1, h2)
+    for c, (i, j) in enumerate([(0, 0), (3, 0), (0, 3), (3, 3)]):
+        np.testing.assert_allclose(p[i, j], corner[c, 0:3], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(3 * (p[1, 0] - p[0, 0]), h1 * corner[0, 3:6], atol=1e-14)
+    np.testing.assert_allclose(3 * (p[0, 1] - p[0, 0]), h2 * corner[0, 6:9], atol=1e-14)
+    np.testing.assert_allclose(3 * (p[3, 0] - p[2, 0]), h1 * corner[1, 3:6], atol=1e-14)
+    np.testing.assert_allclose(3 * (p[3, 3] - p[3, 2]), h2 * corner[3, 6:9], atol=1e-14)
+    np.testing.assert_allclose(9 * (p[1, 1] - p[1, 0] - p[0, 1] + p[0, 0]), h1 * h2 * corner[0, 9:12], atol=1e-13)
+
+
+@pytest.mark.parametrize("newton", [0, 8])
+def test_hits_on_the_saddle_match_the_closed_form(newton):
+    ctrl = _saddle_ctrl()
+    rays = _random_rays(np.random.default_rng(13), 200)
+    hit, patch = R.ray_cast(ctrl, rays, eps=EPS, newton_iters=newton)
+    for r in range(len(rays)):
+        t = _saddle_tau(rays[r, :3], rays[r, 3:])
+        assert math.isfinite(t) and patch[r] == 0
+        s = _sin_incidence(ctrl, 0, hit[r, 1], hit[r, 2], rays[r, 3:])
+        tol = 1e-11 if newton else 2 * EPS / max(s, 1e-3) + 1e-12
+        assert abs(hit[r, 0] - t) <= tol, (r, hit[r], t)
+        x = rays[r, :3] + t * rays[r, 3:]
+        assert abs(hit[r, 1] - x[0]) <= 1e-9 and abs(hit[r, 2] - x[1]) <= 1e-9
+
+
+@pytest.mark.parametrize("newton", [0, 8])
+def test_misses(newton):
+    ctrl = _saddle_ctrl()
+    rng = np.random.default_rng(14)
+    up = _random_rays(rng, 50)
+    up[:, 3:] *= -1                                   # pointing away from the surface
+    outside = _random_rays(rng, 50, lo=1.2, hi=1.8)   # aimed beside the patch
+    for rays in (up, outside):
+        hit, patch = R.ray_cast(ctrl, rays, eps=EPS, newton_iters=newton)
+        for r in range(len(rays)):
+            assert _saddle_tau(rays[r, :3], rays[r, 3:]) == math.inf
+        assert (patch == -1).all() and np.isinf(hit[:, 0]).all()
+
+
+@pytest.mark.parametrize("newton", [0, 8])
+def test_closest_surface_wins_in_any_patch_order(newton):
+    base = _saddle_ctrl()[0]
+    dz = (-0.2, 0.1, 0.0, 0.25)
+    layers = np.stack([base + np.array([0, 0, z]) for z in dz])
+    rays = _random_rays(np.random.default_rng(15), 100, above=1.5)
+    hit, patch = R.ray_cast(layers, rays, eps=EPS, newton_iters=newton)
+    perm = [2, 3, 0, 1]
+    hit2, patch2 = R.ray_cast(layers[perm], rays, eps=EPS, newton_iters=newton)
+    assert (np.array(perm)[patch2] == patch).all()
+    np.testing.assert_allclose(hit2[:, 0], hit[:, 0], rtol=0, atol=1e-9)
+    seen = set()
+    for r in range(len(rays)):
+        taus = [_saddle_tau(rays[r, :3] - np.array([0, 0, z]), rays[r, 3:]) for z in dz]
+        k = int(np.argmin(taus))
+        assert math.isfinite(taus[k]) and patch[r] == k
+        assert abs(hit[r, 0] - taus[k]) <= (1e-11 if newton else 1e-8)
+        seen.add(k)
+    assert len(seen) >= 2      # the nearest layer differs between rays
+
+
+@pytest.mark.parametrize("scene", W.RENDER_SCENES)
+def test_midpoint_and_newton_forms_agree_and_hits_lie_on_rays(scene):
+    ctrl = _scene(scene)
+    rays = W.camera_rays(scene, 32, 32, 1)
+    h0, p0, s0 = R.ray_cast(ctrl, rays, eps=EPS, newton_iters=0, stats=True)
+    h1, p1, s1 = R.ray_cast(ctrl, rays, eps=EPS, newton_iters=8, stats=True)
+    assert ((p0 >= 0) == (p1 >= 0)).all()
+    assert (p0 >= 0).mean() > 0.4
+    for r in np.nonzero(p1 >= 0)[0]:
+        d = rays[r, 3:]
+        s = _sin_incidence(ctrl, p1[r], h1[r, 1], h1[r, 2], d)
+        assert abs(h0[r, 0] - h1[r, 0]) <= 2 * EPS / max(s, 1e-3) + 1e-12
+        for h, p, tol in ((h0, p0, 2 * EPS), (h1, p1, 1e-11)):
+            x, _, _ = R.bezier_eval(ctrl[p[r]], h[r, 1], h[r, 2])
+            assert np.linalg.norm(x - (rays[r, :3] + h[r, 0] * d)) <= tol
+    # the Newton form examines far fewer candidates (Table 1 of the paper)
+    assert s1[:, 0].sum() * 2 < s0[:, 0].sum()
+    assert max(s0[:, 1].max(), s1[:, 1].max()) <= HEAP_MAX // 2
