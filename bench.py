@@ -503,6 +503,79 @@ def _cpu_model():
     return None
 
 
+# Table 1 of the paper: seconds to render each scene on a desktop CPU (16
+# samples per pixel, image size not stated, shading included), for the
+# midpoint subdivision and for the Newton-accelerated form.  Context only.
+PAPER_RENDER_S = {"plane": (58.3, 4.5), "cylinder": (91.6, 9.7), "drape": (86.0, 14.8)}
+
+
+def render_section(stream, width=512, height=512, spp=16, reps=3, eps=1e-10):
+    """Static ray--patch intersection (Sec. 5.1) on the paper's three render
+    scenes (one warped patch, a 10x10-patch cylinder, a 10x10-patch draped
+    sheet): Bezier control points from the shell state on the device, then
+    one pinhole-camera frame of width x height pixels x spp jittered samples,
+    midpoint subdivision and Newton-accelerated forms.  Kernel time from HIP
+    events around `reps` launches; pops = candidate surfaces examined per
+    ray.  The oracle's rate on a seeded sample of the same rays (all host
+    threads) is reported with the CPU baseline."""
+    import torch
+    from paper_2312_14839_amd import shell as S, workloads as W
+    out = {"workload": f"{width}x{height} pixels x {spp} samples per scene, eps {eps:g}, hole 1e-3, "
+                       f"8 Newton steps", "rays_per_frame": width * height * spp}
+    for sc in W.RENDER_SCENES:
+        case = W.render_scene(sc)
+        ctx = S.context_for([case], stream=stream)
+        ctrl = torch.empty((case.patches, 4, 4, 3), dtype=torch.float64, device="cuda")
+        ctx.bezier(torch.as_tensor(case.ref, device="cuda"), ctrl)
+        rays_h = W.camera_rays(sc, width, height, spp)
+        rays = torch.as_tensor(rays_h, device="cuda")
+        n = rays.shape[0]
+        hit = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+        patch = torch.empty(n, dtype=torch.int32, device="cuda")
+        pops = torch.empty(n, dtype=torch.int32, device="cuda")
+        res = {"patches": case.patches}
+        for mode, ni in (("midpoint", 0), ("newton", 8)):
+            S.ray_cast(ctrl, rays, hit, patch, pops, stream=stream, newton_iters=ni, eps=eps)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                S.ray_cast(ctrl, rays, hit, patch, pops, stream=stream, newton_iters=ni, eps=eps)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            p, pp = patch.cpu().numpy(), pops.cpu().numpy()
+            res[mode] = {"ms_per_frame": ms, "rays_per_s": n / (ms * 1e-3), "hit_fraction": float(np.mean(p >= 0)),
+                         "no_result": int(np.sum(p < -1)), "pops_mean": float(pp.mean()),
+                         "pops_p99": float(np.percentile(pp, 99)), "pops_max": int(pp.max()),
+                         "paper_table1_s": PAPER_RENDER_S[sc][0 if ni == 0 else 1]}
+            print(f"[bench] render {sc} {mode}: {ms:.2f} ms/frame, {n / ms / 1e3:.1f} M rays/s, "
+                  f"pops mean {pp.mean():.2f} max {pp.max()}", file=sys.stderr, flush=True)
+        ctx.close()
+        out[sc] = res
+    return out
+
+
+def render_cpu_baseline(width=512, height=512, spp=16, eps=1e-10, sample=200_000):
+    """The oracle's ray casting rate (all host threads) on a seeded sample of
+    the render section's rays, per scene and form."""
+    from oracle import oracle as O, ray_oracle as R
+    from paper_2312_14839_amd import workloads as W
+    out = {"unit": "rays/s", "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+           "kind": "oracle", "sample": f"{sample} of the {width * height * spp} rays of each frame"}
+    for sc in W.RENDER_SCENES:
+        case = W.render_scene(sc)
+        ctrl = R.bezier_grid(O.make_shell(case.n1, case.n2, case.dxi1, case.dxi2, case.young, case.poisson,
+                                          case.thickness, case.density, periodic1=case.periodic1), case.ref)
+        rays = W.camera_rays(sc, width, height, spp)
+        idx = np.random.default_rng(41).choice(len(rays), min(sample, len(rays)), replace=False)
+        for mode, ni in (("midpoint", 0), ("newton", 8)):
+            t0 = time.perf_counter()
+            R.ray_cast(ctrl, rays[idx], eps=eps, newton_iters=ni)
+            out[f"{sc}_{mode}"] = len(idx) / (time.perf_counter() - t0)
+    return out
+
+
 def cpu_baseline(budget_s=12.0, budget_1t=8.0):
     """Oracle patch energy + gradient + Hessian evaluations per second on a
     32x32-patch cylinder section (1024 patches): all host threads (the
@@ -557,6 +630,7 @@ def main():
     ap.add_argument("--no-pseudo", action="store_true")
     ap.add_argument("--no-kernels", action="store_true")
     ap.add_argument("--no-twist", action="store_true", help="skip the 200-step 30x30 twist section")
+    ap.add_argument("--no-render", action="store_true", help="skip the ray--patch intersection section")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="first run a plain device copy of MB megabytes (counter calibration)")
     args = ap.parse_args()
@@ -625,10 +699,14 @@ def main():
         out["hessian_variants"] = pseudo_hessian_section(stream)
     if args.workload == "cylinder" and not args.no_twist:
         out["twist"] = twist_section(stream)
+    if args.workload == "cylinder" and not args.no_render:
+        out["render"] = render_section(stream)
     if not args.no_learned:
         out["learned"] = learned_section(stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
+        if "render" in out:
+            out["cpu_baseline"]["render"] = render_cpu_baseline()
     print(json.dumps(out), flush=True)
 
 

@@ -321,6 +321,62 @@ shell_status shell_mlp_record(shell_ctx *c, float *feat_dev, float *tgt_dev, int
 /* Samples recorded since the last shell_mlp_record. */
 shell_status shell_mlp_recorded(const shell_ctx *c, int64_t *count);
 
+/* ---------------------------------------------- ray--patch intersection
+ * Sec. 5: a bicubic Hermite patch is a bicubic Bezier surface, whose
+ * control-point bounding boxes bound it (convex-hull property); Sec. 5.1
+ * finds the closest intersection of a ray with a set of such surfaces. */
+
+/* Bezier control points of every patch of the context at state q_dev
+ * [total_nodes][12] (Sec. 5, the Bernstein form of the patch).
+ * ctrl_dev [total_patches][4][4][3] float64: p_ij of patch p at
+ * ((4p + i)*4 + j)*3, i along xi1 (local parameter u in [0, 1]), j along xi2
+ * (v); patch (pi, pj) of shell s is patch_begin(s) + pj*n1 + pi, shells in
+ * descriptor order.  Enqueued on the context's stream. */
+shell_status shell_bezier(shell_ctx *c, const double *q_dev, double *ctrl_dev);
+
+#define SHELL_RAY_HEAP_MAX 64
+
+typedef struct {
+    double eps;            /* a candidate whose control-point box has a diagonal <= eps |d| is an answer;
+                              its tau interval is then narrower than eps (tau in units of |d|); > 0 */
+    double newton_tol;     /* Newton converged when |x(u,v) - x0 - tau d| <= newton_tol (length); > 0 */
+    double hole;           /* half-width of the box abandoned around a Newton hit, as a fraction of the
+                              candidate rectangle's width in each direction (Fig. subany); in (0, 0.5) */
+    int32_t newton_iters;  /* 0: midpoint subdivision only, the first answer popped is the result;
+                              1..64: Newton's method from each candidate's centre, at most this many steps */
+    int32_t max_depth;     /* subdivision depth at which a candidate is an answer whatever its size; 1..60 */
+    int32_t heap_cap;      /* candidates one ray may hold; 1..SHELL_RAY_HEAP_MAX */
+    int32_t device;        /* HIP device */
+    void *stream;          /* hipStream_t; NULL = the null stream */
+} shell_ray_opts;
+
+/* eps 1e-10, newton_tol 1e-12, hole 1e-3, newton_iters 8, max_depth 60,
+ * heap_cap SHELL_RAY_HEAP_MAX, device 0, stream NULL. */
+void shell_ray_default_opts(shell_ray_opts *o);
+
+/* Static ray--patch intersection (Sec. 5.1): for each ray x0 + tau d the
+ * smallest tau >= 0 at which it meets one of the n_patches Bezier patches,
+ * by subdivision of the patches with a min-heap of candidate rectangles
+ * keyed by the tau at which the ray enters their control-point box
+ * (Eq. ineqray), optionally accelerated by Newton's method.
+ *   ctrl_dev  [n_patches][4][4][3], e.g. written by shell_bezier (any
+ *             Bezier patches in that layout); n_patches >= 0, < 2^24.
+ *   rays_dev  [n_rays][6] float64: origin xyz, direction xyz.
+ *   hit_dev   [n_rays][3] float64 out: tau, u, v of the closest hit in the
+ *             patch's own parameters; tau = +inf when there is none.
+ *   patch_dev [n_rays] int32 out: the hit's patch, -1 for a miss, -2 when
+ *             the ray's candidates outgrew heap_cap or it examined 65536
+ *             of them (no result: raise heap_cap or eps), -3 for an invalid
+ *             ray (zero or non-finite direction, non-finite origin).
+ *   pops_dev  [n_rays] int32 out, or NULL: candidates the ray examined.
+ * Device pointers valid on opts->stream; the caller owns them.  Enqueued on
+ * that stream; no synchronisation.  Cost per ray is linear in n_patches
+ * (every patch's box is tested; there is no scene hierarchy).  Invalid
+ * sizes or options return SHELL_E_INVAL before anything is enqueued, a
+ * failed launch SHELL_E_DEVICE; shell_last_error(NULL) describes both. */
+shell_status shell_ray_cast(const double *ctrl_dev, int32_t n_patches, const double *rays_dev, int64_t n_rays,
+                            const shell_ray_opts *opts, double *hit_dev, int32_t *patch_dev, int32_t *pops_dev);
+
 #ifdef __cplusplus
 }
 #endif

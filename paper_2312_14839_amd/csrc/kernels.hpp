@@ -25,6 +25,32 @@ void launch_hessian(hipStream_t st, const int* patch_list, int nlist, const int4
                     const ShellParams* shells, const double* phi, const double* q, const double* qbar,
                     double mass_scale, double dt_damp, int elastic, int pseudo, T* vals);
 
+// --------------------------------------------------------- ray kernels
+// ctrl: [P][4][4][3] Bezier control points, p_ij at ((4p + i)*4 + j)*3.
+void launch_bezier(hipStream_t st, int npatch, const int4* patch_nodes, const int* patch_shell,
+                   const ShellParams* shells, const double* q, double* ctrl);
+
+constexpr int RAY_HEAP_MAX = 64;       // candidate surfaces one ray can hold
+constexpr int RAY_MAX_DEPTH = 60;      // depth field of a heap entry: 6 bits
+constexpr int RAY_MAX_PATCHES = (1 << 24) - 1;
+constexpr int RAY_LDS_PATCHES = 128;   // scenes up to this size are staged in LDS
+constexpr int RAY_MAX_POPS = 1 << 16;  // candidates one ray may examine
+constexpr int RAY_CHUNK_PER_LANE = 8;  // rays per block = 256 lanes x this
+
+struct RayParams {
+    double eps;          // a surface whose box diagonal is <= eps |d| ends the subdivision
+    double newton_tol;   // Newton converged when |x(u,v) - x0 - tau d| <= newton_tol
+    double hole;         // abandoned half-width around a Newton hit, fraction of the rectangle
+    int newton_iters;    // 0: midpoint subdivision only
+    int max_depth;       // <= RAY_MAX_DEPTH
+    int heap_cap;        // <= RAY_HEAP_MAX
+};
+// hit: [n][3] tau, u, v; patch: [n] (-1 miss, -2 heap full or RAY_MAX_POPS
+// candidates examined, -3 invalid ray);
+// pops: [n] surfaces popped, may be null.
+void launch_ray_cast(hipStream_t st, const double* ctrl, int npatch, const double* rays, long long nrays,
+                     const RayParams& o, double* hit, int* patch, int* pops);
+
 // ------------------------------------------------------ solver kernels
 // Row partition of the node rows into blocks that never straddle a shell;
 // used by the CG kernel and by the per-shell reductions.

@@ -1559,6 +1559,67 @@ shell_status shell_set_nodal_forces(shell_ctx* c, const double* f_dev) {
     API_CATCH
 }
 
+shell_status shell_bezier(shell_ctx* c, const double* q_dev, double* ctrl_dev) {
+    if (!c) return SHELL_E_INVAL;
+    if (!q_dev || !ctrl_dev) {
+        c->err = "q_dev and ctrl_dev are required";
+        return SHELL_E_INVAL;
+    }
+    API_TRY
+    HIPCHK(hipSetDevice(c->opts.device));
+    launch_bezier(c->stream, c->P, dptr<int4>(c->patch_nodes), dptr<int>(c->patch_shell),
+                  dptr<ShellParams>(c->shells_d), q_dev, ctrl_dev);
+    HIPCHK(hipGetLastError());
+    return SHELL_OK;
+    API_CATCH
+}
+
+void shell_ray_default_opts(shell_ray_opts* o) {
+    if (!o) return;
+    o->eps = 1e-10;
+    o->newton_tol = 1e-12;
+    o->hole = 1e-3;
+    o->newton_iters = 8;
+    o->max_depth = RAY_MAX_DEPTH;
+    o->heap_cap = RAY_HEAP_MAX;
+    o->device = 0;
+    o->stream = nullptr;
+}
+
+shell_status shell_ray_cast(const double* ctrl_dev, int32_t n_patches, const double* rays_dev, int64_t n_rays,
+                            const shell_ray_opts* o, double* hit_dev, int32_t* patch_dev, int32_t* pops_dev) {
+    static_assert(SHELL_RAY_HEAP_MAX == RAY_HEAP_MAX, "heap size of the ABI and of the kernel");
+    g_create_error.clear();
+    auto bad = [](const char* m) {
+        g_create_error = m;
+        return SHELL_E_INVAL;
+    };
+    if (!o) return bad("opts is required");
+    if (n_patches < 0 || n_patches > RAY_MAX_PATCHES) return bad("n_patches must be in [0, 2^24)");
+    if (n_rays < 0 || n_rays > (int64_t)256 * INT32_MAX) return bad("n_rays out of range");
+    if (n_rays == 0) return SHELL_OK;
+    if (!rays_dev || !hit_dev || !patch_dev || (n_patches > 0 && !ctrl_dev))
+        return bad("rays_dev, hit_dev, patch_dev and (with patches) ctrl_dev are required");
+    if (!(o->eps > 0) || !std::isfinite(o->eps)) return bad("eps must be > 0");
+    if (!(o->newton_tol > 0) || !std::isfinite(o->newton_tol)) return bad("newton_tol must be > 0");
+    if (!(o->hole > 0 && o->hole < 0.5)) return bad("hole must be in (0, 0.5)");
+    if (o->newton_iters < 0 || o->newton_iters > 64) return bad("newton_iters must be in [0, 64]");
+    if (o->max_depth < 1 || o->max_depth > RAY_MAX_DEPTH) return bad("max_depth must be in [1, 60]");
+    if (o->heap_cap < 1 || o->heap_cap > RAY_HEAP_MAX) return bad("heap_cap must be in [1, SHELL_RAY_HEAP_MAX]");
+    hipError_t e = hipSetDevice(o->device);
+    if (e == hipSuccess) {
+        RayParams rp{o->eps, o->newton_tol, o->hole, o->newton_iters, o->max_depth, o->heap_cap};
+        launch_ray_cast((hipStream_t)o->stream, ctrl_dev, n_patches, rays_dev, n_rays, rp, hit_dev, patch_dev,
+                        pops_dev);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) {
+        g_create_error = std::string("HIP error in shell_ray_cast: ") + hipGetErrorString(e);
+        return SHELL_E_DEVICE;
+    }
+    return SHELL_OK;
+}
+
 shell_status shell_point_load(const shell_desc* d, double xi1, double xi2, const double* force, double* f_nodal) {
     if (!d || !force || !f_nodal || d->n1 < 1 || d->n2 < 1 || !(d->dxi1 > 0) || !(d->dxi2 > 0) ||
         (d->periodic1 && d->n1 < 3) || !std::isfinite(xi1) || !std::isfinite(xi2))

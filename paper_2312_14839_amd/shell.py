@@ -94,6 +94,12 @@ class shell_timing(C.Structure):
                 "cg_iter_blocks": self.cg_iter_blocks, "cg_iters_max": self.cg_iters_max}
 
 
+class shell_ray_opts(C.Structure):
+    _fields_ = [("eps", C.c_double), ("newton_tol", C.c_double), ("hole", C.c_double),
+                ("newton_iters", C.c_int32), ("max_depth", C.c_int32), ("heap_cap", C.c_int32),
+                ("device", C.c_int32), ("stream", C.c_void_p)]
+
+
 class ShellError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -153,6 +159,12 @@ def _load():
     lib.shell_mlp_record.restype = C.c_int32
     lib.shell_mlp_recorded.argtypes = [vp, P(C.c_int64)]
     lib.shell_mlp_recorded.restype = C.c_int32
+    lib.shell_bezier.argtypes = [vp, vp, vp]
+    lib.shell_bezier.restype = C.c_int32
+    lib.shell_ray_default_opts.argtypes = [P(shell_ray_opts)]
+    lib.shell_ray_default_opts.restype = None
+    lib.shell_ray_cast.argtypes = [vp, C.c_int32, vp, C.c_int64, P(shell_ray_opts), vp, vp, vp]
+    lib.shell_ray_cast.restype = C.c_int32
     return lib
 
 
@@ -163,7 +175,7 @@ EXPORTED = ["shell_default_opts", "shell_create", "shell_destroy", "shell_last_e
             "shell_newton_step", "shell_timing_enable", "shell_timing_get", "shell_mlp_set_params",
             "shell_mlp_get_params", "shell_mlp_forward", "shell_mlp_loss_grad", "shell_mlp_train",
             "shell_mlp_record", "shell_mlp_recorded", "shell_autotune", "shell_set_nodal_forces",
-            "shell_point_load"]
+            "shell_point_load", "shell_bezier", "shell_ray_default_opts", "shell_ray_cast"]
 
 MLP_IN, MLP_HIDDEN, MLP_OUT = 36, 128, 12
 MLP_PARAMS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_OUT + MLP_OUT
@@ -243,6 +255,10 @@ class ShellContext:
         e = (C.c_double * self.n_shells)()
         self._check(lib.shell_energy_grad_hess(self.h, _ptr(q), e, _ptr(grad), int(hessian)))
         return np.array(e[:])
+
+    def bezier(self, q, ctrl):
+        """Bezier control points ctrl [total_patches, 4, 4, 3] of state q."""
+        self._check(lib.shell_bezier(self.h, _ptr(q), _ptr(ctrl)))
 
     def assemble(self, q, mass_scale=0.0, elastic=True):
         self._check(lib.shell_assemble(self.h, _ptr(q), float(mass_scale), int(elastic)))
@@ -354,6 +370,30 @@ def point_load(case, xi1, xi2, force, f_nodal=None):
     if rc != SHELL_OK:
         raise ShellError(rc, "point outside the shell's parameter domain or invalid descriptor")
     return out
+
+
+def ray_opts(**kw) -> shell_ray_opts:
+    """shell_ray_opts with the library's defaults, then the given fields."""
+    o = shell_ray_opts()
+    lib.shell_ray_default_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def ray_cast(ctrl, rays, hit, patch, pops=None, stream=None, **kw):
+    """shell_ray_cast on device tensors: ctrl [P, 4, 4, 3] float64 (or None
+    for no patches), rays [n, 6] float64, hit [n, 3] float64, patch [n] int32,
+    pops [n] int32 or None; ``stream`` a hipStream_t handle (int) or None for
+    the null stream.  Keyword arguments set fields of shell_ray_opts."""
+    o = ray_opts(**kw)
+    o.device = rays.device.index or 0
+    o.stream = C.c_void_p(stream)  # None: the null stream
+    n_patches = ctrl.shape[0] if ctrl is not None else 0
+    rc = lib.shell_ray_cast(_ptr(ctrl) if n_patches else None, n_patches, _ptr(rays), rays.shape[0], C.byref(o),
+                            _ptr(hit), _ptr(patch), _ptr(pops))
+    if rc != SHELL_OK:
+        raise ShellError(rc, lib.shell_last_error(None).decode())
 
 
 def context_for(cases, **kw) -> ShellContext:

@@ -115,3 +115,32 @@ def test_point_load_is_the_consistent_nodal_load():
             assert abs(np.sum(fn * q) - f @ x) <= 1e-13 * max(1.0, abs(f @ x))
     with pytest.raises(S().ShellError):
         S().point_load(cases[0], -0.1, 0.2, (0, 0, 1))
+
+
+def test_ray_opts_defaults_and_validation():
+    """shell_ray_cast checks sizes, pointers and options on the host and
+    returns SHELL_E_INVAL before any device call; no rays is a no-op."""
+    s = S()
+    o = s.ray_opts()
+    assert (o.eps, o.newton_tol, o.hole) == (1e-10, 1e-12, 1e-3)
+    assert (o.newton_iters, o.max_depth, o.heap_cap, o.device) == (8, 60, s_heap_max(), 0)
+    fake = C.c_void_p(0x1000)     # never dereferenced: validation fails first
+    lib = s.lib
+
+    def call(n_patches=1, n_rays=1, ctrl=fake, rays=fake, hit=fake, patch=fake, **kw):
+        return lib.shell_ray_cast(ctrl, n_patches, rays, n_rays, C.byref(s.ray_opts(**kw)), hit, patch, None)
+
+    assert lib.shell_ray_cast(fake, 1, fake, 1, None, fake, fake, None) == s.SHELL_E_INVAL
+    assert call(n_rays=0, rays=None, hit=None, patch=None) == s.SHELL_OK
+    cases = [dict(n_patches=-1), dict(n_patches=1 << 24), dict(n_rays=-1), dict(rays=None), dict(hit=None),
+             dict(patch=None), dict(ctrl=None), dict(eps=0.0), dict(eps=float("nan")), dict(newton_tol=0.0),
+             dict(hole=0.0), dict(hole=0.5), dict(newton_iters=-1), dict(newton_iters=65), dict(max_depth=0),
+             dict(max_depth=61), dict(heap_cap=0), dict(heap_cap=s_heap_max() + 1)]
+    for kw in cases:
+        assert call(**kw) == s.SHELL_E_INVAL, kw
+        assert lib.shell_last_error(None).decode(), kw
+
+
+def s_heap_max():
+    src = open(HEADER).read()
+    return int(re.search(r"#define SHELL_RAY_HEAP_MAX (\d+)", src).group(1))

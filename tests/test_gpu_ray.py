@@ -1,0 +1,195 @@
+"""Ray--patch intersection on the GPU through the C ABI, against the oracle.
+
+The Bezier control points of shell_bezier are compared with the oracle's
+conversion element by element.  Ray casting is compared on the render
+scenes (one warped patch, a 10x10 cylinder, a 10x10 draped sheet) in the
+midpoint and the Newton forms, each side on its own control points.  Both
+sides run the same search, but they round differently (blossoms against
+De Casteljau splits, reciprocal order, fused multiply-adds), so the two may
+end on different answer boxes of one hit: tau must agree within the
+method's own accuracy, 2 eps / sin(incidence) (an answer box has a diagonal
+of at most eps |d|, and near grazing incidence the surface stays that close
+to the ray over a longer stretch), the hit/miss decision must be the same,
+the patch the same unless the hit lies on a patch edge, and the device's
+(u, v) must lie on its ray.  Then the launch of the bench (512x512 pixels,
+16 samples, 4.19 M rays) on a sample, the path for scenes too large for LDS,
+degenerate inputs and the heap-capacity status."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle import ray_oracle as R
+from paper_2312_14839_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+EPS = 1e-10
+
+
+def S():
+    from paper_2312_14839_amd import shell
+    return shell
+
+
+def _dev(a, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype or torch.float64, device="cuda")
+
+
+def _oracle_ctrl(case, q):
+    sh = O.make_shell(case.n1, case.n2, case.dxi1, case.dxi2, case.young, case.poisson, case.thickness,
+                      case.density, periodic1=case.periodic1)
+    return R.bezier_grid(sh, q)
+
+
+def _gpu_ctrl(cases, qs):
+    ctx = S().context_for(cases)
+    try:
+        P = sum(c.patches for c in cases)
+        ctrl = torch.empty((P, 4, 4, 3), dtype=torch.float64, device="cuda")
+        ctx.bezier(_dev(np.concatenate(qs)), ctrl)
+        torch.cuda.synchronize()
+    finally:
+        ctx.close()
+    return ctrl
+
+
+def _cast(ctrl, rays, **kw):
+    n = len(rays)
+    hit = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    patch = torch.empty(n, dtype=torch.int32, device="cuda")
+    pops = torch.empty(n, dtype=torch.int32, device="cuda")
+    S().ray_cast(ctrl, _dev(rays), hit, patch, pops, eps=EPS, **kw)
+    torch.cuda.synchronize()
+    return hit.cpu().numpy(), patch.cpu().numpy(), pops.cpu().numpy()
+
+
+def _on_edge(u, v, tol=1e-6):
+    return min(u, 1 - u, v, 1 - v) <= tol
+
+
+def _compare(ctrl_o, rays, hg, pg, ho, po):
+    assert (pg >= -1).all() and (po >= -1).all()
+    assert ((pg >= 0) == (po >= 0)).all(), np.nonzero((pg >= 0) != (po >= 0))[0][:10]
+    for r in np.nonzero(po >= 0)[0]:
+        d = rays[r, 3:]
+        _, xu, xv = R.bezier_eval(ctrl_o[po[r]], ho[r, 1], ho[r, 2])
+        n = np.cross(xu, xv)
+        s = abs(n @ d) / (np.linalg.norm(n) * np.linalg.norm(d))
+        assert abs(hg[r, 0] - ho[r, 0]) <= 2 * EPS / max(s, 1e-3) + 1e-11, (r, hg[r], ho[r])
+        assert pg[r] == po[r] or (_on_edge(*hg[r, 1:]) and _on_edge(*ho[r, 1:])), (r, pg[r], po[r])
+        x, _, _ = R.bezier_eval(ctrl_o[pg[r]], hg[r, 1], hg[r, 2])
+        assert np.linalg.norm(x - (rays[r, :3] + hg[r, 0] * d)) <= 2 * EPS * np.linalg.norm(d) + 1e-10
+
+
+def test_bezier_matches_oracle():
+    cyl = W.render_scene("cylinder")
+    cases = [W.render_scene("plane"), cyl, W.render_scene("drape"), W.case_twist(n=6)]
+    qs = [c.ref for c in cases[:3]] + [W.random_state(cases[3], seed=21)]
+    got = _gpu_ctrl(cases, qs).cpu().numpy()
+    off = 0
+    for c, q in zip(cases, qs):
+        want = _oracle_ctrl(c, q)
+        np.testing.assert_allclose(got[off:off + c.patches], want, rtol=0, atol=1e-14 * max(1.0, np.abs(q).max()))
+        off += c.patches
+    assert off == got.shape[0]
+
+
+@pytest.mark.parametrize("newton", [0, 8], ids=["midpoint", "newton"])
+@pytest.mark.parametrize("scene", W.RENDER_SCENES)
+def test_ray_cast_matches_oracle(scene, newton):
+    case = W.render_scene(scene)
+    ctrl_o = _oracle_ctrl(case, case.ref)
+    ctrl_g = _gpu_ctrl([case], [case.ref])
+    rays = W.camera_rays(scene, 48, 48, 1, seed=31)
+    ho, po = R.ray_cast(ctrl_o, rays, eps=EPS, newton_iters=newton)
+    hg, pg, pops = _cast(ctrl_g, rays, newton_iters=newton)
+    assert (po >= 0).mean() > 0.4
+    _compare(ctrl_o, rays, hg, pg, ho, po)
+    assert (pops[pg >= 0] >= 1).all()
+
+
+@pytest.mark.parametrize("newton", [0, 8], ids=["midpoint", "newton"])
+def test_scene_larger_than_lds(newton):
+    """256 patches: the kernel reads the control points from global memory."""
+    case = W._scene_case("drape16", 16, 16, 0, 1 / 16, 1 / 16,
+                         W.height_field_ref(16, 16, W._drape, x0=-0.5, y0=-0.5))
+    ctrl_o = _oracle_ctrl(case, case.ref)
+    ctrl_g = _gpu_ctrl([case], [case.ref])
+    rays = W.camera_rays("drape", 32, 32, 1, seed=32)
+    ho, po = R.ray_cast(ctrl_o, rays, eps=EPS, newton_iters=newton)
+    hg, pg, _ = _cast(ctrl_g, rays, newton_iters=newton)
+    _compare(ctrl_o, rays, hg, pg, ho, po)
+
+
+@pytest.mark.parametrize("newton", [0, 8], ids=["midpoint", "newton"])
+def test_full_frame_sampled(newton):
+    """The bench's launch: 512 x 512 pixels x 16 samples of the cylinder."""
+    case = W.render_scene("cylinder")
+    ctrl_o = _oracle_ctrl(case, case.ref)
+    ctrl_g = _gpu_ctrl([case], [case.ref])
+    rays = W.camera_rays("cylinder", 512, 512, 16)
+    hg, pg, _ = _cast(ctrl_g, rays, newton_iters=newton)
+    assert (pg >= -1).all()
+    assert 0.3 < (pg >= 0).mean() < 0.9
+    idx = np.random.default_rng(33).choice(len(rays), 1500, replace=False)
+    ho, po = R.ray_cast(ctrl_o, rays[idx], eps=EPS, newton_iters=newton)
+    _compare(ctrl_o, rays[idx], hg[idx], pg[idx], ho, po)
+    hg2, pg2, _ = _cast(ctrl_g, rays, newton_iters=newton)
+    assert np.array_equal(hg2, hg) and np.array_equal(pg2, pg)       # run to run
+
+
+def test_degenerate_inputs():
+    s = S()
+    case = W.render_scene("plane")
+    ctrl_g = _gpu_ctrl([case], [case.ref])
+    rays = W.camera_rays("plane", 8, 8, 1)
+    # no rays: nothing to do
+    empty = torch.empty((0, 6), dtype=torch.float64, device="cuda")
+    s.ray_cast(ctrl_g, empty, torch.empty((0, 3), dtype=torch.float64, device="cuda"),
+               torch.empty(0, dtype=torch.int32, device="cuda"))
+    # no patches: every ray misses
+    h, p, pops = _cast(None, rays)
+    assert (p == -1).all() and np.isinf(h[:, 0]).all() and (pops == 0).all()
+    # invalid rays
+    bad = rays[:4].copy()
+    bad[0, 3:] = 0.0
+    bad[1, 4] = np.nan
+    bad[2, 0] = np.inf
+    h, p, _ = _cast(ctrl_g, bad)
+    assert list(p[:3]) == [-3, -3, -3] and p[3] == 0 and np.isinf(h[:3, 0]).all()
+    # a ray starting under the surface looking up hits it from below
+    up = np.array([[0.5, 0.5, -1.0, 0.0, 0.0, 1.0]])
+    h, p, _ = _cast(ctrl_g, up)
+    ho, po = R.ray_cast(_oracle_ctrl(case, case.ref), up, eps=EPS, newton_iters=8)
+    assert p[0] == po[0] == 0 and abs(h[0, 0] - ho[0, 0]) <= 1e-11
+
+
+def test_heap_capacity_status():
+    """With room for one candidate most rays of the cylinder run out of heap
+    (status -2, no result); the others are exact."""
+    case = W.render_scene("cylinder")
+    ctrl_o = _oracle_ctrl(case, case.ref)
+    ctrl_g = _gpu_ctrl([case], [case.ref])
+    rays = W.camera_rays("cylinder", 32, 32, 1)
+    hg, pg, _ = _cast(ctrl_g, rays, newton_iters=8, heap_cap=1)
+    assert (pg == -2).sum() > 100 and np.isinf(hg[pg == -2, 0]).all()
+    ok = pg != -2
+    ho, po = R.ray_cast(ctrl_o, rays[ok], eps=EPS, newton_iters=8)
+    _compare(ctrl_o, rays[ok], hg[ok], pg[ok], ho, po)
+
+
+def test_user_stream():
+    case = W.render_scene("drape")
+    ctrl_g = _gpu_ctrl([case], [case.ref])
+    rays = _dev(W.camera_rays("drape", 16, 16, 1))
+    hit = torch.empty((256, 3), dtype=torch.float64, device="cuda")
+    patch = torch.empty(256, dtype=torch.int32, device="cuda")
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        S().ray_cast(ctrl_g, rays, hit, patch, stream=st.cuda_stream, eps=EPS)
+    st.synchronize()
+    h0, p0, _ = _cast(ctrl_g, rays.cpu().numpy())
+    assert np.array_equal(hit.cpu().numpy(), h0) and np.array_equal(patch.cpu().numpy(), p0)
