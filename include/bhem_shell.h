@@ -365,7 +365,7 @@ void shell_ray_default_opts(shell_ray_opts *o);
  *   hit_dev   [n_rays][3] float64 out: tau, u, v of the closest hit in the
  *             patch's own parameters; tau = +inf when there is none.
  *   patch_dev [n_rays] int32 out: the hit's patch, -1 for a miss, -2 when
- *             the ray's candidates outgrew heap_cap or it examined 65536
+ *             the ray's candidates outgrew heap_cap or it examined 2^18
  *             of them (no result: raise heap_cap or eps), -3 for an invalid
  *             ray (zero or non-finite direction, non-finite origin).
  *   pops_dev  [n_rays] int32 out, or NULL: candidates the ray examined.

@@ -34,8 +34,10 @@ constexpr int RAY_HEAP_MAX = 64;       // candidate surfaces one ray can hold
 constexpr int RAY_MAX_DEPTH = 60;      // depth field of a heap entry: 6 bits
 constexpr int RAY_MAX_PATCHES = (1 << 24) - 1;
 constexpr int RAY_LDS_PATCHES = 128;   // scenes up to this size are staged in LDS
-constexpr int RAY_MAX_POPS = 1 << 16;  // candidates one ray may examine
+constexpr int RAY_MAX_POPS = 1 << 18;  // candidates one ray may examine
 constexpr int RAY_CHUNK_PER_LANE = 8;  // rays per block = 256 lanes x this
+constexpr int RAY_TAIL_BUDGET = 512;   // candidates before a ray goes to the cooperative search
+constexpr int RAY_TAIL_SLOTS = 16384;  // rays the cooperative search takes per launch
 
 struct RayParams {
     double eps;          // a surface whose box diagonal is <= eps |d| ends the subdivision

@@ -20,6 +20,7 @@
 // and root boxes) once per block.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "kernels.hpp"
@@ -318,17 +319,88 @@ struct Heap {
     }
 };
 
+// Newton's method from the centre of candidate rc (accelerated form) and
+// the four sub-rectangles: the quadrants of the midpoint, or the pinwheel
+// around the abandoned box about a Newton hit inside rc.  Each
+// sub-rectangle whose box the ray enters before `best` goes to
+// emit(key, thi, rect, tag); emit returns false to stop.  A Newton hit is
+// returned in (ht, hu, hv), ht = INF when there is none.
+template <class Emit>
+__device__ inline void expand(const double* cp, const Ray& r, const RayParams& o, double small, double best,
+                              const double rc[4], int patch, int depth, double& ht, double& hu, double& hv,
+                              Emit&& emit) {
+    double cu = 0.5 * (rc[0] + rc[1]), cv = 0.5 * (rc[2] + rc[3]);
+    double ua = cu, ub = cu, va = cv, vb = cv;
+    ht = INFINITY;
+    if (o.newton_iters > 0) {
+        double u = cu, v = cv, tau;
+        if (newton_hit(cp, r, o.newton_iters, o.newton_tol, u, v, tau) && u >= rc[0] && u <= rc[1] && v >= rc[2] &&
+            v <= rc[3] && tau > 0.0) {
+            ht = tau;
+            hu = u;
+            hv = v;
+            best = fmin(best, tau);
+            const double hw = o.hole * (rc[1] - rc[0]), hh = o.hole * (rc[3] - rc[2]);
+            ua = fmax(rc[0], u - hw);
+            ub = fmin(rc[1], u + hw);
+            va = fmax(rc[2], v - hh);
+            vb = fmin(rc[3], v + hh);
+        }
+    }
+    // left, top, bottom, right of the box [ua, ub] x [va, vb]
+    const double kids[4][4] = {
+        {rc[0], ua, va, rc[3]}, {ua, rc[1], vb, rc[3]}, {rc[0], ub, rc[2], va}, {ub, rc[1], rc[2], vb}};
+    const int ntag = patch | ((depth + 1) << 24) | ((depth + 1 >= o.max_depth) ? (1 << 30) : 0);
+#pragma unroll 1
+    for (int k = 0; k < 4; ++k) {
+        if (!(kids[k][1] > kids[k][0]) || !(kids[k][3] > kids[k][2])) continue;
+        double lo[3], hi[3];
+        sub_box(cp, kids[k][0], kids[k][1], kids[k][2], kids[k][3], lo, hi);
+        double klo, khi, diag;
+        if (!slab(r, lo, hi, klo, khi, diag) || !(klo < best)) continue;
+        if (!emit(klo, khi, kids[k], ntag | (diag <= small ? (1 << 30) : 0))) break;
+    }
+}
+
+// A ray handed from the one-lane search to the cooperative one: its heap
+// and its best answer so far.
+struct LongRay {
+    double best, bu, bv;
+    int bp, pops, n;
+    long long rid;
+};
+struct RayTail {
+    int* count;          // long rays handed over
+    int cap;             // slots
+    LongRay* rays;       // [cap]
+    double* key;         // [cap][RAY_HEAP_MAX]
+    double* thi;         // [cap][RAY_HEAP_MAX]
+    double* rect;        // [cap][RAY_HEAP_MAX][4]
+    int* tag;            // [cap][RAY_HEAP_MAX]
+    int budget;          // candidates a lane examines before handing its ray over (0: never)
+};
+
+__device__ inline void write_result(double* hit, int* patch_out, int* pops_out, long long rid, double t, double u,
+                                    double v, int p, int pops) {
+    hit[3 * rid] = t;
+    hit[3 * rid + 1] = u;
+    hit[3 * rid + 2] = v;
+    patch_out[rid] = p;
+    if (pops_out) pops_out[rid] = pops;
+}
+
 // Rays are handed out per lane: a block owns `chunk` consecutive rays and
 // each lane takes the next unstarted one from an LDS counter when its ray is
-// done, so a lane held by a long search (a ray grazing a silhouette can
-// need thousands of candidates) does not keep the other lanes of its wave
-// idle.  Each loop trip either starts a ray (root boxes of every patch) or
-// examines one candidate.
+// done, so that one lane held by a long search does not keep the rest of
+// its wave idle.  Each loop trip either starts a ray (root boxes of every
+// patch) or examines one candidate.  A ray still searching after
+// `tail.budget` candidates (one grazing a silhouette can need tens of
+// thousands) is handed to k_ray_tail, which works on it with a whole wave.
 template <bool LDS>
 __global__ void __launch_bounds__(256) k_ray_cast(const double* __restrict__ ctrl, int npatch,
                                                   const double* __restrict__ rays, long long nrays, int chunk,
-                                                  RayParams o, double* __restrict__ hit, int* __restrict__ patch_out,
-                                                  int* __restrict__ pops_out) {
+                                                  RayParams o, RayTail tail, double* __restrict__ hit,
+                                                  int* __restrict__ patch_out, int* __restrict__ pops_out) {
     extern __shared__ double lds[];
     __shared__ int s_next;
     const double* cps = ctrl;
@@ -358,7 +430,7 @@ __global__ void __launch_bounds__(256) k_ray_cast(const double* __restrict__ ctr
     Ray r;
     double small = 0.0, best = INFINITY, bu = 0.0, bv = 0.0;
     long long rid = 0;
-    int bp = -1, pops = 0;
+    int bp = -1, pops = 0, budget = 0;
     bool active = false, full = false;
 
     for (;;) {
@@ -373,11 +445,7 @@ __global__ void __launch_bounds__(256) k_ray_cast(const double* __restrict__ ctr
             }
             const double dn = sqrt(dot3(r.d, r.d));
             if (!(dn > 0.0) || !isfinite(dn) || !isfinite(r.o[0] + r.o[1] + r.o[2])) {
-                hit[3 * rid] = INFINITY;
-                hit[3 * rid + 1] = 0.0;
-                hit[3 * rid + 2] = 0.0;
-                patch_out[rid] = -3;
-                if (pops_out) pops_out[rid] = 0;
+                write_result(hit, patch_out, pops_out, rid, INFINITY, 0.0, 0.0, -3, 0);
                 continue;
             }
             small = o.eps * dn;
@@ -386,6 +454,7 @@ __global__ void __launch_bounds__(256) k_ray_cast(const double* __restrict__ ctr
             bu = bv = 0.0;
             bp = -1;
             pops = 0;
+            budget = tail.budget;
             full = false;
             for (int p = 0; p < npatch && !full; ++p) {
                 double lo[3], hi[3];
@@ -410,103 +479,333 @@ __global__ void __launch_bounds__(256) k_ray_cast(const double* __restrict__ ctr
                 hp.push(tlo, thi, rc, p | ((diag <= small || o.max_depth == 0) ? (1 << 30) : 0));
             }
             if (full || hp.n == 0) {  // no candidate (a miss) or no room for them
-                hit[3 * rid] = INFINITY;
-                hit[3 * rid + 1] = 0.0;
-                hit[3 * rid + 2] = 0.0;
-                patch_out[rid] = full ? -2 : -1;
-                if (pops_out) pops_out[rid] = 0;
+                write_result(hit, patch_out, pops_out, rid, INFINITY, 0.0, 0.0, full ? -2 : -1, 0);
                 continue;
             }
             active = true;
+            continue;
+        }
+        // one candidate (the heap is not empty)
+        if (pops == budget) {
+            const int s = atomicAdd(tail.count, 1);
+            if (s < tail.cap) {
+                LongRay lr;
+                lr.best = best;
+                lr.bu = bu;
+                lr.bv = bv;
+                lr.bp = bp;
+                lr.pops = pops;
+                lr.n = hp.n;
+                lr.rid = rid;
+                tail.rays[s] = lr;
+                for (int e = 0; e < hp.n; ++e) {
+                    const long long q = (long long)s * RAY_HEAP_MAX + e;
+                    tail.key[q] = hp.key[e];
+                    tail.thi[q] = hp.thi[e];
+                    tail.rect[4 * q] = hp.rect[e][0];
+                    tail.rect[4 * q + 1] = hp.rect[e][1];
+                    tail.rect[4 * q + 2] = hp.rect[e][2];
+                    tail.rect[4 * q + 3] = hp.rect[e][3];
+                    tail.tag[q] = hp.tag[e];
+                }
+                active = false;
+                continue;
+            }
+            budget = 0;  // no slot left: finish here
+        }
+        bool done = false;
+        if (pops == RAY_MAX_POPS) {  // search budget spent: no result, like a full heap
+            full = true;
         } else {
-            // one candidate (the heap is not empty); `done` ends the search
-            bool done = false;
-            if (pops == RAY_MAX_POPS) {  // search budget spent: no result, like a full heap
-                full = true;
+            double tlo, thi, rc[4];
+            int tg;
+            hp.pop(tlo, thi, rc, tg);
+            ++pops;
+            const int patch = tg & 0xFFFFFF, depth = (tg >> 24) & 63;
+            if (!(tlo < best)) {
+                done = true;
+            } else if (tg & (1 << 30)) {
+                const double t = 0.5 * (tlo + thi);
+                if (t < best) {
+                    best = t;
+                    bu = 0.5 * (rc[0] + rc[1]);
+                    bv = 0.5 * (rc[2] + rc[3]);
+                    bp = patch;
+                }
+                done = o.newton_iters == 0;
             } else {
-                double tlo, thi, rc[4];
-                int tg;
-                hp.pop(tlo, thi, rc, tg);
-                ++pops;
-                const int patch = tg & 0xFFFFFF, depth = (tg >> 24) & 63;
-                if (!(tlo < best)) {
-                    done = true;
-                } else if (tg & (1 << 30)) {
-                    const double t = 0.5 * (tlo + thi);
-                    if (t < best) {
-                        best = t;
-                        bu = 0.5 * (rc[0] + rc[1]);
-                        bv = 0.5 * (rc[2] + rc[3]);
-                        bp = patch;
-                    }
-                    done = o.newton_iters == 0;
-                } else {
-                    const double* cp = cps + 48 * patch;
-                    double cu = 0.5 * (rc[0] + rc[1]), cv = 0.5 * (rc[2] + rc[3]);
-                    double ua = cu, ub = cu, va = cv, vb = cv;
-                    if (o.newton_iters > 0) {
-                        double u = cu, v = cv, tau;
-                        if (newton_hit(cp, r, o.newton_iters, o.newton_tol, u, v, tau) && u >= rc[0] &&
-                            u <= rc[1] && v >= rc[2] && v <= rc[3] && tau > 0.0) {
-                            if (tau < best) {
-                                best = tau;
-                                bu = u;
-                                bv = v;
-                                bp = patch;
-                            }
-                            const double hu = o.hole * (rc[1] - rc[0]), hv = o.hole * (rc[3] - rc[2]);
-                            ua = fmax(rc[0], u - hu);
-                            ub = fmin(rc[1], u + hu);
-                            va = fmax(rc[2], v - hv);
-                            vb = fmin(rc[3], v + hv);
-                        }
-                    }
-                    // quadrants of the midpoint, or the pinwheel around the
-                    // abandoned box [ua, ub] x [va, vb]: left, top, bottom, right
-                    const double kids[4][4] = {{rc[0], ua, va, rc[3]},
-                                               {ua, rc[1], vb, rc[3]},
-                                               {rc[0], ub, rc[2], va},
-                                               {ub, rc[1], rc[2], vb}};
-                    const int ntag = patch | ((depth + 1) << 24) | ((depth + 1 >= o.max_depth) ? (1 << 30) : 0);
-#pragma unroll 1
-                    for (int k = 0; k < 4; ++k) {
-                        if (!(kids[k][1] > kids[k][0]) || !(kids[k][3] > kids[k][2])) continue;
-                        double lo[3], hi[3];
-                        sub_box(cp, kids[k][0], kids[k][1], kids[k][2], kids[k][3], lo, hi);
-                        double klo, khi, diag;
-                        if (!slab(r, lo, hi, klo, khi, diag) || !(klo < best)) continue;
-                        if (hp.n == o.heap_cap) {
-                            full = true;
-                            break;
-                        }
-                        hp.push(klo, khi, kids[k], ntag | (diag <= small ? (1 << 30) : 0));
-                    }
+                double ht, hu, hv;
+                expand(cps + 48 * patch, r, o, small, best, rc, patch, depth, ht, hu, hv,
+                       [&](double k, double th, const double* kr, int tg2) {
+                           if (hp.n == o.heap_cap) {
+                               full = true;
+                               return false;
+                           }
+                           hp.push(k, th, kr, tg2);
+                           return true;
+                       });
+                if (ht < best) {
+                    best = ht;
+                    bu = hu;
+                    bv = hv;
+                    bp = patch;
                 }
             }
-            if (done || full || hp.n == 0) {
-                hit[3 * rid] = full ? INFINITY : (bp >= 0 ? best : INFINITY);
-                hit[3 * rid + 1] = bu;
-                hit[3 * rid + 2] = bv;
-                patch_out[rid] = full ? -2 : bp;
-                if (pops_out) pops_out[rid] = pops;
-                active = false;
-            }
+        }
+        if (done || full || hp.n == 0) {
+            write_result(hit, patch_out, pops_out, rid, full ? INFINITY : (bp >= 0 ? best : INFINITY), bu, bv,
+                         full ? -2 : bp, pops);
+            active = false;
         }
     }
 }
+
+// The cooperative search of one handed-over ray per wave (block of 64).
+// The candidates live in an LDS pool; every step sorts their keys (bitonic
+// network over the pool's slots, free slots keyed +inf), takes the (up to)
+// 64 smallest that the ray enters before the best answer, one per lane, and
+// files their sub-rectangles into the slots thus freed.  The midpoint form
+// ends on the batch's first answer in key order; the accelerated form runs
+// until no candidate is left before the best answer.
+constexpr int TAIL_POOL = 1024;
+
+__global__ void __launch_bounds__(64) k_ray_tail(const double* __restrict__ ctrl, const double* __restrict__ rays,
+                                                 RayParams o, RayTail tail, double* __restrict__ hit,
+                                                 int* __restrict__ patch_out, int* __restrict__ pops_out) {
+    __shared__ double key[TAIL_POOL], thi[TAIL_POOL], rect[TAIL_POOL][4];
+    __shared__ int tag[TAIL_POOL];
+    __shared__ double skey[TAIL_POOL];
+    __shared__ short sidx[TAIL_POOL];
+    const int lane = threadIdx.x;
+    const int count = min(*tail.count, tail.cap);
+    for (int s = blockIdx.x; s < count; s += gridDim.x) {
+        const LongRay lr = tail.rays[s];
+        Ray r;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            r.o[c] = rays[6 * lr.rid + c];
+            r.d[c] = rays[6 * lr.rid + 3 + c];
+        }
+        const double small = o.eps * sqrt(dot3(r.d, r.d));
+        double best = lr.best, bu = lr.bu, bv = lr.bv;
+        int bp = lr.bp, pops = lr.pops, hi = lr.n;
+        bool over = false;
+        __syncthreads();
+        for (int e = lane; e < TAIL_POOL; e += 64) {
+            if (e < lr.n) {
+                const long long q = (long long)s * RAY_HEAP_MAX + e;
+                key[e] = tail.key[q];
+                thi[e] = tail.thi[q];
+                rect[e][0] = tail.rect[4 * q];
+                rect[e][1] = tail.rect[4 * q + 1];
+                rect[e][2] = tail.rect[4 * q + 2];
+                rect[e][3] = tail.rect[4 * q + 3];
+                tag[e] = tail.tag[q];
+            } else {
+                key[e] = INFINITY;
+            }
+        }
+        __syncthreads();
+        for (;;) {
+            // sort (key, slot) over the used slots [0, hi)
+            int n2 = 64;
+            while (n2 < hi) n2 <<= 1;
+            for (int e = lane; e < n2; e += 64) {
+                skey[e] = e < hi ? key[e] : INFINITY;
+                sidx[e] = (short)e;
+            }
+            __syncthreads();
+            for (int k = 2; k <= n2; k <<= 1)
+                for (int j = k >> 1; j > 0; j >>= 1) {
+                    for (int e = lane; e < n2; e += 64) {
+                        const int f = e ^ j;
+                        if (f > e) {
+                            const bool up = (e & k) == 0;
+                            const double a = skey[e], b = skey[f];
+                            // (key, slot) order: free slots before the padding
+                            const bool gt = a > b || (a == b && sidx[e] > sidx[f]);
+                            if (gt == up) {
+                                skey[e] = b;
+                                skey[f] = a;
+                                const short t = sidx[e];
+                                sidx[e] = sidx[f];
+                                sidx[f] = t;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            // candidates the ray enters before the best answer
+            int live = 0;
+            for (int e = 0; e < n2; e += 64) {
+                const unsigned long long m = __ballot(e + lane < n2 && skey[e + lane] < best);
+                live += __popcll(m);
+                if (m != ~0ull) break;
+            }
+            if (live == 0) break;
+            if (pops + min(live, 64) > RAY_MAX_POPS) {
+                over = true;
+                break;
+            }
+            const int m = min(live, 64);
+            // this lane's candidate: an answer box, or a Newton hit
+            double ct = INFINITY, cu = 0.0, cv = 0.0;
+            bool is_answer = false;
+            int cpatch = -1;
+            double kk[4][6];
+            int ktag[4];
+            int nk = 0;
+            if (lane < m) {
+                const int e = sidx[lane];
+                const double tlo = key[e], th = thi[e];
+                const double rc[4] = {rect[e][0], rect[e][1], rect[e][2], rect[e][3]};
+                const int tg = tag[e];
+                cpatch = tg & 0xFFFFFF;
+                if (tg & (1 << 30)) {
+                    is_answer = true;
+                    ct = 0.5 * (tlo + th);
+                    cu = 0.5 * (rc[0] + rc[1]);
+                    cv = 0.5 * (rc[2] + rc[3]);
+                } else {
+                    double ht, hu = 0.0, hv = 0.0;
+                    expand(ctrl + 48 * cpatch, r, o, small, best, rc, cpatch, (tg >> 24) & 63, ht, hu, hv,
+                           [&](double k, double th2, const double* kr, int tg2) {
+                               kk[nk][0] = k;
+                               kk[nk][1] = th2;
+                               kk[nk][2] = kr[0];
+                               kk[nk][3] = kr[1];
+                               kk[nk][4] = kr[2];
+                               kk[nk][5] = kr[3];
+                               ktag[nk] = tg2;
+                               ++nk;
+                               return true;
+                           });
+                    ct = ht;
+                    cu = hu;
+                    cv = hv;
+                }
+            }
+            pops += m;
+            // the batch's result: the midpoint form takes its first answer in
+            // key order, the accelerated form the smallest tau (lowest lane
+            // on ties)
+            bool stop = false;
+            if (o.newton_iters == 0) {
+                const unsigned long long am = __ballot(is_answer);
+                if (am) {
+                    const int w = __ffsll((long long)am) - 1;
+                    best = __shfl(ct, w);
+                    bu = __shfl(cu, w);
+                    bv = __shfl(cv, w);
+                    bp = __shfl(cpatch, w);
+                    stop = true;
+                }
+            } else {
+                double t = ct;
+                int wl = lane;
+                for (int off = 32; off > 0; off >>= 1) {
+                    const double t2 = __shfl_xor(t, off);
+                    const int w2 = __shfl_xor(wl, off);
+                    if (t2 < t || (t2 == t && w2 < wl)) {
+                        t = t2;
+                        wl = w2;
+                    }
+                }
+                const double su = __shfl(cu, wl), sv = __shfl(cv, wl);
+                const int sp = __shfl(cpatch, wl);
+                if (t < best) {
+                    best = t;
+                    bu = su;
+                    bv = sv;
+                    bp = sp;
+                }
+            }
+            if (stop) break;
+            // free slots: the m examined, then those past the live ones
+            __syncthreads();
+            for (int e = lane; e < n2; e += 64)
+                if ((e < m || e >= live) && e < hi) key[sidx[e]] = INFINITY;
+            __syncthreads();
+            // file the children round by round (lane order within a round)
+            int filed = 0;
+            const int nfree_tail = max(hi - live, 0);
+            int new_hi = hi;
+            for (int k = 0; k < 4; ++k) {
+                const unsigned long long bm = __ballot(nk > k);
+                if (!bm) break;
+                if (nk > k) {
+                    const int j = filed + __popcll(bm & ((1ull << lane) - 1));
+                    int slot;
+                    if (j < m) slot = sidx[j];
+                    else if (j - m < nfree_tail) slot = sidx[live + (j - m)];
+                    else slot = hi + (j - m - nfree_tail);
+                    if (slot < TAIL_POOL) {
+                        key[slot] = kk[k][0];
+                        thi[slot] = kk[k][1];
+                        rect[slot][0] = kk[k][2];
+                        rect[slot][1] = kk[k][3];
+                        rect[slot][2] = kk[k][4];
+                        rect[slot][3] = kk[k][5];
+                        tag[slot] = ktag[k];
+                    }
+                }
+                filed += __popcll(bm);
+            }
+            if (filed - m > nfree_tail) new_hi = hi + (filed - m - nfree_tail);
+            if (new_hi > TAIL_POOL) {
+                over = true;
+                break;
+            }
+            hi = new_hi;
+            __syncthreads();
+        }
+        __syncthreads();
+        if (lane == 0)
+            write_result(hit, patch_out, pops_out, lr.rid, over ? INFINITY : (bp >= 0 ? best : INFINITY), bu, bv,
+                         over ? -2 : bp, pops);
+    }
+}
+
+// zero the hand-over counter (a kernel, not a memset: safe in graphs)
+__global__ void k_zero_int(int* p) { *p = 0; }
 
 void launch_ray_cast(hipStream_t st, const double* ctrl, int npatch, const double* rays, long long nrays,
                      const RayParams& o, double* hit, int* patch, int* pops) {
     if (nrays <= 0) return;
     const int chunk = 256 * RAY_CHUNK_PER_LANE;
     const unsigned nb = (unsigned)((nrays + chunk - 1) / chunk);
+    RayTail tail{};
+    tail.cap = (int)std::min<long long>(nrays, RAY_TAIL_SLOTS);
+    void* buf = nullptr;
+    const size_t per = sizeof(LongRay) + RAY_HEAP_MAX * (3 * sizeof(double) + 4 * sizeof(double) + sizeof(int));
+    if (hipMallocAsync(&buf, 256 + per * tail.cap, st) == hipSuccess) {
+        char* b = (char*)buf;
+        tail.count = (int*)b;
+        tail.rays = (LongRay*)(b + 256);
+        tail.key = (double*)(tail.rays + tail.cap);
+        tail.thi = tail.key + (size_t)tail.cap * RAY_HEAP_MAX;
+        tail.rect = tail.thi + (size_t)tail.cap * RAY_HEAP_MAX;
+        tail.tag = (int*)(tail.rect + (size_t)tail.cap * RAY_HEAP_MAX * 4);
+        tail.budget = RAY_TAIL_BUDGET;
+        hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, tail.count);
+    } else {
+        (void)hipGetLastError();
+        buf = nullptr;
+        tail.cap = 0;
+        tail.budget = -1;  // never reached: every ray stays on its lane
+    }
     if (npatch <= RAY_LDS_PATCHES) {
         const size_t lds = sizeof(double) * 54 * (size_t)npatch;
-        hipLaunchKernelGGL(k_ray_cast<true>, dim3(nb), dim3(256), lds, st, ctrl, npatch, rays, nrays, chunk, o, hit,
-                           patch, pops);
+        hipLaunchKernelGGL(k_ray_cast<true>, dim3(nb), dim3(256), lds, st, ctrl, npatch, rays, nrays, chunk, o, tail,
+                           hit, patch, pops);
     } else {
-        hipLaunchKernelGGL(k_ray_cast<false>, dim3(nb), dim3(256), 0, st, ctrl, npatch, rays, nrays, chunk, o, hit,
-                           patch, pops);
+        hipLaunchKernelGGL(k_ray_cast<false>, dim3(nb), dim3(256), 0, st, ctrl, npatch, rays, nrays, chunk, o, tail,
+                           hit, patch, pops);
+    }
+    if (buf) {
+        hipLaunchKernelGGL(k_ray_tail, dim3((unsigned)std::min(tail.cap, 2048)), dim3(64), 0, st, ctrl, rays, o,
+                           tail, hit, patch, pops);
+        (void)hipFreeAsync(buf, st);
     }
 }
 

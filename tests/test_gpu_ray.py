@@ -130,12 +130,18 @@ def test_full_frame_sampled(newton):
     ctrl_o = _oracle_ctrl(case, case.ref)
     ctrl_g = _gpu_ctrl([case], [case.ref])
     rays = W.camera_rays("cylinder", 512, 512, 16)
-    hg, pg, _ = _cast(ctrl_g, rays, newton_iters=newton)
+    hg, pg, pops = _cast(ctrl_g, rays, newton_iters=newton)
     assert (pg >= -1).all()
     assert 0.3 < (pg >= 0).mean() < 0.9
     idx = np.random.default_rng(33).choice(len(rays), 1500, replace=False)
     ho, po = R.ray_cast(ctrl_o, rays[idx], eps=EPS, newton_iters=newton)
     _compare(ctrl_o, rays[idx], hg[idx], pg[idx], ho, po)
+    # rays past 512 candidates, finished by the cooperative search
+    long_ = np.nonzero(pops > 512)[0]
+    assert 0 < len(long_) < 2000
+    pick = long_[np.argsort(-pops[long_])[:48]]
+    ho, po = R.ray_cast(ctrl_o, rays[pick], eps=EPS, newton_iters=newton)
+    _compare(ctrl_o, rays[pick], hg[pick], pg[pick], ho, po)
     hg2, pg2, _ = _cast(ctrl_g, rays, newton_iters=newton)
     assert np.array_equal(hg2, hg) and np.array_equal(pg2, pg)       # run to run
 
