@@ -88,6 +88,8 @@ def _load(path=_LIB_PATH):
     lib.orc_ray_cast.restype = C.c_int
     lib.orc_ray_cast_many.argtypes = [d, C.c_int, d, C.c_int64, C.c_double, C.c_int, C.c_double, C.c_double,
                                       C.c_int, d, C.POINTER(C.c_int), i64]
+    lib.orc_ccd_many.argtypes = [d, d, C.c_int, d, C.c_int64, C.c_double, C.c_double, C.c_int, C.c_double,
+                                 C.c_double, C.c_int, d, C.POINTER(C.c_int), i64]
     return lib
 
 

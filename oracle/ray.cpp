@@ -198,6 +198,129 @@ bool newton(const Surf& patch, const double x0[3], const double d[3], int iters,
     }
 }
 
+// ---- Dynamic ray--patch intersection (Sec. 5.2) ----
+// Control points move linearly over the step: p_ij + t v_ij, t in [0, dt];
+// the point moves as x0 + t w.
+
+struct Iv {
+    double lo, hi;
+};
+
+// Intersection of two unions of closed intervals.
+std::vector<Iv> meet(const std::vector<Iv>& a, const std::vector<Iv>& b) {
+    std::vector<Iv> out;
+    for (const Iv& x : a)
+        for (const Iv& y : b) {
+            const double lo = std::max(x.lo, y.lo), hi = std::min(x.hi, y.hi);
+            if (lo <= hi) out.push_back({lo, hi});
+        }
+    std::sort(out.begin(), out.end(), [](const Iv& x, const Iv& y) { return x.lo < y.lo; });
+    return out;
+}
+
+// Eq. ineqccd: the times t in [0, dt] at which the point lies in the
+// axis-aligned box of the moving control points.  Per axis, with
+// a_ij(t) = (p_ij - x0) + t (v_ij - w) along that axis, the lower bound holds
+// where some a_ij(t) <= 0 (a union of half-lines: a prefix [0, L] and a
+// suffix [R, dt]) and the upper bound where some a_ij(t) >= 0 (likewise);
+// the answer is the intersection over both bounds and the three axes.
+std::vector<Iv> feasible_times(const Surf& p, const Surf& v, const double x0[3], const double w[3], double dt) {
+    std::vector<Iv> cur = {{0.0, dt}};
+    for (int c = 0; c < 3 && !cur.empty(); ++c) {
+        for (int side = 0; side < 2; ++side) {  // 0: some a <= 0, 1: some a >= 0
+            double L = -1.0, R = 2.0 * dt + 1.0;  // prefix end, suffix start (empty by default)
+            bool all = false;
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) {
+                    double a = p.p[i][j].x[c] - x0[c], b = v.p[i][j].x[c] - w[c];
+                    if (side == 1) {
+                        a = -a;
+                        b = -b;
+                    }
+                    // a + t b <= 0
+                    if (b > 0.0) L = std::max(L, -a / b);
+                    else if (b < 0.0) R = std::min(R, -a / b);
+                    else if (a <= 0.0) all = true;
+                }
+            std::vector<Iv> s;
+            if (all) {
+                s.push_back({0.0, dt});
+            } else {
+                if (L >= 0.0) s.push_back({0.0, std::min(L, dt)});
+                if (R <= dt) s.push_back({std::max(R, 0.0), dt});
+            }
+            cur = meet(cur, s);
+            if (cur.empty()) break;
+        }
+    }
+    return cur;
+}
+
+double box_diag_at(const Surf& p, const Surf& v, double t) {
+    double d2 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        double lo = INFINITY, hi = -INFINITY;
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) {
+                const double x = p.p[i][j].x[c] + t * v.p[i][j].x[c];
+                lo = std::min(lo, x);
+                hi = std::max(hi, x);
+            }
+        d2 += (hi - lo) * (hi - lo);
+    }
+    return std::sqrt(d2);
+}
+
+struct MCand {
+    double tlo;
+    double u0, u1, v0, v1;
+    int patch, depth;
+    int64_t seq;
+    Surf p, v;
+};
+struct MLater {
+    bool operator()(const MCand& a, const MCand& b) const {
+        return a.tlo != b.tlo ? a.tlo > b.tlo : a.seq > b.seq;
+    }
+};
+
+// Newton's method on F(u, v, t) = x(u, v, t) - x0 - t w over the whole
+// patch from (u, v, t); J = [x_u(t) | x_v(t) | x_t(u, v) - w], Cramer's rule.
+bool newton_ccd(const Surf& P, const Surf& V, const double x0[3], const double w[3], int iters, double tol,
+                double& u, double& v, double& t) {
+    for (int it = 0;; ++it) {
+        double xp[3], xpu[3], xpv[3], xv[3], xvu[3], xvv[3];
+        surf_eval(P, u, v, xp, xpu, xpv);
+        surf_eval(V, u, v, xv, xvu, xvv);
+        double F[3], J[3][3];
+        for (int c = 0; c < 3; ++c) {
+            F[c] = xp[c] + t * xv[c] - x0[c] - t * w[c];
+            J[c][0] = xpu[c] + t * xvu[c];
+            J[c][1] = xpv[c] + t * xvv[c];
+            J[c][2] = xv[c] - w[c];
+        }
+        if (std::sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]) <= tol) return std::isfinite(u + v + t);
+        if (it == iters) return false;
+        auto det3 = [](const double M[3][3]) {
+            return M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+                   M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+        };
+        const double det = det3(J);
+        if (det == 0.0 || !std::isfinite(det)) return false;
+        double delta[3];
+        for (int k = 0; k < 3; ++k) {
+            double Mk[3][3];
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) Mk[r][c] = c == k ? -F[r] : J[r][c];
+            delta[k] = det3(Mk) / det;
+        }
+        u += delta[0];
+        v += delta[1];
+        t += delta[2];
+        if (!std::isfinite(u + v + t)) return false;
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -360,6 +483,114 @@ void orc_ray_cast_many(const double* ctrl, int P, const double* rays, int64_t n,
     for (int64_t r = 0; r < n; ++r)
         patch[r] = orc_ray_cast(ctrl, P, rays + 6 * r, eps, newton_iters, newton_tol, hole, max_depth,
                                 out + 3 * r, stats ? stats + 2 * r : nullptr);
+}
+
+// Dynamic ray--patch intersection (Sec. 5.2) of one moving point with P
+// moving patches over [0, dt].  ctrl, vel: [P][48] control points and their
+// velocities; pt: x0[3], w[3].  Same search as orc_ray_cast with keys = the
+// earliest time of Eq. ineqccd; a candidate is an answer when its box at
+// that time has a diagonal <= eps (a length), the answer being that time and
+// the rectangle's centre.  Newton starts at the candidate's centre and key
+// time.  out = t, u, v; returns the patch or -1.
+int orc_ccd(const double* ctrl, const double* vel, int P, const double* pt, double dt, double eps, int newton_iters,
+            double newton_tol, double hole, int max_depth, double* out, int64_t* stats) {
+    const double* x0 = pt;
+    const double* w = pt + 3;
+    std::priority_queue<MCand, std::vector<MCand>, MLater> heap;
+    int64_t seq = 0, pops = 0, peak = 0;
+    double best = std::numeric_limits<double>::infinity(), bu = 0.0, bv = 0.0;
+    int bp = -1;
+    std::vector<Surf> rp(P), rv(P);
+    auto offer = [&](const Surf& sp, const Surf& sv, double u0, double u1, double v0, double v1, int patch,
+                     int depth) {
+        const std::vector<Iv> T = feasible_times(sp, sv, x0, w, dt);
+        if (T.empty() || !(T.front().lo < best)) return;
+        MCand c;
+        c.tlo = T.front().lo;
+        c.u0 = u0;
+        c.u1 = u1;
+        c.v0 = v0;
+        c.v1 = v1;
+        c.patch = patch;
+        c.depth = depth;
+        c.seq = seq++;
+        c.p = sp;
+        c.v = sv;
+        heap.push(c);
+        peak = std::max<int64_t>(peak, (int64_t)heap.size());
+    };
+    for (int q = 0; q < P; ++q) {
+        std::memcpy(rp[q].p, ctrl + 48 * q, sizeof rp[q].p);
+        std::memcpy(rv[q].p, vel + 48 * q, sizeof rv[q].p);
+        offer(rp[q], rv[q], 0.0, 1.0, 0.0, 1.0, q, 0);
+    }
+    while (!heap.empty()) {
+        const MCand c = heap.top();
+        heap.pop();
+        ++pops;
+        if (!(c.tlo < best)) break;
+        if (box_diag_at(c.p, c.v, c.tlo) <= eps || c.depth >= max_depth) {
+            if (c.tlo < best) {
+                best = c.tlo;
+                bu = 0.5 * (c.u0 + c.u1);
+                bv = 0.5 * (c.v0 + c.v1);
+                bp = c.patch;
+            }
+            if (newton_iters == 0) break;
+            continue;
+        }
+        double cu = 0.5 * (c.u0 + c.u1), cv = 0.5 * (c.v0 + c.v1);
+        bool hit = false;
+        if (newton_iters > 0) {
+            double u = cu, v = cv, t = c.tlo;
+            if (newton_ccd(rp[c.patch], rv[c.patch], x0, w, newton_iters, newton_tol, u, v, t) && u >= c.u0 &&
+                u <= c.u1 && v >= c.v0 && v <= c.v1 && t >= 0.0 && t <= dt) {
+                hit = true;
+                if (t < best) {
+                    best = t;
+                    bu = u;
+                    bv = v;
+                    bp = c.patch;
+                }
+                cu = u;
+                cv = v;
+            }
+        }
+        double ua = cu, ub = cu, va = cv, vb = cv;
+        if (hit) {
+            const double hu = hole * (c.u1 - c.u0), hv = hole * (c.v1 - c.v0);
+            ua = std::max(c.u0, cu - hu);
+            ub = std::min(c.u1, cu + hu);
+            va = std::max(c.v0, cv - hv);
+            vb = std::min(c.v1, cv + hv);
+        }
+        const double rect[4][4] = {{c.u0, ua, va, c.v1}, {ua, c.u1, vb, c.v1}, {c.u0, ub, c.v0, va}, {ub, c.u1, c.v0, vb}};
+        const double wu = c.u1 - c.u0, wv = c.v1 - c.v0;
+        for (const auto& r : rect) {
+            if (!(r[1] > r[0]) || !(r[3] > r[2])) continue;
+            const double a0 = (r[0] - c.u0) / wu, a1 = (r[1] - c.u0) / wu, b0 = (r[2] - c.v0) / wv, b1 = (r[3] - c.v0) / wv;
+            const Surf sp = restrict_dir(restrict_dir(c.p, 0, a0, a1), 1, b0, b1);
+            const Surf sv = restrict_dir(restrict_dir(c.v, 0, a0, a1), 1, b0, b1);
+            offer(sp, sv, r[0], r[1], r[2], r[3], c.patch, c.depth + 1);
+        }
+    }
+    out[0] = bp >= 0 ? best : std::numeric_limits<double>::infinity();
+    out[1] = bu;
+    out[2] = bv;
+    if (stats) {
+        stats[0] = pops;
+        stats[1] = peak;
+    }
+    return bp;
+}
+
+void orc_ccd_many(const double* ctrl, const double* vel, int P, const double* pts, int64_t n, double dt, double eps,
+                  int newton_iters, double newton_tol, double hole, int max_depth, double* out, int* patch,
+                  int64_t* stats) {
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t r = 0; r < n; ++r)
+        patch[r] = orc_ccd(ctrl, vel, P, pts + 6 * r, dt, eps, newton_iters, newton_tol, hole, max_depth, out + 3 * r,
+                           stats ? stats + 2 * r : nullptr);
 }
 
 }  // extern "C"

@@ -9,7 +9,9 @@ it.  Thin numpy wrappers over ``oracle/ray.cpp``:
 * ``bezier_eval``: x, x_u, x_v of a Bezier surface;
 * ``ray_cast``: the static ray--patch intersection of Sec. 5.1 (AABB tests
   of Eq. ineqray, min-heap of candidate surfaces, De Casteljau splits,
-  optional Newton acceleration with the split of Fig. subany).
+  optional Newton acceleration with the split of Fig. subany);
+* ``ccd``: the dynamic intersection of Sec. 5.2 (a moving point against
+  moving patches over one step, boxes by Eq. ineqccd).
 
 Control points are ``[patches, 4, 4, 3]`` float64, ``p[i, j]`` with ``i``
 along xi1 (local parameter u) and ``j`` along xi2 (v); rays are ``[n, 6]``
@@ -69,4 +71,23 @@ def ray_cast(ctrl, rays, eps=1e-10, newton_iters=0, newton_tol=1e-12, hole=1e-3,
     O.lib().orc_ray_cast_many(O._d(c), c.shape[0], O._d(r), n, float(eps), int(newton_iters), float(newton_tol),
                               float(hole), int(max_depth), O._d(hit), patch.ctypes.data_as(C.POINTER(C.c_int)),
                               st.ctypes.data_as(_i64))
+    return (hit, patch, st) if stats else (hit, patch)
+
+
+def ccd(ctrl, vel, points, dt, eps=1e-10, newton_iters=0, newton_tol=1e-12, hole=1e-3, max_depth=60, stats=False):
+    """Earliest contact over [0, dt] of each moving point (points [n, 6]:
+    x0, velocity) with the moving patches (ctrl, vel [P, 4, 4, 3]: control
+    points and their velocities), Sec. 5.2.  Returns (hit [n, 3] = t, u, v,
+    t = inf when there is none, patch [n] int32, -1 none) and, with
+    ``stats``, [n, 2] int64 = candidates examined and the largest heap."""
+    c = O._f64(np.asarray(ctrl).reshape(-1, 48))
+    v = O._f64(np.asarray(vel).reshape(-1, 48))
+    pts = O._f64(np.asarray(points).reshape(-1, 6))
+    n = pts.shape[0]
+    hit = np.empty((n, 3))
+    patch = np.empty(n, dtype=np.int32)
+    st = np.empty((n, 2), dtype=np.int64)
+    O.lib().orc_ccd_many(O._d(c), O._d(v), c.shape[0], O._d(pts), n, float(dt), float(eps), int(newton_iters),
+                         float(newton_tol), float(hole), int(max_depth), O._d(hit),
+                         patch.ctypes.data_as(C.POINTER(C.c_int)), st.ctypes.data_as(_i64))
     return (hit, patch, st) if stats else (hit, patch)

@@ -71,6 +71,10 @@ MUTANTS = [
     ("Newton: Jacobian column of tau with the wrong sign", "ray.cpp",
      "{xu[0], xv[0], -d[0]}, {xu[1], xv[1], -d[1]}, {xu[2], xv[2], -d[2]}",
      "{xu[0], xv[0], d[0]}, {xu[1], xv[1], d[1]}, {xu[2], xv[2], d[2]}"),
+    ("moving box: prefix bound taken as the smallest", "ray.cpp",
+     "if (b > 0.0) L = std::max(L, -a / b);", "if (b > 0.0) L = std::min(L, -a / b);"),
+    ("moving Newton: time column without the point's velocity", "ray.cpp",
+     "J[c][2] = xv[c] - w[c];", "J[c][2] = xv[c];"),
     ("heap ordered by the far end of the box interval", "ray.cpp",
      "return a.tlo != b.tlo ? a.tlo > b.tlo : a.seq > b.seq;", "return a.thi != b.thi ? a.thi > b.thi : a.seq > b.seq;"),
 ]
@@ -94,6 +98,9 @@ def _pins():
              (TR.test_hits_on_the_saddle_match_the_closed_form, TR.test_misses,
               TR.test_closest_surface_wins_in_any_patch_order)]
     pins += [lambda s=s: TR.test_midpoint_and_newton_forms_agree_and_hits_lie_on_rays(s) for s in W.RENDER_SCENES]
+    pins += [lambda n=n, f=f: f(n) for n in (0, 8) for f in
+             (TR.test_ccd_translating_saddle_matches_the_closed_form, TR.test_ccd_of_resting_patches_is_the_static_ray_cast)]
+    pins += [TR.test_ccd_misses_and_the_step_end]
     rows = TB._golden("dof_counts.txt")
     pins += [lambda r=r: TB.test_printed_dof_and_nonzero_counts(r) for r in rows]
     return pins

@@ -174,3 +174,70 @@ def test_midpoint_and_newton_forms_agree_and_hits_lie_on_rays(scene):
     # the Newton form examines far fewer candidates (Table 1 of the paper)
     assert s1[:, 0].sum() * 2 < s0[:, 0].sum()
     assert max(s0[:, 1].max(), s1[:, 1].max()) <= HEAP_MAX // 2
+
+
+# ---------------------------------------------------------------- Sec. 5.2
+DT = 0.5
+
+
+def _moving_points(rng, n, speed=2.0):
+    """Points above the saddle moving towards a point on it, with speed
+    U[0.5, 1.5] x `speed` (some reach it within DT, some not)."""
+    rays = _random_rays(rng, n, above=0.6)
+    v = rays[:, 3:] * rng.uniform(0.5, 1.5, (n, 1)) * speed
+    return np.hstack([rays[:, :3], v])
+
+
+@pytest.mark.parametrize("newton", [0, 8])
+def test_ccd_translating_saddle_matches_the_closed_form(newton):
+    """Every control point moving with velocity V: the contact time of a
+    point moving with w is the static hit of the ray with direction w - V."""
+    ctrl = _saddle_ctrl()
+    rng = np.random.default_rng(16)
+    V = np.array([0.1, -0.05, -0.3])
+    vel = np.broadcast_to(V, ctrl.shape).copy()
+    pts = _moving_points(rng, 150)
+    hit, patch = R.ccd(ctrl, vel, pts, DT, eps=EPS, newton_iters=newton)
+    n_hit = 0
+    for r in range(len(pts)):
+        d = pts[r, 3:] - V
+        t = _saddle_tau(pts[r, :3], d)
+        if t > DT:
+            assert patch[r] == -1 and math.isinf(hit[r, 0]), (r, t, hit[r])
+            continue
+        n_hit += 1
+        assert patch[r] == 0
+        s = _sin_incidence(ctrl, 0, hit[r, 1], hit[r, 2], d)
+        tol = 1e-11 if newton else 2 * EPS / (np.linalg.norm(d) * max(s, 1e-3)) + 1e-12
+        assert abs(hit[r, 0] - t) <= tol, (r, hit[r], t)
+    assert 30 < n_hit < 140
+
+
+@pytest.mark.parametrize("newton", [0, 8])
+def test_ccd_of_resting_patches_is_the_static_ray_cast(newton):
+    ctrl = _scene("drape")
+    pts = W.camera_rays("drape", 24, 24, 1)
+    pts[:, 3:] *= 3.0                              # |w| = 3: reaches tau <= 1.5
+    hit, patch = R.ccd(ctrl, np.zeros_like(ctrl), pts, DT, eps=EPS, newton_iters=newton)
+    h2, p2 = R.ray_cast(ctrl, pts, eps=EPS, newton_iters=newton)
+    reach = (p2 >= 0) & (h2[:, 0] <= DT)
+    assert reach.sum() > 50 and ((p2 >= 0) & ~reach).sum() > 50
+    assert ((patch >= 0) == reach).all()
+    for r in np.nonzero(reach)[0]:
+        s = _sin_incidence(ctrl, p2[r], h2[r, 1], h2[r, 2], pts[r, 3:])
+        assert abs(hit[r, 0] - h2[r, 0]) <= (1e-11 if newton else 4 * EPS / max(s, 1e-3) / 3.0 + 1e-12)
+
+
+def test_ccd_misses_and_the_step_end():
+    ctrl = _saddle_ctrl()
+    V = np.array([0.0, 0.0, -0.5])
+    vel = np.broadcast_to(V, ctrl.shape).copy()
+    z = 0.25 * 0.4 * 0.6 - 0.15 * 0.16 + 0.1 * 0.36
+    pts = np.array([[0.4, 0.6, 0.3, 0, 0, 0.0],          # the surface falls away from a resting point
+                    [0.4, 0.6, z - 0.1, 0, 0, 0.0],      # ... and reaches one below it at t = 0.2
+                    [0.4, 0.6, z - 0.1, 0, 0, -0.6],     # falling faster than the surface: never
+                    [0.4, 0.6, z + 0.3, 0, 0, -0.2]])    # meets at t = 1.0 > DT
+    for newton in (0, 8):
+        hit, patch = R.ccd(ctrl, vel, pts, DT, eps=EPS, newton_iters=newton)
+        assert list(patch) == [-1, 0, -1, -1]
+        assert abs(hit[1, 0] - 0.2) <= 1e-9
