@@ -365,9 +365,12 @@ void shell_ray_default_opts(shell_ray_opts *o);
  *   hit_dev   [n_rays][3] float64 out: tau, u, v of the closest hit in the
  *             patch's own parameters; tau = +inf when there is none.
  *   patch_dev [n_rays] int32 out: the hit's patch, -1 for a miss, -2 when
- *             the ray's candidates outgrew heap_cap or it examined 2^18
- *             of them (no result: raise heap_cap or eps), -3 for an invalid
- *             ray (zero or non-finite direction, non-finite origin).
+ *             there is no result: more root candidates than heap_cap, or
+ *             the cooperative search (which takes over a ray after 512
+ *             candidates or when its heap of heap_cap nears full, with room
+ *             for 1,024 candidates and 16,384 rays per call) ran out of room,
+ *             or 2^18 candidates examined; -3 for an invalid ray (zero or
+ *             non-finite direction, non-finite origin).
  *   pops_dev  [n_rays] int32 out, or NULL: candidates the ray examined.
  * Device pointers valid on opts->stream; the caller owns them.  Enqueued on
  * that stream; no synchronisation.  Cost per ray is linear in n_patches
@@ -376,6 +379,27 @@ void shell_ray_default_opts(shell_ray_opts *o);
  * failed launch SHELL_E_DEVICE; shell_last_error(NULL) describes both. */
 shell_status shell_ray_cast(const double *ctrl_dev, int32_t n_patches, const double *rays_dev, int64_t n_rays,
                             const shell_ray_opts *opts, double *hit_dev, int32_t *patch_dev, int32_t *pops_dev);
+
+/* Dynamic ray--patch intersection (Sec. 5.2): for each point moving as
+ * x0 + t w over one step t in [0, dt], the earliest t at which it meets one
+ * of the patches whose control points move as p + t v (Eq. ineqccd bounds
+ * the times at which the point can be inside a candidate's box), by the
+ * same subdivision search as shell_ray_cast with keys = earliest feasible
+ * times.  Control-point velocities are shell_bezier of the nodal velocities
+ * (the Bezier form is linear in the nodal values).
+ *   ctrl_dev, vel_dev [n_patches][4][4][3]: control points at t = 0 and
+ *             their velocities.
+ *   points_dev [n_points][6]: x0 xyz, w xyz.
+ *   hit_dev   [n_points][3] out: t, u, v of the first contact; t = +inf
+ *             when there is none within the step.
+ *   patch_dev, pops_dev: as for shell_ray_cast (-3: non-finite point).
+ *   opts: as for shell_ray_cast, except that eps is a length: a candidate
+ *         whose box at its earliest time has a diagonal <= eps is an answer
+ *         (its earliest time and rectangle centre).
+ * Same ownership, stream and error rules as shell_ray_cast; dt > 0. */
+shell_status shell_ccd(const double *ctrl_dev, const double *vel_dev, int32_t n_patches, const double *points_dev,
+                       int64_t n_points, double dt, const shell_ray_opts *opts, double *hit_dev, int32_t *patch_dev,
+                       int32_t *pops_dev);
 
 #ifdef __cplusplus
 }

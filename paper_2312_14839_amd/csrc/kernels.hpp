@@ -52,6 +52,10 @@ struct RayParams {
 // pops: [n] surfaces popped, may be null.
 void launch_ray_cast(hipStream_t st, const double* ctrl, int npatch, const double* rays, long long nrays,
                      const RayParams& o, double* hit, int* patch, int* pops);
+// Moving point x0 + t w (pts: [n][6]) against patches with control points
+// ctrl + t vel over [0, dt]; hit: [n][3] t, u, v; statuses as above.
+void launch_ccd(hipStream_t st, const double* ctrl, const double* vel, int npatch, const double* pts,
+                long long npts, double dt, const RayParams& o, double* hit, int* patch, int* pops);
 
 // ------------------------------------------------------ solver kernels
 // Row partition of the node rows into blocks that never straddle a shell;

@@ -485,8 +485,10 @@ __global__ void __launch_bounds__(256) k_ray_cast(const double* __restrict__ ctr
             active = true;
             continue;
         }
-        // one candidate (the heap is not empty)
-        if (pops == budget) {
+        // one candidate (the heap is not empty); a ray that has used its
+        // budget or whose heap may not take the next four children goes to
+        // the cooperative search
+        if (pops == budget || (budget > 0 && hp.n > o.heap_cap - 4)) {
             const int s = atomicAdd(tail.count, 1);
             if (s < tail.cap) {
                 LongRay lr;
@@ -560,6 +562,317 @@ __global__ void __launch_bounds__(256) k_ray_cast(const double* __restrict__ ctr
     }
 }
 
+// ------------------------------------------------- dynamic intersection
+// Sec. 5.2: control points p_ij + t v_ij and the point x0 + t w over
+// [0, dt].  Per axis and per bound of Eq. ineqccd the feasible times are a
+// prefix [0, L] and/or a suffix [R, dt] of the step (a union of half-lines
+// a_ij + t b_ij <= 0); TimeSet intersects such sets.
+struct TimeSet {
+    double lo[8], hi[8];
+    int n;
+};
+
+__device__ inline void meet_prefix_suffix(TimeSet& s, double L, double R, bool all, double dt) {
+    if (all) return;
+    TimeSet o;
+    o.n = 0;
+    const double pe = fmin(L, dt), ss = fmax(R, 0.0);
+    const bool hp = L >= 0.0, hs = R <= dt;
+    for (int k = 0; k < s.n; ++k) {
+        // pieces in sorted order: the prefix part comes first
+        if (hp) {
+            const double a = s.lo[k], b = fmin(s.hi[k], pe);
+            if (a <= b && o.n < 8) {
+                o.lo[o.n] = a;
+                o.hi[o.n] = b;
+                ++o.n;
+            }
+        }
+        if (hs) {
+            const double a = fmax(s.lo[k], ss), b = s.hi[k];
+            if (a <= b && o.n < 8) {
+                if (o.n > 0 && a <= o.hi[o.n - 1]) {
+                    o.hi[o.n - 1] = fmax(o.hi[o.n - 1], b);
+                } else {
+                    o.lo[o.n] = a;
+                    o.hi[o.n] = b;
+                    ++o.n;
+                }
+            }
+        }
+    }
+    s = o;
+}
+
+// Earliest feasible time of the candidate [u0,u1] x [v0,v1] of a moving
+// patch; false when there is none in [0, dt].
+__device__ bool earliest_time(const double* cp, const double* cv, double u0, double u1, double v0, double v1,
+                              const double x0[3], const double w[3], double dt, double& t0) {
+    TimeSet ts;
+    ts.n = 1;
+    ts.lo[0] = 0.0;
+    ts.hi[0] = dt;
+#pragma unroll 1
+    for (int c = 0; c < 3; ++c) {
+        double Lm = -1.0, Rm = 2.0 * dt + 1.0, Lp = -1.0, Rp = 2.0 * dt + 1.0;
+        bool am = false, ap = false;
+        double UP[4][4], UV[4][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            double qp[4], qv[4];
+            blossom4(cp[j * 3 + c], cp[(4 + j) * 3 + c], cp[(8 + j) * 3 + c], cp[(12 + j) * 3 + c], u0, u1, qp);
+            blossom4(cv[j * 3 + c], cv[(4 + j) * 3 + c], cv[(8 + j) * 3 + c], cv[(12 + j) * 3 + c], u0, u1, qv);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                UP[i][j] = qp[i];
+                UV[i][j] = qv[i];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            double qp[4], qv[4];
+            blossom4(UP[i][0], UP[i][1], UP[i][2], UP[i][3], v0, v1, qp);
+            blossom4(UV[i][0], UV[i][1], UV[i][2], UV[i][3], v0, v1, qv);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const double a = qp[k] - x0[c], b = qv[k] - w[c];
+                // some a + t b <= 0 (lower bound of the box)
+                if (b > 0.0) Lm = fmax(Lm, -a / b);
+                else if (b < 0.0) Rm = fmin(Rm, -a / b);
+                else if (a <= 0.0) am = true;
+                // some a + t b >= 0 (upper bound)
+                if (b < 0.0) Lp = fmax(Lp, -a / b);
+                else if (b > 0.0) Rp = fmin(Rp, -a / b);
+                else if (a >= 0.0) ap = true;
+            }
+        }
+        meet_prefix_suffix(ts, Lm, Rm, am, dt);
+        meet_prefix_suffix(ts, Lp, Rp, ap, dt);
+        if (ts.n == 0) return false;
+    }
+    t0 = ts.lo[0];
+    return true;
+}
+
+// Diagonal of the control-point box of the candidate at time t.
+__device__ double diag_at(const double* cp, const double* cv, double u0, double u1, double v0, double v1, double t) {
+    double d2 = 0.0;
+#pragma unroll 1
+    for (int c = 0; c < 3; ++c) {
+        double U[4][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            double qq[4];
+            blossom4(fma(t, cv[j * 3 + c], cp[j * 3 + c]), fma(t, cv[(4 + j) * 3 + c], cp[(4 + j) * 3 + c]),
+                     fma(t, cv[(8 + j) * 3 + c], cp[(8 + j) * 3 + c]), fma(t, cv[(12 + j) * 3 + c], cp[(12 + j) * 3 + c]),
+                     u0, u1, qq);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) U[i][j] = qq[i];
+        }
+        double l = INFINITY, h = -INFINITY;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            double qq[4];
+            blossom4(U[i][0], U[i][1], U[i][2], U[i][3], v0, v1, qq);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                l = fmin(l, qq[k]);
+                h = fmax(h, qq[k]);
+            }
+        }
+        d2 = fma(h - l, h - l, d2);
+    }
+    return sqrt(d2);
+}
+
+// Newton's method on x(u,v) + t xdot(u,v) - x0 - t w = 0 from (u, v, t).
+__device__ bool newton_ccd(const double* cp, const double* cv, const double x0[3], const double w[3], int iters,
+                           double tol, double& u, double& v, double& t) {
+    const double tol2 = tol * tol;
+    for (int it = 0;; ++it) {
+        double x[3], xu[3], xv[3], y[3], yu[3], yv[3];
+        surf_eval(cp, u, v, x, xu, xv);
+        surf_eval(cv, u, v, y, yu, yv);
+        double F[3], a[3], b[3], c3[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            F[c] = fma(t, y[c] - w[c], x[c] - x0[c]);
+            a[c] = fma(t, yu[c], xu[c]);
+            b[c] = fma(t, yv[c], xv[c]);
+            c3[c] = y[c] - w[c];
+        }
+        if (dot3(F, F) <= tol2) return isfinite(u + v + t);
+        if (it == iters) return false;
+        const double rhs[3] = {-F[0], -F[1], -F[2]};
+        double bc[3], rc[3], br[3];
+        cross3(b, c3, bc);
+        const double det = dot3(a, bc);
+        if (det == 0.0 || !isfinite(det)) return false;
+        cross3(rhs, c3, rc);
+        cross3(b, rhs, br);
+        const double inv = 1.0 / det;
+        u += dot3(rhs, bc) * inv;
+        v += dot3(a, rc) * inv;
+        t += dot3(a, br) * inv;
+        if (!isfinite(u + v + t)) return false;
+    }
+}
+
+// Newton's method (accelerated form) and the four sub-rectangles of a
+// candidate of a moving patch, keyed by their earliest feasible times;
+// emit and the Newton hit as in expand().
+template <class Emit>
+__device__ inline void expand_ccd(const double* cp, const double* cv, const double x0[3], const double w[3], double dt,
+                                  const RayParams& o, double best, double t_key, const double rc[4], int patch,
+                                  int depth, double& ht, double& hu, double& hv, Emit&& emit) {
+    double cu = 0.5 * (rc[0] + rc[1]), cc = 0.5 * (rc[2] + rc[3]);
+    double ua = cu, ub = cu, va = cc, vb = cc;
+    ht = INFINITY;
+    if (o.newton_iters > 0) {
+        double u = cu, v = cc, t = t_key;
+        if (newton_ccd(cp, cv, x0, w, o.newton_iters, o.newton_tol, u, v, t) && u >= rc[0] && u <= rc[1] &&
+            v >= rc[2] && v <= rc[3] && t >= 0.0 && t <= dt) {
+            ht = t;
+            hu = u;
+            hv = v;
+            best = fmin(best, t);
+            const double hw = o.hole * (rc[1] - rc[0]), hh = o.hole * (rc[3] - rc[2]);
+            ua = fmax(rc[0], u - hw);
+            ub = fmin(rc[1], u + hw);
+            va = fmax(rc[2], v - hh);
+            vb = fmin(rc[3], v + hh);
+        }
+    }
+    const double kids[4][4] = {
+        {rc[0], ua, va, rc[3]}, {ua, rc[1], vb, rc[3]}, {rc[0], ub, rc[2], va}, {ub, rc[1], rc[2], vb}};
+#pragma unroll 1
+    for (int q = 0; q < 4; ++q) {
+        if (!(kids[q][1] > kids[q][0]) || !(kids[q][3] > kids[q][2])) continue;
+        double t0;
+        if (!earliest_time(cp, cv, kids[q][0], kids[q][1], kids[q][2], kids[q][3], x0, w, dt, t0) || !(t0 < best))
+            continue;
+        if (!emit(t0, 0.0, kids[q], patch | ((depth + 1) << 24))) break;
+    }
+}
+
+// One moving point per lane, handed out like the rays of k_ray_cast; the
+// same heap search with keys = earliest feasible times and answers = boxes
+// (at that time) with a diagonal <= eps; points past the budget, or whose
+// heap nears capacity, go to k_ray_tail<true>.
+__global__ void __launch_bounds__(256) k_ccd(const double* __restrict__ ctrl, const double* __restrict__ vel,
+                                             int npatch, const double* __restrict__ pts, long long npts, double dt,
+                                             int chunk, RayParams o, RayTail tail, double* __restrict__ hit,
+                                             int* __restrict__ patch_out, int* __restrict__ pops_out) {
+    __shared__ int s_next;
+    if (threadIdx.x == 0) s_next = 0;
+    __syncthreads();
+    const long long base = (long long)blockIdx.x * chunk;
+    const int cnt = (int)(npts - base < chunk ? npts - base : chunk);
+    Heap hp;
+    for (;;) {
+        const int k = atomicAdd(&s_next, 1);
+        if (k >= cnt) break;
+        const long long rid = base + k;
+        double x0[3], w[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            x0[c] = pts[6 * rid + c];
+            w[c] = pts[6 * rid + 3 + c];
+        }
+        if (!isfinite(x0[0] + x0[1] + x0[2] + w[0] + w[1] + w[2])) {
+            write_result(hit, patch_out, pops_out, rid, INFINITY, 0.0, 0.0, -3, 0);
+            continue;
+        }
+        hp.n = 0;
+        double best = INFINITY, bu = 0.0, bv = 0.0;
+        int bp = -1, pops = 0, budget = tail.budget;
+        bool full = false, handed = false;
+        const double unit[4] = {0.0, 1.0, 0.0, 1.0};
+        for (int p = 0; p < npatch && !full; ++p) {
+            double t0;
+            if (!earliest_time(ctrl + 48 * p, vel + 48 * p, 0.0, 1.0, 0.0, 1.0, x0, w, dt, t0)) continue;
+            if (hp.n == o.heap_cap) {
+                full = true;
+                break;
+            }
+            hp.push(t0, 0.0, unit, p);
+        }
+        while (hp.n > 0 && !full) {
+            if (pops == budget || (budget > 0 && hp.n > o.heap_cap - 4)) {
+                const int s = atomicAdd(tail.count, 1);
+                if (s < tail.cap) {
+                    LongRay lr;
+                    lr.best = best;
+                    lr.bu = bu;
+                    lr.bv = bv;
+                    lr.bp = bp;
+                    lr.pops = pops;
+                    lr.n = hp.n;
+                    lr.rid = rid;
+                    tail.rays[s] = lr;
+                    for (int e = 0; e < hp.n; ++e) {
+                        const long long q = (long long)s * RAY_HEAP_MAX + e;
+                        tail.key[q] = hp.key[e];
+                        tail.thi[q] = 0.0;
+                        tail.rect[4 * q] = hp.rect[e][0];
+                        tail.rect[4 * q + 1] = hp.rect[e][1];
+                        tail.rect[4 * q + 2] = hp.rect[e][2];
+                        tail.rect[4 * q + 3] = hp.rect[e][3];
+                        tail.tag[q] = hp.tag[e];
+                    }
+                    handed = true;
+                    break;
+                }
+                budget = 0;
+            }
+            if (pops == RAY_MAX_POPS) {
+                full = true;
+                break;
+            }
+            double tlo, unused, rc[4];
+            int tg;
+            hp.pop(tlo, unused, rc, tg);
+            ++pops;
+            if (!(tlo < best)) break;
+            const int patch = tg & 0xFFFFFF, depth = (tg >> 24) & 63;
+            const double* cp = ctrl + 48 * patch;
+            const double* cv = vel + 48 * patch;
+            if (depth >= o.max_depth || diag_at(cp, cv, rc[0], rc[1], rc[2], rc[3], tlo) <= o.eps) {
+                if (tlo < best) {
+                    best = tlo;
+                    bu = 0.5 * (rc[0] + rc[1]);
+                    bv = 0.5 * (rc[2] + rc[3]);
+                    bp = patch;
+                }
+                if (o.newton_iters == 0) break;
+                continue;
+            }
+            double ht, hu, hv;
+            expand_ccd(cp, cv, x0, w, dt, o, best, tlo, rc, patch, depth, ht, hu, hv,
+                       [&](double k2, double th, const double* kr, int tg2) {
+                           if (hp.n == o.heap_cap) {
+                               full = true;
+                               return false;
+                           }
+                           hp.push(k2, th, kr, tg2);
+                           return true;
+                       });
+            if (ht < best) {
+                best = ht;
+                bu = hu;
+                bv = hv;
+                bp = patch;
+            }
+        }
+        if (!handed)
+            write_result(hit, patch_out, pops_out, rid, full ? INFINITY : (bp >= 0 ? best : INFINITY), bu, bv,
+                         full ? -2 : bp, pops);
+    }
+}
+
+void launch_ccd(hipStream_t st, const double* ctrl, const double* vel, int npatch, const double* pts,
+                long long npts, double dt, const RayParams& o, double* hit, int* patch, int* pops);
+
 // The cooperative search of one handed-over ray per wave (block of 64).
 // The candidates live in an LDS pool; every step sorts their keys (bitonic
 // network over the pool's slots, free slots keyed +inf), takes the (up to)
@@ -569,9 +882,11 @@ __global__ void __launch_bounds__(256) k_ray_cast(const double* __restrict__ ctr
 // until no candidate is left before the best answer.
 constexpr int TAIL_POOL = 1024;
 
-__global__ void __launch_bounds__(64) k_ray_tail(const double* __restrict__ ctrl, const double* __restrict__ rays,
-                                                 RayParams o, RayTail tail, double* __restrict__ hit,
-                                                 int* __restrict__ patch_out, int* __restrict__ pops_out) {
+template <bool MOVING>
+__global__ void __launch_bounds__(64) k_ray_tail(const double* __restrict__ ctrl, const double* __restrict__ vel,
+                                                 const double* __restrict__ rays, double dt, RayParams o, RayTail tail,
+                                                 double* __restrict__ hit, int* __restrict__ patch_out,
+                                                 int* __restrict__ pops_out) {
     __shared__ double key[TAIL_POOL], thi[TAIL_POOL], rect[TAIL_POOL][4];
     __shared__ int tag[TAIL_POOL];
     __shared__ double skey[TAIL_POOL];
@@ -587,6 +902,8 @@ __global__ void __launch_bounds__(64) k_ray_tail(const double* __restrict__ ctrl
             r.d[c] = rays[6 * lr.rid + 3 + c];
         }
         const double small = o.eps * sqrt(dot3(r.d, r.d));
+        (void)dt;
+        (void)vel;
         double best = lr.best, bu = lr.bu, bv = lr.bv;
         int bp = lr.bp, pops = lr.pops, hi = lr.n;
         bool over = false;
@@ -661,15 +978,20 @@ __global__ void __launch_bounds__(64) k_ray_tail(const double* __restrict__ ctrl
                 const double rc[4] = {rect[e][0], rect[e][1], rect[e][2], rect[e][3]};
                 const int tg = tag[e];
                 cpatch = tg & 0xFFFFFF;
-                if (tg & (1 << 30)) {
+                bool ans;
+                if constexpr (MOVING)
+                    ans = ((tg >> 24) & 63) >= o.max_depth ||
+                          diag_at(ctrl + 48 * cpatch, vel + 48 * cpatch, rc[0], rc[1], rc[2], rc[3], tlo) <= o.eps;
+                else
+                    ans = (tg & (1 << 30)) != 0;
+                if (ans) {
                     is_answer = true;
-                    ct = 0.5 * (tlo + th);
+                    ct = MOVING ? tlo : 0.5 * (tlo + th);
                     cu = 0.5 * (rc[0] + rc[1]);
                     cv = 0.5 * (rc[2] + rc[3]);
                 } else {
                     double ht, hu = 0.0, hv = 0.0;
-                    expand(ctrl + 48 * cpatch, r, o, small, best, rc, cpatch, (tg >> 24) & 63, ht, hu, hv,
-                           [&](double k, double th2, const double* kr, int tg2) {
+                    auto emit = [&](double k, double th2, const double* kr, int tg2) {
                                kk[nk][0] = k;
                                kk[nk][1] = th2;
                                kk[nk][2] = kr[0];
@@ -679,7 +1001,12 @@ __global__ void __launch_bounds__(64) k_ray_tail(const double* __restrict__ ctrl
                                ktag[nk] = tg2;
                                ++nk;
                                return true;
-                           });
+                           };
+                    if constexpr (MOVING)
+                        expand_ccd(ctrl + 48 * cpatch, vel + 48 * cpatch, r.o, r.d, dt, o, best, tlo, rc, cpatch,
+                                   (tg >> 24) & 63, ht, hu, hv, emit);
+                    else
+                        expand(ctrl + 48 * cpatch, r, o, small, best, rc, cpatch, (tg >> 24) & 63, ht, hu, hv, emit);
                     ct = ht;
                     cu = hu;
                     cv = hv;
@@ -769,13 +1096,11 @@ __global__ void __launch_bounds__(64) k_ray_tail(const double* __restrict__ ctrl
 // zero the hand-over counter (a kernel, not a memset: safe in graphs)
 __global__ void k_zero_int(int* p) { *p = 0; }
 
-void launch_ray_cast(hipStream_t st, const double* ctrl, int npatch, const double* rays, long long nrays,
-                     const RayParams& o, double* hit, int* patch, int* pops) {
-    if (nrays <= 0) return;
-    const int chunk = 256 * RAY_CHUNK_PER_LANE;
-    const unsigned nb = (unsigned)((nrays + chunk - 1) / chunk);
-    RayTail tail{};
-    tail.cap = (int)std::min<long long>(nrays, RAY_TAIL_SLOTS);
+// Per-launch hand-over buffer of the cooperative search (stream-ordered
+// allocation); on failure every ray stays on its lane.
+static void* tail_setup(hipStream_t st, long long n, RayTail& tail) {
+    tail = RayTail{};
+    tail.cap = (int)std::min<long long>(n, RAY_TAIL_SLOTS);
     void* buf = nullptr;
     const size_t per = sizeof(LongRay) + RAY_HEAP_MAX * (3 * sizeof(double) + 4 * sizeof(double) + sizeof(int));
     if (hipMallocAsync(&buf, 256 + per * tail.cap, st) == hipSuccess) {
@@ -794,6 +1119,16 @@ void launch_ray_cast(hipStream_t st, const double* ctrl, int npatch, const doubl
         tail.cap = 0;
         tail.budget = -1;  // never reached: every ray stays on its lane
     }
+    return buf;
+}
+
+void launch_ray_cast(hipStream_t st, const double* ctrl, int npatch, const double* rays, long long nrays,
+                     const RayParams& o, double* hit, int* patch, int* pops) {
+    if (nrays <= 0) return;
+    const int chunk = 256 * RAY_CHUNK_PER_LANE;
+    const unsigned nb = (unsigned)((nrays + chunk - 1) / chunk);
+    RayTail tail;
+    void* buf = tail_setup(st, nrays, tail);
     if (npatch <= RAY_LDS_PATCHES) {
         const size_t lds = sizeof(double) * 54 * (size_t)npatch;
         hipLaunchKernelGGL(k_ray_cast<true>, dim3(nb), dim3(256), lds, st, ctrl, npatch, rays, nrays, chunk, o, tail,
@@ -803,8 +1138,23 @@ void launch_ray_cast(hipStream_t st, const double* ctrl, int npatch, const doubl
                            hit, patch, pops);
     }
     if (buf) {
-        hipLaunchKernelGGL(k_ray_tail, dim3((unsigned)std::min(tail.cap, 2048)), dim3(64), 0, st, ctrl, rays, o,
-                           tail, hit, patch, pops);
+        hipLaunchKernelGGL(k_ray_tail<false>, dim3((unsigned)std::min(tail.cap, 2048)), dim3(64), 0, st, ctrl,
+                           nullptr, rays, 0.0, o, tail, hit, patch, pops);
+        (void)hipFreeAsync(buf, st);
+    }
+}
+
+void launch_ccd(hipStream_t st, const double* ctrl, const double* vel, int npatch, const double* pts,
+                long long npts, double dt, const RayParams& o, double* hit, int* patch, int* pops) {
+    if (npts <= 0) return;
+    const int chunk = 256 * RAY_CHUNK_PER_LANE;
+    RayTail tail;
+    void* buf = tail_setup(st, npts, tail);
+    hipLaunchKernelGGL(k_ccd, dim3((unsigned)((npts + chunk - 1) / chunk)), dim3(256), 0, st, ctrl, vel, npatch, pts,
+                       npts, dt, chunk, o, tail, hit, patch, pops);
+    if (buf) {
+        hipLaunchKernelGGL(k_ray_tail<true>, dim3((unsigned)std::min(tail.cap, 2048)), dim3(64), 0, st, ctrl, vel,
+                           pts, dt, o, tail, hit, patch, pops);
         (void)hipFreeAsync(buf, st);
     }
 }

@@ -1620,6 +1620,41 @@ shell_status shell_ray_cast(const double* ctrl_dev, int32_t n_patches, const dou
     return SHELL_OK;
 }
 
+shell_status shell_ccd(const double* ctrl_dev, const double* vel_dev, int32_t n_patches, const double* points_dev,
+                       int64_t n_points, double dt, const shell_ray_opts* o, double* hit_dev, int32_t* patch_dev,
+                       int32_t* pops_dev) {
+    g_create_error.clear();
+    auto bad = [](const char* m) {
+        g_create_error = m;
+        return SHELL_E_INVAL;
+    };
+    if (!o) return bad("opts is required");
+    if (n_patches < 0 || n_patches > RAY_MAX_PATCHES) return bad("n_patches must be in [0, 2^24)");
+    if (n_points < 0 || n_points > (int64_t)256 * INT32_MAX) return bad("n_points out of range");
+    if (!(dt > 0) || !std::isfinite(dt)) return bad("dt must be > 0");
+    if (n_points == 0) return SHELL_OK;
+    if (!points_dev || !hit_dev || !patch_dev || (n_patches > 0 && (!ctrl_dev || !vel_dev)))
+        return bad("points_dev, hit_dev, patch_dev and (with patches) ctrl_dev and vel_dev are required");
+    if (!(o->eps > 0) || !std::isfinite(o->eps)) return bad("eps must be > 0");
+    if (!(o->newton_tol > 0) || !std::isfinite(o->newton_tol)) return bad("newton_tol must be > 0");
+    if (!(o->hole > 0 && o->hole < 0.5)) return bad("hole must be in (0, 0.5)");
+    if (o->newton_iters < 0 || o->newton_iters > 64) return bad("newton_iters must be in [0, 64]");
+    if (o->max_depth < 1 || o->max_depth > RAY_MAX_DEPTH) return bad("max_depth must be in [1, 60]");
+    if (o->heap_cap < 1 || o->heap_cap > RAY_HEAP_MAX) return bad("heap_cap must be in [1, SHELL_RAY_HEAP_MAX]");
+    hipError_t e = hipSetDevice(o->device);
+    if (e == hipSuccess) {
+        RayParams rp{o->eps, o->newton_tol, o->hole, o->newton_iters, o->max_depth, o->heap_cap};
+        launch_ccd((hipStream_t)o->stream, ctrl_dev, vel_dev, n_patches, points_dev, n_points, dt, rp, hit_dev,
+                   patch_dev, pops_dev);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) {
+        g_create_error = std::string("HIP error in shell_ccd: ") + hipGetErrorString(e);
+        return SHELL_E_DEVICE;
+    }
+    return SHELL_OK;
+}
+
 shell_status shell_point_load(const shell_desc* d, double xi1, double xi2, const double* force, double* f_nodal) {
     if (!d || !force || !f_nodal || d->n1 < 1 || d->n2 < 1 || !(d->dxi1 > 0) || !(d->dxi2 > 0) ||
         (d->periodic1 && d->n1 < 3) || !std::isfinite(xi1) || !std::isfinite(xi2))

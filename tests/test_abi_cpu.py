@@ -144,3 +144,16 @@ def test_ray_opts_defaults_and_validation():
 def s_heap_max():
     src = open(HEADER).read()
     return int(re.search(r"#define SHELL_RAY_HEAP_MAX (\d+)", src).group(1))
+
+
+def test_ccd_validation():
+    s = S()
+    fake = C.c_void_p(0x1000)
+    lib = s.lib
+    o = s.ray_opts()
+    assert lib.shell_ccd(fake, fake, 1, fake, 0, 1.0, C.byref(o), None, None, None) == s.SHELL_OK
+    for dt in (0.0, -1.0, float("inf")):
+        assert lib.shell_ccd(fake, fake, 1, fake, 1, dt, C.byref(o), fake, fake, None) == s.SHELL_E_INVAL
+    assert lib.shell_ccd(fake, None, 1, fake, 1, 1.0, C.byref(o), fake, fake, None) == s.SHELL_E_INVAL
+    assert lib.shell_ccd(fake, fake, 1, fake, 1, 1.0, None, fake, fake, None) == s.SHELL_E_INVAL
+    assert lib.shell_ccd(fake, fake, 1, fake, 1, 1.0, C.byref(s.ray_opts(eps=0.0)), fake, fake, None) == s.SHELL_E_INVAL

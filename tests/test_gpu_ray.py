@@ -173,8 +173,9 @@ def test_degenerate_inputs():
 
 
 def test_heap_capacity_status():
-    """With room for one candidate most rays of the cylinder run out of heap
-    (status -2, no result); the others are exact."""
+    """With room for one candidate on the lane, rays entering two or more
+    patch boxes have no room for their roots (status -2, no result); every
+    other ray moves to the cooperative search at once and is exact."""
     case = W.render_scene("cylinder")
     ctrl_o = _oracle_ctrl(case, case.ref)
     ctrl_g = _gpu_ctrl([case], [case.ref])
@@ -199,3 +200,70 @@ def test_user_stream():
     st.synchronize()
     h0, p0, _ = _cast(ctrl_g, rays.cpu().numpy())
     assert np.array_equal(hit.cpu().numpy(), h0) and np.array_equal(patch.cpu().numpy(), p0)
+
+
+# ---------------------------------------------------------------- Sec. 5.2
+def _rigid_velocity(case, V=(0.0, 0.0, -0.5), w=(0.3, -0.2, 0.5)):
+    """Nodal velocities of a rigid motion: V + w x x for positions, w x
+    (derivative) for the derivative DOFs."""
+    q = case.ref.reshape(-1, 4, 3)
+    out = np.cross(np.asarray(w), q)
+    out[:, 0] += np.asarray(V)
+    return out.reshape(-1, 12)
+
+
+def _ccd_gpu(ctrl, vel, pts, dt, **kw):
+    n = len(pts)
+    hit = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    patch = torch.empty(n, dtype=torch.int32, device="cuda")
+    pops = torch.empty(n, dtype=torch.int32, device="cuda")
+    S().ccd(ctrl, vel, _dev(pts), dt, hit, patch, pops, eps=EPS, **kw)
+    torch.cuda.synchronize()
+    return hit.cpu().numpy(), patch.cpu().numpy(), pops.cpu().numpy()
+
+
+@pytest.mark.parametrize("newton", [0, 8], ids=["midpoint", "newton"])
+@pytest.mark.parametrize("scene", ["cylinder", "drape"])
+def test_ccd_matches_oracle(scene, newton):
+    case = W.render_scene(scene)
+    vq = _rigid_velocity(case)
+    ctrl_o, vel_o = _oracle_ctrl(case, case.ref), _oracle_ctrl(case, vq)
+    ctrl_g, vel_g = _gpu_ctrl([case], [case.ref]), _gpu_ctrl([case], [vq])
+    np.testing.assert_allclose(vel_g.cpu().numpy(), vel_o, rtol=0, atol=1e-14)
+    pts = W.camera_rays(scene, 40, 40, 1, seed=34)
+    pts[:, :3] += 1.0 * pts[:, 3:]          # start 1 m along the camera rays
+    pts[:, 3:] *= 3.0
+    dt = 0.5
+    ho, po = R.ccd(ctrl_o, vel_o, pts, dt, eps=EPS, newton_iters=newton)
+    hg, pg, _ = _ccd_gpu(ctrl_g, vel_g, pts, dt, newton_iters=newton)
+    assert (pg >= -1).all()
+    assert ((pg >= 0) == (po >= 0)).all(), np.nonzero((pg >= 0) != (po >= 0))[0][:10]
+    assert 0.1 < (po >= 0).mean() < 0.9
+    for r in np.nonzero(po >= 0)[0]:
+        t, u, v = ho[r]
+        x, xu, xv = R.bezier_eval(ctrl_o[po[r]] + t * vel_o[po[r]], u, v)
+        vs, _, _ = R.bezier_eval(vel_o[po[r]], u, v)
+        d = pts[r, 3:] - vs
+        n = np.cross(xu, xv)
+        s = abs(n @ d) / (np.linalg.norm(n) * np.linalg.norm(d))
+        tol = 1e-10 if newton else 2 * EPS / (np.linalg.norm(d) * max(s, 1e-3)) + 1e-11
+        assert abs(hg[r, 0] - t) <= tol, (r, hg[r], ho[r])
+        assert pg[r] == po[r] or (_on_edge(*hg[r, 1:]) and _on_edge(u, v)), (r, pg[r], po[r])
+        xg, _, _ = R.bezier_eval(ctrl_o[pg[r]] + hg[r, 0] * vel_o[pg[r]], hg[r, 1], hg[r, 2])
+        assert np.linalg.norm(xg - (pts[r, :3] + hg[r, 0] * pts[r, 3:])) <= 4 * EPS + 1e-10
+
+
+def test_ccd_degenerate_inputs():
+    case = W.render_scene("plane")
+    ctrl_g = _gpu_ctrl([case], [case.ref])
+    vel_g = torch.zeros_like(ctrl_g)
+    pts = W.camera_rays("plane", 8, 8, 1)
+    h, p, pops = _ccd_gpu(None, None, pts, 1.0)
+    assert (p == -1).all() and np.isinf(h[:, 0]).all()
+    bad = pts[:3].copy()
+    bad[0, 0] = np.nan
+    bad[1, 5] = np.inf
+    h, p, _ = _ccd_gpu(ctrl_g, vel_g, bad, 5.0)
+    assert list(p[:2]) == [-3, -3] and p[2] == 0
+    S().ccd(ctrl_g, vel_g, torch.empty((0, 6), dtype=torch.float64, device="cuda"), 1.0,
+            torch.empty((0, 3), dtype=torch.float64, device="cuda"), torch.empty(0, dtype=torch.int32, device="cuda"))
