@@ -517,7 +517,9 @@ def render_section(stream, width=512, height=512, spp=16, reps=3, eps=1e-10):
     midpoint subdivision and Newton-accelerated forms.  Kernel time from HIP
     events around `reps` launches; pops = candidate surfaces examined per
     ray.  The oracle's rate on a seeded sample of the same rays (all host
-    threads) is reported with the CPU baseline."""
+    threads) is reported with the CPU baseline.  The cylinder and the drape
+    also run the dynamic intersection of Sec. 5.2 (`ccd_frame`) on the same
+    number of moving points."""
     import torch
     from paper_2312_14839_amd import shell as S, workloads as W
     out = {"workload": f"{width}x{height} pixels x {spp} samples per scene, eps {eps:g}, hole 1e-3, "
@@ -551,9 +553,62 @@ def render_section(stream, width=512, height=512, spp=16, reps=3, eps=1e-10):
                          "paper_table1_s": PAPER_RENDER_S[sc][0 if ni == 0 else 1]}
             print(f"[bench] render {sc} {mode}: {ms:.2f} ms/frame, {n / ms / 1e3:.1f} M rays/s, "
                   f"pops mean {pp.mean():.2f} max {pp.max()}", file=sys.stderr, flush=True)
+        if sc != "plane":
+            res["ccd"] = ccd_frame(ctx, case, ctrl, stream, width, height, spp, reps, eps)
         ctx.close()
         out[sc] = res
     return out
+
+
+def rigid_velocity(case, V=(0.0, 0.0, -0.5), w=(0.3, -0.2, 0.5)):
+    """Nodal velocities of the rigid motion V + w x x (derivative DOFs: w x)."""
+    q = case.ref.reshape(-1, 4, 3)
+    out = np.cross(np.asarray(w), q)
+    out[:, 0] += np.asarray(V)
+    return out.reshape(-1, 12)
+
+
+def ccd_points(scene, width, height, spp):
+    """Points starting 1 m along the scene's camera rays, moving along them
+    at 3 m/s (one step of 0.5 s)."""
+    from paper_2312_14839_amd import workloads as W
+    pts = W.camera_rays(scene, width, height, spp)
+    pts[:, :3] += pts[:, 3:]
+    pts[:, 3:] *= 3.0
+    return pts
+
+
+def ccd_frame(ctx, case, ctrl, stream, width, height, spp, reps, eps, dt=0.5):
+    """Dynamic intersection (Sec. 5.2): the scene moving rigidly (0.5 m/s
+    down, rotating at |w| = 0.62 rad/s) against the moving points of
+    ccd_points over one step; control-point velocities from the nodal ones
+    with shell_bezier."""
+    import torch
+    from paper_2312_14839_amd import shell as S
+    vel = torch.empty_like(ctrl)
+    ctx.bezier(torch.as_tensor(rigid_velocity(case), device="cuda"), vel)
+    pts = torch.as_tensor(ccd_points(case.name, width, height, spp), device="cuda")
+    n = pts.shape[0]
+    hit = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    patch = torch.empty(n, dtype=torch.int32, device="cuda")
+    pops = torch.empty(n, dtype=torch.int32, device="cuda")
+    res = {}
+    for mode, ni in (("midpoint", 0), ("newton", 8)):
+        S.ccd(ctrl, vel, pts, dt, hit, patch, pops, stream=stream, newton_iters=ni, eps=eps)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            S.ccd(ctrl, vel, pts, dt, hit, patch, pops, stream=stream, newton_iters=ni, eps=eps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        p, pp = patch.cpu().numpy(), pops.cpu().numpy()
+        res[mode] = {"ms": ms, "points_per_s": n / (ms * 1e-3), "contact_fraction": float(np.mean(p >= 0)),
+                     "no_result": int(np.sum(p < -1)), "pops_mean": float(pp.mean()), "pops_max": int(pp.max())}
+        print(f"[bench] ccd {case.name} {mode}: {ms:.2f} ms, {n / ms / 1e3:.1f} M points/s, "
+              f"pops mean {pp.mean():.2f} max {pp.max()}", file=sys.stderr, flush=True)
+    return res
 
 
 def render_cpu_baseline(width=512, height=512, spp=16, eps=1e-10, sample=200_000):
@@ -573,6 +628,15 @@ def render_cpu_baseline(width=512, height=512, spp=16, eps=1e-10, sample=200_000
             t0 = time.perf_counter()
             R.ray_cast(ctrl, rays[idx], eps=eps, newton_iters=ni)
             out[f"{sc}_{mode}"] = len(idx) / (time.perf_counter() - t0)
+        if sc != "plane":
+            vel = R.bezier_grid(O.make_shell(case.n1, case.n2, case.dxi1, case.dxi2, case.young, case.poisson,
+                                             case.thickness, case.density, periodic1=case.periodic1),
+                                rigid_velocity(case))
+            pts = ccd_points(sc, width, height, spp)[idx]
+            for mode, ni in (("midpoint", 0), ("newton", 8)):
+                t0 = time.perf_counter()
+                R.ccd(ctrl, vel, pts, 0.5, eps=eps, newton_iters=ni)
+                out[f"ccd_{sc}_{mode}"] = len(idx) / (time.perf_counter() - t0)
     return out
 
 
