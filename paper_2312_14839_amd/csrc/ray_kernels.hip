@@ -873,25 +873,35 @@ __global__ void __launch_bounds__(256) k_ccd(const double* __restrict__ ctrl, co
 void launch_ccd(hipStream_t st, const double* ctrl, const double* vel, int npatch, const double* pts,
                 long long npts, double dt, const RayParams& o, double* hit, int* patch, int* pops);
 
-// The cooperative search of one handed-over ray per wave (block of 64).
-// The candidates live in an LDS pool; every step sorts their keys (bitonic
-// network over the pool's slots, free slots keyed +inf), takes the (up to)
-// 64 smallest that the ray enters before the best answer, one per lane, and
-// files their sub-rectangles into the slots thus freed.  The midpoint form
-// ends on the batch's first answer in key order; the accelerated form runs
-// until no candidate is left before the best answer.
-constexpr int TAIL_POOL = 1024;
+// The cooperative search of one handed-over ray per block of TAIL_THREADS
+// (4 waves).  The candidates live in an LDS pool; every step sorts their
+// keys (bitonic network over the pool's slots, free slots keyed +inf), takes
+// the (up to) TAIL_THREADS smallest that the ray enters before the best
+// answer, one per thread, and files their sub-rectangles into the slots thus
+// freed.  The midpoint form ends on the step's first answer in key order;
+// the accelerated form runs until no candidate is left before the best
+// answer.  Block-wide values (best answer, counts) go through LDS.
+constexpr int TAIL_POOL = 2048;
+constexpr int TAIL_THREADS = 256;
+constexpr size_t TAIL_LDS = (size_t)TAIL_POOL * (7 * sizeof(double) + sizeof(int) + sizeof(short));
 
 template <bool MOVING>
-__global__ void __launch_bounds__(64) k_ray_tail(const double* __restrict__ ctrl, const double* __restrict__ vel,
-                                                 const double* __restrict__ rays, double dt, RayParams o, RayTail tail,
-                                                 double* __restrict__ hit, int* __restrict__ patch_out,
-                                                 int* __restrict__ pops_out) {
-    __shared__ double key[TAIL_POOL], thi[TAIL_POOL], rect[TAIL_POOL][4];
-    __shared__ int tag[TAIL_POOL];
-    __shared__ double skey[TAIL_POOL];
-    __shared__ short sidx[TAIL_POOL];
-    const int lane = threadIdx.x;
+__global__ void __launch_bounds__(TAIL_THREADS) k_ray_tail(const double* __restrict__ ctrl,
+                                                           const double* __restrict__ vel,
+                                                           const double* __restrict__ rays, double dt, RayParams o,
+                                                           RayTail tail, double* __restrict__ hit,
+                                                           int* __restrict__ patch_out, int* __restrict__ pops_out) {
+    extern __shared__ double dyn[];
+    double* key = dyn;
+    double* thi = key + TAIL_POOL;
+    double* skey = thi + TAIL_POOL;
+    double(*rect)[4] = (double(*)[4])(skey + TAIL_POOL);
+    int* tag = (int*)(rect + TAIL_POOL);
+    short* sidx = (short*)(tag + TAIL_POOL);
+    __shared__ double w_t[TAIL_THREADS / 64], s_best, s_bu, s_bv;
+    __shared__ int w_i[TAIL_THREADS / 64], w_c[TAIL_THREADS / 64], s_live, s_bp;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int NW = TAIL_THREADS / 64;
     const int count = min(*tail.count, tail.cap);
     for (int s = blockIdx.x; s < count; s += gridDim.x) {
         const LongRay lr = tail.rays[s];
@@ -902,13 +912,11 @@ __global__ void __launch_bounds__(64) k_ray_tail(const double* __restrict__ ctrl
             r.d[c] = rays[6 * lr.rid + 3 + c];
         }
         const double small = o.eps * sqrt(dot3(r.d, r.d));
-        (void)dt;
-        (void)vel;
         double best = lr.best, bu = lr.bu, bv = lr.bv;
         int bp = lr.bp, pops = lr.pops, hi = lr.n;
         bool over = false;
         __syncthreads();
-        for (int e = lane; e < TAIL_POOL; e += 64) {
+        for (int e = tid; e < TAIL_POOL; e += TAIL_THREADS) {
             if (e < lr.n) {
                 const long long q = (long long)s * RAY_HEAP_MAX + e;
                 key[e] = tail.key[q];
@@ -927,14 +935,14 @@ __global__ void __launch_bounds__(64) k_ray_tail(const double* __restrict__ ctrl
             // sort (key, slot) over the used slots [0, hi)
             int n2 = 64;
             while (n2 < hi) n2 <<= 1;
-            for (int e = lane; e < n2; e += 64) {
+            for (int e = tid; e < n2; e += TAIL_THREADS) {
                 skey[e] = e < hi ? key[e] : INFINITY;
                 sidx[e] = (short)e;
             }
             __syncthreads();
             for (int k = 2; k <= n2; k <<= 1)
                 for (int j = k >> 1; j > 0; j >>= 1) {
-                    for (int e = lane; e < n2; e += 64) {
+                    for (int e = tid; e < n2; e += TAIL_THREADS) {
                         const int f = e ^ j;
                         if (f > e) {
                             const bool up = (e & k) == 0;
@@ -952,28 +960,34 @@ __global__ void __launch_bounds__(64) k_ray_tail(const double* __restrict__ ctrl
                     }
                     __syncthreads();
                 }
-            // candidates the ray enters before the best answer
-            int live = 0;
-            for (int e = 0; e < n2; e += 64) {
-                const unsigned long long m = __ballot(e + lane < n2 && skey[e + lane] < best);
-                live += __popcll(m);
-                if (m != ~0ull) break;
+            // candidates the ray enters before the best answer (sorted: a
+            // binary search)
+            if (tid == 0) {
+                int lo = 0, up = n2;
+                while (lo < up) {
+                    const int mid = (lo + up) >> 1;
+                    if (skey[mid] < best) lo = mid + 1;
+                    else up = mid;
+                }
+                s_live = lo;
             }
+            __syncthreads();
+            const int live = s_live;
             if (live == 0) break;
-            if (pops + min(live, 64) > RAY_MAX_POPS) {
+            const int m = min(live, TAIL_THREADS);
+            if (pops + m > RAY_MAX_POPS) {
                 over = true;
                 break;
             }
-            const int m = min(live, 64);
-            // this lane's candidate: an answer box, or a Newton hit
+            // this thread's candidate: an answer box, or a Newton hit
             double ct = INFINITY, cu = 0.0, cv = 0.0;
             bool is_answer = false;
             int cpatch = -1;
             double kk[4][6];
             int ktag[4];
             int nk = 0;
-            if (lane < m) {
-                const int e = sidx[lane];
+            if (tid < m) {
+                const int e = sidx[tid];
                 const double tlo = key[e], th = thi[e];
                 const double rc[4] = {rect[e][0], rect[e][1], rect[e][2], rect[e][3]};
                 const int tg = tag[e];
@@ -992,16 +1006,16 @@ __global__ void __launch_bounds__(64) k_ray_tail(const double* __restrict__ ctrl
                 } else {
                     double ht, hu = 0.0, hv = 0.0;
                     auto emit = [&](double k, double th2, const double* kr, int tg2) {
-                               kk[nk][0] = k;
-                               kk[nk][1] = th2;
-                               kk[nk][2] = kr[0];
-                               kk[nk][3] = kr[1];
-                               kk[nk][4] = kr[2];
-                               kk[nk][5] = kr[3];
-                               ktag[nk] = tg2;
-                               ++nk;
-                               return true;
-                           };
+                        kk[nk][0] = k;
+                        kk[nk][1] = th2;
+                        kk[nk][2] = kr[0];
+                        kk[nk][3] = kr[1];
+                        kk[nk][4] = kr[2];
+                        kk[nk][5] = kr[3];
+                        ktag[nk] = tg2;
+                        ++nk;
+                        return true;
+                    };
                     if constexpr (MOVING)
                         expand_ccd(ctrl + 48 * cpatch, vel + 48 * cpatch, r.o, r.d, dt, o, best, tlo, rc, cpatch,
                                    (tg >> 24) & 63, ht, hu, hv, emit);
@@ -1013,55 +1027,66 @@ __global__ void __launch_bounds__(64) k_ray_tail(const double* __restrict__ ctrl
                 }
             }
             pops += m;
-            // the batch's result: the midpoint form takes its first answer in
-            // key order, the accelerated form the smallest tau (lowest lane
-            // on ties)
-            bool stop = false;
-            if (o.newton_iters == 0) {
-                const unsigned long long am = __ballot(is_answer);
-                if (am) {
-                    const int w = __ffsll((long long)am) - 1;
-                    best = __shfl(ct, w);
-                    bu = __shfl(cu, w);
-                    bv = __shfl(cv, w);
-                    bp = __shfl(cpatch, w);
-                    stop = true;
-                }
-            } else {
-                double t = ct;
-                int wl = lane;
-                for (int off = 32; off > 0; off >>= 1) {
-                    const double t2 = __shfl_xor(t, off);
-                    const int w2 = __shfl_xor(wl, off);
-                    if (t2 < t || (t2 == t && w2 < wl)) {
-                        t = t2;
-                        wl = w2;
-                    }
-                }
-                const double su = __shfl(cu, wl), sv = __shfl(cv, wl);
-                const int sp = __shfl(cpatch, wl);
-                if (t < best) {
-                    best = t;
-                    bu = su;
-                    bv = sv;
-                    bp = sp;
+            // the step's result: the midpoint form takes its first answer in
+            // key order, the accelerated form the smallest tau (lowest
+            // thread on ties)
+            double t = (o.newton_iters == 0) ? (is_answer ? (double)tid : INFINITY) : ct;
+            int wl = tid;
+            for (int off = 32; off > 0; off >>= 1) {
+                const double t2 = __shfl_xor(t, off);
+                const int w2 = __shfl_xor(wl, off);
+                if (t2 < t || (t2 == t && w2 < wl)) {
+                    t = t2;
+                    wl = w2;
                 }
             }
-            if (stop) break;
-            // free slots: the m examined, then those past the live ones
+            if (lane == 0) {
+                w_t[wave] = t;
+                w_i[wave] = wl;
+            }
             __syncthreads();
-            for (int e = lane; e < n2; e += 64)
+            double tb = w_t[0];
+            int ib = w_i[0];
+            for (int q = 1; q < NW; ++q)
+                if (w_t[q] < tb || (w_t[q] == tb && w_i[q] < ib)) {
+                    tb = w_t[q];
+                    ib = w_i[q];
+                }
+            const bool found = o.newton_iters == 0 ? tb < INFINITY : tb < best;
+            if (found && tid == ib) {
+                s_best = ct;
+                s_bu = cu;
+                s_bv = cv;
+                s_bp = cpatch;
+            }
+            __syncthreads();
+            if (found) {
+                best = s_best;
+                bu = s_bu;
+                bv = s_bv;
+                bp = s_bp;
+            }
+            if (o.newton_iters == 0 && found) break;
+            // free slots: the m examined, then those past the live ones
+            for (int e = tid; e < n2; e += TAIL_THREADS)
                 if ((e < m || e >= live) && e < hi) key[sidx[e]] = INFINITY;
             __syncthreads();
-            // file the children round by round (lane order within a round)
+            // file the children round by round (thread order within a round)
             int filed = 0;
             const int nfree_tail = max(hi - live, 0);
-            int new_hi = hi;
             for (int k = 0; k < 4; ++k) {
                 const unsigned long long bm = __ballot(nk > k);
-                if (!bm) break;
+                if (lane == 0) w_c[wave] = __popcll(bm);
+                __syncthreads();
+                int basew = 0, total = 0;
+                for (int q = 0; q < NW; ++q) {
+                    if (q < wave) basew += w_c[q];
+                    total += w_c[q];
+                }
+                __syncthreads();
+                if (total == 0) break;
                 if (nk > k) {
-                    const int j = filed + __popcll(bm & ((1ull << lane) - 1));
+                    const int j = filed + basew + __popcll(bm & ((1ull << lane) - 1));
                     int slot;
                     if (j < m) slot = sidx[j];
                     else if (j - m < nfree_tail) slot = sidx[live + (j - m)];
@@ -1076,9 +1101,9 @@ __global__ void __launch_bounds__(64) k_ray_tail(const double* __restrict__ ctrl
                         tag[slot] = ktag[k];
                     }
                 }
-                filed += __popcll(bm);
+                filed += total;
             }
-            if (filed - m > nfree_tail) new_hi = hi + (filed - m - nfree_tail);
+            const int new_hi = filed - m > nfree_tail ? hi + (filed - m - nfree_tail) : hi;
             if (new_hi > TAIL_POOL) {
                 over = true;
                 break;
@@ -1087,7 +1112,7 @@ __global__ void __launch_bounds__(64) k_ray_tail(const double* __restrict__ ctrl
             __syncthreads();
         }
         __syncthreads();
-        if (lane == 0)
+        if (tid == 0)
             write_result(hit, patch_out, pops_out, lr.rid, over ? INFINITY : (bp >= 0 ? best : INFINITY), bu, bv,
                          over ? -2 : bp, pops);
     }
@@ -1102,8 +1127,14 @@ static void* tail_setup(hipStream_t st, long long n, RayTail& tail) {
     tail = RayTail{};
     tail.cap = (int)std::min<long long>(n, RAY_TAIL_SLOTS);
     void* buf = nullptr;
+    // the cooperative search needs more LDS than a launch gets by default
+    const bool lds_ok =
+        hipFuncSetAttribute((const void*)k_ray_tail<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)TAIL_LDS) == hipSuccess &&
+        hipFuncSetAttribute((const void*)k_ray_tail<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)TAIL_LDS) == hipSuccess;
     const size_t per = sizeof(LongRay) + RAY_HEAP_MAX * (3 * sizeof(double) + 4 * sizeof(double) + sizeof(int));
-    if (hipMallocAsync(&buf, 256 + per * tail.cap, st) == hipSuccess) {
+    if (lds_ok && hipMallocAsync(&buf, 256 + per * tail.cap, st) == hipSuccess) {
         char* b = (char*)buf;
         tail.count = (int*)b;
         tail.rays = (LongRay*)(b + 256);
@@ -1138,8 +1169,8 @@ void launch_ray_cast(hipStream_t st, const double* ctrl, int npatch, const doubl
                            hit, patch, pops);
     }
     if (buf) {
-        hipLaunchKernelGGL(k_ray_tail<false>, dim3((unsigned)std::min(tail.cap, 2048)), dim3(64), 0, st, ctrl,
-                           nullptr, rays, 0.0, o, tail, hit, patch, pops);
+        hipLaunchKernelGGL(k_ray_tail<false>, dim3((unsigned)std::min(tail.cap, 1024)), dim3(TAIL_THREADS), TAIL_LDS,
+                           st, ctrl, nullptr, rays, 0.0, o, tail, hit, patch, pops);
         (void)hipFreeAsync(buf, st);
     }
 }
@@ -1153,8 +1184,8 @@ void launch_ccd(hipStream_t st, const double* ctrl, const double* vel, int npatc
     hipLaunchKernelGGL(k_ccd, dim3((unsigned)((npts + chunk - 1) / chunk)), dim3(256), 0, st, ctrl, vel, npatch, pts,
                        npts, dt, chunk, o, tail, hit, patch, pops);
     if (buf) {
-        hipLaunchKernelGGL(k_ray_tail<true>, dim3((unsigned)std::min(tail.cap, 2048)), dim3(64), 0, st, ctrl, vel,
-                           pts, dt, o, tail, hit, patch, pops);
+        hipLaunchKernelGGL(k_ray_tail<true>, dim3((unsigned)std::min(tail.cap, 1024)), dim3(TAIL_THREADS), TAIL_LDS,
+                           st, ctrl, vel, pts, dt, o, tail, hit, patch, pops);
         (void)hipFreeAsync(buf, st);
     }
 }
