@@ -368,7 +368,7 @@ void shell_ray_default_opts(shell_ray_opts *o);
  *             there is no result: more root candidates than heap_cap, or
  *             the cooperative search (which takes over a ray after 512
  *             candidates or when its heap of heap_cap nears full, with room
- *             for 1,024 candidates and 16,384 rays per call) ran out of room,
+ *             for 2,048 candidates and 16,384 rays per call) ran out of room,
  *             or 2^18 candidates examined; -3 for an invalid ray (zero or
  *             non-finite direction, non-finite origin).
  *   pops_dev  [n_rays] int32 out, or NULL: candidates the ray examined.
