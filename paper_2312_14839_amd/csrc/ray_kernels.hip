@@ -759,12 +759,24 @@ __device__ inline void expand_ccd(const double* cp, const double* cv, const doub
 // same heap search with keys = earliest feasible times and answers = boxes
 // (at that time) with a diagonal <= eps; points past the budget, or whose
 // heap nears capacity, go to k_ray_tail<true>.
-__global__ void __launch_bounds__(256) k_ccd(const double* __restrict__ ctrl, const double* __restrict__ vel,
+template <bool LDS>
+__global__ void __launch_bounds__(256) k_ccd(const double* __restrict__ ctrl_g, const double* __restrict__ vel_g,
                                              int npatch, const double* __restrict__ pts, long long npts, double dt,
                                              int chunk, RayParams o, RayTail tail, double* __restrict__ hit,
                                              int* __restrict__ patch_out, int* __restrict__ pops_out) {
+    extern __shared__ double lds[];
     __shared__ int s_next;
     if (threadIdx.x == 0) s_next = 0;
+    const double* ctrl = ctrl_g;
+    const double* vel = vel_g;
+    if (LDS) {  // positions, then velocities
+        for (int k = threadIdx.x; k < 48 * npatch; k += blockDim.x) {
+            lds[k] = ctrl_g[k];
+            lds[48 * npatch + k] = vel_g[k];
+        }
+        ctrl = lds;
+        vel = lds + 48 * npatch;
+    }
     __syncthreads();
     const long long base = (long long)blockIdx.x * chunk;
     const int cnt = (int)(npts - base < chunk ? npts - base : chunk);
@@ -1181,8 +1193,18 @@ void launch_ccd(hipStream_t st, const double* ctrl, const double* vel, int npatc
     const int chunk = 256 * RAY_CHUNK_PER_LANE;
     RayTail tail;
     void* buf = tail_setup(st, npts, tail);
-    hipLaunchKernelGGL(k_ccd, dim3((unsigned)((npts + chunk - 1) / chunk)), dim3(256), 0, st, ctrl, vel, npatch, pts,
-                       npts, dt, chunk, o, tail, hit, patch, pops);
+    const unsigned nb = (unsigned)((npts + chunk - 1) / chunk);
+    const size_t lds = sizeof(double) * 96 * (size_t)npatch;
+    if (npatch <= RAY_LDS_PATCHES &&
+        hipFuncSetAttribute((const void*)k_ccd<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) ==
+            hipSuccess) {
+        hipLaunchKernelGGL(k_ccd<true>, dim3(nb), dim3(256), lds, st, ctrl, vel, npatch, pts, npts, dt, chunk, o, tail,
+                           hit, patch, pops);
+    } else {
+        (void)hipGetLastError();
+        hipLaunchKernelGGL(k_ccd<false>, dim3(nb), dim3(256), 0, st, ctrl, vel, npatch, pts, npts, dt, chunk, o, tail,
+                           hit, patch, pops);
+    }
     if (buf) {
         hipLaunchKernelGGL(k_ray_tail<true>, dim3((unsigned)std::min(tail.cap, 1024)), dim3(TAIL_THREADS), TAIL_LDS,
                            st, ctrl, vel, pts, dt, o, tail, hit, patch, pops);
