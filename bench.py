@@ -680,6 +680,69 @@ def cpu_baseline(budget_s=12.0, budget_1t=8.0):
     return out
 
 
+def oracle_newton_baseline(gpu_step1=None, cyl=True):
+    """The oracle's implicit Newton step, timed on the host: the banded
+    LDL^T Newton (the paper's solver class) on the 8x8 sheet and on step 1
+    of the 30x30 twist, on all host threads and on one; the oracle's own
+    block-Jacobi CG Newton on step 1 of the 256x256 cylinder (all threads
+    only: about a minute), and the relative displacement error of the GPU's
+    step-1 states (gpu_step1: {form: state}) against it."""
+    import ctypes
+    from oracle import oracle as O
+    from paper_2312_14839_amd import workloads as W
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    try:
+        omp = ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        omp = None
+    out = {"unit": "ms per implicit step", "cores": cores, "kind": "oracle"}
+
+    def step(case, solver, tol, threads):
+        if omp is not None:
+            omp.omp_set_num_threads(threads)
+        s = O.shell_from_case(case)
+        qp = case.presc(case.dt) if case.presc is not None else None
+        t0 = time.perf_counter()
+        rc, q1, _, st = O.newton_step(s, case.ref, case.fixed, case.dt, case.q0, case.v0, qp, solver=solver, **tol)
+        ms = 1e3 * (time.perf_counter() - t0)
+        if omp is not None:
+            omp.omp_set_num_threads(cores)
+        return rc, q1, st, ms
+
+    for name, case, solver, tol in (
+            ("sheet8x8_ldlt", W.case_small_sheet(), "ldlt", dict(newton_rtol=1e-10)),
+            ("twist30x30_step1_ldlt", W.case_twist(30), "ldlt", dict(newton_rtol=1e-10))):
+        rc, _, st, ms_all = step(case, solver, tol, cores)
+        _, _, _, ms_one = step(case, solver, tol, 1) if omp is not None else (None, None, None, None)
+        out[name] = {"ms": ms_all, "ms_1thread": ms_one, "status": rc, "newton_iters": st["newton_iters"]}
+        print(f"[bench] oracle {name}: {ms_all:.0f} ms ({cores} threads), {ms_one} ms (1 thread)",
+              file=sys.stderr, flush=True)
+    if cyl:
+        case = W.case_cylinder(256, 256)
+        rc, q1, st, ms = step(case, "pcg", dict(newton_rtol=1e-10, pcg_rtol=1e-8), cores)
+        res = {"ms": ms, "status": rc, "newton_iters": st["newton_iters"], "cg_iters": st["pcg_iters_total"]}
+        for form, q in (gpu_step1 or {}).items():
+            num = np.linalg.norm((q - q1)[:, 0:3])
+            den = np.linalg.norm((q1 - case.q0)[:, 0:3])
+            res[f"rel_disp_err_{form}_vs_oracle"] = float(num / den)
+        out["cylinder256_step1_pcg"] = res
+        print(f"[bench] oracle cylinder step 1 (PCG): {ms / 1e3:.1f} s, errors "
+              f"{ {k: v for k, v in res.items() if k.startswith('rel_')} }", file=sys.stderr, flush=True)
+    return out
+
+
+def teardown():
+    """Finish device work and release what the process holds on the
+    device before the interpreter exits: contexts still referenced (closed
+    by their finaliser), then torch's cached device memory."""
+    import gc
+    import torch
+    torch.cuda.synchronize()
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -769,8 +832,15 @@ def main():
         out["learned"] = learned_section(stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
+        gpu_step1 = None
+        if args.workload == "cylinder":
+            gpu_step1 = {"fp64": qstate_after(case, S.SHELL_FP64, 1, stream, tol)}
+            if not args.no_mixed:
+                gpu_step1["mixed"] = qstate_after(case, S.SHELL_MIXED, 1, stream, tol)
+        out["cpu_baseline"]["newton_step"] = oracle_newton_baseline(gpu_step1, cyl=args.workload == "cylinder")
         if "render" in out:
             out["cpu_baseline"]["render"] = render_cpu_baseline()
+    teardown()
     print(json.dumps(out), flush=True)
 
 

@@ -123,6 +123,13 @@ int orc_newton_step(const Shell* s, const double* qb, const uint8_t* fixed, doub
     return newton_step(*s, qb, fixed, dt, qn, vn, qpresc, f_ext, *o, qn1, vn1, st);
 }
 
+// The same step with a record of its iterations (see NewtonTrace).
+int orc_newton_step_traced(const Shell* s, const double* qb, const uint8_t* fixed, double dt, const double* qn,
+                           const double* vn, const double* qpresc, const double* f_ext, const NewtonOpts* o,
+                           double* qn1, double* vn1, NewtonStats* st, NewtonTrace* tr) {
+    return newton_step(*s, qb, fixed, dt, qn, vn, qpresc, f_ext, *o, qn1, vn1, st, tr);
+}
+
 // Solve (K + mass_scale M) x = b with fixed DOFs replaced by identity rows
 // and columns; solver 0: banded LDL^T, 1: block-Jacobi CG.  For solver tests.
 // Returns 0 on success.

@@ -358,7 +358,7 @@ double norm2(const std::vector<double>& v) {
 
 int newton_step(const Shell& s, const double* qb, const uint8_t* fixed, double dt, const double* qn, const double* vn,
                 const double* qpresc, const double* f_ext, const NewtonOpts& o, double* qn1, double* vn1,
-                NewtonStats* st) {
+                NewtonStats* st, NewtonTrace* tr) {
     Problem P(s, qb, fixed, dt, f_ext);
     P.qn = qn;
     const int n = P.n();
@@ -449,15 +449,30 @@ int newton_step(const Shell& s, const double* qb, const uint8_t* fixed, double d
         }
         for (int i = 0; i < n; ++i)
             if (P.is_fixed(i)) d[i] = 0.0;
+        // trace row of this iteration (recording only)
+        const bool rec = tr && k < tr->cap_iters;
+        if (rec) {
+            tr->n_iters = k + 1;
+            if (tr->delta) tr->delta[k] = delta;
+            if (tr->energy) tr->energy[k] = E;
+            if (tr->q_iter) std::copy(q.begin(), q.end(), tr->q_iter + (size_t)k * n);
+        }
         // Backtracking line search on E along d (the paper's solver uses the
         // quadratic and cubic line searches of ArcSim): Armijo with c1 = 1e-4;
         // the first new step from a quadratic fit, later ones from a cubic
         // fit, each clamped to [0.1, 0.5] of the previous step.
         double slope = 0;
         for (int i = 0; i < n; ++i) slope += g[i] * d[i];
-        if (!(slope < 0.0)) {
+        const bool steepest = !(slope < 0.0);
+        if (steepest) {
             for (int i = 0; i < n; ++i) d[i] = -g[i];
             slope = -gn * gn;
+        }
+        if (rec) {
+            if (tr->slope) tr->slope[k] = slope;
+            if (tr->steepest) tr->steepest[k] = steepest ? 1 : 0;
+            if (tr->d_iter) std::copy(d.begin(), d.end(), tr->d_iter + (size_t)k * n);
+            if (tr->n_trials) tr->n_trials[k] = 0;
         }
         double alpha = 1.0, a_prev = 0.0, E_prev = 0.0;
         bool accepted = false;
@@ -465,6 +480,11 @@ int newton_step(const Shell& s, const double* qb, const uint8_t* fixed, double d
         for (int t = 0; t < 20; ++t) {
             for (int i = 0; i < n; ++i) qt[i] = q[i] + alpha * d[i];
             Et = P.eval(qt.data(), gt.data(), &scale_t);
+            if (rec) {
+                if (tr->alpha) tr->alpha[20 * k + t] = alpha;
+                if (tr->e_trial) tr->e_trial[20 * k + t] = Et;
+                if (tr->n_trials) tr->n_trials[k] = t + 1;
+            }
             if (std::isfinite(Et)) {
                 if (Et <= E + 1e-4 * alpha * slope) {
                     accepted = true;

@@ -46,6 +46,16 @@ class NewtonStats(C.Structure):
     ]
 
 
+class NewtonTrace(C.Structure):
+    _fields_ = [
+        ("cap_iters", C.c_int), ("n_iters", C.c_int),
+        ("delta", C.POINTER(C.c_double)), ("energy", C.POINTER(C.c_double)), ("slope", C.POINTER(C.c_double)),
+        ("steepest", C.POINTER(C.c_int)), ("n_trials", C.POINTER(C.c_int)),
+        ("alpha", C.POINTER(C.c_double)), ("e_trial", C.POINTER(C.c_double)),
+        ("q_iter", C.POINTER(C.c_double)), ("d_iter", C.POINTER(C.c_double)),
+    ]
+
+
 def _load(path=_LIB_PATH):
     if not os.path.exists(path):
         from . import build_oracle
@@ -78,6 +88,10 @@ def _load(path=_LIB_PATH):
     lib.orc_newton_step.argtypes = [sp, d, C.POINTER(C.c_uint8), C.c_double, d, d, d, d,
                                     C.POINTER(NewtonOpts), d, d, C.POINTER(NewtonStats)]
     lib.orc_newton_step.restype = C.c_int
+    lib.orc_newton_step_traced.argtypes = [sp, d, C.POINTER(C.c_uint8), C.c_double, d, d, d, d,
+                                           C.POINTER(NewtonOpts), d, d, C.POINTER(NewtonStats),
+                                           C.POINTER(NewtonTrace)]
+    lib.orc_newton_step_traced.restype = C.c_int
     lib.orc_linear_solve.argtypes = [sp, d, d, C.POINTER(C.c_uint8), C.c_double, C.c_int, d, d,
                                      C.c_double, C.c_int, C.POINTER(C.c_int)]
     lib.orc_linear_solve.restype = C.c_int
@@ -255,10 +269,13 @@ def matrix_dense(shell, q, qb, which="hessian", pseudo=False):
 
 
 def newton_step(shell, qb, fixed, dt, qn, vn, qpresc=None, solver="ldlt", pseudo=False,
-                newton_rtol=1e-10, newton_maxit=50, pcg_rtol=1e-10, pcg_maxit=100000, f_ext=None):
+                newton_rtol=1e-10, newton_maxit=50, pcg_rtol=1e-10, pcg_maxit=100000, f_ext=None, trace=0):
     """One implicit-Euler step (mass-proportional damping from shell.damping,
     optional external nodal forces f_ext [nodes, 12]).  Returns (status,
-    q_next, v_next, stats dict)."""
+    q_next, v_next, stats dict); with trace = K > 0 the stats also hold
+    "trace", a record of the first K Newton iterations (regulariser delta,
+    energy, slope, steepest-descent fallback, line-search trials, iterate
+    and direction of each)."""
     qb, qn, vn = _f64(qb), _f64(qn), _f64(vn)
     fe = _f64(f_ext) if f_ext is not None else None
     fx = np.ascontiguousarray(fixed, dtype=np.uint8) if fixed is not None else None
@@ -267,11 +284,28 @@ def newton_step(shell, qb, fixed, dt, qn, vn, qpresc=None, solver="ldlt", pseudo
                    int(pcg_maxit), float(pcg_rtol))
     st = NewtonStats()
     q1, v1 = np.zeros_like(qn), np.zeros_like(qn)
-    rc = lib().orc_newton_step(C.byref(shell), _d(qb),
-                               fx.ctypes.data_as(C.POINTER(C.c_uint8)) if fx is not None else None,
-                               float(dt), _d(qn), _d(vn), _d(qp) if qp is not None else None,
-                               _d(fe) if fe is not None else None, C.byref(o), _d(q1), _d(v1), C.byref(st))
+    args = (C.byref(shell), _d(qb), fx.ctypes.data_as(C.POINTER(C.c_uint8)) if fx is not None else None,
+            float(dt), _d(qn), _d(vn), _d(qp) if qp is not None else None,
+            _d(fe) if fe is not None else None, C.byref(o), _d(q1), _d(v1), C.byref(st))
+    if trace:
+        K, n = int(trace), qn.size
+        rec = {"delta": np.zeros(K), "energy": np.zeros(K), "slope": np.zeros(K),
+               "steepest": np.zeros(K, np.int32), "n_trials": np.zeros(K, np.int32),
+               "alpha": np.zeros((K, 20)), "e_trial": np.zeros((K, 20)),
+               "q_iter": np.zeros((K, n)), "d_iter": np.zeros((K, n))}
+        tr = NewtonTrace(K, 0, *[rec[k].ctypes.data_as(C.POINTER(C.c_int if rec[k].dtype == np.int32
+                                                                   else C.c_double))
+                                 for k in ("delta", "energy", "slope", "steepest", "n_trials", "alpha",
+                                           "e_trial", "q_iter", "d_iter")])
+        rc = lib().orc_newton_step_traced(*args, C.byref(tr))
+        m = tr.n_iters
+        rec = {k: v[:m] for k, v in rec.items()}
+    else:
+        rc = lib().orc_newton_step(*args)
+        rec = None
     stats = {k: getattr(st, k) for k, _ in NewtonStats._fields_ if k != "pad"}
+    if rec is not None:
+        stats["trace"] = rec
     return rc, q1, v1, stats
 
 

@@ -47,6 +47,22 @@ struct NewtonStats {
     int newton_iters, pcg_iters_total, ls_backtracks, pad;
     double grad_norm0, grad_norm, grad_floor, reg_delta;
 };
+// Optional record of the Newton iterations, for tests that check each step
+// of the method on its own (regulariser, direction, line search).  Arrays
+// hold cap_iters rows; pointers may be NULL to skip a record.
+struct NewtonTrace {
+    int cap_iters;     // rows available
+    int n_iters;       // rows written (iterations that produced a direction)
+    double* delta;     // [cap] regulariser delta of iteration k (0: none)
+    double* energy;    // [cap] E at the iterate of iteration k
+    double* slope;     // [cap] g . d along the direction taken
+    int* steepest;     // [cap] 1: the solve's direction was not a descent direction, -g taken
+    int* n_trials;     // [cap] line-search trials (the last one accepted if the search succeeded)
+    double* alpha;     // [cap][20] trial step lengths
+    double* e_trial;   // [cap][20] E at each trial
+    double* q_iter;    // [cap][n] iterate of iteration k
+    double* d_iter;    // [cap][n] direction of iteration k
+};
 // Converged when ||g_k|| <= max(newton_rtol ||g_0||, 4 eps || P_free |A_{k-1}| |q_k| ||).
 // Returns 0 converged, 1 Newton iteration cap, 2 line search failed,
 // 3 no positive definite system within the regulariser cap.
@@ -54,6 +70,6 @@ struct NewtonStats {
 // the areal gravity load.
 int newton_step(const Shell& s, const double* qb, const uint8_t* fixed, double dt, const double* qn, const double* vn,
                 const double* qpresc, const double* f_ext, const NewtonOpts& o, double* qn1, double* vn1,
-                NewtonStats* st);
+                NewtonStats* st, NewtonTrace* trace = nullptr);
 
 }  // namespace orc

@@ -986,7 +986,33 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_ray_tail(const double* __restr
             __syncthreads();
             const int live = s_live;
             if (live == 0) break;
-            const int m = min(live, TAIL_THREADS);
+            int m = min(live, TAIL_THREADS);
+            // is this thread's candidate (the tid-th smallest key) an answer box
+            bool ans = false;
+            if (tid < m) {
+                const int e = sidx[tid];
+                const int tg = tag[e];
+                if constexpr (MOVING)
+                    ans = ((tg >> 24) & 63) >= o.max_depth ||
+                          diag_at(ctrl + 48 * (tg & 0xFFFFFF), vel + 48 * (tg & 0xFFFFFF), rect[e][0], rect[e][1],
+                                  rect[e][2], rect[e][3], key[e]) <= o.eps;
+                else
+                    ans = (tg & (1 << 30)) != 0;
+            }
+            // Midpoint form: the result is the first answer in key order over
+            // the whole search, so a step examines only the candidates ahead
+            // of its first answer (their children may hold an answer with a
+            // smaller key) and leaves that answer in the pool; only an answer
+            // with the smallest key of all is taken.
+            if (o.newton_iters == 0) {
+                const unsigned long long bal = __ballot(ans);
+                if (lane == 0) w_c[wave] = bal ? wave * 64 + (__ffsll(bal) - 1) : TAIL_THREADS;
+                __syncthreads();
+                int first = TAIL_THREADS;
+                for (int q = 0; q < NW; ++q) first = min(first, w_c[q]);
+                __syncthreads();
+                m = first == 0 ? 1 : min(first, m);
+            }
             if (pops + m > RAY_MAX_POPS) {
                 over = true;
                 break;
@@ -1004,12 +1030,6 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_ray_tail(const double* __restr
                 const double rc[4] = {rect[e][0], rect[e][1], rect[e][2], rect[e][3]};
                 const int tg = tag[e];
                 cpatch = tg & 0xFFFFFF;
-                bool ans;
-                if constexpr (MOVING)
-                    ans = ((tg >> 24) & 63) >= o.max_depth ||
-                          diag_at(ctrl + 48 * cpatch, vel + 48 * cpatch, rc[0], rc[1], rc[2], rc[3], tlo) <= o.eps;
-                else
-                    ans = (tg & (1 << 30)) != 0;
                 if (ans) {
                     is_answer = true;
                     ct = MOVING ? tlo : 0.5 * (tlo + th);

@@ -1416,18 +1416,25 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
         sync(c);
         std::vector<double> slope(c->h_red, c->h_red + S);
         std::vector<double> alpha(S, 0.0), a_prev(S, 0.0), E_prev(S, 0.0);
-        std::vector<int> searching(S, 0);
+        std::vector<int> searching(S, 0), steepest(S, 0);
+        bool any_steep = false;
         for (int s = 0; s < S; ++s)
             if (active[s]) {
                 searching[s] = 1;
                 alpha[s] = 1.0;
-                if (!(slope[s] < 0.0)) {   // not a descent direction: fall back to -g (never expected)
-                    status[s] = SHELL_E_LINESEARCH;
-                    active[s] = 0;
-                    searching[s] = 0;
-                    alpha[s] = 0.0;
+                if (!(slope[s] < 0.0)) {   // not a descent direction (an indefinite system the CG did
+                    steepest[s] = 1;       // not detect): search along -g instead
+                    slope[s] = -gn[s] * gn[s];
+                    any_steep = true;
                 }
             }
+        if (any_steep) {
+            h2d(c, c->flag_shell.p, steepest.data(), S * sizeof(int));
+            launch_neg_masked(st, c->N, g, dptr<uint16_t>(c->freemask), dptr<int>(c->node_shell),
+                              dptr<int>(c->flag_shell), rhs);
+            launch_copy_shell(st, c->N, rhs, dptr<int>(c->node_shell), dptr<int>(c->flag_shell), d);
+            HIPCHK(hipGetLastError());
+        }
         for (int trial = 0; trial < 20; ++trial) {
             bool anys = false;
             for (int s = 0; s < S; ++s) anys |= searching[s] != 0;

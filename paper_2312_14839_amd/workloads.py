@@ -247,6 +247,26 @@ def case_compression(n: int = 64, seed: int = 5, pct_per_100: float = 1.0, dt: f
                 m["density"], (0.0, 0.0, 0.0), ref, fixed, q0, np.zeros_like(q0), dt, presc)
 
 
+def case_precompressed(n: int = 6, strain: float = 0.01, thickness: float = 0.02, dt: float = 1.0, seed: int = 11,
+                       sigma: float = 1e-4, young: float = 1e5, gravity=GRAVITY) -> Case:
+    """n x n sheet already shortened along x by ``strain`` (positions and
+    x-slopes scaled by 1 - strain), edges xi1 = 0 and xi1 = 1 clamped in that
+    state, gravity, N(0, sigma) out-of-plane perturbation of free nodes.
+    With a large time step the inertia no longer stabilises the compressed
+    membrane, so the Newton systems of its first steps are indefinite."""
+    rng = np.random.default_rng(seed)
+    ref = flat_sheet_ref(n, n)
+    q0 = ref.copy()
+    q0[:, 0] *= 1.0 - strain
+    q0[:, 3] *= 1.0 - strain
+    fixed = clamp_edges(n, n, ("x0", "x1"))
+    free = ~fixed.any(axis=1)
+    q0[free, 2] += rng.normal(0.0, sigma, size=int(free.sum()))
+    m = _material(young=young, thickness=thickness)
+    return Case(f"precompressed{n}x{n}", n, n, 0, 1.0 / n, 1.0 / n, m["young"], m["poisson"], m["thickness"],
+                m["density"], tuple(gravity), ref, fixed, q0, np.zeros_like(q0), dt)
+
+
 def case_random_load(n: int, seed: int, dt: float = 2e-3) -> Case:
     """The load mix of the learned warm start's evaluation: with probability
     1/2 a twist at omega ~ U[0.5, 2] rad/s about a random interior node,

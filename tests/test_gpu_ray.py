@@ -124,15 +124,18 @@ def test_scene_larger_than_lds(newton):
 
 
 @pytest.mark.parametrize("newton", [0, 8], ids=["midpoint", "newton"])
-def test_full_frame_sampled(newton):
-    """The bench's launch: 512 x 512 pixels x 16 samples of the cylinder."""
-    case = W.render_scene("cylinder")
+@pytest.mark.parametrize("scene", ["cylinder", "drape"])
+def test_full_frame_sampled(scene, newton):
+    """The bench's launch: 512 x 512 pixels x 16 samples of the cylinder
+    and of the drape, a sample of the rays and the 48 longest (finished by
+    the cooperative search) against the oracle."""
+    case = W.render_scene(scene)
     ctrl_o = _oracle_ctrl(case, case.ref)
     ctrl_g = _gpu_ctrl([case], [case.ref])
-    rays = W.camera_rays("cylinder", 512, 512, 16)
+    rays = W.camera_rays(scene, 512, 512, 16)
     hg, pg, pops = _cast(ctrl_g, rays, newton_iters=newton)
     assert (pg >= -1).all()
-    assert 0.3 < (pg >= 0).mean() < 0.9
+    assert 0.3 < (pg >= 0).mean() < 0.95
     idx = np.random.default_rng(33).choice(len(rays), 1500, replace=False)
     ho, po = R.ray_cast(ctrl_o, rays[idx], eps=EPS, newton_iters=newton)
     _compare(ctrl_o, rays[idx], hg[idx], pg[idx], ho, po)
@@ -187,6 +190,36 @@ def test_heap_capacity_status():
     _compare(ctrl_o, rays[ok], hg[ok], pg[ok], ho, po)
 
 
+def _two_layer_scene():
+    """Two copies of a 6x6 draped sheet, the second 3 cm lower and 10 cm to
+    the side (72 patches): rays grazing the upper sheet's folds pass close
+    to the lower one, and part of the lower sheet is in view."""
+    ref = W.height_field_ref(6, 6, W._drape, x0=-0.5, y0=-0.5)
+    low = ref.copy()
+    low[:, 0] += 0.1
+    low[:, 2] -= 0.03
+    case = W._scene_case("drape6", 6, 6, 0, 1 / 6, 1 / 6, ref)
+    return case, [ref, low]
+
+
+@pytest.mark.parametrize("newton", [0, 8], ids=["midpoint", "newton"])
+def test_cooperative_search_two_layers(newton):
+    """With room for four candidates on the lane almost every ray moves to
+    the cooperative search after a few candidates; on two stacked sheets it
+    must still return the nearer surface (in the midpoint form, the first
+    answer in key order over the whole search), as the oracle does."""
+    case, refs = _two_layer_scene()
+    ctrl_o = np.concatenate([_oracle_ctrl(case, r) for r in refs])
+    ctrl_g = _gpu_ctrl([case, case], refs)
+    rays = W.camera_rays("drape", 40, 40, 1, seed=35)
+    hg, pg, pops = _cast(ctrl_g, rays, newton_iters=newton, heap_cap=4)
+    ok = pg != -2
+    assert ok.mean() > 0.5
+    ho, po = R.ray_cast(ctrl_o, rays[ok], eps=EPS, newton_iters=newton)
+    assert (po >= 36).sum() > 20 and (po[po >= 0] < 36).sum() > 100   # both layers are hit
+    _compare(ctrl_o, rays[ok], hg[ok], pg[ok], ho, po)
+
+
 def test_user_stream():
     case = W.render_scene("drape")
     ctrl_g = _gpu_ctrl([case], [case.ref])
@@ -222,6 +255,13 @@ def _ccd_gpu(ctrl, vel, pts, dt, **kw):
     return hit.cpu().numpy(), patch.cpu().numpy(), pops.cpu().numpy()
 
 
+def _ccd_points(scene, n, seed=34):
+    pts = W.camera_rays(scene, n, n, 1, seed=seed)
+    pts[:, :3] += 1.0 * pts[:, 3:]          # start 1 m along the camera rays
+    pts[:, 3:] *= 3.0
+    return pts
+
+
 @pytest.mark.parametrize("newton", [0, 8], ids=["midpoint", "newton"])
 @pytest.mark.parametrize("scene", ["cylinder", "drape"])
 def test_ccd_matches_oracle(scene, newton):
@@ -230,15 +270,52 @@ def test_ccd_matches_oracle(scene, newton):
     ctrl_o, vel_o = _oracle_ctrl(case, case.ref), _oracle_ctrl(case, vq)
     ctrl_g, vel_g = _gpu_ctrl([case], [case.ref]), _gpu_ctrl([case], [vq])
     np.testing.assert_allclose(vel_g.cpu().numpy(), vel_o, rtol=0, atol=1e-14)
-    pts = W.camera_rays(scene, 40, 40, 1, seed=34)
-    pts[:, :3] += 1.0 * pts[:, 3:]          # start 1 m along the camera rays
-    pts[:, 3:] *= 3.0
+    pts = _ccd_points(scene, 40)
     dt = 0.5
     ho, po = R.ccd(ctrl_o, vel_o, pts, dt, eps=EPS, newton_iters=newton)
     hg, pg, _ = _ccd_gpu(ctrl_g, vel_g, pts, dt, newton_iters=newton)
     assert (pg >= -1).all()
-    assert ((pg >= 0) == (po >= 0)).all(), np.nonzero((pg >= 0) != (po >= 0))[0][:10]
     assert 0.1 < (po >= 0).mean() < 0.9
+    _compare_ccd(ctrl_o, vel_o, pts, hg, pg, ho, po, newton)
+
+
+@pytest.mark.parametrize("newton", [0, 8], ids=["midpoint", "newton"])
+def test_ccd_scene_larger_than_lds(newton):
+    """256 moving patches: the dynamic kernel reads positions and
+    velocities from global memory."""
+    case = W._scene_case("drape16", 16, 16, 0, 1 / 16, 1 / 16,
+                         W.height_field_ref(16, 16, W._drape, x0=-0.5, y0=-0.5))
+    vq = _rigid_velocity(case)
+    ctrl_o, vel_o = _oracle_ctrl(case, case.ref), _oracle_ctrl(case, vq)
+    ctrl_g, vel_g = _gpu_ctrl([case], [case.ref]), _gpu_ctrl([case], [vq])
+    pts = _ccd_points("drape", 32, seed=36)
+    ho, po = R.ccd(ctrl_o, vel_o, pts, 0.5, eps=EPS, newton_iters=newton)
+    hg, pg, _ = _ccd_gpu(ctrl_g, vel_g, pts, 0.5, newton_iters=newton)
+    assert (pg >= -1).all() and (po >= 0).mean() > 0.1
+    _compare_ccd(ctrl_o, vel_o, pts, hg, pg, ho, po, newton)
+
+
+@pytest.mark.parametrize("newton", [0, 8], ids=["midpoint", "newton"])
+def test_ccd_heap_capacity_status(newton):
+    """With room for one candidate on the lane, moving points whose path
+    meets two or more patch boxes have no room for their roots (status -2);
+    every other point moves to the cooperative search at once and matches
+    the oracle."""
+    case = W.render_scene("drape")
+    vq = _rigid_velocity(case)
+    ctrl_o, vel_o = _oracle_ctrl(case, case.ref), _oracle_ctrl(case, vq)
+    ctrl_g, vel_g = _gpu_ctrl([case], [case.ref]), _gpu_ctrl([case], [vq])
+    pts = _ccd_points("drape", 40, seed=37)
+    hg, pg, _ = _ccd_gpu(ctrl_g, vel_g, pts, 0.5, newton_iters=newton, heap_cap=1)
+    assert (pg == -2).sum() > 50 and np.isinf(hg[pg == -2, 0]).all()
+    ok = pg != -2
+    ho, po = R.ccd(ctrl_o, vel_o, pts[ok], 0.5, eps=EPS, newton_iters=newton)
+    assert (po >= 0).sum() > 50
+    _compare_ccd(ctrl_o, vel_o, pts[ok], hg[ok], pg[ok], ho, po, newton)
+
+
+def _compare_ccd(ctrl_o, vel_o, pts, hg, pg, ho, po, newton):
+    assert ((pg >= 0) == (po >= 0)).all(), np.nonzero((pg >= 0) != (po >= 0))[0][:10]
     for r in np.nonzero(po >= 0)[0]:
         t, u, v = ho[r]
         x, xu, xv = R.bezier_eval(ctrl_o[po[r]] + t * vel_o[po[r]], u, v)

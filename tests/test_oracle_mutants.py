@@ -21,6 +21,7 @@ from paper_2312_14839_amd import workloads as W
 
 import test_oracle_basis as TB
 import test_oracle_mechanics as TM
+import test_oracle_newton as TN
 import test_oracle_ray as TR
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -77,7 +78,30 @@ MUTANTS = [
      "J[c][2] = xv[c] - w[c];", "J[c][2] = xv[c];"),
     ("heap ordered by the far end of the box interval", "ray.cpp",
      "return a.tlo != b.tlo ? a.tlo > b.tlo : a.seq > b.seq;", "return a.thi != b.thi ? a.thi > b.thi : a.seq > b.seq;"),
+    ("regulariser: delta times the identity instead of diag(A)", "global.cpp",
+     "A.find(r, r)[13 * i] += (nd_ - delta) * diag[12 * r + i];", "A.find(r, r)[13 * i] += (nd_ - delta);"),
+    ("regulariser added to the first column instead of the diagonal", "global.cpp",
+     "A.find(r, r)[13 * i] += (nd_ - delta) * diag[12 * r + i];",
+     "A.find(r, r)[12 * i] += (nd_ - delta) * diag[12 * r + i];"),
+    ("line search: cubic step from the other root", "global.cpp",
+     "(-cb + std::sqrt(disc)) / (3.0 * ca)", "(-cb - std::sqrt(disc)) / (3.0 * ca)"),
+    ("line search: quadratic step without the factor 2", "global.cpp",
+     "a_new = -slope * alpha * alpha / (2.0 * (Et - E - slope * alpha));",
+     "a_new = -slope * alpha * alpha / (Et - E - slope * alpha);"),
+    ("pseudo Hessian drops the membrane geometric term instead of the bending one", [
+        ("patch.cpp", "for (int i = 0; i < 3; ++i) add_identity(d2al[i] * Ha[i], G1);",
+         "if (!pseudo) for (int i = 0; i < 3; ++i) add_identity(d2al[i] * Ha[i], G1);"),
+        ("patch.cpp", "                if (!pseudo) {\n                    for (int i = 0; i < 3; ++i) {",
+         "                if (true) {\n                    for (int i = 0; i < 3; ++i) {")]),
+    ("pseudo Hessian also drops the membrane geometric term", "patch.cpp",
+     "for (int i = 0; i < 3; ++i) add_identity(d2al[i] * Ha[i], G1);",
+     "if (!pseudo) for (int i = 0; i < 3; ++i) add_identity(d2al[i] * Ha[i], G1);"),
 ]
+
+
+def _sites(m):
+    """The (file, original, planted) edits of a mutant entry."""
+    return m[1] if len(m) == 2 else [(m[1], m[2], m[3])]
 
 
 def _pins():
@@ -101,6 +125,11 @@ def _pins():
     pins += [lambda n=n, f=f: f(n) for n in (0, 8) for f in
              (TR.test_ccd_translating_saddle_matches_the_closed_form, TR.test_ccd_of_resting_patches_is_the_static_ray_cast)]
     pins += [TR.test_ccd_misses_and_the_step_end]
+    pins += [TN.test_regulariser_solves_the_regularised_system_and_is_the_first_definite_step,
+             TN.test_line_search_trials_follow_armijo_and_the_interpolation_steps,
+             TN.test_iteration_cap_returns_the_last_iterate, TN.test_indefinite_beyond_the_regulariser_cap,
+             TN.test_pseudo_equals_exact_hessian_in_a_pure_membrane_state,
+             TN.test_pseudo_hessian_keeps_the_membrane_part_and_a_semidefinite_bending_part]
     rows = TB._golden("dof_counts.txt")
     pins += [lambda r=r: TB.test_printed_dof_and_nonzero_counts(r) for r in rows]
     return pins
@@ -111,8 +140,7 @@ def _build(tmp, name, mutation):
     os.makedirs(d)
     for f in SOURCES + HEADERS:
         shutil.copy(os.path.join(ORACLE, f), d)
-    if mutation is not None:
-        fname, old, new = mutation
+    for fname, old, new in (mutation or []):
         path = os.path.join(d, fname)
         text = open(path).read()
         assert text.count(old) >= 1, f"mutation site not found: {old!r}"
@@ -125,11 +153,19 @@ def _build(tmp, name, mutation):
 
 @contextlib.contextmanager
 def _using(path):
+    """Point the oracle module at the library at `path`, with few OpenMP
+    threads: the pins' grids are tiny, and per-column parallel regions of the
+    banded factorisation crawl when test workers oversubscribe the cores."""
+    import ctypes
     saved = O._lib
     O._lib = O._load(path)
+    omp = ctypes.CDLL("libgomp.so.1")
+    nthr = omp.omp_get_max_threads()
+    omp.omp_set_num_threads(2)
     try:
         yield
     finally:
+        omp.omp_set_num_threads(nthr)
         O._lib = saved
 
 
@@ -147,7 +183,7 @@ def _failures(lib_path):
 @pytest.fixture(scope="module")
 def built():
     tmp = tempfile.mkdtemp(prefix="orc_mut_")
-    jobs = [("clean", None)] + [(f"m{i}", (f, o, n)) for i, (_, f, o, n) in enumerate(MUTANTS)]
+    jobs = [("clean", None)] + [(f"m{i}", _sites(m)) for i, m in enumerate(MUTANTS)]
     with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
         paths = dict(zip([j[0] for j in jobs], ex.map(lambda j: _build(tmp, *j), jobs)))
     yield paths
