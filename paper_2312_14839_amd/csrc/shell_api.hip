@@ -1354,9 +1354,11 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
             launch_regularize(st, c->N, dptr<int>(c->diag_blk), c->vals.p, c->fp32, dptr<double>(c->diag0),
                               dptr<int>(c->node_shell), dptr<double>(c->delta_shell));
         };
-        auto bump = [&](int s) -> bool {   // next regulariser value; false at the cap
-            delta[s] = delta[s] == 0.0 ? 1e-6 : delta[s] * 10.0;
-            return delta[s] <= 1e2 * (1 + 1e-12);
+        auto bump = [&](int s) -> bool {   // next regulariser value; false past the cap (delta stays 1e2)
+            const double next = delta[s] == 0.0 ? 1e-6 : delta[s] * 10.0;
+            if (next > 1e2 * (1 + 1e-12)) return false;
+            delta[s] = next;
+            return true;
         };
         for (bool first = true;; first = false) {
             if (!first) bj_factor(c);
