@@ -380,6 +380,25 @@ void shell_ray_default_opts(shell_ray_opts *o);
 shell_status shell_ray_cast(const double *ctrl_dev, int32_t n_patches, const double *rays_dev, int64_t n_rays,
                             const shell_ray_opts *opts, double *hit_dev, int32_t *patch_dev, int32_t *pops_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * search as shell_ray_cast, with the same arguments, validation and
+ * results, except that rays go to the cooperative search through a fixed
+ * device buffer of the library instead of a per-call stream-ordered
+ * allocation.  The call allocates and frees nothing.
+ *   The buffer holds SHELL_RAY_NOALLOC_TAIL_RAYS handed-over rays (about
+ *   15 MiB of device memory, held on every device the library runs on until
+ *   the process ends); no input size is rejected for it: rays that find it
+ *   full report -2, as shell_ray_cast's do past its 16,384.  Its counter is
+ *   cleared by a kernel on opts->stream at the start of each call.
+ *   Every call on one device shares that device's buffer: calls that
+ *   overlap on one GPU (other streams, other threads) race and must be
+ *   serialised by the caller. */
+#define SHELL_RAY_NOALLOC_TAIL_RAYS 4096
+shell_status shell_ray_cast_noalloc(const double *ctrl_dev, int32_t n_patches, const double *rays_dev,
+                                    int64_t n_rays, const shell_ray_opts *opts, double *hit_dev,
+                                    int32_t *patch_dev, int32_t *pops_dev);
+
 /* Dynamic ray--patch intersection (Sec. 5.2): for each point moving as
  * x0 + t w over one step t in [0, dt], the earliest t at which it meets one
  * of the patches whose control points move as p + t v (Eq. ineqccd bounds

@@ -38,6 +38,7 @@ constexpr int RAY_MAX_POPS = 1 << 18;  // candidates one ray may examine
 constexpr int RAY_CHUNK_PER_LANE = 8;  // rays per block = 256 lanes x this
 constexpr int RAY_TAIL_BUDGET = 512;   // candidates before a ray goes to the cooperative search
 constexpr int RAY_TAIL_SLOTS = 16384;  // rays the cooperative search takes per launch
+constexpr int RAY_TAIL_STATIC_SLOTS = 4096;   // the same with the library's fixed buffer
 
 struct RayParams {
     double eps;          // a surface whose box diagonal is <= eps |d| ends the subdivision
@@ -50,8 +51,14 @@ struct RayParams {
 // hit: [n][3] tau, u, v; patch: [n] (-1 miss, -2 heap full or RAY_MAX_POPS
 // candidates examined, -3 invalid ray);
 // pops: [n] surfaces popped, may be null.
+// fixed_tail: NULL, or the device address of the library's fixed hand-over
+// buffer (ray_scratch_address): no allocation, room for RAY_TAIL_STATIC_SLOTS
+// handed-over rays
 void launch_ray_cast(hipStream_t st, const double* ctrl, int npatch, const double* rays, long long nrays,
-                     const RayParams& o, double* hit, int* patch, int* pops);
+                     const RayParams& o, double* hit, int* patch, int* pops, void* fixed_tail = nullptr);
+// Device address of the fixed hand-over buffer on `device`, which must be
+// the current device (looked up once per device, then cached).
+hipError_t ray_scratch_address(int device, void** out);
 // Moving point x0 + t w (pts: [n][6]) against patches with control points
 // ctrl + t vel over [0, dt]; hit: [n][3] t, u, v; statuses as above.
 void launch_ccd(hipStream_t st, const double* ctrl, const double* vel, int npatch, const double* pts,

@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "kernels.hpp"
 
@@ -1153,29 +1154,80 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_ray_tail(const double* __restr
 // zero the hand-over counter (a kernel, not a memset: safe in graphs)
 __global__ void k_zero_int(int* p) { *p = 0; }
 
-// Per-launch hand-over buffer of the cooperative search (stream-ordered
-// allocation); on failure every ray stays on its lane.
-static void* tail_setup(hipStream_t st, long long n, RayTail& tail) {
+// bytes of the hand-over buffer per ray: its record and its heap
+constexpr size_t TAIL_BYTES_PER_RAY =
+    sizeof(LongRay) + RAY_HEAP_MAX * (3 * sizeof(double) + 4 * sizeof(double) + sizeof(int));
+
+// Fixed hand-over buffer of the allocation-free ray cast: a counter line and
+// RAY_TAIL_STATIC_SLOTS rays (about 15 MiB, held by every device the library
+// runs on until the process ends).  Host code never passes this name to a
+// kernel: it stands for a host-side shadow there; the device address comes
+// from hipGetSymbolAddress (ray_scratch_address).
+constexpr size_t RAY_SCRATCH_BYTES = 256 + (size_t)RAY_TAIL_STATIC_SLOTS * TAIL_BYTES_PER_RAY;
+static __device__ __align__(256) unsigned char scratch[RAY_SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[SCRATCH_MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t ray_scratch_address(int device, void** out) {
+    *out = nullptr;
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;   // the caller makes `device` current first
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[device] = p;
+    }
+    *out = g_scratch_dev[device];
+    return hipSuccess;
+}
+
+// Lay the hand-over state of `cap` rays out in `buf` (>= 256 +
+// TAIL_BYTES_PER_RAY * cap bytes) and clear its counter on the stream.
+static void tail_carve(hipStream_t st, void* buf, int cap, RayTail& tail) {
+    char* b = (char*)buf;
+    tail.cap = cap;
+    tail.count = (int*)b;
+    tail.rays = (LongRay*)(b + 256);
+    tail.key = (double*)(tail.rays + tail.cap);
+    tail.thi = tail.key + (size_t)tail.cap * RAY_HEAP_MAX;
+    tail.rect = tail.thi + (size_t)tail.cap * RAY_HEAP_MAX;
+    tail.tag = (int*)(tail.rect + (size_t)tail.cap * RAY_HEAP_MAX * 4);
+    tail.budget = RAY_TAIL_BUDGET;
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, tail.count);
+}
+
+// The cooperative search needs more LDS than a launch gets by default.
+static bool tail_lds_ok() {
+    return hipFuncSetAttribute((const void*)k_ray_tail<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)TAIL_LDS) == hipSuccess &&
+           hipFuncSetAttribute((const void*)k_ray_tail<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)TAIL_LDS) == hipSuccess;
+}
+
+// Hand-over buffer of one launch: the caller's fixed buffer of `fixed_slots`
+// rays when `fixed` is given (nothing to free: returns NULL), else a
+// stream-ordered allocation (returned, to be freed after the tail kernel).
+// Without LDS or memory every ray stays on its lane.
+static void* tail_setup(hipStream_t st, long long n, RayTail& tail, void* fixed, int fixed_slots) {
     tail = RayTail{};
-    tail.cap = (int)std::min<long long>(n, RAY_TAIL_SLOTS);
     void* buf = nullptr;
-    // the cooperative search needs more LDS than a launch gets by default
-    const bool lds_ok =
-        hipFuncSetAttribute((const void*)k_ray_tail<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)TAIL_LDS) == hipSuccess &&
-        hipFuncSetAttribute((const void*)k_ray_tail<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)TAIL_LDS) == hipSuccess;
-    const size_t per = sizeof(LongRay) + RAY_HEAP_MAX * (3 * sizeof(double) + 4 * sizeof(double) + sizeof(int));
-    if (lds_ok && hipMallocAsync(&buf, 256 + per * tail.cap, st) == hipSuccess) {
-        char* b = (char*)buf;
-        tail.count = (int*)b;
-        tail.rays = (LongRay*)(b + 256);
-        tail.key = (double*)(tail.rays + tail.cap);
-        tail.thi = tail.key + (size_t)tail.cap * RAY_HEAP_MAX;
-        tail.rect = tail.thi + (size_t)tail.cap * RAY_HEAP_MAX;
-        tail.tag = (int*)(tail.rect + (size_t)tail.cap * RAY_HEAP_MAX * 4);
-        tail.budget = RAY_TAIL_BUDGET;
-        hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, tail.count);
+    const bool lds_ok = tail_lds_ok();
+    if (lds_ok && fixed) {
+        tail_carve(st, fixed, (int)std::min<long long>(n, fixed_slots), tail);
+        return nullptr;
+    }
+    const int cap = (int)std::min<long long>(n, RAY_TAIL_SLOTS);
+    if (lds_ok && hipMallocAsync(&buf, 256 + TAIL_BYTES_PER_RAY * cap, st) == hipSuccess) {
+        tail_carve(st, buf, cap, tail);
     } else {
         (void)hipGetLastError();
         buf = nullptr;
@@ -1186,12 +1238,12 @@ static void* tail_setup(hipStream_t st, long long n, RayTail& tail) {
 }
 
 void launch_ray_cast(hipStream_t st, const double* ctrl, int npatch, const double* rays, long long nrays,
-                     const RayParams& o, double* hit, int* patch, int* pops) {
+                     const RayParams& o, double* hit, int* patch, int* pops, void* fixed_tail) {
     if (nrays <= 0) return;
     const int chunk = 256 * RAY_CHUNK_PER_LANE;
     const unsigned nb = (unsigned)((nrays + chunk - 1) / chunk);
     RayTail tail;
-    void* buf = tail_setup(st, nrays, tail);
+    void* buf = tail_setup(st, nrays, tail, fixed_tail, RAY_TAIL_STATIC_SLOTS);
     if (npatch <= RAY_LDS_PATCHES) {
         const size_t lds = sizeof(double) * 54 * (size_t)npatch;
         hipLaunchKernelGGL(k_ray_cast<true>, dim3(nb), dim3(256), lds, st, ctrl, npatch, rays, nrays, chunk, o, tail,
@@ -1200,10 +1252,10 @@ void launch_ray_cast(hipStream_t st, const double* ctrl, int npatch, const doubl
         hipLaunchKernelGGL(k_ray_cast<false>, dim3(nb), dim3(256), 0, st, ctrl, npatch, rays, nrays, chunk, o, tail,
                            hit, patch, pops);
     }
-    if (buf) {
+    if (tail.cap > 0) {
         hipLaunchKernelGGL(k_ray_tail<false>, dim3((unsigned)std::min(tail.cap, 1024)), dim3(TAIL_THREADS), TAIL_LDS,
                            st, ctrl, nullptr, rays, 0.0, o, tail, hit, patch, pops);
-        (void)hipFreeAsync(buf, st);
+        if (buf) (void)hipFreeAsync(buf, st);
     }
 }
 
@@ -1212,7 +1264,7 @@ void launch_ccd(hipStream_t st, const double* ctrl, const double* vel, int npatc
     if (npts <= 0) return;
     const int chunk = 256 * RAY_CHUNK_PER_LANE;
     RayTail tail;
-    void* buf = tail_setup(st, npts, tail);
+    void* buf = tail_setup(st, npts, tail, nullptr, 0);
     const unsigned nb = (unsigned)((npts + chunk - 1) / chunk);
     const size_t lds = sizeof(double) * 96 * (size_t)npatch;
     if (npatch <= RAY_LDS_PATCHES &&
@@ -1225,10 +1277,10 @@ void launch_ccd(hipStream_t st, const double* ctrl, const double* vel, int npatc
         hipLaunchKernelGGL(k_ccd<false>, dim3(nb), dim3(256), 0, st, ctrl, vel, npatch, pts, npts, dt, chunk, o, tail,
                            hit, patch, pops);
     }
-    if (buf) {
+    if (tail.cap > 0) {
         hipLaunchKernelGGL(k_ray_tail<true>, dim3((unsigned)std::min(tail.cap, 1024)), dim3(TAIL_THREADS), TAIL_LDS,
                            st, ctrl, vel, pts, dt, o, tail, hit, patch, pops);
-        (void)hipFreeAsync(buf, st);
+        if (buf) (void)hipFreeAsync(buf, st);
     }
 }
 

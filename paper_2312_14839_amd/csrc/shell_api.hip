@@ -1595,9 +1595,18 @@ void shell_ray_default_opts(shell_ray_opts* o) {
     o->stream = nullptr;
 }
 
-shell_status shell_ray_cast(const double* ctrl_dev, int32_t n_patches, const double* rays_dev, int64_t n_rays,
-                            const shell_ray_opts* o, double* hit_dev, int32_t* patch_dev, int32_t* pops_dev) {
+}  // extern "C"
+
+namespace {
+
+// shell_ray_cast and shell_ray_cast_noalloc: the same validation and
+// kernels; `noalloc` hands rays over to the cooperative search through the
+// library's fixed device buffer instead of a stream-ordered allocation.
+shell_status ray_cast_impl(const double* ctrl_dev, int32_t n_patches, const double* rays_dev, int64_t n_rays,
+                           const shell_ray_opts* o, double* hit_dev, int32_t* patch_dev, int32_t* pops_dev,
+                           bool noalloc) {
     static_assert(SHELL_RAY_HEAP_MAX == RAY_HEAP_MAX, "heap size of the ABI and of the kernel");
+    static_assert(SHELL_RAY_NOALLOC_TAIL_RAYS == RAY_TAIL_STATIC_SLOTS, "fixed hand-over buffer of ABI and kernel");
     g_create_error.clear();
     auto bad = [](const char* m) {
         g_create_error = m;
@@ -1616,17 +1625,35 @@ shell_status shell_ray_cast(const double* ctrl_dev, int32_t n_patches, const dou
     if (o->max_depth < 1 || o->max_depth > RAY_MAX_DEPTH) return bad("max_depth must be in [1, 60]");
     if (o->heap_cap < 1 || o->heap_cap > RAY_HEAP_MAX) return bad("heap_cap must be in [1, SHELL_RAY_HEAP_MAX]");
     hipError_t e = hipSetDevice(o->device);
+    void* fixed_tail = nullptr;
+    if (e == hipSuccess && noalloc) e = ray_scratch_address(o->device, &fixed_tail);
     if (e == hipSuccess) {
         RayParams rp{o->eps, o->newton_tol, o->hole, o->newton_iters, o->max_depth, o->heap_cap};
         launch_ray_cast((hipStream_t)o->stream, ctrl_dev, n_patches, rays_dev, n_rays, rp, hit_dev, patch_dev,
-                        pops_dev);
+                        pops_dev, fixed_tail);
         e = hipGetLastError();
     }
     if (e != hipSuccess) {
-        g_create_error = std::string("HIP error in shell_ray_cast: ") + hipGetErrorString(e);
+        g_create_error = std::string("HIP error in ") + (noalloc ? "shell_ray_cast_noalloc: " : "shell_ray_cast: ") +
+                         hipGetErrorString(e);
         return SHELL_E_DEVICE;
     }
     return SHELL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+shell_status shell_ray_cast(const double* ctrl_dev, int32_t n_patches, const double* rays_dev, int64_t n_rays,
+                            const shell_ray_opts* o, double* hit_dev, int32_t* patch_dev, int32_t* pops_dev) {
+    return ray_cast_impl(ctrl_dev, n_patches, rays_dev, n_rays, o, hit_dev, patch_dev, pops_dev, false);
+}
+
+shell_status shell_ray_cast_noalloc(const double* ctrl_dev, int32_t n_patches, const double* rays_dev,
+                                    int64_t n_rays, const shell_ray_opts* o, double* hit_dev, int32_t* patch_dev,
+                                    int32_t* pops_dev) {
+    return ray_cast_impl(ctrl_dev, n_patches, rays_dev, n_rays, o, hit_dev, patch_dev, pops_dev, true);
 }
 
 shell_status shell_ccd(const double* ctrl_dev, const double* vel_dev, int32_t n_patches, const double* points_dev,

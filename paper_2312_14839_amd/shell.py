@@ -165,6 +165,8 @@ def _load():
     lib.shell_ray_default_opts.restype = None
     lib.shell_ray_cast.argtypes = [vp, C.c_int32, vp, C.c_int64, P(shell_ray_opts), vp, vp, vp]
     lib.shell_ray_cast.restype = C.c_int32
+    lib.shell_ray_cast_noalloc.argtypes = [vp, C.c_int32, vp, C.c_int64, P(shell_ray_opts), vp, vp, vp]
+    lib.shell_ray_cast_noalloc.restype = C.c_int32
     lib.shell_ccd.argtypes = [vp, vp, C.c_int32, vp, C.c_int64, C.c_double, P(shell_ray_opts), vp, vp, vp]
     lib.shell_ccd.restype = C.c_int32
     return lib
@@ -177,7 +179,8 @@ EXPORTED = ["shell_default_opts", "shell_create", "shell_destroy", "shell_last_e
             "shell_newton_step", "shell_timing_enable", "shell_timing_get", "shell_mlp_set_params",
             "shell_mlp_get_params", "shell_mlp_forward", "shell_mlp_loss_grad", "shell_mlp_train",
             "shell_mlp_record", "shell_mlp_recorded", "shell_autotune", "shell_set_nodal_forces",
-            "shell_point_load", "shell_bezier", "shell_ray_default_opts", "shell_ray_cast", "shell_ccd"]
+            "shell_point_load", "shell_bezier", "shell_ray_default_opts", "shell_ray_cast", "shell_ray_cast_noalloc",
+            "shell_ccd"]
 
 MLP_IN, MLP_HIDDEN, MLP_OUT = 36, 128, 12
 MLP_PARAMS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_OUT + MLP_OUT
@@ -383,17 +386,19 @@ def ray_opts(**kw) -> shell_ray_opts:
     return o
 
 
-def ray_cast(ctrl, rays, hit, patch, pops=None, stream=None, **kw):
-    """shell_ray_cast on device tensors: ctrl [P, 4, 4, 3] float64 (or None
-    for no patches), rays [n, 6] float64, hit [n, 3] float64, patch [n] int32,
-    pops [n] int32 or None; ``stream`` a hipStream_t handle (int) or None for
-    the null stream.  Keyword arguments set fields of shell_ray_opts."""
+def ray_cast(ctrl, rays, hit, patch, pops=None, stream=None, noalloc=False, **kw):
+    """shell_ray_cast (shell_ray_cast_noalloc if ``noalloc``) on device
+    tensors: ctrl [P, 4, 4, 3] float64 (or None for no patches), rays [n, 6]
+    float64, hit [n, 3] float64, patch [n] int32, pops [n] int32 or None;
+    ``stream`` a hipStream_t handle (int) or None for the null stream.
+    Keyword arguments set fields of shell_ray_opts."""
     o = ray_opts(**kw)
     o.device = rays.device.index or 0
     o.stream = C.c_void_p(stream)  # None: the null stream
     n_patches = ctrl.shape[0] if ctrl is not None else 0
-    rc = lib.shell_ray_cast(_ptr(ctrl) if n_patches else None, n_patches, _ptr(rays), rays.shape[0], C.byref(o),
-                            _ptr(hit), _ptr(patch), _ptr(pops))
+    fn = lib.shell_ray_cast_noalloc if noalloc else lib.shell_ray_cast
+    rc = fn(_ptr(ctrl) if n_patches else None, n_patches, _ptr(rays), rays.shape[0], C.byref(o),
+            _ptr(hit), _ptr(patch), _ptr(pops))
     if rc != SHELL_OK:
         raise ShellError(rc, lib.shell_last_error(None).decode())
 
