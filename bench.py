@@ -152,27 +152,29 @@ def qstate_after(case, precision, nsteps, stream, tol):
 
 
 def cg_resident(layout, fp32):
-    """Whether the CG ran its register-resident instance: blocks of at most
-    4 (FP64 matrix, <= 512 threads) or 2 row passes of threads/64 x 10 rows."""
+    """Whether the CG ran its resident instance (its own rows' vectors in
+    registers and LDS): blocks of at most 4 (FP64 matrix, <= 512 threads;
+    none at 1024) or 2 (FP32) row passes of threads/64 x 10 rows."""
     if not layout:
         return False
-    maxp = 4 if (not fp32 and layout["threads"] <= 512) else 2
+    maxp = (4 if layout["threads"] <= 512 else 0) if not fp32 else 2
     return layout["rows_per_block"] <= maxp * (layout["threads"] // 64) * 10
 
 
 def cg_bytes(case, timing, tm_bytes, tv_bytes, resident):
-    """Algorithmic HBM bytes of the CG kernel.  Per iteration: every stored
-    block (the upper-triangle blocks: 144 values, a column and a slot index,
-    and the 12-value transposed product written to its slot in phase A and
-    read back in phase B; the diagonal blocks, symmetric: 84 values); per
-    node row its inverse diagonal block (symmetric, 84 stored values), the
-    row pointer, slot range and free mask (10 bytes) and the passes over
-    12-vectors: with the register-resident instance 5 (phase A reads z,
-    p_old and writes p_new; phase B reads p_new and writes z), else 11 (also
-    u written and read, r and x read and written)."""
+    """Algorithmic HBM bytes of the CG kernel (single-reduction form).  Per
+    iteration: every stored block (the upper-triangle blocks: 144 values, a
+    column and a slot index, and the 12-value transposed product written to
+    its slot by the product phase and read back by the update phase; the
+    diagonal blocks, symmetric: 84 values); per node row its inverse
+    diagonal block (symmetric, 84 stored values), the row pointer, slot range
+    and free mask (10 bytes) and the passes over 12-vectors: with the
+    resident instance 3 (the update reads the old u and writes the new one,
+    the product reads it), else 13 (also r, x, p and s read and written, the
+    stored part of w written and read)."""
     blocks = timing["cg_iter_blocks"]
     rows = timing["cg_iter_rows"]
-    vec = 5 if resident else 11
+    vec = 3 if resident else 13
     return ((blocks - rows) * (144 * tm_bytes + 8 + 24 * tv_bytes)
             + rows * (84 * tm_bytes + 84 * tv_bytes + 10 + vec * 12 * tv_bytes))
 

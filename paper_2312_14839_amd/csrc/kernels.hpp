@@ -75,6 +75,7 @@ struct RowBlocks {
     const int* blk_row1;     // [nblk]
     const int* shell_blk0;   // [nshell]
     const int* shell_nblk;   // [nshell]
+    const int* blk_nbhi;     // [nblk] highest block of the shell owning a column of this block's stored blocks
 };
 
 struct CgShellOut {
@@ -143,12 +144,15 @@ void launch_save_diag(hipStream_t st, int nnodes, const int* diag_blk, const voi
 void launch_regularize(hipStream_t st, int nnodes, const int* diag_blk, void* vals, int vals_fp32,
                        const double* diag, const int* node_shell, const double* delta_shell);
 
-// Persistent block-Jacobi CG; nthreads is 256, 512 or 1024 per block.
+// Persistent block-Jacobi CG (single-reduction form); nthreads is 256, 512
+// or 1024 per block.  x, r, u, p, s, w: [nnodes][12] work vectors (x the
+// solution); nbflag: [nblk][32] neighbour-sync flags, zeroed before launch.
 template <class TM, class TV>
 hipError_t launch_cg(hipStream_t st, int nblk, int nthreads, const RowBlocks& rb, const SymBsr& m, const TM* vals,
-                     const TV* dinv, const uint16_t* freemask, const double* b, TV* x, TV* r, TV* z, TV* p0, TV* p1,
-                     TV* qv, TV* slot, double* partial /* [2][nblk][4] */, void* sync, int* abort_flag, const double* rtol2_shell,
-                     const int* maxit_shell, const int* active_shell, CgShellOut* out);
+                     const TV* dinv, const uint16_t* freemask, const double* b, TV* x, TV* r, TV* u, TV* p, TV* s,
+                     TV* w, TV* slot, double* partial /* [2][nblk][4] */, void* sync, unsigned* nbflag,
+                     int* abort_flag, const double* rtol2_shell, const int* maxit_shell, const int* active_shell,
+                     CgShellOut* out);
 int cg_max_blocks(int device, int tm_fp32, int nthreads);   // co-resident blocks of the CG kernel
 size_t cg_sync_bytes();                                     // per-shell synchronisation state of the CG kernel
 int cg_rows_per_pass(int tm_fp32, int nthreads);            // node rows one CG block covers per pass

@@ -63,7 +63,7 @@ struct shell_ctx {
     DevBuf patch_kid;     // [P] uint64 local block index of each stored local block (4 bits each)
     DevBuf shells_d, phi, qbar, freemask, node_shell, patch_nodes, patch_shell, patch_slots, colour_list, inc_ptr,
         inc, row_ptr, col_idx, tslot, lptr, diag_blk, vals, slot, diag0, dinv;
-    DevBuf blk_shell, blk_row0, blk_row1, shell_blk0, shell_nblk;
+    DevBuf blk_shell, blk_row0, blk_row1, shell_blk0, shell_nblk, blk_nbhi, cg_nbflag;
     DevBuf e_patch, g_patch, e_shell, red_part, red_out;
     // Newton / CG work vectors (FP64 [N*12] unless noted)
     DevBuf qhat, q, qt, g, gt, dvec, rhs, cg_x, cg_r, cg_z, cg_p0, cg_p1, cg_q, r64, x64;
@@ -124,7 +124,7 @@ struct shell_ctx {
 
     RowBlocks rb() {
         return RowBlocks{nblk, cg_resident ? cg_max_rows : INT32_MAX, dptr<int>(blk_shell), dptr<int>(blk_row0),
-                         dptr<int>(blk_row1), dptr<int>(shell_blk0), dptr<int>(shell_nblk)};
+                         dptr<int>(blk_row1), dptr<int>(shell_blk0), dptr<int>(shell_nblk), dptr<int>(blk_nbhi)};
     }
     ~shell_ctx() {
         graphs_reset();
@@ -317,6 +317,21 @@ bool set_row_blocks(shell_ctx* c, int nt, int spread) {
         }
         used += nb;
     }
+    // per block, the last block whose rows its stored (upper-triangle)
+    // blocks reach: the CG's neighbour sync waits for blocks k+1 .. nbhi[k]
+    std::vector<int> nbhi(used);
+    {
+        std::vector<int> row_blk(N);
+        for (int k = 0; k < used; ++k)
+            for (int rr = brow0[k]; rr < brow1[k]; ++rr) row_blk[rr] = k;
+        for (int k = 0; k < used; ++k) {
+            int hi = k;
+            for (int rr = brow0[k]; rr < brow1[k]; ++rr)
+                for (int e = c->h_row_ptr[rr]; e < c->h_row_ptr[rr + 1]; ++e)
+                    hi = std::max(hi, row_blk[c->h_col_idx[e]]);
+            nbhi[k] = hi;
+        }
+    }
     hipStream_t st = c->stream;
     c->nblk = used;
     c->cg_max_rows = 0;
@@ -328,6 +343,8 @@ bool set_row_blocks(shell_ctx* c, int nt, int spread) {
     upload(c->blk_row1, brow1, st);
     upload(c->shell_blk0, c->h_shell_blk0, st);
     upload(c->shell_nblk, c->h_shell_nblk, st);
+    upload(c->blk_nbhi, nbhi, st);
+    alloc(c->cg_nbflag, (size_t)c->nblk * 32 * sizeof(unsigned));
     alloc(c->red_part, (size_t)c->nblk * sizeof(double));
     alloc(c->cg_partial, (size_t)c->nblk * 8 * sizeof(double));   // [2][nblk][4]: by barrier parity
     alloc(c->feat_part, (size_t)c->nblk * 12 * sizeof(double));
@@ -698,6 +715,7 @@ void cg_launch(shell_ctx* c, const double* b, const std::vector<int>& active, co
     run_graph(c, c->g_cg, (double)(uintptr_t)b, [&] {
     hipStream_t st = c->stream;
     launch_zero(st, c->cg_bar.p, c->cg_bar.n);
+    launch_zero(st, c->cg_nbflag.p, c->cg_nbflag.n);
     launch_zero(st, c->cg_abort.p, c->cg_abort.n);
     GroupTimer tmr(c, SHELL_T_CG);
     hipError_t e;
@@ -706,7 +724,8 @@ void cg_launch(shell_ctx* c, const double* b, const std::vector<int>& active, co
                                     dptr<float>(c->dinv), dptr<uint16_t>(c->freemask), b,
                                     dptr<float>(c->cg_x), dptr<float>(c->cg_r), dptr<float>(c->cg_z),
                                     dptr<float>(c->cg_p0), dptr<float>(c->cg_p1), dptr<float>(c->cg_q),
-                                    dptr<float>(c->slot), dptr<double>(c->cg_partial), c->cg_bar.p, dptr<int>(c->cg_abort),
+                                    dptr<float>(c->slot), dptr<double>(c->cg_partial), c->cg_bar.p,
+                                    dptr<unsigned>(c->cg_nbflag), dptr<int>(c->cg_abort),
                                     dptr<double>(c->cg_rtol2), dptr<int>(c->cg_maxit), dptr<int>(c->cg_active),
                                     dptr<CgShellOut>(c->cg_out));
     else
@@ -714,7 +733,8 @@ void cg_launch(shell_ctx* c, const double* b, const std::vector<int>& active, co
                                       dptr<double>(c->dinv), dptr<uint16_t>(c->freemask), b,
                                       dptr<double>(c->cg_x), dptr<double>(c->cg_r), dptr<double>(c->cg_z),
                                       dptr<double>(c->cg_p0), dptr<double>(c->cg_p1), dptr<double>(c->cg_q),
-                                      dptr<double>(c->slot), dptr<double>(c->cg_partial), c->cg_bar.p, dptr<int>(c->cg_abort),
+                                      dptr<double>(c->slot), dptr<double>(c->cg_partial), c->cg_bar.p,
+                                      dptr<unsigned>(c->cg_nbflag), dptr<int>(c->cg_abort),
                                       dptr<double>(c->cg_rtol2), dptr<int>(c->cg_maxit), dptr<int>(c->cg_active),
                                       dptr<CgShellOut>(c->cg_out));
     HIPCHK(e);

@@ -561,37 +561,82 @@ __device__ __forceinline__ bool reduce_barrier(ShellSync* ss, double* __restrict
 }
 
 // ---------------------------------------------------- persistent CG
-// Block-Jacobi preconditioned CG for every shell at once.  Each shell owns a
-// contiguous set of blocks and node rows; the only synchronisation is the
-// per-shell reduce-barrier (two per iteration).  p is double-buffered so that
-// the update p = z + beta p is fused into the matrix product:
-//   phase A: p_new = z + beta p_old (own rows); the stored blocks give
-//            u = (A_ii p_i + sum_{j>i} A_ij p_j) and A_ji p_i into the
-//            slots; p^T A p = sum_i (2 p_i.u_i - p_i^T A_ii p_i)
-//   phase B: q = u + own slots (masked), x += alpha p, r -= alpha q,
-//            z = Dinv r, sums r.z and r.r
+// Block-Jacobi preconditioned CG for every shell at once, in the
+// single-reduction form of Chronopoulos and Gear: the matrix product is
+// applied to the preconditioned residual u = Dinv r instead of to the
+// search direction, and A p is carried along by its own recurrence, so the
+// three scalars an iteration needs -- gamma = r.u, delta = u.A u and r.r --
+// are ready together and one reduce-barrier per iteration suffices:
+//   phase 1 (own rows; alpha, beta from the last barrier):
+//            w = (stored part of A u) + own slots (masked),
+//            p = u + beta p,  s = w + beta s   (s = A p),
+//            x += alpha p,  r -= alpha s,  u = Dinv r (masked);
+//            partial sums r.u and r.r
+//   neighbour sync: every block waits for the blocks whose rows its stored
+//            blocks reach (the blocks above it) to finish phase 1, so the
+//            u it reads is new and the slots it writes have been read
+//   phase 2: the stored blocks give the product of u (this lane's rows) and
+//            A_ji u_i into the slots; u.A u = sum_i (2 u_i.w_i - u_i^T A_ii u_i)
+//   reduce-barrier (gamma, delta, r.r): beta = gamma / gamma_old,
+//            alpha = gamma / (delta - beta gamma / alpha_old), the last
+//            denominator being p^T A p (<= 0: the system is not positive
+//            definite).
+// In exact arithmetic these are the iterates of the standard method; the
+// neighbour sync replaces the second grid-wide barrier of that method (a
+// wait on two or three blocks instead of every block of the shell), and the
+// product reads one gathered vector (u) where the fused standard form read
+// two (z and the old p).
 // A lane handles the same node rows (one per pass over the block's rows) in
-// every phase.  With MAXP > 0 the block has at most MAXP passes and u, r and
-// x of the lane's rows stay in registers for the whole solve (x is written
-// once at the end): only p, z and the slots, which other rows read, go
-// through memory.  Writes mixed into an HBM-bound read stream cost several
-// times their share of the bytes (measured: 25 MB of slot stores added to a
-// 379 MB block stream cost as much as 100 MB more of reads), so keeping
-// these three vectors resident saves more than their bytes.  MAXP = 0: any
-// number of passes, u, r and x in memory.  Odd iterations take a block's
-// passes last to first, so each phase starts on the rows the same phase of
-// the previous iteration read last, the ones most likely still in the L2
-// and memory-side caches (FP64 on the 256x256 cylinder: 128 -> 118.5 us per
-// iteration).
+// every phase.  With MAXP > 0 the block has at most MAXP passes and r, x,
+// p, s and the stored part of w of the lane's rows stay in registers for
+// the whole solve (x is written once at the end): only u and the slots,
+// which other rows read, go through memory.  Writes mixed into an
+// HBM-bound read stream cost several times their share of the bytes, so
+// keeping these vectors resident saves more than their bytes.  MAXP = 0:
+// any number of passes, the vectors in memory (r, x, p, s, w).  Odd
+// iterations take a block's passes last to first, so each phase starts on
+// the rows the same phase of the previous iteration touched last, the ones
+// most likely still cached.
+
+// Publish this block's writes of the phase just ended and wait until the
+// blocks blk+1 .. hi of the same shell have published theirs (flag value k,
+// monotone).  Bounded like reduce_barrier.
+__device__ __forceinline__ bool neighbour_sync(unsigned* __restrict__ flags, int blk, int hi, unsigned k,
+                                               int* abort_flag) {
+    __shared__ int s_nok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(&flags[32 * (size_t)blk], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int ok = 1;
+        unsigned spins = 0;
+        for (int b2 = blk + 1; b2 <= hi && ok; ++b2)
+            while (__hip_atomic_load(&flags[32 * (size_t)b2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < k) {
+                if ((++spins & 31u) == 0 &&
+                    (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || spins > (1u << 22))) {
+                    __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        if (ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s_nok = ok;
+    }
+    __syncthreads();
+    return s_nok != 0;
+}
+
 template <class TM, class TV, int NT, int MAXP>
 __global__ __launch_bounds__(NT) void k_cg(
     const int* __restrict__ blk_shell, const int* __restrict__ blk_row0, const int* __restrict__ blk_row1,
-    const int* __restrict__ shell_blk0, const int* __restrict__ shell_nblk, SymBsr m,
+    const int* __restrict__ shell_blk0, const int* __restrict__ shell_nblk, const int* __restrict__ blk_nbhi, SymBsr m,
     const TM* __restrict__ vals, const TV* __restrict__ dinv, const uint16_t* __restrict__ fm,
-    const double* __restrict__ b, TV* __restrict__ x, TV* __restrict__ r, TV* __restrict__ z, TV* __restrict__ p0,
-    TV* __restrict__ p1, TV* __restrict__ qv, TV* __restrict__ slot, double* __restrict__ partial,
-    ShellSync* __restrict__ sync, int* __restrict__ abort_flag, const double* __restrict__ rtol2_shell,
-    const int* __restrict__ maxit_shell, const int* __restrict__ active_shell, CgShellOut* __restrict__ out) {
+    const double* __restrict__ b, TV* __restrict__ x, TV* __restrict__ r, TV* __restrict__ u, TV* __restrict__ p,
+    TV* __restrict__ s, TV* __restrict__ w, TV* __restrict__ slot, double* __restrict__ partial,
+    ShellSync* __restrict__ sync, unsigned* __restrict__ nbflag, int* __restrict__ abort_flag,
+    const double* __restrict__ rtol2_shell, const int* __restrict__ maxit_shell, const int* __restrict__ active_shell,
+    CgShellOut* __restrict__ out) {
     constexpr int R = Lay<TM>::R, L = Lay<TM>::L, G = Lay<TM>::G;
     constexpr int NW = NT / 64;
     constexpr int NP = MAXP > 0 ? MAXP : 1;   // register-resident passes
@@ -602,13 +647,14 @@ __global__ __launch_bounds__(NT) void k_cg(
     const int sh = blk_shell[blk];
     const int row0 = blk_row0[blk], row1 = blk_row1[blk];
     const int sb0 = shell_blk0[sh], snb = shell_nblk[sh];
+    const int nbhi = blk_nbhi[blk];
     ShellSync* ss = sync + sh;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int grp = lane / L, t = lane % L;
     const bool lane_ok = grp < G;
     const int gsrc = lane_ok ? lane - t : 0;   // first lane of this lane's group
     const int rows_per_pass = NW * G;
-    unsigned nbar = 0;
+    unsigned nbar = 0, nnb = 0;
     const bool leader = blk == sb0 && threadIdx.x == 0;
 
     if (!active_shell[sh]) {
@@ -617,53 +663,73 @@ __global__ __launch_bounds__(NT) void k_cg(
         return;
     }
 
-    // Resident r, x, u of the lane's rows (MAXP > 0): entry 0 belongs to the
-    // current pass; after every pass (taken or not) the arrays rotate by one,
-    // so the loop body is emitted once and indexes its registers statically.
-    TV rk[NP][R], xk[NP][R], uk[NP][R];
-    auto rotate = [&]() {
+    // Resident vectors of the lane's rows (MAXP > 0): r and w in registers,
+    // x, p and s (each touched once per iteration) in LDS, which leaves the
+    // registers the product needs.  Entry 0 of each register array belongs
+    // to the current pass; after every pass (taken or not) the arrays rotate
+    // by one, so the loop body is emitted once and indexes its registers
+    // statically.  Register order: r, w.
+    constexpr int NV = 2;
+    TV res[NV][NP][R];
+    constexpr int LROWS = MAXP > 0 ? MAXP * NW * G : 1;
+    __shared__ TV xres[LROWS * 12], pres[LROWS * 12], sres[LROWS * 12];
+    auto rotate = [&](bool back) {
 #pragma unroll
-        for (int i = 0; i < R; ++i) {
-            const TV r0 = rk[0][i], x0 = xk[0][i], u0 = uk[0][i];
+        for (int v = 0; v < NV; ++v)
 #pragma unroll
-            for (int q = 0; q + 1 < NP; ++q) {
-                rk[q][i] = rk[q + 1][i];
-                xk[q][i] = xk[q + 1][i];
-                uk[q][i] = uk[q + 1][i];
+            for (int i = 0; i < R; ++i) {
+                if (back) {
+                    const TV e = res[v][NP - 1][i];
+#pragma unroll
+                    for (int q = NP - 1; q > 0; --q) res[v][q][i] = res[v][q - 1][i];
+                    res[v][0][i] = e;
+                } else {
+                    const TV e = res[v][0][i];
+#pragma unroll
+                    for (int q = 0; q + 1 < NP; ++q) res[v][q][i] = res[v][q + 1][i];
+                    res[v][NP - 1][i] = e;
+                }
             }
-            rk[NP - 1][i] = r0;
-            xk[NP - 1][i] = x0;
-            uk[NP - 1][i] = u0;
-        }
-    };
-    auto rotate_back = [&]() {
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            const TV r0 = rk[NP - 1][i], x0 = xk[NP - 1][i], u0 = uk[NP - 1][i];
-#pragma unroll
-            for (int q = NP - 1; q > 0; --q) {
-                rk[q][i] = rk[q - 1][i];
-                xk[q][i] = xk[q - 1][i];
-                uk[q][i] = uk[q - 1][i];
-            }
-            rk[0][i] = r0;
-            xk[0][i] = x0;
-            uk[0][i] = u0;
-        }
     };
     // runs f(base) over the block's passes, last pass first if rev
     auto passes = [&](auto&& f, bool rev = false) {
         if constexpr (MAXP > 0) {
 #pragma unroll 1
             for (int i = 0; i < MAXP; ++i) {
-                if (rev) rotate_back();
+                if (rev) rotate(true);
                 const int base = row0 + (rev ? MAXP - 1 - i : i) * rows_per_pass;
                 if (base < row1) f(base);
-                if (!rev) rotate();
+                if (!rev) rotate(false);
             }
         } else {
             const int np = (row1 - row0 + rows_per_pass - 1) / rows_per_pass;
             for (int i = 0; i < np; ++i) f(row0 + (rev ? np - 1 - i : i) * rows_per_pass);
+        }
+    };
+    // vector v (0 r, 1 x, 2 p, 3 s, 4 w) of this lane's entry i of the pass
+    // starting at row `base` (global entry `at`)
+    TV* const vmem[5] = {r, x, p, s, w};
+    auto lds_at = [&](int base, int i) {
+        return (size_t)(((base - row0) / rows_per_pass) * NW * G + wv * G + grp) * 12 + R * t + i;
+    };
+    auto vget = [&](int v, int base, size_t at, int i) -> TV {
+        if constexpr (MAXP > 0) {
+            if (v == 1) return xres[lds_at(base, i)];
+            if (v == 2) return pres[lds_at(base, i)];
+            if (v == 3) return sres[lds_at(base, i)];
+            return res[v == 0 ? 0 : 1][0][i];
+        } else {
+            return vmem[v][at];
+        }
+    };
+    auto vset = [&](int v, int base, size_t at, int i, TV val) {
+        if constexpr (MAXP > 0) {
+            if (v == 1) xres[lds_at(base, i)] = val;
+            else if (v == 2) pres[lds_at(base, i)] = val;
+            else if (v == 3) sres[lds_at(base, i)] = val;
+            else res[v == 0 ? 0 : 1][0][i] = val;
+        } else {
+            vmem[v][at] = val;
         }
     };
 
@@ -679,7 +745,7 @@ __global__ __launch_bounds__(NT) void k_cg(
         t = lane % t;
         asm volatile("" : "+v"(t));
         const TV* dn = dinv + (size_t)node * SYM12_VALS;
-        TV m[6][4];
+        TV mm[6][4];
         TV s0 = TV(0), s1 = TV(0);
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
@@ -688,28 +754,54 @@ __global__ __launch_bounds__(NT) void k_cg(
                 __builtin_amdgcn_sched_barrier(0);
                 if (k == 0) {
 #pragma unroll
-                    for (int h = 0; h < 3; ++h) Vec4<TV>::ld(dn + 12 * t + 4 * h, m[h]);   // (t, t+h)
+                    for (int h = 0; h < 3; ++h) Vec4<TV>::ld(dn + 12 * t + 4 * h, mm[h]);   // (t, t+h)
                 } else {
-                    Vec4<TV>::ld(dn + 72 + 4 * (t % 3), m[3]);         // (t, t+3), transposed for t >= 3
-                    Vec4<TV>::ld(dn + 12 * ((t + 4) % 6) + 8, m[4]);   // (t-2, t), transposed
-                    Vec4<TV>::ld(dn + 12 * ((t + 5) % 6) + 4, m[5]);   // (t-1, t), transposed
+                    Vec4<TV>::ld(dn + 72 + 4 * (t % 3), mm[3]);         // (t, t+3), transposed for t >= 3
+                    Vec4<TV>::ld(dn + 12 * ((t + 4) % 6) + 8, mm[4]);   // (t-2, t), transposed
+                    Vec4<TV>::ld(dn + 12 * ((t + 5) % 6) + 4, mm[5]);   // (t-1, t), transposed
                 }
             }
             const int src = gsrc + (t + k) % 6;
             const TV r0 = __shfl(rr[0], src), r1 = __shfl(rr[1], src);
             const bool tr = k >= 4 || (k == 3 && t >= 3);
-            const TV m01 = tr ? m[k][2] : m[k][1], m10 = tr ? m[k][1] : m[k][2];
-            s0 += m[k][0] * r0;
+            const TV m01 = tr ? mm[k][2] : mm[k][1], m10 = tr ? mm[k][1] : mm[k][2];
+            s0 += mm[k][0] * r0;
             s0 += m01 * r1;
             s1 += m10 * r0;
-            s1 += m[k][3] * r1;
+            s1 += mm[k][3] * r1;
         }
         zz[0] = s0;
         zz[1] = s1;
     };
 
-    // ---- init: r = b (masked), x = 0, p_old = 0, z = Dinv r; sums r.z and b.b
-    double sums[2] = {0.0, 0.0};
+    // phase 2: the product of u over the lane's rows: w (stored part) and
+    // the slots; returns the block-lane's share of u.A u
+    auto product = [&](bool rev) {
+        double uau = 0.0;
+        passes([&](int base) {
+            const int node = base + wv * G + grp;
+            if (!(lane_ok && node < row1)) return;
+            auto xe = [&](int col, TV* xv) {
+#pragma unroll
+                for (int i = 0; i < R; ++i) xv[i] = u[(size_t)col * 12 + R * t + i];
+            };
+            TV un[R], part[12], wr[R];
+            xe(node, un);
+            const TV dl = row_sym<TM, TV, false, sizeof(TM) == 8 ? 12 : 4>(m, vals, node, t, un, xe,
+                                                                          xls[wv] + grp * 12, slot, part);
+            group_sum<TV, R, L>(part, lane, t, gsrc, red[wv], wr);
+            uau -= (double)dl;
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                vset(4, base, (size_t)node * 12 + R * t + i, i, wr[i]);
+                uau += 2.0 * (double)un[i] * (double)wr[i];
+            }
+        }, rev);
+        return uau;
+    };
+
+    // ---- init: r = b (masked), x = p = s = 0, u = Dinv r; sums r.u and b.b
+    double sums[3] = {0.0, 0.0, 0.0};
     passes([&](int base) {
         const int node = base + wv * G + grp;
         const bool ok = lane_ok && node < row1;
@@ -717,161 +809,136 @@ __global__ __launch_bounds__(NT) void k_cg(
         TV rr[R], zz[R];
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-            const int w = R * t + i;
-            rr[i] = ok && is_free(fm, node, w) ? (TV)b[(size_t)node * 12 + w] : TV(0);
+            const int wd = R * t + i;
+            rr[i] = ok && is_free(fm, node, wd) ? (TV)b[(size_t)node * 12 + wd] : TV(0);
         }
         precond(nd, rr, zz);
-        if (ok) {
 #pragma unroll
-            for (int i = 0; i < R; ++i) {
-                const int w = R * t + i;
-                const size_t at = (size_t)node * 12 + w;
-                if (!is_free(fm, node, w)) zz[i] = TV(0);
-                if constexpr (MAXP > 0) {
-                    rk[0][i] = rr[i];
-                    xk[0][i] = TV(0);
-                } else {
-                    r[at] = rr[i];
-                }
-                z[at] = zz[i];
-                x[at] = TV(0);
-                p0[at] = TV(0);
-                sums[0] += (double)rr[i] * (double)zz[i];
-                sums[1] += (double)rr[i] * (double)rr[i];
-            }
+        for (int i = 0; i < R; ++i) {
+            const int wd = R * t + i;
+            const size_t at = (size_t)nd * 12 + wd;
+            if (!ok) continue;
+            if (!is_free(fm, node, wd)) zz[i] = TV(0);
+            vset(0, base, at, i, rr[i]);
+            vset(1, base, at, i, TV(0));
+            vset(2, base, at, i, TV(0));
+            vset(3, base, at, i, TV(0));
+            u[at] = zz[i];
+            sums[0] += (double)rr[i] * (double)zz[i];
+            sums[2] += (double)rr[i] * (double)rr[i];
         }
     });
-    if (!reduce_barrier<2, NW>(ss, partial, blk, sb0, snb, nbar++, sums, abort_flag, lds)) {
+    int it = 0, status = 1;
+    if (!neighbour_sync(nbflag, blk, nbhi, ++nnb, abort_flag)) {
         if (leader) out[sh] = CgShellOut{0, 3, 0.0, 0.0};
         return;
     }
-    double rz = sums[0];
-    const double bb = sums[1];
+    sums[1] = product(false);
+    if (!reduce_barrier<3, NW>(ss, partial, blk, sb0, snb, nbar++, sums, abort_flag, lds)) {
+        if (leader) out[sh] = CgShellOut{0, 3, 0.0, 0.0};
+        return;
+    }
+    double gamma = sums[0];
+    const double bb = sums[2];
     const double tol2 = rtol2_shell[sh] * bb;
     const int maxit = maxit_shell[sh];
     if (bb == 0.0) {
         if (leader) out[sh] = CgShellOut{0, 0, 0.0, 0.0};
         return;
     }
-    double beta = 0.0;
-    TV* pin = p0;
-    TV* pout = p1;
-    int it = 0, status = 1;
     double rr2 = bb;
-    for (; it < maxit; ++it) {
-        // ---- phase A
-        double pq[1] = {0.0};
-        passes([&](int base) {
-            const int node = base + wv * G + grp;
-            if (!(lane_ok && node < row1)) return;
-            const TV bt = (TV)beta;
-            auto xe = [&](int col, TV* xv) {
+    double alpha = 0.0, beta = 0.0;
+    if (!(sums[1] > 0.0)) {
+        status = 2;   // p^T A p of the first direction (p = u)
+    } else {
+        alpha = gamma / sums[1];
+        for (; it < maxit; ++it) {
+            const bool rev = (it & 1) != 0;   // both phases of odd iterations run last to first
+            // ---- phase 1
+            double s1[3] = {0.0, 0.0, 0.0};
+            passes([&](int base) {
+                const int node = base + wv * G + grp;
+                const bool ok = lane_ok && node < row1;
+                const int nd = ok ? node : row0;
+                // every load of the row is issued before the first use
+                const unsigned fmask = fm[nd];
+                const int k0 = m.lptr[nd], k1 = m.lptr[nd + 1];
+                TV rr[R], ww[R], uo[R];
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
-                    const size_t at = (size_t)col * 12 + R * t + i;
-                    xv[i] = z[at] + bt * pin[at];
+                    const size_t at = (size_t)nd * 12 + R * t + i;
+                    rr[i] = vget(0, base, at, i);
+                    ww[i] = vget(4, base, at, i);
+                    uo[i] = u[at];
                 }
-            };
-            TV pn[R], part[12], u[R];
-            xe(node, pn);
-            const TV dl = row_sym<TM, TV, false, sizeof(TM) == 8 ? 12 : 4>(m, vals, node, t, pn, xe,
-                                                                          xls[wv] + grp * 12, slot, part);
-            group_sum<TV, R, L>(part, lane, t, gsrc, red[wv], u);
-            pq[0] -= (double)dl;
+                // the transposed products of the rows above (4 per interior node)
+                for (int k = k0; k < k1; k += 4) {
+                    TV sv[4][R];
 #pragma unroll
-            for (int i = 0; i < R; ++i) {
-                const size_t at = (size_t)node * 12 + R * t + i;
-                pout[at] = pn[i];
-                if constexpr (MAXP > 0) uk[0][i] = u[i];
-                else qv[at] = u[i];
-                pq[0] += 2.0 * (double)pn[i] * (double)u[i];
-            }
-        }, (it & 1) != 0);
-        if (!reduce_barrier<1, NW>(ss, partial, blk, sb0, snb, nbar++, pq, abort_flag, lds)) {
-            status = 3;
-            break;
-        }
-        if (!(pq[0] > 0.0)) {
-            status = 2;
-            break;
-        }
-        const double alpha = rz / pq[0];
-        // ---- phase B
-        double s2[2] = {0.0, 0.0};
-        passes([&](int base) {
-            const int node = base + wv * G + grp;
-            const bool ok = lane_ok && node < row1;
-            const int nd = ok ? node : row0;
-            // every load of the row is issued before the first use
-            const unsigned fmask = fm[nd];
-            const int k0 = m.lptr[nd], k1 = m.lptr[nd + 1];
-            TV rr[R], zz[R], xo[R], pp[R], qq[R];
-#pragma unroll
-            for (int i = 0; i < R; ++i) {
-                const size_t at = (size_t)nd * 12 + R * t + i;
-                if constexpr (MAXP > 0) {
-                    rr[i] = rk[0][i];
-                    qq[i] = uk[0][i];
-                    xo[i] = xk[0][i];
-                } else {
-                    rr[i] = r[at];
-                    qq[i] = qv[at];
-                    xo[i] = x[at];
-                }
-                pp[i] = pout[at];
-            }
-            // the transposed products of the rows above (4 per interior node)
-            for (int k = k0; k < k1; k += 4) {
-                TV sv[4][R];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int kk = k + u < k1 ? k + u : k0;
-                    VecLoad<TV, R>::ld(slot + (size_t)kk * 12 + R * t, sv[u]);
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int i = 0; i < R; ++i)
-                        if (k + u < k1) qq[i] += sv[u][i];
-            }
-#pragma unroll
-            for (int i = 0; i < R; ++i)
-                if ((fmask >> (R * t + i)) & 1u) rr[i] -= (TV)alpha * qq[i];
-            precond(nd, rr, zz);
-            if (ok) {
-#pragma unroll
-                for (int i = 0; i < R; ++i) {
-                    const int w = R * t + i;
-                    const size_t at = (size_t)node * 12 + w;
-                    if (!((fmask >> w) & 1u)) zz[i] = TV(0);
-                    if constexpr (MAXP > 0) {
-                        xk[0][i] = xo[i] + (TV)alpha * pp[i];
-                        rk[0][i] = rr[i];
-                    } else {
-                        x[at] = xo[i] + (TV)alpha * pp[i];
-                        r[at] = rr[i];
+                    for (int q = 0; q < 4; ++q) {
+                        const int kk = k + q < k1 ? k + q : k0;
+                        VecLoad<TV, R>::ld(slot + (size_t)kk * 12 + R * t, sv[q]);
                     }
-                    z[at] = zz[i];
-                    s2[0] += (double)rr[i] * (double)zz[i];
-                    s2[1] += (double)rr[i] * (double)rr[i];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int i = 0; i < R; ++i)
+                            if (k + q < k1) ww[i] += sv[q][i];
                 }
+                TV zz[R];
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    const size_t at = (size_t)nd * 12 + R * t + i;
+                    const bool fr = (fmask >> (R * t + i)) & 1u;
+                    const TV pn = uo[i] + (TV)beta * vget(2, base, at, i);
+                    const TV sn = (fr ? ww[i] : TV(0)) + (TV)beta * vget(3, base, at, i);
+                    if (ok) {
+                        vset(1, base, at, i, vget(1, base, at, i) + (TV)alpha * pn);
+                        vset(2, base, at, i, pn);
+                        vset(3, base, at, i, sn);
+                    }
+                    rr[i] -= (TV)alpha * sn;
+                }
+                precond(nd, rr, zz);
+                if (ok) {
+#pragma unroll
+                    for (int i = 0; i < R; ++i) {
+                        const int wd = R * t + i;
+                        const size_t at = (size_t)node * 12 + wd;
+                        if (!((fmask >> wd) & 1u)) zz[i] = TV(0);
+                        vset(0, base, at, i, rr[i]);
+                        u[at] = zz[i];
+                        s1[0] += (double)rr[i] * (double)zz[i];
+                        s1[2] += (double)rr[i] * (double)rr[i];
+                    }
+                }
+            }, rev);
+            if (!neighbour_sync(nbflag, blk, nbhi, ++nnb, abort_flag)) {
+                status = 3;
+                break;
             }
-        }, (it & 1) != 0);
-        if (!reduce_barrier<2, NW>(ss, partial, blk, sb0, snb, nbar++, s2, abort_flag, lds)) {
-            status = 3;
-            break;
+            // ---- phase 2
+            s1[1] = product(rev);
+            if (!reduce_barrier<3, NW>(ss, partial, blk, sb0, snb, nbar++, s1, abort_flag, lds)) {
+                status = 3;
+                break;
+            }
+            rr2 = s1[2];
+            if (rr2 <= tol2) {
+                status = 0;
+                ++it;
+                break;
+            }
+            beta = s1[0] / gamma;
+            const double den = s1[1] - beta * s1[0] / alpha;   // p^T A p of the next direction
+            if (!(den > 0.0)) {
+                status = 2;
+                ++it;
+                break;
+            }
+            alpha = s1[0] / den;
+            gamma = s1[0];
         }
-        rr2 = s2[1];
-        if (rr2 <= tol2) {
-            status = 0;
-            ++it;
-            break;
-        }
-        beta = s2[0] / rz;
-        rz = s2[0];
-        TV* tmp = pin;
-        pin = pout;
-        pout = tmp;
     }
     if constexpr (MAXP > 0) {
         // the solution of the lane's rows, once
@@ -879,7 +946,7 @@ __global__ __launch_bounds__(NT) void k_cg(
             const int node = base + wv * G + grp;
             if (!(lane_ok && node < row1)) return;
 #pragma unroll
-            for (int i = 0; i < R; ++i) x[(size_t)node * 12 + R * t + i] = xk[0][i];
+            for (int i = 0; i < R; ++i) x[(size_t)node * 12 + R * t + i] = xres[lds_at(base, i)];
         });
     }
     if (leader) out[sh] = CgShellOut{it, status, bb, rr2};
@@ -1059,11 +1126,12 @@ void launch_regularize(hipStream_t st, int nnodes, const int* diag_blk, void* va
                        node_shell, delta_shell);
 }
 
-// Passes over a block's rows up to which the CG keeps u, r and x in
-// registers (beyond it the memory instance runs): 4 for FP64 matrices at
-// most 512 threads per block, 2 otherwise, within the register budget.
+// Passes over a block's rows up to which the CG keeps its own rows' vectors
+// in registers and LDS (beyond it the memory instance runs): 4 for FP64
+// matrices at most 512 threads per block, none for FP64 at 1024 threads
+// (the LDS would not hold them), 2 for FP32, within the register budget.
 template <class TM> constexpr int cg_maxp(int nthreads) {
-    return sizeof(TM) == 8 && nthreads <= 512 ? 4 : 2;
+    return sizeof(TM) == 8 ? (nthreads <= 512 ? 4 : 0) : 2;
 }
 
 // the CG kernel instance for a block size of 256, 512 or 1024 threads,
@@ -1080,28 +1148,28 @@ template <class TM, class TV> const void* cg_fn(int nthreads, bool resident) {
 
 template <class TM, class TV>
 hipError_t launch_cg(hipStream_t st, int nblk, int nthreads, const RowBlocks& rb, const SymBsr& m, const TM* vals,
-                     const TV* dinv, const uint16_t* freemask, const double* b, TV* x, TV* r, TV* z, TV* p0, TV* p1,
-                     TV* qv, TV* slot, double* partial, void* sync, int* abort_flag, const double* rtol2_shell,
-                     const int* maxit_shell, const int* active_shell, CgShellOut* out) {
+                     const TV* dinv, const uint16_t* freemask, const double* b, TV* x, TV* r, TV* u, TV* p, TV* s,
+                     TV* w, TV* slot, double* partial, void* sync, unsigned* nbflag, int* abort_flag,
+                     const double* rtol2_shell, const int* maxit_shell, const int* active_shell, CgShellOut* out) {
     ShellSync* ss = static_cast<ShellSync*>(sync);
     SymBsr mm = m;
     void* args[] = {(void*)&rb.blk_shell, (void*)&rb.blk_row0, (void*)&rb.blk_row1, (void*)&rb.shell_blk0,
-                    (void*)&rb.shell_nblk, (void*)&mm, (void*)&vals, (void*)&dinv, (void*)&freemask, (void*)&b,
-                    (void*)&x, (void*)&r, (void*)&z, (void*)&p0, (void*)&p1, (void*)&qv, (void*)&slot,
-                    (void*)&partial, (void*)&ss, (void*)&abort_flag, (void*)&rtol2_shell, (void*)&maxit_shell,
-                    (void*)&active_shell, (void*)&out};
+                    (void*)&rb.shell_nblk, (void*)&rb.blk_nbhi, (void*)&mm, (void*)&vals, (void*)&dinv,
+                    (void*)&freemask, (void*)&b, (void*)&x, (void*)&r, (void*)&u, (void*)&p, (void*)&s, (void*)&w,
+                    (void*)&slot, (void*)&partial, (void*)&ss, (void*)&nbflag, (void*)&abort_flag,
+                    (void*)&rtol2_shell, (void*)&maxit_shell, (void*)&active_shell, (void*)&out};
     const int pass = (nthreads / 64) * Lay<TM>::G;
     const bool resident = rb.max_rows <= cg_maxp<TM>(nthreads) * pass;
     return hipLaunchCooperativeKernel(cg_fn<TM, TV>(nthreads, resident), dim3(nblk), dim3(nthreads), args, 0, st);
 }
 template hipError_t launch_cg<double, double>(hipStream_t, int, int, const RowBlocks&, const SymBsr&, const double*,
                                               const double*, const uint16_t*, const double*, double*, double*,
-                                              double*, double*, double*, double*, double*, double*, void*, int*,
-                                              const double*, const int*, const int*, CgShellOut*);
+                                              double*, double*, double*, double*, double*, double*, void*, unsigned*,
+                                              int*, const double*, const int*, const int*, CgShellOut*);
 template hipError_t launch_cg<float, float>(hipStream_t, int, int, const RowBlocks&, const SymBsr&, const float*,
                                             const float*, const uint16_t*, const double*, float*, float*, float*,
-                                            float*, float*, float*, float*, double*, void*, int*, const double*,
-                                            const int*, const int*, CgShellOut*);
+                                            float*, float*, float*, float*, double*, void*, unsigned*, int*,
+                                            const double*, const int*, const int*, CgShellOut*);
 
 size_t cg_sync_bytes() { return sizeof(ShellSync); }
 int cg_rows_per_pass(int tm_fp32, int nthreads) { return (nthreads / 64) * (tm_fp32 ? Lay<float>::G : Lay<double>::G); }
