@@ -495,6 +495,73 @@ def learned_section(stream):
     return out
 
 
+def collision_section(stream, steps=40):
+    """Collision handling (Sec. 6.2) against a sphere: a 64x64-patch sheet
+    clamped along one edge falls under gravity onto it, each step an
+    implicit Newton step and then the collision pass (s = 3 samples a side,
+    36,864 samples; rollback, impulses, push-out); wall time of both per
+    step.  Then the sampled detection alone at the cylinder's scale: 589,824
+    samples of the 256x256 cylinder's first step against a sphere inside it
+    (no contact), per call."""
+    import torch
+    from paper_2312_14839_amd import shell as S, workloads as W
+    case = W.sheet_case(64, edges=("y0",), sigma=0.0, dt=5e-3)
+    sphere = [("sphere", (0.5, 0.7, -0.32), 0.3)]
+    ctx = S.context_for([case], stream=stream)
+    q = torch.from_numpy(case.q0.reshape(-1).copy()).cuda()
+    v = torch.zeros_like(q)
+    q1, v1, qo, vo = (torch.empty_like(q) for _ in range(4))
+    t_newton = t_coll = 0.0
+    contacts = steps_with_contact = 0
+    sim_time = 0.0
+    for k in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st = ctx.newton_step(case.dt, q, v, None, q1, v1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        cs = ctx.collide(case.dt, q, q1, v1, sphere, qo, vo)
+        t2 = time.perf_counter()
+        if rc != S.SHELL_OK:
+            raise RuntimeError(f"collision run: step {k + 1} failed: {S.STATUS_NAMES.get(rc)}")
+        if k >= 2:
+            t_newton += t1 - t0
+            t_coll += t2 - t1
+        contacts += cs["contacts"]
+        steps_with_contact += cs["contacts"] > 0
+        sim_time += cs["t_contact"] if cs["contacts"] else case.dt
+        q, qo = qo, q
+        v, vo = vo, v
+    ctx.close()
+    out = {"workload": "sheet 64x64 patches clamped along one edge, falling onto a sphere (R 0.3 m), dt 5 ms, "
+                       f"{steps} steps, 3x3 samples per patch",
+           "newton_ms_per_step": 1e3 * t_newton / (steps - 2), "collide_ms_per_step": 1e3 * t_coll / (steps - 2),
+           "steps_with_contact": steps_with_contact, "contacts_per_step": contacts / steps,
+           "simulated_time_s": sim_time}
+    cyl = W.case_cylinder(256, 256)
+    ctx = S.context_for([cyl], stream=stream)
+    q0 = torch.from_numpy(cyl.q0.reshape(-1).copy()).cuda()
+    v0 = torch.zeros_like(q0)
+    q1, v1, qo, vo = (torch.empty_like(q0) for _ in range(4))
+    ctx.newton_step(cyl.dt, q0, v0, torch.from_numpy(cyl.presc(cyl.dt).reshape(-1).copy()).cuda(), q1, v1)
+    inner = [("sphere", (0.0, 0.0, 0.5), 0.19)]
+    ctx.collide(cyl.dt, q0, q1, v1, inner, qo, vo)
+    reps = 20
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.collide(cyl.dt, q0, q1, v1, inner, qo, vo)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / reps
+    ctx.close()
+    nsamp = cyl.patches * 9
+    out["detection_cylinder256"] = {"samples": nsamp, "ms_per_call": ms, "samples_per_s": nsamp / (ms * 1e-3)}
+    print(f"[bench] collision: newton {out['newton_ms_per_step']:.2f} ms + collide {out['collide_ms_per_step']:.2f} ms "
+          f"per step, {out['contacts_per_step']:.1f} contacts/step; detection {ms:.3f} ms for {nsamp} samples",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -760,6 +827,7 @@ def main():
     ap.add_argument("--no-kernels", action="store_true")
     ap.add_argument("--no-twist", action="store_true", help="skip the 200-step 30x30 twist section")
     ap.add_argument("--no-render", action="store_true", help="skip the ray--patch intersection section")
+    ap.add_argument("--no-collision", action="store_true", help="skip the collision-handling section")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="first run a plain device copy of MB megabytes (counter calibration)")
     args = ap.parse_args()
@@ -830,6 +898,8 @@ def main():
         out["twist"] = twist_section(stream)
     if args.workload == "cylinder" and not args.no_render:
         out["render"] = render_section(stream)
+    if args.workload == "cylinder" and not args.no_collision:
+        out["collision"] = collision_section(stream)
     if not args.no_learned:
         out["learned"] = learned_section(stream)
     if not args.no_cpu_baseline:

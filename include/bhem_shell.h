@@ -321,6 +321,77 @@ shell_status shell_mlp_record(shell_ctx *c, float *feat_dev, float *tgt_dev, int
 /* Samples recorded since the last shell_mlp_record. */
 shell_status shell_mlp_recorded(const shell_ctx *c, int64_t *count);
 
+/* ------------------------------------------------- collision handling
+ * Sec. 6.2 ("Collision Handling") for colliders of simple shape: the shell
+ * midsurface is sampled uniformly and every sample tested against the
+ * colliders; the step is rolled back to the earliest contact; impulses with
+ * zero restitution (and Coulomb friction) on the earliest simultaneous
+ * contacts, each a linear constraint on the generalized velocities, solved
+ * together in the least-squares sense; then every resolved contact point is
+ * pushed a small distance off the collider, a constraint on the generalized
+ * positions solved the same way. */
+enum { SHELL_COLLIDER_PLANE = 0, SHELL_COLLIDER_SPHERE = 1 };
+
+typedef struct {
+    int32_t kind;                /* SHELL_COLLIDER_PLANE or SHELL_COLLIDER_SPHERE; static */
+    double point[3];             /* plane: a point of it; sphere: its centre */
+    double normal[3];            /* plane: its normal (normalised by the call); the shell stays on the side it
+                                    points to */
+    double radius;               /* sphere: radius > 0; the shell stays outside */
+} shell_collider;
+
+typedef struct {
+    int32_t samples;             /* s: each patch sampled at the s x s parameter points ((a + 1/2)/s, (b + 1/2)/s);
+                                    1..16 */
+    double friction;             /* Coulomb coefficient mu >= 0 (0: frictionless) */
+    double push_out;             /* distance each resolved contact point is moved off its collider (1e-4 m) */
+    double simultaneous;         /* contacts within simultaneous * dt of the earliest are resolved together */
+    double rtol;                 /* relative residual of the constraint solves */
+} shell_collide_opts;
+
+typedef struct {
+    double t_contact;            /* time of the earliest contact after the step's start; +inf: none */
+    int32_t contacts;            /* resolved contacts (pushed out) */
+    int32_t approaching;         /* of those, the ones moving into their collider (impulses) */
+    int32_t impulse_iters;       /* CG iterations on J M^-1 J^T of the velocity constraints */
+    int32_t push_iters;          /* the same for the position constraints */
+} shell_collide_stats;
+
+/* samples 3, friction 0, push_out 1e-4, simultaneous 1e-3, rtol 1e-12. */
+void shell_collide_default_opts(shell_collide_opts *o);
+
+/* One collision pass after an implicit step from q_n to q_np1 with velocity
+ * v (= (q_np1 - q_n)/dt, e.g. from shell_newton_step) of every shell of the
+ * context:
+ *   1. each sample moves on a straight line over the step (the generalized
+ *      coordinates move linearly); its contact time is the earliest tau in
+ *      [0, dt] at which it reaches a collider (0 if it starts inside);
+ *   2. tau_min = the earliest; the state is rolled back to
+ *      q_r = q_n + (tau_min / dt)(q_np1 - q_n), the velocity kept;
+ *   3. the samples with contact times <= tau_min + simultaneous * dt are the
+ *      contacts, each with the collider's normal n at its point;
+ *   4. on those moving into their collider (n . v(xi) < 0): constraints
+ *      n . v(xi) = 0 (friction > 0: also the tangential velocity 0), with
+ *      v(xi) = sum_I Phi^I(xi) qdot_I; dqdot = M^-1 J^T lambda, lambda the
+ *      minimum-norm solution of (J M^-1 J^T) lambda = -J qdot (M the
+ *      consistent mass matrix, Eq. mass; prescribed DOFs do not move); with
+ *      friction each tangential impulse is then scaled into the cone
+ *      |lambda_t| <= friction * lambda_n (0 if lambda_n <= 0);
+ *   5. for every contact the position constraint n . (x(xi) - p) = push_out
+ *      (p its point on the collider), solved the same way: dq = M^-1 J^T mu.
+ * Outputs: q_out = q_r + dq, v_out = v + dqdot, and the stats (t_contact: the
+ * step has advanced by tau_min, which the caller takes as the step's length).
+ * Without a contact q_out = q_np1, v_out = v, t_contact = +inf.
+ *   q_n_dev, q_np1_dev, v_dev, q_out_dev, v_out_dev  [total_nodes][12];
+ *   outputs may not alias inputs; colliders_host: n_colliders (host, copied);
+ *   opts NULL: the defaults.
+ * Overwrites the context's matrix with the mass matrix (the next Newton
+ * step assembles its own); SHELL_E_INVAL for invalid colliders or options. */
+shell_status shell_collide(shell_ctx *c, double dt, const double *q_n_dev, const double *q_np1_dev,
+                           const double *v_dev, const shell_collider *colliders_host, int32_t n_colliders,
+                           const shell_collide_opts *opts, double *q_out_dev, double *v_out_dev,
+                           shell_collide_stats *stats_host);
+
 /* ---------------------------------------------- ray--patch intersection
  * Sec. 5: a bicubic Hermite patch is a bicubic Bezier surface, whose
  * control-point bounding boxes bound it (convex-hull property); Sec. 5.1

@@ -64,6 +64,42 @@ hipError_t ray_scratch_address(int device, void** out);
 void launch_ccd(hipStream_t st, const double* ctrl, const double* vel, int npatch, const double* pts,
                 long long npts, double dt, const RayParams& o, double* hit, int* patch, int* pops);
 
+// ----------------------------------------------------- collision kernels
+// A static collider: kind 0 plane through p with unit normal n (the shell
+// on the side n points to), kind 1 sphere of centre p and radius r.
+struct CollCollider {
+    int kind;
+    double p[3], n[3], r;
+};
+// One resolved contact: its sample, collider, patch nodes and 16 shape
+// function values, the sample point x at the rolled-back state, the
+// collider's normal and two tangents (dir[0..2]), the point p on the
+// collider and the normal velocity of the sample before the response.
+struct CollContact {
+    int sample, collider, node[4];
+    double phi[16];
+    double dir[3][3];
+    double x[3], p[3];
+    double vn;
+};
+// per sample (s x s per patch): earliest contact time tc (inf: none) and
+// collider cid; blk_min[b]: the smallest tc of block b (256 samples)
+void launch_coll_samples(hipStream_t st, int nsamp, int s, const int4* patch_nodes, const int* patch_shell,
+                         const ShellParams* shells, const double* qn, const double* q1, double dt,
+                         const CollCollider* cols, int ncol, double* tc, int* cid, double* blk_min);
+void launch_coll_count(hipStream_t st, int nsamp, const double* tc, double thr, int* blk_cnt);
+void launch_coll_compact(hipStream_t st, int nsamp, const double* tc, double thr, const int* blk_off, int* list);
+void launch_coll_rollback(hipStream_t st, int n, const double* qn, const double* q1, double f, double* qs);
+void launch_coll_setup(hipStream_t st, int ncon, int s, const int* list, const int* cid, const int4* patch_nodes,
+                       const int* patch_shell, const ShellParams* shells, const double* qs, const double* v,
+                       const CollCollider* cols, CollContact* out);
+// y = J^T lam as nodal vector (inc: per node its (contact, corner) pairs);
+// rows of contact j: row_of[j] .. + m - 1 (row_of[j] < 0: none)
+void launch_coll_scatter(hipStream_t st, int nnodes, const int* inc_ptr, const int2* inc, const CollContact* con,
+                         const int* row_of, int m, const double* lam, const uint16_t* fm, double* y);
+void launch_coll_gather(hipStream_t st, int ncon, const CollContact* con, const int* row_of, int m, const double* z,
+                        double* out);
+
 // ------------------------------------------------------ solver kernels
 // Row partition of the node rows into blocks that never straddle a shell;
 // used by the CG kernel and by the per-shell reductions.

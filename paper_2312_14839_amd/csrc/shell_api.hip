@@ -109,6 +109,10 @@ struct shell_ctx {
     }
     // damping enters the inertia term of Newton steps only: dt there, 0 otherwise
     double dt_damp = 0.0;
+    // collision handling (shell_collide): per-sample times, block minima,
+    // contact lists and constraint work arrays, sized on first use
+    DevBuf coll_tc, coll_cid, coll_blk, coll_cnt, coll_list, coll_cols, coll_con, coll_incp, coll_inc, coll_rowof,
+        coll_lam, coll_out;
     // external nodal forces (shell_set_nodal_forces)
     DevBuf fext;
     bool has_fext = false;
@@ -1709,6 +1713,284 @@ shell_status shell_ccd(const double* ctrl_dev, const double* vel_dev, int32_t n_
         return SHELL_E_DEVICE;
     }
     return SHELL_OK;
+}
+
+void shell_collide_default_opts(shell_collide_opts* o) {
+    if (!o) return;
+    o->samples = 3;
+    o->friction = 0.0;
+    o->push_out = 1e-4;
+    o->simultaneous = 1e-3;
+    o->rtol = 1e-12;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Minimum-norm solution of (J M^-1 J^T) lam = b by CG on the host over the
+// nrow constraint rows, each product on the device: J^T p as nodal forces
+// (scatter), M^-1 by the context's block-Jacobi CG on the mass matrix
+// (prescribed DOFs masked), J back (gather).  Returns the iterations; lam
+// and the nodal M^-1 J^T lam (in dq) hold the result.
+// dq = M^-1 J^T x (nodal; 0 on prescribed DOFs) for the nrow rows of x;
+// with Sx, also Sx = J dq.  M^-1 by the context's CG on the mass matrix.
+void coll_minv_jt(shell_ctx* c, int ncon, int m, int nrow, const std::vector<double>& x, double* dq,
+                  std::vector<double>* Sx) {
+    hipStream_t st = c->stream;
+    double* lam_dev = dptr<double>(c->coll_lam);
+    double* y = dptr<double>(c->rhs);
+    HIPCHK(hipMemcpyAsync(lam_dev, x.data(), nrow * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_coll_scatter(st, c->N, dptr<int>(c->coll_incp), dptr<int2>(c->coll_inc), dptr<CollContact>(c->coll_con),
+                        dptr<int>(c->coll_rowof), m, lam_dev, dptr<uint16_t>(c->freemask), y);
+    HIPCHK(hipGetLastError());
+    SolveResult R = solve(c, y, dq, std::vector<int>(c->S, 1), std::vector<double>(c->S, 1e-13), c->opts.pcg_maxit);
+    for (int s = 0; s < c->S; ++s)
+        if (R.status[s] == 2) throw StatusErr{SHELL_E_INDEFINITE, "mass matrix not positive definite"};
+    if (Sx) {
+        launch_coll_gather(st, ncon, dptr<CollContact>(c->coll_con), dptr<int>(c->coll_rowof), m, dq,
+                           dptr<double>(c->coll_out));
+        HIPCHK(hipGetLastError());
+        Sx->resize(nrow);
+        HIPCHK(hipMemcpyAsync(Sx->data(), c->coll_out.p, nrow * sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    sync(c);
+}
+
+int coll_cg(shell_ctx* c, int ncon, int m, int nrow, const std::vector<double>& b, double rtol, double* dq,
+            std::vector<double>& lam) {
+    auto apply = [&](const std::vector<double>& x, std::vector<double>* Sx) {
+        coll_minv_jt(c, ncon, m, nrow, x, dq, Sx);
+    };
+    auto dotv = [&](const std::vector<double>& a, const std::vector<double>& bb) {
+        double t = 0.0;
+        for (int i = 0; i < nrow; ++i) t += a[i] * bb[i];
+        return t;
+    };
+    lam.assign(nrow, 0.0);
+    std::vector<double> r = b, p = b, Sp;
+    double rr = dotv(r, r);
+    const double bn = std::sqrt(rr);
+    int it = 0;
+    if (bn > 0.0)
+        for (; it < nrow + 50; ++it) {
+            if (std::sqrt(rr) <= rtol * bn) break;
+            apply(p, &Sp);
+            const double pSp = dotv(p, Sp);
+            if (!(pSp > 0.0)) break;
+            const double al = rr / pSp;
+            for (int i = 0; i < nrow; ++i) {
+                lam[i] += al * p[i];
+                r[i] -= al * Sp[i];
+            }
+            const double rr2 = dotv(r, r);
+            const double be = rr2 / rr;
+            rr = rr2;
+            for (int i = 0; i < nrow; ++i) p[i] = r[i] + be * p[i];
+        }
+    apply(lam, nullptr);   // dq = M^-1 J^T lam
+    return it;
+}
+
+}  // namespace
+
+extern "C" {
+
+shell_status shell_collide(shell_ctx* c, double dt, const double* q_n_dev, const double* q_np1_dev,
+                           const double* v_dev, const shell_collider* colliders, int32_t n_colliders,
+                           const shell_collide_opts* o, double* q_out_dev, double* v_out_dev,
+                           shell_collide_stats* stats_host) {
+    if (!c) return SHELL_E_INVAL;
+    shell_collide_opts dflt;
+    shell_collide_default_opts(&dflt);
+    if (!o) o = &dflt;
+    if (!(dt > 0) || !std::isfinite(dt) || !q_n_dev || !q_np1_dev || !v_dev || !q_out_dev || !v_out_dev ||
+        n_colliders < 0 || (n_colliders > 0 && !colliders)) {
+        c->err = "dt > 0, q_n, q_np1, v, q_out, v_out and the colliders are required";
+        return SHELL_E_INVAL;
+    }
+    if (q_out_dev == q_n_dev || q_out_dev == q_np1_dev || q_out_dev == v_dev || v_out_dev == v_dev ||
+        v_out_dev == q_n_dev || v_out_dev == q_np1_dev || v_out_dev == q_out_dev) {
+        c->err = "outputs may not alias inputs or each other";
+        return SHELL_E_INVAL;
+    }
+    if (o->samples < 1 || o->samples > 16 || !(o->friction >= 0) || !std::isfinite(o->friction) ||
+        !(o->push_out >= 0) || !std::isfinite(o->push_out) || !(o->simultaneous >= 0) ||
+        !std::isfinite(o->simultaneous) || !(o->rtol > 0 && o->rtol < 1)) {
+        c->err = "samples in [1, 16], friction >= 0, push_out >= 0, simultaneous >= 0, rtol in (0, 1)";
+        return SHELL_E_INVAL;
+    }
+    std::vector<CollCollider> cols(n_colliders);
+    for (int k = 0; k < n_colliders; ++k) {
+        const shell_collider& sc = colliders[k];
+        CollCollider& cc = cols[k];
+        cc.kind = sc.kind;
+        for (int i = 0; i < 3; ++i) {
+            cc.p[i] = sc.point[i];
+            cc.n[i] = sc.normal[i];
+        }
+        cc.r = sc.radius;
+        bool ok = (sc.kind == SHELL_COLLIDER_PLANE || sc.kind == SHELL_COLLIDER_SPHERE) && std::isfinite(sc.point[0]) &&
+                  std::isfinite(sc.point[1]) && std::isfinite(sc.point[2]);
+        if (ok && sc.kind == SHELL_COLLIDER_PLANE) {
+            const double l = std::sqrt(cc.n[0] * cc.n[0] + cc.n[1] * cc.n[1] + cc.n[2] * cc.n[2]);
+            ok = l > 0 && std::isfinite(l);
+            for (int i = 0; i < 3 && ok; ++i) cc.n[i] /= l;
+        }
+        if (ok && sc.kind == SHELL_COLLIDER_SPHERE) ok = sc.radius > 0 && std::isfinite(sc.radius);
+        if (!ok) {
+            c->err = "collider " + std::to_string(k) + ": a plane needs a finite point and non-zero normal, a sphere "
+                     "a finite centre and radius > 0";
+            return SHELL_E_INVAL;
+        }
+    }
+    API_TRY
+    HIPCHK(hipSetDevice(c->opts.device));
+    hipStream_t st = c->stream;
+    const int s = o->samples, N12 = c->N * 12;
+    const int nsamp = c->P * s * s;
+    const int nblk = (nsamp + 255) / 256;
+    shell_collide_stats stt;
+    std::memset(&stt, 0, sizeof(stt));
+    stt.t_contact = INFINITY;
+    auto pass_through = [&]() {
+        HIPCHK(hipMemcpyAsync(q_out_dev, q_np1_dev, (size_t)N12 * sizeof(double), hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(v_out_dev, v_dev, (size_t)N12 * sizeof(double), hipMemcpyDeviceToDevice, st));
+        sync(c);
+    };
+    if (nsamp == 0 || n_colliders == 0) {
+        pass_through();
+        if (stats_host) *stats_host = stt;
+        return SHELL_OK;
+    }
+    if (c->coll_tc.n < (size_t)nsamp * sizeof(double)) {
+        alloc(c->coll_tc, (size_t)nsamp * sizeof(double));
+        alloc(c->coll_cid, (size_t)nsamp * sizeof(int));
+        alloc(c->coll_list, (size_t)nsamp * sizeof(int));
+        alloc(c->coll_blk, (size_t)nblk * sizeof(double));
+        alloc(c->coll_cnt, (size_t)nblk * sizeof(int));
+    }
+    if (c->coll_cols.n < cols.size() * sizeof(CollCollider)) alloc(c->coll_cols, cols.size() * sizeof(CollCollider));
+    HIPCHK(hipMemcpyAsync(c->coll_cols.p, cols.data(), cols.size() * sizeof(CollCollider), hipMemcpyHostToDevice, st));
+    // 1-2: samples, earliest contact
+    launch_coll_samples(st, nsamp, s, dptr<int4>(c->patch_nodes), dptr<int>(c->patch_shell),
+                        dptr<ShellParams>(c->shells_d), q_n_dev, q_np1_dev, dt, dptr<CollCollider>(c->coll_cols),
+                        n_colliders, dptr<double>(c->coll_tc), dptr<int>(c->coll_cid), dptr<double>(c->coll_blk));
+    HIPCHK(hipGetLastError());
+    std::vector<double> bmin(nblk);
+    HIPCHK(hipMemcpyAsync(bmin.data(), c->coll_blk.p, nblk * sizeof(double), hipMemcpyDeviceToHost, st));
+    sync(c);
+    double tstar = INFINITY;
+    for (double v : bmin) tstar = std::min(tstar, v);
+    if (!std::isfinite(tstar)) {
+        pass_through();
+        if (stats_host) *stats_host = stt;
+        return SHELL_OK;
+    }
+    stt.t_contact = tstar;
+    // 3: rollback, the earliest simultaneous contacts in sample order
+    double* qs = dptr<double>(c->qt);
+    launch_coll_rollback(st, N12, q_n_dev, q_np1_dev, tstar / dt, qs);
+    const double thr = tstar + o->simultaneous * dt;
+    launch_coll_count(st, nsamp, dptr<double>(c->coll_tc), thr, dptr<int>(c->coll_cnt));
+    std::vector<int> cnt(nblk), off(nblk);
+    HIPCHK(hipMemcpyAsync(cnt.data(), c->coll_cnt.p, nblk * sizeof(int), hipMemcpyDeviceToHost, st));
+    sync(c);
+    int K = 0;
+    for (int b = 0; b < nblk; ++b) {
+        off[b] = K;
+        K += cnt[b];
+    }
+    h2d(c, c->coll_cnt.p, off.data(), nblk * sizeof(int));
+    launch_coll_compact(st, nsamp, dptr<double>(c->coll_tc), thr, dptr<int>(c->coll_cnt), dptr<int>(c->coll_list));
+    if (c->coll_con.n < (size_t)K * sizeof(CollContact)) {
+        alloc(c->coll_con, (size_t)K * sizeof(CollContact));
+        alloc(c->coll_rowof, (size_t)K * sizeof(int));
+        alloc(c->coll_lam, (size_t)K * 3 * sizeof(double));
+        alloc(c->coll_out, (size_t)K * 3 * sizeof(double));
+    }
+    launch_coll_setup(st, K, s, dptr<int>(c->coll_list), dptr<int>(c->coll_cid), dptr<int4>(c->patch_nodes),
+                      dptr<int>(c->patch_shell), dptr<ShellParams>(c->shells_d), qs, v_dev,
+                      dptr<CollCollider>(c->coll_cols), dptr<CollContact>(c->coll_con));
+    HIPCHK(hipGetLastError());
+    std::vector<CollContact> con(K);
+    HIPCHK(hipMemcpyAsync(con.data(), c->coll_con.p, (size_t)K * sizeof(CollContact), hipMemcpyDeviceToHost, st));
+    sync(c);
+    stt.contacts = K;
+    // node incidences of the contacts (contact order within every node)
+    std::vector<int> incp(c->N + 1, 0);
+    for (const auto& ct : con)
+        for (int cc = 0; cc < 4; ++cc) incp[ct.node[cc] + 1]++;
+    for (int n = 0; n < c->N; ++n) incp[n + 1] += incp[n];
+    std::vector<int2> inc(std::max(incp[c->N], 1));
+    {
+        std::vector<int> fill(incp.begin(), incp.end() - 1);
+        for (int j = 0; j < K; ++j)
+            for (int cc = 0; cc < 4; ++cc) inc[fill[con[j].node[cc]]++] = make_int2(j, cc);
+    }
+    upload(c->coll_incp, incp, st);
+    upload(c->coll_inc, inc, st);
+    // the mass matrix (and its block-Jacobi factors) in the context's matrix
+    assemble(c, qs, 1.0, 0);
+    bj_factor(c);
+    for (int sh = 0; sh < c->S; ++sh)
+        if (c->h_fail[sh]) throw StatusErr{SHELL_E_INDEFINITE, "mass matrix block not positive definite"};
+    // 4: impulses on the approaching contacts, zero restitution (+ friction)
+    const int m = o->friction > 0.0 ? 3 : 1;
+    std::vector<int> rowof(K, -1);
+    int na = 0;
+    for (int j = 0; j < K; ++j)
+        if (con[j].vn < 0.0) rowof[j] = m * na++;
+    stt.approaching = na;
+    double* dq = dptr<double>(c->dvec);
+    HIPCHK(hipMemcpyAsync(v_out_dev, v_dev, (size_t)N12 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (na > 0) {
+        upload(c->coll_rowof, rowof, st);
+        std::vector<double> bv(m * na);
+        // -J v: gathered on the device from v
+        launch_coll_gather(st, K, dptr<CollContact>(c->coll_con), dptr<int>(c->coll_rowof), m, v_dev,
+                           dptr<double>(c->coll_out));
+        HIPCHK(hipMemcpyAsync(bv.data(), c->coll_out.p, bv.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        sync(c);
+        for (double& x : bv) x = -x;
+        std::vector<double> lam;
+        stt.impulse_iters = coll_cg(c, K, m, m * na, bv, o->rtol, dq, lam);
+        if (m == 3) {
+            // Coulomb cone: |lambda_t| <= mu lambda_n, none when lambda_n <= 0
+            for (int a = 0; a < na; ++a) {
+                double* l = lam.data() + 3 * a;
+                const double nt = std::sqrt(l[1] * l[1] + l[2] * l[2]);
+                if (l[0] <= 0.0) {
+                    l[1] = l[2] = 0.0;
+                } else if (nt > o->friction * l[0]) {
+                    l[1] *= o->friction * l[0] / nt;
+                    l[2] *= o->friction * l[0] / nt;
+                }
+            }
+            coll_minv_jt(c, K, m, m * na, lam, dq, nullptr);   // dq for the clamped impulses
+        }
+        launch_add_to<double>(st, N12, dq, v_out_dev);
+        HIPCHK(hipGetLastError());
+    }
+    // 5: push-out of every resolved contact along its normal
+    for (int j = 0; j < K; ++j) rowof[j] = j;
+    upload(c->coll_rowof, rowof, st);
+    std::vector<double> bp(K);
+    for (int j = 0; j < K; ++j) {
+        const CollContact& ct = con[j];
+        double d = 0.0;
+        for (int i = 0; i < 3; ++i) d += ct.dir[0][i] * (ct.x[i] - ct.p[i]);
+        bp[j] = o->push_out - d;
+    }
+    std::vector<double> mu;
+    stt.push_iters = coll_cg(c, K, 1, K, bp, o->rtol, dq, mu);
+    HIPCHK(hipMemcpyAsync(q_out_dev, qs, (size_t)N12 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    launch_add_to<double>(st, N12, dq, q_out_dev);
+    HIPCHK(hipGetLastError());
+    sync(c);
+    if (stats_host) *stats_host = stt;
+    return SHELL_OK;
+    API_CATCH
 }
 
 shell_status shell_point_load(const shell_desc* d, double xi1, double xi2, const double* force, double* f_nodal) {

@@ -100,6 +100,42 @@ class shell_ray_opts(C.Structure):
                 ("device", C.c_int32), ("stream", C.c_void_p)]
 
 
+SHELL_COLLIDER_PLANE, SHELL_COLLIDER_SPHERE = 0, 1
+
+
+class shell_collider(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("point", C.c_double * 3), ("normal", C.c_double * 3), ("radius", C.c_double)]
+
+
+class shell_collide_opts(C.Structure):
+    _fields_ = [("samples", C.c_int32), ("friction", C.c_double), ("push_out", C.c_double),
+                ("simultaneous", C.c_double), ("rtol", C.c_double)]
+
+
+class shell_collide_stats(C.Structure):
+    _fields_ = [("t_contact", C.c_double), ("contacts", C.c_int32), ("approaching", C.c_int32),
+                ("impulse_iters", C.c_int32), ("push_iters", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def colliders(specs):
+    """shell_collider array from ("plane", point, normal) / ("sphere", centre, radius) tuples."""
+    arr = (shell_collider * max(len(specs), 1))()
+    for k, sp in enumerate(specs):
+        c = arr[k]
+        c.kind = SHELL_COLLIDER_PLANE if sp[0] == "plane" else SHELL_COLLIDER_SPHERE
+        for i in range(3):
+            c.point[i] = float(sp[1][i])
+        if sp[0] == "plane":
+            for i in range(3):
+                c.normal[i] = float(sp[2][i])
+        else:
+            c.radius = float(sp[2])
+    return arr
+
+
 class ShellError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -159,6 +195,11 @@ def _load():
     lib.shell_mlp_record.restype = C.c_int32
     lib.shell_mlp_recorded.argtypes = [vp, P(C.c_int64)]
     lib.shell_mlp_recorded.restype = C.c_int32
+    lib.shell_collide_default_opts.argtypes = [P(shell_collide_opts)]
+    lib.shell_collide_default_opts.restype = None
+    lib.shell_collide.argtypes = [vp, C.c_double, vp, vp, vp, P(shell_collider), C.c_int32, P(shell_collide_opts),
+                                  vp, vp, P(shell_collide_stats)]
+    lib.shell_collide.restype = C.c_int32
     lib.shell_bezier.argtypes = [vp, vp, vp]
     lib.shell_bezier.restype = C.c_int32
     lib.shell_ray_default_opts.argtypes = [P(shell_ray_opts)]
@@ -180,7 +221,7 @@ EXPORTED = ["shell_default_opts", "shell_create", "shell_destroy", "shell_last_e
             "shell_mlp_get_params", "shell_mlp_forward", "shell_mlp_loss_grad", "shell_mlp_train",
             "shell_mlp_record", "shell_mlp_recorded", "shell_autotune", "shell_set_nodal_forces",
             "shell_point_load", "shell_bezier", "shell_ray_default_opts", "shell_ray_cast", "shell_ray_cast_noalloc",
-            "shell_ccd"]
+            "shell_ccd", "shell_collide_default_opts", "shell_collide"]
 
 MLP_IN, MLP_HIDDEN, MLP_OUT = 36, 128, 12
 MLP_PARAMS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_OUT + MLP_OUT
@@ -308,6 +349,18 @@ class ShellContext:
             self._check(rc)
         return rc, [s.as_dict() for s in st]
 
+
+    def collide(self, dt, q_n, q_np1, v, specs, q_out, v_out, **kw):
+        """shell_collide against the colliders `specs` (see colliders());
+        keyword arguments set shell_collide_opts fields.  Returns the stats."""
+        o = shell_collide_opts()
+        lib.shell_collide_default_opts(C.byref(o))
+        for k, v_ in kw.items():
+            setattr(o, k, v_)
+        st = shell_collide_stats()
+        self._check(lib.shell_collide(self.h, float(dt), _ptr(q_n), _ptr(q_np1), _ptr(v), colliders(specs),
+                                      len(specs), C.byref(o), _ptr(q_out), _ptr(v_out), C.byref(st)))
+        return st.as_dict()
 
     def set_nodal_forces(self, f):
         self._check(lib.shell_set_nodal_forces(self.h, _ptr(f)))
