@@ -107,6 +107,8 @@ typedef struct {
     int32_t warm_start_used;     /* 1 if the Newton iteration started from the learned guess */
     double grad_norm0, grad_norm, grad_floor, reg_delta;
     double t_assemble_ms, t_pcg_ms, t_step_ms;   /* whole-context wall times */
+    double alm_residual;         /* max |c| over this shell's point constraints at the last check */
+    int32_t alm_outer;           /* multiplier updates taken (shell_set_point_constraints) */
 } shell_step_stats;
 
 /* Default options: FP64, exact Hessian, no warm start, newton_rtol = pcg_rtol
@@ -191,6 +193,64 @@ shell_status shell_newton_step(shell_ctx *c, double dt, const double *q_n_dev, c
  * prescribed DOFs they have no effect.  A point force at a parameter point
  * is the vector shell_point_load builds (Sec. 4.3, "External Forces"). */
 shell_status shell_set_nodal_forces(shell_ctx *c, const double *f_dev);
+
+/* Pressure on each shell (Sec. 4.3, "External Forces", f = p n):
+ * pressure_host[n_shells] in Pa, per unit current area along the normal
+ * a_1 x a_2 / |a_1 x a_2| of the parametrisation (positive inflates a
+ * cylinder whose xi1 runs around its axis counter-clockwise and xi2 along
+ * it); NULL or all zero removes it.  A follower load: in shell_newton_step
+ * it is evaluated at the step's start, F_I = p sum_gp w Phi^I (a_1 x a_2)(q_n),
+ * and acts as a dead load within the step (added to the nodal forces), so
+ * every Newton system stays symmetric; its load stiffness, which is not
+ * symmetric, is not used.  A non-finite pressure is rejected with
+ * SHELL_E_INVAL. */
+shell_status shell_set_pressure(shell_ctx *c, const double *pressure_host);
+
+/* The nodal generalized forces of the context's pressures at state q_dev:
+ * f_dev[total_nodes][12] (device), unmasked.  Enqueued on the context's
+ * stream. */
+shell_status shell_pressure_load(shell_ctx *c, const double *q_dev, double *f_dev);
+
+/* Positional constraint at a midsurface point (Sec. 4.2: the position or a
+ * tangent of the midsurface prescribed at an arbitrary parameter point, not
+ * only at a node), imposed in shell_newton_step by the augmented Lagrangian
+ * method (Sec. 6.1): with c = x^(kind)(xi) - target (3 rows per constraint,
+ * linear in q) each Newton solve minimises the incremental potential plus
+ * -lambda.c + (penalty/2)|c|^2; when it has converged and max |c| over a
+ * shell's constraints exceeds tol, that shell's multipliers are updated,
+ * lambda <- lambda - penalty c, and its Newton iteration resumes (at least
+ * one more iteration, newton_maxit again, the convergence test relative to
+ * the step's initial gradient), at most max_outer times (then
+ * SHELL_E_NOT_CONVERGED).  At the result lambda is the constraint force:
+ * grad of the incremental potential = C^T lambda. */
+typedef struct {
+    int32_t shell;               /* shell index */
+    int32_t kind;                /* 0: x, 1: x_xi1, 2: x_xi2 at the point */
+    double xi1, xi2;             /* parameter coordinates, in [0, n1 dxi1] x [0, n2 dxi2] (xi1 modulo
+                                    n1 dxi1 on a periodic shell), patch as shell_point_load */
+    double target[3];
+} shell_point_constraint;
+
+typedef struct {
+    double penalty;              /* > 0, the coefficient of (1/2)|c|^2 */
+    double tol;                  /* > 0, max |c| at which a shell's outer iteration stops */
+    int32_t max_outer;           /* >= 0, multiplier updates per step at most */
+} shell_alm_opts;
+
+/* Set the point constraints of the context (n = 0 or pts NULL removes
+ * them) and zero their multipliers.  Constraints on prescribed DOFs act
+ * on the free DOFs only.  SHELL_E_INVAL for a shell index, kind or point
+ * out of range, a non-finite target or invalid options.  Takes effect in
+ * the next shell_newton_step; shell_energy_grad_hess, shell_assemble and
+ * the other building blocks do not include them. */
+shell_status shell_set_point_constraints(shell_ctx *c, const shell_point_constraint *pts, int32_t n,
+                                         const shell_alm_opts *o);
+
+/* Multipliers lambda_host[n][3] of the constraints in the order they were
+ * set: after a step, its constraint forces; kept as the next step's start
+ * (shell_set_point_multipliers replaces them, e.g. after moving targets). */
+shell_status shell_get_point_multipliers(const shell_ctx *c, double *lambda_host);
+shell_status shell_set_point_multipliers(shell_ctx *c, const double *lambda_host);
 
 /* Consistent nodal load of a point force: adds Phi^I(xi) force into the
  * host array f_nodal[nodes of this shell][12] for the 16 shape functions of

@@ -93,5 +93,6 @@ template <class T> void patch_gradient(const Shell& s, const T* q, const double*
 void patch_hessian(const Shell& s, const double* q, const double* qb, int pseudo, double* hess);
 void patch_mass(const Shell& s, const double* qb, double* mass);
 void patch_gravity(const Shell& s, const double* qb, double* f);
+void patch_pressure(const Shell& s, const double* q, double p, double* f);
 
 }  // namespace orc

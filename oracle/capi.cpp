@@ -79,6 +79,22 @@ void orc_gradient(const Shell* s, const double* q, const double* qb, double* g) 
 
 void orc_gravity(const Shell* s, const double* qb, double* f) { gravity_load(*s, qb, f); }
 
+void orc_patch_pressure(const Shell* s, const double* q, double p, double* f) { patch_pressure(*s, q, p, f); }
+
+// Nodal pressure load of the whole shell at state q (assembled patch loads).
+void orc_pressure_load(const Shell* s, const double* q, double p, double* f) {
+    std::memset(f, 0, sizeof(double) * 12 * num_nodes(*s));
+    for (int pj = 0; pj < s->n2; ++pj)
+        for (int pi = 0; pi < s->n1; ++pi) {
+            double lq[48], lf[48];
+            int nodes[4];
+            gather(*s, pi, pj, q, lq, nodes);
+            patch_pressure(*s, lq, p, lf);
+            for (int c = 0; c < 4; ++c)
+                for (int d = 0; d < 12; ++d) f[12 * nodes[c] + d] += lf[12 * c + d];
+        }
+}
+
 // Global matrix as node blocks.  which = 0: elastic Hessian (pseudo if
 // pseudo != 0); 1: mass matrix.  Writes up to cap blocks: rows[b], cols[b],
 // vals[144 b]; returns the block count.
@@ -128,6 +144,13 @@ int orc_newton_step_traced(const Shell* s, const double* qb, const uint8_t* fixe
                            const double* vn, const double* qpresc, const double* f_ext, const NewtonOpts* o,
                            double* qn1, double* vn1, NewtonStats* st, NewtonTrace* tr) {
     return newton_step(*s, qb, fixed, dt, qn, vn, qpresc, f_ext, *o, qn1, vn1, st, tr);
+}
+
+// The same step with augmented-Lagrangian point constraints (AlmOpts).
+int orc_newton_step_alm(const Shell* s, const double* qb, const uint8_t* fixed, double dt, const double* qn,
+                        const double* vn, const double* qpresc, const double* f_ext, const NewtonOpts* o, double* qn1,
+                        double* vn1, NewtonStats* st, AlmOpts* alm) {
+    return newton_step(*s, qb, fixed, dt, qn, vn, qpresc, f_ext, *o, qn1, vn1, st, nullptr, alm);
 }
 
 // Solve (K + mass_scale M) x = b with fixed DOFs replaced by identity rows

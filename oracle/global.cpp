@@ -320,6 +320,34 @@ struct Problem {
     }
     int n() const { return 12 * num_nodes(s); }
     bool is_fixed(int i) const { return fixed && fixed[i]; }
+    // augmented-Lagrangian point constraints: per constraint its patch's
+    // nodes and the 16 shape-function values of its kind at its point
+    const AlmOpts* alm = nullptr;
+    std::vector<std::array<int, 4>> alm_nodes;
+    std::vector<std::array<double, 16>> alm_psi;
+    void set_alm(const AlmOpts* a) {
+        alm = a;
+        if (!a) return;
+        for (int k = 0; k < a->n; ++k) {
+            const PointConstraint& pc = a->pts[k];
+            std::array<int, 4> nd;
+            patch_nodes(s, pc.pi, pc.pj, nd.data());
+            double ph[6][16];
+            shape_functions(pc.t1, pc.t2, s.dxi1, s.dxi2, ph);
+            std::array<double, 16> psi;
+            for (int I = 0; I < 16; ++I) psi[I] = ph[pc.kind][I];
+            alm_nodes.push_back(nd);
+            alm_psi.push_back(psi);
+        }
+    }
+    // c = x^(kind)(xi) - target of constraint k
+    void residual(int k, const double* q, double c[3]) const {
+        for (int comp = 0; comp < 3; ++comp) {
+            double v = -alm->pts[k].target[comp];
+            for (int I = 0; I < 16; ++I) v += alm_psi[k][I] * q[12 * alm_nodes[k][I >> 2] + 3 * (I & 3) + comp];
+            c[comp] = v;
+        }
+    }
     // E(q), grad E(q) (zero on fixed DOFs) and |E| terms for the noise floor.
     double eval(const double* q, double* g, double* scale) {
         const int nd = n();
@@ -339,12 +367,26 @@ struct Problem {
         }
         double eel = energy(s, q, qb);
         gradient(s, q, qb, g);
+        // - lambda.c + (penalty/2)|c|^2 and its gradient C^T (penalty c - lambda)
+        double ealm = 0.0;
+        if (alm)
+            for (int k = 0; k < alm->n; ++k) {
+                double c[3];
+                residual(k, q, c);
+                for (int comp = 0; comp < 3; ++comp) {
+                    const double lam = alm->lambda[3 * k + comp];
+                    ealm += -lam * c[comp] + 0.5 * alm->penalty * c[comp] * c[comp];
+                    const double w = alm->penalty * c[comp] - lam;
+                    for (int I = 0; I < 16; ++I) g[12 * alm_nodes[k][I >> 2] + 3 * (I & 3) + comp] += w * alm_psi[k][I];
+                }
+            }
         for (int i = 0; i < nd; ++i) {
             g[i] += Mdq[i] / (dt * dt) + c_damp * Mdn[i] - f[i];
             if (is_fixed(i)) g[i] = 0.0;
         }
-        if (scale) *scale = std::fabs(eel) + std::fabs(ekin) + std::fabs(edamp) + std::fabs(egrav);
-        return eel + ekin + edamp + egrav;
+        if (scale)
+            *scale = std::fabs(eel) + std::fabs(ekin) + std::fabs(edamp) + std::fabs(egrav) + std::fabs(ealm);
+        return eel + ekin + edamp + egrav + ealm;
     }
 };
 
@@ -358,9 +400,11 @@ double norm2(const std::vector<double>& v) {
 
 int newton_step(const Shell& s, const double* qb, const uint8_t* fixed, double dt, const double* qn, const double* vn,
                 const double* qpresc, const double* f_ext, const NewtonOpts& o, double* qn1, double* vn1,
-                NewtonStats* st, NewtonTrace* tr) {
+                NewtonStats* st, NewtonTrace* tr, AlmOpts* alm) {
     Problem P(s, qb, fixed, dt, f_ext);
     P.qn = qn;
+    P.set_alm(alm);
+    if (alm) alm->outer_iters = 0;
     const int n = P.n();
     P.qhat.resize(n);
     for (int i = 0; i < n; ++i) P.qhat[i] = qn[i] + dt * vn[i];
@@ -378,6 +422,9 @@ int newton_step(const Shell& s, const double* qb, const uint8_t* fixed, double d
     NodeBlocks Aprev(s);
     bool have_prev = false;
     int status = 1;   // Newton iteration cap
+    int k_total = 0;
+    for (;;) {   // augmented Lagrangian: Newton, then a multiplier update, until the constraints hold
+    status = 1;
     for (int k = 0;; ++k) {
         double gn = norm2(g);
         st->grad_norm = gn;
@@ -409,6 +456,16 @@ int newton_step(const Shell& s, const double* qb, const uint8_t* fixed, double d
             for (auto& e : A.rows[r]) {
                 const double* m = P.M.find(r, e.col);
                 for (int t = 0; t < 144; ++t) e.v[t] += m[t] * mcoef;
+            }
+        // penalty C^T C of the point constraints: penalty (psi psi^T) x I_3 on their patches
+        if (alm)
+            for (int kc = 0; kc < alm->n; ++kc) {
+                std::vector<double> m48(48 * 48, 0.0);
+                for (int I = 0; I < 16; ++I)
+                    for (int J = 0; J < 16; ++J)
+                        for (int comp = 0; comp < 3; ++comp)
+                            m48[(3 * I + comp) * 48 + 3 * J + comp] = alm->penalty * P.alm_psi[kc][I] * P.alm_psi[kc][J];
+                A.add_patch(P.alm_nodes[kc].data(), m48.data(), 1.0);
             }
         Aprev = A;
         have_prev = true;
@@ -522,7 +579,7 @@ int newton_step(const Shell& s, const double* qb, const uint8_t* fixed, double d
             alpha = a_new;
             st->ls_backtracks++;
         }
-        st->newton_iters = k + 1;
+        st->newton_iters = k_total + k + 1;
         if (!accepted) {
             status = 2;
             break;
@@ -531,6 +588,24 @@ int newton_step(const Shell& s, const double* qb, const uint8_t* fixed, double d
         g = gt;
         E = Et;
         scale = scale_t;
+    }
+    k_total = st->newton_iters;
+    if (!alm || status != 0) break;
+    double cmax = 0.0;
+    std::vector<double> cc(3 * alm->n);
+    for (int kc = 0; kc < alm->n; ++kc) {
+        P.residual(kc, q.data(), &cc[3 * kc]);
+        for (int comp = 0; comp < 3; ++comp) cmax = std::max(cmax, std::fabs(cc[3 * kc + comp]));
+    }
+    alm->residual = cmax;
+    if (cmax <= alm->tol) break;
+    if (alm->outer_iters == alm->max_outer) {
+        status = 1;
+        break;
+    }
+    for (int i = 0; i < 3 * alm->n; ++i) alm->lambda[i] -= alm->penalty * cc[i];
+    alm->outer_iters++;
+    E = P.eval(q.data(), g.data(), &scale);
     }
     for (int i = 0; i < n; ++i) {
         qn1[i] = q[i];

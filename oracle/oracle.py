@@ -56,6 +56,17 @@ class NewtonTrace(C.Structure):
     ]
 
 
+class PointConstraint(C.Structure):
+    _fields_ = [("pi", C.c_int), ("pj", C.c_int), ("t1", C.c_double), ("t2", C.c_double), ("kind", C.c_int),
+                ("target", C.c_double * 3)]
+
+
+class AlmOpts(C.Structure):
+    _fields_ = [("n", C.c_int), ("pts", C.POINTER(PointConstraint)), ("penalty", C.c_double), ("tol", C.c_double),
+                ("max_outer", C.c_int), ("lam", C.POINTER(C.c_double)), ("outer_iters", C.c_int),
+                ("residual", C.c_double)]
+
+
 def _load(path=_LIB_PATH):
     if not os.path.exists(path):
         from . import build_oracle
@@ -81,6 +92,8 @@ def _load(path=_LIB_PATH):
     lib.orc_energy.restype = C.c_double
     lib.orc_gradient.argtypes = [sp, d, d, d]
     lib.orc_gravity.argtypes = [sp, d, d]
+    lib.orc_patch_pressure.argtypes = [sp, d, C.c_double, d]
+    lib.orc_pressure_load.argtypes = [sp, d, C.c_double, d]
     lib.orc_matrix_blocks.argtypes = [sp, d, d, C.c_int, C.c_int, C.c_int,
                                       C.POINTER(C.c_int), C.POINTER(C.c_int), d]
     lib.orc_matrix_blocks.restype = C.c_int
@@ -92,6 +105,9 @@ def _load(path=_LIB_PATH):
                                            C.POINTER(NewtonOpts), d, d, C.POINTER(NewtonStats),
                                            C.POINTER(NewtonTrace)]
     lib.orc_newton_step_traced.restype = C.c_int
+    lib.orc_newton_step_alm.argtypes = [sp, d, C.POINTER(C.c_uint8), C.c_double, d, d, d, d,
+                                        C.POINTER(NewtonOpts), d, d, C.POINTER(NewtonStats), C.POINTER(AlmOpts)]
+    lib.orc_newton_step_alm.restype = C.c_int
     lib.orc_linear_solve.argtypes = [sp, d, d, C.POINTER(C.c_uint8), C.c_double, C.c_int, d, d,
                                      C.c_double, C.c_int, C.POINTER(C.c_int)]
     lib.orc_linear_solve.restype = C.c_int
@@ -246,6 +262,23 @@ def gravity(shell, qb):
     return f
 
 
+def patch_pressure(shell, q, p):
+    """Nodal generalized force [48] of a pressure p on one patch at state q
+    (per unit current area, along a_1 x a_2)."""
+    q = _f64(q)
+    f = np.zeros(48)
+    lib().orc_patch_pressure(C.byref(shell), _d(q), float(p), _d(f))
+    return f
+
+
+def pressure_load(shell, q, p):
+    """Nodal generalized force [nodes, 12] of a pressure p on the shell at state q."""
+    q = _f64(q)
+    f = np.zeros_like(q)
+    lib().orc_pressure_load(C.byref(shell), _d(q), float(p), _d(f))
+    return f
+
+
 def matrix_blocks(shell, q, qb, which="hessian", pseudo=False):
     """Global matrix as node blocks: (rows[nb], cols[nb], vals[nb, 12, 12])."""
     q, qb = _f64(q), _f64(qb)
@@ -269,7 +302,8 @@ def matrix_dense(shell, q, qb, which="hessian", pseudo=False):
 
 
 def newton_step(shell, qb, fixed, dt, qn, vn, qpresc=None, solver="ldlt", pseudo=False,
-                newton_rtol=1e-10, newton_maxit=50, pcg_rtol=1e-10, pcg_maxit=100000, f_ext=None, trace=0):
+                newton_rtol=1e-10, newton_maxit=50, pcg_rtol=1e-10, pcg_maxit=100000, f_ext=None, trace=0,
+                pressure=0.0, points=None, penalty=0.0, alm_tol=1e-10, max_outer=30, lam=None):
     """One implicit-Euler step (mass-proportional damping from shell.damping,
     optional external nodal forces f_ext [nodes, 12]).  Returns (status,
     q_next, v_next, stats dict); with trace = K > 0 the stats also hold
@@ -277,6 +311,11 @@ def newton_step(shell, qb, fixed, dt, qn, vn, qpresc=None, solver="ldlt", pseudo
     energy, slope, steepest-descent fallback, line-search trials, iterate
     and direction of each)."""
     qb, qn, vn = _f64(qb), _f64(qn), _f64(vn)
+    if pressure:
+        # follower pressure, its direction taken at the step's start (a dead
+        # load within the step, so the step stays a minimisation)
+        pl = pressure_load(shell, qn, pressure).reshape(qn.shape)
+        f_ext = pl if f_ext is None else _f64(f_ext).reshape(qn.shape) + pl
     fe = _f64(f_ext) if f_ext is not None else None
     fx = np.ascontiguousarray(fixed, dtype=np.uint8) if fixed is not None else None
     qp = _f64(qpresc) if qpresc is not None else None
@@ -287,6 +326,19 @@ def newton_step(shell, qb, fixed, dt, qn, vn, qpresc=None, solver="ldlt", pseudo
     args = (C.byref(shell), _d(qb), fx.ctypes.data_as(C.POINTER(C.c_uint8)) if fx is not None else None,
             float(dt), _d(qn), _d(vn), _d(qp) if qp is not None else None,
             _d(fe) if fe is not None else None, C.byref(o), _d(q1), _d(v1), C.byref(st))
+    if points is not None:
+        # points: list of (pi, pj, t1, t2, kind, target[3]); lam: [3 n] start (zeros if None)
+        arr = (PointConstraint * max(len(points), 1))()
+        for k, (pi, pj, t1, t2, kind, tgt) in enumerate(points):
+            arr[k].pi, arr[k].pj, arr[k].t1, arr[k].t2, arr[k].kind = int(pi), int(pj), float(t1), float(t2), int(kind)
+            for c in range(3):
+                arr[k].target[c] = float(tgt[c])
+        lam_arr = np.zeros(3 * len(points)) if lam is None else np.array(lam, dtype=np.float64).reshape(-1).copy()
+        al = AlmOpts(len(points), arr, float(penalty), float(alm_tol), int(max_outer), _d(lam_arr), 0, 0.0)
+        rc = lib().orc_newton_step_alm(*args, C.byref(al))
+        stats = {k: getattr(st, k) for k, _ in NewtonStats._fields_ if k != "pad"}
+        stats.update(lam=lam_arr, outer_iters=al.outer_iters, residual=al.residual)
+        return rc, q1, v1, stats
     if trace:
         K, n = int(trace), qn.size
         rec = {"delta": np.zeros(K), "energy": np.zeros(K), "slope": np.zeros(K),

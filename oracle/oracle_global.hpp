@@ -63,6 +63,28 @@ struct NewtonTrace {
     double* q_iter;    // [cap][n] iterate of iteration k
     double* d_iter;    // [cap][n] direction of iteration k
 };
+// Positional constraints at arbitrary midsurface points (Sec. 4.2: the
+// position, or a first derivative, prescribed at a point that need not be a
+// node), imposed by the augmented Lagrangian method (Sec. 6.1).  Constraint
+// c = x^(kind)(xi) - target (3 rows, linear in q); the Newton iteration
+// minimises E(q) - lambda.c + (penalty/2)|c|^2; after it converges the
+// multipliers are updated, lambda <- lambda - penalty c, until max |c| <= tol.
+struct PointConstraint {
+    int pi, pj;          // patch
+    double t1, t2;       // local parameters in [0, 1]
+    int kind;            // 0: x, 1: dx/dxi1, 2: dx/dxi2
+    double target[3];
+};
+struct AlmOpts {
+    int n;
+    const PointConstraint* pts;
+    double penalty;
+    double tol;
+    int max_outer;
+    double* lambda;      // [3 n] multipliers: in, the starting values; out, the final ones
+    int outer_iters;     // out: multiplier updates made
+    double residual;     // out: max |c| at the end
+};
 // Converged when ||g_k|| <= max(newton_rtol ||g_0||, 4 eps || P_free |A_{k-1}| |q_k| ||).
 // Returns 0 converged, 1 Newton iteration cap, 2 line search failed,
 // 3 no positive definite system within the regulariser cap.
@@ -70,6 +92,6 @@ struct NewtonTrace {
 // the areal gravity load.
 int newton_step(const Shell& s, const double* qb, const uint8_t* fixed, double dt, const double* qn, const double* vn,
                 const double* qpresc, const double* f_ext, const NewtonOpts& o, double* qn1, double* vn1,
-                NewtonStats* st, NewtonTrace* trace = nullptr);
+                NewtonStats* st, NewtonTrace* trace = nullptr, AlmOpts* alm = nullptr);
 
 }  // namespace orc

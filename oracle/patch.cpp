@@ -495,6 +495,24 @@ void patch_gravity(const Shell& s, const double* qb, double* f) {
     }
 }
 
+// Pressure load (Sec. 4.3, "External Forces", f = p n): a pressure p acts
+// on the current surface, per unit current area, along n = a_1 x a_2 /
+// |a_1 x a_2|, so p n dA = p (a_1 x a_2) dxi1 dxi2 and the nodal generalized
+// force is F_I = sum_gp w p Phi^I (a_1 x a_2) (no sqrt(abar): the area
+// element is the current one).
+void patch_pressure(const Shell& s, const double* q, double p, double* f) {
+    QPoint qp[16];
+    quad_points(s, qp);
+    for (int i = 0; i < 48; ++i) f[i] = 0.0;
+    for (int g = 0; g < 16; ++g) {
+        Geo<double> cur = geometry<double>(qp[g].phi, q);
+        const V3<double> n = cross(cur.a[0], cur.a[1]);
+        const double wq = qp[g].weight * p;
+        for (int I = 0; I < 16; ++I)
+            for (int c = 0; c < 3; ++c) f[3 * I + c] += wq * qp[g].phi[0][I] * compc(n, c);
+    }
+}
+
 template double patch_energy_tensor<double>(const Shell&, const double*, const double*);
 template std::complex<double> patch_energy_tensor<std::complex<double>>(const Shell&, const std::complex<double>*,
                                                                         const double*);

@@ -16,6 +16,11 @@ void launch_gather_grad(hipStream_t st, int nnodes, const int* inc_ptr, const in
                         const uint16_t* freemask, const int* node_shell, const int* write_shell, double* grad);
 void launch_shell_energy(hipStream_t st, int nshell, const ShellParams* shells, const double* e_patch,
                          double* e_shell);
+// per-patch pressure loads (pressure[shell], per unit current area along
+// a_1 x a_2) into g_patch [P][48], to be gathered to nodes
+void launch_pressure(hipStream_t st, int npatch, const int4* patch_nodes, const int* patch_shell,
+                     const ShellParams* shells, const double* pressure, const double* phi, const double* q,
+                     double* g_patch);
 // patch_slots[16 * p + m]: stored block of the patch's m-th stored local block
 // (-1 past the last), patch_kid[p]: its local block index in bits 4m..4m+3,
 // patch_first[p]: bit m set where patch p is the first to reach that block
@@ -99,6 +104,29 @@ void launch_coll_scatter(hipStream_t st, int nnodes, const int* inc_ptr, const i
                          const int* row_of, int m, const double* lam, const uint16_t* fm, double* y);
 void launch_coll_gather(hipStream_t st, int ncon, const CollContact* con, const int* row_of, int m, const double* z,
                         double* out);
+
+// ------------------------------------------------- point constraints
+// Constraint x^(kind)(xi) = target at a midsurface point: its patch's four
+// nodes and the 16 shape-function values psi[4c + k] of that kind (corner c,
+// DOF kind k), so that c = sum_I psi_I q[node[I / 4]][3 (I % 4) + comp] - target.
+struct AlmPoint {
+    int node[4];
+    double psi[16];
+    double target[3];
+};
+// grad += C^T (kappa c - lam) on free DOFs (fm NULL: all) of the nodes of
+// shells with write_shell set (all if NULL); inc: per node its
+// (constraint, corner) pairs
+void launch_alm_grad(hipStream_t st, int nnodes, const int* incp, const int2* inc, const AlmPoint* pts,
+                     const double* lam, double kappa, const double* q, const uint16_t* fm, const int* node_shell,
+                     const int* write_shell, double* grad);
+// e_shell[3 s + 2] += sum over the shell's constraints of -lam.c + kappa/2 |c|^2
+void launch_alm_energy(hipStream_t st, int nshell, const int* shell_pt, const AlmPoint* pts, const double* lam,
+                       double kappa, const double* q, double* e_shell);
+// out[3 j + comp] = c_j
+void launch_alm_residual(hipStream_t st, int npts, const AlmPoint* pts, const double* q, double* out);
+// vals[pos[i]] += val[i], distinct positions (vals FP32 or FP64)
+void launch_add_sparse(hipStream_t st, int n, const long long* pos, const double* val, void* vals, int vals_fp32);
 
 // ------------------------------------------------------ solver kernels
 // Row partition of the node rows into blocks that never straddle a shell;

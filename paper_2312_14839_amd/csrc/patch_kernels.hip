@@ -171,6 +171,51 @@ __global__ void k_gather_grad(int nnodes, const int* __restrict__ inc_ptr, const
     grad[(size_t)node * 12 + w] = s;
 }
 
+// Pressure load per patch (Sec. 4.3, "External Forces"): a pressure p of
+// the patch's shell acts per unit current area along a_1 x a_2, so the
+// generalized force of local coordinate I = 4c + k is
+//   F_I = sum_gp w p Phi^I (a_1 x a_2),
+// written as g_patch[48 p + 12 c + 3 k + comp] (gathered like the gradient).
+// One thread per (patch, I); a_1, a_2 at the 16 Gauss points from the theta
+// basis table (slots 0, 1 and the value slot 5).
+__global__ void __launch_bounds__(256) k_pressure(int npatch, const int4* __restrict__ patch_nodes,
+                                                  const int* __restrict__ patch_shell,
+                                                  const ShellParams* __restrict__ shells,
+                                                  const double* __restrict__ pressure, const double* __restrict__ phi,
+                                                  const double* __restrict__ q, double* __restrict__ g_patch) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 16 * npatch) return;
+    const int p = t >> 4, I = t & 15;
+    const int sh = patch_shell[p];
+    const ShellParams& sp = shells[sh];
+    const double pr = pressure[sh];
+    const int4 nd = patch_nodes[p];
+    const int node[4] = {nd.x, nd.y, nd.z, nd.w};
+    double f[3] = {0.0, 0.0, 0.0};
+    if (pr != 0.0)
+        for (int g = 0; g < 16; ++g) {
+            const double* ph = phi + (size_t)g * 96;
+            double a1[3] = {0.0, 0.0, 0.0}, a2[3] = {0.0, 0.0, 0.0};
+            for (int J = 0; J < 16; ++J) {
+                const double ks = kind_scale(J & 3, sp.dxi1, sp.dxi2);
+                const double* v = q + 12 * (size_t)node[J >> 2] + 3 * (J & 3);
+                const double p1 = ph[0 * 16 + J] * ks, p2 = ph[1 * 16 + J] * ks;
+                for (int c = 0; c < 3; ++c) {
+                    a1[c] += p1 * v[c];
+                    a2[c] += p2 * v[c];
+                }
+            }
+            const double s1 = slot_scale(0, sp.dxi1, sp.dxi2), s2 = slot_scale(1, sp.dxi1, sp.dxi2);
+            const double n[3] = {s1 * s2 * (a1[1] * a2[2] - a1[2] * a2[1]), s1 * s2 * (a1[2] * a2[0] - a1[0] * a2[2]),
+                                 s1 * s2 * (a1[0] * a2[1] - a1[1] * a2[0])};
+            const double w = gauss_weight(g & 3) * gauss_weight(g >> 2) * sp.dxi1 * sp.dxi2 * pr *
+                             ph[5 * 16 + I] * kind_scale(I & 3, sp.dxi1, sp.dxi2);
+            for (int c = 0; c < 3; ++c) f[c] += w * n[c];
+        }
+    double* out = g_patch + 48 * (size_t)p + 12 * (I >> 2) + 3 * (I & 3);
+    for (int c = 0; c < 3; ++c) out[c] = f[c];
+}
+
 // Per-shell sums of the three patch energies, fixed summation order.
 __global__ void k_shell_energy(int nshell, const ShellParams* __restrict__ shells, const double* __restrict__ e_patch,
                                double* __restrict__ e_shell) {
@@ -422,6 +467,14 @@ void launch_gather_grad(hipStream_t st, int nnodes, const int* inc_ptr, const in
     if (n == 0) return;
     hipLaunchKernelGGL(k_gather_grad, dim3((n + 255) / 256), dim3(256), 0, st, nnodes, inc_ptr, inc, g_patch,
                        freemask, node_shell, write_shell, grad);
+}
+
+void launch_pressure(hipStream_t st, int npatch, const int4* patch_nodes, const int* patch_shell,
+                     const ShellParams* shells, const double* pressure, const double* phi, const double* q,
+                     double* g_patch) {
+    if (npatch == 0) return;
+    hipLaunchKernelGGL(k_pressure, dim3((16 * npatch + 255) / 256), dim3(256), 0, st, npatch, patch_nodes,
+                       patch_shell, shells, pressure, phi, q, g_patch);
 }
 
 void launch_shell_energy(hipStream_t st, int nshell, const ShellParams* shells, const double* e_patch,

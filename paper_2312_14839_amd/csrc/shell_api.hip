@@ -116,6 +116,23 @@ struct shell_ctx {
     // external nodal forces (shell_set_nodal_forces)
     DevBuf fext;
     bool has_fext = false;
+    // pressure per shell (shell_set_pressure): a load evaluated at each
+    // step's start, added to fext into fstep for that step
+    DevBuf pressure, fstep;
+    bool has_pressure = false, use_fstep = false;
+    // point constraints (shell_set_point_constraints), sorted by shell:
+    // alm_order[j] is the caller's index of the j-th, alm_shell_pt [S + 1]
+    // their ranges; h_lam the multipliers [3 alm_n]; the penalty's matrix
+    // kappa C^T C merged into alm_nsp values at positions of vals
+    int alm_n = 0, alm_max_outer = 0, alm_nsp = 0;
+    double alm_kappa = 0.0, alm_tol = 0.0;
+    bool alm_on = false;   // set within shell_newton_step
+    std::vector<int> alm_order, alm_shell_pt;
+    std::vector<double> h_lam;
+    DevBuf alm_pts, alm_lam, alm_incp, alm_inc, alm_spt, alm_pos, alm_val, alm_c;
+    std::vector<int> grid_n1, grid_n2, grid_per;   // per shell
+    const double* load_vec() { return use_fstep ? dptr<double>(fstep) : dptr<double>(fext); }
+    bool has_load() const { return use_fstep || has_fext; }
     // event timing
     bool timing = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -382,6 +399,9 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
         sp.patch_begin = P;
         P += d.n1 * d.n2;
         sp.patch_end = P;
+        c->grid_n1.push_back(d.n1);
+        c->grid_n2.push_back(d.n2);
+        c->grid_per.push_back(d.periodic1 ? 1 : 0);
     }
     c->N = N;
     c->P = P;
@@ -633,8 +653,16 @@ void eval_energy_grad(shell_ctx* c, const double* q_in, const double* qhat, doub
         launch_gather_grad(st, c->N, dptr<int>(c->inc_ptr), dptr<int>(c->inc), dptr<double>(c->g_patch),
                            masked ? dptr<uint16_t>(c->freemask) : nullptr, dptr<int>(c->node_shell), write_shell_dev,
                            grad_out);
-    if (loads && c->has_fext && qhat)
-        launch_nodal_load(st, c->rb(), c->S, dptr<double>(c->fext), q_in, qhat, dptr<uint16_t>(c->freemask),
+    if (c->alm_on) {   // -lambda.c + (kappa/2)|c|^2 of the point constraints
+        if (grad_out)
+            launch_alm_grad(st, c->N, dptr<int>(c->alm_incp), dptr<int2>(c->alm_inc), dptr<AlmPoint>(c->alm_pts),
+                            dptr<double>(c->alm_lam), c->alm_kappa, q_in, masked ? dptr<uint16_t>(c->freemask) : nullptr,
+                            dptr<int>(c->node_shell), write_shell_dev, grad_out);
+        launch_alm_energy(st, c->S, dptr<int>(c->alm_spt), dptr<AlmPoint>(c->alm_pts), dptr<double>(c->alm_lam),
+                          c->alm_kappa, q_in, dptr<double>(c->e_shell));
+    }
+    if (loads && c->has_load() && qhat)
+        launch_nodal_load(st, c->rb(), c->S, c->load_vec(), q_in, qhat, dptr<uint16_t>(c->freemask),
                           dptr<int>(c->node_shell), write_shell_dev, grad_out, dptr<double>(c->red_part),
                           dptr<double>(c->e_shell));
     HIPCHK(hipGetLastError());
@@ -1292,6 +1320,12 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
         ~DampScope() { c->dt_damp = 0.0; }
     } damp_scope{c};
     c->dt_damp = dt;
+    // point constraints enter this step's energy, gradient and Hessian
+    struct AlmScope {
+        shell_ctx* c;
+        ~AlmScope() { c->alm_on = false; }
+    } alm_scope{c};
+    c->alm_on = c->alm_n > 0;
     const double t_start = now_ms();
     const int S = c->S, N12 = c->N * 12;
     hipStream_t st = c->stream;
@@ -1308,6 +1342,20 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
     launch_predict(st, N12, q_n_dev, v_n_dev, q_presc_dev, dptr<uint16_t>(c->freemask), dptr<int>(c->node_shell),
                    dptr<ShellParams>(c->shells_d), dt, qhat, q);
     HIPCHK(hipGetLastError());
+    // pressure: its load at the step's start, a dead load within the step
+    struct LoadScope {
+        shell_ctx* c;
+        ~LoadScope() { c->use_fstep = false; }
+    } load_scope{c};
+    if (c->has_pressure) {
+        launch_pressure(st, c->P, dptr<int4>(c->patch_nodes), dptr<int>(c->patch_shell), dptr<ShellParams>(c->shells_d),
+                        dptr<double>(c->pressure), dptr<double>(c->phi), q_n_dev, dptr<double>(c->g_patch));
+        launch_gather_grad(st, c->N, dptr<int>(c->inc_ptr), dptr<int>(c->inc), dptr<double>(c->g_patch), nullptr,
+                           dptr<int>(c->node_shell), nullptr, dptr<double>(c->fstep));
+        if (c->has_fext) launch_add_to<double>(st, N12, dptr<double>(c->fext), dptr<double>(c->fstep));
+        HIPCHK(hipGetLastError());
+        c->use_fstep = true;
+    }
     // E, g at the initial guess
     eval_energy_grad(c, q, qhat, ms, 1, true, g, nullptr);
     shell_dot(c, g, g, true);
@@ -1338,6 +1386,10 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
     const double eps = 2.220446049250313e-16;
     bool have_prev = false;
     double t_asm = 0, t_cg = 0;
+    // per shell: Newton iterations of the current augmented-Lagrangian round
+    // and of the rounds before, multiplier updates, last max |c|
+    std::vector<int> kk(S, 0), kbase(S, 0), outer(S, 0);
+    std::vector<double> alm_res(S, 0.0), h_c;
     for (int k = 0;; ++k) {
         // rounding floor of the gradient from the previous Hessian: 4 eps || P_free |A| |q| ||
         if (have_prev) {
@@ -1349,24 +1401,78 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
             for (int s = 0; s < S; ++s) floor_[s] = 4.0 * eps * std::sqrt(c->h_red[s]);
         }
         bool any = false;
+        std::vector<int> conv(S, 0);
         for (int s = 0; s < S; ++s) {
             if (!active[s]) continue;
             stats[s].grad_norm = gn[s];
             stats[s].grad_floor = floor_[s];
-            if (gn[s] == 0.0 || (k > 0 && gn[s] <= std::max(c->opts.newton_rtol * g0[s], floor_[s]))) {
+            if (gn[s] == 0.0 || (kk[s] > 0 && gn[s] <= std::max(c->opts.newton_rtol * g0[s], floor_[s]))) {
                 status[s] = SHELL_OK;
                 active[s] = 0;
-            } else if (k == c->opts.newton_maxit) {
+                conv[s] = 1;
+            } else if (kk[s] == c->opts.newton_maxit) {
                 status[s] = SHELL_E_NOT_CONVERGED;
                 active[s] = 0;
             }
-            any |= active[s] != 0;
         }
+        if (c->alm_on) {
+            // augmented Lagrangian (Sec. 6.1): a converged shell whose point
+            // constraints are not yet met updates its multipliers and resumes
+            bool check = false;
+            for (int s = 0; s < S; ++s) check |= conv[s] && c->alm_shell_pt[s] < c->alm_shell_pt[s + 1];
+            if (check) {
+                h_c.resize(3 * (size_t)c->alm_n);
+                launch_alm_residual(st, c->alm_n, dptr<AlmPoint>(c->alm_pts), q, dptr<double>(c->alm_c));
+                HIPCHK(hipGetLastError());
+                HIPCHK(hipMemcpyAsync(h_c.data(), c->alm_c.p, h_c.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+                sync(c);
+                std::vector<int> resume(S, 0);
+                bool any_resume = false;
+                for (int s = 0; s < S; ++s) {
+                    const int j0 = c->alm_shell_pt[s], j1 = c->alm_shell_pt[s + 1];
+                    if (!conv[s] || j0 == j1) continue;
+                    double cmax = 0.0;
+                    for (int i = 3 * j0; i < 3 * j1; ++i) cmax = std::max(cmax, std::fabs(h_c[i]));
+                    alm_res[s] = cmax;
+                    if (cmax <= c->alm_tol) continue;
+                    if (outer[s] == c->alm_max_outer) {
+                        status[s] = SHELL_E_NOT_CONVERGED;
+                        continue;
+                    }
+                    for (int i = 3 * j0; i < 3 * j1; ++i) c->h_lam[i] -= c->alm_kappa * h_c[i];
+                    outer[s]++;
+                    kbase[s] += kk[s];
+                    kk[s] = 0;
+                    status[s] = SHELL_E_NOT_CONVERGED;
+                    active[s] = resume[s] = 1;
+                    any_resume = true;
+                }
+                if (any_resume) {   // E and g of the resumed shells with the new multipliers
+                    h2d(c, c->alm_lam.p, c->h_lam.data(), c->h_lam.size() * sizeof(double));
+                    h2d(c, c->write_shell.p, resume.data(), S * sizeof(int));
+                    eval_energy_grad(c, q, qhat, ms, 1, true, g, dptr<int>(c->write_shell));
+                    shell_dot(c, g, g, true);
+                    sync(c);
+                    for (int s = 0; s < S; ++s) {
+                        if (!resume[s]) continue;
+                        const double* e = c->h_e_shell + 3 * s;
+                        E[s] = e[0] + e[1] + e[2];
+                        Escale[s] = std::fabs(e[0]) + std::fabs(e[1]) + std::fabs(e[2]);
+                        gn[s] = std::sqrt(c->h_red[s]);
+                        stats[s].grad_norm = gn[s];
+                    }
+                }
+            }
+        }
+        for (int s = 0; s < S; ++s) any |= active[s] != 0;
         if (!any) break;
         // A = K(q) + M/dt^2, block-Jacobi, regulariser on failure
         double t0 = now_ms();
         run_graph(c, c->g_asm, ms, [&] {
             assemble(c, q, ms, 1);
+            if (c->alm_on)   // + kappa C^T C of the point constraints
+                launch_add_sparse(c->stream, c->alm_nsp, dptr<long long>(c->alm_pos), dptr<double>(c->alm_val),
+                                  c->vals.p, c->fp32);
             launch_save_diag(c->stream, c->N, dptr<int>(c->diag_blk), c->vals.p, c->fp32, dptr<double>(c->diag0));
             bj_factor_enqueue(c);
         });
@@ -1527,7 +1633,7 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
             launch_copy_shell(st, c->N, gt, dptr<int>(c->node_shell), dptr<int>(c->flag_shell), g);
         }
         for (int s = 0; s < S; ++s) {
-            if (active[s]) stats[s].newton_iters = k + 1;
+            if (active[s]) stats[s].newton_iters = kbase[s] + (kk[s]++) + 1;
             if (searching[s]) {
                 status[s] = SHELL_E_LINESEARCH;
                 active[s] = 0;
@@ -1566,6 +1672,8 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
         stats[s].t_assemble_ms = t_asm;
         stats[s].t_pcg_ms = t_cg;
         stats[s].t_step_ms = t_step;
+        stats[s].alm_residual = alm_res[s];
+        stats[s].alm_outer = outer[s];
         if (status[s] < worst) worst = status[s];
     }
     if (stats_host) std::memcpy(stats_host, stats.data(), sizeof(shell_step_stats) * S);
@@ -1575,11 +1683,239 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
 }
 
 // ------------------------------------------------------------ loads
+shell_status shell_set_pressure(shell_ctx* c, const double* pressure_host) {
+    if (!c) return SHELL_E_INVAL;
+    std::vector<double> p(c->S, 0.0);
+    bool any = false;
+    if (pressure_host)
+        for (int s = 0; s < c->S; ++s) {
+            if (!std::isfinite(pressure_host[s])) {
+                c->err = "pressure not finite";
+                return SHELL_E_INVAL;
+            }
+            p[s] = pressure_host[s];
+            any |= p[s] != 0.0;
+        }
+    API_TRY
+    HIPCHK(hipSetDevice(c->opts.device));
+    if (!c->pressure.p) {
+        alloc(c->pressure, (size_t)c->S * sizeof(double));
+        alloc(c->fstep, (size_t)c->N * 12 * sizeof(double));
+    }
+    HIPCHK(hipMemcpyAsync(c->pressure.p, p.data(), (size_t)c->S * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    sync(c);
+    c->has_pressure = any;
+    c->graphs_reset();
+    return SHELL_OK;
+    API_CATCH
+}
+
+shell_status shell_pressure_load(shell_ctx* c, const double* q_dev, double* f_dev) {
+    if (!c) return SHELL_E_INVAL;
+    if (!q_dev || !f_dev) {
+        c->err = "q_dev and f_dev are required";
+        return SHELL_E_INVAL;
+    }
+    API_TRY
+    HIPCHK(hipSetDevice(c->opts.device));
+    if (!c->pressure.p) {
+        alloc(c->pressure, (size_t)c->S * sizeof(double));
+        alloc(c->fstep, (size_t)c->N * 12 * sizeof(double));
+        launch_zero(c->stream, c->pressure.p, c->pressure.n);
+    }
+    launch_pressure(c->stream, c->P, dptr<int4>(c->patch_nodes), dptr<int>(c->patch_shell),
+                    dptr<ShellParams>(c->shells_d), dptr<double>(c->pressure), dptr<double>(c->phi), q_dev,
+                    dptr<double>(c->g_patch));
+    launch_gather_grad(c->stream, c->N, dptr<int>(c->inc_ptr), dptr<int>(c->inc), dptr<double>(c->g_patch), nullptr,
+                       dptr<int>(c->node_shell), nullptr, f_dev);
+    HIPCHK(hipGetLastError());
+    return SHELL_OK;
+    API_CATCH
+}
+
+// ------------------------------------------------ point constraints
+shell_status shell_set_point_constraints(shell_ctx* c, const shell_point_constraint* pts, int32_t n,
+                                         const shell_alm_opts* o) {
+    if (!c) return SHELL_E_INVAL;
+    if (n < 0 || (n > 0 && pts && !o)) {
+        c->err = "n >= 0 and options are required";
+        return SHELL_E_INVAL;
+    }
+    if (!pts) n = 0;
+    if (n > 0 && (!(o->penalty > 0) || !std::isfinite(o->penalty) || !(o->tol > 0) || !std::isfinite(o->tol) ||
+                  o->max_outer < 0)) {
+        c->err = "need penalty > 0, tol > 0 (finite) and max_outer >= 0";
+        return SHELL_E_INVAL;
+    }
+    API_TRY
+    HIPCHK(hipSetDevice(c->opts.device));
+    const int S = c->S;
+    std::vector<AlmPoint> ap(n);
+    std::vector<int> order(n), spt(S + 1, 0);
+    for (int u = 0; u < n; ++u) {
+        const shell_point_constraint& pc = pts[u];
+        const std::string who = "point constraint " + std::to_string(u) + ": ";
+        if (pc.shell < 0 || pc.shell >= S) throw InvalErr{who + "shell index out of range"};
+        if (pc.kind < 0 || pc.kind > 2) throw InvalErr{who + "kind must be 0, 1 or 2"};
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(pc.target[k])) throw InvalErr{who + "target not finite"};
+        if (!std::isfinite(pc.xi1) || !std::isfinite(pc.xi2)) throw InvalErr{who + "point not finite"};
+        spt[pc.shell + 1]++;
+    }
+    for (int s = 0; s < S; ++s) spt[s + 1] += spt[s];
+    {
+        std::vector<int> fill(spt.begin(), spt.end() - 1);
+        for (int u = 0; u < n; ++u) order[fill[pts[u].shell]++] = u;
+    }
+    for (int j = 0; j < n; ++j) {
+        const shell_point_constraint& pc = pts[order[j]];
+        const int s = pc.shell, n1 = c->grid_n1[s], n2 = c->grid_n2[s], per = c->grid_per[s];
+        const double d1 = c->shells[s].dxi1, d2 = c->shells[s].dxi2;
+        const double L1 = n1 * d1, L2 = n2 * d2;
+        double xi1 = pc.xi1;
+        if (per) xi1 -= L1 * std::floor(xi1 / L1);
+        if (xi1 < 0 || xi1 > L1 || pc.xi2 < 0 || pc.xi2 > L2)
+            throw InvalErr{"point constraint " + std::to_string(order[j]) + ": point outside the parameter domain"};
+        const int pi = std::min((int)(xi1 / d1), n1 - 1), pj = std::min((int)(pc.xi2 / d2), n2 - 1);
+        const double t1 = xi1 / d1 - pi, t2 = pc.xi2 / d2 - pj;
+        const int cols = per ? n1 : n1 + 1;
+        AlmPoint& a = ap[j];
+        for (int cc = 0; cc < 4; ++cc) {
+            const int p = cc & 1, qq = cc >> 1;
+            int ni = pi + p;
+            if (per) ni %= n1;
+            a.node[cc] = c->shells[s].node_begin + (pj + qq) * cols + ni;
+            for (int k = 0; k < 4; ++k) {
+                const int r = k & 1, sk = k >> 1;
+                // shape function of corner cc, DOF kind k, differentiated
+                // along xi1 (kind 1) or xi2 (kind 2) for a tangent constraint
+                const double o1 = pc.kind == 1 ? 1 : 0, o2 = pc.kind == 2 ? 1 : 0;
+                a.psi[4 * cc + k] = hermite(p, r, (int)o1, t1) * hermite(qq, sk, (int)o2, t2) *
+                                    (r ? d1 : 1.0) * (sk ? d2 : 1.0) / (o1 ? d1 : 1.0) / (o2 ? d2 : 1.0);
+            }
+        }
+        for (int k = 0; k < 3; ++k) a.target[k] = pc.target[k];
+    }
+    // per node its (constraint, corner) incidences, in constraint order
+    std::vector<int> incp(c->N + 1, 0);
+    for (int j = 0; j < n; ++j)
+        for (int cc = 0; cc < 4; ++cc) incp[ap[j].node[cc] + 1]++;
+    for (int i = 0; i < c->N; ++i) incp[i + 1] += incp[i];
+    std::vector<int2> inc(incp[c->N]);
+    {
+        std::vector<int> fill(incp.begin(), incp.end() - 1);
+        for (int j = 0; j < n; ++j)
+            for (int cc = 0; cc < 4; ++cc) inc[fill[ap[j].node[cc]]++] = make_int2(j, cc);
+    }
+    // kappa C^T C: kappa psi_I psi_J on each component, merged per stored value
+    const double kappa = n > 0 ? o->penalty : 0.0;
+    std::map<long long, double> off;
+    std::map<int, std::array<double, 144>> dg;
+    auto stored = [&](int lo, int hi) {
+        const int* b = c->h_ucol.data() + c->h_urow[lo];
+        const int* e = c->h_ucol.data() + c->h_urow[lo + 1];
+        const int* f = std::lower_bound(b, e, hi);
+        if (f == e || *f != hi) throw InvalErr{"point constraint outside the block pattern"};
+        return (long long)(f - c->h_ucol.data());
+    };
+    for (int j = 0; j < n; ++j)
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) {
+                const int na = ap[j].node[a], nb = ap[j].node[b];
+                if (na > nb) continue;   // the stored block of the pair is A_{min, max}
+                std::array<double, 144>* D = nullptr;
+                long long base = 0;
+                if (na == nb) {
+                    auto it = dg.find(na);
+                    if (it == dg.end()) {
+                        std::array<double, 144> z{};
+                        it = dg.emplace(na, z).first;
+                    }
+                    D = &it->second;
+                } else {
+                    base = stored(na, nb) * 144;
+                }
+                for (int k = 0; k < 4; ++k)
+                    for (int l = 0; l < 4; ++l)
+                        for (int comp = 0; comp < 3; ++comp) {
+                            const double v = kappa * ap[j].psi[4 * a + k] * ap[j].psi[4 * b + l];
+                            const int r = 3 * k + comp, cl = 3 * l + comp;
+                            if (D)
+                                (*D)[r * 12 + cl] += v;
+                            else
+                                off[base + r * 12 + cl] += v;
+                        }
+            }
+    for (auto& kv : dg) {
+        const long long base = stored(kv.first, kv.first) * 144;
+        for (int p = 0; p < SYM12_VALS; ++p) off[base + p] += kv.second[sym12_row(p) * 12 + sym12_col(p)];
+    }
+    std::vector<long long> pos;
+    std::vector<double> val;
+    for (auto& kv : off) {
+        pos.push_back(kv.first);
+        val.push_back(kv.second);
+    }
+    hipStream_t st = c->stream;
+    sync(c);
+    upload(c->alm_pts, ap, st);
+    upload(c->alm_incp, incp, st);
+    upload(c->alm_inc, inc, st);
+    upload(c->alm_spt, spt, st);
+    upload(c->alm_pos, pos, st);
+    upload(c->alm_val, val, st);
+    c->h_lam.assign(3 * (size_t)n, 0.0);
+    upload(c->alm_lam, c->h_lam, st);
+    alloc(c->alm_c, 3 * (size_t)n * sizeof(double));
+    sync(c);
+    c->alm_n = n;
+    c->alm_nsp = (int)pos.size();
+    c->alm_kappa = kappa;
+    c->alm_tol = n > 0 ? o->tol : 0.0;
+    c->alm_max_outer = n > 0 ? o->max_outer : 0;
+    c->alm_order = order;
+    c->alm_shell_pt = spt;
+    c->graphs_reset();
+    return SHELL_OK;
+    API_CATCH
+}
+
+shell_status shell_get_point_multipliers(const shell_ctx* c, double* lambda_host) {
+    if (!c || (!lambda_host && c->alm_n > 0)) return SHELL_E_INVAL;
+    for (int j = 0; j < c->alm_n; ++j)
+        for (int k = 0; k < 3; ++k) lambda_host[3 * (size_t)c->alm_order[j] + k] = c->h_lam[3 * (size_t)j + k];
+    return SHELL_OK;
+}
+
+shell_status shell_set_point_multipliers(shell_ctx* c, const double* lambda_host) {
+    if (!c) return SHELL_E_INVAL;
+    if (!lambda_host && c->alm_n > 0) {
+        c->err = "lambda_host is required";
+        return SHELL_E_INVAL;
+    }
+    API_TRY
+    HIPCHK(hipSetDevice(c->opts.device));
+    for (int j = 0; j < c->alm_n; ++j)
+        for (int k = 0; k < 3; ++k) {
+            const double v = lambda_host[3 * (size_t)c->alm_order[j] + k];
+            if (!std::isfinite(v)) throw InvalErr{"multiplier not finite"};
+            c->h_lam[3 * (size_t)j + k] = v;
+        }
+    if (c->alm_n > 0) {
+        HIPCHK(hipMemcpyAsync(c->alm_lam.p, c->h_lam.data(), c->h_lam.size() * sizeof(double), hipMemcpyHostToDevice,
+                              c->stream));
+        sync(c);
+    }
+    return SHELL_OK;
+    API_CATCH
+}
+
 shell_status shell_set_nodal_forces(shell_ctx* c, const double* f_dev) {
     if (!c) return SHELL_E_INVAL;
     API_TRY
     HIPCHK(hipSetDevice(c->opts.device));
     if (!f_dev) {
+        if (c->has_fext) c->graphs_reset();   // the captured evaluations lose the load kernels
         c->has_fext = false;
         return SHELL_OK;
     }

@@ -71,6 +71,7 @@ class shell_step_stats(C.Structure):
         ("grad_norm0", C.c_double), ("grad_norm", C.c_double), ("grad_floor", C.c_double),
         ("reg_delta", C.c_double),
         ("t_assemble_ms", C.c_double), ("t_pcg_ms", C.c_double), ("t_step_ms", C.c_double),
+        ("alm_residual", C.c_double), ("alm_outer", C.c_int32),
     ]
 
     def as_dict(self):
@@ -118,6 +119,15 @@ class shell_collide_stats(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class shell_point_constraint(C.Structure):
+    _fields_ = [("shell", C.c_int32), ("kind", C.c_int32), ("xi1", C.c_double), ("xi2", C.c_double),
+                ("target", C.c_double * 3)]
+
+
+class shell_alm_opts(C.Structure):
+    _fields_ = [("penalty", C.c_double), ("tol", C.c_double), ("max_outer", C.c_int32)]
 
 
 def colliders(specs):
@@ -174,6 +184,16 @@ def _load():
     lib.shell_timing_enable.restype = C.c_int32
     lib.shell_timing_get.argtypes = [vp, P(shell_timing)]
     lib.shell_timing_get.restype = C.c_int32
+    lib.shell_set_pressure.argtypes = [vp, P(C.c_double)]
+    lib.shell_set_pressure.restype = C.c_int32
+    lib.shell_pressure_load.argtypes = [vp, vp, vp]
+    lib.shell_pressure_load.restype = C.c_int32
+    lib.shell_set_point_constraints.argtypes = [vp, P(shell_point_constraint), C.c_int32, P(shell_alm_opts)]
+    lib.shell_set_point_constraints.restype = C.c_int32
+    lib.shell_get_point_multipliers.argtypes = [vp, P(C.c_double)]
+    lib.shell_get_point_multipliers.restype = C.c_int32
+    lib.shell_set_point_multipliers.argtypes = [vp, P(C.c_double)]
+    lib.shell_set_point_multipliers.restype = C.c_int32
     lib.shell_set_nodal_forces.argtypes = [vp, vp]
     lib.shell_set_nodal_forces.restype = C.c_int32
     lib.shell_point_load.argtypes = [P(shell_desc), C.c_double, C.c_double, P(C.c_double), P(C.c_double)]
@@ -221,7 +241,8 @@ EXPORTED = ["shell_default_opts", "shell_create", "shell_destroy", "shell_last_e
             "shell_mlp_get_params", "shell_mlp_forward", "shell_mlp_loss_grad", "shell_mlp_train",
             "shell_mlp_record", "shell_mlp_recorded", "shell_autotune", "shell_set_nodal_forces",
             "shell_point_load", "shell_bezier", "shell_ray_default_opts", "shell_ray_cast", "shell_ray_cast_noalloc",
-            "shell_ccd", "shell_collide_default_opts", "shell_collide"]
+            "shell_ccd", "shell_collide_default_opts", "shell_collide", "shell_set_pressure", "shell_pressure_load",
+            "shell_set_point_constraints", "shell_get_point_multipliers", "shell_set_point_multipliers"]
 
 MLP_IN, MLP_HIDDEN, MLP_OUT = 36, 128, 12
 MLP_PARAMS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_OUT + MLP_OUT
@@ -361,6 +382,42 @@ class ShellContext:
         self._check(lib.shell_collide(self.h, float(dt), _ptr(q_n), _ptr(q_np1), _ptr(v), colliders(specs),
                                       len(specs), C.byref(o), _ptr(q_out), _ptr(v_out), C.byref(st)))
         return st.as_dict()
+
+    def set_pressure(self, pressures):
+        """Pressure per shell (Pa, along a_1 x a_2); None removes it."""
+        if pressures is None:
+            self._check(lib.shell_set_pressure(self.h, None))
+            return
+        arr = np.ascontiguousarray(pressures, dtype=np.float64)
+        assert arr.size == self.n_shells
+        self._check(lib.shell_set_pressure(self.h, arr.ctypes.data_as(C.POINTER(C.c_double))))
+
+    def pressure_load(self, q, f):
+        self._check(lib.shell_pressure_load(self.h, _ptr(q), _ptr(f)))
+
+    def set_point_constraints(self, points, penalty=1e4, tol=1e-10, max_outer=30):
+        """Point constraints (shell, kind, xi1, xi2, target[3]) imposed by the
+        augmented Lagrangian method in later Newton steps; [] removes them.
+        Multipliers start at zero."""
+        n = len(points)
+        arr = (shell_point_constraint * max(n, 1))()
+        for i, (sh, kind, xi1, xi2, tgt) in enumerate(points):
+            arr[i].shell, arr[i].kind, arr[i].xi1, arr[i].xi2 = int(sh), int(kind), float(xi1), float(xi2)
+            for k in range(3):
+                arr[i].target[k] = float(tgt[k])
+        o = shell_alm_opts(float(penalty), float(tol), int(max_outer))
+        self._check(lib.shell_set_point_constraints(self.h, arr if n else None, n, C.byref(o)))
+        self._n_points = n
+
+    def point_multipliers(self):
+        lam = np.zeros((getattr(self, "_n_points", 0), 3))
+        self._check(lib.shell_get_point_multipliers(self.h, lam.ctypes.data_as(C.POINTER(C.c_double))))
+        return lam
+
+    def set_point_multipliers(self, lam):
+        arr = np.ascontiguousarray(lam, dtype=np.float64).reshape(-1)
+        assert arr.size == 3 * getattr(self, "_n_points", 0)
+        self._check(lib.shell_set_point_multipliers(self.h, arr.ctypes.data_as(C.POINTER(C.c_double))))
 
     def set_nodal_forces(self, f):
         self._check(lib.shell_set_nodal_forces(self.h, _ptr(f)))

@@ -157,3 +157,31 @@ def test_ccd_validation():
     assert lib.shell_ccd(fake, None, 1, fake, 1, 1.0, C.byref(o), fake, fake, None) == s.SHELL_E_INVAL
     assert lib.shell_ccd(fake, fake, 1, fake, 1, 1.0, None, fake, fake, None) == s.SHELL_E_INVAL
     assert lib.shell_ccd(fake, fake, 1, fake, 1, 1.0, C.byref(s.ray_opts(eps=0.0)), fake, fake, None) == s.SHELL_E_INVAL
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every ctypes mirror of a header struct has the header's field offsets
+    and size (a C program built with gcc against the header prints them)."""
+    import subprocess
+    s = S()
+    structs = [s.shell_desc, s.shell_opts, s.shell_step_stats, s.shell_timing, s.shell_tune_result,
+               s.shell_ray_opts, s.shell_collider, s.shell_collide_opts, s.shell_collide_stats,
+               s.shell_point_constraint, s.shell_alm_opts]
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "bhem_shell.h"', 'int main(void) {']
+    for st in structs:
+        n = st.__name__
+        lines.append(f'printf("{n} %zu\\n", sizeof({n}));')
+        for f, _ in st._fields_:
+            lines.append(f'printf("{n}.{f} %zu\\n", offsetof({n}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                  check=True).stdout.splitlines())
+    for st in structs:
+        n = st.__name__
+        assert int(got[n]) == C.sizeof(st), n
+        for f, _ in st._fields_:
+            assert int(got[f"{n}.{f}"]) == getattr(st, f).offset, (n, f)

@@ -6,8 +6,9 @@ onto a sphere over several Newton steps with the collision pass after each
 (per-step parity: the oracle gets the GPU's own step each time).
 
 Tolerances: contact time and contact counts exact up to rounding of the
-sample points (1e-13); states 1e-9 relative (the constraint solves run CG
-to 1e-12 on J M^-1 J^T and 1e-13 on M)."""
+sample points (1e-13); states 1e-9 relative to the larger of the incoming
+and resolved velocities (the constraint solves run CG to 1e-12 on
+J M^-1 J^T and 1e-13 on M)."""
 import numpy as np
 import pytest
 
@@ -50,7 +51,10 @@ def check(r, st, qo, vo, v, tol=1e-9):
     if np.isfinite(r["t_star"]):
         assert abs(st["t_contact"] - r["t_star"]) <= 1e-13 * max(1.0, r["t_star"])
     assert st["contacts"] == len(r["contacts"]) and st["approaching"] == len(r["approach"])
-    scale_v = max(np.abs(v).max(), 1e-300)
+    # relative to the larger of the incoming and the resolved velocities: a
+    # coupled band of contacts can change the twist DOFs by far more than the
+    # incoming speed, and the constraint solves are relative to their result
+    scale_v = max(np.abs(v).max(), np.abs(r["v"]).max(), 1e-300)
     assert np.abs(vo - r["v"]).max() <= tol * scale_v, np.abs(vo - r["v"]).max()
     dq_ref = r["q"] - (r["q_rollback"] if "q_rollback" in r else r["q"])
     scale_q = max(np.abs(dq_ref).max(), 1e-4)

@@ -21,7 +21,9 @@ from paper_2312_14839_amd import workloads as W
 
 import test_oracle_basis as TB
 import test_oracle_mechanics as TM
+import test_oracle_alm as TA
 import test_oracle_newton as TN
+import test_oracle_pressure as TP
 import test_oracle_ray as TR
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -93,6 +95,18 @@ MUTANTS = [
          "if (!pseudo) for (int i = 0; i < 3; ++i) add_identity(d2al[i] * Ha[i], G1);"),
         ("patch.cpp", "                if (!pseudo) {\n                    for (int i = 0; i < 3; ++i) {",
          "                if (true) {\n                    for (int i = 0; i < 3; ++i) {")]),
+    ("pressure along a_2 x a_1", "patch.cpp", "const V3<double> n = cross(cur.a[0], cur.a[1]);",
+     "const V3<double> n = cross(cur.a[1], cur.a[0]);"),
+    ("pressure per unit parameter area along the unit normal", "patch.cpp", "const double wq = qp[g].weight * p;",
+     "const double wq = qp[g].weight * p / cur.sqrta;"),
+    ("pressure weighted by the xi1-slope of the shape function", "patch.cpp",
+     "f[3 * I + c] += wq * qp[g].phi[0][I] * compc(n, c);", "f[3 * I + c] += wq * qp[g].phi[1][I] * compc(n, c);"),
+    ("augmented Lagrangian: multiplier update with the wrong sign", "global.cpp",
+     "alm->lambda[i] -= alm->penalty * cc[i];", "alm->lambda[i] += alm->penalty * cc[i];"),
+    ("augmented Lagrangian: multiplier term of the gradient with the wrong sign", "global.cpp",
+     "const double w = alm->penalty * c[comp] - lam;", "const double w = alm->penalty * c[comp] + lam;"),
+    ("point constraint on the position whatever its kind", "global.cpp",
+     "for (int I = 0; I < 16; ++I) psi[I] = ph[pc.kind][I];", "for (int I = 0; I < 16; ++I) psi[I] = ph[0][I];"),
     ("pseudo Hessian also drops the membrane geometric term", "patch.cpp",
      "for (int i = 0; i < 3; ++i) add_identity(d2al[i] * Ha[i], G1);",
      "if (!pseudo) for (int i = 0; i < 3; ++i) add_identity(d2al[i] * Ha[i], G1);"),
@@ -130,6 +144,10 @@ def _pins():
              TN.test_iteration_cap_returns_the_last_iterate, TN.test_indefinite_beyond_the_regulariser_cap,
              TN.test_pseudo_equals_exact_hessian_in_a_pure_membrane_state,
              TN.test_pseudo_hessian_keeps_the_membrane_part_and_a_semidefinite_bending_part]
+    pins += [TP.test_flat_sheet_total_force_and_moment, lambda: TP.test_force_is_the_derivative_of_the_enclosed_volume(1),
+             TP.test_pressurised_cylinder_hoop_closed_form]
+    pins += [TA.test_kkt_at_the_result, TA.test_moving_target_of_a_free_sheet_needs_no_force]
+    pins += [lambda k=k: TA.test_constraint_at_a_node_is_the_nodal_constraint(k) for k in (0, 1, 2)]
     rows = TB._golden("dof_counts.txt")
     pins += [lambda r=r: TB.test_printed_dof_and_nonzero_counts(r) for r in rows]
     return pins
