@@ -212,7 +212,7 @@ def roofline(case, timing, fp32, layout=None):
         total = cg_bytes(case, timing, tb, tb, cg_resident(layout, fp32))
         ach = total / (ms[grp] * 1e-3) / 1e9
         traffic = profiled_traffic(case, fp32, "k_cg")
-        inst = "register-resident u, r, x" if cg_resident(layout, fp32) else "vectors in memory"
+        inst = "single-reduction, r, x, p, s, w resident" if cg_resident(layout, fp32) else "vectors in memory"
         return grp, {"kernel": f"k_cg (persistent block-Jacobi CG, {inst})", "bound": "hbm", "achieved": ach,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
@@ -562,6 +562,106 @@ def collision_section(stream, steps=40):
     return out
 
 
+def batch_section(stream, steps=3, warmup=1):
+    """The 256-sheet batch in one context (a14): 256 flat sheets with patch
+    grids U{8..64}^2, one persistent CG launch for all of them per Newton
+    iteration; FP64, the CG layout autotuned; wall time per step and patch
+    evaluations per second (each Newton iteration of a shell evaluates all
+    of its patches)."""
+    case_list, desc, tol = make_case("batch")
+    case = Batch(case_list)
+    wall, st, tm, tune = run_steps(case, 0, steps, warmup, stream, tol, True)
+    cg_its = sum(s["pcg_iters_total"] for s in st) / steps
+    out = {"workload": desc, "shells": len(case_list), "patches": case.patches, "dof": 12 * case.nodes,
+           "ms_per_step": 1e3 * wall / steps, "patch_evals_per_s": sum(s["patch_evals"] for s in st) / wall,
+           "newton_iters_per_step_slowest_shell": sum(s["newton_iters"] for s in st) / steps,
+           "cg_iters_per_step_summed": cg_its, "cg_layout": tune, "kernel_ms_event_timed_steps": tm["ms"],
+           "cg_launches_event_timed_steps": tm["launches"]["cg"]}
+    print(f"[bench] batch: {out['ms_per_step']:.1f} ms/step, {out['patch_evals_per_s'] / 1e6:.2f} M patch evals/s",
+          file=sys.stderr, flush=True)
+    return out
+
+
+def loads_section(stream, steps=3):
+    """Follower pressure (Sec. 4.3) and point constraints imposed by the
+    augmented Lagrangian method (Sec. 4.2, 6.1) at scale.  (a) The 256x256
+    cylinder of the main workload with an internal pressure of 5 Pa, its
+    load evaluated at each step's start, against the same steps without it.
+    (b) A 64x64-patch sheet under gravity held only at two points inside
+    patches and with one prescribed tangent there, against the same sheet
+    with its edge y = 0 clamped instead (nodal constraints)."""
+    import torch
+    from paper_2312_14839_amd import shell as S, workloads as W
+    out = {}
+    cyl = W.case_cylinder(256, 256)
+    presc = presc_on_device(cyl, steps + 1)
+    for label, p in (("no_pressure", None), ("pressure_5Pa", [5.0])):
+        ctx = S.context_for([cyl], stream=stream, newton_rtol=1e-10, pcg_rtol=1e-8)
+        if p is not None:
+            ctx.set_pressure(p)
+        q = torch.from_numpy(cyl.q0.reshape(-1).copy()).cuda()
+        v = torch.zeros_like(q)
+        q1, v1 = torch.empty_like(q), torch.empty_like(q)
+        ctx.newton_step(cyl.dt, q, v, presc[0], q1, v1)   # warm-up (graph capture)
+        q, q1, v, v1 = q1, q, v1, v
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = cg = 0
+        for k in range(steps):
+            rc, st = ctx.newton_step(cyl.dt, q, v, presc[k + 1], q1, v1)
+            its += st[0]["newton_iters"]
+            cg += st[0]["pcg_iters_total"]
+            q, q1, v, v1 = q1, q, v1, v
+        torch.cuda.synchronize()
+        out[label] = {"ms_per_step": 1e3 * (time.perf_counter() - t0) / steps, "newton_iters_per_step": its / steps,
+                      "cg_iters_per_step": cg / steps}
+        ctx.close()
+    n = 64
+    free = W.sheet_case(n, edges=(), sigma=0.0, dt=5e-3)
+    clamped = W.sheet_case(n, edges=("y0",), sigma=0.0, dt=5e-3)
+    # two points inside patches near the edge y = 0 held at their reference
+    # positions, and the tangent x_xi2 at the first one prescribed
+    pts = []
+    for xi1 in (0.2 + 0.3 / n, 0.8 + 0.3 / n):
+        xi2 = 0.6 / n
+        pts.append((0, 0, xi1, xi2, (xi1, xi2, 0.0)))
+    pts.append((0, 2, pts[0][2], pts[0][3], (0.0, 1.0, 0.0)))
+    for label, case, cons in (("nodal_clamp", clamped, None), ("point_constraints", free, pts)):
+        ctx = S.context_for([case], stream=stream)
+        if cons:
+            ctx.set_point_constraints(cons, penalty=1e4, tol=1e-9)
+        q = torch.from_numpy(case.q0.reshape(-1).copy()).cuda()
+        v = torch.zeros_like(q)
+        q1, v1 = torch.empty_like(q), torch.empty_like(q)
+        rc, st = ctx.newton_step(case.dt, q, v, None, q1, v1)
+        q, q1, v, v1 = q1, q, v1, v
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = cg = outer = 0
+        res = 0.0
+        for k in range(steps):
+            rc, st = ctx.newton_step(case.dt, q, v, None, q1, v1)
+            its += st[0]["newton_iters"]
+            cg += st[0]["pcg_iters_total"]
+            outer += st[0]["alm_outer"]
+            res = max(res, st[0]["alm_residual"])
+            q, q1, v, v1 = q1, q, v1, v
+        torch.cuda.synchronize()
+        out[label] = {"ms_per_step": 1e3 * (time.perf_counter() - t0) / steps, "newton_iters_per_step": its / steps,
+                      "cg_iters_per_step": cg / steps}
+        if cons:
+            out[label].update(multiplier_updates_per_step=outer / steps, max_constraint_residual=res,
+                              constraints=len(cons))
+        ctx.close()
+    out["workload"] = ("cylinder 256x256 with and without 5 Pa internal pressure (steps 2-4); sheet 64x64, "
+                       "gravity, dt 5 ms, edge y=0 clamped vs held at two interior points + one tangent "
+                       "(penalty 1e4, tol 1e-9), steps 2-4")
+    print(f"[bench] loads: cylinder {out['no_pressure']['ms_per_step']:.1f} -> {out['pressure_5Pa']['ms_per_step']:.1f} "
+          f"ms/step with pressure; sheet clamp {out['nodal_clamp']['ms_per_step']:.1f} ms/step, point constraints "
+          f"{out['point_constraints']['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
+    return out
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -828,6 +928,8 @@ def main():
     ap.add_argument("--no-twist", action="store_true", help="skip the 200-step 30x30 twist section")
     ap.add_argument("--no-render", action="store_true", help="skip the ray--patch intersection section")
     ap.add_argument("--no-collision", action="store_true", help="skip the collision-handling section")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-sheet batch section")
+    ap.add_argument("--no-loads", action="store_true", help="skip the pressure / point-constraint section")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="first run a plain device copy of MB megabytes (counter calibration)")
     args = ap.parse_args()
@@ -900,6 +1002,10 @@ def main():
         out["render"] = render_section(stream)
     if args.workload == "cylinder" and not args.no_collision:
         out["collision"] = collision_section(stream)
+    if args.workload == "cylinder" and not args.no_loads:
+        out["loads"] = loads_section(stream)
+    if args.workload == "cylinder" and not args.no_batch:
+        out["batch"] = batch_section(stream)
     if not args.no_learned:
         out["learned"] = learned_section(stream)
     if not args.no_cpu_baseline:
