@@ -475,17 +475,24 @@ def learned_section(stream):
     res = {"plain": [0, 0.0], "learned": [0, 0.0], "extrapolation_only": [0, 0.0]}
     zero = L.init_params(0)
     steps = 12
+    strict = True
     for sc in scenes:
+        per = {}
         for key, th in (("plain", None), ("learned", theta), ("extrapolation_only", zero)):
             L.run(sc, 2, theta=th, stream=stream)                      # warm-up (graph capture, caches)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             r = L.run(sc, steps, theta=th, stream=stream)
             torch.cuda.synchronize()
-            res[key][0] += int(np.sum(r["pcg_iters"]))
+            per[key] = int(np.sum(r["pcg_iters"]))
+            res[key][0] += per[key]
             res[key][1] += time.perf_counter() - t0
+        strict = strict and per["learned"] < per["extrapolation_only"]
     nsteps = steps * len(scenes)
     out = {k: {"cg_iters_per_step": v[0] / nsteps, "ms_per_step": 1e3 * v[1] / nsteps} for k, v in res.items()}
+    # the gate's rule: the network counts only if it beats the same start
+    # without it (extrapolation of the previous correction) on every scene
+    out["network_accepted"] = bool(strict)
     out.update({"train_steps": int(losses.size), "train_loss_first": float(np.mean(losses[:20])),
                 "train_loss_last": float(np.mean(losses[-100:])), "record_s": t_rec, "train_s": t_train,
                 "eval": "twist/compression 64x64 (seeds 906, 910) and 128x128 (seed 903), 12 steps each, dt 2e-3"})

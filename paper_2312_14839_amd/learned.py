@@ -6,8 +6,9 @@ described with the ``shell_mlp_*`` declarations of the C header).  This
 module only orchestrates: it steps scenes of several shells through one
 context, records training samples from the solver's own time steps, trains
 the network with the library's kernels, and applies the acceptance gate that
-keeps a trained network only if it lowers the CG iteration count against the
-plain solver on held-out scenes.  Every computation runs in libbhem.
+keeps a trained network only if it lowers the CG iteration count on
+held-out scenes below that of the same warm start without the network
+(extrapolation of the previous correction only).  Every computation runs in libbhem.
 """
 from __future__ import annotations
 
@@ -124,15 +125,21 @@ def training_scene(count: int = 12, seed: int = 100, nmin: int = 24, nmax: int =
 
 def gate(theta: np.ndarray, scenes: Sequence[Scene], steps: int, **kw) -> Dict:
     """Acceptance gate: the network is kept only if, on every held-out scene,
-    CG needs fewer iterations with it than block-Jacobi alone and the
-    results agree.  Returns the per-scene counts and the decision."""
-    plain, learned, accept = [], [], True
+    CG needs strictly fewer iterations with it than with the
+    extrapolation-only start (the same warm start with a zero network, i.e.
+    everything but the network's own contribution) and every step of both
+    converged.  Returns the per-scene CG iteration counts of the plain
+    solver, the extrapolation-only start and the learned start, and the
+    decision."""
+    zero = init_params(0)
+    plain, extra, learned, accept = [], [], [], True
     for sc in scenes:
         a = run(sc, steps, **kw)
+        e = run(sc, steps, theta=zero, **kw)
         b = run(sc, steps, theta=theta, **kw)
-        ia, ib = int(np.sum(a["pcg_iters"])), int(np.sum(b["pcg_iters"]))
-        plain.append(ia)
-        learned.append(ib)
-        ok = all(s == S.SHELL_OK for s in a["status"] + b["status"])
-        accept = accept and ok and ib < ia
-    return {"accept": accept, "plain_iters": plain, "learned_iters": learned}
+        plain.append(int(np.sum(a["pcg_iters"])))
+        extra.append(int(np.sum(e["pcg_iters"])))
+        learned.append(int(np.sum(b["pcg_iters"])))
+        ok = all(s == S.SHELL_OK for s in a["status"] + e["status"] + b["status"])
+        accept = accept and ok and learned[-1] < extra[-1]
+    return {"accept": accept, "plain_iters": plain, "extrapolation_iters": extra, "learned_iters": learned}
