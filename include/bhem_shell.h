@@ -95,6 +95,16 @@ typedef struct {
                                     its own rows' residual, solution and product in registers
                                     instead of device memory; 0: always in device memory (same
                                     arithmetic, for comparison) */
+    int32_t device_newton;       /* 1: each Newton iteration (Sec. 6.1) is one launch sequence, a
+                                    single HIP graph when graphs is on: assembly, factorisation, the
+                                    CG (mixed form: up to 2 refinement sweeps), the slope, up to 2
+                                    line-search trials and the next convergence test, every decision
+                                    taken on the device per shell; the host reads the shells' state
+                                    once per iteration and finishes only a shell that needs the
+                                    regulariser, more sweeps or more trials, with the same arithmetic
+                                    as the host-driven iteration (0).  Not with point constraints or
+                                    event timing on, which use the host-driven iteration.  The
+                                    iteration's time counts as t_pcg_ms. */
 } shell_opts;
 
 /* Per-shell statistics of one shell_newton_step. */
@@ -113,7 +123,8 @@ typedef struct {
 
 /* Default options: FP64, exact Hessian, no warm start, newton_rtol = pcg_rtol
  * = 1e-10, 50 Newton and 100000 CG iterations, device 0, default stream,
- * graphs on, register-resident CG vectors on. */
+ * graphs on, register-resident CG vectors on, device-driven Newton
+ * iterations on. */
 void shell_default_opts(shell_opts *o);
 
 /* Create a context for n_shells shells (batching: one context holds all of

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = ["patch_kernels.hip", "solver_kernels.hip", "mlp_kernels.hip", "ray_kernels.hip", "collision_kernels.hip",
-           "constraint_kernels.hip", "shell_api.hip"]
+           "constraint_kernels.hip", "newton_kernels.hip", "shell_api.hip"]
 LIB = os.path.join(HERE, "libbhem.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -11,7 +11,7 @@ namespace bhem {
 void launch_energy_grad(hipStream_t st, int npatch, const int4* patch_nodes, const int* patch_shell,
                         const ShellParams* shells, const double* phi, const double* q, const double* qbar,
                         const double* qhat, double mass_scale, double dt_damp, int elastic, int loads,
-                        double* e_patch, double* g_patch);
+                        const int* eval_shell /* NULL: every shell */, double* e_patch, double* g_patch);
 void launch_gather_grad(hipStream_t st, int nnodes, const int* inc_ptr, const int* inc, const double* g_patch,
                         const uint16_t* freemask, const int* node_shell, const int* write_shell, double* grad);
 void launch_shell_energy(hipStream_t st, int nshell, const ShellParams* shells, const double* e_patch,
@@ -146,6 +146,41 @@ struct CgShellOut {
     int iters, status;       // status: 0 converged, 1 iteration cap, 2 p^T A p <= 0, 3 barrier timeout
     double bnorm2, rnorm2;   // ||b||^2 and the final recursive ||r||^2
 };
+
+// Per-shell state of the device-driven Newton iteration (newton_kernels.hip):
+// written by the host before each iteration, updated by the control kernels
+// between the iteration's matrix and vector kernels, read back once.
+constexpr int NT_STATUS_OK = 0, NT_STATUS_NOT_CONVERGED = -4;   // shell_status values
+// stage at which a shell leaves the device iteration to the host
+constexpr int NT_HOST_FACTOR = 1, NT_HOST_INDEFINITE = 2, NT_HOST_LINESEARCH = 3, NT_HOST_REFINE = 4;
+struct NewtonCtl {
+    double E, Escale, gn, g0;           // incremental potential, its scale, ||g||, ||g|| at the step's start
+    double floor, grad_norm_checked;    // rounding floor and ||g|| at the last convergence test
+    double slope, alpha, a_prev, E_prev;   // line search
+    double bn2, prev, relres;           // refinement (mixed form): ||b||^2, last relative residual
+    int active;                         // the shell iterates
+    int k;                              // Newton iterations of this step
+    int status;                         // shell status once inactive
+    int need_host;                      // 0 or the NT_HOST_ stage the host takes over at
+    int solving, refining, searching, steepest, trial;
+    int pcg_iters, solve_iters, sweeps, backtracks, newton_iters;   // counted on the device
+    int fault;                          // a CG launch gave up on its grid barrier (status 3)
+};
+void launch_nt_factor(hipStream_t st, int S, NewtonCtl* ctl, const int* fail_shell, int* cg_active, double* cg_rtol2,
+                      int* cg_maxit, double pcg_rtol, int pcg_maxit);
+void launch_nt_cg64(hipStream_t st, int S, NewtonCtl* ctl, const CgShellOut* out, int* flag_shell);
+void launch_nt_ref_init(hipStream_t st, int S, NewtonCtl* ctl, const double* red, int* cg_active, double* cg_rtol2,
+                        double pcg_rtol);
+void launch_nt_ref_cg(hipStream_t st, int S, NewtonCtl* ctl, const CgShellOut* out, int* cg_active);
+void launch_nt_ref_check(hipStream_t st, int S, NewtonCtl* ctl, const double* red, int* cg_active, double* cg_rtol2,
+                         double pcg_rtol, int pcg_maxit);
+void launch_nt_ref_end(hipStream_t st, int S, NewtonCtl* ctl, int* flag_shell);
+void launch_nt_ls_init(hipStream_t st, int S, NewtonCtl* ctl, const double* red, double* alpha_shell,
+                       int* flag_shell, int* write_shell);
+void launch_nt_ls_step(hipStream_t st, int S, int trial, NewtonCtl* ctl, const double* e_shell, const double* red,
+                       double* alpha_shell, int* flag_shell, int* write_shell);
+void launch_nt_ls_end(hipStream_t st, int S, NewtonCtl* ctl);
+void launch_nt_check(hipStream_t st, int S, NewtonCtl* ctl, const double* red, double newton_rtol, int newton_maxit);
 
 // Symmetric block storage: block row i stores its blocks (i, j >= i), the
 // diagonal first; the stored block of pair (i, j) holds A_ji column-major

@@ -40,13 +40,16 @@ __global__ __launch_bounds__(256) void k_energy_grad(int npatch, const int4* __r
                                                      const double* __restrict__ q, const double* __restrict__ qbar,
                                                      const double* __restrict__ qhat, double mass_scale,
                                                      double dt_damp, int elastic, int loads,
+                                                     const int* __restrict__ eval_shell,
                                                      double* __restrict__ e_patch,
                                                      double* __restrict__ g_patch) {
     __shared__ double s_u[EG_PATCHES][48], s_b[EG_PATCHES][48], s_d[EG_PATCHES][48];
     __shared__ double s_dpsi[EG_PATCHES][16][18];
     const int lane = threadIdx.x & 15, pl = threadIdx.x >> 4;
     const int patch = blockIdx.x * EG_PATCHES + pl;
-    const bool active = patch < npatch;
+    // eval_shell (or NULL: all): the patches of other shells are skipped and
+    // keep their previous outputs
+    const bool active = patch < npatch && (!eval_shell || eval_shell[patch_shell[patch]]);
     ShellParams sp;
     int4 nd = make_int4(0, 0, 0, 0);
     if (active) {
@@ -454,11 +457,11 @@ __global__ __launch_bounds__(256) void k_hessian(const int* __restrict__ patch_l
 void launch_energy_grad(hipStream_t st, int npatch, const int4* patch_nodes, const int* patch_shell,
                         const ShellParams* shells, const double* phi, const double* q, const double* qbar,
                         const double* qhat, double mass_scale, double dt_damp, int elastic, int loads,
-                        double* e_patch, double* g_patch) {
+                        const int* eval_shell, double* e_patch, double* g_patch) {
     if (npatch == 0) return;
     const int nb = (npatch + EG_PATCHES - 1) / EG_PATCHES;
     hipLaunchKernelGGL(k_energy_grad, dim3(nb), dim3(256), 0, st, npatch, patch_nodes, patch_shell, shells, phi, q,
-                       qbar, qhat, mass_scale, dt_damp, elastic, loads, e_patch, g_patch);
+                       qbar, qhat, mass_scale, dt_damp, elastic, loads, eval_shell, e_patch, g_patch);
 }
 
 void launch_gather_grad(hipStream_t st, int nnodes, const int* inc_ptr, const int* inc, const double* g_patch,

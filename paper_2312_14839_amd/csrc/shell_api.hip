@@ -68,12 +68,13 @@ struct shell_ctx {
     // Newton / CG work vectors (FP64 [N*12] unless noted)
     DevBuf qhat, q, qt, g, gt, dvec, rhs, cg_x, cg_r, cg_z, cg_p0, cg_p1, cg_q, r64, x64;
     DevBuf cg_partial, cg_bar, cg_abort, cg_rtol2, cg_maxit, cg_active, cg_out, fail_shell, delta_shell, alpha_shell,
-        flag_shell, write_shell;
+        flag_shell, write_shell, nt_ctl;
     // pinned host mirrors
     double* h_e_shell = nullptr;   // [S*3]
     double* h_red = nullptr;       // [S]
     CgShellOut* h_cg_out = nullptr;
     int* h_fail = nullptr;
+    NewtonCtl* h_ctl = nullptr;    // [S] per-shell state of the device-driven Newton iteration
     char* h_stage = nullptr;       // staging of control uploads
     size_t stage_cap = 0, stage_off = 0;
     // warm-start network: FP32 master weights, bf16 operand copies, Adam state
@@ -100,9 +101,9 @@ struct shell_ctx {
     bool graphs = true;
     bool cg_resident = true;   // register-resident CG vectors where the layout allows
     hipStream_t cap_stream = nullptr;
-    Seg g_asm, g_trial, g_floor, g_cg;
+    Seg g_asm, g_trial, g_floor, g_cg, g_newton;
     void graphs_reset() {
-        for (Seg* g : {&g_asm, &g_trial, &g_floor, &g_cg}) {
+        for (Seg* g : {&g_asm, &g_trial, &g_floor, &g_cg, &g_newton}) {
             if (g->exec) (void)hipGraphExecDestroy(g->exec);
             g->exec = nullptr;
         }
@@ -156,6 +157,7 @@ struct shell_ctx {
         if (h_red) (void)hipHostFree(h_red);
         if (h_cg_out) (void)hipHostFree(h_cg_out);
         if (h_fail) (void)hipHostFree(h_fail);
+        if (h_ctl) (void)hipHostFree(h_ctl);
         if (h_stage) (void)hipHostFree(h_stage);
     }
 };
@@ -303,9 +305,10 @@ void validate(const shell_desc& d, int s) {
 // multiple of the rows one pass of the block covers, at least `spread` x
 // the fewest that fit all blocks on the device at once; spread = 0: the
 // fewest rows per block that fit (every co-resident slot used, the last
-// pass of a block partly idle).  Uploads the layout and sizes the per-block
-// buffers.  False if the shells do not fit (more shells than co-resident
-// blocks).
+// pass of a block partly idle); spread = -1: one block per shell (the CG of
+// a shell of one block needs no grid barrier).  Uploads the layout and sizes
+// the per-block buffers.  False if the shells do not fit (more shells than
+// co-resident blocks).
 bool set_row_blocks(shell_ctx* c, int nt, int spread) {
     const int S = c->S, N = c->N;
     const int cap = cg_max_blocks(c->opts.device, c->fp32, nt);
@@ -315,13 +318,18 @@ bool set_row_blocks(shell_ctx* c, int nt, int spread) {
     int target = std::max(pass, (N + cap - 1) / cap);
     target = ((target + pass - 1) / pass) * pass;
     int used = 0;
-    for (;; target += pass) {   // grow the rows per block until every block fits on the device at once
-        used = 0;
-        for (int s = 0; s < S; ++s)
-            used += std::max(1, (c->shells[s].node_end - c->shells[s].node_begin + target - 1) / target);
-        if (used <= cap) break;
+    if (spread < 0) {
+        target = 1;
+        for (int s = 0; s < S; ++s) target = std::max(target, c->shells[s].node_end - c->shells[s].node_begin);
+    } else {
+        for (;; target += pass) {   // grow the rows per block until every block fits on the device at once
+            used = 0;
+            for (int s = 0; s < S; ++s)
+                used += std::max(1, (c->shells[s].node_end - c->shells[s].node_begin + target - 1) / target);
+            if (used <= cap) break;
+        }
+        target *= std::max(1, spread);
     }
-    target *= std::max(1, spread);
     std::vector<int> bshell, brow0, brow1;
     c->h_shell_blk0.assign(S, 0);
     c->h_shell_nblk.assign(S, 0);
@@ -635,19 +643,25 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
     HIPCHK(hipHostMalloc((void**)&c->h_red, (size_t)S * sizeof(double), 0));
     HIPCHK(hipHostMalloc((void**)&c->h_cg_out, (size_t)S * sizeof(CgShellOut), 0));
     HIPCHK(hipHostMalloc((void**)&c->h_fail, (size_t)S * sizeof(int), 0));
+    HIPCHK(hipHostMalloc((void**)&c->h_ctl, (size_t)S * sizeof(NewtonCtl), 0));
+    alloc(c->nt_ctl, (size_t)S * sizeof(NewtonCtl));
     HIPCHK(hipMemsetAsync(c->vals.p, 0, c->vals.n, st));
     sync(c);
 }
 
 // -------------------------------------------------------- building blocks
 // Energies (three parts per shell, host) and gradient at q_in.
+// eval_shell_dev: only the patches of shells flagged there are evaluated
+// (the others keep their previous patch outputs); NULL: every shell.
 void eval_energy_grad(shell_ctx* c, const double* q_in, const double* qhat, double mass_scale, int loads,
-                      bool masked, double* grad_out, const int* write_shell_dev) {
+                      bool masked, double* grad_out, const int* write_shell_dev, const int* eval_shell_dev = nullptr,
+                      bool to_host = true) {
     hipStream_t st = c->stream;
     GroupTimer tmr(c, SHELL_T_ENERGY_GRAD);
     launch_energy_grad(st, c->P, dptr<int4>(c->patch_nodes), dptr<int>(c->patch_shell),
                        dptr<ShellParams>(c->shells_d), dptr<double>(c->phi), q_in, dptr<double>(c->qbar), qhat,
-                       mass_scale, c->dt_damp, 1, loads, dptr<double>(c->e_patch), dptr<double>(c->g_patch));
+                       mass_scale, c->dt_damp, 1, loads, eval_shell_dev, dptr<double>(c->e_patch),
+                       dptr<double>(c->g_patch));
     launch_shell_energy(st, c->S, dptr<ShellParams>(c->shells_d), dptr<double>(c->e_patch), dptr<double>(c->e_shell));
     if (grad_out)
         launch_gather_grad(st, c->N, dptr<int>(c->inc_ptr), dptr<int>(c->inc), dptr<double>(c->g_patch),
@@ -667,14 +681,19 @@ void eval_energy_grad(shell_ctx* c, const double* q_in, const double* qhat, doub
                           dptr<double>(c->e_shell));
     HIPCHK(hipGetLastError());
     tmr.stop();
-    HIPCHK(hipMemcpyAsync(c->h_e_shell, c->e_shell.p, (size_t)c->S * 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (to_host)
+        HIPCHK(hipMemcpyAsync(c->h_e_shell, c->e_shell.p, (size_t)c->S * 3 * sizeof(double), hipMemcpyDeviceToHost,
+                              st));
 }
 
-// per-shell x.y over free DOFs (masked) or all DOFs; result in c->h_red after sync
-void shell_dot(shell_ctx* c, const double* x, const double* y, bool masked) {
+// per-shell x.y over free DOFs (masked) or all DOFs; result in red_out, and
+// in c->h_red after sync when to_host
+void shell_dot(shell_ctx* c, const double* x, const double* y, bool masked, bool to_host = true) {
     launch_shell_dot(c->stream, c->rb(), c->S, x, y, masked ? dptr<uint16_t>(c->freemask) : nullptr,
                      dptr<double>(c->red_part), dptr<double>(c->red_out));
-    HIPCHK(hipMemcpyAsync(c->h_red, c->red_out.p, (size_t)c->S * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (to_host)
+        HIPCHK(hipMemcpyAsync(c->h_red, c->red_out.p, (size_t)c->S * sizeof(double), hipMemcpyDeviceToHost,
+                              c->stream));
 }
 
 void assemble(shell_ctx* c, const double* q_in, double mass_scale, int elastic) {
@@ -735,16 +754,10 @@ void bj_factor(shell_ctx* c) {
     sync(c);
 }
 
-// One CG launch on rhs b for the shells with active[s]; solution in cg_x.
-void cg_launch(shell_ctx* c, const double* b, const std::vector<int>& active, const std::vector<double>& rtol,
-               int maxit) {
-    std::vector<double> rt2(c->S);
-    std::vector<int> mi(c->S, maxit);
-    for (int s = 0; s < c->S; ++s) rt2[s] = rtol[s] * rtol[s];
-    h2d(c, c->cg_rtol2.p, rt2.data(), c->S * sizeof(double));
-    h2d(c, c->cg_maxit.p, mi.data(), c->S * sizeof(int));
-    h2d(c, c->cg_active.p, active.data(), c->S * sizeof(int));
-    run_graph(c, c->g_cg, (double)(uintptr_t)b, [&] {
+// Enqueue one CG launch on rhs b for the shells flagged in cg_active, with
+// the tolerances and caps in cg_rtol2 / cg_maxit (device); solution in cg_x,
+// per-shell results in cg_out (and h_cg_out after sync when to_host).
+void cg_enqueue(shell_ctx* c, const double* b, bool to_host) {
     hipStream_t st = c->stream;
     launch_zero(st, c->cg_bar.p, c->cg_bar.n);
     launch_zero(st, c->cg_nbflag.p, c->cg_nbflag.n);
@@ -771,8 +784,21 @@ void cg_launch(shell_ctx* c, const double* b, const std::vector<int>& active, co
                                       dptr<CgShellOut>(c->cg_out));
     HIPCHK(e);
     tmr.stop();
-    HIPCHK(hipMemcpyAsync(c->h_cg_out, c->cg_out.p, (size_t)c->S * sizeof(CgShellOut), hipMemcpyDeviceToHost, st));
-    });
+    if (to_host)
+        HIPCHK(hipMemcpyAsync(c->h_cg_out, c->cg_out.p, (size_t)c->S * sizeof(CgShellOut), hipMemcpyDeviceToHost,
+                              st));
+}
+
+// One CG launch on rhs b for the shells with active[s]; solution in cg_x.
+void cg_launch(shell_ctx* c, const double* b, const std::vector<int>& active, const std::vector<double>& rtol,
+               int maxit) {
+    std::vector<double> rt2(c->S);
+    std::vector<int> mi(c->S, maxit);
+    for (int s = 0; s < c->S; ++s) rt2[s] = rtol[s] * rtol[s];
+    h2d(c, c->cg_rtol2.p, rt2.data(), c->S * sizeof(double));
+    h2d(c, c->cg_maxit.p, mi.data(), c->S * sizeof(int));
+    h2d(c, c->cg_active.p, active.data(), c->S * sizeof(int));
+    run_graph(c, c->g_cg, (double)(uintptr_t)b, [&] { cg_enqueue(c, b, true); });
     sync(c);
     if (c->timing) {
         long long mx = 0;
@@ -819,6 +845,13 @@ struct SolveResult {
     std::vector<int> iters, status, sweeps;   // status: 0 ok, 1 cap, 2 indefinite
     std::vector<double> relres;
 };
+// per shell: still refining, ||b||^2, last relative residual (mixed form)
+struct RefineState {
+    std::vector<int> active;
+    std::vector<double> bn2, prev;
+};
+void refine_sweeps(shell_ctx* c, const double* b, const std::vector<int>& active_in, RefineState& F,
+                   const std::vector<double>& rtol, int maxit, SolveResult& R, int sweep0);
 
 // Solve A x = b (masked) for the active shells and write x into x_out for
 // those shells only (other shells' entries of x_out are left as they are).
@@ -856,10 +889,30 @@ SolveResult solve(shell_ctx* c, const double* b, double* x_out, const std::vecto
     HIPCHK(hipMemcpyAsync(r64, b, (size_t)c->N * 12 * sizeof(double), hipMemcpyDeviceToDevice, st));
     shell_dot(c, b, b, true);
     sync(c);
-    std::vector<double> bn2(c->h_red, c->h_red + S);
-    std::vector<int> active = active_in;
-    std::vector<double> prev(S, 1.0);
-    for (int sweep = 0; sweep < 30; ++sweep) {
+    RefineState F;
+    F.bn2.assign(c->h_red, c->h_red + S);
+    F.active = active_in;
+    F.prev.assign(S, 1.0);
+    refine_sweeps(c, b, active_in, F, rtol, maxit, R, 0);
+    h2d(c, c->flag_shell.p, active_in.data(), S * sizeof(int));
+    launch_copy_shell(st, c->N, x64, dptr<int>(c->node_shell), dptr<int>(c->flag_shell), x_out);
+    HIPCHK(hipGetLastError());
+    return R;
+}
+
+// Sweeps sweep0 .. 29 of the mixed form from the current x64 and r64 = b -
+// A x64 (FP64): each asks the FP32 CG for the reduction still needed (with a
+// margin) on the residual, adds its correction and recomputes the residual.
+void refine_sweeps(shell_ctx* c, const double* b, const std::vector<int>& active_in, RefineState& F,
+                   const std::vector<double>& rtol, int maxit, SolveResult& R, int sweep0) {
+    const int S = c->S;
+    hipStream_t st = c->stream;
+    double* x64 = dptr<double>(c->x64);
+    double* r64 = dptr<double>(c->r64);
+    std::vector<int>& active = F.active;
+    std::vector<double>& bn2 = F.bn2;
+    std::vector<double>& prev = F.prev;
+    for (int sweep = sweep0; sweep < 30; ++sweep) {
         bool any = false;
         for (int s = 0; s < S; ++s) {
             if (active[s] && bn2[s] == 0.0) active[s] = 0;
@@ -899,10 +952,79 @@ SolveResult solve(shell_ctx* c, const double* b, double* x_out, const std::vecto
             prev[s] = rel;
         }
     }
-    h2d(c, c->flag_shell.p, active_in.data(), S * sizeof(int));
-    launch_copy_shell(st, c->N, x64, dptr<int>(c->node_shell), dptr<int>(c->flag_shell), x_out);
+}
+
+// One Newton iteration of every active shell as one launch sequence, the
+// decisions taken by the control kernels of newton_kernels.hip on nt_ctl:
+// A = K(q) + M/dt^2 and its block-Jacobi factors, the direction A d = -g
+// (one FP64 CG, or NT_REFINE_SWEEPS sweeps of the mixed form), the slope
+// g.d, NT_LS_TRIALS line-search trials, and the convergence test of the
+// next iteration with the rounding floor from this iteration's matrix.  A
+// shell that needs the regulariser, more sweeps or more trials is left to
+// the host at that stage (NewtonCtl::need_host).  The per-shell state goes
+// back to h_ctl at the end.
+constexpr int NT_REFINE_SWEEPS = 2, NT_LS_TRIALS = 2;
+void newton_iteration_device(shell_ctx* c, double ms, double* q, double* g, double* qt, double* gt, double* d,
+                             double* rhs, const double* qhat) {
+    hipStream_t st = c->stream;
+    const int S = c->S, N = c->N;
+    NewtonCtl* ctl = dptr<NewtonCtl>(c->nt_ctl);
+    int* cg_active = dptr<int>(c->cg_active);
+    int* flag = dptr<int>(c->flag_shell);
+    int* wr = dptr<int>(c->write_shell);
+    double* red = dptr<double>(c->red_out);
+    double* alpha = dptr<double>(c->alpha_shell);
+    double* x64 = dptr<double>(c->x64);
+    const uint16_t* fm = dptr<uint16_t>(c->freemask);
+    const int* ns = dptr<int>(c->node_shell);
+    assemble(c, q, ms, 1);
+    launch_save_diag(st, N, dptr<int>(c->diag_blk), c->vals.p, c->fp32, dptr<double>(c->diag0));
+    bj_factor_enqueue(c);
+    launch_nt_factor(st, S, ctl, dptr<int>(c->fail_shell), cg_active, dptr<double>(c->cg_rtol2),
+                     dptr<int>(c->cg_maxit), c->opts.pcg_rtol, c->opts.pcg_maxit);
+    launch_neg_masked(st, N, g, fm, ns, cg_active, rhs);
+    launch_zero(st, c->x64.p, c->x64.n);
+    if (!c->fp32) {
+        cg_enqueue(c, rhs, false);
+        launch_add_to<double>(st, N * 12, dptr<double>(c->cg_x), x64);
+        launch_nt_cg64(st, S, ctl, dptr<CgShellOut>(c->cg_out), flag);
+    } else {
+        double* r64 = dptr<double>(c->r64);
+        HIPCHK(hipMemcpyAsync(r64, rhs, (size_t)N * 12 * sizeof(double), hipMemcpyDeviceToDevice, st));
+        shell_dot(c, rhs, rhs, true, false);
+        launch_nt_ref_init(st, S, ctl, red, cg_active, dptr<double>(c->cg_rtol2), c->opts.pcg_rtol);
+        for (int sw = 0; sw < NT_REFINE_SWEEPS; ++sw) {
+            cg_enqueue(c, r64, false);
+            launch_nt_ref_cg(st, S, ctl, dptr<CgShellOut>(c->cg_out), cg_active);
+            launch_add_to<float>(st, N * 12, dptr<float>(c->cg_x), x64);
+            spmv(c, x64, rhs, r64, 1 | 4);
+            shell_dot(c, r64, r64, true, false);
+            launch_nt_ref_check(st, S, ctl, red, cg_active, dptr<double>(c->cg_rtol2), c->opts.pcg_rtol,
+                                c->opts.pcg_maxit);
+        }
+        launch_nt_ref_end(st, S, ctl, flag);
+    }
+    launch_copy_shell(st, N, x64, ns, flag, d);
+    // line search along d (-g where d is not a descent direction)
+    shell_dot(c, g, d, true, false);
+    launch_nt_ls_init(st, S, ctl, red, alpha, flag, wr);
+    launch_neg_masked(st, N, g, fm, ns, flag, rhs);
+    launch_copy_shell(st, N, rhs, ns, flag, d);
+    for (int t = 0; t < NT_LS_TRIALS; ++t) {
+        launch_axpy_shell(st, N, q, d, alpha, ns, qt);
+        eval_energy_grad(c, qt, qhat, ms, 1, true, gt, wr, wr, false);
+        shell_dot(c, gt, gt, true, false);
+        launch_nt_ls_step(st, S, t, ctl, dptr<double>(c->e_shell), red, alpha, flag, wr);
+        launch_copy_shell(st, N, qt, ns, flag, q);
+        launch_copy_shell(st, N, gt, ns, flag, g);
+    }
+    launch_nt_ls_end(st, S, ctl);
+    // the next iteration's convergence test
+    spmv(c, q, nullptr, rhs, 8 | 2);
+    shell_dot(c, rhs, rhs, true, false);
+    launch_nt_check(st, S, ctl, red, c->opts.newton_rtol, c->opts.newton_maxit);
     HIPCHK(hipGetLastError());
-    return R;
+    HIPCHK(hipMemcpyAsync(c->h_ctl, c->nt_ctl.p, (size_t)S * sizeof(NewtonCtl), hipMemcpyDeviceToHost, st));
 }
 
 // Learned warm start of the Newton iteration.  Two directions from the
@@ -1072,6 +1194,7 @@ void shell_default_opts(shell_opts* o) {
     o->stream = nullptr;
     o->graphs = 1;
     o->cg_resident = 1;
+    o->device_newton = 1;
 }
 
 const char* shell_last_error(const shell_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
@@ -1384,26 +1507,28 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
     }
     if (learned) newton_warm_start(c, ms, active, E, Escale, gn, stats);
     const double eps = 2.220446049250313e-16;
-    bool have_prev = false;
     double t_asm = 0, t_cg = 0;
     // per shell: Newton iterations of the current augmented-Lagrangian round
     // and of the rounds before, multiplier updates, last max |c|
     std::vector<int> kk(S, 0), kbase(S, 0), outer(S, 0);
     std::vector<double> alm_res(S, 0.0), h_c;
-    for (int k = 0;; ++k) {
-        // rounding floor of the gradient from the previous Hessian: 4 eps || P_free |A| |q| ||
+    // Convergence test of the shells in `only` (all if NULL): the rounding
+    // floor of the gradient from the current matrix, 4 eps || P_free |A| |q| ||
+    // (after the first iteration), then the augmented-Lagrangian rounds.
+    // Returns whether any shell still iterates.
+    auto check = [&](bool have_prev, const std::vector<int>* only) -> bool {
         if (have_prev) {
             run_graph(c, c->g_floor, 0.0, [&] {
                 spmv(c, q, nullptr, rhs, 8 | 2);
                 shell_dot(c, rhs, rhs, true);
             });
             sync(c);
-            for (int s = 0; s < S; ++s) floor_[s] = 4.0 * eps * std::sqrt(c->h_red[s]);
+            for (int s = 0; s < S; ++s)
+                if (!only || (*only)[s]) floor_[s] = 4.0 * eps * std::sqrt(c->h_red[s]);
         }
-        bool any = false;
         std::vector<int> conv(S, 0);
         for (int s = 0; s < S; ++s) {
-            if (!active[s]) continue;
+            if (!active[s] || (only && !(*only)[s])) continue;
             stats[s].grad_norm = gn[s];
             stats[s].grad_floor = floor_[s];
             if (gn[s] == 0.0 || (kk[s] > 0 && gn[s] <= std::max(c->opts.newton_rtol * g0[s], floor_[s]))) {
@@ -1418,9 +1543,9 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
         if (c->alm_on) {
             // augmented Lagrangian (Sec. 6.1): a converged shell whose point
             // constraints are not yet met updates its multipliers and resumes
-            bool check = false;
-            for (int s = 0; s < S; ++s) check |= conv[s] && c->alm_shell_pt[s] < c->alm_shell_pt[s + 1];
-            if (check) {
+            bool chk = false;
+            for (int s = 0; s < S; ++s) chk |= conv[s] && c->alm_shell_pt[s] < c->alm_shell_pt[s + 1];
+            if (chk) {
                 h_c.resize(3 * (size_t)c->alm_n);
                 launch_alm_residual(st, c->alm_n, dptr<AlmPoint>(c->alm_pts), q, dptr<double>(c->alm_c));
                 HIPCHK(hipGetLastError());
@@ -1464,37 +1589,32 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
                 }
             }
         }
+        bool any = false;
         for (int s = 0; s < S; ++s) any |= active[s] != 0;
-        if (!any) break;
-        // A = K(q) + M/dt^2, block-Jacobi, regulariser on failure
-        double t0 = now_ms();
-        run_graph(c, c->g_asm, ms, [&] {
-            assemble(c, q, ms, 1);
-            if (c->alm_on)   // + kappa C^T C of the point constraints
-                launch_add_sparse(c->stream, c->alm_nsp, dptr<long long>(c->alm_pos), dptr<double>(c->alm_val),
-                                  c->vals.p, c->fp32);
-            launch_save_diag(c->stream, c->N, dptr<int>(c->diag_blk), c->vals.p, c->fp32, dptr<double>(c->diag0));
-            bj_factor_enqueue(c);
-        });
-        sync(c);
-        have_prev = true;
-        std::vector<double> delta(S, 0.0);
-        auto apply_delta = [&]() {
-            h2d(c, c->delta_shell.p, delta.data(), S * sizeof(double));
-            launch_regularize(st, c->N, dptr<int>(c->diag_blk), c->vals.p, c->fp32, dptr<double>(c->diag0),
-                              dptr<int>(c->node_shell), dptr<double>(c->delta_shell));
-        };
-        auto bump = [&](int s) -> bool {   // next regulariser value; false past the cap (delta stays 1e2)
-            const double next = delta[s] == 0.0 ? 1e-6 : delta[s] * 10.0;
-            if (next > 1e2 * (1 + 1e-12)) return false;
-            delta[s] = next;
-            return true;
-        };
+        return any;
+    };
+    // regulariser of the current iteration: delta diag(A) added to the
+    // diagonal blocks of a shell, from 1e-6 up by factors of 10 to 1e2
+    std::vector<double> delta(S, 0.0);
+    auto apply_delta = [&]() {
+        h2d(c, c->delta_shell.p, delta.data(), S * sizeof(double));
+        launch_regularize(st, c->N, dptr<int>(c->diag_blk), c->vals.p, c->fp32, dptr<double>(c->diag0),
+                          dptr<int>(c->node_shell), dptr<double>(c->delta_shell));
+    };
+    auto bump = [&](int s) -> bool {   // next regulariser value; false past the cap (delta stays 1e2)
+        const double next = delta[s] == 0.0 ? 1e-6 : delta[s] * 10.0;
+        if (next > 1e2 * (1 + 1e-12)) return false;
+        delta[s] = next;
+        return true;
+    };
+    // the shells of `sub` whose block-Jacobi factorisation failed (h_fail):
+    // regularise and factor again until every diagonal block is definite
+    auto factor_fixup = [&](const std::vector<int>& sub) {
         for (bool first = true;; first = false) {
             if (!first) bj_factor(c);
             bool again = false;
             for (int s = 0; s < S; ++s)
-                if (active[s] && c->h_fail[s]) {
+                if (sub[s] && active[s] && c->h_fail[s]) {
                     if (bump(s))
                         again = true;
                     else {
@@ -1505,11 +1625,30 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
             if (!again) break;
             apply_delta();
         }
-        t_asm += now_ms() - t0;
-        t0 = now_ms();
-        // Newton direction: A d = -g
-        std::vector<int> todo = active;
+    };
+    // A d = -g for the shells of `todo`, regularising a shell whose CG finds
+    // p^T A p <= 0 and solving again for it; `indefinite`: the shells whose
+    // last solve found it already (regularise before the first solve)
+    auto solve_fixup = [&](std::vector<int> todo, const std::vector<int>& indefinite) {
+        bool pre = false;
+        for (int s = 0; s < S; ++s)
+            if (todo[s] && indefinite[s]) {
+                if (bump(s))
+                    pre = true;
+                else {
+                    status[s] = SHELL_E_INDEFINITE;
+                    active[s] = 0;
+                    todo[s] = 0;
+                }
+            }
+        if (pre) {
+            apply_delta();
+            bj_factor(c);
+        }
         for (;;) {
+            bool anyt = false;
+            for (int s = 0; s < S; ++s) anyt |= todo[s] != 0;
+            if (!anyt) break;
             h2d(c, c->cg_active.p, todo.data(), S * sizeof(int));
             launch_neg_masked(st, c->N, g, dptr<uint16_t>(c->freemask), dptr<int>(c->node_shell),
                               dptr<int>(c->cg_active), rhs);
@@ -1538,28 +1677,29 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
         }
         // (solve() writes d only for the shells it was asked to solve, so a
         // retry after regularising one shell keeps the others' directions)
-        for (int s = 0; s < S; ++s) stats[s].reg_delta = std::max(stats[s].reg_delta, delta[s]);
-        t_cg += now_ms() - t0;
-        bool any2 = false;
-        for (int s = 0; s < S; ++s) any2 |= active[s] != 0;
-        if (!any2) break;
-        // line search along d, per shell
+    };
+    // line search along d for the shells of `sub` (their direction solved):
+    // Armijo with quadratic, then cubic interpolation, up to 20 trials;
+    // trial0 > 0 continues a search the device began (state in ls_*)
+    std::vector<double> ls_slope(S, 0.0), ls_alpha(S, 0.0), ls_aprev(S, 0.0), ls_Eprev(S, 0.0);
+    std::vector<int> ls_searching(S, 0);
+    auto line_search_start = [&](const std::vector<int>& sub) {
         shell_dot(c, g, d, true);
         sync(c);
-        std::vector<double> slope(c->h_red, c->h_red + S);
-        std::vector<double> alpha(S, 0.0), a_prev(S, 0.0), E_prev(S, 0.0);
-        std::vector<int> searching(S, 0), steepest(S, 0);
+        std::vector<int> steepest(S, 0);
         bool any_steep = false;
-        for (int s = 0; s < S; ++s)
-            if (active[s]) {
-                searching[s] = 1;
-                alpha[s] = 1.0;
-                if (!(slope[s] < 0.0)) {   // not a descent direction (an indefinite system the CG did
-                    steepest[s] = 1;       // not detect): search along -g instead
-                    slope[s] = -gn[s] * gn[s];
-                    any_steep = true;
-                }
+        for (int s = 0; s < S; ++s) {
+            ls_searching[s] = 0;
+            if (!(sub[s] && active[s])) continue;
+            ls_searching[s] = 1;
+            ls_alpha[s] = 1.0;
+            ls_slope[s] = c->h_red[s];
+            if (!(ls_slope[s] < 0.0)) {   // not a descent direction (an indefinite system the CG did
+                steepest[s] = 1;          // not detect): search along -g instead
+                ls_slope[s] = -gn[s] * gn[s];
+                any_steep = true;
             }
+        }
         if (any_steep) {
             h2d(c, c->flag_shell.p, steepest.data(), S * sizeof(int));
             launch_neg_masked(st, c->N, g, dptr<uint16_t>(c->freemask), dptr<int>(c->node_shell),
@@ -1567,7 +1707,14 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
             launch_copy_shell(st, c->N, rhs, dptr<int>(c->node_shell), dptr<int>(c->flag_shell), d);
             HIPCHK(hipGetLastError());
         }
-        for (int trial = 0; trial < 20; ++trial) {
+    };
+    auto line_search = [&](int trial0) {
+        std::vector<double>& alpha = ls_alpha;
+        std::vector<double>& a_prev = ls_aprev;
+        std::vector<double>& E_prev = ls_Eprev;
+        std::vector<double>& slope = ls_slope;
+        std::vector<int>& searching = ls_searching;
+        for (int trial = trial0; trial < 20; ++trial) {
             bool anys = false;
             for (int s = 0; s < S; ++s) anys |= searching[s] != 0;
             if (!anys) break;
@@ -1632,13 +1779,188 @@ shell_status shell_newton_step(shell_ctx* c, double dt, const double* q_n_dev, c
             launch_copy_shell(st, c->N, qt, dptr<int>(c->node_shell), dptr<int>(c->flag_shell), q);
             launch_copy_shell(st, c->N, gt, dptr<int>(c->node_shell), dptr<int>(c->flag_shell), g);
         }
+    };
+    // end of the iteration for the shells of `sub`: count it; a search that
+    // found no acceptable step ends the shell's Newton iteration
+    auto finish = [&](const std::vector<int>& sub) {
         for (int s = 0; s < S; ++s) {
+            if (!sub[s]) continue;
             if (active[s]) stats[s].newton_iters = kbase[s] + (kk[s]++) + 1;
-            if (searching[s]) {
+            if (ls_searching[s]) {
                 status[s] = SHELL_E_LINESEARCH;
                 active[s] = 0;
             }
         }
+    };
+    // The whole Newton iteration runs as one device launch sequence (one
+    // graph) unless the point constraints' outer loop, event timing or the
+    // option says otherwise; the host then reads the per-shell state once.
+    const bool device_iter = c->opts.device_newton && !c->alm_on && !c->timing;
+    bool any = check(false, nullptr);
+    while (any) {
+        delta.assign(S, 0.0);
+        if (device_iter) {
+            for (int s = 0; s < S; ++s) {
+                NewtonCtl& n = c->h_ctl[s];
+                std::memset(&n, 0, sizeof(n));
+                n.E = E[s];
+                n.Escale = Escale[s];
+                n.gn = gn[s];
+                n.g0 = g0[s];
+                n.floor = floor_[s];
+                n.active = active[s];
+                n.k = kk[s];
+                n.status = status[s];
+            }
+            h2d(c, c->nt_ctl.p, c->h_ctl, (size_t)S * sizeof(NewtonCtl));
+            const double t0 = now_ms();
+            run_graph(c, c->g_newton, ms, [&] {
+                newton_iteration_device(c, ms, q, g, qt, gt, d, rhs, qhat);
+            });
+            sync(c);
+            t_cg += now_ms() - t0;
+            std::vector<int> handed(S, 0), indefinite(S, 0), solve_todo(S, 0), refine(S, 0), ls_more(S, 0),
+                fresh_ls(S, 0);
+            bool any_handed = false;
+            for (int s = 0; s < S; ++s) {
+                const NewtonCtl& n = c->h_ctl[s];
+                if (n.fault) throw StatusErr{SHELL_E_DEVICE, "CG grid barrier timed out"};
+                if (!active[s]) continue;
+                stats[s].pcg_iters_total += n.pcg_iters;
+                stats[s].refine_sweeps += n.sweeps;
+                stats[s].ls_backtracks += n.backtracks;
+                E[s] = n.E;
+                Escale[s] = n.Escale;
+                gn[s] = n.gn;
+                if (n.need_host) {
+                    handed[s] = 1;
+                    any_handed = true;
+                    if (n.need_host == NT_HOST_FACTOR) {
+                        solve_todo[s] = fresh_ls[s] = 1;
+                    } else if (n.need_host == NT_HOST_INDEFINITE) {
+                        solve_todo[s] = indefinite[s] = fresh_ls[s] = 1;
+                    } else if (n.need_host == NT_HOST_REFINE) {
+                        refine[s] = fresh_ls[s] = 1;
+                    } else {   // NT_HOST_LINESEARCH
+                        ls_more[s] = 1;
+                        ls_slope[s] = n.slope;
+                        ls_alpha[s] = n.alpha;
+                        ls_aprev[s] = n.a_prev;
+                        ls_Eprev[s] = n.E_prev;
+                    }
+                    continue;
+                }
+                // finished on the device, next convergence test included
+                kk[s] = n.k;
+                stats[s].newton_iters = kbase[s] + kk[s];
+                floor_[s] = n.floor;
+                if (n.active) {
+                    stats[s].grad_norm = n.grad_norm_checked;
+                    stats[s].grad_floor = n.floor;
+                } else {
+                    stats[s].grad_norm = n.grad_norm_checked;
+                    stats[s].grad_floor = n.floor;
+                    status[s] = n.status;
+                    active[s] = 0;
+                }
+            }
+            if (any_handed) {
+                // the rest of this iteration on the host, for the shells the
+                // device handed over, then their convergence test
+                factor_fixup(solve_todo);
+                for (int s = 0; s < S; ++s)
+                    if (!active[s]) solve_todo[s] = fresh_ls[s] = 0;
+                bool anyr = false;
+                for (int s = 0; s < S; ++s) anyr |= refine[s] != 0;
+                if (anyr) {
+                    // more sweeps of the mixed form from the device's state
+                    RefineState F;
+                    F.active = refine;
+                    F.bn2.assign(S, 0.0);
+                    F.prev.assign(S, 1.0);
+                    SolveResult R;
+                    R.iters.assign(S, 0);
+                    R.status.assign(S, 0);
+                    R.sweeps.assign(S, 0);
+                    R.relres.assign(S, 0.0);
+                    for (int s = 0; s < S; ++s)
+                        if (refine[s]) {
+                            F.bn2[s] = c->h_ctl[s].bn2;
+                            F.prev[s] = c->h_ctl[s].prev;
+                            R.iters[s] = c->h_ctl[s].solve_iters;
+                        }
+                    h2d(c, c->cg_active.p, refine.data(), S * sizeof(int));
+                    launch_neg_masked(st, c->N, g, dptr<uint16_t>(c->freemask), dptr<int>(c->node_shell),
+                                      dptr<int>(c->cg_active), rhs);
+                    refine_sweeps(c, rhs, refine, F, std::vector<double>(S, c->opts.pcg_rtol), c->opts.pcg_maxit,
+                                  R, NT_REFINE_SWEEPS);
+                    h2d(c, c->flag_shell.p, refine.data(), S * sizeof(int));
+                    launch_copy_shell(st, c->N, dptr<double>(c->x64), dptr<int>(c->node_shell),
+                                      dptr<int>(c->flag_shell), d);
+                    HIPCHK(hipGetLastError());
+                    for (int s = 0; s < S; ++s) {
+                        if (!refine[s]) continue;
+                        stats[s].pcg_iters_total += R.iters[s] - c->h_ctl[s].solve_iters;
+                        stats[s].refine_sweeps += R.sweeps[s];
+                        if (R.status[s] == 2) solve_todo[s] = indefinite[s] = 1;
+                    }
+                }
+                solve_fixup(solve_todo, indefinite);
+                for (int s = 0; s < S; ++s) stats[s].reg_delta = std::max(stats[s].reg_delta, delta[s]);
+                for (int s = 0; s < S; ++s)
+                    if (!active[s]) fresh_ls[s] = 0;
+                line_search_start(fresh_ls);
+                const std::vector<int> fresh_search = ls_searching;
+                // a search the device began continues at its next trial (the
+                // interpolation depends on the trial), then the new searches
+                std::vector<int> cont_failed(S, 0);
+                bool anyc = false;
+                for (int s = 0; s < S; ++s) anyc |= ls_more[s] != 0;
+                if (anyc) {
+                    for (int s = 0; s < S; ++s) ls_searching[s] = ls_more[s] && active[s];
+                    line_search(NT_LS_TRIALS);
+                    cont_failed = ls_searching;
+                }
+                ls_searching = fresh_search;
+                line_search(0);
+                for (int s = 0; s < S; ++s)
+                    if (cont_failed[s]) ls_searching[s] = 1;
+                finish(handed);
+                any = check(true, &handed);
+                for (int s = 0; s < S; ++s) any |= active[s] != 0;
+            } else {
+                any = false;
+                for (int s = 0; s < S; ++s) any |= active[s] != 0;
+            }
+            continue;
+        }
+        // A = K(q) + M/dt^2, block-Jacobi, regulariser on failure
+        double t0 = now_ms();
+        run_graph(c, c->g_asm, ms, [&] {
+            assemble(c, q, ms, 1);
+            if (c->alm_on)   // + kappa C^T C of the point constraints
+                launch_add_sparse(c->stream, c->alm_nsp, dptr<long long>(c->alm_pos), dptr<double>(c->alm_val),
+                                  c->vals.p, c->fp32);
+            launch_save_diag(c->stream, c->N, dptr<int>(c->diag_blk), c->vals.p, c->fp32, dptr<double>(c->diag0));
+            bj_factor_enqueue(c);
+        });
+        sync(c);
+        factor_fixup(active);
+        t_asm += now_ms() - t0;
+        t0 = now_ms();
+        // Newton direction: A d = -g
+        solve_fixup(active, std::vector<int>(S, 0));
+        for (int s = 0; s < S; ++s) stats[s].reg_delta = std::max(stats[s].reg_delta, delta[s]);
+        t_cg += now_ms() - t0;
+        bool any2 = false;
+        for (int s = 0; s < S; ++s) any2 |= active[s] != 0;
+        if (!any2) break;
+        // line search along d, per shell
+        const std::vector<int> iter_shells = active;
+        line_search_start(active);
+        line_search(0);
+        finish(iter_shells);
+        any = check(true, nullptr);
     }
     if (learned || c->rec_feat) {
         // this step's correction q_{n+1} - q_start of the converged shells:
@@ -2421,8 +2743,13 @@ shell_status shell_autotune(shell_ctx* c, int32_t cg_iters, shell_tune_result* o
     r.us_per_iter_default = time_cg(c, dptr<double>(c->rhs), cg_iters);
     if (!cached) {
         double best = 1e300;
+        int max_rows = 0;
+        for (int s = 0; s < c->S; ++s) max_rows = std::max(max_rows, c->shells[s].node_end - c->shells[s].node_begin);
         for (int nt : {256, 512, 1024})
-            for (int spread : {0, 1, 2, 4}) {
+            for (int spread : {-1, 0, 1, 2, 4}) {
+                // one block per shell only where a block covers the largest
+                // shell in two passes
+                if (spread < 0 && max_rows > 2 * cg_rows_per_pass(c->fp32, nt)) continue;
                 if (!set_row_blocks(c, nt, spread)) continue;
                 const double t = time_cg(c, dptr<double>(c->rhs), cg_iters);
                 r.candidates++;

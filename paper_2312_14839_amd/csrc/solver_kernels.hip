@@ -488,6 +488,9 @@ __device__ __forceinline__ bool reduce_barrier(ShellSync* ss, double* __restrict
     __shared__ int s_ok;
     __shared__ double s_tot[N];
     block_sum<N, NW>(v, lds);
+    // a shell of one block: its sum is the block's (the block sum's barrier
+    // orders the phase's writes for the block's own next phase)
+    if (snb == 1) return true;
     double* buf = part + (size_t)(k & 1) * 4 * gridDim.x;
     if (threadIdx.x == 0) {
 #pragma unroll
@@ -601,10 +604,13 @@ __device__ __forceinline__ bool reduce_barrier(ShellSync* ss, double* __restrict
 // Publish this block's writes of the phase just ended and wait until the
 // blocks blk+1 .. hi of the same shell have published theirs (flag value k,
 // monotone).  Bounded like reduce_barrier.
+// A shell of one block (solo) has no other block to publish to or wait
+// for: the block barrier alone orders its phases.
 __device__ __forceinline__ bool neighbour_sync(unsigned* __restrict__ flags, int blk, int hi, unsigned k,
-                                               int* abort_flag) {
+                                               int* abort_flag, bool solo) {
     __shared__ int s_nok;
     __syncthreads();
+    if (solo) return true;
     if (threadIdx.x == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __hip_atomic_store(&flags[32 * (size_t)blk], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -829,7 +835,7 @@ __global__ __launch_bounds__(NT) void k_cg(
         }
     });
     int it = 0, status = 1;
-    if (!neighbour_sync(nbflag, blk, nbhi, ++nnb, abort_flag)) {
+    if (!neighbour_sync(nbflag, blk, nbhi, ++nnb, abort_flag, snb == 1)) {
         if (leader) out[sh] = CgShellOut{0, 3, 0.0, 0.0};
         return;
     }
@@ -913,7 +919,7 @@ __global__ __launch_bounds__(NT) void k_cg(
                     }
                 }
             }, rev);
-            if (!neighbour_sync(nbflag, blk, nbhi, ++nnb, abort_flag)) {
+            if (!neighbour_sync(nbflag, blk, nbhi, ++nnb, abort_flag, snb == 1)) {
                 status = 3;
                 break;
             }

@@ -49,6 +49,7 @@ class shell_opts(C.Structure):
         ("newton_maxit", C.c_int32), ("pcg_maxit", C.c_int32),
         ("newton_rtol", C.c_double), ("pcg_rtol", C.c_double),
         ("device", C.c_int32), ("stream", C.c_void_p), ("graphs", C.c_int32), ("cg_resident", C.c_int32),
+        ("device_newton", C.c_int32),
     ]
 
 
@@ -269,7 +270,8 @@ class ShellContext:
 
     def __init__(self, cases: Sequence, precision=SHELL_FP64, hessian=SHELL_HESS_EXACT,
                  newton_rtol=1e-10, pcg_rtol=1e-10, newton_maxit=50, pcg_maxit=100000,
-                 device=0, stream=None, warm_start=SHELL_WS_NONE, graphs=True, cg_resident=True):
+                 device=0, stream=None, warm_start=SHELL_WS_NONE, graphs=True, cg_resident=True,
+                 device_newton=True):
         self._keep = []
         self._lib = lib   # kept for close() during interpreter shutdown
         descs = (shell_desc * len(cases))()
@@ -294,6 +296,7 @@ class ShellContext:
         o.device = int(device)
         o.graphs = int(bool(graphs))
         o.cg_resident = int(bool(cg_resident))
+        o.device_newton = int(bool(device_newton))
         o.stream = C.c_void_p(stream) if stream else None
         h = C.c_void_p()
         rc = lib.shell_create(descs, len(cases), C.byref(o), C.byref(h))
