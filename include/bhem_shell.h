@@ -295,23 +295,38 @@ shell_status shell_timing_enable(shell_ctx *c, int32_t enable);
 /* Copy the counters accumulated since the last shell_timing_enable. */
 shell_status shell_timing_get(const shell_ctx *c, shell_timing *out);
 
-/* CG layout autotuner.  The persistent CG kernel covers each shell's node
- * rows with contiguous row blocks; the tunable layout is the threads per
- * block (256, 512 or 1024) and the rows per block (the fewest that keep
- * every block resident at once, or 1, 2 or 4 times that rounded up to the
- * rows one pass of a block covers).  shell_autotune times cg_iters
- * CG iterations of every candidate on K(qbar) + M (overwriting the
- * context's matrix) and keeps the fastest.  Results are cached for the
- * process by (device, nodes, shells, block non-zeros, precision); a cached
- * layout is applied without timing the candidates (candidates = 0,
- * from_cache = 1).  Times are wall-clock microseconds per CG iteration. */
+/* Autotuner of the batched form's launch shapes.  CG layout: the persistent
+ * CG kernel covers each shell's node rows with contiguous row blocks; the
+ * tunable layout is the threads per block (256, 512 or 1024) and the rows
+ * per block (the fewest that keep every block resident at once, or 1, 2 or
+ * 4 times that rounded up to the rows one pass of a block covers, or one
+ * block per shell where a block covers the largest shell in two passes).
+ * shell_autotune times cg_iters CG iterations of every candidate on K(qbar)
+ * + M (overwriting the context's matrix) and keeps the fastest.  Patch
+ * kernel tiles: the patches (wavefronts) per block of the Hessian kernel
+ * (1, 2, 4 or 8) and the patches per block of the energy and gradient
+ * kernel (4, 8 or 16, 16 threads each), each chosen by the wall time of one
+ * assembly / one evaluation at qbar.  Results are cached for the process by
+ * (device, nodes, shells, block non-zeros, precision); a cached choice is
+ * applied without timing the candidates (candidates = 0, from_cache = 1).
+ * Times are wall-clock microseconds: per CG iteration, per assembly, per
+ * evaluation. */
 typedef struct {
     int32_t threads, rows_per_block, blocks;   /* chosen layout */
     int32_t default_threads, default_rows_per_block;   /* layout before the call */
     int32_t candidates, from_cache;
     double us_per_iter, us_per_iter_default;
+    int32_t hess_waves, energy_patches;        /* chosen patch kernel tiles */
+    double hess_us, hess_us_default, energy_us, energy_us_default;
 } shell_tune_result;
 shell_status shell_autotune(shell_ctx *c, int32_t cg_iters, shell_tune_result *out);
+
+/* Set the patch kernel tiles by hand: hess_waves patches (wavefronts) per
+ * block of the Hessian kernel (1, 2, 4 or 8), energy_patches patches per
+ * block of the energy and gradient kernel (4, 8 or 16).  Results do not
+ * depend on them (each patch is computed by one wavefront or 16 lanes, and
+ * patches of one colour share no matrix block).  SHELL_E_INVAL otherwise. */
+shell_status shell_set_patch_tiles(shell_ctx *c, int32_t hess_waves, int32_t energy_patches);
 
 /* ------------------------------------------------------------------
  * Learned warm start of the Newton iteration.  This is an extension: the

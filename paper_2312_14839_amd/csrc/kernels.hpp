@@ -11,7 +11,8 @@ namespace bhem {
 void launch_energy_grad(hipStream_t st, int npatch, const int4* patch_nodes, const int* patch_shell,
                         const ShellParams* shells, const double* phi, const double* q, const double* qbar,
                         const double* qhat, double mass_scale, double dt_damp, int elastic, int loads,
-                        const int* eval_shell /* NULL: every shell */, double* e_patch, double* g_patch);
+                        const int* eval_shell /* NULL: every shell */, double* e_patch, double* g_patch,
+                        int patches_per_block /* 4, 8 or 16 */);
 void launch_gather_grad(hipStream_t st, int nnodes, const int* inc_ptr, const int* inc, const double* g_patch,
                         const uint16_t* freemask, const int* node_shell, const int* write_shell, double* grad);
 void launch_shell_energy(hipStream_t st, int nshell, const ShellParams* shells, const double* e_patch,
@@ -28,7 +29,8 @@ template <class T>
 void launch_hessian(hipStream_t st, const int* patch_list, int nlist, const int4* patch_nodes, const int* patch_shell,
                     const int* patch_slots, const uint64_t* patch_kid, const uint16_t* patch_first,
                     const ShellParams* shells, const double* phi, const double* q, const double* qbar,
-                    double mass_scale, double dt_damp, int elastic, int pseudo, T* vals);
+                    double mass_scale, double dt_damp, int elastic, int pseudo, T* vals,
+                    int waves /* patches (wavefronts) per block: 1, 2, 4 or 8 */);
 
 // --------------------------------------------------------- ray kernels
 // ctrl: [P][4][4][3] Bezier control points, p_ij at ((4p + i)*4 + j)*3.

@@ -31,9 +31,10 @@ namespace bhem {
 // ---------------------------------------------------------------- K1
 // Energies: e_patch[p][0] elastic, [1] kinetic (mass_scale/2)(x - xhat)^T rho h (x - xhat),
 // [2] load -rho h g.(x - xhat).  Gradient of their sum per patch in g_patch[p][48].
-constexpr int EG_PATCHES = 16;   // patches per 256-thread block
-
-__global__ __launch_bounds__(256) void k_energy_grad(int npatch, const int4* __restrict__ patch_nodes,
+// EGP patches per block of 16 EGP threads (4, 8 or 16; chosen by the
+// autotuner, 16 by default)
+template <int EGP>
+__global__ __launch_bounds__(16 * EGP) void k_energy_grad(int npatch, const int4* __restrict__ patch_nodes,
                                                      const int* __restrict__ patch_shell,
                                                      const ShellParams* __restrict__ shells,
                                                      const double* __restrict__ phi,
@@ -43,10 +44,10 @@ __global__ __launch_bounds__(256) void k_energy_grad(int npatch, const int4* __r
                                                      const int* __restrict__ eval_shell,
                                                      double* __restrict__ e_patch,
                                                      double* __restrict__ g_patch) {
-    __shared__ double s_u[EG_PATCHES][48], s_b[EG_PATCHES][48], s_d[EG_PATCHES][48];
-    __shared__ double s_dpsi[EG_PATCHES][16][18];
+    __shared__ double s_u[EGP][48], s_b[EGP][48], s_d[EGP][48];
+    __shared__ double s_dpsi[EGP][16][18];
     const int lane = threadIdx.x & 15, pl = threadIdx.x >> 4;
-    const int patch = blockIdx.x * EG_PATCHES + pl;
+    const int patch = blockIdx.x * EGP + pl;
     // eval_shell (or NULL: all): the patches of other shells are skipped and
     // keep their previous outputs
     const bool active = patch < npatch && (!eval_shell || eval_shell[patch_shell[patch]]);
@@ -245,14 +246,15 @@ __global__ void k_shell_energy(int nshell, const ShellParams* __restrict__ shell
 }
 
 // ---------------------------------------------------------------- K2
-constexpr int HS_WAVES = 4;   // patches (wavefronts) per block
+// NWV patches (wavefronts) per block: 1, 2, 4 or 8, chosen by the
+// autotuner (4 by default)
 
 __host__ __device__ constexpr int pair_index(int i, int j) {   // i <= j
     return i == j ? i : (i == 0 ? (j == 1 ? 3 : 4) : 5);
 }
 
-template <class T>
-__global__ __launch_bounds__(256) void k_hessian(const int* __restrict__ patch_list, int nlist,
+template <class T, int NWV>
+__global__ __launch_bounds__(64 * NWV) void k_hessian(const int* __restrict__ patch_list, int nlist,
                                                  const int4* __restrict__ patch_nodes,
                                                  const int* __restrict__ patch_shell,
                                                  const int* __restrict__ patch_slots,
@@ -265,13 +267,13 @@ __global__ __launch_bounds__(256) void k_hessian(const int* __restrict__ patch_l
     typedef Mfma<T> MM;
     constexpr int WSZ = 16 * 121;   // packed W per Gauss point (+ mass term) and pair staging (6*256)
     static_assert(WSZ >= 6 * 256, "staging must fit");
-    __shared__ T s_u[HS_WAVES][48], s_b[HS_WAVES][48];
-    __shared__ T s_kin[HS_WAVES][16][30];
-    __shared__ T s_w[HS_WAVES][WSZ];
+    __shared__ T s_u[NWV][48], s_b[NWV][48];
+    __shared__ T s_kin[NWV][16][30];
+    __shared__ T s_w[NWV][WSZ];
     // the wavefront's patch and everything derived from it are wave-uniform
     // (scalar registers and loads)
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int li = blockIdx.x * HS_WAVES + wv;
+    const int li = blockIdx.x * NWV + wv;
     const bool active = li < nlist;
     const int patch = active ? patch_list[li] : 0;
     ShellParams sp = shells[active ? patch_shell[patch] : 0];
@@ -457,11 +459,17 @@ __global__ __launch_bounds__(256) void k_hessian(const int* __restrict__ patch_l
 void launch_energy_grad(hipStream_t st, int npatch, const int4* patch_nodes, const int* patch_shell,
                         const ShellParams* shells, const double* phi, const double* q, const double* qbar,
                         const double* qhat, double mass_scale, double dt_damp, int elastic, int loads,
-                        const int* eval_shell, double* e_patch, double* g_patch) {
+                        const int* eval_shell, double* e_patch, double* g_patch, int patches_per_block) {
     if (npatch == 0) return;
-    const int nb = (npatch + EG_PATCHES - 1) / EG_PATCHES;
-    hipLaunchKernelGGL(k_energy_grad, dim3(nb), dim3(256), 0, st, npatch, patch_nodes, patch_shell, shells, phi, q,
-                       qbar, qhat, mass_scale, dt_damp, elastic, loads, eval_shell, e_patch, g_patch);
+    const int egp = patches_per_block == 4 || patches_per_block == 8 ? patches_per_block : 16;
+    const int nb = (npatch + egp - 1) / egp;
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(nb), dim3(16 * egp), 0, st, npatch, patch_nodes, patch_shell, shells, phi, q,
+                           qbar, qhat, mass_scale, dt_damp, elastic, loads, eval_shell, e_patch, g_patch);
+    };
+    if (egp == 4) go(k_energy_grad<4>);
+    else if (egp == 8) go(k_energy_grad<8>);
+    else go(k_energy_grad<16>);
 }
 
 void launch_gather_grad(hipStream_t st, int nnodes, const int* inc_ptr, const int* inc, const double* g_patch,
@@ -489,18 +497,26 @@ template <class T>
 void launch_hessian(hipStream_t st, const int* patch_list, int nlist, const int4* patch_nodes, const int* patch_shell,
                     const int* patch_slots, const uint64_t* patch_kid, const uint16_t* patch_first,
                     const ShellParams* shells, const double* phi, const double* q, const double* qbar,
-                    double mass_scale, double dt_damp, int elastic, int pseudo, T* vals) {
+                    double mass_scale, double dt_damp, int elastic, int pseudo, T* vals, int waves) {
     if (nlist == 0) return;
-    const int nb = (nlist + HS_WAVES - 1) / HS_WAVES;
-    hipLaunchKernelGGL(k_hessian<T>, dim3(nb), dim3(256), 0, st, patch_list, nlist, patch_nodes, patch_shell,
-                       patch_slots, patch_kid, patch_first, shells, phi, q, qbar, mass_scale, dt_damp, elastic, pseudo, vals);
+    const int nw = waves == 1 || waves == 2 || waves == 8 ? waves : 4;
+    const int nb = (nlist + nw - 1) / nw;
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(nb), dim3(64 * nw), 0, st, patch_list, nlist, patch_nodes, patch_shell,
+                           patch_slots, patch_kid, patch_first, shells, phi, q, qbar, mass_scale, dt_damp, elastic,
+                           pseudo, vals);
+    };
+    if (nw == 1) go(k_hessian<T, 1>);
+    else if (nw == 2) go(k_hessian<T, 2>);
+    else if (nw == 8) go(k_hessian<T, 8>);
+    else go(k_hessian<T, 4>);
 }
 
 template void launch_hessian<double>(hipStream_t, const int*, int, const int4*, const int*, const int*,
                                      const uint64_t*, const uint16_t*, const ShellParams*, const double*, const double*,
-                                     const double*, double, double, int, int, double*);
+                                     const double*, double, double, int, int, double*, int);
 template void launch_hessian<float>(hipStream_t, const int*, int, const int4*, const int*, const int*,
                                     const uint64_t*, const uint16_t*, const ShellParams*, const double*, const double*,
-                                    const double*, double, double, int, int, float*);
+                                    const double*, double, double, int, int, float*, int);
 
 }  // namespace bhem

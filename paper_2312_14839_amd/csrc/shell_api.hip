@@ -100,6 +100,8 @@ struct shell_ctx {
     };
     bool graphs = true;
     bool cg_resident = true;   // register-resident CG vectors where the layout allows
+    int hs_waves = 4;          // patches (wavefronts) per block of the Hessian kernel
+    int eg_patches = 16;       // patches per block of the energy and gradient kernel
     hipStream_t cap_stream = nullptr;
     Seg g_asm, g_trial, g_floor, g_cg, g_newton;
     void graphs_reset() {
@@ -661,7 +663,7 @@ void eval_energy_grad(shell_ctx* c, const double* q_in, const double* qhat, doub
     launch_energy_grad(st, c->P, dptr<int4>(c->patch_nodes), dptr<int>(c->patch_shell),
                        dptr<ShellParams>(c->shells_d), dptr<double>(c->phi), q_in, dptr<double>(c->qbar), qhat,
                        mass_scale, c->dt_damp, 1, loads, eval_shell_dev, dptr<double>(c->e_patch),
-                       dptr<double>(c->g_patch));
+                       dptr<double>(c->g_patch), c->eg_patches);
     launch_shell_energy(st, c->S, dptr<ShellParams>(c->shells_d), dptr<double>(c->e_patch), dptr<double>(c->e_shell));
     if (grad_out)
         launch_gather_grad(st, c->N, dptr<int>(c->inc_ptr), dptr<int>(c->inc), dptr<double>(c->g_patch),
@@ -707,12 +709,13 @@ void assemble(shell_ctx* c, const double* q_in, double mass_scale, int elastic) 
             launch_hessian<float>(st, list, n, dptr<int4>(c->patch_nodes), dptr<int>(c->patch_shell),
                                   dptr<int>(c->patch_slots), dptr<uint64_t>(c->patch_kid), dptr<uint16_t>(c->patch_first),
                                   dptr<ShellParams>(c->shells_d), dptr<double>(c->phi), q_in,
-                                  dptr<double>(c->qbar), mass_scale, c->dt_damp, elastic, pseudo, dptr<float>(c->vals));
+                                  dptr<double>(c->qbar), mass_scale, c->dt_damp, elastic, pseudo, dptr<float>(c->vals),
+                                  c->hs_waves);
         else
             launch_hessian<double>(st, list, n, dptr<int4>(c->patch_nodes), dptr<int>(c->patch_shell),
                                    dptr<int>(c->patch_slots), dptr<uint64_t>(c->patch_kid), dptr<uint16_t>(c->patch_first),
                                    dptr<ShellParams>(c->shells_d), dptr<double>(c->phi), q_in, dptr<double>(c->qbar), mass_scale, c->dt_damp, elastic, pseudo,
-                                   dptr<double>(c->vals));
+                                   dptr<double>(c->vals), c->hs_waves);
     }
     HIPCHK(hipGetLastError());
     tmr.stop();
@@ -2687,8 +2690,12 @@ struct TuneKey {
         return std::tie(device, N, S, fp32, nnzb) < std::tie(o.device, o.N, o.S, o.fp32, o.nnzb);
     }
 };
+struct TuneChoice {
+    int threads, spread;   // CG layout
+    int hs_waves, eg_patches;   // patch kernel tiles
+};
 std::mutex g_tune_mutex;
-std::map<TuneKey, std::pair<int, int>> g_tune_cache;   // -> (threads, spread)
+std::map<TuneKey, TuneChoice> g_tune_cache;
 
 // Wall time per CG iteration of the current layout: `iters` iterations of
 // every shell on b (tolerance 0), second of two runs.
@@ -2707,6 +2714,19 @@ double time_cg(shell_ctx* c, const double* b, int iters) {
 }
 }  // namespace
 
+shell_status shell_set_patch_tiles(shell_ctx* c, int32_t hess_waves, int32_t energy_patches) {
+    if (!c) return SHELL_E_INVAL;
+    if (!(hess_waves == 1 || hess_waves == 2 || hess_waves == 4 || hess_waves == 8) ||
+        !(energy_patches == 4 || energy_patches == 8 || energy_patches == 16)) {
+        c->err = "hess_waves must be 1, 2, 4 or 8 and energy_patches 4, 8 or 16";
+        return SHELL_E_INVAL;
+    }
+    c->hs_waves = hess_waves;
+    c->eg_patches = energy_patches;
+    c->graphs_reset();   // the captured sequences hold the launch shapes
+    return SHELL_OK;
+}
+
 shell_status shell_autotune(shell_ctx* c, int32_t cg_iters, shell_tune_result* out) {
     if (!c) return SHELL_E_INVAL;
     if (cg_iters < 1) {
@@ -2719,7 +2739,7 @@ shell_status shell_autotune(shell_ctx* c, int32_t cg_iters, shell_tune_result* o
     std::memset(&r, 0, sizeof(r));
     const TuneKey key{c->opts.device, c->N, c->S, (int)c->fp32, c->nnzb};
     bool cached = false;
-    std::pair<int, int> choice{c->cg_threads, 1};
+    TuneChoice choice{c->cg_threads, 1, c->hs_waves, c->eg_patches};
     {
         std::lock_guard<std::mutex> lk(g_tune_mutex);
         auto it = g_tune_cache.find(key);
@@ -2741,6 +2761,23 @@ shell_status shell_autotune(shell_ctx* c, int32_t cg_iters, shell_tune_result* o
     sync(c);
     const int nt0 = c->cg_threads, target0 = c->cg_rows_target;
     r.us_per_iter_default = time_cg(c, dptr<double>(c->rhs), cg_iters);
+    // patch kernel tiles: wall time of one assembly (Hessian kernels of all
+    // colours) and of one energy and gradient evaluation, best of three
+    auto time_best = [&](auto&& f) {
+        double best = 1e300;
+        for (int rep = 0; rep < 4; ++rep) {
+            const double t0 = now_ms();
+            f();
+            sync(c);
+            if (rep > 0) best = std::min(best, now_ms() - t0);
+        }
+        return 1e3 * best;
+    };
+    double* qb = dptr<double>(c->qbar);
+    auto t_hess = [&] { return time_best([&] { assemble(c, qb, 1.0, 1); }); };
+    auto t_eg = [&] { return time_best([&] { eval_energy_grad(c, qb, qb, 1.0, 1, true, dptr<double>(c->gt), nullptr); }); };
+    r.hess_us_default = t_hess();
+    r.energy_us_default = t_eg();
     if (!cached) {
         double best = 1e300;
         int max_rows = 0;
@@ -2755,13 +2792,37 @@ shell_status shell_autotune(shell_ctx* c, int32_t cg_iters, shell_tune_result* o
                 r.candidates++;
                 if (t < best) {
                     best = t;
-                    choice = {nt, spread};
+                    choice.threads = nt;
+                    choice.spread = spread;
                 }
             }
+        double bh = 1e300, be = 1e300;
+        for (int w : {1, 2, 4, 8}) {
+            c->hs_waves = w;
+            const double t = t_hess();
+            if (t < bh) {
+                bh = t;
+                choice.hs_waves = w;
+            }
+        }
+        for (int p : {4, 8, 16}) {
+            c->eg_patches = p;
+            const double t = t_eg();
+            if (t < be) {
+                be = t;
+                choice.eg_patches = p;
+            }
+        }
         std::lock_guard<std::mutex> lk(g_tune_mutex);
         g_tune_cache[key] = choice;
     }
-    if (!set_row_blocks(c, choice.first, choice.second)) throw StatusErr{SHELL_E_DEVICE, "autotuned layout lost"};
+    c->hs_waves = choice.hs_waves;
+    c->eg_patches = choice.eg_patches;
+    r.hess_us = t_hess();
+    r.energy_us = t_eg();
+    r.hess_waves = c->hs_waves;
+    r.energy_patches = c->eg_patches;
+    if (!set_row_blocks(c, choice.threads, choice.spread)) throw StatusErr{SHELL_E_DEVICE, "autotuned layout lost"};
     r.us_per_iter = time_cg(c, dptr<double>(c->rhs), cg_iters);
     r.threads = c->cg_threads;
     r.rows_per_block = c->cg_rows_target;

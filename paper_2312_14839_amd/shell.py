@@ -59,6 +59,9 @@ class shell_tune_result(C.Structure):
         ("default_threads", C.c_int32), ("default_rows_per_block", C.c_int32),
         ("candidates", C.c_int32), ("from_cache", C.c_int32),
         ("us_per_iter", C.c_double), ("us_per_iter_default", C.c_double),
+        ("hess_waves", C.c_int32), ("energy_patches", C.c_int32),
+        ("hess_us", C.c_double), ("hess_us_default", C.c_double), ("energy_us", C.c_double),
+        ("energy_us_default", C.c_double),
     ]
 
     def as_dict(self):
@@ -201,6 +204,8 @@ def _load():
     lib.shell_point_load.restype = C.c_int32
     lib.shell_autotune.argtypes = [vp, C.c_int32, P(shell_tune_result)]
     lib.shell_autotune.restype = C.c_int32
+    lib.shell_set_patch_tiles.argtypes = [vp, C.c_int32, C.c_int32]
+    lib.shell_set_patch_tiles.restype = C.c_int32
     lib.shell_mlp_set_params.argtypes = [vp, P(C.c_float)]
     lib.shell_mlp_set_params.restype = C.c_int32
     lib.shell_mlp_get_params.argtypes = [vp, P(C.c_float)]
@@ -240,7 +245,7 @@ EXPORTED = ["shell_default_opts", "shell_create", "shell_destroy", "shell_last_e
             "shell_energy_grad_hess", "shell_assemble", "shell_get_bsr", "shell_spmv", "shell_pcg_solve",
             "shell_newton_step", "shell_timing_enable", "shell_timing_get", "shell_mlp_set_params",
             "shell_mlp_get_params", "shell_mlp_forward", "shell_mlp_loss_grad", "shell_mlp_train",
-            "shell_mlp_record", "shell_mlp_recorded", "shell_autotune", "shell_set_nodal_forces",
+            "shell_mlp_record", "shell_mlp_recorded", "shell_autotune", "shell_set_patch_tiles", "shell_set_nodal_forces",
             "shell_point_load", "shell_bezier", "shell_ray_default_opts", "shell_ray_cast", "shell_ray_cast_noalloc",
             "shell_ccd", "shell_collide_default_opts", "shell_collide", "shell_set_pressure", "shell_pressure_load",
             "shell_set_point_constraints", "shell_get_point_multipliers", "shell_set_point_multipliers"]
@@ -424,6 +429,9 @@ class ShellContext:
 
     def set_nodal_forces(self, f):
         self._check(lib.shell_set_nodal_forces(self.h, _ptr(f)))
+
+    def set_patch_tiles(self, hess_waves, energy_patches):
+        self._check(lib.shell_set_patch_tiles(self.h, int(hess_waves), int(energy_patches)))
 
     def autotune(self, cg_iters=100):
         r = shell_tune_result()

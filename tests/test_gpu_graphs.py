@@ -1,11 +1,12 @@
-"""HIP graphs and the CG layout autotuner of the batched form.
+"""HIP graphs and the autotuner of the batched form.
 
 Graph replays run the same kernels in the same order as direct launches, so
 every Newton step (several replays of each captured sequence, with the
 solver's own eager work and synchronisations between them) must give
 bit-identical states.  The autotuner changes the CG row-block layout, which
 changes the order of the CG reductions only: results agree to the Newton
-tolerance.  A second context of the same shape takes the cached layout."""
+tolerance; its patch kernel tiles change nothing.  A second context of the
+same shape takes the cached choice."""
 import numpy as np
 import pytest
 
@@ -68,6 +69,35 @@ def test_autotune_same_result_and_cache():
     assert info["us_per_iter"] > 0
     disp = np.abs(a[-1] - np.concatenate([c.q0.reshape(-1) for c in cases])).max()
     assert np.abs(a[-1] - b[-1]).max() <= 1e-8 * disp
+    assert info["hess_waves"] in (1, 2, 4, 8) and info["energy_patches"] in (4, 8, 16)
+    assert info["hess_us"] > 0 and info["energy_us"] > 0
     _, _, info2 = _run(cases, 1, 0, graphs=True, tune=True)
     assert info2["from_cache"] == 1 and info2["candidates"] == 0
     assert (info2["threads"], info2["rows_per_block"]) == (info["threads"], info["rows_per_block"])
+    assert (info2["hess_waves"], info2["energy_patches"]) == (info["hess_waves"], info["energy_patches"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_patch_kernel_tiles_do_not_change_results(precision):
+    """Every patch is one wavefront's (Hessian) or 16 lanes' (energy) work
+    and patches of one colour share no matrix block, so the tiles only move
+    work between blocks: energies, gradient and matrix are bit-identical for
+    every tile the autotuner may choose."""
+    from paper_2312_14839_amd import shell as sh
+    case = W.case_twist(12)
+    prec = sh.SHELL_MIXED if precision == "mixed" else sh.SHELL_FP64
+    q = torch.from_numpy(W.random_state(case, seed=5).reshape(-1)).cuda()
+    ref = None
+    for waves, patches in ((4, 16), (1, 4), (2, 8), (8, 16)):
+        ctx = sh.context_for([case], precision=prec)
+        ctx.set_patch_tiles(waves, patches)
+        g = torch.empty_like(q)
+        e = ctx.energy_grad_hess(q, g, hessian=True)
+        rp, ci, vals = ctx.get_bsr(0)
+        out = (e, g.cpu().numpy(), vals)
+        ctx.close()
+        if ref is None:
+            ref = out
+        else:
+            assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1])
+            assert np.array_equal(out[2], ref[2]), (waves, patches)
