@@ -454,22 +454,23 @@ def post_buckling_section(stream, steps=3, before=300):
 
 
 def learned_section(stream):
-    """The learned Newton warm start on held-out sheets: samples recorded on
-    12 training sheets (24..48 patches a side, random twist / compression,
-    30 steps), the network trained on the GPU, then 12 steps of two 64x64
-    and one 128x128 unseen sheet, plain solver vs warm start (and the
-    extrapolation-only start, zero network, as the ablation)."""
+    """The learned Newton warm start on held-out sheets: samples recorded from
+    the solver's own steps on the twisting 30x30 sheet, the 256 batched
+    sheets and the 256x256 cylinder, the network trained on the GPU, then 12
+    steps of two 64x64 and one 128x128 unseen sheet under random twist /
+    compression, plain solver vs warm start (and the extrapolation-only
+    start, zero network, as the ablation)."""
     import torch
     from paper_2312_14839_amd import learned as L, workloads as W
     t0 = time.perf_counter()
-    rec = L.run(L.training_scene(count=12, seed=100), 30, record=dict(capacity=600000, per_shell=1024, seed=7),
-                stream=stream)
+    rec = L.record_configs(stream=stream)
     t_rec = time.perf_counter() - t0
     t0 = time.perf_counter()
     theta, losses = L.train(rec["feat"], rec["tgt"], rec["n_samples"], schedule=((8000, 1e-3), (4000, 3e-4)),
                             batch=512, seed=1)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    n_samples, per_workload = rec["n_samples"], rec["per_workload"]
     del rec
     scenes = [L.Scene([W.case_random_load(n, seed=sd)]) for n, sd in ((64, 906), (64, 910), (128, 903))]
     res = {"plain": [0, 0.0], "learned": [0, 0.0], "extrapolation_only": [0, 0.0]}
@@ -493,7 +494,8 @@ def learned_section(stream):
     # the gate's rule: the network counts only if it beats the same start
     # without it (extrapolation of the previous correction) on every scene
     out["network_accepted"] = bool(strict)
-    out.update({"train_steps": int(losses.size), "train_loss_first": float(np.mean(losses[:20])),
+    out.update({"train_samples": int(n_samples), "train_samples_per_workload": per_workload,
+                "train_steps": int(losses.size), "train_loss_first": float(np.mean(losses[:20])),
                 "train_loss_last": float(np.mean(losses[-100:])), "record_s": t_rec, "train_s": t_train,
                 "eval": "twist/compression 64x64 (seeds 906, 910) and 128x128 (seed 903), 12 steps each, dt 2e-3"})
     print(f"[bench] learned: CG its/step plain {out['plain']['cg_iters_per_step']:.1f} learned "

@@ -334,11 +334,11 @@ shell_status shell_set_patch_tiles(shell_ctx *c, int32_t hess_waves, int32_t ene
  * their parametric derivatives carry different units (Sec. 8, "Loss
  * functions"); the features are therefore scaled per DOF kind.
  *
- * A per-node network 36 -> 128 -> 128 -> 12 (ReLU, ReLU, linear):
+ * A per-node network 60 -> 128 -> 128 -> 12 (ReLU, ReLU, linear):
  *   h1 = relu(x W1 + b1), h2 = relu(h1 W2 + b2), y = h2 W3 + b3,
  * products in bfloat16 (round to nearest even) with FP32 accumulation,
  * FP32 master parameters.  Parameter vector (float, row-major, this order):
- *   W1[36][128], b1[128], W2[128][128], b2[128], W3[128][12], b3[12].
+ *   W1[60][128], b1[128], W2[128][128], b2[128], W3[128][12], b3[12].
  * Each step's Newton iteration starts at q_s (qhat = q_n + dt v_n on free
  * DOFs, prescribed values on the others) and ends at q_{n+1}; its
  * correction is D = q_{n+1} - q_s on free DOFs.  Features of node n of shell
@@ -347,8 +347,12 @@ shell_status shell_set_patch_tiles(shell_ctx *c, int32_t hess_waves, int32_t ene
  *   x[w]      = (q_s - qbar)[n][w] / s_u[s][k]   (displacement from the reference)
  *   x[12 + w] = b[n][w] / s_b[s][k]             (b = -grad E(q_s), 0 on prescribed DOFs)
  *   x[24 + w] = Dprev[n][w] / s_d[s][k]          (the previous step's correction)
+ *   x[36 + w] = (L b)[n][w] / s_b[s][k],  x[48 + w] = (L Dprev)[n][w] / s_d[s][k]
  * with s_*[s][k] the root mean square of that quantity over the free DOFs of
- * kind k of shell s (1 if it is zero).  The network predicts the change of
+ * kind k of shell s (1 if it is zero), and L the node's 3x3 grid stencil
+ * (L f)[n] = (4 sum of f over the four edge neighbours + sum over the four
+ * diagonal ones) / 20 - f[n], a missing neighbour (an open edge) counted as
+ * the node itself.  The network predicts the change of
  * the correction, w = s_d y on free DOFs.  The Newton iteration then starts
  * at q_s + c1 Dprev + c2 w, c the Galerkin solution of the quadratic model
  * of the incremental potential E in span{Dprev, w} (its Hessian from the
@@ -360,10 +364,10 @@ shell_status shell_set_patch_tiles(shell_ctx *c, int32_t hess_waves, int32_t ene
  * finite, it starts at q_s exactly as without a warm start.
  * Convergence is still measured against ||grad E(q_s)||.
  * ------------------------------------------------------------------ */
-#define SHELL_MLP_IN 36
+#define SHELL_MLP_IN 60
 #define SHELL_MLP_HIDDEN 128
 #define SHELL_MLP_OUT 12
-#define SHELL_MLP_PARAMS 22796
+#define SHELL_MLP_PARAMS 25868
 
 /* Load the network's parameters (theta_host: SHELL_MLP_PARAMS floats, host
  * memory, copied) and reset the Adam state.  Required before a step with
@@ -373,12 +377,12 @@ shell_status shell_mlp_set_params(shell_ctx *c, const float *theta_host);
 /* Copy the current parameters to theta_host (SHELL_MLP_PARAMS floats). */
 shell_status shell_mlp_get_params(shell_ctx *c, float *theta_host);
 
-/* Inference: out_dev[n][12] = y(feat_dev[n][36]), device arrays, n >= 0. */
+/* Inference: out_dev[n][12] = y(feat_dev[n][60]), device arrays, n >= 0. */
 shell_status shell_mlp_forward(shell_ctx *c, const float *feat_dev, float *out_dev, int64_t n);
 
 /* Loss and gradient of one mini-batch: samples idx_dev[batch] (int64,
  * device, each in [0, n_samples), checked: SHELL_E_INVAL otherwise) of
- * feat_dev[n_samples][36] / tgt_dev[n_samples][12]; loss = mean over the
+ * feat_dev[n_samples][60] / tgt_dev[n_samples][12]; loss = mean over the
  * batch of sum_w (y_w - t_w)^2.  batch is a positive multiple of 32.
  * loss_host (1 double) and grad_host (SHELL_MLP_PARAMS floats) may be NULL.
  * The parameters are not changed. */
@@ -396,7 +400,7 @@ shell_status shell_mlp_train(shell_ctx *c, const float *feat_dev, const float *t
 /* Record training samples during shell_newton_step: after each step,
  * per_shell nodes of every shell that converged and has a previous
  * correction (picked by a hash of seed, call and sample index) append their
- * features at the step's start (feat_dev[.][36]) and the target
+ * features at the step's start (feat_dev[.][60]) and the target
  * t = (D - Dprev) / s_d (tgt_dev[.][12]), while capacity samples are not
  * exceeded.  The buffers are the caller's device memory and must outlive
  * the recording; feat_dev = NULL stops recording.  The sample count

@@ -1,7 +1,7 @@
 """CPU oracle of the per-node warm-start MLP.  TEST INFRASTRUCTURE ONLY.
 
-The network maps 36 node features to a 12-DOF correction:
-    h1 = relu(x W1 + b1)   (36 -> 128)
+The network maps 60 node features to a 12-DOF correction:
+    h1 = relu(x W1 + b1)   (60 -> 128)
     h2 = relu(h1 W2 + b2)  (128 -> 128)
     y  = h2 W3 + b3        (128 -> 12)
 and is trained on the squared error mean over samples of sum_k (y_k - t_k)^2.
@@ -14,11 +14,11 @@ products.  With bf16=False it
 is a plain FP64 network (used for finite-difference checks).
 
 Parameter vector layout (FP32 on the device, FP64 here), row-major:
-W1[36][128], b1[128], W2[128][128], b2[128], W3[128][12], b3[12].
+W1[60][128], b1[128], W2[128][128], b2[128], W3[128][12], b3[12].
 """
 import numpy as np
 
-N_IN, N_H, N_OUT = 36, 128, 12
+N_IN, N_H, N_OUT = 60, 128, 12
 SHAPES = [("W1", (N_IN, N_H)), ("b1", (N_H,)), ("W2", (N_H, N_H)), ("b2", (N_H,)), ("W3", (N_H, N_OUT)),
           ("b3", (N_OUT,))]
 N_PARAMS = sum(int(np.prod(s)) for _, s in SHAPES)

@@ -291,7 +291,7 @@ void launch_add_shell(hipStream_t st, int nnodes, const double* src, const int* 
                       double* dst);
 
 // --------------------------------------------------- warm-start network
-constexpr int MLP_IN = 36, MLP_H = 128, MLP_OUT = 12;
+constexpr int MLP_IN = 60, MLP_H = 128, MLP_OUT = 12;
 constexpr int MLP_NPARAMS = MLP_IN * MLP_H + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H * MLP_OUT + MLP_OUT;
 int mlp_bf16_elems();
 size_t mlp_train_work_bytes(int batch);
@@ -308,10 +308,11 @@ void launch_feat_scale(hipStream_t st, const RowBlocks& rb, int nshell, const do
                        float* scale);
 void launch_mlp_record(hipStream_t st, int nshell, int K, unsigned long long seed, const ShellParams* shells,
                        const long long* sbase, const double* q, const double* qbar, const double* b,
-                       const double* dprev, const double* d, const float* scale, float* feat_out, float* tgt_out);
+                       const double* dprev, const double* d, const int* nbr8 /* [N][8] */, const float* scale,
+                       float* feat_out, float* tgt_out);
 void launch_mlp_guess(hipStream_t st, int nnodes, const float* theta, const void* w, const int* node_shell,
                       const int* flag, const double* q, const double* qbar, const double* b, const double* dprev,
-                      const uint16_t* fm, const float* scale, double* corr);
+                      const uint16_t* fm, const int* nbr8, const float* scale, double* corr);
 void launch_axpy2_shell(hipStream_t st, int nnodes, const double* x, const double* d1, const double* d2,
                         const double* coef, const int* node_shell, double* y);
 void launch_masked_diff(hipStream_t st, int nnodes, const double* a, const double* b, const uint16_t* fm,

@@ -1,6 +1,6 @@
 // Per-node warm-start network of libbhem (gfx950, BF16 matrix cores).
 //
-// y = W3^T relu(W2^T relu(W1^T x + b1) + b2) + b3, 36 -> 128 -> 128 -> 12,
+// y = W3^T relu(W2^T relu(W1^T x + b1) + b2) + b3, 60 -> 128 -> 128 -> 12,
 // operands of every product in bfloat16, accumulation in FP32
 // (v_mfma_f32_16x16x32_bf16: 16x16 output, K = 32 per instruction).
 //
@@ -30,14 +30,14 @@ __device__ __forceinline__ f4_t mma_bf16(bf8_t a, bf8_t b, f4_t c) {
 __device__ __forceinline__ bf8_t load_bf8(const __bf16* p) { return *reinterpret_cast<const bf8_t*>(p); }
 
 // Parameter offsets of the FP32 master vector (math layout, row-major):
-// W1[36][128], b1[128], W2[128][128], b2[128], W3[128][12], b3[12].
+// W1[60][128], b1[128], W2[128][128], b2[128], W3[128][12], b3[12].
 constexpr int O_W1 = 0, O_B1 = O_W1 + MLP_IN * MLP_H, O_W2 = O_B1 + MLP_H, O_B2 = O_W2 + MLP_H * MLP_H,
               O_W3 = O_B2 + MLP_H, O_B3 = O_W3 + MLP_H * MLP_OUT;
 static_assert(O_B3 + MLP_OUT == MLP_NPARAMS, "parameter layout");
 
 // bf16 operand copies: forward [n][k] with K padded to a multiple of 32,
 // backward math layout [k][n] with N padded to 32 for W3.
-constexpr int K1P = 64;      // 36 -> 64
+constexpr int K1P = 64;      // 60 -> 64
 constexpr int N3P = 16;      // 12 -> 16 (forward output tile)
 constexpr int K3BP = 32;     // 12 -> 32 (backward reduction over outputs)
 constexpr int OFF_F1 = 0;                      // W1nk [128][64]
@@ -269,21 +269,23 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_bwd(const float* __restrict__ t
 // grad(W)[m][n] += sum over samples of AT[m][s] * DT[n][s] for one 16x16
 // output tile and one slice of samples; A operand lane: AT[m = row][s..],
 // B operand lane: DT[n][s..] (samples contiguous in both).
+// output tiles: W1 (MLP_IN rows, padded to K1P) x 8, W2 8x8, W3 8x1
+constexpr int WG_T1 = ((MLP_IN + 15) / 16) * 8, WG_T2 = WG_T1 + 64, WG_TILES = WG_T2 + 8;
+static_assert(MLP_IN <= K1P, "input features fit the padded first layer");
 __global__ __launch_bounds__(64) void k_mlp_wgrad(TrainWork W, int B, int slice, float* __restrict__ grad) {
-    // tiles: W1 3x8 (rows 0..47 of the padded 64), W2 8x8, W3 8x1
     const int tile = blockIdx.x, sl = blockIdx.y;
     const int lane = threadIdx.x, r = lane & 15, kq = lane >> 4, c = lane & 15, rq = lane >> 4;
     const __bf16 *AT, *DT;
     int m0, n0, go, ldn, mlim, nlim;
-    if (tile < 24) {
+    if (tile < WG_T1) {
         AT = W.XT; DT = W.D1T; m0 = 16 * (tile / 8); n0 = 16 * (tile % 8); go = O_W1; ldn = MLP_H; mlim = MLP_IN;
         nlim = MLP_H;
-    } else if (tile < 88) {
-        const int t = tile - 24;
+    } else if (tile < WG_T2) {
+        const int t = tile - WG_T1;
         AT = W.H1T; DT = W.D2T; m0 = 16 * (t / 8); n0 = 16 * (t % 8); go = O_W2; ldn = MLP_H; mlim = MLP_H;
         nlim = MLP_H;
     } else {
-        const int t = tile - 88;
+        const int t = tile - WG_T2;
         AT = W.H2T; DT = W.DYT; m0 = 16 * t; n0 = 0; go = O_W3; ldn = MLP_OUT; mlim = MLP_H; nlim = MLP_OUT;
     }
     f4_t acc = {0, 0, 0, 0};
@@ -360,9 +362,17 @@ __global__ void k_feat_scale_fin(int nshell, const int* __restrict__ shell_blk0,
     scale[t] = (float)(rms > 1e-300 ? rms : 1.0);
 }
 
-// 36 features of node `node`: u / s_u, b / s_b, dprev / s_d (per kind).
+// 60 features of node `node` (per kind scales sc): u / s_u, b / s_b,
+// dprev / s_d, and the 3x3 grid stencil L b / s_b, L dprev / s_d with
+// (L f)[n] = (4 sum over the edge neighbours + sum over the diagonal ones) / 20
+// - f[n]; nbr: the node's 8 neighbours (edge ones at 1, 3, 4, 6), a missing
+// neighbour given as the node itself.
 __device__ __forceinline__ void node_features(int node, const double* q, const double* qbar, const double* b,
-                                              const double* dprev, const float* sc, float* f) {
+                                              const double* dprev, const int* __restrict__ nbr8, const float* sc,
+                                              float* f) {
+    int nb[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) nb[k] = nbr8[8 * (size_t)node + k];
 #pragma unroll
     for (int w = 0; w < 12; ++w) {
         const size_t e = (size_t)node * 12 + w;
@@ -370,6 +380,15 @@ __device__ __forceinline__ void node_features(int node, const double* q, const d
         f[w] = (float)((q[e] - qbar[e]) / sc[kind]);
         f[12 + w] = (float)(b[e] / sc[4 + kind]);
         f[24 + w] = (float)(dprev[e] / sc[8 + kind]);
+        double sb = 0.0, sd = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const double wk = (k == 1 || k == 3 || k == 4 || k == 6) ? 4.0 : 1.0;
+            sb += wk * b[(size_t)nb[k] * 12 + w];
+            sd += wk * dprev[(size_t)nb[k] * 12 + w];
+        }
+        f[36 + w] = (float)((sb / 20.0 - b[e]) / sc[4 + kind]);
+        f[48 + w] = (float)((sd / 20.0 - dprev[e]) / sc[8 + kind]);
     }
 }
 
@@ -381,8 +400,8 @@ __global__ void k_mlp_record(int nshell, int K, unsigned long long seed, const S
                              const long long* __restrict__ sbase, const double* __restrict__ q,
                              const double* __restrict__ qbar, const double* __restrict__ b,
                              const double* __restrict__ dprev, const double* __restrict__ d,
-                             const float* __restrict__ scale, float* __restrict__ feat_out,
-                             float* __restrict__ tgt_out) {
+                             const int* __restrict__ nbr8, const float* __restrict__ scale,
+                             float* __restrict__ feat_out, float* __restrict__ tgt_out) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nshell * K) return;
     const int s = t / K;
@@ -399,7 +418,7 @@ __global__ void k_mlp_record(int nshell, int K, unsigned long long seed, const S
     const int node = n0 + (int)(x % (unsigned long long)nn);
     const float* sc = scale + 12 * s;
     float f[MLP_IN];
-    node_features(node, q, qbar, b, dprev, sc, f);
+    node_features(node, q, qbar, b, dprev, nbr8, sc, f);
     for (int k = 0; k < MLP_IN; ++k) o[k] = f[k];
     for (int w = 0; w < 12; ++w) {
         const size_t e = (size_t)node * 12 + w;
@@ -414,7 +433,8 @@ __global__ __launch_bounds__(256) void k_mlp_guess(int nnodes, const float* __re
                                                    const int* __restrict__ flag, const double* __restrict__ q,
                                                    const double* __restrict__ qbar, const double* __restrict__ b,
                                                    const double* __restrict__ dprev, const uint16_t* __restrict__ fm,
-                                                   const float* __restrict__ scale, double* __restrict__ corr) {
+                                                   const int* __restrict__ nbr8, const float* __restrict__ scale,
+                                                   double* __restrict__ corr) {
     __shared__ MlpTileLds lds[MLP_WAVES];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     MlpTileLds& L = lds[wv];
@@ -422,7 +442,7 @@ __global__ __launch_bounds__(256) void k_mlp_guess(int nnodes, const float* __re
     if (lane < 16) {
         const int node = tile0 + lane;
         float f[MLP_IN];
-        if (node < nnodes) node_features(node, q, qbar, b, dprev, scale + 12 * node_shell[node], f);
+        if (node < nnodes) node_features(node, q, qbar, b, dprev, nbr8, scale + 12 * node_shell[node], f);
         for (int k = 0; k < K1P; ++k) L.X[lane * K1P + k] = (__bf16)((k < MLP_IN && node < nnodes) ? f[k] : 0.0f);
     }
     __syncthreads();
@@ -497,7 +517,7 @@ void launch_mlp_grad(hipStream_t st, const float* th, const void* w, const float
     hipLaunchKernelGGL(k_mlp_fwd_bwd, dim3((tiles + MLP_WAVES - 1) / MLP_WAVES), dim3(256), 0, st, th,
                        (const __bf16*)w, feat, tgt, idx, B, W, grad, loss);
     const int slice = 256;
-    hipLaunchKernelGGL(k_mlp_wgrad, dim3(96, (B + slice - 1) / slice), dim3(64), 0, st, W, B, slice, grad);
+    hipLaunchKernelGGL(k_mlp_wgrad, dim3(WG_TILES, (B + slice - 1) / slice), dim3(64), 0, st, W, B, slice, grad);
 }
 
 void launch_mlp_adam(hipStream_t st, float* th, const float* g, float* m, float* v, int n, float lr, int step) {
@@ -518,10 +538,11 @@ void launch_feat_scale(hipStream_t st, const RowBlocks& rb, int nshell, const do
 
 void launch_mlp_record(hipStream_t st, int nshell, int K, unsigned long long seed, const ShellParams* shells,
                        const long long* sbase, const double* q, const double* qbar, const double* b,
-                       const double* dprev, const double* d, const float* scale, float* feat_out, float* tgt_out) {
+                       const double* dprev, const double* d, const int* nbr8, const float* scale, float* feat_out,
+                       float* tgt_out) {
     const int n = nshell * K;
     hipLaunchKernelGGL(k_mlp_record, dim3((n + 127) / 128), dim3(128), 0, st, nshell, K, seed, shells, sbase, q, qbar,
-                       b, dprev, d, scale, feat_out, tgt_out);
+                       b, dprev, d, nbr8, scale, feat_out, tgt_out);
 }
 
 void launch_sample_idx(hipStream_t st, long long n, int batch, unsigned long long seed, long long* idx) {
@@ -530,10 +551,10 @@ void launch_sample_idx(hipStream_t st, long long n, int batch, unsigned long lon
 
 void launch_mlp_guess(hipStream_t st, int nnodes, const float* th, const void* w, const int* node_shell,
                       const int* flag, const double* q, const double* qbar, const double* b, const double* dprev,
-                      const uint16_t* fm, const float* scale, double* corr) {
+                      const uint16_t* fm, const int* nbr8, const float* scale, double* corr) {
     const int tiles = (nnodes + 15) / 16;
     hipLaunchKernelGGL(k_mlp_guess, dim3((tiles + MLP_WAVES - 1) / MLP_WAVES), dim3(256), 0, st, nnodes, th,
-                       (const __bf16*)w, node_shell, flag, q, qbar, b, dprev, fm, scale, corr);
+                       (const __bf16*)w, node_shell, flag, q, qbar, b, dprev, fm, nbr8, scale, corr);
 }
 
 void launch_axpy2_shell(hipStream_t st, int nnodes, const double* x, const double* d1, const double* d2,

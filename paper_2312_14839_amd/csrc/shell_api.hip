@@ -82,6 +82,7 @@ struct shell_ctx {
     int adam_step = 0;
     DevBuf mlp_theta, mlp_w, mlp_m, mlp_v, mlp_grad, mlp_loss, mlp_idx, mlp_work, feat_part, feat_scale, cnt_kind,
         dstep, qstart, b0, guess, rec_base;
+    DevBuf nbr8;   // [N][8] grid neighbours of each node (the node itself where there is none)
     std::vector<char> h_hist;   // per shell: dstep holds the last step's correction
     int mlp_work_batch = 0;
     long long mlp_loss_n = 0;
@@ -430,6 +431,32 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
             c->h_freemask[nb + i] = m;
             c->h_node_shell[nb + i] = s;
         }
+    }
+    // the 3x3 grid neighbours of every node, row by row: (-1,-1), (0,-1),
+    // (1,-1), (-1,0), (1,0), (-1,1), (0,1), (1,1); across a periodic seam
+    // the column wraps, past an open edge the node stands for itself
+    {
+        std::vector<int> nbr((size_t)N * 8);
+        for (int s = 0; s < S; ++s) {
+            const shell_desc& d = ds[s];
+            const int cols = node_cols(d), nb = c->shells[s].node_begin;
+            for (int j = 0; j <= d.n2; ++j)
+                for (int i = 0; i < cols; ++i) {
+                    const int self = nb + j * cols + i;
+                    int k = 0;
+                    for (int dj = -1; dj <= 1; ++dj)
+                        for (int di = -1; di <= 1; ++di) {
+                            if (di == 0 && dj == 0) continue;
+                            int ii = i + di;
+                            const int jj = j + dj;
+                            if (d.periodic1) ii = (ii + cols) % cols;
+                            const bool in = ii >= 0 && ii < cols && jj >= 0 && jj <= d.n2;
+                            nbr[(size_t)self * 8 + k++] = in ? nb + jj * cols + ii : self;
+                        }
+                }
+        }
+        upload(c->nbr8, nbr, st);
+        sync(c);   // the host vector is released at the end of this scope
     }
     // patches, colours, pattern
     std::vector<int4> pnodes(P);
@@ -1063,7 +1090,7 @@ void newton_warm_start(shell_ctx* c, double ms, const std::vector<int>& active, 
     h2d(c, c->flag_shell.p, cand.data(), S * sizeof(int));
     launch_mlp_guess(st, c->N, dptr<float>(c->mlp_theta), c->mlp_w.p, dptr<int>(c->node_shell),
                      dptr<int>(c->flag_shell), q, dptr<double>(c->qbar), dptr<double>(c->b0), d1,
-                     dptr<uint16_t>(c->freemask), dptr<float>(c->feat_scale), d2);
+                     dptr<uint16_t>(c->freemask), dptr<int>(c->nbr8), dptr<float>(c->feat_scale), d2);
     HIPCHK(hipGetLastError());
     auto dots = [&](const double* x, const double* y) {
         shell_dot(c, x, y, true);
@@ -1175,7 +1202,7 @@ void record_samples(shell_ctx* c, const double* d, const std::vector<int>& flag)
     const unsigned long long seed = c->rec_seed + 0xD1B54A32D192ED03ull * (unsigned long long)(++c->rec_calls);
     launch_mlp_record(c->stream, S, c->rec_K, seed, dptr<ShellParams>(c->shells_d), dptr<long long>(c->rec_base),
                       dptr<double>(c->qstart), dptr<double>(c->qbar), dptr<double>(c->b0), dptr<double>(c->dstep), d,
-                      dptr<float>(c->feat_scale), c->rec_feat, c->rec_tgt);
+                      dptr<int>(c->nbr8), dptr<float>(c->feat_scale), c->rec_feat, c->rec_tgt);
     HIPCHK(hipGetLastError());
 }
 

@@ -123,6 +123,36 @@ def training_scene(count: int = 12, seed: int = 100, nmin: int = 24, nmax: int =
     return Scene(cases)
 
 
+def record_configs(stream=None, twist_steps: int = 60, batch_steps: int = 3, cylinder_steps: int = 4,
+                   seed: int = 7) -> Dict:
+    """Training samples recorded from the solver's own converged steps on
+    the three workloads of the method: the 30x30 twisting sheet
+    (`twist_steps` steps, 512 nodes a step), the 256 batched sheets
+    (`batch_steps` steps, 32 nodes per sheet a step) and the 256x256
+    compressed cylinder (`cylinder_steps` steps, 4096 nodes a step; FP64
+    throughout).  A step records only once its shell has a previous
+    correction.  Returns the concatenated device tensors, their count and the
+    count per workload."""
+    import torch
+    plan = [("twist30", Scene([W.case_twist(30)]), twist_steps, 512, 1e-10),
+            ("batch256", Scene(W.case_batch(256)), batch_steps, 32, 1e-10),
+            ("cylinder256", Scene([W.case_cylinder(256, 256)]), cylinder_steps, 4096, 1e-8)]
+    feats, tgts, counts = [], [], {}
+    for k, (name, sc, steps, per_shell, pcg_rtol) in enumerate(plan):
+        cap = per_shell * len(sc.cases) * steps
+        r = run(sc, steps, record=dict(capacity=cap, per_shell=per_shell, seed=seed + k), pcg_rtol=pcg_rtol,
+                stream=stream)
+        if any(st != S.SHELL_OK for st in r["status"]):
+            raise RuntimeError(f"recording on {name}: a step did not converge")
+        n = int(r["n_samples"])
+        counts[name] = n
+        feats.append(r["feat"][:n])
+        tgts.append(r["tgt"][:n])
+    feat = torch.cat(feats).contiguous()
+    tgt = torch.cat(tgts).contiguous()
+    return {"feat": feat, "tgt": tgt, "n_samples": int(feat.shape[0]), "per_workload": counts}
+
+
 def gate(theta: np.ndarray, scenes: Sequence[Scene], steps: int, **kw) -> Dict:
     """Acceptance gate: the network is kept only if, on every held-out scene,
     CG needs strictly fewer iterations with it than with the

@@ -250,7 +250,7 @@ EXPORTED = ["shell_default_opts", "shell_create", "shell_destroy", "shell_last_e
             "shell_ccd", "shell_collide_default_opts", "shell_collide", "shell_set_pressure", "shell_pressure_load",
             "shell_set_point_constraints", "shell_get_point_multipliers", "shell_set_point_multipliers"]
 
-MLP_IN, MLP_HIDDEN, MLP_OUT = 36, 128, 12
+MLP_IN, MLP_HIDDEN, MLP_OUT = 60, 128, 12
 MLP_PARAMS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_OUT + MLP_OUT
 
 

@@ -49,7 +49,7 @@ def test_forward_matches_oracle():
     rng = np.random.default_rng(3)
     theta = _theta(1)
     n = 1003                      # 62 full tiles of 16 and a ragged one
-    x = rng.normal(size=(n, 36)).astype(np.float32)
+    x = rng.normal(size=(n, M.N_IN)).astype(np.float32)
     ctx = _ctx()
     ctx.mlp_set_params(theta)
     out = torch.zeros((n, 12), dtype=torch.float32, device="cuda")
@@ -64,7 +64,7 @@ def test_forward_matches_oracle():
     y64, _ = M.forward(theta, x.astype(np.float64), bf16=False)
     assert np.abs(y64 - y_ref).max() > 10 * np.median(err) + 1e-7 * scale
     # empty input is a no-op
-    ctx.mlp_forward(torch.zeros((0, 36), dtype=torch.float32, device="cuda"),
+    ctx.mlp_forward(torch.zeros((0, M.N_IN), dtype=torch.float32, device="cuda"),
                     torch.zeros((0, 12), dtype=torch.float32, device="cuda"))
     ctx.close()
 
@@ -74,7 +74,7 @@ def test_loss_and_gradient_match_oracle(batch):
     rng = np.random.default_rng(batch)
     theta = _theta(2)
     n = 777
-    x = rng.normal(size=(n, 36)).astype(np.float32)
+    x = rng.normal(size=(n, M.N_IN)).astype(np.float32)
     t = rng.normal(size=(n, 12)).astype(np.float32)
     idx = rng.integers(0, n, size=batch)          # with repeats
     ctx = _ctx()
@@ -99,7 +99,7 @@ def test_loss_and_gradient_match_oracle(batch):
 def test_invalid_batch_rejected():
     ctx = _ctx()
     ctx.mlp_set_params(_theta(0))
-    x = torch.zeros((64, 36), dtype=torch.float32, device="cuda")
+    x = torch.zeros((64, M.N_IN), dtype=torch.float32, device="cuda")
     t = torch.zeros((64, 12), dtype=torch.float32, device="cuda")
     idx = torch.zeros(48, dtype=torch.int64, device="cuda")
     with pytest.raises(S().ShellError):
@@ -116,8 +116,8 @@ def test_invalid_batch_rejected():
 def test_training_lowers_loss_and_adam_first_step():
     rng = np.random.default_rng(5)
     n = 4096
-    x = rng.normal(size=(n, 36)).astype(np.float32)
-    A = rng.normal(size=(36, 12)) / 6.0
+    x = rng.normal(size=(n, M.N_IN)).astype(np.float32)
+    A = rng.normal(size=(M.N_IN, 12)) / np.sqrt(M.N_IN)
     B = rng.normal(size=(12, 12)) / 3.0
     t = (np.tanh(x @ A) @ B).astype(np.float32)          # a smooth teacher
     ctx = _ctx()
@@ -190,7 +190,8 @@ def test_extrapolation_warm_start_same_result():
 
 def test_trained_warm_start_gate_on_unseen_sheets():
     """The whole learned path: samples recorded from the solver's own steps
-    on training sheets (24..48 patches a side), network trained on the GPU,
+    on the twisting sheet, the batched sheets and the cylinder, network
+    trained on the GPU,
     then held-out 64x64 sheets under random twist / compression.  The
     acceptance gate compares the learned start with the extrapolation-only
     start (zero network): it keeps the network only if every held-out scene
@@ -198,8 +199,10 @@ def test_trained_warm_start_gate_on_unseen_sheets():
     warm-started states agree with the plain solver's and the extrapolation
     start is no worse than plain."""
     from paper_2312_14839_amd import learned as L
-    rec = L.run(L.training_scene(count=12, seed=100), 30, record=dict(capacity=600000, per_shell=1024, seed=7))
-    assert all(st == 0 for st in rec["status"]) and rec["n_samples"] > 100000
+    rec = L.record_configs()
+    print("samples", rec["per_workload"], flush=True)
+    assert rec["n_samples"] >= 50000 and all(v > 0 for v in rec["per_workload"].values())
+    assert bool(torch.isfinite(rec["feat"]).all()) and bool(torch.isfinite(rec["tgt"]).all())
     theta, losses = L.train(rec["feat"], rec["tgt"], rec["n_samples"], schedule=((8000, 1e-3), (4000, 3e-4)),
                             batch=512, seed=1)
     assert np.mean(losses[-100:]) < 0.8 * np.mean(losses[:20])

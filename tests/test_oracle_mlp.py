@@ -9,17 +9,24 @@ from oracle import mlp_oracle as M
 
 
 def test_parameter_count():
-    assert M.N_PARAMS == 36 * 128 + 128 + 128 * 128 + 128 + 128 * 12 + 12
+    assert M.N_PARAMS == 60 * 128 + 128 + 128 * 128 + 128 + 128 * 12 + 12
 
 
 def test_backward_matches_central_differences():
     rng = np.random.default_rng(0)
     theta = M.init_params(1)
     theta += 0.05 * rng.normal(size=theta.shape)      # non-zero last layer
-    x = rng.normal(size=(7, 36))
+    x = rng.normal(size=(7, M.N_IN))
     t = rng.normal(size=(7, 12))
     loss, g = M.loss_and_grad(theta, x, t)
-    idx = rng.choice(theta.size, 60, replace=False)
+    # random entries plus a few of every parameter tensor (all of the small
+    # output bias), so a slip in any tensor's gradient shows
+    idx = list(rng.choice(theta.size, 60, replace=False))
+    off = 0
+    for name, shape in M.SHAPES:
+        size = int(np.prod(shape))
+        idx += list(off + rng.choice(size, min(size, 12), replace=False))
+        off += size
     for i in idx:
         e = np.zeros_like(theta)
         e[i] = 1e-6
