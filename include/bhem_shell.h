@@ -304,7 +304,7 @@ shell_status shell_timing_get(const shell_ctx *c, shell_timing *out);
  * shell_autotune times cg_iters CG iterations of every candidate on K(qbar)
  * + M (overwriting the context's matrix) and keeps the fastest.  Patch
  * kernel tiles: the patches (wavefronts) per block of the Hessian kernel
- * (1, 2, 4 or 8) and the patches per block of the energy and gradient
+ * (4 or 8) and the patches per block of the energy and gradient
  * kernel (4, 8 or 16, 16 threads each), each chosen by the wall time of one
  * assembly / one evaluation at qbar.  Results are cached for the process by
  * (device, nodes, shells, block non-zeros, precision); a cached choice is
@@ -322,7 +322,7 @@ typedef struct {
 shell_status shell_autotune(shell_ctx *c, int32_t cg_iters, shell_tune_result *out);
 
 /* Set the patch kernel tiles by hand: hess_waves patches (wavefronts) per
- * block of the Hessian kernel (1, 2, 4 or 8), energy_patches patches per
+ * block of the Hessian kernel (4 or 8), energy_patches patches per
  * block of the energy and gradient kernel (4, 8 or 16).  Results do not
  * depend on them (each patch is computed by one wavefront or 16 lanes, and
  * patches of one colour share no matrix block).  SHELL_E_INVAL otherwise. */

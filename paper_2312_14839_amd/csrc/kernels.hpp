@@ -30,7 +30,7 @@ void launch_hessian(hipStream_t st, const int* patch_list, int nlist, const int4
                     const int* patch_slots, const uint64_t* patch_kid, const uint16_t* patch_first,
                     const ShellParams* shells, const double* phi, const double* q, const double* qbar,
                     double mass_scale, double dt_damp, int elastic, int pseudo, T* vals,
-                    int waves /* patches (wavefronts) per block: 1, 2, 4 or 8 */);
+                    int waves /* patches (wavefronts) per block: 4 or 8 */);
 
 // --------------------------------------------------------- ray kernels
 // ctrl: [P][4][4][3] Bezier control points, p_ij at ((4p + i)*4 + j)*3.

@@ -246,8 +246,12 @@ __global__ void k_shell_energy(int nshell, const ShellParams* __restrict__ shell
 }
 
 // ---------------------------------------------------------------- K2
-// NWV patches (wavefronts) per block: 1, 2, 4 or 8, chosen by the
-// autotuner (4 by default)
+// NWV patches (wavefronts) per block: 4 or 8, chosen by the autotuner (4
+// by default).  Each wavefront gathers, contracts and scatters its own
+// patch; the second derivative of the energy density (phase 1b) is shared
+// out by part instead: in each group of four wavefronts, wavefront w
+// computes part w of it (hess_blocks) for the group's four patches x 16
+// Gauss points, one per lane, so no wavefront diverges on the part.
 
 __host__ __device__ constexpr int pair_index(int i, int j) {   // i <= j
     return i == j ? i : (i == 0 ? (j == 1 ? 3 : 4) : 5);
@@ -267,9 +271,13 @@ __global__ __launch_bounds__(64 * NWV) void k_hessian(const int* __restrict__ pa
     typedef Mfma<T> MM;
     constexpr int WSZ = 16 * 121;   // packed W per Gauss point (+ mass term) and pair staging (6*256)
     static_assert(WSZ >= 6 * 256, "staging must fit");
+    static_assert(NWV % 4 == 0, "phase 1b shares four patches among four wavefronts");
     __shared__ T s_u[NWV][48], s_b[NWV][48];
     __shared__ T s_kin[NWV][16][30];
     __shared__ T s_w[NWV][WSZ];
+    // per patch of the block: lam, mu, h, dxi1, dxi2, mass coefficient
+    // rho h mass_scale (1 + alpha dt_damp)
+    __shared__ double s_par[NWV][6];
     // the wavefront's patch and everything derived from it are wave-uniform
     // (scalar registers and loads)
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -289,12 +297,20 @@ __global__ __launch_bounds__(64 * NWV) void k_hessian(const int* __restrict__ pa
         s_u[wv][lane] = (T)(ks * (q[gi] - qb));
         s_b[wv][lane] = (T)(ks * qb);
     }
+    if (active && lane == 0) {
+        s_par[wv][0] = sp.lam;
+        s_par[wv][1] = sp.mu;
+        s_par[wv][2] = sp.h;
+        s_par[wv][3] = sp.dxi1;
+        s_par[wv][4] = sp.dxi2;
+        s_par[wv][5] = sp.rho_h * mass_scale * (1.0 + sp.damp * dt_damp);
+    }
     __syncthreads();
     // phase 1a: kinematics, 30 values per Gauss point split over 4 lanes
-    const int g = lane >> 2, quarter = lane & 3;
     if (active) {
+        const int g = lane >> 2, sub = lane & 3;
         const double* ph = phi + g * 96;
-        for (int vi = quarter; vi < 30; vi += 4) {
+        for (int vi = sub; vi < 30; vi += 4) {
             const int src = vi / 15, a = (vi % 15) / 3, comp = vi % 3;
             const T* x = src ? s_u[wv] : s_b[wv];
             T acc = T(0);
@@ -303,22 +319,27 @@ __global__ __launch_bounds__(64 * NWV) void k_hessian(const int* __restrict__ pa
         }
     }
     __syncthreads();
-    // phase 1b: 15x15 second derivative of the energy density (+ mass term)
-    if (active) {
-        T kin[30];
+    // phase 1b: 15x15 second derivative of the energy density (+ mass term);
+    // lane = (patch slot of the group, Gauss point), part = wavefront in group
+    {
+        const int part = wv & 3, slot = (wv & ~3) + (lane >> 4), gp = lane & 15;
+        if (blockIdx.x * NWV + slot < nlist) {
+            const double* par = s_par[slot];
+            T kin[30];
 #pragma unroll
-        for (int k = 0; k < 30; ++k) kin[k] = s_kin[wv][g][k];
-        GaussPoint<T> G;
-        const T wt = (T)(gauss_weight(g & 3) * gauss_weight(g >> 2) * sp.dxi1 * sp.dxi2);
-        gauss_point<T>(kin, wt, (T)sp.lam, (T)sp.mu, (T)sp.h, G);
-        T* Wg = W + g * 121;
-        if (elastic) {
-            T sc[5];
+            for (int k = 0; k < 30; ++k) kin[k] = s_kin[slot][gp][k];
+            GaussPoint<T> G;
+            const T wt = (T)(gauss_weight(gp & 3) * gauss_weight(gp >> 2) * par[3] * par[4]);
+            gauss_point<T>(kin, wt, (T)par[0], (T)par[1], (T)par[2], G);
+            T* Wg = s_w[slot] + gp * 121;
+            if (elastic) {
+                T sc[5];
 #pragma unroll
-            for (int a = 0; a < 5; ++a) sc[a] = (T)slot_scale(a, sp.dxi1, sp.dxi2);
-            hess_blocks<T>(G, quarter, pseudo, sc, Wg);
+                for (int a = 0; a < 5; ++a) sc[a] = (T)slot_scale(a, par[3], par[4]);
+                hess_blocks<T>(G, part, pseudo, sc, Wg);
+            }
+            if (part == 3) Wg[120] = G.wq * (T)par[5];
         }
-        if (quarter == 3) Wg[120] = G.wq * (T)(sp.rho_h * mass_scale * (1.0 + sp.damp * dt_damp));
     }
     __syncthreads();
     // phase 2: K^{ij} = sum over (slot a, Gauss point g) of Phi^T W^{ij} Phi on the matrix cores.
@@ -499,16 +520,14 @@ void launch_hessian(hipStream_t st, const int* patch_list, int nlist, const int4
                     const ShellParams* shells, const double* phi, const double* q, const double* qbar,
                     double mass_scale, double dt_damp, int elastic, int pseudo, T* vals, int waves) {
     if (nlist == 0) return;
-    const int nw = waves == 1 || waves == 2 || waves == 8 ? waves : 4;
+    const int nw = waves == 8 ? 8 : 4;
     const int nb = (nlist + nw - 1) / nw;
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(nb), dim3(64 * nw), 0, st, patch_list, nlist, patch_nodes, patch_shell,
                            patch_slots, patch_kid, patch_first, shells, phi, q, qbar, mass_scale, dt_damp, elastic,
                            pseudo, vals);
     };
-    if (nw == 1) go(k_hessian<T, 1>);
-    else if (nw == 2) go(k_hessian<T, 2>);
-    else if (nw == 8) go(k_hessian<T, 8>);
+    if (nw == 8) go(k_hessian<T, 8>);
     else go(k_hessian<T, 4>);
 }
 

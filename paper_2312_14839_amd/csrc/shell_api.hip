@@ -2743,9 +2743,8 @@ double time_cg(shell_ctx* c, const double* b, int iters) {
 
 shell_status shell_set_patch_tiles(shell_ctx* c, int32_t hess_waves, int32_t energy_patches) {
     if (!c) return SHELL_E_INVAL;
-    if (!(hess_waves == 1 || hess_waves == 2 || hess_waves == 4 || hess_waves == 8) ||
-        !(energy_patches == 4 || energy_patches == 8 || energy_patches == 16)) {
-        c->err = "hess_waves must be 1, 2, 4 or 8 and energy_patches 4, 8 or 16";
+    if (!(hess_waves == 4 || hess_waves == 8) || !(energy_patches == 4 || energy_patches == 8 || energy_patches == 16)) {
+        c->err = "hess_waves must be 4 or 8 and energy_patches 4, 8 or 16";
         return SHELL_E_INVAL;
     }
     c->hs_waves = hess_waves;
@@ -2824,7 +2823,7 @@ shell_status shell_autotune(shell_ctx* c, int32_t cg_iters, shell_tune_result* o
                 }
             }
         double bh = 1e300, be = 1e300;
-        for (int w : {1, 2, 4, 8}) {
+        for (int w : {4, 8}) {
             c->hs_waves = w;
             const double t = t_hess();
             if (t < bh) {

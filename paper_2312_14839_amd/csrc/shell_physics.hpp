@@ -164,9 +164,11 @@ template <class T> struct Blk {
     }
 };
 
-// Hessian d2psi/dg2 (15x15), split over four lanes per quadrature point:
-//   quarter 0: blocks (a1,a1), (a2,a2);  quarter 1: (a1,a2);
-//   quarter 2: (a_alpha, v_k);          quarter 3: (v_k, v_l).
+// Hessian d2psi/dg2 (15x15) of one quadrature point in four parts of about
+// equal cost (a part is a wavefront's share for four patches, so the branch
+// is uniform across the wavefront):
+//   part 0: (a1,a1) and (v_0, v_l), l = 0..2;  part 1: (a2,a2) and (v_k, v_l),
+//   1 <= k <= l;  part 2: (a1,a2);  part 3: (a_A, v_l), A = 0, 1, l = 0..2.
 // Material part: J^T diag(Hm, Hb) J, J = d(alpha, beta)/dg, where
 //   d alpha/d a_1 = (a1, 0, a2), d alpha/d a_2 = (0, a2, a1),
 //   d beta_k/d a_A = c_k Z-vectors below, d beta_k/d v_k = c_k a3, c = (1,1,2).
@@ -179,21 +181,22 @@ template <class T> struct Blk {
 // The pseudo Hessian drops the bending geometric blocks.  Every value is
 // multiplied by wq sc[A] sc[B] (sc = slot scales).
 template <class T>
-__device__ __forceinline__ void hess_blocks(const GaussPoint<T>& G, int quarter, int pseudo, const T* sc, T* W) {
+__device__ __forceinline__ void hess_blocks(const GaussPoint<T>& G, int part, int pseudo, const T* sc, T* W) {
     const T ck[3] = {T(1), T(1), T(2)};
     const T is = T(1) / G.s;
     const T mt[3] = {G.mom[0], G.mom[1], T(2) * G.mom[2]};
-    if (quarter == 3) {
-        Blk<T> b;
+    Blk<T> b;
+    if (part <= 1) {
+        // (v_k, v_l): part 0 the row k = 0, part 1 the rows k = 1, 2
 #pragma unroll
         for (int k = 0; k < 3; ++k)
 #pragma unroll
             for (int l = k; l < 3; ++l) {
+                if ((k == 0) != (part == 0)) continue;
                 b.zero();
                 b.outer(G.Hb[k][l] * ck[k] * ck[l], G.a3, G.a3);
                 b.store(W, 2 + k, 2 + l, G.wq * sc[2 + k] * sc[2 + l]);
             }
-        return;
     }
     // Z_k[A] and Y_k[A] = sum_l Hb[k][l] Z_l[A], A = 0 (a1), 1 (a2)
     v3<T> Z[2][3], Y[2][3];
@@ -212,8 +215,7 @@ __device__ __forceinline__ void hess_blocks(const GaussPoint<T>& G, int quarter,
     const T Bv = dot(V, G.a3);
     const v3<T> P = V - Bv * G.a3;
     const T is2 = is * is;
-    Blk<T> b;
-    if (quarter == 0) {
+    if (part == 0) {
         // (a1, a1)
         b.zero();
         b.outer(G.Hm[0][0], G.a1, G.a1);
@@ -232,6 +234,7 @@ __device__ __forceinline__ void hess_blocks(const GaussPoint<T>& G, int quarter,
             b.outer(Bv * is2, G.t1, G.t1);
         }
         b.store(W, 0, 0, G.wq * sc[0] * sc[0]);
+    } else if (part == 1) {
         // (a2, a2)
         b.zero();
         b.outer(G.Hm[1][1], G.a2, G.a2);
@@ -250,7 +253,7 @@ __device__ __forceinline__ void hess_blocks(const GaussPoint<T>& G, int quarter,
             b.outer(Bv * is2, G.t2, G.t2);
         }
         b.store(W, 1, 1, G.wq * sc[1] * sc[1]);
-    } else if (quarter == 1) {
+    } else if (part == 2) {
         // (a1, a2)
         b.zero();
         b.outer(G.Hm[0][1], G.a1, G.a2);
