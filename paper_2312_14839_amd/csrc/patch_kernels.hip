@@ -306,16 +306,29 @@ __global__ __launch_bounds__(64 * NWV) void k_hessian(const int* __restrict__ pa
         s_par[wv][5] = sp.rho_h * mass_scale * (1.0 + sp.damp * dt_damp);
     }
     __syncthreads();
-    // phase 1a: kinematics, 30 values per Gauss point split over 4 lanes
+    // phase 1a: kinematics on the matrix cores.  For slot a, the 16 Gauss
+    // points' values out[g][c] = sum_I Phi_g[a][I] X[I][c] with X[I] = (the
+    // reference coordinates' 3 components | the displacement's 3), a 16 x 16
+    // x 16 product in four k-steps of 4 basis functions; lanes of columns
+    // c < 6 keep theirs (30 values per Gauss point: s_kin[g][15 src + 3 a + comp]).
     if (active) {
-        const int g = lane >> 2, sub = lane & 3;
-        const double* ph = phi + g * 96;
-        for (int vi = sub; vi < 30; vi += 4) {
-            const int src = vi / 15, a = (vi % 15) / 3, comp = vi % 3;
-            const T* x = src ? s_u[wv] : s_b[wv];
-            T acc = T(0);
-            for (int I = 0; I < 16; ++I) acc += (T)ph[a * 16 + I] * x[3 * I + comp];
-            s_kin[wv][g][vi] = acc * (T)slot_scale(a, sp.dxi1, sp.dxi2);
+        const int gc = lane & 15, kq = lane >> 4;
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            typename MM::acc_t kacc{T(0), T(0), T(0), T(0)};
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+                const int I = 4 * st + kq;
+                const T av = (T)phi[(gc * 6 + a) * 16 + I];   // A[row g = gc][k = I]
+                const T bv = gc < 3 ? s_b[wv][3 * I + gc] : gc < 6 ? s_u[wv][3 * I + gc - 3] : T(0);   // B[k = I][c = gc]
+                kacc = MM::mma(av, bv, kacc);
+            }
+            const T sc = (T)slot_scale(a, sp.dxi1, sp.dxi2);
+            if (gc < 6) {
+                const int vi = gc < 3 ? 3 * a + gc : 15 + 3 * a + gc - 3;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) s_kin[wv][MM::row(lane, v)][vi] = kacc[v] * sc;
+            }
         }
     }
     __syncthreads();
