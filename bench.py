@@ -30,9 +30,11 @@ METRIC = ("patch E/grad/Hess evals/s + Newton-step ms at 1e-5 rel err, plain FP6
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
-# matrix-core flops per patch of the Hessian contraction (3 diagonal component
-# pairs with 96-long reductions incl. the mass slot, 3 off-diagonal with 80)
-HESS_MFMA_FLOPS = 2 * 16 * 16 * (3 * 96 + 3 * 80)
+# algorithmic matrix-core flops per patch of the Hessian kernel: the
+# contraction (3 diagonal component pairs with 96-long reductions incl. the
+# mass slot, 3 off-diagonal with 80) and the kinematics (16 Gauss points x 30
+# values x 16 basis functions)
+HESS_MFMA_FLOPS = 2 * 16 * 16 * (3 * 96 + 3 * 80) + 2 * 16 * 30 * 16
 
 
 def make_case(name):
@@ -260,6 +262,7 @@ def kernels_section(case, stream, reps=20):
     out = {}
     for name, prec, s, peak in (("fp64", S.SHELL_FP64, 8, FP64_PEAK_TFLOPS), ("fp32", S.SHELL_MIXED, 4, FP32_PEAK_TFLOPS)):
         ctx = S.context_for(shells_of(case), precision=prec, stream=stream)
+        tiles = ctx.autotune(20)
         rows = ctx.total_nodes
         stored = (ctx.nnzb + rows) // 2
         q = torch.from_numpy(case.q0.reshape(-1).copy()).cuda()
@@ -292,6 +295,9 @@ def kernels_section(case, stream, reps=20):
                          "frac_mfma": fl_asm / t_asm / 1e12 / peak, "bytes": b_asm,
                          "GB_s": b_asm / t_asm / 1e9},
             "assembly_plus_spmv_frac_hbm": (b_spmv + b_asm) / (t_spmv + t_asm) / 1e9 / HBM_PEAK_GBS,
+            "tiles": {"hess_patches_per_block": tiles["hess_waves"], "energy_patches_per_block": tiles["energy_patches"],
+                      "hess_us": tiles["hess_us"], "hess_us_default_tiles": tiles["hess_us_default"],
+                      "energy_us": tiles["energy_us"], "energy_us_default_tiles": tiles["energy_us_default"]},
         }
         print(f"[bench] {name}: SpMV {t_spmv * 1e6:.1f} us ({b_spmv / t_spmv / 1e9:.0f} GB/s), assembly "
               f"{t_asm * 1e3:.3f} ms ({fl_asm / t_asm / 1e12:.1f} TFLOP/s MFMA, {b_asm / t_asm / 1e9:.0f} GB/s)",
