@@ -220,14 +220,19 @@ __global__ void __launch_bounds__(256) k_pressure(int npatch, const int4* __rest
     for (int c = 0; c < 3; ++c) out[c] = f[c];
 }
 
-// Per-shell sums of the three patch energies, fixed summation order.
-__global__ void k_shell_energy(int nshell, const ShellParams* __restrict__ shells, const double* __restrict__ e_patch,
-                               double* __restrict__ e_shell) {
+// Per-shell sums of the three patch energies, fixed summation order: one
+// block of 1024 threads per shell, each thread its strided patches in order
+// (eight loads in flight), then a fixed tree.
+__global__ __launch_bounds__(1024) void k_shell_energy(int nshell, const ShellParams* __restrict__ shells,
+                                                       const double* __restrict__ e_patch,
+                                                       double* __restrict__ e_shell) {
     const int s = blockIdx.x;
     if (s >= nshell) return;
-    __shared__ double red[3][256];
+    __shared__ double red[3][1024];
     double a0 = 0, a1 = 0, a2 = 0;
-    for (int p = shells[s].patch_begin + threadIdx.x; p < shells[s].patch_end; p += blockDim.x) {
+    const int p1 = shells[s].patch_end;
+#pragma unroll 8
+    for (int p = shells[s].patch_begin + threadIdx.x; p < p1; p += 1024) {
         a0 += e_patch[3 * (size_t)p];
         a1 += e_patch[3 * (size_t)p + 1];
         a2 += e_patch[3 * (size_t)p + 2];
@@ -524,7 +529,7 @@ void launch_pressure(hipStream_t st, int npatch, const int4* patch_nodes, const 
 
 void launch_shell_energy(hipStream_t st, int nshell, const ShellParams* shells, const double* e_patch,
                          double* e_shell) {
-    hipLaunchKernelGGL(k_shell_energy, dim3(nshell), dim3(256), 0, st, nshell, shells, e_patch, e_shell);
+    hipLaunchKernelGGL(k_shell_energy, dim3(nshell), dim3(1024), 0, st, nshell, shells, e_patch, e_shell);
 }
 
 template <class T>

@@ -975,13 +975,19 @@ __global__ __launch_bounds__(256) void k_shell_dot_part(const int* __restrict__ 
     if (threadIdx.x == 0) part[blk] = s[0];
 }
 
-__global__ void k_shell_dot_fin(int nshell, const int* __restrict__ shell_blk0, const int* __restrict__ shell_nblk,
-                                const double* __restrict__ part, double* __restrict__ out) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+// One wavefront per shell: lane l sums the shell's block partials l, l + 64,
+// ... in order, then a fixed butterfly over the lanes.
+__global__ __launch_bounds__(64) void k_shell_dot_fin(int nshell, const int* __restrict__ shell_blk0,
+                                                      const int* __restrict__ shell_nblk,
+                                                      const double* __restrict__ part, double* __restrict__ out) {
+    const int s = blockIdx.x;
     if (s >= nshell) return;
+    const int b0 = shell_blk0[s], nb = shell_nblk[s];
     double v = 0.0;
-    for (int i = 0; i < shell_nblk[s]; ++i) v += part[shell_blk0[s] + i];
-    out[s] = v;
+    for (int i = threadIdx.x; i < nb; i += 64) v += part[b0 + i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (threadIdx.x == 0) out[s] = v;
 }
 
 // ------------------------------------------------------------ elementwise
@@ -1197,7 +1203,7 @@ void launch_shell_dot(hipStream_t st, const RowBlocks& rb, int nshell, const dou
                       const uint16_t* freemask, double* partial, double* out) {
     hipLaunchKernelGGL(k_shell_dot_part, dim3(rb.nblk), dim3(256), 0, st, rb.blk_row0, rb.blk_row1, x, y, freemask,
                        partial);
-    hipLaunchKernelGGL(k_shell_dot_fin, grid1(nshell), dim3(256), 0, st, nshell, rb.shell_blk0, rb.shell_nblk,
+    hipLaunchKernelGGL(k_shell_dot_fin, dim3(nshell), dim3(64), 0, st, nshell, rb.shell_blk0, rb.shell_nblk,
                        partial, out);
 }
 
