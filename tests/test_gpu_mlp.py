@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 from oracle import mlp_oracle as M
+from oracle import oracle as O
 from paper_2312_14839_amd import workloads as W
 
 torch = pytest.importorskip("torch")
@@ -217,3 +218,111 @@ def test_trained_warm_start_gate_on_unseen_sheets():
         a, b = L.run(sc, 12), L.run(sc, 12, theta=theta)
         disp = np.abs(a["q"] - sc.q0).max()
         assert np.abs(b["q"] - a["q"]).max() <= 1e-6 * disp
+
+
+def _host_features(case, q_s, b, dprev):
+    """The 60 warm-start features of every node, written out from their
+    definition: u = q_s - qbar, b, Dprev and the 3x3 grid stencil of b and
+    Dprev, each over its per-kind RMS on free DOFs."""
+    free = ~case.fixed.astype(bool)                       # [nodes, 12]
+    kind = np.arange(12) // 3
+
+    def rms(x):
+        out = np.ones(4)
+        for k in range(4):
+            m = free[:, kind == k]
+            if m.any():
+                v = x[:, kind == k][m]
+                r = np.sqrt(np.mean(v * v))
+                out[k] = r if r > 0 else 1.0
+        return out[kind]                                  # per DOF w
+
+    u = q_s - case.ref
+    su, sb, sd = rms(u), rms(b), rms(dprev)
+    cols = case.cols
+
+    def stencil(x):
+        out = np.zeros_like(x)
+        for j in range(case.n2 + 1):
+            for i in range(cols):
+                acc = np.zeros(12)
+                for dj in (-1, 0, 1):
+                    for di in (-1, 0, 1):
+                        if di == 0 and dj == 0:
+                            continue
+                        ii, jj = i + di, j + dj
+                        if case.periodic1:
+                            ii %= cols
+                        inside = 0 <= ii < cols and 0 <= jj <= case.n2
+                        nb = jj * cols + ii if inside else j * cols + i
+                        acc += (4.0 if di == 0 or dj == 0 else 1.0) * x[nb]
+                out[j * cols + i] = acc / 20.0 - x[j * cols + i]
+        return out
+
+    f = np.concatenate([u / su, b / sb, dprev / sd, stencil(b) / sb, stencil(dprev) / sd], axis=1)
+    return f, sd
+
+
+@pytest.mark.parametrize("which", ["twist_sheet", "periodic_cylinder"])
+def test_recorded_features_and_targets_match_their_definition(which):
+    """Samples recorded at step 2 (the first step with a previous
+    correction) against the features computed on the host from the step's
+    start state: the predicted state, b = -grad E there (the oracle's
+    gradient of the incremental potential) and the first step's correction;
+    each sample's node is found by its first 36 features (and, among the
+    nodes of a clamped ring that share them, by the rest).  The stencil
+    features cover open edges and corners (sheet) and the periodic seam
+    (cylinder)."""
+    from gpu_util import oracle_matrix
+    sh = S()
+    case = W.case_twist(8) if which == "twist_sheet" else W.case_cylinder(8, 6)
+    ctx = sh.context_for([case], newton_rtol=1e-12, pcg_rtol=1e-12)
+    K = 3 * case.nodes
+    feat = torch.zeros((K, M.N_IN), dtype=torch.float32, device="cuda")
+    tgt = torch.zeros((K, 12), dtype=torch.float32, device="cuda")
+    ctx.mlp_record(feat, tgt, K, K, seed=5)
+    dt = case.dt
+    fixed = case.fixed.astype(bool)
+    q, v = case.q0.copy(), case.v0.copy()
+    qs_list, out = [], []
+    for k in range(2):
+        presc = case.presc((k + 1) * dt) if case.presc is not None else case.q0
+        q_s = np.where(fixed, presc, q + dt * v)
+        qd, vd = torch.from_numpy(q.reshape(-1).copy()).cuda(), torch.from_numpy(v.reshape(-1).copy()).cuda()
+        q1, v1 = torch.empty_like(qd), torch.empty_like(qd)
+        rc, st = ctx.newton_step(dt, qd, vd, torch.from_numpy(presc.reshape(-1).copy()).cuda(), q1, v1)
+        assert rc == sh.SHELL_OK
+        qs_list.append((q_s, q.copy(), v.copy()))
+        q, v = q1.cpu().numpy().reshape(-1, 12), v1.cpu().numpy().reshape(-1, 12)
+        out.append(q.copy())
+    n = ctx.mlp_recorded()
+    ctx.close()
+    assert n == K
+    # the step-2 start: q_s, b = -grad E(q_s) (free DOFs), Dprev = q_1 - q_s1
+    q_s1 = qs_list[0][0]
+    q_s2, qn2, vn2 = qs_list[1]
+    dprev = np.where(fixed, 0.0, out[0] - q_s1)
+    s = O.shell_from_case(case)
+    Mm = oracle_matrix(case, case.ref, "mass")
+    qhat = qn2 + dt * vn2
+    g = (Mm @ (q_s2 - qhat).reshape(-1) / dt ** 2).reshape(-1, 12) + O.gradient(s, q_s2, case.ref) \
+        - O.gravity(s, case.ref)
+    b = np.where(fixed, 0.0, -g)
+    f_host, sd = _host_features(case, q_s2, b, dprev)
+    d2 = np.where(fixed, 0.0, out[1] - q_s2)
+    t_host = (d2 - dprev) / sd
+    fr = feat.cpu().numpy().astype(np.float64)
+    tr = tgt.cpu().numpy().astype(np.float64)
+    seen = set()
+    for r in range(n):
+        # the node: first 36 features (the node's own values; nodes of a
+        # clamped ring share them), then the stencil features among those
+        own = np.abs(f_host[:, :36] - fr[r, :36]).max(axis=1)
+        cand = np.flatnonzero(own <= own.min() + 1e-4 * max(1.0, np.abs(fr[r, :36]).max()))
+        node = int(cand[np.argmin(np.abs(f_host[cand] - fr[r]).max(axis=1))])
+        seen.add(node)
+        err = np.abs(fr[r] - f_host[node]).max()
+        assert err <= 2e-4 * max(1.0, np.abs(f_host[node]).max()), (r, node, err)
+        terr = np.abs(tr[r] - t_host[node]).max()
+        assert terr <= 1e-3 * max(1.0, np.abs(t_host[node]).max()), (r, node, terr)
+    assert len(seen) >= 0.6 * case.nodes
