@@ -305,6 +305,58 @@ def kernels_section(case, stream, reps=20):
     return out
 
 
+def cg_phases_section(case, stream, first=10):
+    """Where a CG iteration's time goes, from the CG's own phase trace (the
+    GPU's 100 MHz constant clock, stamped by each block's first thread): one
+    solve on K(q0) + M/dt^2 with the autotuned layout, iterations
+    `first`..63, means over blocks and iterations in microseconds.  update:
+    the own rows' vector and preconditioner phase; neighbour_wait: waiting for
+    the blocks whose rows the transposed products reach; product: the block's
+    share of the symmetric product; arrival_tail: from the first thread's end
+    of the product to the block's arrival at the reduce-barrier (its other
+    wavefronts finishing); barrier_wait: from arrival to the barrier's exit;
+    arrival_spread: per iteration, latest minus earliest arrival over the
+    blocks."""
+    import torch
+    from paper_2312_14839_amd import shell as S
+    out = {}
+    for name, prec in (("fp64", S.SHELL_FP64), ("mixed", S.SHELL_MIXED)):
+        ctx = S.context_for(shells_of(case), precision=prec, stream=stream)
+        ctx.autotune(20)
+        ctx.cg_trace_enable(True)
+        q = torch.from_numpy(case.q0.reshape(-1).copy()).cuda()
+        ctx.assemble(q, mass_scale=1.0 / case.dt ** 2)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(5)
+        b = torch.randn(q.shape, dtype=q.dtype, device="cuda", generator=g)
+        x = torch.zeros_like(b)
+        ctx.pcg_solve(b, x, rtol=1e-10)
+        tr = ctx.cg_trace_get().astype(np.int64)
+        ctx.close()
+        reached = int(np.count_nonzero(tr[0, :, 0]))
+        r = tr[:, first:reached, :] * 1e-2   # us
+        if r.shape[1] == 0:
+            continue
+        solo = bool(np.all(r[:, :, 4] == 0))
+        arr = r[:, :, 3] if solo else r[:, :, 4]
+        out[name] = {
+            "blocks": int(tr.shape[0]), "iterations": [first, reached],
+            "update_us": float((r[:, :, 1] - r[:, :, 0]).mean()),
+            "neighbour_wait_us": float((r[:, :, 2] - r[:, :, 1]).mean()),
+            "product_us": float((r[:, :, 3] - r[:, :, 2]).mean()),
+            "arrival_tail_us": float((arr - r[:, :, 3]).mean()),
+            "barrier_wait_us": float((r[:, :, 5] - arr).mean()),
+            "arrival_spread_us": float((arr.max(axis=0) - arr.min(axis=0)).mean()),
+            "iteration_us": float((r[:, 1:, 0] - r[:, :-1, 0]).mean()) if r.shape[1] > 1 else None,
+        }
+        o = out[name]
+        print(f"[bench] CG phases {name}: update {o['update_us']:.2f}, neighbour wait {o['neighbour_wait_us']:.2f}, "
+              f"product {o['product_us']:.2f}, arrival tail {o['arrival_tail_us']:.2f}, barrier "
+              f"{o['barrier_wait_us']:.2f}, iteration {o['iteration_us']:.2f} us ({o['blocks']} blocks)",
+              file=sys.stderr, flush=True)
+    return out
+
+
 def pseudo_hessian_section(stream, steps=3, warmup=1):
     """Exact vs pseudo Hessian (the bending geometric term dropped) on the
     256x256 cylinder, FP64: Newton and CG iterations and time per step."""
@@ -1003,6 +1055,7 @@ def main():
         print(f"[bench] mixed: {1e3 * wallm / args.steps:.2f} ms/step, err {err:.2e}", file=sys.stderr, flush=True)
     if not args.no_kernels:
         out["kernels"] = kernels_section(case, stream)
+        out["cg_phases"] = cg_phases_section(case, stream)
     if args.workload == "cylinder" and not args.no_post_buckling:
         out["post_buckling"] = post_buckling_section(stream)
     if args.workload == "cylinder" and not args.no_pseudo:

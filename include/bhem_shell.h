@@ -295,6 +295,22 @@ shell_status shell_timing_enable(shell_ctx *c, int32_t enable);
 /* Copy the counters accumulated since the last shell_timing_enable. */
 shell_status shell_timing_get(const shell_ctx *c, shell_timing *out);
 
+/* Phase trace of the persistent CG (enable != 0: on).  While on, every CG
+ * launch records, for each of its blocks (a block owns contiguous node rows
+ * of one shell) and each of its first 64 iterations, six timestamps of the
+ * GPU's constant 100 MHz clock taken by the block's first thread: the
+ * iteration's start, the end of the update phase (own rows: vectors and
+ * preconditioner), the end of the wait for the neighbouring blocks, the end
+ * of its own share of the product phase, its arrival at the iteration's
+ * reduce-barrier (every wavefront of the block done and its partial sums
+ * published; 0 for a shell held by one block, which needs no grid barrier)
+ * and the barrier's exit.  Results are unchanged by tracing. */
+shell_status shell_cg_trace_enable(shell_ctx *c, int32_t enable);
+/* The last CG launch's trace: *nblocks blocks x *iters iterations x 6
+ * timestamps into ts_host (host, [nblocks][iters][6], may be NULL to query
+ * the sizes; zeros where an iteration was not reached or tracing is off). */
+shell_status shell_cg_trace_get(shell_ctx *c, int32_t *nblocks, int32_t *iters, uint64_t *ts_host);
+
 /* Autotuner of the batched form's launch shapes.  CG layout: the persistent
  * CG kernel covers each shell's node rows with contiguous row blocks; the
  * tunable layout is the threads per block (256, 512 or 1024) and the rows

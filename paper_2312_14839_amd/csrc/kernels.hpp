@@ -253,7 +253,13 @@ hipError_t launch_cg(hipStream_t st, int nblk, int nthreads, const RowBlocks& rb
                      const TV* dinv, const uint16_t* freemask, const double* b, TV* x, TV* r, TV* u, TV* p, TV* s,
                      TV* w, TV* slot, double* partial /* [2][nblk][4] */, void* sync, unsigned* nbflag,
                      int* abort_flag, const double* rtol2_shell, const int* maxit_shell, const int* active_shell,
-                     CgShellOut* out);
+                     CgShellOut* out, unsigned long long* trace /* NULL, or [nblk][CG_TRACE_ITERS][6] */);
+// Phase timestamps of the CG (shell_cg_trace_*): per block and iteration,
+// the constant 100 MHz clock at the iteration's start, the end of the update
+// phase, the end of the neighbour wait, the end of thread 0's product
+// phase, the block's arrival at the reduce-barrier (all its wavefronts done,
+// partials published) and the barrier's exit.
+constexpr int CG_TRACE_ITERS = 64;
 int cg_max_blocks(int device, int tm_fp32, int nthreads);   // co-resident blocks of the CG kernel
 size_t cg_sync_bytes();                                     // per-shell synchronisation state of the CG kernel
 int cg_rows_per_pass(int tm_fp32, int nthreads);            // node rows one CG block covers per pass

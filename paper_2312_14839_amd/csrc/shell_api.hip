@@ -83,6 +83,7 @@ struct shell_ctx {
     DevBuf mlp_theta, mlp_w, mlp_m, mlp_v, mlp_grad, mlp_loss, mlp_idx, mlp_work, feat_part, feat_scale, cnt_kind,
         dstep, qstart, b0, guess, rec_base;
     DevBuf nbr8;   // [N][8] grid neighbours of each node (the node itself where there is none)
+    DevBuf cg_trace;   // [nblk][CG_TRACE_ITERS][6] phase timestamps of the last CG launch, when tracing
     std::vector<char> h_hist;   // per shell: dstep holds the last step's correction
     int mlp_work_batch = 0;
     long long mlp_loss_n = 0;
@@ -101,6 +102,7 @@ struct shell_ctx {
     };
     bool graphs = true;
     bool cg_resident = true;   // register-resident CG vectors where the layout allows
+    bool cg_tracing = false;   // the CG records its phase timestamps (shell_cg_trace_enable)
     int hs_waves = 4;          // patches (wavefronts) per block of the Hessian kernel
     int eg_patches = 16;       // patches per block of the energy and gradient kernel
     hipStream_t cap_stream = nullptr;
@@ -380,6 +382,7 @@ bool set_row_blocks(shell_ctx* c, int nt, int spread) {
     alloc(c->red_part, (size_t)c->nblk * sizeof(double));
     alloc(c->cg_partial, (size_t)c->nblk * 8 * sizeof(double));   // [2][nblk][4]: by barrier parity
     alloc(c->feat_part, (size_t)c->nblk * 12 * sizeof(double));
+    if (c->cg_tracing) alloc(c->cg_trace, (size_t)c->nblk * CG_TRACE_ITERS * 6 * sizeof(unsigned long long));
     sync(c);
     c->graphs_reset();
     return true;
@@ -789,6 +792,12 @@ void bj_factor(shell_ctx* c) {
 // per-shell results in cg_out (and h_cg_out after sync when to_host).
 void cg_enqueue(shell_ctx* c, const double* b, bool to_host) {
     hipStream_t st = c->stream;
+    unsigned long long* trace = nullptr;
+    const size_t trace_bytes = (size_t)c->nblk * CG_TRACE_ITERS * 6 * sizeof(unsigned long long);
+    if (c->cg_tracing && c->cg_trace.n >= trace_bytes) {   // sized by shell_cg_trace_enable / set_row_blocks
+        trace = dptr<unsigned long long>(c->cg_trace);
+        launch_zero(st, c->cg_trace.p, trace_bytes);
+    }
     launch_zero(st, c->cg_bar.p, c->cg_bar.n);
     launch_zero(st, c->cg_nbflag.p, c->cg_nbflag.n);
     launch_zero(st, c->cg_abort.p, c->cg_abort.n);
@@ -802,7 +811,7 @@ void cg_enqueue(shell_ctx* c, const double* b, bool to_host) {
                                     dptr<float>(c->slot), dptr<double>(c->cg_partial), c->cg_bar.p,
                                     dptr<unsigned>(c->cg_nbflag), dptr<int>(c->cg_abort),
                                     dptr<double>(c->cg_rtol2), dptr<int>(c->cg_maxit), dptr<int>(c->cg_active),
-                                    dptr<CgShellOut>(c->cg_out));
+                                    dptr<CgShellOut>(c->cg_out), trace);
     else
         e = launch_cg<double, double>(st, c->nblk, c->cg_threads, c->rb(), c->sym(), dptr<double>(c->vals),
                                       dptr<double>(c->dinv), dptr<uint16_t>(c->freemask), b,
@@ -811,7 +820,7 @@ void cg_enqueue(shell_ctx* c, const double* b, bool to_host) {
                                       dptr<double>(c->slot), dptr<double>(c->cg_partial), c->cg_bar.p,
                                       dptr<unsigned>(c->cg_nbflag), dptr<int>(c->cg_abort),
                                       dptr<double>(c->cg_rtol2), dptr<int>(c->cg_maxit), dptr<int>(c->cg_active),
-                                      dptr<CgShellOut>(c->cg_out));
+                                      dptr<CgShellOut>(c->cg_out), trace);
     HIPCHK(e);
     tmr.stop();
     if (to_host)
@@ -2880,6 +2889,37 @@ shell_status shell_timing_get(const shell_ctx* c, shell_timing* out) {
     if (!c || !out) return SHELL_E_INVAL;
     *out = c->tm;
     return SHELL_OK;
+}
+
+shell_status shell_cg_trace_enable(shell_ctx* c, int32_t enable) {
+    if (!c) return SHELL_E_INVAL;
+    API_TRY
+    HIPCHK(hipSetDevice(c->opts.device));
+    sync(c);
+    c->cg_tracing = enable != 0;
+    if (c->cg_tracing) alloc(c->cg_trace, (size_t)c->nblk * CG_TRACE_ITERS * 6 * sizeof(unsigned long long));
+    c->graphs_reset();   // the captured CG launches hold the trace pointer
+    return SHELL_OK;
+    API_CATCH
+}
+
+shell_status shell_cg_trace_get(shell_ctx* c, int32_t* nblocks, int32_t* iters, uint64_t* ts_host) {
+    if (!c) return SHELL_E_INVAL;
+    API_TRY
+    HIPCHK(hipSetDevice(c->opts.device));
+    sync(c);
+    const size_t n = (size_t)c->nblk * CG_TRACE_ITERS * 6;
+    if (nblocks) *nblocks = c->nblk;
+    if (iters) *iters = CG_TRACE_ITERS;
+    if (ts_host) {
+        if (!c->cg_tracing || c->cg_trace.n < n * sizeof(unsigned long long)) {
+            std::memset(ts_host, 0, n * sizeof(uint64_t));
+        } else {
+            HIPCHK(hipMemcpy(ts_host, c->cg_trace.p, n * sizeof(uint64_t), hipMemcpyDeviceToHost));
+        }
+    }
+    return SHELL_OK;
+    API_CATCH
 }
 
 // ------------------------------------------------------- warm-start network

@@ -484,7 +484,8 @@ struct alignas(128) ShellSync {
 // waits are one matrix-product phase).
 template <int N, int NW>
 __device__ __forceinline__ bool reduce_barrier(ShellSync* ss, double* __restrict__ part, int blk, int sb0, int snb,
-                                               unsigned k, double (&v)[N], int* abort_flag, double* lds) {
+                                               unsigned k, double (&v)[N], int* abort_flag, double* lds,
+                                               unsigned long long* arrive = nullptr) {
     __shared__ int s_ok;
     __shared__ double s_tot[N];
     block_sum<N, NW>(v, lds);
@@ -506,6 +507,7 @@ __device__ __forceinline__ bool reduce_barrier(ShellSync* ss, double* __restrict
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
             __hip_atomic_fetch_add(&ss->cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+        if (arrive) *arrive = __builtin_amdgcn_s_memrealtime();
         // poll with plain coherent loads
         int ok = 1;
         unsigned spins = 0;
@@ -642,7 +644,7 @@ __global__ __launch_bounds__(NT) void k_cg(
     TV* __restrict__ s, TV* __restrict__ w, TV* __restrict__ slot, double* __restrict__ partial,
     ShellSync* __restrict__ sync, unsigned* __restrict__ nbflag, int* __restrict__ abort_flag,
     const double* __restrict__ rtol2_shell, const int* __restrict__ maxit_shell, const int* __restrict__ active_shell,
-    CgShellOut* __restrict__ out) {
+    CgShellOut* __restrict__ out, unsigned long long* __restrict__ trace) {
     constexpr int R = Lay<TM>::R, L = Lay<TM>::L, G = Lay<TM>::G;
     constexpr int NW = NT / 64;
     constexpr int NP = MAXP > 0 ? MAXP : 1;   // register-resident passes
@@ -860,6 +862,10 @@ __global__ __launch_bounds__(NT) void k_cg(
         alpha = gamma / sums[1];
         for (; it < maxit; ++it) {
             const bool rev = (it & 1) != 0;   // both phases of odd iterations run last to first
+            // trace record of this block and iteration (first CG_TRACE_ITERS iterations, thread 0)
+            unsigned long long* tr =
+                trace && threadIdx.x == 0 && it < CG_TRACE_ITERS ? trace + ((size_t)blk * CG_TRACE_ITERS + it) * 6 : nullptr;
+            if (tr) tr[0] = __builtin_amdgcn_s_memrealtime();
             // ---- phase 1
             double s1[3] = {0.0, 0.0, 0.0};
             passes([&](int base) {
@@ -919,16 +925,21 @@ __global__ __launch_bounds__(NT) void k_cg(
                     }
                 }
             }, rev);
+            if (tr) tr[1] = __builtin_amdgcn_s_memrealtime();
             if (!neighbour_sync(nbflag, blk, nbhi, ++nnb, abort_flag, snb == 1)) {
                 status = 3;
                 break;
             }
+            if (tr) tr[2] = __builtin_amdgcn_s_memrealtime();
             // ---- phase 2
             s1[1] = product(rev);
-            if (!reduce_barrier<3, NW>(ss, partial, blk, sb0, snb, nbar++, s1, abort_flag, lds)) {
+            if (tr) tr[3] = __builtin_amdgcn_s_memrealtime();
+            if (tr) tr[4] = 0;
+            if (!reduce_barrier<3, NW>(ss, partial, blk, sb0, snb, nbar++, s1, abort_flag, lds, tr ? tr + 4 : nullptr)) {
                 status = 3;
                 break;
             }
+            if (tr) tr[5] = __builtin_amdgcn_s_memrealtime();
             rr2 = s1[2];
             if (rr2 <= tol2) {
                 status = 0;
@@ -1162,14 +1173,15 @@ template <class TM, class TV>
 hipError_t launch_cg(hipStream_t st, int nblk, int nthreads, const RowBlocks& rb, const SymBsr& m, const TM* vals,
                      const TV* dinv, const uint16_t* freemask, const double* b, TV* x, TV* r, TV* u, TV* p, TV* s,
                      TV* w, TV* slot, double* partial, void* sync, unsigned* nbflag, int* abort_flag,
-                     const double* rtol2_shell, const int* maxit_shell, const int* active_shell, CgShellOut* out) {
+                     const double* rtol2_shell, const int* maxit_shell, const int* active_shell, CgShellOut* out,
+                     unsigned long long* trace) {
     ShellSync* ss = static_cast<ShellSync*>(sync);
     SymBsr mm = m;
     void* args[] = {(void*)&rb.blk_shell, (void*)&rb.blk_row0, (void*)&rb.blk_row1, (void*)&rb.shell_blk0,
                     (void*)&rb.shell_nblk, (void*)&rb.blk_nbhi, (void*)&mm, (void*)&vals, (void*)&dinv,
                     (void*)&freemask, (void*)&b, (void*)&x, (void*)&r, (void*)&u, (void*)&p, (void*)&s, (void*)&w,
                     (void*)&slot, (void*)&partial, (void*)&ss, (void*)&nbflag, (void*)&abort_flag,
-                    (void*)&rtol2_shell, (void*)&maxit_shell, (void*)&active_shell, (void*)&out};
+                    (void*)&rtol2_shell, (void*)&maxit_shell, (void*)&active_shell, (void*)&out, (void*)&trace};
     const int pass = (nthreads / 64) * Lay<TM>::G;
     const bool resident = rb.max_rows <= cg_maxp<TM>(nthreads) * pass;
     return hipLaunchCooperativeKernel(cg_fn<TM, TV>(nthreads, resident), dim3(nblk), dim3(nthreads), args, 0, st);
@@ -1177,11 +1189,12 @@ hipError_t launch_cg(hipStream_t st, int nblk, int nthreads, const RowBlocks& rb
 template hipError_t launch_cg<double, double>(hipStream_t, int, int, const RowBlocks&, const SymBsr&, const double*,
                                               const double*, const uint16_t*, const double*, double*, double*,
                                               double*, double*, double*, double*, double*, double*, void*, unsigned*,
-                                              int*, const double*, const int*, const int*, CgShellOut*);
+                                              int*, const double*, const int*, const int*, CgShellOut*,
+                                              unsigned long long*);
 template hipError_t launch_cg<float, float>(hipStream_t, int, int, const RowBlocks&, const SymBsr&, const float*,
                                             const float*, const uint16_t*, const double*, float*, float*, float*,
                                             float*, float*, float*, float*, double*, void*, unsigned*, int*,
-                                            const double*, const int*, const int*, CgShellOut*);
+                                            const double*, const int*, const int*, CgShellOut*, unsigned long long*);
 
 size_t cg_sync_bytes() { return sizeof(ShellSync); }
 int cg_rows_per_pass(int tm_fp32, int nthreads) { return (nthreads / 64) * (tm_fp32 ? Lay<float>::G : Lay<double>::G); }
