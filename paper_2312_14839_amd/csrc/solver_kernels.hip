@@ -851,6 +851,9 @@ __global__ __launch_bounds__(NT) void k_cg(
     const double tol2 = rtol2_shell[sh] * bb;
     const int maxit = maxit_shell[sh];
     if (bb == 0.0) {
+        // x = 0 solves it (the resident instance would otherwise leave x
+        // unwritten: it stores its LDS copy only after the iterations)
+        for (int e = threadIdx.x; e < (row1 - row0) * 12; e += blockDim.x) x[(size_t)row0 * 12 + e] = TV(0);
         if (leader) out[sh] = CgShellOut{0, 0, 0.0, 0.0};
         return;
     }

@@ -155,6 +155,32 @@ def test_spmv(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_pcg_zero_rhs_shell_gives_zero(precision):
+    """A shell whose right-hand side is zero gets x = 0 exactly, also after a
+    solve that left other values in the solver's buffers, while the other
+    shell of the context is solved (regression: the register-resident CG
+    instance returned early without writing x)."""
+    cases = [W.case_small_sheet(), W.sheet_case(4, seed=2)]
+    sh = S()
+    ctx = sh.context_for(cases, precision=sh.SHELL_MIXED if precision == "mixed" else sh.SHELL_FP64)
+    q = np.concatenate([_state(c).reshape(-1) for c in cases])
+    ctx.assemble(dev(q), mass_scale=1.0 / cases[0].dt ** 2)
+    free = ~np.concatenate([c.fixed.reshape(-1) for c in cases]).astype(bool)
+    b = np.random.default_rng(8).normal(size=free.size) * free
+    n0 = cases[0].nodes * 12
+    x = torch.zeros_like(dev(b))
+    ctx.pcg_solve(dev(b), x, rtol=1e-10)
+    assert np.all(host(x)[n0:][free[n0:]] != 0)
+    b[n0:] = 0.0
+    x.fill_(float("nan"))
+    rc, its, rel = ctx.pcg_solve(dev(b), x, rtol=1e-10)
+    xs = host(x)
+    assert np.all(xs[n0:] == 0.0)
+    assert np.all(np.isfinite(xs[:n0])) and its[0] > 0
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_pcg_solve(precision):
     case = W.case_small_sheet()
     q = _state(case)
