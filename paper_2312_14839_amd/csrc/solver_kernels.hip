@@ -230,6 +230,10 @@ __device__ __forceinline__ TV row_sym(const SymBsr& m, const TM* __restrict__ va
                                       TV (&part)[12]) {
     constexpr int R = Lay<TM>::R;
     const int b0 = m.row_ptr[node], b1 = m.row_ptr[node + 1];
+    // column of the next off-diagonal block, loaded one block ahead so that
+    // x of each block's column is requested as the block starts (an index in
+    // bounds is loaded also past the row's last block; the value is unused)
+    int col = m.col_idx[b0 + 1 < b1 ? b0 + 1 : b0];
 #pragma unroll
     for (int k = 0; k < R; ++k) xl[R * t + k] = xo[k];
     wave_lds_sync();
@@ -240,7 +244,8 @@ __device__ __forceinline__ TV row_sym(const SymBsr& m, const TM* __restrict__ va
     TV* pst = nullptr;
     for (int b = b0 + 1; b < b1; ++b) {
         TV xv[R], tv[R];
-        xe(m.col_idx[b], xv);
+        xe(col, xv);
+        col = m.col_idx[b + 1 < b1 ? b + 1 : b];
         const int ts = m.tslot[b];
 #pragma unroll
         for (int k = 0; k < R; ++k) tv[k] = TV(0);
