@@ -465,12 +465,14 @@ template <int N, int NW> __device__ __forceinline__ void block_sum(double (&v)[N
 }
 
 // Synchronisation state of one shell during a CG launch (zeroed before it).
-// Arrivals go through CG_GROUPS group counters on separate 128-byte lines
-// and then one top counter, so no single address takes more than about
-// nblk/CG_GROUPS (or CG_GROUPS) atomic operations per barrier.
+// Arrivals of a shell of more than CG_GROUPS blocks go through CG_GROUPS
+// group counters on separate 128-byte lines and then one top counter, so no
+// single address takes more than about nblk/CG_GROUPS (or CG_GROUPS) atomic
+// operations per barrier; the blocks of a smaller shell arrive at the top
+// counter itself (a group of one block would only add an atomic).
 constexpr int CG_GROUPS = 4;
 struct alignas(128) ShellSync {
-    unsigned cnt;        // top-level arrivals (group leaders), monotone
+    unsigned cnt;        // top-level arrivals (group leaders, or every block of a small shell), monotone
     unsigned pad0[31];
     unsigned gcnt[CG_GROUPS][32];   // per-group arrivals, monotone, one line each
 };
@@ -503,14 +505,19 @@ __device__ __forceinline__ bool reduce_barrier(ShellSync* ss, double* __restrict
         for (int n = 0; n < N; ++n) buf[4 * (size_t)blk + n] = v[n];
         // one release fence publishes this block's vector writes and partials
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const int ng = snb < CG_GROUPS ? snb : CG_GROUPS;
-        const int lb = blk - sb0, g = lb % ng;
-        const unsigned gsize = (unsigned)((snb - g + ng - 1) / ng);
-        const unsigned og = __hip_atomic_fetch_add(&ss->gcnt[g][0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (og == gsize * (k + 1) - 1) {
-            // last of its group: carry the group's arrival to the top counter
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        const int ng = snb <= CG_GROUPS ? snb : CG_GROUPS;
+        if (snb <= CG_GROUPS) {
             __hip_atomic_fetch_add(&ss->cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const int lb = blk - sb0, g = lb % ng;
+            const unsigned gsize = (unsigned)((snb - g + ng - 1) / ng);
+            const unsigned og =
+                __hip_atomic_fetch_add(&ss->gcnt[g][0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (og == gsize * (k + 1) - 1) {
+                // last of its group: carry the group's arrival to the top counter
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+                __hip_atomic_fetch_add(&ss->cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
         if (arrive) *arrive = __builtin_amdgcn_s_memrealtime();
         // poll with plain coherent loads
