@@ -305,6 +305,34 @@ def kernels_section(case, stream, reps=20):
     return out
 
 
+def hbm_achievable(gib=2, reps=10):
+    """What the chip streams for plain kernels (torch's sum and copy over
+    `gib` GiB of FP64): the achievable reference beside the 8 TB/s peak."""
+    import torch
+    n = gib * (1 << 30) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    out = {}
+    for name, fn, nbytes in (("read", lambda: x.sum(), 8 * n), ("copy", lambda: y.copy_(x), 16 * n)):
+        for _ in range(2):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / reps * 1e-3
+        out[name + "_GB_s"] = nbytes / t / 1e9
+    out["bytes_read"] = 8 * n
+    del x, y
+    torch.cuda.empty_cache()
+    print(f"[bench] achievable: read {out['read_GB_s']:.0f} GB/s, copy {out['copy_GB_s']:.0f} GB/s (read + write)",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def cg_phases_section(case, stream, first=10):
     """Where a CG iteration's time goes, from the CG's own phase trace (the
     GPU's 100 MHz constant clock, stamped by each block's first thread): one
@@ -1056,6 +1084,7 @@ def main():
     if not args.no_kernels:
         out["kernels"] = kernels_section(case, stream)
         out["cg_phases"] = cg_phases_section(case, stream)
+        out["hbm_achievable"] = hbm_achievable()
     if args.workload == "cylinder" and not args.no_post_buckling:
         out["post_buckling"] = post_buckling_section(stream)
     if args.workload == "cylinder" and not args.no_pseudo:
