@@ -336,6 +336,8 @@ __global__ void k_spmv_fin(int nnodes, const int* __restrict__ lptr, const doubl
 // ---------------------------------------------------- block-Jacobi factor
 // Inverse of each node's 12x12 diagonal block (prescribed rows/columns
 // replaced by identity) by an FP64 Cholesky factorisation; 16 lanes per node.
+// The 16 lanes of a node lie in one wavefront, so the factorisation's
+// steps are ordered by wavefront-level LDS synchronisation only.
 // The inverse is symmetric, so a node keeps its 21 distinct 2x2 blocks
 // (84 values instead of 144, layout at SYM12_VALS).  A 2x2 diagonal block
 // takes both off-diagonal entries from column 2a + 1, so the stored matrix
@@ -361,7 +363,7 @@ __global__ __launch_bounds__(256) void k_bj_factor(int nnodes, const int* __rest
             A[sub][ln][c] = v;
         }
     }
-    __syncthreads();
+    wave_lds_sync();
     // right-looking Cholesky: A = L L^T, L stored in the lower triangle
     for (int j = 0; j < 12; ++j) {
         if (act && ln == j) {
@@ -372,12 +374,12 @@ __global__ __launch_bounds__(256) void k_bj_factor(int nnodes, const int* __rest
             }
             A[sub][j][j] = sqrt(d);
         }
-        __syncthreads();
+        wave_lds_sync();
         if (act && ln > j && ln < 12) A[sub][ln][j] /= A[sub][j][j];
-        __syncthreads();
+        wave_lds_sync();
         if (act && ln > j && ln < 12)
             for (int k = j + 1; k <= ln; ++k) A[sub][ln][k] -= A[sub][ln][j] * A[sub][k][j];
-        __syncthreads();
+        wave_lds_sync();
     }
     if (act && ln < 12) {
         // column ln of the inverse: L y = e_ln, L^T x = y
