@@ -335,9 +335,12 @@ __global__ void k_spmv_fin(int nnodes, const int* __restrict__ lptr, const doubl
 
 // ---------------------------------------------------- block-Jacobi factor
 // Inverse of each node's 12x12 diagonal block (prescribed rows/columns
-// replaced by identity) by an FP64 Cholesky factorisation; 16 lanes per node.
-// The 16 lanes of a node lie in one wavefront, so the factorisation's
-// steps are ordered by wavefront-level LDS synchronisation only.
+// replaced by identity) by Gauss-Jordan elimination in FP64 without
+// pivoting (the block is symmetric positive definite; the pivot of step k is
+// the Schur complement's diagonal entry, the square of a Cholesky factor's,
+// and one <= 0 marks the block as not positive definite).  16 lanes per
+// node, lane c holding column c in registers; each step takes column k from
+// lane k by shuffles, so no LDS and no barrier is involved.
 // The inverse is symmetric, so a node keeps its 21 distinct 2x2 blocks
 // (84 values instead of 144, layout at SYM12_VALS).  A 2x2 diagonal block
 // takes both off-diagonal entries from column 2a + 1, so the stored matrix
@@ -347,74 +350,69 @@ __global__ __launch_bounds__(256) void k_bj_factor(int nnodes, const int* __rest
                                                    const void* __restrict__ vals, int vals_fp32,
                                                    const uint16_t* __restrict__ fm, const int* __restrict__ node_shell,
                                                    TV* __restrict__ dinv, int* __restrict__ fail_shell) {
-    __shared__ double A[16][12][13];
-    __shared__ int bad[16];
     const int ln = threadIdx.x & 15, sub = threadIdx.x >> 4;
     const int node = blockIdx.x * 16 + sub;
     const bool act = node < nnodes;
-    if (ln == 0) bad[sub] = 0;
-    if (act && ln < 12) {
+    const int c = ln < 12 ? ln : 0;   // lanes 12..15 carry a copy of column 0, never stored
+    double a[12];
+    if (act) {
         const size_t base = (size_t)diag_blk[node] * 144;
-        for (int c = 0; c < 12; ++c) {
-            const size_t at = base + sym12_pos(ln, c);
+        const bool fc = is_free(fm, node, c);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            const size_t at = base + sym12_pos(i, c);
             double v = vals_fp32 ? (double)((const float*)vals)[at] : ((const double*)vals)[at];
-            const bool fr = is_free(fm, node, ln), fc = is_free(fm, node, c);
-            if (!fr || !fc) v = (ln == c && !fr) ? 1.0 : 0.0;
-            A[sub][ln][c] = v;
+            const bool fr = is_free(fm, node, i);
+            if (!fr || !fc) v = (i == c && !fr) ? 1.0 : 0.0;
+            a[i] = v;
         }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 12; ++i) a[i] = i == c ? 1.0 : 0.0;
     }
-    wave_lds_sync();
-    // right-looking Cholesky: A = L L^T, L stored in the lower triangle
-    for (int j = 0; j < 12; ++j) {
-        if (act && ln == j) {
-            double d = A[sub][j][j];
-            if (!(d > 0.0)) {
-                bad[sub] = 1;
-                d = 1.0;
-            }
-            A[sub][j][j] = sqrt(d);
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        // column k of the current matrix, from lane k of the node's lanes
+        double ck[12];
+#pragma unroll
+        for (int i = 0; i < 12; ++i) ck[i] = __shfl(a[i], k, 16);
+        double piv = ck[k];
+        if (!(piv > 0.0)) {
+            bad = true;
+            piv = 1.0;
         }
-        wave_lds_sync();
-        if (act && ln > j && ln < 12) A[sub][ln][j] /= A[sub][j][j];
-        wave_lds_sync();
-        if (act && ln > j && ln < 12)
-            for (int k = j + 1; k <= ln; ++k) A[sub][ln][k] -= A[sub][ln][j] * A[sub][k][j];
-        wave_lds_sync();
+        // row k of this column after scaling; column k becomes that of the
+        // inverse of the eliminated part
+        const double rk = (c == k ? 1.0 : a[k]) / piv;
+#pragma unroll
+        for (int i = 0; i < 12; ++i)
+            if (i != k) a[i] = (c == k ? 0.0 : a[i]) - ck[i] * rk;
+        a[k] = rk;
     }
     if (act && ln < 12) {
-        // column ln of the inverse: L y = e_ln, L^T x = y
-        double y[12];
-        for (int i = 0; i < 12; ++i) {
-            double v = (i == ln) ? 1.0 : 0.0;
-            for (int k = 0; k < i; ++k) v -= A[sub][i][k] * y[k];
-            y[i] = v / A[sub][i][i];
-        }
-        for (int i = 11; i >= 0; --i) {
-            double v = y[i];
-            for (int k = i + 1; k < 12; ++k) v -= A[sub][k][i] * y[k];
-            y[i] = v / A[sub][i][i];
-        }
         // column ln = 2b + j goes into the stored blocks (a, b) of column
         // pair b: a = b - k (mod 6) at 12 a + 4 k, and a = b - 3 at 72 + 4 a
         const int bc = ln >> 1, j = ln & 1;
         TV* dn = dinv + (size_t)node * SYM12_VALS;
+#pragma unroll
         for (int k = 1; k < 3; ++k) {
-            const int a = (bc + 6 - k) % 6;
-            dn[12 * a + 4 * k + j] = (TV)y[2 * a];
-            dn[12 * a + 4 * k + 2 + j] = (TV)y[2 * a + 1];
+            const int r = (bc + 6 - k) % 6;
+            dn[12 * r + 4 * k + j] = (TV)a[2 * r];
+            dn[12 * r + 4 * k + 2 + j] = (TV)a[2 * r + 1];
         }
         if (bc >= 3) {
-            const int a = bc - 3;
-            dn[72 + 4 * a + j] = (TV)y[2 * a];
-            dn[72 + 4 * a + 2 + j] = (TV)y[2 * a + 1];
+            const int r = bc - 3;
+            dn[72 + 4 * r + j] = (TV)a[2 * r];
+            dn[72 + 4 * r + 2 + j] = (TV)a[2 * r + 1];
         }
         if (j == 0) {
-            dn[12 * bc] = (TV)y[2 * bc];
+            dn[12 * bc] = (TV)a[2 * bc];
         } else {
-            dn[12 * bc + 1] = dn[12 * bc + 2] = (TV)y[2 * bc];
-            dn[12 * bc + 3] = (TV)y[2 * bc + 1];
+            dn[12 * bc + 1] = dn[12 * bc + 2] = (TV)a[2 * bc];
+            dn[12 * bc + 3] = (TV)a[2 * bc + 1];
         }
-        if (ln == 0 && bad[sub]) atomicOr(&fail_shell[node_shell[node]], 1);
+        if (ln == 0 && bad) atomicOr(&fail_shell[node_shell[node]], 1);
     }
 }
 
