@@ -8,6 +8,9 @@
 namespace bhem {
 
 // ------------------------------------------------------- patch kernels
+// phi: the basis table Phi_g[a][I] at 96 g + 16 a + I (16 Gauss points x 6
+// slots x 16 local basis functions); launch_energy_grad and launch_hessian
+// also read its transpose, which follows it at 1536 + 16 (16 a + I) + g
 void launch_energy_grad(hipStream_t st, int npatch, const int4* patch_nodes, const int* patch_shell,
                         const ShellParams* shells, const double* phi, const double* q, const double* qbar,
                         const double* qhat, double mass_scale, double dt_damp, int elastic, int loads,

@@ -80,7 +80,9 @@ __global__ __launch_bounds__(16 * EGP) void k_energy_grad(int npatch, const int4
     if (active) {
         const int g = lane;
         double kin[30], xd[3] = {0, 0, 0};
-        const double* ph = phi + g * 96;
+        // the transposed table: the 16 lanes of a patch read 16 consecutive
+        // values (one cache line) per load
+        const double* ph = phi + 16 * 96 + g;
 #pragma unroll
         for (int a = 0; a < 5; ++a) {
             const double sc = slot_scale(a, sp.dxi1, sp.dxi2);
@@ -88,7 +90,7 @@ __global__ __launch_bounds__(16 * EGP) void k_energy_grad(int npatch, const int4
             for (int comp = 0; comp < 3; ++comp) {
                 double sb = 0.0, su = 0.0;
                 for (int I = 0; I < 16; ++I) {
-                    const double f = ph[a * 16 + I];
+                    const double f = ph[(a * 16 + I) * 16];
                     sb += f * s_b[pl][3 * I + comp];
                     su += f * s_u[pl][3 * I + comp];
                 }
@@ -99,7 +101,7 @@ __global__ __launch_bounds__(16 * EGP) void k_energy_grad(int npatch, const int4
 #pragma unroll
         for (int comp = 0; comp < 3; ++comp) {
             double s = 0.0;
-            for (int I = 0; I < 16; ++I) s += ph[5 * 16 + I] * s_d[pl][3 * I + comp];
+            for (int I = 0; I < 16; ++I) s += ph[(5 * 16 + I) * 16] * s_d[pl][3 * I + comp];
             xd[comp] = s;
         }
         GaussPoint<double> G;
@@ -324,7 +326,8 @@ __global__ __launch_bounds__(64 * NWV) void k_hessian(const int* __restrict__ pa
 #pragma unroll
             for (int st = 0; st < 4; ++st) {
                 const int I = 4 * st + kq;
-                const T av = (T)phi[(gc * 6 + a) * 16 + I];   // A[row g = gc][k = I]
+                // A[row g = gc][k = I], from the transposed table
+                const T av = (T)phi[16 * 96 + (a * 16 + I) * 16 + gc];
                 const T bv = gc < 3 ? s_b[wv][3 * I + gc] : gc < 6 ? s_u[wv][3 * I + gc - 3] : T(0);   // B[k = I][c = gc]
                 kacc = MM::mma(av, bv, kacc);
             }

@@ -613,9 +613,13 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
     if (!set_row_blocks(c, nt0, 1) && !set_row_blocks(c, 256, 1))
         throw InvalErr{"too many shells for one context (limit " +
                        std::to_string(cg_max_blocks(c->opts.device, c->fp32, 256)) + ")"};
-    // theta-space basis table
-    std::vector<double> phi(16 * 6 * 16);
+    // theta-space basis table Phi_g[a][I] at 96 g + 16 a + I, followed by
+    // its transpose at 1536 + 16 (16 a + I) + g (read where consecutive
+    // lanes take consecutive Gauss points)
+    std::vector<double> phi(2 * 16 * 6 * 16);
     build_theta_basis(phi.data());
+    for (int g = 0; g < 16; ++g)
+        for (int e = 0; e < 96; ++e) phi[1536 + 16 * e + g] = phi[96 * g + e];
     // uploads
     upload(c->shells_d, c->shells, st);
     upload(c->phi, phi, st);
