@@ -920,9 +920,8 @@ SolveResult solve(shell_ctx* c, const double* b, double* x_out, const std::vecto
             R.sweeps[s] = 1;
         }
         h2d(c, c->flag_shell.p, active_in.data(), S * sizeof(int));
-        HIPCHK(hipMemsetAsync(x64, 0, (size_t)c->N * 12 * sizeof(double), st));
-        launch_add_to<double>(st, c->N * 12, dptr<double>(c->cg_x), x64);
-        launch_copy_shell(st, c->N, x64, dptr<int>(c->node_shell), dptr<int>(c->flag_shell), x_out);
+        launch_copy_shell(st, c->N, dptr<double>(c->cg_x), dptr<int>(c->node_shell), dptr<int>(c->flag_shell),
+                          x_out);
         HIPCHK(hipGetLastError());
         return R;
     }
@@ -1026,13 +1025,13 @@ void newton_iteration_device(shell_ctx* c, double ms, double* q, double* g, doub
     launch_nt_factor(st, S, ctl, dptr<int>(c->fail_shell), cg_active, dptr<double>(c->cg_rtol2),
                      dptr<int>(c->cg_maxit), c->opts.pcg_rtol, c->opts.pcg_maxit);
     launch_neg_masked(st, N, g, fm, ns, cg_active, rhs);
-    launch_zero(st, c->x64.p, c->x64.n);
     if (!c->fp32) {
+        // the FP64 CG's x is the direction itself
         cg_enqueue(c, rhs, false);
-        launch_add_to<double>(st, N * 12, dptr<double>(c->cg_x), x64);
         launch_nt_cg64(st, S, ctl, dptr<CgShellOut>(c->cg_out), flag);
     } else {
         double* r64 = dptr<double>(c->r64);
+        launch_zero(st, c->x64.p, c->x64.n);
         HIPCHK(hipMemcpyAsync(r64, rhs, (size_t)N * 12 * sizeof(double), hipMemcpyDeviceToDevice, st));
         shell_dot(c, rhs, rhs, true, false);
         launch_nt_ref_init(st, S, ctl, red, cg_active, dptr<double>(c->cg_rtol2), c->opts.pcg_rtol);
@@ -1047,7 +1046,7 @@ void newton_iteration_device(shell_ctx* c, double ms, double* q, double* g, doub
         }
         launch_nt_ref_end(st, S, ctl, flag);
     }
-    launch_copy_shell(st, N, x64, ns, flag, d);
+    launch_copy_shell(st, N, c->fp32 ? x64 : dptr<double>(c->cg_x), ns, flag, d);
     // line search along d (-g where d is not a descent direction)
     shell_dot(c, g, d, true, false);
     launch_nt_ls_init(st, S, ctl, red, alpha, flag, wr);
