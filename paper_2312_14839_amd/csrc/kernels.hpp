@@ -291,11 +291,16 @@ void launch_neg_masked(hipStream_t st, int nnodes, const double* g, const uint16
 void launch_velocity(hipStream_t st, int n, const double* q1, const double* qn, double dt, double* v);
 void launch_copy_shell(hipStream_t st, int nnodes, const double* src, const int* node_shell, const int* flag_shell,
                        double* dst);
+// both copies of launch_copy_shell in one launch
+void launch_copy_shell2(hipStream_t st, int nnodes, const double* src0, const double* src1, const int* node_shell,
+                        const int* flag_shell, double* dst0, double* dst1);
 template <class TV>
 void launch_add_to(hipStream_t st, int n, const TV* dx, double* x);
 void launch_cast_to_float(hipStream_t st, int n, const double* x, float* y);
 // zero `bytes` (a multiple of 4, 16-byte aligned start) with a kernel
 void launch_zero(hipStream_t st, void* p, size_t bytes);
+// three buffers in one launch (each 16-byte aligned, sizes multiples of 4 bytes)
+void launch_zero3(hipStream_t st, void* p0, size_t b0, void* p1, size_t b1, void* p2, size_t b2);
 void launch_add_shell(hipStream_t st, int nnodes, const double* src, const int* node_shell, const int* flag_shell,
                       double* dst);
 

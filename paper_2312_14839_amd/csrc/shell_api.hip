@@ -802,9 +802,7 @@ void cg_enqueue(shell_ctx* c, const double* b, bool to_host) {
         trace = dptr<unsigned long long>(c->cg_trace);
         launch_zero(st, c->cg_trace.p, trace_bytes);
     }
-    launch_zero(st, c->cg_bar.p, c->cg_bar.n);
-    launch_zero(st, c->cg_nbflag.p, c->cg_nbflag.n);
-    launch_zero(st, c->cg_abort.p, c->cg_abort.n);
+    launch_zero3(st, c->cg_bar.p, c->cg_bar.n, c->cg_nbflag.p, c->cg_nbflag.n, c->cg_abort.p, c->cg_abort.n);
     GroupTimer tmr(c, SHELL_T_CG);
     hipError_t e;
     if (c->fp32)
@@ -1057,8 +1055,7 @@ void newton_iteration_device(shell_ctx* c, double ms, double* q, double* g, doub
         eval_energy_grad(c, qt, qhat, ms, 1, true, gt, wr, wr, false);
         shell_dot(c, gt, gt, true, false);
         launch_nt_ls_step(st, S, t, ctl, dptr<double>(c->e_shell), red, alpha, flag, wr);
-        launch_copy_shell(st, N, qt, ns, flag, q);
-        launch_copy_shell(st, N, gt, ns, flag, g);
+        launch_copy_shell2(st, N, qt, gt, ns, flag, q, g);
     }
     launch_nt_ls_end(st, S, ctl);
     // the next iteration's convergence test

@@ -1089,6 +1089,17 @@ __global__ void k_copy_shell(int n, const double* __restrict__ src, const int* _
     if (t < n && flag_shell[node_shell[t / 12]]) dst[t] = src[t];
 }
 
+// two vectors at once: dst0 = src0 and dst1 = src1 on the flagged shells
+__global__ void k_copy_shell2(int n, const double* __restrict__ src0, const double* __restrict__ src1,
+                              const int* __restrict__ node_shell, const int* __restrict__ flag_shell,
+                              double* __restrict__ dst0, double* __restrict__ dst1) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n && flag_shell[node_shell[t / 12]]) {
+        dst0[t] = src0[t];
+        dst1[t] = src1[t];
+    }
+}
+
 __global__ void k_add_shell(int n, const double* __restrict__ src, const int* __restrict__ node_shell,
                             const int* __restrict__ flag_shell, double* __restrict__ dst) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1108,6 +1119,20 @@ __global__ void k_zero(size_t n16, uint4* __restrict__ p, size_t n4_tail, uint32
     if (t < n4_tail) tail[t] = 0u;
 }
 
+// Up to three buffers zeroed by one launch (blockIdx.y picks the buffer).
+struct ZeroSpan {
+    uint4* p;
+    size_t n16;
+    uint32_t* tail;
+    size_t n4;
+};
+__global__ void k_zero_spans(ZeroSpan a, ZeroSpan b, ZeroSpan c) {
+    const ZeroSpan z = blockIdx.y == 0 ? a : blockIdx.y == 1 ? b : c;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = t; i < z.n16; i += stride) z.p[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (t < z.n4) z.tail[t] = 0u;
+}
+
 // ------------------------------------------------------------ launchers
 static inline dim3 grid1(int n) { return dim3((n + 255) / 256); }
 
@@ -1116,6 +1141,16 @@ void launch_zero(hipStream_t st, void* p, size_t bytes) {
     const size_t blocks = std::min<size_t>(std::max<size_t>((n16 + 255) / 256, 1), 4096);
     hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st, n16, (uint4*)p, n4,
                        (uint32_t*)((char*)p + n16 * 16));
+}
+
+void launch_zero3(hipStream_t st, void* p0, size_t b0, void* p1, size_t b1, void* p2, size_t b2) {
+    auto span = [](void* p, size_t bytes) {
+        return ZeroSpan{(uint4*)p, bytes / 16, (uint32_t*)((char*)p + bytes / 16 * 16), (bytes % 16) / 4};
+    };
+    const size_t n16 = std::max(b0, std::max(b1, b2)) / 16;
+    const size_t blocks = std::min<size_t>(std::max<size_t>((n16 + 255) / 256, 1), 4096);
+    hipLaunchKernelGGL(k_zero_spans, dim3((unsigned)blocks, 3), dim3(256), 0, st, span(p0, b0), span(p1, b1),
+                       span(p2, b2));
 }
 
 template <class TM>
@@ -1266,6 +1301,11 @@ void launch_copy_shell(hipStream_t st, int nnodes, const double* src, const int*
                        double* dst) {
     const int n = nnodes * 12;
     hipLaunchKernelGGL(k_copy_shell, grid1(n), dim3(256), 0, st, n, src, node_shell, flag_shell, dst);
+}
+void launch_copy_shell2(hipStream_t st, int nnodes, const double* src0, const double* src1, const int* node_shell,
+                        const int* flag_shell, double* dst0, double* dst1) {
+    const int n = nnodes * 12;
+    hipLaunchKernelGGL(k_copy_shell2, grid1(n), dim3(256), 0, st, n, src0, src1, node_shell, flag_shell, dst0, dst1);
 }
 void launch_add_shell(hipStream_t st, int nnodes, const double* src, const int* node_shell, const int* flag_shell,
                       double* dst) {
