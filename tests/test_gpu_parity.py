@@ -154,6 +154,33 @@ def test_spmv(precision):
         assert torch.equal(yb[1:], y)
 
 
+@pytest.mark.parametrize("n", [3, 5, 9, 10, 12])
+def test_pcg_solve_across_block_counts(n):
+    """The CG's reduce-barrier arrives at one counter for shells of up to
+    four blocks and through group counters beyond: sheets of n x n patches
+    span 1 to 5 CG blocks; every solve reaches the tolerance on the stored
+    matrix."""
+    case = W.sheet_case(n, seed=n)
+    q = _state(case)
+    sh = S()
+    ctx = sh.context_for([case], precision=sh.SHELL_FP64)
+    ctx.cg_trace_enable(True)
+    ctx.assemble(dev(q), mass_scale=1.0 / case.dt ** 2)
+    free = ~case.fixed.reshape(-1).astype(bool)
+    b = np.random.default_rng(n).normal(size=free.size) * free
+    x = torch.zeros_like(dev(b))
+    rc, its, rel = ctx.pcg_solve(dev(b), x, rtol=1e-10)
+    nblk = ctx.cg_trace_get().shape[0]
+    A = bsr_from_gpu(*ctx.get_bsr(0)).toarray()
+    ctx.close()
+    xs = host(x)
+    r = b[free] - A[np.ix_(free, free)] @ xs[free]
+    rr = np.linalg.norm(r) / np.linalg.norm(b)
+    print(f"sheet {n}x{n}: {nblk} CG blocks, {its[0]} iterations, rel. residual {rr:.2e}", flush=True)
+    assert its[0] > 0
+    assert rr <= 2e-10
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_pcg_zero_rhs_shell_gives_zero(precision):
     """A shell whose right-hand side is zero gets x = 0 exactly, also after a
