@@ -344,6 +344,19 @@ shell_status shell_autotune(shell_ctx *c, int32_t cg_iters, shell_tune_result *o
  * patches of one colour share no matrix block).  SHELL_E_INVAL otherwise. */
 shell_status shell_set_patch_tiles(shell_ctx *c, int32_t hess_waves, int32_t energy_patches);
 
+/* Form of the Hessian assembly (Appendix B.2 scattered into the stored
+ * triangle).  single_launch = 0: one launch per patch colour, each adding
+ * its patches' blocks into the matrix (patches of one colour share no
+ * block).  single_launch = 1: one launch over all patches writing their
+ * stored local blocks to a scratch array of the context, then one that
+ * sums each stored block's contributions in colour order -- the same
+ * additions in the same order, so the same matrix bit for bit, with two
+ * launches instead of one per colour.  It needs every patch's Hessian
+ * block resident on the device at once (shells of up to a few thousand
+ * patches); contexts that allow it start with it.  SHELL_E_INVAL where
+ * single_launch = 1 is not allowed. */
+shell_status shell_set_assembly(shell_ctx *c, int32_t single_launch);
+
 /* ------------------------------------------------------------------
  * Learned warm start of the Newton iteration.  This is an extension: the
  * paper has no learned component.  Its conclusions note that positions and

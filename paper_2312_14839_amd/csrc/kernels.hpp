@@ -33,7 +33,15 @@ void launch_hessian(hipStream_t st, const int* patch_list, int nlist, const int4
                     const int* patch_slots, const uint64_t* patch_kid, const uint16_t* patch_first,
                     const ShellParams* shells, const double* phi, const double* q, const double* qbar,
                     double mass_scale, double dt_damp, int elastic, int pseudo, T* vals,
-                    int waves /* patches (wavefronts) per block: 4 or 8 */);
+                    int waves /* patches (wavefronts) per block: 4 or 8 */,
+                    T* scr /* NULL: add into vals; else each stored local block to scr[(10 p + m) 144] */);
+// patches whose Hessian blocks (4 patches each) are all resident on the device at once
+int hessian_resident_patches(int device, int fp32);
+// vals[sb] = sum over k in cptr[sb] .. cptr[sb + 1] of scr[cidx[k]] (144 values,
+// 84 where diag[sb]): the assembly of launch_hessian's scratch output
+template <class T>
+void launch_gather_blocks(hipStream_t st, int nsb, const int* cptr, const int* cidx, const uint8_t* diag, const T* scr,
+                          T* vals);
 
 // --------------------------------------------------------- ray kernels
 // ctrl: [P][4][4][3] Bezier control points, p_ij at ((4p + i)*4 + j)*3.

@@ -274,7 +274,8 @@ __global__ __launch_bounds__(64 * NWV) void k_hessian(const int* __restrict__ pa
                                                  const ShellParams* __restrict__ shells,
                                                  const double* __restrict__ phi, const double* __restrict__ q,
                                                  const double* __restrict__ qbar, double mass_scale,
-                                                 double dt_damp, int elastic, int pseudo, T* __restrict__ vals) {
+                                                 double dt_damp, int elastic, int pseudo, T* __restrict__ vals,
+                                                 T* __restrict__ scr) {
     typedef Mfma<T> MM;
     constexpr int WSZ = 16 * 121;   // packed W per Gauss point (+ mass term) and pair staging (6*256)
     static_assert(WSZ >= 6 * 256, "staging must fit");
@@ -427,6 +428,9 @@ __global__ __launch_bounds__(64 * NWV) void k_hessian(const int* __restrict__ pa
     // is done once; the block's nodes and slot are the same for the whole
     // wavefront.  Four blocks per round keep 12 reads per lane in flight.
     if (active) {
+        // the scaled block value is rounded before it is added (no fused
+        // multiply-add), as the single-launch form's sum in colour order does
+#pragma clang fp contract(off)
         const int* slots = patch_slots + 16 * (size_t)patch;
         const uint64_t kid = patch_kid[patch];
         const unsigned first = patch_first[patch];
@@ -454,9 +458,32 @@ __global__ __launch_bounds__(64 * NWV) void k_hessian(const int* __restrict__ pa
             ks[u] = (T)(kind_scale(k, sp.dxi1, sp.dxi2) * kind_scale(l, sp.dxi1, sp.dxi2));
         }
         constexpr int MB = 4;
+        // scr: each stored local block goes to its own slot of the scratch,
+        // scr[(10 p + m) 144 + element], for k_gather_blocks to sum in colour
+        // order, instead of into the matrix
+        if (scr) {
+#pragma unroll 1
+            for (int m = 0; m < 10; ++m) {
+                const int sl = slots[m];
+                if (sl < 0) break;
+                const int blk = (int)((kid >> (4 * m)) & 15u);
+                const int c = blk >> 2, d = blk & 3;
+                const int cd = 64 * c + 4 * d, dc = 64 * d + 4 * c;
+                T* dst = scr + ((size_t)patch * 10 + m) * 144;
+                const bool dg = m < 4;
+                const int nu = dg ? 2 : 3;
+                const bool last_ok = dg ? lane < 20 : lane < 16;
+                for (int u = 0; u < nu; ++u) {
+                    const int v = dg ? u + 3 : u;
+                    if (u < nu - 1 || last_ok) dst[lane + 64 * u] = ks[v] * W[lo[v] + (sw[v] ? dc : cd)];
+                }
+            }
+            return;
+        }
         // one round: blocks m0 .. m0 + MB - 1 of the list, all diagonal (DG)
         // or all off the diagonal
         auto round = [&](int m0, auto dg_tag) {
+#pragma clang fp contract(off)
             constexpr bool DG = decltype(dg_tag)::value;
             constexpr int NU = DG ? 2 : 3;
             const bool last_ok = DG ? lane < 20 : lane < 16;   // u = NU - 1
@@ -539,24 +566,69 @@ template <class T>
 void launch_hessian(hipStream_t st, const int* patch_list, int nlist, const int4* patch_nodes, const int* patch_shell,
                     const int* patch_slots, const uint64_t* patch_kid, const uint16_t* patch_first,
                     const ShellParams* shells, const double* phi, const double* q, const double* qbar,
-                    double mass_scale, double dt_damp, int elastic, int pseudo, T* vals, int waves) {
+                    double mass_scale, double dt_damp, int elastic, int pseudo, T* vals, int waves, T* scr) {
     if (nlist == 0) return;
     const int nw = waves == 8 ? 8 : 4;
     const int nb = (nlist + nw - 1) / nw;
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(nb), dim3(64 * nw), 0, st, patch_list, nlist, patch_nodes, patch_shell,
                            patch_slots, patch_kid, patch_first, shells, phi, q, qbar, mass_scale, dt_damp, elastic,
-                           pseudo, vals);
+                           pseudo, vals, scr);
     };
     if (nw == 8) go(k_hessian<T, 8>);
     else go(k_hessian<T, 4>);
 }
 
+// One wavefront per stored block: the sum, in colour order, of the local
+// blocks in scr that the patches add to it (cptr/cidx), from 0 -- the same
+// operations as the colour launches' first store and read-modify-writes.
+// A diagonal block has its 84 packed values, the others 144.
+template <class T>
+__global__ __launch_bounds__(256) void k_gather_blocks(int nsb, const int* __restrict__ cptr,
+                                                       const int* __restrict__ cidx,
+                                                       const uint8_t* __restrict__ diag,
+                                                       const T* __restrict__ scr, T* __restrict__ vals) {
+    const int lane = threadIdx.x & 63;
+    const int sb = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (sb >= nsb) return;
+    const int k0 = cptr[sb], k1 = cptr[sb + 1];
+    const bool dg = diag[sb] != 0;
+    const int nu = dg ? 2 : 3;
+    const bool last_ok = dg ? lane < 20 : lane < 16;
+    for (int u = 0; u < nu; ++u) {
+        if (u == nu - 1 && !last_ok) break;
+        const int e = lane + 64 * u;
+        T v = T(0);
+        for (int k = k0; k < k1; ++k) v = v + scr[(size_t)cidx[k] * 144 + e];
+        vals[(size_t)sb * 144 + e] = v;
+    }
+}
+
+template <class T>
+void launch_gather_blocks(hipStream_t st, int nsb, const int* cptr, const int* cidx, const uint8_t* diag, const T* scr,
+                          T* vals) {
+    if (nsb == 0) return;
+    hipLaunchKernelGGL(k_gather_blocks<T>, dim3((nsb + 3) / 4), dim3(256), 0, st, nsb, cptr, cidx, diag, scr, vals);
+}
+int hessian_resident_patches(int device, int fp32) {
+    int per_cu = 0, cus = 0;
+    const void* fn = fp32 ? (const void*)k_hessian<float, 4> : (const void*)k_hessian<double, 4>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        return 0;
+    return 4 * per_cu * cus;
+}
+
+template void launch_gather_blocks<double>(hipStream_t, int, const int*, const int*, const uint8_t*, const double*,
+                                           double*);
+template void launch_gather_blocks<float>(hipStream_t, int, const int*, const int*, const uint8_t*, const float*,
+                                          float*);
+
 template void launch_hessian<double>(hipStream_t, const int*, int, const int4*, const int*, const int*,
                                      const uint64_t*, const uint16_t*, const ShellParams*, const double*, const double*,
-                                     const double*, double, double, int, int, double*, int);
+                                     const double*, double, double, int, int, double*, int, double*);
 template void launch_hessian<float>(hipStream_t, const int*, int, const int4*, const int*, const int*,
                                     const uint64_t*, const uint16_t*, const ShellParams*, const double*, const double*,
-                                    const double*, double, double, int, int, float*, int);
+                                    const double*, double, double, int, int, float*, int, float*);
 
 }  // namespace bhem

@@ -61,6 +61,11 @@ struct shell_ctx {
     // device data
     DevBuf patch_first;   // [P] uint16 first-touch bits of the stored local blocks
     DevBuf patch_kid;     // [P] uint64 local block index of each stored local block (4 bits each)
+    // single-launch assembly (asm_gather): the patches' stored local blocks
+    // in scratch [P][10][144], and per stored block the scratch entries to
+    // sum, in colour order, and whether it is a diagonal block
+    bool asm_gather = false, asm_eligible = false;
+    DevBuf asm_scr, asm_cptr, asm_cidx, asm_diag;
     DevBuf shells_d, phi, qbar, freemask, node_shell, patch_nodes, patch_shell, patch_slots, colour_list, inc_ptr,
         inc, row_ptr, col_idx, tslot, lptr, diag_blk, vals, slot, diag0, dinv;
     DevBuf blk_shell, blk_row0, blk_row1, shell_blk0, shell_nblk, blk_nbhi, cg_nbflag;
@@ -631,6 +636,38 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
     upload(c->patch_slots, slots, st);
     upload(c->patch_kid, kid, st);
     upload(c->colour_list, clist, st);
+    // Where every patch's Hessian block is resident at once, one launch over
+    // all patches writes the local blocks to scratch and a second sums each
+    // stored block's contributions in colour order (the same additions as
+    // the colour launches, so the same bits) instead of one launch per
+    // colour, each a full round of block latency.
+    {
+        const int cap = hessian_resident_patches(c->opts.device, c->fp32);
+        c->asm_eligible = c->asm_gather = P > 0 && cap > 0 && P <= cap;
+        if (c->asm_gather) {
+            std::vector<int> cnt((size_t)c->nnzb_u + 1, 0);
+            std::vector<uint8_t> dg((size_t)c->nnzb_u, 0);
+            for (int p : clist)
+                for (int m = 0; m < 10; ++m) {
+                    const int sl = slots[(size_t)p * 16 + m];
+                    if (sl < 0) break;
+                    cnt[sl + 1]++;
+                    if (m < 4) dg[sl] = 1;
+                }
+            for (long long k = 0; k < c->nnzb_u; ++k) cnt[k + 1] += cnt[k];
+            std::vector<int> cidx(cnt[c->nnzb_u]), fill(cnt.begin(), cnt.end() - 1);
+            for (int p : clist)
+                for (int m = 0; m < 10; ++m) {
+                    const int sl = slots[(size_t)p * 16 + m];
+                    if (sl < 0) break;
+                    cidx[fill[sl]++] = 10 * p + m;
+                }
+            upload(c->asm_cptr, cnt, st);
+            upload(c->asm_cidx, cidx, st);
+            upload(c->asm_diag, dg, st);
+            alloc(c->asm_scr, (size_t)P * 10 * 144 * (c->fp32 ? sizeof(float) : sizeof(double)));
+        }
+    }
     upload(c->patch_first, first, st);
     upload(c->inc_ptr, inc_ptr, st);
     upload(c->inc, inc_flat, st);
@@ -736,20 +773,36 @@ void assemble(shell_ctx* c, const double* q_in, double mass_scale, int elastic) 
     hipStream_t st = c->stream;
     GroupTimer tmr(c, SHELL_T_HESSIAN);
     const int pseudo = c->opts.hessian == SHELL_HESS_PSEUDO;
-    for (size_t col = 0; col + 1 < c->colour_off.size(); ++col) {
-        const int off = c->colour_off[col], n = c->colour_off[col + 1] - off;
+    // one launch over all patches into scratch, or one per colour into the matrix
+    const int nlaunch = c->asm_gather ? 1 : (int)c->colour_off.size() - 1;
+    for (int col = 0; col < nlaunch; ++col) {
+        const int off = c->asm_gather ? 0 : c->colour_off[col];
+        const int n = c->asm_gather ? c->P : c->colour_off[col + 1] - off;
         const int* list = dptr<int>(c->colour_list) + off;
+        const int* slots = dptr<int>(c->patch_slots);
+        const uint64_t* kid = dptr<uint64_t>(c->patch_kid);
+        const uint16_t* first = dptr<uint16_t>(c->patch_first);
+        const ShellParams* sh = dptr<ShellParams>(c->shells_d);
+        const double* phi = dptr<double>(c->phi);
+        const double* qbar = dptr<double>(c->qbar);
         if (c->fp32)
-            launch_hessian<float>(st, list, n, dptr<int4>(c->patch_nodes), dptr<int>(c->patch_shell),
-                                  dptr<int>(c->patch_slots), dptr<uint64_t>(c->patch_kid), dptr<uint16_t>(c->patch_first),
-                                  dptr<ShellParams>(c->shells_d), dptr<double>(c->phi), q_in,
-                                  dptr<double>(c->qbar), mass_scale, c->dt_damp, elastic, pseudo, dptr<float>(c->vals),
-                                  c->hs_waves);
+            launch_hessian<float>(st, list, n, dptr<int4>(c->patch_nodes), dptr<int>(c->patch_shell), slots, kid,
+                                  first, sh, phi, q_in, qbar, mass_scale, c->dt_damp, elastic, pseudo,
+                                  dptr<float>(c->vals), c->hs_waves,
+                                  c->asm_gather ? dptr<float>(c->asm_scr) : nullptr);
         else
-            launch_hessian<double>(st, list, n, dptr<int4>(c->patch_nodes), dptr<int>(c->patch_shell),
-                                   dptr<int>(c->patch_slots), dptr<uint64_t>(c->patch_kid), dptr<uint16_t>(c->patch_first),
-                                   dptr<ShellParams>(c->shells_d), dptr<double>(c->phi), q_in, dptr<double>(c->qbar), mass_scale, c->dt_damp, elastic, pseudo,
-                                   dptr<double>(c->vals), c->hs_waves);
+            launch_hessian<double>(st, list, n, dptr<int4>(c->patch_nodes), dptr<int>(c->patch_shell), slots, kid,
+                                   first, sh, phi, q_in, qbar, mass_scale, c->dt_damp, elastic, pseudo,
+                                   dptr<double>(c->vals), c->hs_waves,
+                                   c->asm_gather ? dptr<double>(c->asm_scr) : nullptr);
+    }
+    if (c->asm_gather) {
+        if (c->fp32)
+            launch_gather_blocks<float>(st, (int)c->nnzb_u, dptr<int>(c->asm_cptr), dptr<int>(c->asm_cidx),
+                                        dptr<uint8_t>(c->asm_diag), dptr<float>(c->asm_scr), dptr<float>(c->vals));
+        else
+            launch_gather_blocks<double>(st, (int)c->nnzb_u, dptr<int>(c->asm_cptr), dptr<int>(c->asm_cidx),
+                                         dptr<uint8_t>(c->asm_diag), dptr<double>(c->asm_scr), dptr<double>(c->vals));
     }
     HIPCHK(hipGetLastError());
     tmr.stop();
@@ -2759,6 +2812,17 @@ shell_status shell_set_patch_tiles(shell_ctx* c, int32_t hess_waves, int32_t ene
     c->hs_waves = hess_waves;
     c->eg_patches = energy_patches;
     c->graphs_reset();   // the captured sequences hold the launch shapes
+    return SHELL_OK;
+}
+
+shell_status shell_set_assembly(shell_ctx* c, int32_t single_launch) {
+    if (!c) return SHELL_E_INVAL;
+    if (single_launch && !c->asm_eligible) {
+        c->err = "the single-launch assembly needs every patch's Hessian block resident at once";
+        return SHELL_E_INVAL;
+    }
+    c->asm_gather = single_launch != 0;
+    c->graphs_reset();   // the captured assembly holds its launches
     return SHELL_OK;
 }
 

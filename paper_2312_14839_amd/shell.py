@@ -206,6 +206,8 @@ def _load():
     lib.shell_autotune.restype = C.c_int32
     lib.shell_set_patch_tiles.argtypes = [vp, C.c_int32, C.c_int32]
     lib.shell_set_patch_tiles.restype = C.c_int32
+    lib.shell_set_assembly.argtypes = [vp, C.c_int32]
+    lib.shell_set_assembly.restype = C.c_int32
     lib.shell_cg_trace_enable.argtypes = [vp, C.c_int32]
     lib.shell_cg_trace_enable.restype = C.c_int32
     lib.shell_cg_trace_get.argtypes = [vp, P(C.c_int32), P(C.c_int32), C.c_void_p]
@@ -250,7 +252,7 @@ EXPORTED = ["shell_default_opts", "shell_create", "shell_destroy", "shell_last_e
             "shell_newton_step", "shell_timing_enable", "shell_timing_get", "shell_mlp_set_params",
             "shell_mlp_get_params", "shell_mlp_forward", "shell_mlp_loss_grad", "shell_mlp_train",
             "shell_mlp_record", "shell_mlp_recorded", "shell_autotune", "shell_set_patch_tiles", "shell_set_nodal_forces",
-            "shell_cg_trace_enable", "shell_cg_trace_get",
+            "shell_cg_trace_enable", "shell_cg_trace_get", "shell_set_assembly",
             "shell_point_load", "shell_bezier", "shell_ray_default_opts", "shell_ray_cast", "shell_ray_cast_noalloc",
             "shell_ccd", "shell_collide_default_opts", "shell_collide", "shell_set_pressure", "shell_pressure_load",
             "shell_set_point_constraints", "shell_get_point_multipliers", "shell_set_point_multipliers"]
@@ -446,6 +448,9 @@ class ShellContext:
         out = np.zeros((nb.value, it.value, 6), np.uint64)
         self._check(lib.shell_cg_trace_get(self.h, C.byref(nb), C.byref(it), out.ctypes.data_as(C.c_void_p)))
         return out
+
+    def set_assembly(self, single_launch):
+        self._check(lib.shell_set_assembly(self.h, int(bool(single_launch))))
 
     def set_patch_tiles(self, hess_waves, energy_patches):
         self._check(lib.shell_set_patch_tiles(self.h, int(hess_waves), int(energy_patches)))

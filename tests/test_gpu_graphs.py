@@ -101,3 +101,56 @@ def test_patch_kernel_tiles_do_not_change_results(precision):
         else:
             assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1])
             assert np.array_equal(out[2], ref[2]), (waves, patches)
+
+
+ASM_CASES = {
+    "sheet8": lambda: [W.case_small_sheet()],
+    "twist12": lambda: [W.case_twist(12)],
+    "cyl7x3_six_colours": lambda: [W.case_cylinder(7, 3)],
+    "batch4": lambda: W.case_batch(4, nmin=4, nmax=10),
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", list(ASM_CASES))
+def test_single_launch_assembly_equals_colour_launches(name, precision):
+    """The single-launch assembly (every patch's local blocks to scratch,
+    then each stored block summed in colour order) performs the colour
+    launches' additions in their order: the matrix of every shell is
+    bit-identical, and so are two Newton steps (graphs replayed)."""
+    from paper_2312_14839_amd import shell as sh
+    cases = ASM_CASES[name]()
+    prec = sh.SHELL_MIXED if precision == "mixed" else sh.SHELL_FP64
+    q0 = np.concatenate([W.random_state(c, seed=5).reshape(-1) for c in cases])
+    out = []
+    for single in (0, 1):
+        ctx = sh.context_for(cases, precision=prec)
+        ctx.set_assembly(single)
+        q = torch.from_numpy(q0.copy()).cuda()
+        ctx.assemble(q, mass_scale=1.0 / cases[0].dt ** 2)
+        mats = [ctx.get_bsr(s)[2] for s in range(len(cases))]
+        qn = torch.from_numpy(np.concatenate([c.q0.reshape(-1) for c in cases])).cuda()
+        v = torch.zeros_like(qn)
+        q1, v1 = torch.empty_like(qn), torch.empty_like(qn)
+        for k in range(2):
+            pr = torch.from_numpy(np.concatenate([(c.presc((k + 1) * c.dt) if c.presc else c.q0).reshape(-1)
+                                                  for c in cases])).cuda()
+            ctx.newton_step(cases[0].dt, qn, v, pr, q1, v1)
+            qn, q1 = q1, qn
+            v, v1 = v1, v
+        out.append((mats, qn.cpu().numpy()))
+        ctx.close()
+    for s, (a, b) in enumerate(zip(out[0][0], out[1][0])):
+        assert np.array_equal(a, b), s
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+
+
+def test_single_launch_assembly_needs_resident_patches():
+    """A shell whose Hessian blocks do not all fit on the device at once
+    keeps the colour launches; asking for the single launch is an error."""
+    from paper_2312_14839_amd import shell as sh
+    ctx = sh.context_for([W.case_cylinder(128, 128)], precision=sh.SHELL_FP64)
+    with pytest.raises(sh.ShellError):
+        ctx.set_assembly(1)
+    ctx.set_assembly(0)
+    ctx.close()
