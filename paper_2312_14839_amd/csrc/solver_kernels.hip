@@ -139,6 +139,26 @@ __device__ __forceinline__ void group_sum(const TV (&part)[12], int lane, int t,
 // previous block's transposed product, stored after this block's first
 // loads are issued (loads and stores share one in-order completion counter,
 // so a store issued first would delay the wait for the loads behind it).
+// The block's values already in registers (a[12][R], its 12 rows of this
+// lane's columns): the same arithmetic as block_sym.
+template <class TM, class TV, bool ABS>
+__device__ __forceinline__ void block_sym_regs(const TM (&a)[12][Lay<TM>::R], const TV (&xv)[Lay<TM>::R],
+                                               const TV* __restrict__ xl, TV (&part)[12], TV (&tv)[Lay<TM>::R]) {
+    constexpr int R = Lay<TM>::R;
+#pragma unroll
+    for (int cc = 0; cc < 12; ++cc) {
+        const TV xc = xl[cc];
+        TV sacc = part[cc];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const TV av = ABS ? (TV)fabs(a[cc][k]) : (TV)a[cc][k];
+            sacc += av * xv[k];
+            tv[k] += av * xc;
+        }
+        part[cc] = sacc;
+    }
+}
+
 template <class TM, class TV, bool ABS, int NR>
 __device__ __forceinline__ void block_sym(const TM* __restrict__ blk, const TV (&xv)[Lay<TM>::R],
                                           const TV* __restrict__ xl, TV (&part)[12], TV (&tv)[Lay<TM>::R],
@@ -224,7 +244,10 @@ __device__ __forceinline__ void block_diag_sym(const TM* __restrict__ dblk, int 
 // values), copied for the group to xl[12] in LDS; xe(col, xv) gives this
 // lane's R entries of x for column block col.  ABS multiplies by |A|
 // instead of A.
-template <class TM, class TV, bool ABS, int NR, class XF>
+// PF: the next off-diagonal block's values are loaded while the current one
+// is multiplied (registers for two blocks; for blocks of few rows, whose
+// product is a chain of round trips per row)
+template <class TM, class TV, bool ABS, int NR, class XF, bool PF = false>
 __device__ __forceinline__ TV row_sym(const SymBsr& m, const TM* __restrict__ vals, int node, int t,
                                       const TV (&xo)[Lay<TM>::R], XF xe, TV* __restrict__ xl, TV* __restrict__ slot,
                                       TV (&part)[12]) {
@@ -242,6 +265,38 @@ __device__ __forceinline__ TV row_sym(const SymBsr& m, const TM* __restrict__ va
     block_diag_sym<TM, TV, ABS>(vals + (size_t)b0 * 144, t, xo, xl, part, dl);
     TV pv[R];
     TV* pst = nullptr;
+    if constexpr (PF) {
+        TM an[12][R];
+        if (b0 + 1 < b1) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) VecLoad<TM, R>::ld(vals + (size_t)(b0 + 1) * 144 + R * t + c * 12, an[c]);
+        }
+        for (int b = b0 + 1; b < b1; ++b) {
+            TM a[12][R];
+#pragma unroll
+            for (int c = 0; c < 12; ++c)
+#pragma unroll
+                for (int k = 0; k < R; ++k) a[c][k] = an[c][k];
+            TV xv[R], tv[R];
+            xe(col, xv);
+            col = m.col_idx[b + 1 < b1 ? b + 1 : b];
+            const int ts = m.tslot[b];
+            if (b + 1 < b1) {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) VecLoad<TM, R>::ld(vals + (size_t)(b + 1) * 144 + R * t + c * 12, an[c]);
+            }
+            if (pst) VecStore<TV, R>::st(pst, pv);
+#pragma unroll
+            for (int k = 0; k < R; ++k) tv[k] = TV(0);
+            block_sym_regs<TM, TV, ABS>(a, xv, xl, part, tv);
+            pst = slot + (size_t)ts * 12 + R * t;
+#pragma unroll
+            for (int k = 0; k < R; ++k) pv[k] = tv[k];
+        }
+        if (pst) VecStore<TV, R>::st(pst, pv);
+        wave_lds_sync();
+        return dl;
+    }
     for (int b = b0 + 1; b < b1; ++b) {
         TV xv[R], tv[R];
         xe(col, xv);
@@ -648,7 +703,7 @@ __device__ __forceinline__ bool neighbour_sync(unsigned* __restrict__ flags, int
 }
 
 template <class TM, class TV, int NT, int MAXP>
-__global__ __launch_bounds__(NT) void k_cg(
+__global__ __launch_bounds__(NT, MAXP == 1 ? 2 : 1) void k_cg(
     const int* __restrict__ blk_shell, const int* __restrict__ blk_row0, const int* __restrict__ blk_row1,
     const int* __restrict__ shell_blk0, const int* __restrict__ shell_nblk, const int* __restrict__ blk_nbhi, SymBsr m,
     const TM* __restrict__ vals, const TV* __restrict__ dinv, const uint16_t* __restrict__ fm,
@@ -807,8 +862,12 @@ __global__ __launch_bounds__(NT) void k_cg(
             };
             TV un[R], part[12], wr[R];
             xe(node, un);
-            const TV dl = row_sym<TM, TV, false, sizeof(TM) == 8 ? 12 : 4>(m, vals, node, t, un, xe,
-                                                                          xls[wv] + grp * 12, slot, part);
+            // FP32 blocks of one pass (small shells) load the next block's
+            // values during the current one's products (in FP64 the two
+            // blocks' registers spill and the plain order is faster)
+            constexpr bool PF = MAXP == 1 && sizeof(TM) == 4;
+            const TV dl = row_sym<TM, TV, false, sizeof(TM) == 8 || PF ? 12 : 4, decltype(xe), PF>(
+                m, vals, node, t, un, xe, xls[wv] + grp * 12, slot, part);
             group_sum<TV, R, L>(part, lane, t, gsrc, red[wv], wr);
             uau -= (double)dl;
 #pragma unroll
@@ -1234,7 +1293,11 @@ hipError_t launch_cg(hipStream_t st, int nblk, int nthreads, const RowBlocks& rb
                     (void*)&rtol2_shell, (void*)&maxit_shell, (void*)&active_shell, (void*)&out, (void*)&trace};
     const int pass = (nthreads / 64) * Lay<TM>::G;
     const bool resident = rb.max_rows <= cg_maxp<TM>(nthreads) * pass;
-    return hipLaunchCooperativeKernel(cg_fn<TM, TV>(nthreads, resident), dim3(nblk), dim3(nthreads), args, 0, st);
+    // 256-thread blocks of one pass: the instance that loads the next
+    // stored block ahead
+    const void* fn = nthreads == 256 && rb.max_rows <= pass ? (const void*)k_cg<TM, TV, 256, 1>
+                                                            : cg_fn<TM, TV>(nthreads, resident);
+    return hipLaunchCooperativeKernel(fn, dim3(nblk), dim3(nthreads), args, 0, st);
 }
 template hipError_t launch_cg<double, double>(hipStream_t, int, int, const RowBlocks&, const SymBsr&, const double*,
                                               const double*, const uint16_t*, const double*, double*, double*,
@@ -1258,6 +1321,11 @@ int cg_max_blocks(int device, int tm_fp32, int nthreads) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nthreads, 0) != hipSuccess) return -1;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, fn2, nthreads, 0) != hipSuccess) return -1;
     per_cu = per_cu < per_cu2 ? per_cu : per_cu2;
+    if (nthreads == 256) {   // and the one-pass instance
+        const void* fn1 = tm_fp32 ? (const void*)k_cg<float, float, 256, 1> : (const void*)k_cg<double, double, 256, 1>;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, fn1, nthreads, 0) != hipSuccess) return -1;
+        per_cu = per_cu < per_cu2 ? per_cu : per_cu2;
+    }
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return -1;
     return per_cu * cus;
 }
