@@ -396,7 +396,7 @@ __device__ inline void write_result(double* hit, int* patch_out, int* pops_out, 
 // its wave idle.  Each loop trip either starts a ray (root boxes of every
 // patch) or examines one candidate.  A ray still searching after
 // `tail.budget` candidates (one grazing a silhouette can need tens of
-// thousands) is handed to k_ray_tail, which works on it with a whole wave.
+// thousands) is handed to k_ray_tail, which works on it with a whole block.
 template <bool LDS>
 __global__ void __launch_bounds__(256) k_ray_cast(const double* __restrict__ ctrl, int npatch,
                                                   const double* __restrict__ rays, long long nrays, int chunk,
@@ -887,7 +887,8 @@ void launch_ccd(hipStream_t st, const double* ctrl, const double* vel, int npatc
                 long long npts, double dt, const RayParams& o, double* hit, int* patch, int* pops);
 
 // The cooperative search of one handed-over ray per block of TAIL_THREADS
-// (4 waves).  The candidates live in an LDS pool; every step sorts their
+// (8 waves; 4 took 1.7 times as long on the drape's grazing rays, 16 spill
+// registers).  The candidates live in an LDS pool; every step sorts their
 // keys (bitonic network over the pool's slots, free slots keyed +inf), takes
 // the (up to) TAIL_THREADS smallest that the ray enters before the best
 // answer, one per thread, and files their sub-rectangles into the slots thus
@@ -895,7 +896,7 @@ void launch_ccd(hipStream_t st, const double* ctrl, const double* vel, int npatc
 // the accelerated form runs until no candidate is left before the best
 // answer.  Block-wide values (best answer, counts) go through LDS.
 constexpr int TAIL_POOL = 2048;
-constexpr int TAIL_THREADS = 256;
+constexpr int TAIL_THREADS = 512;
 constexpr size_t TAIL_LDS = (size_t)TAIL_POOL * (7 * sizeof(double) + sizeof(int) + sizeof(short));
 
 template <bool MOVING>
@@ -987,7 +988,10 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_ray_tail(const double* __restr
             __syncthreads();
             const int live = s_live;
             if (live == 0) break;
-            int m = min(live, TAIL_THREADS);
+            // examined candidates free their slots and file up to 4 children
+            // each: at most (TAIL_POOL - live) / 3 of them keeps the pool from
+            // overflowing (the result does not depend on how many a step takes)
+            int m = min(min(live, TAIL_THREADS), max(1, (TAIL_POOL - live) / 3));
             // is this thread's candidate (the tid-th smallest key) an answer box
             bool ans = false;
             if (tid < m) {
