@@ -183,7 +183,8 @@ def cg_bytes(case, timing, tm_bytes, tv_bytes, resident):
 
 def profiled_traffic(case, fp32, kernel):
     """HBM bytes per launch of `kernel` (its FP64 or FP32 instance) from the
-    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of this workload, or
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of this workload (the
+    FP64 section's or the mixed section's), or
     None when there is none or the kernel source has changed since it was
     taken."""
     import hashlib
@@ -191,7 +192,8 @@ def profiled_traffic(case, fp32, kernel):
         return None
     tag = f"{kernel}_fp32" if fp32 else kernel
     here = os.path.dirname(os.path.abspath(__file__))
-    path = os.path.join(here, "profiles", "cylinder256_rocprof.txt")
+    name = "cylinder256_mixed_rocprof.txt" if fp32 else "cylinder256_rocprof.txt"
+    path = os.path.join(here, "profiles", name)
     src = os.path.join(here, "paper_2312_14839_amd", "csrc", "solver_kernels.hip")
     if not os.path.exists(path):
         return None
