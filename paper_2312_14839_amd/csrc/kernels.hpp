@@ -9,8 +9,10 @@ namespace bhem {
 
 // ------------------------------------------------------- patch kernels
 // phi: the basis table Phi_g[a][I] at 96 g + 16 a + I (16 Gauss points x 6
-// slots x 16 local basis functions); launch_energy_grad and launch_hessian
-// also read its transpose, which follows it at 1536 + 16 (16 a + I) + g
+// slots x 16 local basis functions); launch_hessian and launch_energy_grad
+// also read the copies that follow it: its transpose at 1536 + 16 (16 a + I)
+// + g, and by pairs at 3072 + 32 (8 a + I / 2) + 2 g + I % 2 and at
+// 4608 + 32 (3 g + a / 2) + 2 I + a % 2
 void launch_energy_grad(hipStream_t st, int npatch, const int4* patch_nodes, const int* patch_shell,
                         const ShellParams* shells, const double* phi, const double* q, const double* qbar,
                         const double* qhat, double mass_scale, double dt_damp, int elastic, int loads,

@@ -80,29 +80,45 @@ __global__ __launch_bounds__(16 * EGP) void k_energy_grad(int npatch, const int4
     if (active) {
         const int g = lane;
         double kin[30], xd[3] = {0, 0, 0};
-        // the transposed table: the 16 lanes of a patch read 16 consecutive
-        // values (one cache line) per load
-        const double* ph = phi + 16 * 96 + g;
+        // the table by Gauss point and pairs of basis functions: one 16-byte
+        // load gives the lane Phi_g[a][I] and Phi_g[a][I + 1], and the 16
+        // lanes of a patch read 256 consecutive bytes (each sum still runs
+        // over I in ascending order)
+        const double* ph = phi + 2 * 1536 + 2 * g;
 #pragma unroll
         for (int a = 0; a < 5; ++a) {
             const double sc = slot_scale(a, sp.dxi1, sp.dxi2);
+            double sb[3] = {0.0, 0.0, 0.0}, su[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ip = 0; ip < 8; ++ip) {
+                const double2 f = *reinterpret_cast<const double2*>(ph + (a * 8 + ip) * 32);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int I = 2 * ip + h;
+                    const double fv = h ? f.y : f.x;
+#pragma unroll
+                    for (int comp = 0; comp < 3; ++comp) {
+                        sb[comp] += fv * s_b[pl][3 * I + comp];
+                        su[comp] += fv * s_u[pl][3 * I + comp];
+                    }
+                }
+            }
 #pragma unroll
             for (int comp = 0; comp < 3; ++comp) {
-                double sb = 0.0, su = 0.0;
-                for (int I = 0; I < 16; ++I) {
-                    const double f = ph[(a * 16 + I) * 16];
-                    sb += f * s_b[pl][3 * I + comp];
-                    su += f * s_u[pl][3 * I + comp];
-                }
-                kin[3 * a + comp] = sc * sb;
-                kin[15 + 3 * a + comp] = sc * su;
+                kin[3 * a + comp] = sc * sb[comp];
+                kin[15 + 3 * a + comp] = sc * su[comp];
             }
         }
 #pragma unroll
-        for (int comp = 0; comp < 3; ++comp) {
-            double s = 0.0;
-            for (int I = 0; I < 16; ++I) s += ph[(5 * 16 + I) * 16] * s_d[pl][3 * I + comp];
-            xd[comp] = s;
+        for (int ip = 0; ip < 8; ++ip) {
+            const double2 f = *reinterpret_cast<const double2*>(ph + (5 * 8 + ip) * 32);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int I = 2 * ip + h;
+                const double fv = h ? f.y : f.x;
+#pragma unroll
+                for (int comp = 0; comp < 3; ++comp) xd[comp] += fv * s_d[pl][3 * I + comp];
+            }
         }
         GaussPoint<double> G;
         const double wt = gauss_weight(g & 3) * gauss_weight(g >> 2) * sp.dxi1 * sp.dxi2;
@@ -143,13 +159,20 @@ __global__ __launch_bounds__(16 * EGP) void k_energy_grad(int npatch, const int4
         const int I = lane;
         const double ks = kind_scale(I & 3, sp.dxi1, sp.dxi2);
         double gr[3] = {0, 0, 0};
+        // the table by Gauss point and pairs of slots: one 16-byte load gives
+        // the lane Phi_g[a][I] and Phi_g[a + 1][I]
+        const double* ph = phi + 3 * 1536 + 2 * I;
         for (int g = 0; g < 16; ++g) {
-            const double* ph = phi + g * 96;
 #pragma unroll
-            for (int a = 0; a < 6; ++a) {
-                const double f = ph[a * 16 + I];
+            for (int ap = 0; ap < 3; ++ap) {
+                const double2 f = *reinterpret_cast<const double2*>(ph + (g * 3 + ap) * 32);
 #pragma unroll
-                for (int comp = 0; comp < 3; ++comp) gr[comp] += f * s_dpsi[pl][g][3 * a + comp];
+                for (int h = 0; h < 2; ++h) {
+                    const int a = 2 * ap + h;
+                    const double fv = h ? f.y : f.x;
+#pragma unroll
+                    for (int comp = 0; comp < 3; ++comp) gr[comp] += fv * s_dpsi[pl][g][3 * a + comp];
+                }
             }
         }
 #pragma unroll

@@ -619,12 +619,21 @@ void build(shell_ctx* c, const shell_desc* ds, int S) {
         throw InvalErr{"too many shells for one context (limit " +
                        std::to_string(cg_max_blocks(c->opts.device, c->fp32, 256)) + ")"};
     // theta-space basis table Phi_g[a][I] at 96 g + 16 a + I, followed by
-    // its transpose at 1536 + 16 (16 a + I) + g (read where consecutive
-    // lanes take consecutive Gauss points)
-    std::vector<double> phi(2 * 16 * 6 * 16);
+    // three copies ordered for the lanes that read them: its transpose at
+    // 1536 + 16 (16 a + I) + g (consecutive lanes take consecutive Gauss
+    // points), at 3072 + 32 (8 a + I / 2) + 2 g + I % 2 (pairs of basis
+    // functions per Gauss point) and at 4608 + 32 (3 g + a / 2) + 2 I + a % 2
+    // (pairs of slots per basis function)
+    std::vector<double> phi(4 * 16 * 6 * 16);
     build_theta_basis(phi.data());
     for (int g = 0; g < 16; ++g)
-        for (int e = 0; e < 96; ++e) phi[1536 + 16 * e + g] = phi[96 * g + e];
+        for (int a = 0; a < 6; ++a)
+            for (int I = 0; I < 16; ++I) {
+                const double v = phi[96 * g + 16 * a + I];
+                phi[1536 + 16 * (16 * a + I) + g] = v;
+                phi[3072 + 32 * (8 * a + I / 2) + 2 * g + I % 2] = v;
+                phi[4608 + 32 * (3 * g + a / 2) + 2 * I + a % 2] = v;
+            }
     // uploads
     upload(c->shells_d, c->shells, st);
     upload(c->phi, phi, st);
